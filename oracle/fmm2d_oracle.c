@@ -1,0 +1,478 @@
+/*
+ * fmm2d_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, CPU reference for the asymmetric adaptive 2D FMM of
+ * Engblom, "On well-separated sets and fast multipole methods".  Only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * this library.  It shares no code, header, table or constant with the GPU
+ * library; both sides only see the same seeded inputs.
+ *
+ * Everything is binary64.  OpenMP is used only over independent outputs
+ * (targets, boxes); the arithmetic order of each single output is the plain
+ * sequential one written below.  Build with -ffp-contract=off so that no
+ * multiply-add is fused: the geometry and theta-test must round exactly as
+ * written.
+ *
+ * Notation follows the paper: the interaction sum (1.1), the theta-criterion
+ * (Criterion 2.1), the median-split pyramid and the connectivity rule
+ * (Section 4), and the classical complex multipole / local representation
+ * that the experiments use (Section 5).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* O1: the interaction sum (1.1) with charges, G = log|x - y|, written as the
+ * plain definition.  Pairs with identical coordinates (this includes j == i)
+ * contribute nothing.  Neumaier-compensated summation over j.               */
+/* ------------------------------------------------------------------------ */
+static inline void neumaier_add(double *s, double *c, double t)
+{
+    double u = *s + t;
+    if (fabs(*s) >= fabs(t))
+        *c += (*s - u) + t;
+    else
+        *c += (t - u) + *s;
+    *s = u;
+}
+
+void orc_direct(int64_t n, const double *x, const double *y, const double *q,
+                int64_t m, const int64_t *targets, double *phi)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; ++t) {
+        int64_t i = targets[t];
+        double s = 0.0, c = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (x[j] == x[i] && y[j] == y[i])
+                continue;
+            neumaier_add(&s, &c, q[j] * log(hypot(x[i] - x[j], y[i] - y[j])));
+        }
+        phi[t] = s + c;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2: the balanced pyramid of median splits (Section 4, Fig. 1.1).
+ *
+ * A box with n members is split along x: members are ordered by the pair
+ * (x_j, j) and the first floor(n/2) form the low side.  Each side is then
+ * split along y the same way with the key (y_j, j).  Children of box b are
+ * 4b + 2*[high x] + [high y].  The split line is the midpoint of the two
+ * straddling order statistics.  Inside a leaf, points are listed by (x_j, j).
+ *
+ * Outputs: perm[n] (original indices in leaf order), start[4^L + 1] (leaf
+ * offsets into perm), rects[nbox_total][4] = (xlo, xhi, ylo, yhi) for every
+ * box of every level, level l starting at box (4^l - 1)/3.                 */
+/* ------------------------------------------------------------------------ */
+static const double *g_key;
+static int cmp_key_then_index(const void *a, const void *b)
+{
+    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    if (g_key[i] < g_key[j]) return -1;
+    if (g_key[i] > g_key[j]) return 1;
+    return (i < j) ? -1 : (i > j);
+}
+
+static void sort_by(int64_t *idx, int64_t n, const double *key)
+{
+    g_key = key; /* the tree build is sequential: a file-scope key is fine */
+    qsort(idx, (size_t)n, sizeof(int64_t), cmp_key_then_index);
+}
+
+static int64_t level_offset(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 3; }
+
+int orc_tree(int64_t n, const double *x, const double *y, int L,
+             int64_t *perm, int64_t *leaf_start, double *rects)
+{
+    if (L < 0 || L > 13 || n < (((int64_t)1) << (2 * L)))
+        return -1;
+    int64_t nleaf = ((int64_t)1) << (2 * L);
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
+    int64_t *nstart = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
+    if (!start || !nstart) { free(start); free(nstart); return -2; }
+
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    double xmin = x[0], xmax = x[0], ymin = y[0], ymax = y[0];
+    for (int64_t i = 1; i < n; ++i) {
+        if (x[i] < xmin) xmin = x[i];
+        if (x[i] > xmax) xmax = x[i];
+        if (y[i] < ymin) ymin = y[i];
+        if (y[i] > ymax) ymax = y[i];
+    }
+    rects[0] = xmin; rects[1] = xmax; rects[2] = ymin; rects[3] = ymax;
+    start[0] = 0; start[1] = n;
+
+    for (int l = 0; l < L; ++l) {
+        int64_t nb = ((int64_t)1) << (2 * l);
+        for (int64_t b = 0; b < nb; ++b) {
+            int64_t a = start[b], e = start[b + 1], nn = e - a;
+            const double *R = rects + 4 * (level_offset(l) + b);
+            /* x split */
+            sort_by(perm + a, nn, x);
+            int64_t kx = nn / 2;
+            double sx = 0.5 * (x[perm[a + kx - 1]] + x[perm[a + kx]]);
+            /* y split of each side */
+            int64_t side_a[2] = {a, a + kx}, side_n[2] = {kx, nn - kx};
+            for (int s = 0; s < 2; ++s) {
+                int64_t sa = side_a[s], sn = side_n[s];
+                sort_by(perm + sa, sn, y);
+                int64_t ky = sn / 2;
+                double sy = 0.5 * (y[perm[sa + ky - 1]] + y[perm[sa + ky]]);
+                double xlo = s ? sx : R[0], xhi = s ? R[1] : sx;
+                int64_t c0 = 4 * b + 2 * s;
+                double *C0 = rects + 4 * (level_offset(l + 1) + c0);
+                double *C1 = C0 + 4;
+                C0[0] = xlo; C0[1] = xhi; C0[2] = R[2]; C0[3] = sy;
+                C1[0] = xlo; C1[1] = xhi; C1[2] = sy;   C1[3] = R[3];
+                nstart[c0] = sa;
+                nstart[c0 + 1] = sa + ky;
+            }
+        }
+        nstart[4 * nb] = n;
+        int64_t *tmp = start; start = nstart; nstart = tmp;
+    }
+    for (int64_t b = 0; b < nleaf; ++b)
+        sort_by(perm + start[b], start[b + 1] - start[b], x);
+    memcpy(leaf_start, start, sizeof(int64_t) * (size_t)(nleaf + 1));
+    free(start); free(nstart);
+    return 0;
+}
+
+/* Box centre and radius of the enclosing ball (half diagonal), each line a
+ * single rounded binary64 operation (Criterion 2.1 applied to the tiling
+ * rectangle).                                                               */
+void orc_geometry(int64_t nbox, const double *rects, double *geom)
+{
+    for (int64_t b = 0; b < nbox; ++b) {
+        const double *R = rects + 4 * b;
+        double cx = 0.5 * (R[0] + R[1]);
+        double cy = 0.5 * (R[2] + R[3]);
+        double w = R[1] - R[0];
+        double h = R[3] - R[2];
+        double w2 = w * w;
+        double h2 = h * h;
+        double r = 0.5 * sqrt(w2 + h2);
+        geom[3 * b + 0] = cx;
+        geom[3 * b + 1] = cy;
+        geom[3 * b + 2] = r;
+    }
+}
+
+/* Criterion 2.1: well separated iff R + theta*r <= theta*d.                 */
+int orc_theta_test(double theta, const double *gb, const double *gc)
+{
+    double dx = gb[0] - gc[0];
+    double dy = gb[1] - gc[1];
+    double dx2 = dx * dx;
+    double dy2 = dy * dy;
+    double d = sqrt(dx2 + dy2);
+    double R = gb[2] > gc[2] ? gb[2] : gc[2];
+    double r = gb[2] > gc[2] ? gc[2] : gb[2];
+    double lhs = R + theta * r;
+    double rhs = theta * d;
+    return lhs <= rhs;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O3: connectivity of one level (Section 4).  For box b with parent P, every
+ * child c of every box in S(P) joins W(b) if the theta-criterion holds, else
+ * S(b).  Candidates are visited in ascending order, so both lists come out
+ * ascending.  geom_l holds (cx, cy, r) of the boxes of level l.
+ * Returns 0, or -1 if a capacity is exceeded.                              */
+/* ------------------------------------------------------------------------ */
+int orc_lists_level(int l, double theta, const double *geom_l,
+                    const int64_t *sptr_prev, const int64_t *sidx_prev,
+                    int64_t *sptr, int64_t *sidx, int64_t *wptr, int64_t *widx,
+                    int64_t cap)
+{
+    int64_t nb = ((int64_t)1) << (2 * l);
+    int64_t ns = 0, nw = 0;
+    sptr[0] = 0; wptr[0] = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t P = b / 4;
+        for (int64_t t = sptr_prev[P]; t < sptr_prev[P + 1]; ++t) {
+            int64_t qbox = sidx_prev[t];
+            for (int64_t c = 4 * qbox; c < 4 * qbox + 4; ++c) {
+                if (orc_theta_test(theta, geom_l + 3 * b, geom_l + 3 * c)) {
+                    if (nw >= cap) return -1;
+                    widx[nw++] = c;
+                } else {
+                    if (ns >= cap) return -1;
+                    sidx[ns++] = c;
+                }
+            }
+        }
+        sptr[b + 1] = ns;
+        wptr[b + 1] = nw;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O4: the expansion operators in the classical complex representation
+ * (Section 5), with every expansion normalised by its box scale s.
+ *
+ *   multipole of a box (centre c, scale s):
+ *       phi(z) = A_0 log(z - c) + sum_{k=1..p} A_k (s / (z - c))^k
+ *   local expansion about a box (centre c, scale s):
+ *       psi(z) = sum_{l=0..p} B_l ((z - c) / s)^l
+ * The potential is the real part.                                          */
+/* ------------------------------------------------------------------------ */
+/* Binomial coefficients by Pascal's rule in binary64 (exact below 2^53),
+ * filled once when the library is loaded.                                   */
+#define ORC_BINOM_N 160
+static double g_binom[ORC_BINOM_N][ORC_BINOM_N];
+__attribute__((constructor)) static void orc_fill_binom(void)
+{
+    for (int i = 0; i < ORC_BINOM_N; ++i) {
+        g_binom[i][0] = 1.0;
+        g_binom[i][i] = 1.0;
+        for (int j = 1; j < i; ++j) g_binom[i][j] = g_binom[i - 1][j - 1] + g_binom[i - 1][j];
+    }
+}
+static double binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    return g_binom[n][k];
+}
+
+/* P2M: A_0 = sum q_j,  A_k = -(1/k) sum q_j ((z_j - c)/s)^k.               */
+void orc_p2m(int64_t n, const double *x, const double *y, const double *q,
+             double cx, double cy, double s, int p, double *A /* 2(p+1) */)
+{
+    cplx acc[64 + 1];
+    for (int k = 0; k <= p; ++k) acc[k] = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        cplx zeta = ((x[j] - cx) + I * (y[j] - cy)) / s;
+        cplx pw = 1.0;
+        acc[0] += q[j];
+        for (int k = 1; k <= p; ++k) {
+            pw *= zeta;
+            acc[k] += -(q[j] / k) * pw;
+        }
+    }
+    for (int k = 0; k <= p; ++k) { A[2 * k] = creal(acc[k]); A[2 * k + 1] = cimag(acc[k]); }
+}
+
+/* M2M: child multipole (centre cc, scale sc) re-expanded about the parent
+ * (centre cp, scale sp) and added to Ap.  With delta = (cc - cp)/sp and
+ * sigma = sc/sp:
+ *   A_0(P) += A_0(c)
+ *   A_l(P) += -A_0(c) delta^l / l + sum_{k=1..l} A_k(c) sigma^k delta^(l-k) C(l-1, k-1). */
+void orc_m2m(const double *Ac, double ccx, double ccy, double sc,
+             double cpx, double cpy, double sp, int p, double *Ap)
+{
+    cplx delta = ((ccx - cpx) + I * (ccy - cpy)) / sp;
+    double sigma = sc / sp;
+    cplx a[65], out[65], dpow[65];
+    double spow[65];
+    for (int k = 0; k <= p; ++k) a[k] = Ac[2 * k] + I * Ac[2 * k + 1];
+    dpow[0] = 1.0; spow[0] = 1.0;
+    for (int k = 1; k <= p; ++k) { dpow[k] = dpow[k - 1] * delta; spow[k] = spow[k - 1] * sigma; }
+    out[0] = a[0];
+    for (int l = 1; l <= p; ++l) {
+        cplx t = -a[0] * dpow[l] / (double)l;
+        for (int k = 1; k <= l; ++k)
+            t += a[k] * spow[k] * dpow[l - k] * binom(l - 1, k - 1);
+        out[l] = t;
+    }
+    for (int k = 0; k <= p; ++k) { Ap[2 * k] += creal(out[k]); Ap[2 * k + 1] += cimag(out[k]); }
+}
+
+/* M2L: source multipole (centre cs, scale ss) converted to a local expansion
+ * about the target (centre ct, scale st) and added to Bt.  With
+ * z0 = cs - ct, rho_s = ss/z0, rho_t = st/z0, u_0 = A_0, u_k = A_k rho_s^k:
+ *   B_0 += A_0 log|z0| + sum_{k>=1} (-1)^k u_k
+ *   B_l += rho_t^l ( -A_0 / l + sum_{k>=1} (-1)^k C(l+k-1, k-1) u_k ),  l >= 1.
+ * (Only Re B_0 influences the real potential; the constant imaginary part of
+ * A_0 log(-z0) is dropped.)                                                */
+void orc_m2l(const double *As, double csx, double csy, double ss,
+             double ctx, double cty, double st, int p, double *Bt)
+{
+    cplx z0 = (csx - ctx) + I * (csy - cty);
+    cplx rs = ss / z0, rt = st / z0;
+    cplx u[65], rtp[65], out[65];
+    cplx pw = 1.0;
+    u[0] = As[0] + I * As[1];
+    for (int k = 1; k <= p; ++k) { pw *= rs; u[k] = (As[2 * k] + I * As[2 * k + 1]) * pw; }
+    rtp[0] = 1.0;
+    for (int l = 1; l <= p; ++l) rtp[l] = rtp[l - 1] * rt;
+    {
+        cplx t = u[0] * log(cabs(z0));
+        for (int k = 1; k <= p; ++k) t += ((k & 1) ? -1.0 : 1.0) * u[k];
+        out[0] = t;
+    }
+    for (int l = 1; l <= p; ++l) {
+        cplx t = -u[0] / (double)l;
+        for (int k = 1; k <= p; ++k)
+            t += ((k & 1) ? -1.0 : 1.0) * binom(l + k - 1, k - 1) * u[k];
+        out[l] = rtp[l] * t;
+    }
+    for (int k = 0; k <= p; ++k) { Bt[2 * k] += creal(out[k]); Bt[2 * k + 1] += cimag(out[k]); }
+}
+
+/* L2L: parent local expansion (centre cp, scale sp) re-centred at the child
+ * (centre cc, scale sc), added to Bc.  With delta = (cc - cp)/sp, tau = sc/sp:
+ *   B_l(c) += sum_{k=l..p} B_k(P) C(k, l) tau^l delta^(k-l).               */
+void orc_l2l(const double *Bp, double cpx, double cpy, double sp,
+             double ccx, double ccy, double sc, int p, double *Bc)
+{
+    cplx delta = ((ccx - cpx) + I * (ccy - cpy)) / sp;
+    double tau = sc / sp;
+    cplx b[65], dpow[65];
+    double tpow[65];
+    for (int k = 0; k <= p; ++k) b[k] = Bp[2 * k] + I * Bp[2 * k + 1];
+    dpow[0] = 1.0; tpow[0] = 1.0;
+    for (int k = 1; k <= p; ++k) { dpow[k] = dpow[k - 1] * delta; tpow[k] = tpow[k - 1] * tau; }
+    for (int l = 0; l <= p; ++l) {
+        cplx t = 0;
+        for (int k = l; k <= p; ++k) t += b[k] * binom(k, l) * dpow[k - l];
+        t *= tpow[l];
+        Bc[2 * l] += creal(t);
+        Bc[2 * l + 1] += cimag(t);
+    }
+}
+
+/* L2P: Re sum_l B_l ((z - c)/s)^l at each point, by Horner's rule.          */
+void orc_l2p(const double *B, double cx, double cy, double s, int p,
+             int64_t n, const double *x, const double *y, double *phi)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        cplx zeta = ((x[i] - cx) + I * (y[i] - cy)) / s;
+        cplx v = B[2 * p] + I * B[2 * p + 1];
+        for (int l = p - 1; l >= 0; --l) v = v * zeta + (B[2 * l] + I * B[2 * l + 1]);
+        phi[i] += creal(v);
+    }
+}
+
+/* Multipole expansion evaluated at points (used by the operator pins).      */
+void orc_m2p(const double *A, double cx, double cy, double s, int p,
+             int64_t n, const double *x, const double *y, double *phi)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        cplx w = (x[i] - cx) + I * (y[i] - cy);
+        cplx v = (A[0] + I * A[1]) * clog(w);
+        cplx rho = s / w, pw = 1.0;
+        for (int k = 1; k <= p; ++k) { pw *= rho; v += (A[2 * k] + I * A[2 * k + 1]) * pw; }
+        phi[i] += creal(v);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O4: the whole FMM on a tree and lists built by orc_tree / orc_lists_level
+ * (Section 4): upward pass (P2M at the leaves, M2M to the root), M2L along
+ * the weak lists of every level >= 1, L2L downwards, and at the finest level
+ * L2P plus the direct sum over the strong list.  The scale of a box is its
+ * radius r, or 1 for a box of zero size.  Inputs are in original order;
+ * phi is returned in original order.
+ *
+ * geom: (cx, cy, r) of every box of every level (level offsets (4^l-1)/3).
+ * wptr/widx: per level l = 0..L, concatenated; wptr_off[l], widx_off[l] give
+ * the start of level l in the two arrays.  sptr_L / sidx_L: finest level.  */
+/* ------------------------------------------------------------------------ */
+static double box_scale(const double *g) { return g[2] > 0.0 ? g[2] : 1.0; }
+
+int orc_fmm_eval(int64_t n, const double *x, const double *y, const double *q,
+                 int L, int p, const int64_t *perm, const int64_t *leaf_start,
+                 const double *geom, const int64_t *wptr, const int64_t *widx,
+                 const int64_t *wptr_off, const int64_t *widx_off,
+                 const int64_t *sptr_L, const int64_t *sidx_L, double *phi)
+{
+    if (p < 1 || p > 64) return -1;
+    int64_t nbox = level_offset(L + 1);
+    int64_t nleaf = ((int64_t)1) << (2 * L);
+    int64_t stride = 2 * (p + 1);
+    double *A = (double *)calloc((size_t)(nbox * stride), sizeof(double));
+    double *B = (double *)calloc((size_t)(nbox * stride), sizeof(double));
+    double *xs = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ys = (double *)malloc(sizeof(double) * (size_t)n);
+    double *qs = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ps = (double *)calloc((size_t)n, sizeof(double));
+    if (!A || !B || !xs || !ys || !qs || !ps) {
+        free(A); free(B); free(xs); free(ys); free(qs); free(ps);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i) { xs[i] = x[perm[i]]; ys[i] = y[perm[i]]; qs[i] = q[perm[i]]; }
+    const int64_t off_L = level_offset(L);
+
+    /* P2M at the leaves */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < nleaf; ++b) {
+        const double *g = geom + 3 * (off_L + b);
+        int64_t a = leaf_start[b], e = leaf_start[b + 1];
+        orc_p2m(e - a, xs + a, ys + a, qs + a, g[0], g[1], box_scale(g), p,
+                A + stride * (off_L + b));
+    }
+    /* M2M, finest-but-one level up to the root */
+    for (int l = L - 1; l >= 0; --l) {
+        int64_t nb = ((int64_t)1) << (2 * l), off = level_offset(l), offc = level_offset(l + 1);
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t P = 0; P < nb; ++P) {
+            const double *gp = geom + 3 * (off + P);
+            for (int c = 0; c < 4; ++c) {
+                int64_t cb = offc + 4 * P + c;
+                const double *gc = geom + 3 * cb;
+                orc_m2m(A + stride * cb, gc[0], gc[1], box_scale(gc),
+                        gp[0], gp[1], box_scale(gp), p, A + stride * (off + P));
+            }
+        }
+    }
+    /* downward pass: M2L along W at level l, then L2L to level l+1 */
+    for (int l = 1; l <= L; ++l) {
+        int64_t nb = ((int64_t)1) << (2 * l), off = level_offset(l);
+        const int64_t *wp = wptr + wptr_off[l];
+        const int64_t *wi = widx + widx_off[l];
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t b = 0; b < nb; ++b) {
+            const double *gt = geom + 3 * (off + b);
+            for (int64_t t = wp[b]; t < wp[b + 1]; ++t) {
+                int64_t c = wi[t];
+                const double *gs = geom + 3 * (off + c);
+                orc_m2l(A + stride * (off + c), gs[0], gs[1], box_scale(gs),
+                        gt[0], gt[1], box_scale(gt), p, B + stride * (off + b));
+            }
+        }
+        if (l < L) {
+            int64_t offc = level_offset(l + 1);
+#pragma omp parallel for schedule(dynamic, 64)
+            for (int64_t P = 0; P < nb; ++P) {
+                const double *gp = geom + 3 * (off + P);
+                for (int c = 0; c < 4; ++c) {
+                    int64_t cb = offc + 4 * P + c;
+                    const double *gc = geom + 3 * cb;
+                    orc_l2l(B + stride * (off + P), gp[0], gp[1], box_scale(gp),
+                            gc[0], gc[1], box_scale(gc), p, B + stride * cb);
+                }
+            }
+        }
+    }
+    /* L2P and the direct sum over the finest-level strong list */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < nleaf; ++b) {
+        const double *g = geom + 3 * (off_L + b);
+        int64_t a = leaf_start[b], e = leaf_start[b + 1];
+        orc_l2p(B + stride * (off_L + b), g[0], g[1], box_scale(g), p, e - a,
+                xs + a, ys + a, ps + a);
+        for (int64_t i = a; i < e; ++i) {
+            double s = 0.0, c = 0.0;
+            for (int64_t t = sptr_L[b]; t < sptr_L[b + 1]; ++t) {
+                int64_t cb = sidx_L[t];
+                for (int64_t j = leaf_start[cb]; j < leaf_start[cb + 1]; ++j) {
+                    if (xs[j] == xs[i] && ys[j] == ys[i])
+                        continue;
+                    neumaier_add(&s, &c, qs[j] * log(hypot(xs[i] - xs[j], ys[i] - ys[j])));
+                }
+            }
+            ps[i] += s + c;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) phi[perm[i]] = ps[i];
+    free(A); free(B); free(xs); free(ys); free(qs); free(ps);
+    return 0;
+}
