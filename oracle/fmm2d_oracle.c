@@ -87,7 +87,7 @@ static void sort_by(int64_t *idx, int64_t n, const double *key)
 
 static int64_t level_offset(int l) { return ((((int64_t)1) << (2 * l)) - 1) / 3; }
 
-int orc_tree(int64_t n, const double *x, const double *y, int L,
+int orc_tree(int64_t n, const double *x_in, const double *y_in, int L,
              int64_t *perm, int64_t *leaf_start, double *rects)
 {
     if (L < 0 || L > 13 || n < (((int64_t)1) << (2 * L)))
@@ -95,7 +95,12 @@ int orc_tree(int64_t n, const double *x, const double *y, int L,
     int64_t nleaf = ((int64_t)1) << (2 * L);
     int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
     int64_t *nstart = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
-    if (!start || !nstart) { free(start); free(nstart); return -2; }
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!start || !nstart || !x || !y) { free(start); free(nstart); free(x); free(y); return -2; }
+    /* A coordinate -0 is the number 0: read it as +0, so that a split line or
+     * box edge never depends on which of two equal zeros was met first. */
+    for (int64_t i = 0; i < n; ++i) { x[i] = x_in[i] + 0.0; y[i] = y_in[i] + 0.0; }
 
     for (int64_t i = 0; i < n; ++i) perm[i] = i;
     double xmin = x[0], xmax = x[0], ymin = y[0], ymax = y[0];
@@ -140,7 +145,7 @@ int orc_tree(int64_t n, const double *x, const double *y, int L,
     for (int64_t b = 0; b < nleaf; ++b)
         sort_by(perm + start[b], start[b + 1] - start[b], x);
     memcpy(leaf_start, start, sizeof(int64_t) * (size_t)(nleaf + 1));
-    free(start); free(nstart);
+    free(start); free(nstart); free(x); free(y);
     return 0;
 }
 

@@ -140,3 +140,19 @@ def test_geometry_closed_form(orc):
     assert g[0].tolist() == [0.5, 0.5, 0.5 * np.sqrt(2.0)]
     assert g[1].tolist() == [0.5, -0.25, 0.5 * np.sqrt(0.25 + 2.25)]
     assert g[2].tolist() == [2.0, 3.0, 0.0]
+
+
+def test_negative_zero_is_zero(orc):
+    # -0 and +0 are the same number: trees of the two inputs are identical
+    # bit for bit (rectangles included).
+    ps = W.uniform(500, seed=31)
+    x, y = ps.x.copy(), ps.y.copy()
+    x[:60] = 0.0
+    y[:40] = 0.0
+    xn, yn = x.copy(), y.copy()
+    xn[:30] = -0.0
+    yn[10:25] = -0.0
+    a = orc.tree(x, y, 3)
+    b = orc.tree(xn, yn, 3)
+    assert np.array_equal(a.perm, b.perm)
+    assert np.array_equal(a.rects.view(np.int64), b.rects.view(np.int64))
