@@ -1,0 +1,148 @@
+/*
+ * fmm2d.h -- C ABI of an MI355X (gfx950) implementation of the asymmetric
+ * adaptive fast multipole method for the 2D logarithmic potential, after
+ * S. Engblom, "On well-separated sets and fast multipole methods".
+ *
+ * The library computes, for points z_i = (x_i, y_i) with real charges q_i,
+ *
+ *     phi_i = sum_{j : z_j != z_i} q_j log|z_i - z_j|                  (1.1)
+ *
+ * (the interaction sum of eq. (1.1) with G = log|x - y| and charges; pairs at
+ * one location are left out like j == i).  The three stages of Section 4 are
+ * separate calls: the balanced median-split tree, the strong/weak
+ * connectivity under the theta-criterion (Criterion 2.1), and the
+ * evaluation of the expansions and of the near field.
+ *
+ * Conventions for every function:
+ *  - Every function returns an int status: FMM2D_OK or a negative code.
+ *    Nothing throws across the ABI.  On error, fmm2d_last_error() describes
+ *    the failure.  Arguments are validated on the host before any launch,
+ *    and a call that fails validation leaves the context unchanged.
+ *  - Pointers documented as "device" are HIP device pointers on the
+ *    context's device; the caller owns them.  Work is enqueued on the
+ *    context's stream; device inputs must stay valid, and device outputs are
+ *    complete, once that stream has passed the call (synchronise the stream
+ *    before reading them on the host).  Pointers documented as "host" are
+ *    ordinary host memory, read or written before the call returns.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - The context owns its scratch memory (hipMalloc, kept and reused across
+ *    calls, freed by fmm2d_destroy).
+ */
+#ifndef FMM2D_H
+#define FMM2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define FMM2D_OK          0
+#define FMM2D_EINVAL     -1  /* an argument is out of range or NULL          */
+#define FMM2D_ENOMEM     -2  /* a device allocation failed                    */
+#define FMM2D_EDEVICE    -3  /* a HIP runtime error; see fmm2d_last_error()   */
+#define FMM2D_ESTATE     -4  /* wrong call order (e.g. evaluate before lists) */
+
+/* Precision modes of fmm2d_evaluate.  In every mode the tree, the lists,
+ * P2M, M2M, L2L and L2P run in binary64; the modes differ in the two hot
+ * steps, the M2L conversion along the weak lists and the near-field sum.
+ *   FP64        M2L and near field in binary64.
+ *   FP32        M2L as an FP32 matrix product on the matrix cores with FP32
+ *               accumulation and FP32 power scaling; near field in FP32 on
+ *               box-local coordinates; FP32 accumulation.
+ *   BF16X3      as FP32, with the M2L product done as three BF16 products of
+ *               a two-way BF16 split of both operands.
+ *   FP32_ACC64  as FP32, with the per-pair power scaling in binary64 and the
+ *               M2L and near-field sums accumulated in binary64.           */
+#define FMM2D_MODE_FP64        0
+#define FMM2D_MODE_FP32        1
+#define FMM2D_MODE_BF16X3      2
+#define FMM2D_MODE_FP32_ACC64  3
+
+#define FMM2D_MAX_LEVELS 13
+#define FMM2D_MAX_P      63
+
+typedef struct fmm2d_ctx fmm2d_ctx;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int fmm2d_version(void);
+
+/* Creates a context on HIP device `device` that enqueues all work on
+ * `stream` (a hipStream_t; NULL means the device's null stream).  *out
+ * receives the context. */
+int fmm2d_create(fmm2d_ctx **out, int device, void *stream);
+
+/* Frees the context and all its device memory.  Synchronises its stream. */
+int fmm2d_destroy(fmm2d_ctx *ctx);
+
+/* Message of the last failing call on ctx (owned by ctx, valid until the
+ * next call on it).  Returns "" when there was none, or a fixed message when
+ * ctx is NULL. */
+const char *fmm2d_last_error(const fmm2d_ctx *ctx);
+
+/* Replaces the stream used by later calls. */
+int fmm2d_set_stream(fmm2d_ctx *ctx, void *stream);
+
+/* Builds the balanced pyramid (Section 4 and Fig. 1.1).  x, y: device,
+ * binary64 [n], every value finite with |value| <= 2^500.  levels: 0..13,
+ * with n >= 4^levels (every box must split) and n <= 2^31 - 1.
+ *
+ * Each box is split along x so that its floor(m/2) first members in
+ * (x, original index) order go low, then each half is split along y the same
+ * way with (y, index); the children of box b are 4b + 2*[x high] + [y high]
+ * and a split line is the midpoint of the two straddling coordinates.  The
+ * root is the tight bounding box.  Inside each leaf, points are kept in
+ * (x, index) order.  Replaces any earlier tree and invalidates the lists. */
+int fmm2d_build_tree(fmm2d_ctx *ctx, const double *x, const double *y,
+                     int64_t n, int levels);
+
+/* Builds the strong and weak interaction lists of every level (Section 4)
+ * with the theta-criterion R + theta r <= theta d on the boxes' enclosing
+ * balls (centre of the rectangle, half its diagonal).  0 < theta < 1.
+ * Needs a tree.  Synchronises the stream once (to size the lists). */
+int fmm2d_connectivity(fmm2d_ctx *ctx, double theta);
+
+/* Evaluates phi (eq. (1.1)) with expansion order p (degrees 0..p, so p + 1
+ * coefficients per expansion), 1 <= p <= 63, in precision `mode`
+ * (FMM2D_MODE_*).  q: device binary64 [n] charges in input order.  phi:
+ * device binary64 [n] output in input order.  Needs tree and lists.
+ * Asynchronous on the stream. */
+int fmm2d_evaluate(fmm2d_ctx *ctx, const double *q, int p, int mode, double *phi);
+
+/* Direct binary64 sum (eq. (1.1)) at m target indices, with compensated
+ * summation: the error judge.  x, y, q: device binary64 [n]; targets: device
+ * int64 [m] with values in [0, n); phi_m: device binary64 [m].  Independent
+ * of any tree.  Asynchronous on the stream. */
+int fmm2d_direct(fmm2d_ctx *ctx, const double *x, const double *y, const double *q,
+                 int64_t n, const int64_t *targets, int64_t m, double *phi_m);
+
+/* ---- introspection (used by the parity tests) ---------------------------- */
+
+/* Host outputs: number of points, levels and boxes of the current tree. */
+int fmm2d_tree_info(const fmm2d_ctx *ctx, int64_t *n, int *levels, int64_t *nbox);
+
+/* Device output int32 [n]: original index of each point in leaf order. */
+int fmm2d_get_perm(fmm2d_ctx *ctx, int32_t *perm);
+
+/* Device output int32 [4^levels + 1]: first position of each leaf in perm. */
+int fmm2d_get_leaf_start(fmm2d_ctx *ctx, int32_t *start);
+
+/* Device output binary64 [nbox][4]: (xlo, xhi, ylo, yhi) of every box, level
+ * by level, level l starting at box (4^l - 1)/3. */
+int fmm2d_get_rects(fmm2d_ctx *ctx, double *rects);
+
+/* Host outputs: number of strong and weak list entries at `level`. */
+int fmm2d_list_sizes(const fmm2d_ctx *ctx, int level, int64_t *n_strong, int64_t *n_weak);
+
+/* Device outputs for one level: CSR row pointers int32 [4^level + 1] and
+ * column indices (box numbers within the level, ascending per row) of the
+ * strong list S and the weak list W.  Any pointer may be NULL to skip it. */
+int fmm2d_get_lists(fmm2d_ctx *ctx, int level, int32_t *sptr, int32_t *sidx,
+                    int32_t *wptr, int32_t *widx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM2D_H */

@@ -1,0 +1,288 @@
+// C ABI of the library: argument validation, call-order checks, error
+// reporting, and the sequencing of the device passes on the context stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "devutil.h"
+#include "internal.h"
+
+using namespace fmm2d;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int fail(fmm2d_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(fmm2d_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+    return code;
+}
+
+int hip_fail(fmm2d_ctx *c, hipError_t e, const char *where) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(c, FMM2D_ENOMEM, "%s: device allocation failed (%s)", where, hipGetErrorString(e));
+    return fail(c, FMM2D_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// flags[0]: non-finite or |v| > 2^500 seen; flags[1]: index out of range
+__global__ void k_check_coords(const double *__restrict__ v, int64_t n, int *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double a = fabs(v[i]);
+        if (!(a <= 0x1p500)) flags[0] = 1;  // also catches NaN
+    }
+}
+__global__ void k_check_targets(const int64_t *__restrict__ t, int64_t m, int64_t n, int *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m && (t[i] < 0 || t[i] >= n)) flags[1] = 1;
+}
+__global__ void k_zero_flags(int *flags) {
+    flags[0] = 0;
+    flags[1] = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmm2d_version(void) { return 100; }
+
+int fmm2d_create(fmm2d_ctx **out, int device, void *stream) {
+    if (!out) return FMM2D_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FMM2D_EINVAL;
+    fmm2d_ctx *c = new (std::nothrow) fmm2d_ctx;
+    if (!c) return FMM2D_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    *out = c;
+    return FMM2D_OK;
+}
+
+int fmm2d_destroy(fmm2d_ctx *c) {
+    if (!c) return FMM2D_EINVAL;
+    {
+        DeviceGuard g(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        TreeState &t = c->tree;
+        for (DevBuf *b : {&t.xsorted, &t.ysorted, &t.xorder, &t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1,
+                          &t.starts, &t.rects, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
+                          &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state})
+            b->release();
+        EvalState &e = c->ev;
+        for (DevBuf *b : {&e.binom, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();
+        Scratch &s = c->scr;
+        for (DevBuf *b : {&s.keys0, &s.keys1, &s.vals0, &s.vals1, &s.hist, &s.aux, &s.tiles, &s.tiles2, &s.segbase,
+                          &s.thr, &s.split0, &s.split1, &s.flag})
+            b->release();
+    }
+    delete c;
+    return FMM2D_OK;
+}
+
+const char *fmm2d_last_error(const fmm2d_ctx *c) {
+    if (!c) return "fmm2d: NULL context";
+    return c->err.c_str();
+}
+
+int fmm2d_set_stream(fmm2d_ctx *c, void *stream) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    c->stream = static_cast<hipStream_t>(stream);
+    return FMM2D_OK;
+}
+
+int fmm2d_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, int levels) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!x || !y) return fail(c, FMM2D_EINVAL, "build_tree: x and y must be device pointers");
+    if (levels < 0 || levels > FMM2D_MAX_LEVELS) return fail(c, FMM2D_EINVAL, "build_tree: levels %d not in [0, 13]", levels);
+    if (n < 1 || n > 2147483647LL) return fail(c, FMM2D_EINVAL, "build_tree: n = %lld not in [1, 2^31-1]", (long long)n);
+    if (n < (int64_t(1) << (2 * levels)))
+        return fail(c, FMM2D_EINVAL, "build_tree: n = %lld < 4^levels = %lld", (long long)n,
+                    (long long)(int64_t(1) << (2 * levels)));
+    DeviceGuard g(c->device);
+    hipError_t e;
+    // validate the coordinates before touching the current tree
+    if ((e = c->scr.aux.ensure(4096)) != hipSuccess) return hip_fail(c, e, "build_tree");
+    int *flags = reinterpret_cast<int *>(c->scr.aux.as<char>() + 2048);
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(1), 0, c->stream, flags);
+    hipLaunchKernelGGL(k_check_coords, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, x, n, flags);
+    hipLaunchKernelGGL(k_check_coords, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, y, n, flags);
+    int hf[2] = {0, 0};
+    if ((e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return hip_fail(c, e, "build_tree");
+    if (hf[0]) return fail(c, FMM2D_EINVAL, "build_tree: coordinates must be finite with |v| <= 2^500");
+    TreeState &t = c->tree;
+    t.has_lists = false;
+    t.n = n;
+    t.L = levels;
+    if ((e = build_tree_device(c, x, y)) != hipSuccess) {
+        t.L = -1;
+        return hip_fail(c, e, "build_tree");
+    }
+    return FMM2D_OK;
+}
+
+int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!(theta > 0.0 && theta < 1.0)) return fail(c, FMM2D_EINVAL, "connectivity: theta must lie in (0, 1)");
+    TreeState &t = c->tree;
+    if (t.L < 0) return fail(c, FMM2D_ESTATE, "connectivity: no tree (call fmm2d_build_tree first)");
+    DeviceGuard g(c->device);
+    const int64_t nbox = level_offset(t.L + 1);
+    int64_t cap_s = 32 * nbox + 64, cap_w = 96 * nbox + 64;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        bool overflow = false;
+        hipError_t e = build_lists_device(c, theta, cap_s, cap_w, &overflow);
+        if (e != hipSuccess) {
+            t.has_lists = false;
+            return hip_fail(c, e, "connectivity");
+        }
+        if (!overflow) {
+            t.has_lists = true;
+            t.theta = theta;
+            return FMM2D_OK;
+        }
+        cap_s *= 4;
+        cap_w *= 4;
+        if (cap_s > 2147483647LL) cap_s = 2147483647LL;
+        if (cap_w > 2147483647LL) cap_w = 2147483647LL;
+    }
+    t.has_lists = false;
+    return fail(c, FMM2D_ENOMEM, "connectivity: interaction lists exceed 2^31 entries");
+}
+
+int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!q || !phi) return fail(c, FMM2D_EINVAL, "evaluate: q and phi must be device pointers");
+    if (p < 1 || p > FMM2D_MAX_P) return fail(c, FMM2D_EINVAL, "evaluate: p = %d not in [1, 63]", p);
+    if (mode < FMM2D_MODE_FP64 || mode > FMM2D_MODE_FP32_ACC64) return fail(c, FMM2D_EINVAL, "evaluate: unknown mode %d", mode);
+    if (c->tree.L < 0 || !c->tree.has_lists)
+        return fail(c, FMM2D_ESTATE, "evaluate: needs a tree and its lists (build_tree, connectivity)");
+    DeviceGuard g(c->device);
+    hipError_t e = evaluate_device(c, q, p, mode, phi);
+    if (e != hipSuccess) return hip_fail(c, e, "evaluate");
+    return FMM2D_OK;
+}
+
+int fmm2d_direct(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n, const int64_t *targets,
+                 int64_t m, double *phi_m) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!x || !y || !q || (m > 0 && (!targets || !phi_m))) return fail(c, FMM2D_EINVAL, "direct: NULL pointer");
+    if (n < 1 || m < 0) return fail(c, FMM2D_EINVAL, "direct: need n >= 1 and m >= 0");
+    if (m == 0) return FMM2D_OK;
+    DeviceGuard g(c->device);
+    hipError_t e;
+    if ((e = c->scr.aux.ensure(4096)) != hipSuccess) return hip_fail(c, e, "direct");
+    int *flags = reinterpret_cast<int *>(c->scr.aux.as<char>() + 2048);
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(1), 0, c->stream, flags);
+    hipLaunchKernelGGL(k_check_targets, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, targets, m, n, flags);
+    int hf[2] = {0, 0};
+    if ((e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return hip_fail(c, e, "direct");
+    if (hf[1]) return fail(c, FMM2D_EINVAL, "direct: a target index is outside [0, n)");
+    if ((e = direct_device(c, x, y, q, n, targets, m, phi_m)) != hipSuccess) return hip_fail(c, e, "direct");
+    return FMM2D_OK;
+}
+
+int fmm2d_tree_info(const fmm2d_ctx *c, int64_t *n, int *levels, int64_t *nbox) {
+    if (!c) return FMM2D_EINVAL;
+    if (c->tree.L < 0) return FMM2D_ESTATE;
+    if (n) *n = c->tree.n;
+    if (levels) *levels = c->tree.L;
+    if (nbox) *nbox = level_offset(c->tree.L + 1);
+    return FMM2D_OK;
+}
+
+int fmm2d_get_perm(fmm2d_ctx *c, int32_t *perm) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!perm) return fail(c, FMM2D_EINVAL, "get_perm: NULL pointer");
+    if (c->tree.L < 0) return fail(c, FMM2D_ESTATE, "get_perm: no tree");
+    DeviceGuard g(c->device);
+    hipError_t e = hipMemcpyAsync(perm, c->tree.perm.ptr, sizeof(int32_t) * c->tree.n, hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_perm");
+}
+
+int fmm2d_get_leaf_start(fmm2d_ctx *c, int32_t *start) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!start) return fail(c, FMM2D_EINVAL, "get_leaf_start: NULL pointer");
+    if (c->tree.L < 0) return fail(c, FMM2D_ESTATE, "get_leaf_start: no tree");
+    DeviceGuard g(c->device);
+    const int L = c->tree.L;
+    hipError_t e = hipMemcpyAsync(start, c->tree.starts.as<int32_t>() + depth_offset(2 * L),
+                                  sizeof(int32_t) * ((int64_t(1) << (2 * L)) + 1), hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_leaf_start");
+}
+
+int fmm2d_get_rects(fmm2d_ctx *c, double *rects) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!rects) return fail(c, FMM2D_EINVAL, "get_rects: NULL pointer");
+    if (c->tree.L < 0) return fail(c, FMM2D_ESTATE, "get_rects: no tree");
+    DeviceGuard g(c->device);
+    hipError_t e = hipMemcpyAsync(rects, c->tree.rects.ptr, sizeof(double) * 4 * level_offset(c->tree.L + 1),
+                                  hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_rects");
+}
+
+int fmm2d_list_sizes(const fmm2d_ctx *c, int level, int64_t *ns, int64_t *nw) {
+    if (!c) return FMM2D_EINVAL;
+    const TreeState &t = c->tree;
+    if (t.L < 0 || !t.has_lists) return FMM2D_ESTATE;
+    if (level < 0 || level > t.L) return FMM2D_EINVAL;
+    if (ns) *ns = t.s_off[level + 1] - t.s_off[level];
+    if (nw) *nw = t.w_off[level + 1] - t.w_off[level];
+    return FMM2D_OK;
+}
+
+int fmm2d_get_lists(fmm2d_ctx *c, int level, int32_t *sptr, int32_t *sidx, int32_t *wptr, int32_t *widx) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    TreeState &t = c->tree;
+    if (t.L < 0 || !t.has_lists) return fail(c, FMM2D_ESTATE, "get_lists: no lists");
+    if (level < 0 || level > t.L) return fail(c, FMM2D_EINVAL, "get_lists: level %d not in [0, %d]", level, t.L);
+    DeviceGuard g(c->device);
+    const int64_t nb = int64_t(1) << (2 * level);
+    const int64_t ns = t.s_off[level + 1] - t.s_off[level], nw = t.w_off[level + 1] - t.w_off[level];
+    hipError_t e = hipSuccess;
+    if (sptr && e == hipSuccess)
+        e = hipMemcpyAsync(sptr, t.sptr.as<int32_t>() + ptr_offset(level), sizeof(int32_t) * (nb + 1),
+                           hipMemcpyDeviceToDevice, c->stream);
+    if (wptr && e == hipSuccess)
+        e = hipMemcpyAsync(wptr, t.wptr.as<int32_t>() + ptr_offset(level), sizeof(int32_t) * (nb + 1),
+                           hipMemcpyDeviceToDevice, c->stream);
+    if (sidx && ns > 0 && e == hipSuccess)
+        e = hipMemcpyAsync(sidx, t.sidx.as<int32_t>() + t.s_off[level], sizeof(int32_t) * ns, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (widx && nw > 0 && e == hipSuccess)
+        e = hipMemcpyAsync(widx, t.widx.as<int32_t>() + t.w_off[level], sizeof(int32_t) * nw, hipMemcpyDeviceToDevice,
+                           c->stream);
+    return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_lists");
+}
+
+}  // extern "C"

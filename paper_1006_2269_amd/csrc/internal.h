@@ -1,0 +1,116 @@
+// Internal declarations of the fmm2d HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fmm2d.h"
+
+namespace fmm2d {
+
+constexpr int WAVE = 64;
+
+// Global id of the first box of level l: (4^l - 1) / 3.
+__host__ __device__ inline int64_t level_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+// Offset of level l in an array holding (4^m + 1) entries per level m.
+__host__ __device__ inline int64_t ptr_offset(int l) { return level_offset(l) + l; }
+// Offset of depth d in an array holding (2^e + 1) entries per depth e.
+__host__ __device__ inline int64_t depth_offset(int d) { return ((int64_t(1) << d) - 1) + d; }
+
+// Growable device buffer owned by the context.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap && ptr) return hipSuccess;
+        if (ptr) { hipError_t e = hipFree(ptr); ptr = nullptr; cap = 0; if (e != hipSuccess) return e; }
+        size_t b = bytes < 256 ? 256 : bytes;
+        hipError_t e = hipMalloc(&ptr, b);
+        if (e == hipSuccess) cap = b;
+        return e;
+    }
+    void release() { if (ptr) (void)hipFree(ptr); ptr = nullptr; cap = 0; }
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Everything a tree and its lists leave on the device.
+struct TreeState {
+    int64_t n = 0;
+    int L = -1;
+    // sorted coordinates and the x-order permutation
+    DevBuf xsorted, ysorted, xorder;
+    // rank lists (structure of arrays): XL sorted by x rank within segments,
+    // YL sorted by y rank within segments; each holds (x rank, y rank)
+    DevBuf XLx, XLy, YLx, YLy, T0, T1;
+    DevBuf starts;          // int32, all depths 0..2L, (2^d + 1) entries each
+    DevBuf rects;           // double [nbox][4]
+    DevBuf geom;            // double4 [nbox]: cx, cy, r, scale
+    DevBuf perm;            // int32 [n]
+    DevBuf leafid;          // int32 [n]: leaf of each leaf-ordered point
+    DevBuf px, py;          // double [n], leaf order
+    DevBuf loc;             // float2 [n], offsets from the leaf centre
+    // lists: row pointers of every level (ptr_offset), index pools
+    DevBuf sptr, wptr, sidx, widx, cnt_s, cnt_w;
+    DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
+    std::vector<int64_t> s_off, w_off;  // host copy: pool offset of each level
+    bool has_lists = false;
+    double theta = 0.0;
+};
+
+struct EvalState {
+    DevBuf binom;           // double [128][128] binomial coefficients
+    bool binom_ready = false;
+    DevBuf A, B;            // expansions, complex<double> [nbox][p+1]
+    DevBuf qs;              // double [n] charges in leaf order
+    DevBuf phi_leaf;        // double [n]
+    DevBuf work;            // mode-dependent scratch
+    DevBuf src;             // float4 [n]: FP32 local offsets and charge
+};
+
+struct Scratch {
+    DevBuf keys0, keys1, vals0, vals1, hist, aux, tiles, tiles2, segbase, thr, split0, split1, flag;
+};
+
+}  // namespace fmm2d
+
+struct fmm2d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    fmm2d::TreeState tree;
+    fmm2d::EvalState ev;
+    fmm2d::Scratch scr;
+};
+
+namespace fmm2d {
+
+// ---- launchers (each returns the launch's hipError_t) ---------------------
+// sort.hip
+hipError_t sort_coordinate(fmm2d_ctx *c, const double *v, int64_t n, double *sorted, int32_t *order);
+// scan.hip: exclusive scan of int32 in[n] into out[n+1] (out[n] = total)
+hipError_t scan_exclusive(fmm2d_ctx *c, const int32_t *in, int64_t n, int32_t *out);
+// tree.hip
+hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y);
+// lists.hip
+hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t cap_w, bool *overflow);
+// expand.hip
+hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, double *phi);
+// judge.hip
+hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                         const int64_t *targets, int64_t m, double *phi);
+
+inline unsigned grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace fmm2d
+
+#define FMM2D_TRY(expr)                          \
+    do {                                         \
+        hipError_t e__ = (expr);                 \
+        if (e__ != hipSuccess) return e__;       \
+    } while (0)

@@ -1,0 +1,306 @@
+// Balanced median-split pyramid (Section 4, Fig. 1.1) on the GPU.
+//
+// Design.  Both coordinates are sorted once by (value, index).  A point is
+// then represented by its two ranks (x rank, y rank); comparing ranks is
+// comparing (value, index) pairs.  Two lists are kept, partitioned into the
+// current boxes ("segments"): XL, each segment in x-rank order, and YL, each
+// segment in y-rank order.  Splitting a segment of m points along x needs no
+// selection: its low side is the first floor(m/2) entries of its XL part, so
+// the median is the entry at floor(m/2) and a point is low iff its x rank is
+// below that entry's.  XL is already partitioned by this split; YL is
+// partitioned stably by the flag (x rank < median rank), which keeps it in
+// y-rank order inside each half.  The y split of each half is the mirror
+// image (YL gives the median, XL is partitioned).  Segment sizes never depend
+// on the data: a segment of m points has floor(m/2) low points, so all
+// segment offsets are known before a level is examined, and the stable
+// partition needs only a global prefix count of the low flags.
+#include "devutil.h"
+#include "internal.h"
+
+namespace fmm2d {
+namespace {
+
+constexpr int PT = 256;     // threads per partition block
+constexpr int PI = 16;      // items per thread (blocked)
+constexpr int PTILE = PT * PI;
+
+struct Rect {
+    double xlo, xhi, ylo, yhi;
+};
+
+__device__ inline int64_t find_seg(const int32_t *__restrict__ st, int64_t nseg, int64_t n, int64_t i) {
+    int64_t s = (i * nseg) / n;
+    if (s > nseg - 1) s = nseg - 1;
+    while (st[s] > i) --s;
+    while (st[s + 1] <= i) ++s;
+    return s;
+}
+
+__global__ void k_root(const double *__restrict__ xs, const double *__restrict__ ys, int64_t n,
+                       int32_t *__restrict__ st0, Rect *__restrict__ rects) {
+    st0[0] = 0;
+    st0[1] = (int32_t)n;
+    rects[0] = Rect{xs[0], xs[n - 1], ys[0], ys[n - 1]};
+}
+
+__global__ void k_invert(const int32_t *__restrict__ order, int64_t n, int32_t *__restrict__ rank) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) rank[order[r]] = (int32_t)r;
+}
+
+__global__ void k_init_lists(const int32_t *__restrict__ xorder, const int32_t *__restrict__ yorder,
+                             const int32_t *__restrict__ xrank, const int32_t *__restrict__ yrank, int64_t n,
+                             int32_t *__restrict__ XLx, int32_t *__restrict__ XLy, int32_t *__restrict__ YLx,
+                             int32_t *__restrict__ YLy) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) {
+        XLx[r] = (int32_t)r;
+        XLy[r] = yrank[xorder[r]];
+        YLy[r] = (int32_t)r;
+        YLx[r] = xrank[yorder[r]];
+    }
+}
+
+// One thread per segment of depth h: median rank, split line, child offsets,
+// and (after a y split) the four child rectangles.
+__global__ void k_threshold(int h, int64_t nseg, int64_t n, const int32_t *__restrict__ st,
+                            int32_t *__restrict__ st1, const int32_t *__restrict__ sorted_list,
+                            const double *__restrict__ coord, int32_t *__restrict__ thr,
+                            double *__restrict__ split_cur, const double *__restrict__ split_prev,
+                            Rect *__restrict__ rects) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    const int32_t a = st[s], e = st[s + 1];
+    const int32_t k = (e - a) >> 1;
+    const int32_t r_hi = sorted_list[a + k], r_lo = sorted_list[a + k - 1];
+    thr[s] = r_hi;
+    const double sp = 0.5 * (coord[r_lo] + coord[r_hi]);
+    split_cur[s] = sp;
+    st1[2 * s] = a;
+    st1[2 * s + 1] = a + k;
+    if (s == nseg - 1) st1[2 * nseg] = (int32_t)n;
+    if (h & 1) {
+        const int l = (h - 1) >> 1;
+        const int64_t b = s >> 1;
+        const int xside = (int)(s & 1);
+        const Rect R = rects[level_offset(l) + b];
+        const double sx = split_prev[b];
+        const double xlo = xside ? sx : R.xlo;
+        const double xhi = xside ? R.xhi : sx;
+        const int64_t c0 = level_offset(l + 1) + 4 * b + 2 * xside;
+        rects[c0] = Rect{xlo, xhi, R.ylo, sp};
+        rects[c0 + 1] = Rect{xlo, xhi, sp, R.yhi};
+    }
+}
+
+// Count the low flags of each tile and record, for every segment starting in
+// the tile, the number of low flags in the tile before its start.
+__global__ void __launch_bounds__(PT) k_part_count(const int32_t *__restrict__ key, int64_t n,
+                                                   const int32_t *__restrict__ st, int64_t nseg,
+                                                   const int32_t *__restrict__ thr, int32_t *__restrict__ tcount,
+                                                   int32_t *__restrict__ segbase_local) {
+    __shared__ int32_t tmp[PT / 64];
+    const int64_t i0 = (int64_t)blockIdx.x * PTILE + (int64_t)threadIdx.x * PI;
+    int64_t seg = (i0 < n) ? find_seg(st, nseg, n, i0) : 0;
+    int32_t flags = 0, starts = 0, cnt = 0;
+    int64_t segs[PI];
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {
+        const int64_t i = i0 + r;
+        segs[r] = 0;
+        if (i < n) {
+            while (st[seg + 1] <= i) ++seg;
+            segs[r] = seg;
+            const int32_t f = key[i] < thr[seg];
+            flags |= f << r;
+            starts |= (int32_t)(st[seg] == i) << r;
+            cnt += f;
+        }
+    }
+    int32_t total;
+    int32_t run = block_excl_scan<PT>(cnt, tmp, total);
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {
+        if ((starts >> r) & 1) segbase_local[segs[r]] = run;
+        run += (flags >> r) & 1;
+    }
+    if (threadIdx.x == 0) tcount[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(PT) k_part_scatter(const int32_t *__restrict__ R0, const int32_t *__restrict__ R1,
+                                                     int keysel, int64_t n, const int32_t *__restrict__ st,
+                                                     const int32_t *__restrict__ st1, int64_t nseg,
+                                                     const int32_t *__restrict__ thr, const int32_t *__restrict__ tpre,
+                                                     const int32_t *__restrict__ segbase_local,
+                                                     int32_t *__restrict__ O0, int32_t *__restrict__ O1) {
+    __shared__ int32_t tmp[PT / 64];
+    const int64_t i0 = (int64_t)blockIdx.x * PTILE + (int64_t)threadIdx.x * PI;
+    int64_t seg = (i0 < n) ? find_seg(st, nseg, n, i0) : 0;
+    int32_t v0[PI], v1[PI];
+    int64_t segs[PI];
+    int32_t flags = 0, cnt = 0;
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {
+        const int64_t i = i0 + r;
+        segs[r] = 0;
+        v0[r] = 0;
+        v1[r] = 0;
+        if (i < n) {
+            while (st[seg + 1] <= i) ++seg;
+            segs[r] = seg;
+            v0[r] = R0[i];
+            v1[r] = R1[i];
+            const int32_t f = (keysel ? v1[r] : v0[r]) < thr[seg];
+            flags |= f << r;
+            cnt += f;
+        }
+    }
+    int32_t total;
+    int32_t run = tpre[blockIdx.x] + block_excl_scan<PT>(cnt, tmp, total);
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {
+        const int64_t i = i0 + r;
+        if (i < n) {
+            const int64_t s = segs[r];
+            const int32_t a = st[s];
+            const int32_t lowbase = tpre[a / PTILE] + segbase_local[s];
+            const int32_t below = run - lowbase;  // low flags in the segment before i
+            const int32_t f = (flags >> r) & 1;
+            int64_t dst;
+            if (f) dst = (int64_t)a + below;
+            else dst = (int64_t)st1[2 * s + 1] + ((int32_t)(i - a) - below);
+            O0[dst] = v0[r];
+            O1[dst] = v1[r];
+            run += f;
+        }
+    }
+}
+
+// Centre and radius (half diagonal) of every box, each expression one
+// correctly rounded binary64 operation, no contraction.
+__global__ void k_geometry(const Rect *__restrict__ rects, int64_t nbox, double4 *__restrict__ geom) {
+#pragma clang fp contract(off)
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const Rect R = rects[b];
+    const double cx = 0.5 * (R.xlo + R.xhi);
+    const double cy = 0.5 * (R.ylo + R.yhi);
+    const double w = R.xhi - R.xlo;
+    const double h = R.yhi - R.ylo;
+    const double w2 = w * w;
+    const double h2 = h * h;
+    const double r = 0.5 * sqrt(w2 + h2);
+    geom[b] = make_double4(cx, cy, r, r > 0.0 ? r : 1.0);
+}
+
+__global__ void k_gather(const int32_t *__restrict__ XLx, const int32_t *__restrict__ XLy,
+                         const int32_t *__restrict__ xorder, const double *__restrict__ xs,
+                         const double *__restrict__ ys, const int32_t *__restrict__ stL, int64_t nleaf, int64_t n,
+                         const double4 *__restrict__ geomL, int32_t *__restrict__ perm, double *__restrict__ px,
+                         double *__restrict__ py, float2 *__restrict__ loc, int32_t *__restrict__ leafid) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t xr = XLx[i], yr = XLy[i];
+    perm[i] = xorder[xr];
+    const double x = xs[xr], y = ys[yr];
+    px[i] = x;
+    py[i] = y;
+    const int64_t leaf = find_seg(stL, nleaf, n, i);
+    leafid[i] = (int32_t)leaf;
+    const double4 g = geomL[leaf];
+    loc[i] = make_float2((float)(x - g.x), (float)(y - g.y));
+}
+
+}  // namespace
+
+hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
+    TreeState &t = c->tree;
+    Scratch &s = c->scr;
+    const int64_t n = t.n;
+    const int L = t.L;
+    const int64_t nbox = level_offset(L + 1);
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    FMM2D_TRY(t.xsorted.ensure(sizeof(double) * n));
+    FMM2D_TRY(t.ysorted.ensure(sizeof(double) * n));
+    FMM2D_TRY(t.xorder.ensure(sizeof(int32_t) * n));
+    for (DevBuf *b : {&t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1, &t.perm, &t.leafid})
+        FMM2D_TRY(b->ensure(sizeof(int32_t) * n));
+    FMM2D_TRY(t.starts.ensure(sizeof(int32_t) * (depth_offset(2 * L + 1) + 1)));
+    FMM2D_TRY(t.rects.ensure(sizeof(Rect) * nbox));
+    FMM2D_TRY(t.geom.ensure(sizeof(double4) * nbox));
+    FMM2D_TRY(t.px.ensure(sizeof(double) * n));
+    FMM2D_TRY(t.py.ensure(sizeof(double) * n));
+    FMM2D_TRY(t.loc.ensure(sizeof(float2) * n));
+    const int64_t maxseg = int64_t(1) << (2 * L);
+    FMM2D_TRY(s.thr.ensure(sizeof(int32_t) * maxseg));
+    FMM2D_TRY(s.split0.ensure(sizeof(double) * maxseg));
+    FMM2D_TRY(s.split1.ensure(sizeof(double) * maxseg));
+    FMM2D_TRY(s.segbase.ensure(sizeof(int32_t) * maxseg));
+    const int ntile = (int)((n + PTILE - 1) / PTILE);
+    FMM2D_TRY(s.tiles2.ensure(sizeof(int32_t) * (ntile + 1)));
+
+    // 1. sort each coordinate by (value, index)
+    int32_t *yorder = t.YLx.as<int32_t>();  // borrowed until the lists are initialised
+    FMM2D_TRY(sort_coordinate(c, x, n, t.xsorted.as<double>(), t.xorder.as<int32_t>()));
+    FMM2D_TRY(sort_coordinate(c, y, n, t.ysorted.as<double>(), yorder));
+    // 2. ranks and the two rank lists
+    int32_t *xrank = t.T0.as<int32_t>(), *yrank = t.T1.as<int32_t>();
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.xorder.as<int32_t>(), n, xrank);
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, yorder, n, yrank);
+    // YLx is overwritten last: read yorder (== YLx storage) before writing it.
+    // k_init_lists reads yorder[r] and writes YLx[r] for the same r only.
+    hipLaunchKernelGGL(k_init_lists, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.xorder.as<int32_t>(), yorder,
+                       xrank, yrank, n, t.XLx.as<int32_t>(), t.XLy.as<int32_t>(), t.YLx.as<int32_t>(),
+                       t.YLy.as<int32_t>());
+    int32_t *starts = t.starts.as<int32_t>();
+    Rect *rects = t.rects.as<Rect>();
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, c->stream, t.xsorted.as<double>(), t.ysorted.as<double>(), n,
+                       starts, rects);
+    FMM2D_TRY(hipGetLastError());
+
+    // 3. 2L half-levels of median split + stable partition
+    int32_t *XLx = t.XLx.as<int32_t>(), *XLy = t.XLy.as<int32_t>();
+    int32_t *YLx = t.YLx.as<int32_t>(), *YLy = t.YLy.as<int32_t>();
+    int32_t *T0 = t.T0.as<int32_t>(), *T1 = t.T1.as<int32_t>();
+    for (int h = 0; h < 2 * L; ++h) {
+        const int64_t nseg = int64_t(1) << h;
+        const int32_t *st = starts + depth_offset(h);
+        int32_t *st1 = starts + depth_offset(h + 1);
+        const bool xsplit = (h & 1) == 0;
+        double *split_cur = xsplit ? s.split0.as<double>() : s.split1.as<double>();
+        hipLaunchKernelGGL(k_threshold, dim3(grid_for(nseg, 256)), dim3(256), 0, c->stream, h, nseg, n, st, st1,
+                           xsplit ? XLx : YLy, xsplit ? t.xsorted.as<double>() : t.ysorted.as<double>(),
+                           s.thr.as<int32_t>(), split_cur, s.split0.as<double>(), rects);
+        // partition the other list: YL by x flag, or XL by y flag
+        int32_t *R0 = xsplit ? YLx : XLx;
+        int32_t *R1 = xsplit ? YLy : XLy;
+        const int keysel = xsplit ? 0 : 1;
+        hipLaunchKernelGGL(k_part_count, dim3(ntile), dim3(PT), 0, c->stream, keysel ? R1 : R0, n, st, nseg,
+                           s.thr.as<int32_t>(), s.tiles2.as<int32_t>(), s.segbase.as<int32_t>());
+        FMM2D_TRY(scan_exclusive(c, s.tiles2.as<int32_t>(), ntile, s.tiles2.as<int32_t>() + 0));
+        FMM2D_TRY(hipGetLastError());
+        (void)0;
+        hipLaunchKernelGGL(k_part_scatter, dim3(ntile), dim3(PT), 0, c->stream, R0, R1, keysel, n, st, st1, nseg,
+                           s.thr.as<int32_t>(), s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
+        FMM2D_TRY(hipGetLastError());
+        if (xsplit) {
+            YLx = T0; YLy = T1; T0 = R0; T1 = R1;
+        } else {
+            XLx = T0; XLy = T1; T0 = R0; T1 = R1;
+        }
+    }
+    // remember where the final lists live
+    (void)YLx; (void)YLy;
+
+    // 4. geometry of all boxes, leaf-ordered points and local offsets
+    hipLaunchKernelGGL(k_geometry, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, rects, nbox,
+                       t.geom.as<double4>());
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, XLx, XLy,
+                       t.xorder.as<int32_t>(), t.xsorted.as<double>(), t.ysorted.as<double>(),
+                       starts + depth_offset(2 * L), nleaf, n, t.geom.as<double4>() + level_offset(L),
+                       t.perm.as<int32_t>(), t.px.as<double>(), t.py.as<double>(), t.loc.as<float2>(),
+                       t.leafid.as<int32_t>());
+    return hipGetLastError();
+}
+
+}  // namespace fmm2d

@@ -1,0 +1,141 @@
+"""Python binding of the fmm2d C ABI: argument marshalling only.
+
+Every step runs in the HIP library; this module passes torch device tensors
+(device memory and the current stream come from PyTorch) through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _capi
+
+
+class FMM2DError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fmm2d error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t, dtype, device, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor on %s" % (name, dtype, device))
+
+
+class FMM2D:
+    """A context: one device, one stream, one tree and its lists."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self._lib = _capi.load()
+        self.device = torch.device("cuda", device)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self._lib.fmm2d_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream.cuda_stream))
+        if rc != 0:
+            raise FMM2DError(rc, "fmm2d_create failed")
+        self._h = h
+        self.n = None
+        self.levels = None
+
+    # -- helpers ---------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise FMM2DError(rc, self._lib.fmm2d_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fmm2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def stream(self):
+        return self._stream
+
+    # -- the three stages --------------------------------------------------
+    def build_tree(self, x: torch.Tensor, y: torch.Tensor, levels: int):
+        _require(x, torch.float64, self.device, "x")
+        _require(y, torch.float64, self.device, "y")
+        n = x.numel()
+        if y.numel() != n:
+            raise ValueError("x and y differ in length")
+        self._check(self._lib.fmm2d_build_tree(self._h, _ptr(x), _ptr(y), n, int(levels)))
+        self.n, self.levels = n, int(levels)
+
+    def connectivity(self, theta: float):
+        self._check(self._lib.fmm2d_connectivity(self._h, float(theta)))
+
+    def evaluate(self, q: torch.Tensor, p: int, mode: str = "fp64", out: torch.Tensor | None = None):
+        _require(q, torch.float64, self.device, "q")
+        if self.n is not None and q.numel() != self.n:
+            raise ValueError("q has %d entries, the tree %d" % (q.numel(), self.n))
+        if out is None:
+            out = torch.empty_like(q)
+        _require(out, torch.float64, self.device, "out")
+        self._check(self._lib.fmm2d_evaluate(self._h, _ptr(q), int(p), _capi.MODES[mode], _ptr(out)))
+        return out
+
+    def direct(self, x, y, q, targets: torch.Tensor, out: torch.Tensor | None = None):
+        for t, nm in ((x, "x"), (y, "y"), (q, "q")):
+            _require(t, torch.float64, self.device, nm)
+        _require(targets, torch.int64, self.device, "targets")
+        if out is None:
+            out = torch.empty(targets.numel(), dtype=torch.float64, device=self.device)
+        self._check(self._lib.fmm2d_direct(self._h, _ptr(x), _ptr(y), _ptr(q), x.numel(), _ptr(targets),
+                                           targets.numel(), _ptr(out)))
+        return out
+
+    # -- introspection ------------------------------------------------------
+    def tree_info(self):
+        n, nb = ctypes.c_int64(), ctypes.c_int64()
+        L = ctypes.c_int()
+        self._check(self._lib.fmm2d_tree_info(self._h, ctypes.byref(n), ctypes.byref(L), ctypes.byref(nb)))
+        return n.value, L.value, nb.value
+
+    def perm(self):
+        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        self._check(self._lib.fmm2d_get_perm(self._h, _ptr(out)))
+        return out
+
+    def leaf_start(self):
+        out = torch.empty(4 ** self.levels + 1, dtype=torch.int32, device=self.device)
+        self._check(self._lib.fmm2d_get_leaf_start(self._h, _ptr(out)))
+        return out
+
+    def rects(self):
+        nbox = (4 ** (self.levels + 1) - 1) // 3
+        out = torch.empty((nbox, 4), dtype=torch.float64, device=self.device)
+        self._check(self._lib.fmm2d_get_rects(self._h, _ptr(out)))
+        return out
+
+    def list_sizes(self, level: int):
+        ns, nw = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.fmm2d_list_sizes(self._h, level, ctypes.byref(ns), ctypes.byref(nw)))
+        return ns.value, nw.value
+
+    def lists(self, level: int):
+        ns, nw = self.list_sizes(level)
+        nb = 4 ** level
+        dev = self.device
+        sp = torch.empty(nb + 1, dtype=torch.int32, device=dev)
+        wp = torch.empty(nb + 1, dtype=torch.int32, device=dev)
+        si = torch.empty(max(ns, 1), dtype=torch.int32, device=dev)
+        wi = torch.empty(max(nw, 1), dtype=torch.int32, device=dev)
+        self._check(self._lib.fmm2d_get_lists(self._h, level, _ptr(sp), _ptr(si), _ptr(wp), _ptr(wi)))
+        return sp, si[:ns], wp, wi[:nw]

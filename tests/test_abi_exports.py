@@ -1,0 +1,53 @@
+"""The C-ABI library loads on the CPU and exports every function declared in
+include/fmm2d.h (no compute call: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(fmm2d_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fmm2d_build_tree", "fmm2d_connectivity", "fmm2d_evaluate", "fmm2d_direct"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1006_2269_amd import _capi
+
+    if not os.path.exists(_capi.LIB_PATH):
+        pytest.skip("libfmm2d.so not built")
+    lib = ctypes.CDLL(_capi.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # the Python binding declares exactly the header's functions
+    assert sorted(_capi.exported_names()) == declared_functions()
+
+
+def test_version_and_argument_errors_without_gpu():
+    from paper_1006_2269_amd import _capi
+
+    if not os.path.exists(_capi.LIB_PATH):
+        pytest.skip("libfmm2d.so not built")
+    lib = _capi.load()
+    assert lib.fmm2d_version() >= 100
+    # NULL out-pointer and NULL context are rejected before any device call
+    assert lib.fmm2d_create(None, 0, None) == _capi.EINVAL
+    assert lib.fmm2d_destroy(None) == _capi.EINVAL
+    assert lib.fmm2d_build_tree(None, None, None, 10, 1) == _capi.EINVAL
+    assert lib.fmm2d_connectivity(None, 0.5) == _capi.EINVAL
+    assert lib.fmm2d_evaluate(None, None, 10, 0, None) == _capi.EINVAL
+    assert lib.fmm2d_last_error(None) == b"fmm2d: NULL context"

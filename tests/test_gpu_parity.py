@@ -1,0 +1,154 @@
+"""GPU parity through the C ABI against the CPU oracle.
+
+Tree (permutation, leaf offsets, rectangles) and interaction lists must match
+bit for bit; binary64 potentials must match the oracle FMM to 1e-12 relative
+(normwise, e_inf); the direct-sum judge must match the oracle's direct sum.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1006_2269_amd import workloads as W
+from tests.gpu_cases import TREE_CASES
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    ctx = FMM2D(0)
+    yield ctx
+    ctx.close()
+
+
+def _announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("case", sorted(TREE_CASES))
+def test_tree_bit_exact(fmm, orc, case):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    _announce(case, ps.n, L)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    t = orc.tree(ps.x, ps.y, L)
+    torch.cuda.synchronize()
+    assert np.array_equal(fmm.perm().cpu().numpy().astype(np.int64), t.perm)
+    assert np.array_equal(fmm.leaf_start().cpu().numpy().astype(np.int64), t.leaf_start)
+    got = fmm.rects().cpu().numpy()
+    assert np.array_equal(got.view(np.int64), t.rects.view(np.int64))
+
+
+@pytest.mark.parametrize("case", sorted(TREE_CASES))
+@pytest.mark.parametrize("theta", [0.5, 0.3, 0.75])
+def test_lists_bit_exact(fmm, orc, case, theta):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    _announce(case, ps.n, L, theta)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity(theta)
+    ls = orc.lists(orc.tree(ps.x, ps.y, L), theta)
+    for l in range(L + 1):
+        sp, si, wp, wi = (a.cpu().numpy().astype(np.int64) for a in fmm.lists(l))
+        assert np.array_equal(sp, ls.sptr[l]), l
+        assert np.array_equal(si, ls.sidx[l]), l
+        assert np.array_equal(wp, ls.wptr[l]), l
+        assert np.array_equal(wi, ls.widx[l]), l
+
+
+FP64_CASES = ["uniform_1k_L3", "ties_3k_L4", "ragged_4pow5_plus1", "duplicates_4k_L4", "vertical_2k_L3",
+              "scales_3k_L4", "single_box_L0", "uniform_10k_L5", "mixed_scaled_20k_L6",
+              "clustered_scaled_20k_L6", "ring_scaled_20k_L6"]
+
+
+@pytest.mark.parametrize("case", FP64_CASES)
+@pytest.mark.parametrize("p", [3, 17, 40])
+def test_fp64_potentials_match_oracle_fmm(fmm, orc, case, p):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    theta = 0.5
+    _announce(case, ps.n, L, p)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity(theta)
+    phi = fmm.evaluate(_dev(ps.q), p, "fp64").cpu().numpy()
+    ref = orc.fmm(ps.x, ps.y, ps.q, L, p, theta)
+    scale = np.abs(ref).max()
+    assert np.all(np.isfinite(phi))
+    assert np.abs(phi - ref).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("case", ["uniform_10k_L5", "clustered_scaled_20k_L6", "duplicates_4k_L4", "scales_3k_L4"])
+def test_direct_judge_matches_oracle(fmm, orc, case):
+    maker, _ = TREE_CASES[case]
+    ps = maker()
+    _announce(case, ps.n)
+    tg = W.sample_targets(ps.n, 300, seed=5)
+    got = fmm.direct(_dev(ps.x), _dev(ps.y), _dev(ps.q), _dev(tg)).cpu().numpy()
+    ref = orc.direct(ps.x, ps.y, ps.q, tg)
+    assert np.abs(got - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("mode,tol", [("fp32", 2e-5), ("fp32_acc64", 2e-5), ("bf16x3", 1e-3)])
+@pytest.mark.parametrize("case", ["uniform_10k_L5", "clustered_scaled_20k_L6", "ring_scaled_20k_L6"])
+def test_reduced_modes_error(fmm, orc, case, mode, tol):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    _announce(case, mode)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity(0.5)
+    phi = fmm.evaluate(_dev(ps.q), 20, mode).cpu().numpy()
+    ex = orc.direct(ps.x, ps.y, ps.q)
+    e, _ = orc.rel_errors(phi, ex)
+    assert e <= tol
+
+
+def test_call_order_and_argument_errors(fmm):
+    from paper_1006_2269_amd.fmm import FMM2D, FMM2DError
+
+    ctx = FMM2D(0)
+    q = torch.zeros(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(FMM2DError) as e:
+        ctx.connectivity(0.5)
+    assert e.value.code == -4
+    with pytest.raises(FMM2DError) as e:
+        ctx.evaluate(q, 5)
+    assert e.value.code == -4
+    x = torch.rand(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(FMM2DError) as e:
+        ctx.build_tree(x, x, 3)   # 16 < 4^3
+    assert e.value.code == -1
+    bad = x.clone()
+    bad[3] = float("nan")
+    with pytest.raises(FMM2DError) as e:
+        ctx.build_tree(bad, x, 1)
+    assert e.value.code == -1
+    ctx.build_tree(x, x.flip(0).contiguous(), 1)
+    for th in (0.0, 1.0, -0.5, float("nan")):
+        with pytest.raises(FMM2DError):
+            ctx.connectivity(th)
+    ctx.connectivity(0.5)
+    for p in (0, 64):
+        with pytest.raises(FMM2DError):
+            ctx.evaluate(q, p)
+    with pytest.raises(FMM2DError):
+        ctx.evaluate(q, 5, "fp64") if False else ctx._check(ctx._lib.fmm2d_evaluate(ctx._h, q.data_ptr(), 5, 9, q.data_ptr()))
+    tg = torch.tensor([0, 16], dtype=torch.int64, device="cuda")
+    with pytest.raises(FMM2DError):
+        ctx.direct(x, x, q, tg)
+    ctx.close()
