@@ -169,7 +169,10 @@ void orc_geometry(int64_t nbox, const double *rects, double *geom)
     }
 }
 
-/* Criterion 2.1: well separated iff R + theta*r <= theta*d.                 */
+/* Criterion 2.1: well separated iff R + theta*r <= theta*d.  The criterion
+ * is stated for sets inside two disjoint balls; with theta < 1 the inequality
+ * forces d >= R + r, with equality only for two zero-size balls at one point,
+ * which are not disjoint: such a pair (d = 0) is never well separated.      */
 int orc_theta_test(double theta, const double *gb, const double *gc)
 {
     double dx = gb[0] - gc[0];
@@ -181,7 +184,7 @@ int orc_theta_test(double theta, const double *gb, const double *gc)
     double r = gb[2] > gc[2] ? gc[2] : gb[2];
     double lhs = R + theta * r;
     double rhs = theta * d;
-    return lhs <= rhs;
+    return lhs <= rhs && rhs > 0.0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -18,14 +18,16 @@ from paper_1006_2269_amd import workloads as W
 
 
 def separated_exact(theta, gb, gc):
-    """R + theta r <= theta d, decided exactly on the binary64 inputs."""
+    """R + theta r <= theta d for disjoint balls, decided exactly on the
+    binary64 inputs."""
     t = Fraction(theta)
     rb, rc = Fraction(gb[2]), Fraction(gc[2])
     R, r = max(rb, rc), min(rb, rc)
     dx = Fraction(gb[0]) - Fraction(gc[0])
     dy = Fraction(gb[1]) - Fraction(gc[1])
     lhs = R + t * r
-    return lhs * lhs <= t * t * (dx * dx + dy * dy)
+    d2 = dx * dx + dy * dy
+    return lhs * lhs <= t * t * d2 and d2 > 0
 
 
 def test_criterion_boundary_cases(orc):
@@ -37,6 +39,10 @@ def test_criterion_boundary_cases(orc):
     assert orc.theta_test(th, [0.0, 0.0, 2.0], [3.0, 4.0, 1.0])
     assert orc.theta_test(th, [3.0, 4.0, 1.0], [0.0, 0.0, 2.0])          # symmetric
     assert not orc.theta_test(th, [0.0, 0.0, 2.0], [3.0, 3.99, 1.0])
+    # two zero-size balls at one point are not disjoint: never separated;
+    # at distinct points they are
+    assert not orc.theta_test(th, [0.5, 0.5, 0.0], [0.5, 0.5, 0.0])
+    assert orc.theta_test(th, [0.5, 0.5, 0.0], [0.5, 0.5000001, 0.0])
     # a smaller theta is stricter
     assert not orc.theta_test(0.25, [0.0, 0.0, 2.0], [3.0, 4.0, 1.0])
     g = np.random.Generator(np.random.PCG64(3))
