@@ -142,6 +142,29 @@ int fmm2d_list_sizes(const fmm2d_ctx *ctx, int level, int64_t *n_strong, int64_t
 int fmm2d_get_lists(fmm2d_ctx *ctx, int level, int32_t *sptr, int32_t *sidx,
                     int32_t *wptr, int32_t *widx);
 
+/* ---- per-phase GPU timing ------------------------------------------------ */
+
+/* Phases timed by fmm2d_get_timings (index into its output arrays). */
+#define FMM2D_PHASE_TREE    0  /* build_tree: sorts, splits, geometry, gather */
+#define FMM2D_PHASE_LISTS   1  /* connectivity                                */
+#define FMM2D_PHASE_UPWARD  2  /* P2M and M2M                                 */
+#define FMM2D_PHASE_M2L     3  /* M2L along the weak lists (all levels)       */
+#define FMM2D_PHASE_L2L     4  /* L2L                                         */
+#define FMM2D_PHASE_LEAF    5  /* L2P plus the near field (one launch)        */
+#define FMM2D_PHASE_OTHER   6  /* charge gather, scatter to input order       */
+#define FMM2D_PHASE_JUDGE   7  /* fmm2d_direct                                */
+#define FMM2D_PHASE_SELECT  8  /* parameter selection                         */
+#define FMM2D_NPHASE        9
+
+/* enable = 1 clears the accumulated timings and starts recording HIP events
+ * on the context stream around each phase; enable = 0 stops recording. */
+int fmm2d_timing(fmm2d_ctx *ctx, int enable);
+
+/* Host outputs ms[FMM2D_NPHASE] (accumulated GPU milliseconds) and
+ * count[FMM2D_NPHASE] (number of timed intervals) since timing was enabled.
+ * Synchronises the context stream.  Either pointer may be NULL. */
+int fmm2d_get_timings(fmm2d_ctx *ctx, double *ms, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

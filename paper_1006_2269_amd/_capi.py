@@ -43,7 +43,11 @@ SIGNATURES = [
     ("fmm2d_get_rects", I32, [P, P]),
     ("fmm2d_list_sizes", I32, [P, I32, PI64, PI64]),
     ("fmm2d_get_lists", I32, [P, I32, P, P, P, P]),
+    ("fmm2d_timing", I32, [P, I32]),
+    ("fmm2d_get_timings", I32, [P, P, P]),
 ]
+
+PHASES = ["tree", "lists", "upward", "m2l", "l2l", "leaf", "other", "judge", "select"]
 
 
 def load():

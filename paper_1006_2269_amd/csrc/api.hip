@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <new>
 
 #include "devutil.h"
@@ -72,6 +73,10 @@ int fmm2d_create(fmm2d_ctx **out, int device, void *stream) {
     if (!c) return FMM2D_ENOMEM;
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
+    if (const char *lim = getenv("FMM2D_LIST_LIMIT")) {
+        const long long v = atoll(lim);
+        if (v > 0 && v < c->list_limit) c->list_limit = v;
+    }
     *out = c;
     return FMM2D_OK;
 }
@@ -87,8 +92,9 @@ int fmm2d_destroy(fmm2d_ctx *c) {
                           &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state})
             b->release();
         EvalState &e = c->ev;
-        for (DevBuf *b : {&e.binom, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();
+        for (DevBuf *b : {&e.binom, &e.mhat, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();
         Scratch &s = c->scr;
+        for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
         for (DevBuf *b : {&s.keys0, &s.keys1, &s.vals0, &s.vals1, &s.hist, &s.aux, &s.tiles, &s.tiles2, &s.segbase,
                           &s.thr, &s.split0, &s.split1, &s.flag})
             b->release();
@@ -135,7 +141,11 @@ int fmm2d_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, 
     t.has_lists = false;
     t.n = n;
     t.L = levels;
-    if ((e = build_tree_device(c, x, y)) != hipSuccess) {
+    {
+        PhaseScope ps(c, PH_TREE);
+        e = build_tree_device(c, x, y);
+    }
+    if (e != hipSuccess) {
         t.L = -1;
         return hip_fail(c, e, "build_tree");
     }
@@ -151,25 +161,36 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
     DeviceGuard g(c->device);
     const int64_t nbox = level_offset(t.L + 1);
     int64_t cap_s = 32 * nbox + 64, cap_w = 96 * nbox + 64;
-    for (int attempt = 0; attempt < 8; ++attempt) {
-        bool overflow = false;
-        hipError_t e = build_lists_device(c, theta, cap_s, cap_w, &overflow);
+    const int64_t pool_max = int64_t(1) << 34;  // entries per pool, all levels together
+    for (int attempt = 0; attempt < 16; ++attempt) {
+        int overflow = 0;
+        hipError_t e;
+        {
+            PhaseScope ps(c, PH_LISTS);
+            e = build_lists_device(c, theta, cap_s, cap_w, c->list_limit, &overflow);
+        }
         if (e != hipSuccess) {
             t.has_lists = false;
             return hip_fail(c, e, "connectivity");
         }
-        if (!overflow) {
+        if (overflow == 0) {
             t.has_lists = true;
             t.theta = theta;
             return FMM2D_OK;
         }
-        cap_s *= 4;
-        cap_w *= 4;
-        if (cap_s > 2147483647LL) cap_s = 2147483647LL;
-        if (cap_w > 2147483647LL) cap_w = 2147483647LL;
+        if (overflow == 2) {
+            t.has_lists = false;
+            return fail(c, FMM2D_ENOMEM,
+                        "connectivity: a level's strong or weak list exceeds %lld entries (choose fewer levels or "
+                        "another theta for this point set)",
+                        (long long)c->list_limit);
+        }
+        if (cap_s >= pool_max && cap_w >= pool_max) break;
+        cap_s = cap_s * 4 < pool_max ? cap_s * 4 : pool_max;
+        cap_w = cap_w * 4 < pool_max ? cap_w * 4 : pool_max;
     }
     t.has_lists = false;
-    return fail(c, FMM2D_ENOMEM, "connectivity: interaction lists exceed 2^31 entries");
+    return fail(c, FMM2D_ENOMEM, "connectivity: interaction lists exceed 2^34 entries");
 }
 
 int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) {
@@ -204,7 +225,11 @@ int fmm2d_direct(fmm2d_ctx *c, const double *x, const double *y, const double *q
         (e = hipStreamSynchronize(c->stream)) != hipSuccess)
         return hip_fail(c, e, "direct");
     if (hf[1]) return fail(c, FMM2D_EINVAL, "direct: a target index is outside [0, n)");
-    if ((e = direct_device(c, x, y, q, n, targets, m, phi_m)) != hipSuccess) return hip_fail(c, e, "direct");
+    {
+        PhaseScope ps(c, PH_JUDGE);
+        e = direct_device(c, x, y, q, n, targets, m, phi_m);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "direct");
     return FMM2D_OK;
 }
 
@@ -283,6 +308,41 @@ int fmm2d_get_lists(fmm2d_ctx *c, int level, int32_t *sptr, int32_t *sidx, int32
         e = hipMemcpyAsync(widx, t.widx.as<int32_t>() + t.w_off[level], sizeof(int32_t) * nw, hipMemcpyDeviceToDevice,
                            c->stream);
     return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_lists");
+}
+
+int fmm2d_timing(fmm2d_ctx *c, int enable) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (enable) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "timing");
+        c->timer.marks.clear();
+        c->timer.used = 0;
+    }
+    c->timer.on = enable != 0;
+    return FMM2D_OK;
+}
+
+int fmm2d_get_timings(fmm2d_ctx *c, double *ms, int64_t *count) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "get_timings");
+    double acc[PH_COUNT] = {0};
+    int64_t cnt[PH_COUNT] = {0};
+    for (const auto &m : c->timer.marks) {
+        float t = 0.f;
+        if ((e = hipEventElapsedTime(&t, m.a, m.b)) != hipSuccess) return hip_fail(c, e, "get_timings");
+        acc[m.phase] += t;
+        cnt[m.phase] += 1;
+    }
+    for (int k = 0; k < PH_COUNT; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (count) count[k] = cnt[k];
+    }
+    return FMM2D_OK;
 }
 
 }  // extern "C"

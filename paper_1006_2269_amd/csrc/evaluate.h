@@ -7,10 +7,12 @@
 namespace fmm2d {
 
 hipError_t ensure_binomials(fmm2d_ctx *c);
-// M2L of level l in a reduced-precision mode (FP32, BF16X3, FP32_ACC64).
-hipError_t m2l_reduced_level(fmm2d_ctx *c, int l, int p, int mode);
-// L2P plus the near field at the leaves in a reduced-precision mode; writes
-// the leaf-ordered potentials to ev.phi_leaf.
-hipError_t leaf_reduced(fmm2d_ctx *c, int p, int mode);
+// constant M2L matrix (m2l.hip)
+hipError_t ensure_mhat(fmm2d_ctx *c);
+// M2L of level l along its weak lists, in precision `mode` (m2l.hip).
+hipError_t m2l_level(fmm2d_ctx *c, int l, int p, int mode);
+// L2P plus the near field at the leaves in precision `mode`; writes the
+// leaf-ordered potentials to ev.phi_leaf (near.hip).
+hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode);
 
 }  // namespace fmm2d

@@ -9,9 +9,9 @@
 // values (box-major), boxes numbered level by level.
 //
 // Order of the passes: P2M at the leaves, M2M to the root; then for each
-// level from the root down, M2L along that level's weak lists followed by L2L
-// to the next level; finally L2P and the near-field sum over the finest
-// strong lists, and the scatter back to input order.
+// level from the root down, M2L along that level's weak lists (m2l.hip)
+// followed by L2L to the next level; finally L2P and the near-field sum over
+// the finest strong lists (near.hip), and the scatter back to input order.
 #include <vector>
 
 #include "devutil.h"
@@ -119,49 +119,6 @@ __global__ void __launch_bounds__(64) k_m2m(int l, int p, const double4 *__restr
     if (lane <= p) A[pbox * (p + 1) + lane] = acc;
 }
 
-// ---- M2L in binary64: one wavefront per target box, lane l = coefficient ---
-__global__ void __launch_bounds__(64) k_m2l_fp64(int l, int p, const double4 *__restrict__ geomL,
-                                                 const int32_t *__restrict__ wptr, const int32_t *__restrict__ widx,
-                                                 const cd *__restrict__ AL, cd *__restrict__ BL,
-                                                 const double *__restrict__ binom) {
-    __shared__ cd u[64];
-    const int64_t b = blockIdx.x;
-    const int lane = (int)lane_id();
-    const double4 gb = geomL[b];
-    cd acc{0.0, 0.0};
-    const int32_t t0 = wptr[b], t1 = wptr[b + 1];
-    for (int32_t t = t0; t < t1; ++t) {
-        const int32_t c = widx[t];
-        const double4 gc = geomL[c];
-        const cd z0{gc.x - gb.x, gc.y - gb.y};
-        const cd rs = cdiv(cd{gc.w, 0.0}, z0);
-        const cd rt = cdiv(cd{gb.w, 0.0}, z0);
-        const cd ps = wave_powers(rs);
-        const cd pt = wave_powers(rt);
-        if (lane <= p) u[lane] = cmul(AL[(int64_t)c * (p + 1) + lane], ps);
-        __syncthreads();
-        if (lane <= p) {
-            cd w;
-            if (lane == 0) {
-                w = cscale(u[0], log(hypot(z0.re, z0.im)));
-                for (int k = 1; k <= p; ++k) w = (k & 1) ? csub(w, u[k]) : cadd(w, u[k]);
-            } else {
-                w = cscale(u[0], -1.0 / lane);
-                for (int k = 1; k <= p; ++k) {
-                    const double m = ((k & 1) ? -1.0 : 1.0) * binom[(lane + k - 1) * BN + (k - 1)];
-                    w = cadd(w, cscale(u[k], m));
-                }
-            }
-            acc = cadd(acc, cmul(pt, w));
-        }
-        __syncthreads();
-    }
-    if (lane <= p && t1 > t0) {
-        cd *o = BL + b * (p + 1) + lane;
-        *o = cadd(*o, acc);
-    }
-}
-
 // ---- L2L: one wavefront per child box, lane l = coefficient ----------------
 __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restrict__ geom, cd *__restrict__ B,
                                             const double *__restrict__ binom) {
@@ -184,33 +141,6 @@ __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restr
         for (int k = lane; k <= p; ++k) t = cadd(t, cscale(cmul(Bp[k], dp[k - lane]), binom[k * BN + lane]));
         B[cbox * (p + 1) + lane] = cscale(t, tpow);
     }
-}
-
-// ---- L2P + near field in binary64: one thread per point --------------------
-__global__ void __launch_bounds__(256) k_leaf_fp64(int p, int64_t n, const double *__restrict__ px,
-                                                   const double *__restrict__ py, const double *__restrict__ qs,
-                                                   const int32_t *__restrict__ leafid, const int32_t *__restrict__ stL,
-                                                   const double4 *__restrict__ geomL, const cd *__restrict__ BL,
-                                                   const int32_t *__restrict__ sptr, const int32_t *__restrict__ sidx,
-                                                   double *__restrict__ phi_leaf) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t b = leafid[i];
-    const double4 g = geomL[b];
-    const double xi = px[i], yi = py[i];
-    const cd z{(xi - g.x) / g.w, (yi - g.y) / g.w};
-    const cd *Bb = BL + (int64_t)b * (p + 1);
-    cd v = Bb[p];
-    for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
-    double near = 0.0;
-    for (int32_t t = sptr[b]; t < sptr[b + 1]; ++t) {
-        const int32_t cb = sidx[t];
-        for (int32_t j = stL[cb]; j < stL[cb + 1]; ++j) {
-            const double dx = xi - px[j], dy = yi - py[j];
-            if (dx != 0.0 || dy != 0.0) near += qs[j] * (0.5 * log(dx * dx + dy * dy));
-        }
-    }
-    phi_leaf[i] = v.re + near;
 }
 
 __global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restrict__ perm, int64_t n,
@@ -258,7 +188,7 @@ hipError_t ensure_binomials(fmm2d_ctx *c) {
 }
 
 // Upward pass (P2M, M2M) and downward pass (M2L, L2L), binary64 operators,
-// with M2L done by `m2l` (the binary64 kernel or a reduced-precision one).
+// (M2L itself is in m2l.hip.)
 hipError_t upward_pass(fmm2d_ctx *c, int p) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
@@ -280,18 +210,6 @@ hipError_t upward_pass(fmm2d_ctx *c, int p) {
     return hipGetLastError();
 }
 
-hipError_t m2l_fp64_level(fmm2d_ctx *c, int l, int p) {
-    TreeState &t = c->tree;
-    EvalState &e = c->ev;
-    const int64_t nb = int64_t(1) << (2 * l);
-    if (t.w_off[l + 1] == t.w_off[l]) return hipSuccess;
-    hipLaunchKernelGGL(k_m2l_fp64, dim3((unsigned)nb), dim3(64), 0, c->stream, l, p,
-                       t.geom.as<double4>() + level_offset(l), t.wptr.as<int32_t>() + ptr_offset(l),
-                       t.widx.as<int32_t>() + t.w_off[l], e.A.as<cd>() + level_offset(l) * (p + 1),
-                       e.B.as<cd>() + level_offset(l) * (p + 1), e.binom.as<double>());
-    return hipGetLastError();
-}
-
 hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
@@ -306,36 +224,40 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
     const int64_t n = t.n;
     const int L = t.L;
     const int64_t nbox = level_offset(L + 1);
-    FMM2D_TRY(ensure_binomials(c));
+    FMM2D_TRY(ensure_mhat(c));
     FMM2D_TRY(e.A.ensure(sizeof(cd) * nbox * (p + 1)));
     FMM2D_TRY(e.B.ensure(sizeof(cd) * nbox * (p + 1)));
     FMM2D_TRY(e.qs.ensure(sizeof(double) * n));
     FMM2D_TRY(e.phi_leaf.ensure(sizeof(double) * n));
-    hipLaunchKernelGGL(k_gather_q, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, q, t.perm.as<int32_t>(), n,
-                       e.qs.as<double>());
-    FMM2D_TRY(upward_pass(c, p));
-    hipLaunchKernelGGL(k_zero_cd, dim3(1), dim3(64), 0, c->stream, e.B.as<cd>(), (int64_t)(p + 1));
+    {
+        PhaseScope ps(c, PH_OTHER);
+        hipLaunchKernelGGL(k_gather_q, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, q, t.perm.as<int32_t>(), n,
+                           e.qs.as<double>());
+        hipLaunchKernelGGL(k_zero_cd, dim3(1), dim3(64), 0, c->stream, e.B.as<cd>(), (int64_t)(p + 1));
+    }
+    {
+        PhaseScope ps(c, PH_UPWARD);
+        FMM2D_TRY(upward_pass(c, p));
+    }
     for (int l = 0; l <= L; ++l) {
         if (l >= 1) {
-            if (mode == FMM2D_MODE_FP64) FMM2D_TRY(m2l_fp64_level(c, l, p));
-            else FMM2D_TRY(m2l_reduced_level(c, l, p, mode));
+            PhaseScope ps(c, PH_M2L);
+            FMM2D_TRY(m2l_level(c, l, p, mode));
         }
-        if (l < L) FMM2D_TRY(l2l_level(c, l, p));
+        if (l < L) {
+            PhaseScope ps(c, PH_L2L);
+            FMM2D_TRY(l2l_level(c, l, p));
+        }
     }
-    const int64_t offL = level_offset(L);
-    const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
-    const int32_t *sptrL = t.sptr.as<int32_t>() + ptr_offset(L);
-    const int32_t *sidxL = t.sidx.as<int32_t>() + t.s_off[L];
-    if (mode == FMM2D_MODE_FP64) {
-        hipLaunchKernelGGL(k_leaf_fp64, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, p, n, t.px.as<double>(),
-                           t.py.as<double>(), e.qs.as<double>(), t.leafid.as<int32_t>(), stL,
-                           t.geom.as<double4>() + offL, e.B.as<cd>() + offL * (p + 1), sptrL, sidxL,
-                           e.phi_leaf.as<double>());
-    } else {
-        FMM2D_TRY(leaf_reduced(c, p, mode));
+    {
+        PhaseScope ps(c, PH_LEAF);
+        FMM2D_TRY(leaf_pass(c, p, mode));
     }
-    hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, e.phi_leaf.as<double>(),
-                       t.perm.as<int32_t>(), n, phi);
+    {
+        PhaseScope ps(c, PH_OTHER);
+        hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, e.phi_leaf.as<double>(),
+                           t.perm.as<int32_t>(), n, phi);
+    }
     return hipGetLastError();
 }
 

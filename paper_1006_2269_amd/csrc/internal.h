@@ -24,15 +24,30 @@ __host__ __device__ inline int64_t depth_offset(int d) { return ((int64_t(1) << 
 struct DevBuf {
     void *ptr = nullptr;
     size_t cap = 0;
+    // Growing frees the old allocation only after the device is idle, so a
+    // kernel still queued on any stream can never touch freed memory.
     hipError_t ensure(size_t bytes) {
         if (bytes <= cap && ptr) return hipSuccess;
-        if (ptr) { hipError_t e = hipFree(ptr); ptr = nullptr; cap = 0; if (e != hipSuccess) return e; }
+        if (ptr) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e == hipSuccess) e = hipFree(ptr);
+            ptr = nullptr;
+            cap = 0;
+            if (e != hipSuccess) return e;
+        }
         size_t b = bytes < 256 ? 256 : bytes;
         hipError_t e = hipMalloc(&ptr, b);
         if (e == hipSuccess) cap = b;
         return e;
     }
-    void release() { if (ptr) (void)hipFree(ptr); ptr = nullptr; cap = 0; }
+    void release() {
+        if (ptr) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(ptr);
+        }
+        ptr = nullptr;
+        cap = 0;
+    }
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
@@ -54,7 +69,7 @@ struct TreeState {
     DevBuf loc;             // float2 [n], offsets from the leaf centre
     // lists: row pointers of every level (ptr_offset), index pools
     DevBuf sptr, wptr, sidx, widx, cnt_s, cnt_w;
-    DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
+    DevBuf pool_state;      // int64 [2 (L+2) + 3]: s offsets, w offsets, overflow, level totals
     std::vector<int64_t> s_off, w_off;  // host copy: pool offset of each level
     bool has_lists = false;
     double theta = 0.0;
@@ -63,11 +78,36 @@ struct TreeState {
 struct EvalState {
     DevBuf binom;           // double [128][128] binomial coefficients
     bool binom_ready = false;
+    DevBuf mhat;            // double [64][64] rescaled constant M2L matrix
+    bool mhat_ready = false;
     DevBuf A, B;            // expansions, complex<double> [nbox][p+1]
     DevBuf qs;              // double [n] charges in leaf order
     DevBuf phi_leaf;        // double [n]
     DevBuf work;            // mode-dependent scratch
     DevBuf src;             // float4 [n]: FP32 local offsets and charge
+};
+
+// Per-phase GPU time, measured with HIP events recorded on the context stream
+// around each phase's launches while timing is enabled.
+enum Phase { PH_TREE = 0, PH_LISTS, PH_UPWARD, PH_M2L, PH_L2L, PH_LEAF, PH_OTHER, PH_JUDGE, PH_SELECT, PH_COUNT };
+
+struct PhaseTimer {
+    bool on = false;
+    struct Mark {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Mark> marks;
+    hipEvent_t next() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
 };
 
 struct Scratch {
@@ -78,11 +118,13 @@ struct Scratch {
 
 struct fmm2d_ctx {
     int device = 0;
+    int64_t list_limit = 2147483647LL;  // entries per level and list (FMM2D_LIST_LIMIT lowers it)
     hipStream_t stream = nullptr;
     std::string err;
     fmm2d::TreeState tree;
     fmm2d::EvalState ev;
     fmm2d::Scratch scr;
+    fmm2d::PhaseTimer timer;
 };
 
 namespace fmm2d {
@@ -95,12 +137,30 @@ hipError_t scan_exclusive(fmm2d_ctx *c, const int32_t *in, int64_t n, int32_t *o
 // tree.hip
 hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y);
 // lists.hip
-hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t cap_w, bool *overflow);
+// overflow: 0 ok, 1 a pool was too small (grow and retry), 2 a level exceeds `limit` entries
+hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t cap_w, int64_t limit,
+                              int *overflow);
 // expand.hip
 hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, double *phi);
 // judge.hip
 hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
                          const int64_t *targets, int64_t m, double *phi);
+
+// Brackets the launches of one phase with two events when timing is on.
+struct PhaseScope {
+    fmm2d_ctx *c;
+    int phase;
+    hipEvent_t a = nullptr;
+    PhaseScope(fmm2d_ctx *ctx, int ph) : c(ctx), phase(ph) {
+        if (c->timer.on && (a = c->timer.next())) (void)hipEventRecord(a, c->stream);
+    }
+    ~PhaseScope() {
+        if (a) {
+            hipEvent_t b = c->timer.next();
+            if (b && hipEventRecord(b, c->stream) == hipSuccess) c->timer.marks.push_back({phase, a, b});
+        }
+    }
+};
 
 inline unsigned grid_for(int64_t work, int per_block) {
     int64_t g = (work + per_block - 1) / per_block;

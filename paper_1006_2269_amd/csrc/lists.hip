@@ -8,7 +8,13 @@
 // ascending.  Each level is a count pass, an exclusive scan of the counts
 // (the CSR row pointers) and a fill pass.  The index lists of all levels live
 // in two pools; the pool offset of each level is advanced on the device, and
-// the host reads the offsets (and an overflow flag) once, at the end.
+// the host reads the offsets (and an overflow flag) at the end.
+//
+// Row pointers are int32.  A level's candidates number 16 |S_{l-1}| (four
+// children of each of the four children's parents' strong boxes), so the
+// host reads each level's two list totals (one small copy and a stream
+// synchronisation per level) and refuses a level whose candidate count could
+// exceed the entry limit before launching it: no int32 prefix sum can wrap.
 #include "devutil.h"
 #include "internal.h"
 
@@ -30,7 +36,8 @@ __device__ inline bool theta_separated(double theta, double4 gb, double4 gc) {
     const double r = gb.z > gc.z ? gc.z : gb.z;
     const double lhs = R + theta * r;
     const double rhs = theta * d;
-    return lhs <= rhs;
+    // balls must be disjoint: two zero-size boxes at one point (d = 0) never are
+    return lhs <= rhs && rhs > 0.0;
 }
 
 __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool, int64_t *pool_state, int L) {
@@ -107,7 +114,8 @@ __global__ void k_lists_advance(int l, int L, int64_t nb, const int32_t *sptr_cu
 
 }  // namespace
 
-hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t cap_w, bool *overflow) {
+hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t cap_w, int64_t limit,
+                              int *overflow) {
     TreeState &t = c->tree;
     const int L = t.L;
     const int64_t nptr = ptr_offset(L + 1);
@@ -123,7 +131,13 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     int64_t *ps = t.pool_state.as<int64_t>();
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L);
     const double4 *geom = t.geom.as<double4>();
+    int64_t s_prev = 1;  // entries of S at level l-1 (level 0: the root)
     for (int l = 1; l <= L; ++l) {
+        if (16 * s_prev > limit) {
+            FMM2D_TRY(hipStreamSynchronize(c->stream));
+            *overflow = 2;
+            return hipSuccess;
+        }
         const int64_t nb = int64_t(1) << (2 * l);
         const double4 *gL = geom + level_offset(l);
         const unsigned grid = grid_for(nb, LW);
@@ -133,6 +147,13 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
                            t.sidx.as<int32_t>(), t.widx.as<int32_t>());
         FMM2D_TRY(scan_exclusive(c, t.cnt_s.as<int32_t>(), nb, sp_cur));
         FMM2D_TRY(scan_exclusive(c, t.cnt_w.as<int32_t>(), nb, wp_cur));
+        {
+            int32_t h2[2] = {0, 0};
+            FMM2D_TRY(hipMemcpyAsync(h2, sp_cur + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            FMM2D_TRY(hipMemcpyAsync(h2 + 1, wp_cur + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            FMM2D_TRY(hipStreamSynchronize(c->stream));
+            s_prev = h2[0];
+        }
         hipLaunchKernelGGL(k_lists_advance, dim3(1), dim3(1), 0, c->stream, l, L, nb, sp_cur, wp_cur, ps, cap_s,
                            cap_w);
         hipLaunchKernelGGL(k_lists_level<true>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
@@ -143,7 +164,7 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     std::vector<int64_t> h(2 * L + 5);
     FMM2D_TRY(hipMemcpyAsync(h.data(), ps, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
     FMM2D_TRY(hipStreamSynchronize(c->stream));
-    *overflow = h[2 * L + 4] != 0;
+    *overflow = h[2 * L + 4] != 0 ? 1 : 0;
     t.s_off.assign(h.begin(), h.begin() + (L + 2));
     t.w_off.assign(h.begin() + (L + 2), h.begin() + (2 * L + 4));
     return hipSuccess;

@@ -1,0 +1,248 @@
+// M2L along the weak lists (the far-to-local shift of Section 4), done as one
+// constant matrix applied to every pair's pre-scaled multipole vector, with
+// pre- and post-scaling by the pair's geometry.
+//
+// For a weak pair (target b, source c), z0 = c_c - c_b, rho_s = s_c / z0,
+// rho_t = s_b / z0, u_k = A_k rho_s^k, the local coefficients of b gain
+//   B_0 += A_0 log|z0| + sum_{k>=1} M_0k u_k,   B_l += rho_t^l sum_k M_lk u_k,
+// with the constant real matrix M_00 = 0, M_0k = (-1)^k, M_l0 = -1/l and
+// M_lk = (-1)^k C(l+k-1, k-1) (the multipole series re-expanded in powers of
+// (z - c_b)/z0).  Exact power-of-two rescaling, M^_lk = M_lk / 2^(l+k),
+// u'_k = 2^k u_k, T'_l = 2^l rho_t^l, keeps every matrix entry below one.
+//
+// One wavefront per target box walks its weak list in chunks of 16 pairs.
+// Four lanes per pair build that pair's power tables in binary64 (binary
+// exponentiation to the lane's first power, then successive products) into
+// LDS.  The 16x16x4 matrix instruction multiplies a 16-row block (8 pairs x
+// real/imaginary part) of u' by M^T, which every lane keeps in registers;
+// each lane then post-scales its output elements by T' and accumulates its
+// coefficient l.  A cross-lane reduction adds the box's total into B.
+//
+// Variants: the product in FP32 (f32 matrix instruction) or binary64 (f64
+// matrix instruction); accumulation of B in FP32 or binary64.
+#include "evaluate.h"
+
+namespace fmm2d {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename G>
+struct Mfma;
+// Operand A of the 16x16x4 instructions: lane i supplies A[i % 16][i / 16];
+// operand B: lane i supplies B[i / 16][i % 16].  The accumulator layouts
+// differ (measured on gfx950): element r of lane i holds D[4 (i/16) + r][i % 16]
+// for f32 and D[i/16 + 4 r][i % 16] for f64.  Each variant therefore maps an
+// operand row to (pair, real/imaginary part) so that element r of lane group
+// g = i / 16 always holds pair 2g + r/2, part r % 2.
+template <>
+struct Mfma<float> {
+    using V = v4f;
+    static __device__ inline V run(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int pair_of_row(int row) { return row >> 1; }
+    static __device__ inline int part_of_row(int row) { return row & 1; }
+};
+template <>
+struct Mfma<double> {
+    using V = v4d;
+    static __device__ inline V run(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int pair_of_row(int row) { return 2 * (row & 3) + (row >> 3); }
+    static __device__ inline int part_of_row(int row) { return (row >> 2) & 1; }
+};
+
+constexpr int CP = 16;   // pairs per chunk (two 16-row blocks)
+constexpr int LPP = 4;   // lanes per pair for the power tables
+
+__device__ inline cd cpow_int(cd z, int n) {
+    cd r{1.0, 0.0};
+    while (n) {
+        if (n & 1) r = cmul(r, z);
+        z = cmul(z, z);
+        n >>= 1;
+    }
+    return r;
+}
+
+template <int NT, typename G, typename ACC>
+__global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ geomL, const int32_t *__restrict__ wptr,
+                                            const int32_t *__restrict__ widx, const cd *__restrict__ AL,
+                                            cd *__restrict__ BL, const double *__restrict__ Mhat) {
+    using MF = Mfma<G>;
+    using V = typename MF::V;
+    constexpr int KSMAX = 4 * NT;
+    __shared__ G Ur[CP][64], Ui[CP][64];
+    __shared__ double Tr[CP][64], Ti[CP][64];
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t t0 = wptr[b], t1 = wptr[b + 1];
+    if (t1 == t0) return;  // the block is one wavefront: uniform exit
+    const int P1 = p + 1;
+    const int ks_n = (P1 + 3) / 4;
+    const int KR = (P1 + LPP - 1) / LPP;  // LPP * KR == 4 * ks_n: every padded k is written
+    const double4 gb = geomL[b];
+    G mreg[KSMAX][NT];
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks)
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl) {
+            const int k = 4 * ks + lane / 16, l = 16 * tl + lane % 16;
+            mreg[ks][tl] = (k < P1 && l < P1) ? (G)Mhat[l * 64 + k] : (G)0;
+        }
+    ACC accr[NT], acci[NT];
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl) { accr[tl] = 0; acci[tl] = 0; }
+    double ext0 = 0.0;
+    const int q = lane / LPP, slot = lane % LPP;
+    const int k0 = slot * KR;
+    for (int32_t t = t0; t < t1; t += CP) {
+        const int np = (t1 - t) < CP ? (t1 - t) : CP;
+        if (q < np) {
+            const int32_t c = widx[t + q];
+            const double4 gc = geomL[c];
+            const cd z0{gc.x - gb.x, gc.y - gb.y};
+            const cd rs = cdiv(cd{gc.w, 0.0}, z0), rt = cdiv(cd{gb.w, 0.0}, z0);
+            cd ws = cpow_int(rs, k0), wt = cpow_int(rt, k0);
+            double sc2 = ldexp(1.0, k0);
+            const cd *Ac = AL + (int64_t)c * P1;
+            for (int kk = 0; kk < KR; ++kk) {
+                const int k = k0 + kk;
+                if (k < P1) {
+                    const cd u = cmul(Ac[k], ws);
+                    Ur[q][k] = (G)(u.re * sc2);
+                    Ui[q][k] = (G)(u.im * sc2);
+                    Tr[q][k] = wt.re * sc2;
+                    Ti[q][k] = wt.im * sc2;
+                } else if (k < 64) {
+                    Ur[q][k] = (G)0;
+                    Ui[q][k] = (G)0;
+                    Tr[q][k] = 0.0;
+                    Ti[q][k] = 0.0;
+                }
+                ws = cmul(ws, rs);
+                wt = cmul(wt, rt);
+                sc2 *= 2.0;
+            }
+            if (slot == 0) ext0 += Ac[0].re * log(hypot(z0.re, z0.im));
+        } else {
+            for (int kk = 0; kk < KR; ++kk) {
+                const int k = k0 + kk;
+                if (k < 64) {
+                    Ur[q][k] = (G)0;
+                    Ui[q][k] = (G)0;
+                    Tr[q][k] = 0.0;
+                    Ti[q][k] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        const int row = lane % 16, g = lane / 16;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            if (8 * rb >= np) break;
+            const int pa = 8 * rb + MF::pair_of_row(row);
+            const G *urow = MF::part_of_row(row) ? Ui[pa] : Ur[pa];
+#pragma unroll
+            for (int tl = 0; tl < NT; ++tl) {
+                V d = {0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < KSMAX; ++ks)
+                    if (ks < ks_n) d = MF::run(urow[4 * ks + g], mreg[ks][tl], d);
+                const int l = 16 * tl + row;
+                if (l < P1) {
+#pragma unroll
+                    for (int pp = 0; pp < 2; ++pp) {
+                        const int pr = 8 * rb + 2 * g + pp;
+                        if (pr < np) {
+                            const ACC wr = (ACC)d[2 * pp], wi = (ACC)d[2 * pp + 1];
+                            const ACC tr = (ACC)Tr[pr][l], ti = (ACC)Ti[pr][l];
+                            accr[tl] += tr * wr - ti * wi;
+                            acci[tl] += tr * wi + ti * wr;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int tl = 0; tl < NT; ++tl) {
+        accr[tl] += __shfl_xor(accr[tl], 16, 64);
+        acci[tl] += __shfl_xor(acci[tl], 16, 64);
+        accr[tl] += __shfl_xor(accr[tl], 32, 64);
+        acci[tl] += __shfl_xor(acci[tl], 32, 64);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ext0 += __shfl_xor(ext0, off, 64);
+    if (lane < 16) {
+#pragma unroll
+        for (int tl = 0; tl < NT; ++tl) {
+            const int l = 16 * tl + lane;
+            if (l < P1) {
+                cd *o = BL + b * P1 + l;
+                cd v = *o;
+                v.re += (double)accr[tl] + (l == 0 ? ext0 : 0.0);
+                v.im += (double)acci[tl];
+                *o = v;
+            }
+        }
+    }
+}
+
+// M^ table in binary64: M^[l][k] = M_lk / 2^(l+k), 64 x 64.
+__global__ void k_make_mhat(double *Mhat, const double *binom) {
+    const int l = blockIdx.x, k = threadIdx.x;
+    double m;
+    if (l == 0) m = (k == 0) ? 0.0 : ((k & 1) ? -1.0 : 1.0);
+    else if (k == 0) m = -1.0 / l;
+    else m = ((k & 1) ? -1.0 : 1.0) * binom[(l + k - 1) * 128 + (k - 1)];
+    Mhat[l * 64 + k] = ldexp(m, -(l + k));
+}
+
+template <int NT>
+hipError_t launch_m2l(fmm2d_ctx *c, int l, int p, int mode) {
+    TreeState &t = c->tree;
+    EvalState &e = c->ev;
+    const int64_t nb = int64_t(1) << (2 * l);
+    const double4 *gL = t.geom.as<double4>() + level_offset(l);
+    const int32_t *wp = t.wptr.as<int32_t>() + ptr_offset(l);
+    const int32_t *wi = t.widx.as<int32_t>() + t.w_off[l];
+    const cd *AL = e.A.as<cd>() + level_offset(l) * (p + 1);
+    cd *BL = e.B.as<cd>() + level_offset(l) * (p + 1);
+    const double *Mh = e.mhat.as<double>();
+    const dim3 grid((unsigned)nb), block(64);
+    if (mode == FMM2D_MODE_FP64)
+        hipLaunchKernelGGL((k_m2l<NT, double, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, BL, Mh);
+    else if (mode == FMM2D_MODE_FP32_ACC64)
+        hipLaunchKernelGGL((k_m2l<NT, float, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, BL, Mh);
+    else
+        hipLaunchKernelGGL((k_m2l<NT, float, float>), grid, block, 0, c->stream, p, gL, wp, wi, AL, BL, Mh);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t ensure_mhat(fmm2d_ctx *c) {
+    EvalState &e = c->ev;
+    if (e.mhat_ready) return hipSuccess;
+    FMM2D_TRY(ensure_binomials(c));
+    FMM2D_TRY(e.mhat.ensure(sizeof(double) * 64 * 64));
+    hipLaunchKernelGGL(k_make_mhat, dim3(64), dim3(64), 0, c->stream, e.mhat.as<double>(), e.binom.as<double>());
+    FMM2D_TRY(hipGetLastError());
+    e.mhat_ready = true;
+    return hipSuccess;
+}
+
+hipError_t m2l_level(fmm2d_ctx *c, int l, int p, int mode) {
+    TreeState &t = c->tree;
+    if (t.w_off[l + 1] == t.w_off[l]) return hipSuccess;
+    const int nt = (p + 1 + 15) / 16;
+    switch (nt) {
+        case 1: return launch_m2l<1>(c, l, p, mode);
+        case 2: return launch_m2l<2>(c, l, p, mode);
+        case 3: return launch_m2l<3>(c, l, p, mode);
+        default: return launch_m2l<4>(c, l, p, mode);
+    }
+}
+
+}  // namespace fmm2d

@@ -101,6 +101,20 @@ class FMM2D:
                                            targets.numel(), _ptr(out)))
         return out
 
+    # -- timing -------------------------------------------------------------
+    def timing(self, enable: bool):
+        self._check(self._lib.fmm2d_timing(self._h, 1 if enable else 0))
+
+    def timings(self):
+        """{phase: (total GPU ms, intervals)} since timing was enabled."""
+        import numpy as np
+
+        ms = np.zeros(len(_capi.PHASES), dtype=np.float64)
+        cnt = np.zeros(len(_capi.PHASES), dtype=np.int64)
+        self._check(self._lib.fmm2d_get_timings(self._h, ctypes.c_void_p(ms.ctypes.data),
+                                                ctypes.c_void_p(cnt.ctypes.data)))
+        return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(_capi.PHASES)}
+
     # -- introspection ------------------------------------------------------
     def tree_info(self):
         n, nb = ctypes.c_int64(), ctypes.c_int64()

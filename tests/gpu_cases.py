@@ -56,5 +56,6 @@ TREE_CASES = {
     "uniform_10k_L5": (lambda: W.uniform_10k(), 5),
     "mixed_scaled_20k_L6": (lambda: W.mixed_1m(scale=0.02), 6),
     "clustered_scaled_20k_L6": (lambda: W.clustered_10m(scale=0.002), 6),
+    "clustered_scaled_30k_L6": (lambda: W.clustered_10m(scale=0.003, seed=2003), 6),
     "ring_scaled_20k_L6": (lambda: W.ring_4m(scale=0.005), 6),
 }
