@@ -7,6 +7,7 @@
 #include <new>
 
 #include "devutil.h"
+#include "evaluate.h"
 #include "internal.h"
 
 using namespace fmm2d;
@@ -89,14 +90,17 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         TreeState &t = c->tree;
         for (DevBuf *b : {&t.xsorted, &t.ysorted, &t.xorder, &t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1,
                           &t.starts, &t.rects, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
-                          &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state})
+                          &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d})
             b->release();
         EvalState &e = c->ev;
-        for (DevBuf *b : {&e.binom, &e.mhat, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();
+        for (Schedule &sc : c->tree.m2l_seg) { sc.segoff.release(); sc.table.release(); }
+        c->tree.near_seg.segoff.release();
+        c->tree.near_seg.table.release();
+        for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();
         Scratch &s = c->scr;
         for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
         for (DevBuf *b : {&s.keys0, &s.keys1, &s.vals0, &s.vals1, &s.hist, &s.aux, &s.tiles, &s.tiles2, &s.segbase,
-                          &s.thr, &s.split0, &s.split1, &s.flag})
+                          &s.thr, &s.split0, &s.split1, &s.flag, &s.segcnt})
             b->release();
     }
     delete c;
@@ -139,6 +143,7 @@ int fmm2d_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, 
     if (hf[0]) return fail(c, FMM2D_EINVAL, "build_tree: coordinates must be finite with |v| <= 2^500");
     TreeState &t = c->tree;
     t.has_lists = false;
+    t.nrec_valid = false;
     t.n = n;
     t.L = levels;
     {
@@ -167,6 +172,7 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
         hipError_t e;
         {
             PhaseScope ps(c, PH_LISTS);
+            t.nrec_valid = false;
             e = build_lists_device(c, theta, cap_s, cap_w, c->list_limit, &overflow);
         }
         if (e != hipSuccess) {
@@ -174,6 +180,12 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
             return hip_fail(c, e, "connectivity");
         }
         if (overflow == 0) {
+            {
+                PhaseScope ps(c, PH_LISTS);
+                e = near_records(c);
+                if (e == hipSuccess) e = build_schedules(c);
+            }
+            if (e != hipSuccess) return hip_fail(c, e, "connectivity");
             t.has_lists = true;
             t.theta = theta;
             return FMM2D_OK;

@@ -51,6 +51,15 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Segments of a CSR list for the list-driven kernels (sched.hip).
+struct Schedule {
+    DevBuf segoff;          // int32 [rows + 1]: first segment of each row; [rows] = count
+    DevBuf table;           // int2 [bound]: (row, first entry) of each segment
+    int64_t bound = 0;      // upper bound of the segment count (launch size)
+};
+constexpr int M2L_SEG = 128;   // weak-list entries per M2L segment
+constexpr int NEAR_SEG = 64;   // strong-list entries per near-field segment
+
 // Everything a tree and its lists leave on the device.
 struct TreeState {
     int64_t n = 0;
@@ -69,7 +78,11 @@ struct TreeState {
     DevBuf loc;             // float2 [n], offsets from the leaf centre
     // lists: row pointers of every level (ptr_offset), index pools
     DevBuf sptr, wptr, sidx, widx, cnt_s, cnt_w;
-    DevBuf pool_state;      // int64 [2 (L+2) + 3]: s offsets, w offsets, overflow, level totals
+    DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
+    DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range, FP32 centre offset, threshold
+    bool nrec_valid = false;
+    std::vector<Schedule> m2l_seg;  // per level
+    Schedule near_seg;              // finest-level strong lists
     std::vector<int64_t> s_off, w_off;  // host copy: pool offset of each level
     bool has_lists = false;
     double theta = 0.0;
@@ -85,6 +98,7 @@ struct EvalState {
     DevBuf phi_leaf;        // double [n]
     DevBuf work;            // mode-dependent scratch
     DevBuf src;             // float4 [n]: FP32 local offsets and charge
+    DevBuf part;            // partial sums of list segments (M2L and near field)
 };
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream
@@ -111,7 +125,7 @@ struct PhaseTimer {
 };
 
 struct Scratch {
-    DevBuf keys0, keys1, vals0, vals1, hist, aux, tiles, tiles2, segbase, thr, split0, split1, flag;
+    DevBuf keys0, keys1, vals0, vals1, hist, aux, tiles, tiles2, segbase, thr, split0, split1, flag, segcnt;
 };
 
 }  // namespace fmm2d

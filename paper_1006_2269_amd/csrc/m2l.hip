@@ -10,10 +10,12 @@
 // (z - c_b)/z0).  Exact power-of-two rescaling, M^_lk = M_lk / 2^(l+k),
 // u'_k = 2^k u_k, T'_l = 2^l rho_t^l, keeps every matrix entry below one.
 //
-// One wavefront per target box walks its weak list in chunks of 16 pairs.
+// One wavefront per segment of a target box's weak list (at most M2L_SEG
+// pairs, so heavy-tailed lists do not serialise; a second kernel adds the
+// segments' sums into B in order) walks it in chunks of 16 pairs.
 // Four lanes per pair build that pair's power tables in binary64 (binary
 // exponentiation to the lane's first power, then successive products) into
-// LDS.  The 16x16x4 matrix instruction multiplies a 16-row block (8 pairs x
+// LDS, while the next chunk's geometry and coefficients are being loaded.  The 16x16x4 matrix instruction multiplies a 16-row block (8 pairs x
 // real/imaginary part) of u' by M^T, which every lane keeps in registers;
 // each lane then post-scales its output elements by T' and accumulates its
 // coefficient l.  A cross-lane reduction adds the box's total into B.
@@ -67,19 +69,25 @@ __device__ inline cd cpow_int(cd z, int n) {
 template <int NT, typename G, typename ACC>
 __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ geomL, const int32_t *__restrict__ wptr,
                                             const int32_t *__restrict__ widx, const cd *__restrict__ AL,
-                                            cd *__restrict__ BL, const double *__restrict__ Mhat) {
+                                            const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
+                                            cd *__restrict__ part, const double *__restrict__ Mhat) {
     using MF = Mfma<G>;
     using V = typename MF::V;
-    constexpr int KSMAX = 4 * NT;
-    __shared__ G Ur[CP][64], Ui[CP][64];
-    __shared__ double Tr[CP][64], Ti[CP][64];
-    const int64_t b = blockIdx.x;
+    constexpr int KSMAX = 4 * NT;   // K steps when p + 1 = 16 NT
+    constexpr int KP = 16 * NT;     // padded coefficient count held in LDS
+    constexpr int KRMAX = KSMAX;    // powers per lane (LPP lanes per pair)
+    __shared__ G Ur[CP][KP], Ui[CP][KP];
+    __shared__ double Tr[CP][KP], Ti[CP][KP];
+    const int64_t seg = blockIdx.x;
+    if (seg >= *nseg_ptr) return;  // the block is one wavefront: uniform exit
     const int lane = threadIdx.x;
-    const int32_t t0 = wptr[b], t1 = wptr[b + 1];
-    if (t1 == t0) return;  // the block is one wavefront: uniform exit
+    const int2 se = segtab[seg];
+    const int64_t b = se.x;
+    const int32_t t0 = se.y;
+    const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
     const int P1 = p + 1;
     const int ks_n = (P1 + 3) / 4;
-    const int KR = (P1 + LPP - 1) / LPP;  // LPP * KR == 4 * ks_n: every padded k is written
+    const int KR = (P1 + LPP - 1) / LPP;  // LPP * KR == 4 * ks_n <= KP: every padded k is written
     const double4 gb = geomL[b];
     G mreg[KSMAX][NT];
 #pragma unroll
@@ -95,39 +103,81 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
     double ext0 = 0.0;
     const int q = lane / LPP, slot = lane % LPP;
     const int k0 = slot * KR;
+
+    // Software pipeline: the source box of chunk i+2, and the geometry and
+    // coefficients of chunk i+1, are loaded while chunk i is computed.
+    int32_t c_n1 = 0, c_n2 = 0;
+    double4 g_n1 = gb;
+    cd a_n1[KRMAX];
+    {
+        const int np0 = (t1 - t0) < CP ? (t1 - t0) : CP;
+        if (q < np0) c_n1 = widx[t0 + q];
+        if (t0 + CP + q < t1) c_n2 = widx[t0 + CP + q];
+        if (q < np0) {
+            g_n1 = geomL[c_n1];
+#pragma unroll
+            for (int kk = 0; kk < KRMAX; ++kk) {
+                const int k = k0 + kk;
+                a_n1[kk] = (kk < KR && k < P1) ? AL[(int64_t)c_n1 * P1 + k] : cd{0.0, 0.0};
+            }
+        }
+    }
     for (int32_t t = t0; t < t1; t += CP) {
         const int np = (t1 - t) < CP ? (t1 - t) : CP;
+        const double4 gc = g_n1;
+        cd a_cur[KRMAX];
+#pragma unroll
+        for (int kk = 0; kk < KRMAX; ++kk) a_cur[kk] = a_n1[kk];
+        // prefetch for the next chunks
+        {
+            const int32_t tn = t + CP;
+            if (tn + q < t1) {
+                const int32_t cn = c_n2;
+                g_n1 = geomL[cn];
+#pragma unroll
+                for (int kk = 0; kk < KRMAX; ++kk) {
+                    const int k = k0 + kk;
+                    a_n1[kk] = (kk < KR && k < P1) ? AL[(int64_t)cn * P1 + k] : cd{0.0, 0.0};
+                }
+            }
+            if (tn + CP + q < t1) c_n2 = widx[tn + CP + q];
+        }
         if (q < np) {
-            const int32_t c = widx[t + q];
-            const double4 gc = geomL[c];
             const cd z0{gc.x - gb.x, gc.y - gb.y};
-            const cd rs = cdiv(cd{gc.w, 0.0}, z0), rt = cdiv(cd{gb.w, 0.0}, z0);
+            const double d2 = z0.re * z0.re + z0.im * z0.im;  // > 0 for a weak pair
+            const double inv = gc.w / d2;
+            // s_c / z0 with one division; the scaled division where |z0|^2 could underflow
+            const cd rs = d2 > 0x1p-960 ? cd{z0.re * inv, -z0.im * inv} : cdiv(cd{gc.w, 0.0}, z0);
+            const cd rt = cscale(rs, gb.w / gc.w);            // s_b / z0
             cd ws = cpow_int(rs, k0), wt = cpow_int(rt, k0);
             double sc2 = ldexp(1.0, k0);
-            const cd *Ac = AL + (int64_t)c * P1;
-            for (int kk = 0; kk < KR; ++kk) {
-                const int k = k0 + kk;
-                if (k < P1) {
-                    const cd u = cmul(Ac[k], ws);
-                    Ur[q][k] = (G)(u.re * sc2);
-                    Ui[q][k] = (G)(u.im * sc2);
-                    Tr[q][k] = wt.re * sc2;
-                    Ti[q][k] = wt.im * sc2;
-                } else if (k < 64) {
-                    Ur[q][k] = (G)0;
-                    Ui[q][k] = (G)0;
-                    Tr[q][k] = 0.0;
-                    Ti[q][k] = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < KRMAX; ++kk) {
+                if (kk < KR) {
+                    const int k = k0 + kk;
+                    if (k < P1) {
+                        const cd u = cmul(a_cur[kk], ws);
+                        Ur[q][k] = (G)(u.re * sc2);
+                        Ui[q][k] = (G)(u.im * sc2);
+                        Tr[q][k] = wt.re * sc2;
+                        Ti[q][k] = wt.im * sc2;
+                    } else if (k < KP) {
+                        Ur[q][k] = (G)0;
+                        Ui[q][k] = (G)0;
+                        Tr[q][k] = 0.0;
+                        Ti[q][k] = 0.0;
+                    }
+                    ws = cmul(ws, rs);
+                    wt = cmul(wt, rt);
+                    sc2 *= 2.0;
                 }
-                ws = cmul(ws, rs);
-                wt = cmul(wt, rt);
-                sc2 *= 2.0;
             }
-            if (slot == 0) ext0 += Ac[0].re * log(hypot(z0.re, z0.im));
+            if (slot == 0) ext0 += a_cur[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im)));
         } else {
-            for (int kk = 0; kk < KR; ++kk) {
+#pragma unroll
+            for (int kk = 0; kk < KRMAX; ++kk) {
                 const int k = k0 + kk;
-                if (k < 64) {
+                if (kk < KR && k < KP) {
                     Ur[q][k] = (G)0;
                     Ui[q][k] = (G)0;
                     Tr[q][k] = 0.0;
@@ -178,15 +228,24 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
 #pragma unroll
         for (int tl = 0; tl < NT; ++tl) {
             const int l = 16 * tl + lane;
-            if (l < P1) {
-                cd *o = BL + b * P1 + l;
-                cd v = *o;
-                v.re += (double)accr[tl] + (l == 0 ? ext0 : 0.0);
-                v.im += (double)acci[tl];
-                *o = v;
-            }
+            if (l < P1) part[seg * P1 + l] = cd{(double)accr[tl] + (l == 0 ? ext0 : 0.0), (double)acci[tl]};
         }
     }
+}
+
+// B_l(b) += the segments' partial sums, in segment order.
+__global__ void k_m2l_reduce(int p, int64_t nb, const int32_t *__restrict__ segoff, const cd *__restrict__ part,
+                             cd *__restrict__ BL) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int P1 = p + 1;
+    if (e >= nb * P1) return;
+    const int64_t b = e / P1;
+    const int l = (int)(e - b * P1);
+    const int32_t s0 = segoff[b], s1 = segoff[b + 1];
+    if (s1 == s0) return;
+    cd acc{0.0, 0.0};
+    for (int32_t sg = s0; sg < s1; ++sg) acc = cadd(acc, part[(int64_t)sg * P1 + l]);
+    BL[e] = cadd(BL[e], acc);
 }
 
 // M^ table in binary64: M^[l][k] = M_lk / 2^(l+k), 64 x 64.
@@ -203,6 +262,7 @@ template <int NT>
 hipError_t launch_m2l(fmm2d_ctx *c, int l, int p, int mode) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
+    const Schedule &sc = t.m2l_seg[l];
     const int64_t nb = int64_t(1) << (2 * l);
     const double4 *gL = t.geom.as<double4>() + level_offset(l);
     const int32_t *wp = t.wptr.as<int32_t>() + ptr_offset(l);
@@ -210,13 +270,20 @@ hipError_t launch_m2l(fmm2d_ctx *c, int l, int p, int mode) {
     const cd *AL = e.A.as<cd>() + level_offset(l) * (p + 1);
     cd *BL = e.B.as<cd>() + level_offset(l) * (p + 1);
     const double *Mh = e.mhat.as<double>();
-    const dim3 grid((unsigned)nb), block(64);
+    FMM2D_TRY(e.part.ensure(sizeof(cd) * sc.bound * (p + 1)));
+    cd *part = e.part.as<cd>();
+    const int2 *tab = sc.table.as<int2>();
+    const int32_t *nsp = sc.segoff.as<int32_t>() + nb;
+    const dim3 grid((unsigned)sc.bound), block(64);
     if (mode == FMM2D_MODE_FP64)
-        hipLaunchKernelGGL((k_m2l<NT, double, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, BL, Mh);
+        hipLaunchKernelGGL((k_m2l<NT, double, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp, part, Mh);
     else if (mode == FMM2D_MODE_FP32_ACC64)
-        hipLaunchKernelGGL((k_m2l<NT, float, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, BL, Mh);
+        hipLaunchKernelGGL((k_m2l<NT, float, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp, part, Mh);
     else
-        hipLaunchKernelGGL((k_m2l<NT, float, float>), grid, block, 0, c->stream, p, gL, wp, wi, AL, BL, Mh);
+        hipLaunchKernelGGL((k_m2l<NT, float, float>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp, part, Mh);
+    FMM2D_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_m2l_reduce, dim3(grid_for(nb * (p + 1), 256)), dim3(256), 0, c->stream, p, nb,
+                       sc.segoff.as<int32_t>(), part, BL);
     return hipGetLastError();
 }
 

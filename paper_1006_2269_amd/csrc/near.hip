@@ -24,24 +24,52 @@ namespace {
 constexpr double HALF_LN2_D = 0.34657359027997264;  // ln(2)/2
 constexpr int NWB = 4;                                // wavefronts per block
 
+// Per strong-list entry of the finest level: the source leaf's point range
+// and, for the FP32 path, the FP32 centre difference c_b - c_c and the
+// coincidence threshold.  Depends on the tree and lists only.
+__global__ void __launch_bounds__(256) k_near_records(int64_t nleaf, const int32_t *__restrict__ stL,
+                                                      const double4 *__restrict__ geomL,
+                                                      const int32_t *__restrict__ sptr,
+                                                      const int32_t *__restrict__ sidx, int2 *__restrict__ recj,
+                                                      float4 *__restrict__ recd) {
+    // one wavefront per leaf, lanes over its strong entries (coalesced)
+    const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (b >= nleaf) return;
+    const int lane = threadIdx.x % 64;
+    const double4 g = geomL[b];
+    const int32_t t1 = sptr[b + 1];
+    for (int32_t t = sptr[b] + lane; t < t1; t += 64) {
+        const int32_t c = sidx[t];
+        const double4 gc = geomL[c];
+        const float dxc = (float)(g.x - gc.x), dyc = (float)(g.y - gc.y);
+        const float mag = fabsf(dxc) + fabsf(dyc) + (float)g.z + (float)gc.z;
+        recj[t] = make_int2(stL[c], stL[c + 1]);
+        recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+    }
+}
+
+// FP32 near field.  Pipelined: while step s is evaluated, the source points
+// of step s+1 and the records of step s+2 are in flight.  Requires the
+// largest leaf to fit in GL lanes.
 template <int TM, int GL, bool ACC64>
-__global__ void __launch_bounds__(64 * NWB) k_near32(int p, int64_t nitems, int chunks, int maxleaf,
-                                                     const int32_t *__restrict__ stL,
-                                                     const double4 *__restrict__ geomL, const float4 *__restrict__ src,
-                                                     const double *__restrict__ px, const double *__restrict__ py,
-                                                     const cd *__restrict__ BL, const int32_t *__restrict__ sptr,
-                                                     const int32_t *__restrict__ sidx, double *__restrict__ phi_leaf) {
+__global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks, const int32_t *__restrict__ stL,
+                                                     const float4 *__restrict__ src, const int32_t *__restrict__ sptr,
+                                                     const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
+                                                     const int2 *__restrict__ recj, const float4 *__restrict__ recd,
+                                                     double *__restrict__ part) {
     constexpr int LPI = 64 / GL;  // source leaves per step
     const int64_t item = (int64_t)blockIdx.x * NWB + threadIdx.x / 64;
     if (item >= nitems) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
-    const int64_t b = item / chunks;
-    const int ch = (int)(item - b * chunks);
+    const int64_t sg = item / chunks;
+    if (sg >= *nseg_ptr) return;
+    const int ch = (int)(item - sg * chunks);
+    const int2 se = segtab[sg];
+    const int64_t b = se.x;
     const int32_t le = stL[b + 1];
     const int32_t a = stL[b] + ch * TM;
     if (a >= le) return;
     const int nt = (le - a) < TM ? (le - a) : TM;
-    const double4 g = geomL[b];
     float tx[TM], ty[TM], acc[TM];
     double acc64[TM];
 #pragma unroll
@@ -53,41 +81,55 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int p, int64_t nitems, int 
         acc64[k] = 0.0;
     }
     const int grp = lane / GL, jj = lane % GL;
-    const int32_t t0 = sptr[b], t1 = sptr[b + 1];
+    const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
+    const float4 far = make_float4(1e18f, 1e18f, 0.f, 0.f);
+    int2 rj2 = make_int2(0, 0);
+    float4 rd1 = make_float4(0.f, 0.f, 0.f, 0.f), rd2 = rd1;
+    float4 sv1 = far;
+    {
+        const int32_t ta = t0 + grp, tb = t0 + LPI + grp;
+        if (ta < t1) {
+            const int2 rj1 = recj[ta];
+            rd1 = recd[ta];
+            if (jj < rj1.y - rj1.x) sv1 = src[rj1.x + jj];
+        }
+        if (tb < t1) {
+            rj2 = recj[tb];
+            rd2 = recd[tb];
+        }
+    }
     int step = 0;
     for (int32_t t = t0; t < t1; t += LPI, ++step) {
-        const int32_t tt = t + grp;
-        const bool leaf_ok = tt < t1;
-        const int32_t c = sidx[leaf_ok ? tt : t0];
-        const double4 gc = geomL[c];
-        const float dxc = (float)(g.x - gc.x), dyc = (float)(g.y - gc.y);
-        const float mag = fabsf(dxc) + fabsf(dyc) + (float)g.z + (float)gc.z;
-        const float thr = (mag * 0x1p-20f) * (mag * 0x1p-20f);
-        const int32_t j0 = stL[c], j1 = stL[c + 1];
-        for (int jb = 0; jb < maxleaf; jb += GL) {
-            const int32_t j = j0 + jb + jj;
-            float sx = 1e18f, sy = 1e18f, q = 0.f;
-            if (leaf_ok && j < j1) {
-                const float4 s = src[j];
-                sx = s.x - dxc;
-                sy = s.y - dyc;
-                q = s.z;
-            }
-#pragma unroll
-            for (int k = 0; k < TM; ++k) {
-                const float dx = tx[k] - sx, dy = ty[k] - sy;
-                const float r2 = dx * dx + dy * dy;
-                const float lg = __log2f(r2);
-                acc[k] += (r2 > thr) ? q * lg : 0.f;
-            }
+        // issue: records of step s+2, sources of step s+1
+        const int32_t tc = t + 2 * LPI + grp;
+        int2 rj3 = make_int2(0, 0);
+        float4 rd3 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (tc < t1) {
+            rj3 = recj[tc];
+            rd3 = recd[tc];
         }
-        if (ACC64 && (step & 3) == 3) {
+        float4 sv2 = far;
+        if (jj < rj2.y - rj2.x) sv2 = src[rj2.x + jj];
+        // evaluate step s
+        const float sx = sv1.x - rd1.x, sy = sv1.y - rd1.y, q = sv1.z, thr = rd1.z;
+#pragma unroll
+        for (int k = 0; k < TM; ++k) {
+            const float dx = tx[k] - sx, dy = ty[k] - sy;
+            const float r2 = dx * dx + dy * dy;
+            const float lg = __log2f(r2);
+            acc[k] += (r2 > thr) ? q * lg : 0.f;
+        }
+        if (ACC64 && (step & 7) == 7) {
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
                 acc64[k] += (double)acc[k];
                 acc[k] = 0.f;
             }
         }
+        sv1 = sv2;
+        rd1 = rd2;
+        rj2 = rj3;
+        rd2 = rd3;
     }
     double mine = 0.0;
 #pragma unroll
@@ -105,29 +147,106 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int p, int64_t nitems, int 
         }
         if (lane == k) mine = v;
     }
-    if (lane < nt) {
-        const int32_t i = a + lane;
-        const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
-        const cd *Bb = BL + b * (p + 1);
-        cd v = Bb[p];
-        for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
-        phi_leaf[i] = v.re + mine * HALF_LN2_D;
-    }
+    if (lane < TM) part[item * TM + lane] = mine;
 }
 
+// FP32 near field for leaves larger than 64 points: a lane walks its source
+// leaf 64 points at a time (not pipelined).
+template <int TM, bool ACC64>
+__global__ void __launch_bounds__(64 * NWB) k_near32_big(int64_t nitems, int chunks, int maxleaf,
+                                                         const int32_t *__restrict__ stL,
+                                                         const float4 *__restrict__ src,
+                                                         const int32_t *__restrict__ sptr,
+                                                         const int2 *__restrict__ segtab,
+                                                         const int32_t *__restrict__ nseg_ptr,
+                                                         const int2 *__restrict__ recj,
+                                                         const float4 *__restrict__ recd, double *__restrict__ part) {
+    const int64_t item = (int64_t)blockIdx.x * NWB + threadIdx.x / 64;
+    if (item >= nitems) return;  // uniform per wavefront
+    const int lane = threadIdx.x % 64;
+    const int64_t sg = item / chunks;
+    if (sg >= *nseg_ptr) return;
+    const int ch = (int)(item - sg * chunks);
+    const int2 se = segtab[sg];
+    const int64_t b = se.x;
+    const int32_t le = stL[b + 1];
+    const int32_t a = stL[b] + ch * TM;
+    if (a >= le) return;
+    const int nt = (le - a) < TM ? (le - a) : TM;
+    float tx[TM], ty[TM], acc[TM];
+    double acc64[TM];
+#pragma unroll
+    for (int k = 0; k < TM; ++k) {
+        const float4 s = src[a + (k < nt ? k : 0)];
+        tx[k] = s.x;
+        ty[k] = s.y;
+        acc[k] = 0.f;
+        acc64[k] = 0.0;
+    }
+    const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
+    for (int32_t t = t0; t < t1; ++t) {
+        const int2 rj = recj[t];
+        const float4 rd = recd[t];
+        for (int jb = 0; jb < maxleaf; jb += 64) {
+            const int32_t j = rj.x + jb + lane;
+            float sx = 1e18f, sy = 1e18f, q = 0.f;
+            if (j < rj.y) {
+                const float4 s = src[j];
+                sx = s.x - rd.x;
+                sy = s.y - rd.y;
+                q = s.z;
+            }
+#pragma unroll
+            for (int k = 0; k < TM; ++k) {
+                const float dx = tx[k] - sx, dy = ty[k] - sy;
+                const float r2 = dx * dx + dy * dy;
+                const float lg = __log2f(r2);
+                acc[k] += (r2 > rd.z) ? q * lg : 0.f;
+            }
+        }
+        if (ACC64) {
+#pragma unroll
+            for (int k = 0; k < TM; ++k) {
+                acc64[k] += (double)acc[k];
+                acc[k] = 0.f;
+            }
+        }
+    }
+    double mine = 0.0;
+#pragma unroll
+    for (int k = 0; k < TM; ++k) {
+        double v = ACC64 ? acc64[k] + (double)acc[k] : (double)acc[k];
+        if (ACC64) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        } else {
+            float w = acc[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+            v = (double)w;
+        }
+        if (lane == k) mine = v;
+    }
+    if (lane < TM) part[item * TM + lane] = mine;
+}
+
+// Binary64 near field, same decomposition; sources (x, y, q) in binary64.
 template <int TM, int GL>
-__global__ void __launch_bounds__(64 * NWB) k_near64(int p, int64_t nitems, int chunks, int maxleaf,
-                                                     const int32_t *__restrict__ stL,
-                                                     const double4 *__restrict__ geomL, const double *__restrict__ px,
+__global__ void __launch_bounds__(64 * NWB) k_near64(int64_t nitems, int chunks, int maxleaf,
+                                                     const int32_t *__restrict__ stL, const double *__restrict__ px,
                                                      const double *__restrict__ py, const double *__restrict__ qs,
-                                                     const cd *__restrict__ BL, const int32_t *__restrict__ sptr,
-                                                     const int32_t *__restrict__ sidx, double *__restrict__ phi_leaf) {
+                                                     const int32_t *__restrict__ sptr, const int2 *__restrict__ segtab,
+                                                     const int32_t *__restrict__ nseg_ptr,
+                                                     const int2 *__restrict__ recj, double *__restrict__ part) {
     constexpr int LPI = 64 / GL;
     const int64_t item = (int64_t)blockIdx.x * NWB + threadIdx.x / 64;
-    if (item >= nitems) return;
+    if (item >= nitems) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
-    const int64_t b = item / chunks;
-    const int ch = (int)(item - b * chunks);
+    const int64_t sg = item / chunks;
+    if (sg >= *nseg_ptr) return;
+    const int ch = (int)(item - sg * chunks);
+    const int2 se = segtab[sg];
+    const int64_t b = se.x;
     const int32_t le = stL[b + 1];
     const int32_t a = stL[b] + ch * TM;
     if (a >= le) return;
@@ -141,15 +260,14 @@ __global__ void __launch_bounds__(64 * NWB) k_near64(int p, int64_t nitems, int 
         acc[k] = 0.0;
     }
     const int grp = lane / GL, jj = lane % GL;
-    const int32_t t0 = sptr[b], t1 = sptr[b + 1];
+    const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
     for (int32_t t = t0; t < t1; t += LPI) {
         const int32_t tt = t + grp;
-        const bool leaf_ok = tt < t1;
-        const int32_t c = sidx[leaf_ok ? tt : t0];
-        const int32_t j0 = stL[c], j1 = stL[c + 1];
+        int2 rj = make_int2(0, 0);
+        if (tt < t1) rj = recj[tt];
         for (int jb = 0; jb < maxleaf; jb += GL) {
-            const int32_t j = j0 + jb + jj;
-            const bool ok = leaf_ok && j < j1;
+            const int32_t j = rj.x + jb + jj;
+            const bool ok = j < rj.y;
             double sx = 1e300, sy = 1e300, q = 0.0;
             if (ok) {
                 sx = px[j];
@@ -171,15 +289,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near64(int p, int64_t nitems, int 
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == k) mine = v;
     }
-    if (lane < nt) {
-        const int32_t i = a + lane;
-        const double4 g = geomL[b];
-        const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
-        const cd *Bb = BL + b * (p + 1);
-        cd v = Bb[p];
-        for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
-        phi_leaf[i] = v.re + 0.5 * mine;
-    }
+    if (lane < TM) part[item * TM + lane] = mine;
 }
 
 __global__ void k_pack_sources(const float2 *__restrict__ loc, const double *__restrict__ qs, int64_t n,
@@ -191,52 +301,114 @@ __global__ void k_pack_sources(const float2 *__restrict__ loc, const double *__r
     }
 }
 
+// Per point: the partial sums of its leaf's segments in segment order, times
+// `scale`, plus L2P (binary64 Horner) of the leaf's local expansion.
+__global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale, const int32_t *__restrict__ leafid,
+                              const int32_t *__restrict__ stL, const int32_t *__restrict__ segoff,
+                              const double *__restrict__ part, const double4 *__restrict__ geomL,
+                              const double *__restrict__ px, const double *__restrict__ py,
+                              const cd *__restrict__ BL, double *__restrict__ phi_leaf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = leafid[i];
+    const int32_t off = (int32_t)(i - stL[b]);
+    const int ch = off / tm, k = off - ch * tm;
+    double near = 0.0;
+    for (int32_t sg = segoff[b]; sg < segoff[b + 1]; ++sg) near += part[((int64_t)sg * chunks + ch) * tm + k];
+    const double4 g = geomL[b];
+    const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
+    const cd *Bb = BL + (int64_t)b * (p + 1);
+    cd v = Bb[p];
+    for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
+    phi_leaf[i] = v.re + scale * near;
+}
+
 template <int TM, int GL>
 hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int L = t.L;
     const int64_t nleaf = int64_t(1) << (2 * L);
+    const Schedule &sc = t.near_seg;
     const int chunks = (maxleaf + TM - 1) / TM;
-    const int64_t nitems = nleaf * chunks;
+    const int64_t nitems = sc.bound * chunks;
     const int64_t offL = level_offset(L);
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     const double4 *gL = t.geom.as<double4>() + offL;
     const cd *BL = e.B.as<cd>() + offL * (p + 1);
     const int32_t *sp = t.sptr.as<int32_t>() + ptr_offset(L);
-    const int32_t *si = t.sidx.as<int32_t>() + t.s_off[L];
+    const int2 *rj = t.nrec_j.as<int2>();
+    const float4 *rd = t.nrec_d.as<float4>();
+    const int2 *tab = sc.table.as<int2>();
+    const int32_t *nsp = sc.segoff.as<int32_t>() + nleaf;
+    FMM2D_TRY(e.part.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
+    double *part = e.part.as<double>();
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
+    double scale;
     if (mode == FMM2D_MODE_FP64) {
-        hipLaunchKernelGGL((k_near64<TM, GL>), grid, block, 0, c->stream, p, nitems, chunks, maxleaf, stL, gL,
-                           t.px.as<double>(), t.py.as<double>(), e.qs.as<double>(), BL, sp, si,
-                           e.phi_leaf.as<double>());
-    } else if (mode == FMM2D_MODE_FP32_ACC64) {
-        hipLaunchKernelGGL((k_near32<TM, GL, true>), grid, block, 0, c->stream, p, nitems, chunks, maxleaf, stL, gL,
-                           e.src.as<float4>(), t.px.as<double>(), t.py.as<double>(), BL, sp, si,
-                           e.phi_leaf.as<double>());
+        scale = 0.5;
+        hipLaunchKernelGGL((k_near64<TM, GL>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                           t.px.as<double>(), t.py.as<double>(), e.qs.as<double>(), sp, tab, nsp, rj, part);
     } else {
-        hipLaunchKernelGGL((k_near32<TM, GL, false>), grid, block, 0, c->stream, p, nitems, chunks, maxleaf, stL, gL,
-                           e.src.as<float4>(), t.px.as<double>(), t.py.as<double>(), BL, sp, si,
-                           e.phi_leaf.as<double>());
+        scale = HALF_LN2_D;
+        if (maxleaf > 64) {
+            if (mode == FMM2D_MODE_FP32_ACC64)
+                hipLaunchKernelGGL((k_near32_big<TM, true>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+            else
+                hipLaunchKernelGGL((k_near32_big<TM, false>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+        } else if (mode == FMM2D_MODE_FP32_ACC64) {
+            hipLaunchKernelGGL((k_near32<TM, GL, true>), grid, block, 0, c->stream, nitems, chunks, stL,
+                               e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+        } else {
+            hipLaunchKernelGGL((k_near32<TM, GL, false>), grid, block, 0, c->stream, nitems, chunks, stL,
+                               e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+        }
     }
+    FMM2D_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_near_reduce, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, chunks, scale,
+                       t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part, gL, t.px.as<double>(),
+                       t.py.as<double>(), BL, e.phi_leaf.as<double>());
     return hipGetLastError();
 }
 
 }  // namespace
+
+// Records of the finest-level strong entries (after the lists are built).
+hipError_t near_records(fmm2d_ctx *c) {
+    TreeState &t = c->tree;
+    const int L = t.L;
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    const int64_t ns = t.s_off[L + 1] - t.s_off[L];
+    FMM2D_TRY(t.nrec_j.ensure(sizeof(int2) * (ns > 0 ? ns : 1)));
+    FMM2D_TRY(t.nrec_d.ensure(sizeof(float4) * (ns > 0 ? ns : 1)));
+    const int64_t offL = level_offset(L);
+    hipLaunchKernelGGL(k_near_records, dim3(grid_for(nleaf, 4)), dim3(256), 0, c->stream, nleaf,
+                       t.starts.as<int32_t>() + depth_offset(2 * L), t.geom.as<double4>() + offL,
+                       t.sptr.as<int32_t>() + ptr_offset(L), t.sidx.as<int32_t>() + t.s_off[L], t.nrec_j.as<int2>(),
+                       t.nrec_d.as<float4>());
+    FMM2D_TRY(hipGetLastError());
+    t.nrec_valid = true;
+    return hipSuccess;
+}
 
 // L2P plus the near field for every point; writes ev.phi_leaf (leaf order).
 hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int64_t n = t.n;
-    const int64_t maxleaf = (n + (int64_t(1) << (2 * t.L)) - 1) >> (2 * t.L);  // ceil(n / 4^L)
+    const int L = t.L;
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    const int64_t maxleaf = (n + nleaf - 1) >> (2 * L);  // ceil(n / 4^L)
+    if (!t.nrec_valid) FMM2D_TRY(near_records(c));
     if (mode != FMM2D_MODE_FP64) {
         FMM2D_TRY(e.src.ensure(sizeof(float4) * n));
         hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.loc.as<float2>(),
                            e.qs.as<double>(), n, e.src.as<float4>());
     }
-    // GL lanes per source leaf: the smallest power of two >= the largest leaf,
-    // capped at 64 (larger leaves are walked GL points at a time)
+    // GL lanes per source leaf: the smallest power of two >= the largest leaf
+    // (capped at 64; larger leaves take the non-pipelined kernel)
     const int ml = (int)(maxleaf < (int64_t)1 << 30 ? maxleaf : (int64_t)1 << 30);
     if (ml <= 8) return launch_near<8, 8>(c, p, mode, ml);
     if (ml <= 16) return launch_near<16, 16>(c, p, mode, ml);
