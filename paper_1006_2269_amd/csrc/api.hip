@@ -42,14 +42,7 @@ int hip_fail(fmm2d_ctx *c, hipError_t e, const char *where) {
     return fail(c, FMM2D_EDEVICE, "%s: %s", where, hipGetErrorString(e));
 }
 
-// flags[0]: non-finite or |v| > 2^500 seen; flags[1]: index out of range
-__global__ void k_check_coords(const double *__restrict__ v, int64_t n, int *flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const double a = fabs(v[i]);
-        if (!(a <= 0x1p500)) flags[0] = 1;  // also catches NaN
-    }
-}
+// flags[1]: a target index out of range
 __global__ void k_check_targets(const int64_t *__restrict__ t, int64_t m, int64_t n, int *flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m && (t[i] < 0 || t[i] >= n)) flags[1] = 1;
@@ -130,17 +123,15 @@ int fmm2d_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, 
                     (long long)(int64_t(1) << (2 * levels)));
     DeviceGuard g(c->device);
     hipError_t e;
-    // validate the coordinates before touching the current tree
-    if ((e = c->scr.aux.ensure(4096)) != hipSuccess) return hip_fail(c, e, "build_tree");
-    int *flags = reinterpret_cast<int *>(c->scr.aux.as<char>() + 2048);
-    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(1), 0, c->stream, flags);
-    hipLaunchKernelGGL(k_check_coords, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, x, n, flags);
-    hipLaunchKernelGGL(k_check_coords, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, y, n, flags);
-    int hf[2] = {0, 0};
-    if ((e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
-        return hip_fail(c, e, "build_tree");
-    if (hf[0]) return fail(c, FMM2D_EINVAL, "build_tree: coordinates must be finite with |v| <= 2^500");
+    // validate the coordinates (and make the sort keys) before touching the
+    // current tree
+    bool bad = false;
+    {
+        PhaseScope ps(c, PH_TREE);
+        e = sort_prepare(c, x, y, n, &bad);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "build_tree");
+    if (bad) return fail(c, FMM2D_EINVAL, "build_tree: coordinates must be finite with |v| <= 2^500");
     TreeState &t = c->tree;
     t.has_lists = false;
     t.nrec_valid = false;

@@ -126,6 +126,8 @@ struct PhaseTimer {
 
 struct Scratch {
     DevBuf keys0, keys1, vals0, vals1, hist, aux, tiles, tiles2, segbase, thr, split0, split1, flag, segcnt;
+    int64_t sort_n = -1;     // size of the validated keys waiting in keys0 / vals0, or -1
+    uint64_t sort_differ = 0;  // bits in which the keys of either coordinate differ
 };
 
 }  // namespace fmm2d
@@ -145,9 +147,16 @@ namespace fmm2d {
 
 // ---- launchers (each returns the launch's hipError_t) ---------------------
 // sort.hip
-hipError_t sort_coordinate(fmm2d_ctx *c, const double *v, int64_t n, double *sorted, int32_t *order);
+// sort.hip: stable sort of both coordinates by (value, index).  sort_prepare
+// validates (finite, |v| <= 2^500) and touches scratch memory only;
+// sort_finish completes the sort of the keys sort_prepare left.
+hipError_t sort_prepare(fmm2d_ctx *c, const double *x, const double *y, int64_t n, bool *bad_input);
+hipError_t sort_finish(fmm2d_ctx *c, int64_t n, double *xs, double *ys, int32_t *xorder, int32_t *yorder,
+                       int32_t *xrank, int32_t *yrank);
 // scan.hip: exclusive scan of int32 in[n] into out[n+1] (out[n] = total)
 hipError_t scan_exclusive(fmm2d_ctx *c, const int32_t *in, int64_t n, int32_t *out);
+// the same for k (1 or 2) arrays of one length, in the same launches
+hipError_t scan_exclusive_n(fmm2d_ctx *c, int k, const int32_t *const *in, int64_t n, int32_t *const *out);
 // tree.hip
 hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y);
 // lists.hip

@@ -11,10 +11,11 @@
 // the host reads the offsets (and an overflow flag) at the end.
 //
 // Row pointers are int32.  A level's candidates number 16 |S_{l-1}| (four
-// children of each of the four children's parents' strong boxes), so the
-// host reads each level's two list totals (one small copy and a stream
-// synchronisation per level) and refuses a level whose candidate count could
-// exceed the entry limit before launching it: no int32 prefix sum can wrap.
+// children of each of the four children's parents' strong boxes).  The host
+// carries an upper bound of |S_{l-1}| (16^(l-1) until a level's exact total
+// has been read) and reads the exact total back only when 16 times the bound
+// exceeds the entry limit; it refuses a level whose candidate count could
+// exceed the limit before launching it, so no int32 prefix sum can wrap.
 #include "devutil.h"
 #include "internal.h"
 
@@ -131,29 +132,35 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     int64_t *ps = t.pool_state.as<int64_t>();
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L);
     const double4 *geom = t.geom.as<double4>();
-    int64_t s_prev = 1;  // entries of S at level l-1 (level 0: the root)
+    // Upper bound of the entries of S at level l-1 (exact at level 0: the
+    // root).  |S_l| <= 16 |S_{l-1}|, so the bound grows by 16 per level; only
+    // when it reaches the limit is the exact total read back (one copy and a
+    // synchronisation).
+    int64_t s_prev = 1;
     for (int l = 1; l <= L; ++l) {
-        if (16 * s_prev > limit) {
-            FMM2D_TRY(hipStreamSynchronize(c->stream));
-            *overflow = 2;
-            return hipSuccess;
-        }
         const int64_t nb = int64_t(1) << (2 * l);
+        int32_t *sp_prev = sptr + ptr_offset(l - 1), *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
+        if (16 * s_prev > limit) {
+            int32_t tot = 0;
+            FMM2D_TRY(hipMemcpyAsync(&tot, sp_prev + (nb >> 2), sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            FMM2D_TRY(hipStreamSynchronize(c->stream));
+            s_prev = tot;
+            if (16 * s_prev > limit) {
+                *overflow = 2;
+                return hipSuccess;
+            }
+        }
         const double4 *gL = geom + level_offset(l);
         const unsigned grid = grid_for(nb, LW);
-        int32_t *sp_prev = sptr + ptr_offset(l - 1), *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
         hipLaunchKernelGGL(k_lists_level<false>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
                            t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), sp_cur, wp_cur,
                            t.sidx.as<int32_t>(), t.widx.as<int32_t>());
-        FMM2D_TRY(scan_exclusive(c, t.cnt_s.as<int32_t>(), nb, sp_cur));
-        FMM2D_TRY(scan_exclusive(c, t.cnt_w.as<int32_t>(), nb, wp_cur));
         {
-            int32_t h2[2] = {0, 0};
-            FMM2D_TRY(hipMemcpyAsync(h2, sp_cur + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-            FMM2D_TRY(hipMemcpyAsync(h2 + 1, wp_cur + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-            FMM2D_TRY(hipStreamSynchronize(c->stream));
-            s_prev = h2[0];
+            const int32_t *ins[2] = {t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>()};
+            int32_t *outs[2] = {sp_cur, wp_cur};
+            FMM2D_TRY(scan_exclusive_n(c, 2, ins, nb, outs));
         }
+        s_prev *= 16;
         hipLaunchKernelGGL(k_lists_advance, dim3(1), dim3(1), 0, c->stream, l, L, nb, sp_cur, wp_cur, ps, cap_s,
                            cap_w);
         hipLaunchKernelGGL(k_lists_level<true>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,

@@ -43,11 +43,6 @@ __global__ void k_root(const double *__restrict__ xs, const double *__restrict__
     rects[0] = Rect{xs[0], xs[n - 1], ys[0], ys[n - 1]};
 }
 
-__global__ void k_invert(const int32_t *__restrict__ order, int64_t n, int32_t *__restrict__ rank) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) rank[order[r]] = (int32_t)r;
-}
-
 __global__ void k_init_lists(const int32_t *__restrict__ xorder, const int32_t *__restrict__ yorder,
                              const int32_t *__restrict__ xrank, const int32_t *__restrict__ yrank, int64_t n,
                              int32_t *__restrict__ XLx, int32_t *__restrict__ XLy, int32_t *__restrict__ YLx,
@@ -61,19 +56,24 @@ __global__ void k_init_lists(const int32_t *__restrict__ xorder, const int32_t *
     }
 }
 
-// One thread per segment of depth h: median rank, split line, child offsets,
-// and (after a y split) the four child rectangles.
-__global__ void k_threshold(int h, int64_t nseg, int64_t n, const int32_t *__restrict__ st,
-                            int32_t *__restrict__ st1, const int32_t *__restrict__ sorted_list,
-                            const double *__restrict__ coord, int32_t *__restrict__ thr,
-                            double *__restrict__ split_cur, const double *__restrict__ split_prev,
-                            Rect *__restrict__ rects) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nseg) return;
+// Segment s of depth h: its median entry is the one at offset floor(m/2) of
+// the list sorted along the split axis, and an entry of the other list is low
+// iff its rank along that axis is below the median's.
+__device__ inline int32_t seg_threshold(const int32_t *__restrict__ st, const int32_t *__restrict__ med_list,
+                                        int64_t s) {
     const int32_t a = st[s], e = st[s + 1];
-    const int32_t k = (e - a) >> 1;
-    const int32_t r_hi = sorted_list[a + k], r_lo = sorted_list[a + k - 1];
-    thr[s] = r_hi;
+    return med_list[a + ((e - a) >> 1)];
+}
+
+// Per segment of depth h: split line, child offsets, and (after a y split)
+// the four child rectangles.
+__device__ inline void segment_record(int h, int64_t s, int64_t nseg, int64_t n, const int32_t *__restrict__ st,
+                                      int32_t *__restrict__ st1, const int32_t *__restrict__ med_list,
+                                      const double *__restrict__ coord, double *__restrict__ split_cur,
+                                      const double *__restrict__ split_prev, Rect *__restrict__ rects) {
+    const int32_t a = st[s], e = st[s + 1];
+    const int32_t k = (e - a) >> 1;  // >= 1: every segment above the leaves holds >= 2 points
+    const int32_t r_hi = med_list[a + k], r_lo = med_list[a + k - 1];
     const double sp = 0.5 * (coord[r_lo] + coord[r_hi]);
     split_cur[s] = sp;
     st1[2 * s] = a;
@@ -93,85 +93,157 @@ __global__ void k_threshold(int h, int64_t nseg, int64_t n, const int32_t *__res
     }
 }
 
-// Count the low flags of each tile and record, for every segment starting in
-// the tile, the number of low flags in the tile before its start.
-__global__ void __launch_bounds__(PT) k_part_count(const int32_t *__restrict__ key, int64_t n,
-                                                   const int32_t *__restrict__ st, int64_t nseg,
-                                                   const int32_t *__restrict__ thr, int32_t *__restrict__ tcount,
-                                                   int32_t *__restrict__ segbase_local) {
-    __shared__ int32_t tmp[PT / 64];
-    const int64_t i0 = (int64_t)blockIdx.x * PTILE + (int64_t)threadIdx.x * PI;
-    int64_t seg = (i0 < n) ? find_seg(st, nseg, n, i0) : 0;
-    int32_t flags = 0, starts = 0, cnt = 0;
-    int64_t segs[PI];
-#pragma unroll
-    for (int r = 0; r < PI; ++r) {
-        const int64_t i = i0 + r;
-        segs[r] = 0;
-        if (i < n) {
-            while (st[seg + 1] <= i) ++seg;
-            segs[r] = seg;
-            const int32_t f = key[i] < thr[seg];
-            flags |= f << r;
-            starts |= (int32_t)(st[seg] == i) << r;
-            cnt += f;
-        }
-    }
+// Tiles of PTILE consecutive list positions, read striped (position
+// base + r * PT + thread), so that every load is coalesced.  Inside a tile the
+// low flags are ranked in position order by per-round wave ballots: the rank
+// of round r, wave w, lane j is (low flags of rounds < r) + (of waves < w in
+// round r) + (of lanes < j).
+struct TileRank {
+    int32_t before_round[PI];  // low flags of the tile before round r
+    int32_t wave_off[PI];      // low flags of round r in the waves before this one
     int32_t total;
-    int32_t run = block_excl_scan<PT>(cnt, tmp, total);
+};
+
+__device__ inline void tile_rank(const uint64_t *bal, int32_t (*wc)[PT / WAVE], TileRank &tr) {
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int r = 0; r < PI; ++r) wc[r][w] = (int32_t)__popcll(bal[r]);
+    }
+    __syncthreads();
+    int32_t run = 0;
 #pragma unroll
     for (int r = 0; r < PI; ++r) {
-        if ((starts >> r) & 1) segbase_local[segs[r]] = run;
-        run += (flags >> r) & 1;
+        tr.before_round[r] = run;
+        int32_t off = 0;
+#pragma unroll
+        for (int q = 0; q < PT / WAVE; ++q) {
+            const int32_t v = wc[r][q];
+            off += (q < w) ? v : 0;
+            run += v;
+        }
+        tr.wave_off[r] = off;
     }
-    if (threadIdx.x == 0) tcount[blockIdx.x] = total;
+    tr.total = run;
 }
 
-__global__ void __launch_bounds__(PT) k_part_scatter(const int32_t *__restrict__ R0, const int32_t *__restrict__ R1,
-                                                     int keysel, int64_t n, const int32_t *__restrict__ st,
-                                                     const int32_t *__restrict__ st1, int64_t nseg,
-                                                     const int32_t *__restrict__ thr, const int32_t *__restrict__ tpre,
-                                                     const int32_t *__restrict__ segbase_local,
-                                                     int32_t *__restrict__ O0, int32_t *__restrict__ O1) {
-    __shared__ int32_t tmp[PT / 64];
-    const int64_t i0 = (int64_t)blockIdx.x * PTILE + (int64_t)threadIdx.x * PI;
-    int64_t seg = (i0 < n) ? find_seg(st, nseg, n, i0) : 0;
-    int32_t v0[PI], v1[PI];
-    int64_t segs[PI];
-    int32_t flags = 0, cnt = 0;
+// Blocks [0, ntile): count the low flags of each tile, and for every segment
+// that starts in the tile, the low flags of the tile before its start.
+// Blocks [ntile, ...): one thread per segment, segment_record.
+__global__ void __launch_bounds__(PT) k_part_count(int h, const int32_t *__restrict__ key, int64_t n, int ntile,
+                                                   const int32_t *__restrict__ st, int64_t nseg,
+                                                   const int32_t *__restrict__ med_list,
+                                                   int32_t *__restrict__ tcount, int32_t *__restrict__ segbase_local,
+                                                   int32_t *__restrict__ st1, const double *__restrict__ coord,
+                                                   double *__restrict__ split_cur,
+                                                   const double *__restrict__ split_prev, Rect *__restrict__ rects) {
+    if ((int)blockIdx.x >= ntile) {
+        const int64_t s = (int64_t)(blockIdx.x - ntile) * PT + threadIdx.x;
+        if (s < nseg) segment_record(h, s, nseg, n, st, st1, med_list, coord, split_cur, split_prev, rects);
+        return;
+    }
+    __shared__ int32_t wc[PI][PT / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * PTILE + threadIdx.x;
+    uint64_t bal[PI];
+    int32_t startmask = 0;
 #pragma unroll
     for (int r = 0; r < PI; ++r) {
-        const int64_t i = i0 + r;
-        segs[r] = 0;
-        v0[r] = 0;
-        v1[r] = 0;
+        const int64_t i = base + (int64_t)r * PT;
+        bool f = false;
         if (i < n) {
-            while (st[seg + 1] <= i) ++seg;
-            segs[r] = seg;
-            v0[r] = R0[i];
-            v1[r] = R1[i];
-            const int32_t f = (keysel ? v1[r] : v0[r]) < thr[seg];
-            flags |= f << r;
-            cnt += f;
+            const int64_t s = find_seg(st, nseg, n, i);
+            f = key[i] < seg_threshold(st, med_list, s);
+            startmask |= (int32_t)(st[s] == i) << r;
+        }
+        bal[r] = __ballot(f);
+    }
+    TileRank tr;
+    tile_rank(bal, wc, tr);
+    if (startmask) {
+        const uint64_t below_me = (1ull << lane_id()) - 1ull;
+#pragma unroll
+        for (int r = 0; r < PI; ++r) {
+            if ((startmask >> r) & 1) {
+                const int64_t i = base + (int64_t)r * PT;
+                segbase_local[find_seg(st, nseg, n, i)] =
+                    tr.before_round[r] + tr.wave_off[r] + (int32_t)__popcll(bal[r] & below_me);
+            }
         }
     }
-    int32_t total;
-    int32_t run = tpre[blockIdx.x] + block_excl_scan<PT>(cnt, tmp, total);
+    if (threadIdx.x == 0) tcount[blockIdx.x] = tr.total;
+}
+
+// Stable partition of (R0, R1) by the low flag.  tpre: exclusive prefix of the
+// tile counts, or (LOCAL) the raw tile counts, whose prefix every block then
+// forms in LDS (ntile <= LOCAL_TILES).
+constexpr int LOCAL_TILES = 1024;
+template <bool LOCAL>
+__global__ void __launch_bounds__(PT) k_part_scatter(const int32_t *__restrict__ R0, const int32_t *__restrict__ R1,
+                                                     int keysel, int64_t n, int ntile, const int32_t *__restrict__ st,
+                                                     int64_t nseg, const int32_t *__restrict__ med_list,
+                                                     const int32_t *__restrict__ tpre,
+                                                     const int32_t *__restrict__ segbase_local,
+                                                     int32_t *__restrict__ O0, int32_t *__restrict__ O1) {
+    __shared__ int32_t wc[PI][PT / WAVE];
+    __shared__ int32_t tp[LOCAL ? LOCAL_TILES : 1];
+    __shared__ int32_t tmp[PT / WAVE];
+    if (LOCAL) {
+        constexpr int PER = LOCAL_TILES / PT;
+        int32_t v[PER], sum = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int k = threadIdx.x * PER + j;
+            v[j] = k < ntile ? tpre[k] : 0;
+            sum += v[j];
+        }
+        int32_t total;
+        int32_t run = block_excl_scan<PT>(sum, tmp, total);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            tp[threadIdx.x * PER + j] = run;
+            run += v[j];
+        }
+    }
+    const int64_t base = (int64_t)blockIdx.x * PTILE + threadIdx.x;
+    uint64_t bal[PI];
+    int32_t v0[PI], v1[PI], segs[PI];
 #pragma unroll
     for (int r = 0; r < PI; ++r) {
-        const int64_t i = i0 + r;
+        const int64_t i = base + (int64_t)r * PT;
+        bool f = false;
+        v0[r] = 0;
+        v1[r] = 0;
+        segs[r] = 0;
+        if (i < n) {
+            const int64_t s = find_seg(st, nseg, n, i);
+            segs[r] = (int32_t)s;
+            v0[r] = R0[i];
+            v1[r] = R1[i];
+            f = (keysel ? v1[r] : v0[r]) < seg_threshold(st, med_list, s);
+        }
+        bal[r] = __ballot(f);
+    }
+    TileRank tr;
+    tile_rank(bal, wc, tr);  // its barrier also publishes tp
+    const uint64_t below_me = (1ull << lane_id()) - 1ull;
+    const uint64_t me = 1ull << lane_id();
+    const int32_t tile_base = LOCAL ? tp[blockIdx.x] : tpre[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {
+        const int64_t i = base + (int64_t)r * PT;
         if (i < n) {
             const int64_t s = segs[r];
             const int32_t a = st[s];
-            const int32_t lowbase = tpre[a / PTILE] + segbase_local[s];
-            const int32_t below = run - lowbase;  // low flags in the segment before i
-            const int32_t f = (flags >> r) & 1;
+            const int32_t k = (st[s + 1] - a) >> 1;
+            const int32_t tile_a = (int32_t)(a / PTILE);
+            const int32_t lowbase = (LOCAL ? tp[tile_a] : tpre[tile_a]) + segbase_local[s];
+            const int32_t pos = tile_base + tr.before_round[r] + tr.wave_off[r] + (int32_t)__popcll(bal[r] & below_me);
+            const int32_t below = pos - lowbase;  // low flags of the segment before i
             int64_t dst;
-            if (f) dst = (int64_t)a + below;
-            else dst = (int64_t)st1[2 * s + 1] + ((int32_t)(i - a) - below);
+            if (bal[r] & me) dst = (int64_t)a + below;
+            else dst = (int64_t)a + k + ((int32_t)(i - a) - below);
             O0[dst] = v0[r];
             O1[dst] = v1[r];
-            run += f;
         }
     }
 }
@@ -232,21 +304,18 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
     FMM2D_TRY(t.py.ensure(sizeof(double) * n));
     FMM2D_TRY(t.loc.ensure(sizeof(float2) * n));
     const int64_t maxseg = int64_t(1) << (2 * L);
-    FMM2D_TRY(s.thr.ensure(sizeof(int32_t) * maxseg));
     FMM2D_TRY(s.split0.ensure(sizeof(double) * maxseg));
     FMM2D_TRY(s.split1.ensure(sizeof(double) * maxseg));
     FMM2D_TRY(s.segbase.ensure(sizeof(int32_t) * maxseg));
     const int ntile = (int)((n + PTILE - 1) / PTILE);
     FMM2D_TRY(s.tiles2.ensure(sizeof(int32_t) * (ntile + 1)));
 
-    // 1. sort each coordinate by (value, index)
+    // 1. sort each coordinate by (value, index); ranks of the points
     int32_t *yorder = t.YLx.as<int32_t>();  // borrowed until the lists are initialised
-    FMM2D_TRY(sort_coordinate(c, x, n, t.xsorted.as<double>(), t.xorder.as<int32_t>()));
-    FMM2D_TRY(sort_coordinate(c, y, n, t.ysorted.as<double>(), yorder));
-    // 2. ranks and the two rank lists
     int32_t *xrank = t.T0.as<int32_t>(), *yrank = t.T1.as<int32_t>();
-    hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.xorder.as<int32_t>(), n, xrank);
-    hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, yorder, n, yrank);
+    FMM2D_TRY(sort_finish(c, n, t.xsorted.as<double>(), t.ysorted.as<double>(), t.xorder.as<int32_t>(), yorder,
+                          xrank, yrank));
+    // 2. the two rank lists
     // YLx is overwritten last: read yorder (== YLx storage) before writing it.
     // k_init_lists reads yorder[r] and writes YLx[r] for the same r only.
     hipLaunchKernelGGL(k_init_lists, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.xorder.as<int32_t>(), yorder,
@@ -268,20 +337,25 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
         int32_t *st1 = starts + depth_offset(h + 1);
         const bool xsplit = (h & 1) == 0;
         double *split_cur = xsplit ? s.split0.as<double>() : s.split1.as<double>();
-        hipLaunchKernelGGL(k_threshold, dim3(grid_for(nseg, 256)), dim3(256), 0, c->stream, h, nseg, n, st, st1,
-                           xsplit ? XLx : YLy, xsplit ? t.xsorted.as<double>() : t.ysorted.as<double>(),
-                           s.thr.as<int32_t>(), split_cur, s.split0.as<double>(), rects);
-        // partition the other list: YL by x flag, or XL by y flag
+        // partition the other list: YL by the x flag, or XL by the y flag
         int32_t *R0 = xsplit ? YLx : XLx;
         int32_t *R1 = xsplit ? YLy : XLy;
         const int keysel = xsplit ? 0 : 1;
-        hipLaunchKernelGGL(k_part_count, dim3(ntile), dim3(PT), 0, c->stream, keysel ? R1 : R0, n, st, nseg,
-                           s.thr.as<int32_t>(), s.tiles2.as<int32_t>(), s.segbase.as<int32_t>());
-        FMM2D_TRY(scan_exclusive(c, s.tiles2.as<int32_t>(), ntile, s.tiles2.as<int32_t>() + 0));
+        const int32_t *med = xsplit ? XLx : YLy;
+        const int nrec_blocks = (int)grid_for(nseg, PT);
+        hipLaunchKernelGGL(k_part_count, dim3(ntile + nrec_blocks), dim3(PT), 0, c->stream, h, keysel ? R1 : R0, n,
+                           ntile, st, nseg, med, s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), st1,
+                           xsplit ? t.xsorted.as<double>() : t.ysorted.as<double>(), split_cur,
+                           s.split0.as<double>(), rects);
         FMM2D_TRY(hipGetLastError());
-        (void)0;
-        hipLaunchKernelGGL(k_part_scatter, dim3(ntile), dim3(PT), 0, c->stream, R0, R1, keysel, n, st, st1, nseg,
-                           s.thr.as<int32_t>(), s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
+        if (ntile <= LOCAL_TILES) {
+            hipLaunchKernelGGL(k_part_scatter<true>, dim3(ntile), dim3(PT), 0, c->stream, R0, R1, keysel, n, ntile,
+                               st, nseg, med, s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
+        } else {
+            FMM2D_TRY(scan_exclusive(c, s.tiles2.as<int32_t>(), ntile, s.tiles2.as<int32_t>()));
+            hipLaunchKernelGGL(k_part_scatter<false>, dim3(ntile), dim3(PT), 0, c->stream, R0, R1, keysel, n, ntile,
+                               st, nseg, med, s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
+        }
         FMM2D_TRY(hipGetLastError());
         if (xsplit) {
             YLx = T0; YLy = T1; T0 = R0; T1 = R1;
