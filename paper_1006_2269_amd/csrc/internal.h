@@ -78,6 +78,7 @@ struct TreeState {
     DevBuf loc;             // float2 [n], offsets from the leaf centre
     // lists: row pointers of every level (ptr_offset), index pools
     DevBuf sptr, wptr, sidx, widx, cnt_s, cnt_w;
+    DevBuf bits;            // uint64: theta decisions of one level's candidates
     DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
     DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range, FP32 centre offset, threshold
     bool nrec_valid = false;

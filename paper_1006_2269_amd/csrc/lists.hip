@@ -51,12 +51,25 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool,
     pool_state[1] = 1;  // S offset of level 1
 }
 
+// First word of box b's decision bits: candidates of b are preceded by
+// cand(b) = 16 sptr_prev[P] + (b mod 4) 4 |S_{l-1}(P)| candidates of the
+// level, and b needs ceil(ncand / 64) words, so floor(cand(b) / 64) + b never
+// overlaps the words of box b - 1.
+__device__ inline int64_t bits_base(int64_t b, int32_t s0, int32_t s1) {
+    const int64_t cand = 16 * (int64_t)s0 + (b & 3) * 4 * (int64_t)(s1 - s0);
+    return (cand >> 6) + b;
+}
+
+// Count pass (FILL = false): one wavefront per box tests its candidates,
+// stores the decisions (bit set: weak) and the two counts.  Fill pass: the
+// same candidates, the stored decisions, ballot compaction into the lists.
 template <bool FILL>
 __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double theta, const double4 *__restrict__ geomL,
                                                         const int32_t *__restrict__ sptr_prev,
                                                         const int32_t *__restrict__ sidx_pool,
                                                         const int64_t *__restrict__ pool_state, int64_t nb,
                                                         int32_t *__restrict__ ns, int32_t *__restrict__ nw,
+                                                        uint64_t *__restrict__ bits,
                                                         const int32_t *__restrict__ sptr_cur,
                                                         const int32_t *__restrict__ wptr_cur,
                                                         int32_t *__restrict__ sidx_out, int32_t *__restrict__ widx_out) {
@@ -72,7 +85,9 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
     const int64_t P = b >> 2;
     const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
     const int32_t ncand = 4 * (s1 - s0);
-    const double4 gb = geomL[b];
+    uint64_t *bw = bits + bits_base(b, s0, s1);
+    double4 gb;
+    if (!FILL) gb = geomL[b];
     int32_t cs = 0, cw = 0;
     int32_t *so = nullptr, *wo = nullptr;
     if (FILL) {
@@ -83,15 +98,23 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
         const int32_t j = base + (int32_t)lane;
         const bool ok = j < ncand;
         int32_t cbox = 0;
-        bool weak = false;
-        if (ok) {
-            cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
-            weak = theta_separated(theta, gb, geomL[cbox]);
+        uint64_t mw;
+        if (FILL) {
+            mw = bw[base >> 6];
+            if (ok) cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
+        } else {
+            bool weak = false;
+            if (ok) {
+                cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
+                weak = theta_separated(theta, gb, geomL[cbox]);
+            }
+            mw = __ballot(ok && weak);
+            if (lane == 0) bw[base >> 6] = mw;
         }
-        const uint64_t mw = __ballot(ok && weak);
-        const uint64_t ms = __ballot(ok && !weak);
+        const uint64_t okm = __ballot(ok);
+        const uint64_t ms = okm & ~mw;
         if (FILL && ok) {
-            if (weak) wo[cw + (int32_t)popc_below(mw)] = cbox;
+            if ((mw >> lane) & 1) wo[cw + (int32_t)popc_below(mw)] = cbox;
             else so[cs + (int32_t)popc_below(ms)] = cbox;
         }
         cw += (int32_t)__popcll(mw);
@@ -152,8 +175,11 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
         }
         const double4 *gL = geom + level_offset(l);
         const unsigned grid = grid_for(nb, LW);
+        // decision words: at most 16 s_prev candidates / 64 + one spare per box
+        FMM2D_TRY(t.bits.ensure(sizeof(uint64_t) * (size_t)((16 * s_prev) / 64 + nb + 1)));
+        uint64_t *bits = t.bits.as<uint64_t>();
         hipLaunchKernelGGL(k_lists_level<false>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
-                           t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), sp_cur, wp_cur,
+                           t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), bits, sp_cur, wp_cur,
                            t.sidx.as<int32_t>(), t.widx.as<int32_t>());
         {
             const int32_t *ins[2] = {t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>()};
@@ -164,7 +190,7 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
         hipLaunchKernelGGL(k_lists_advance, dim3(1), dim3(1), 0, c->stream, l, L, nb, sp_cur, wp_cur, ps, cap_s,
                            cap_w);
         hipLaunchKernelGGL(k_lists_level<true>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
-                           t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), sp_cur, wp_cur,
+                           t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), bits, sp_cur, wp_cur,
                            t.sidx.as<int32_t>(), t.widx.as<int32_t>());
         FMM2D_TRY(hipGetLastError());
     }

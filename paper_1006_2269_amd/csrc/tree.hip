@@ -21,18 +21,30 @@ namespace fmm2d {
 namespace {
 
 constexpr int PT = 256;     // threads per partition block
-constexpr int PI = 16;      // items per thread (blocked)
+constexpr int PI = 4;       // items per thread (striped)
 constexpr int PTILE = PT * PI;
 
 struct Rect {
     double xlo, xhi, ylo, yhi;
 };
 
-__device__ inline int64_t find_seg(const int32_t *__restrict__ st, int64_t nseg, int64_t n, int64_t i) {
-    int64_t s = (i * nseg) / n;
-    if (s > nseg - 1) s = nseg - 1;
-    while (st[s] > i) --s;
-    while (st[s + 1] <= i) ++s;
+// Segment of depth h holding list position i, and its range [a, e): the
+// split of [a, e) puts floor((e - a) / 2) positions low, so the path from the
+// root follows from i alone (no table lookups).  Segment s of depth 2l is box
+// s of level l.
+__device__ inline int64_t seg_of(int64_t i, int64_t n, int h, int32_t &a, int32_t &e) {
+    int32_t lo = 0, hi = (int32_t)n;
+    const int32_t ii = (int32_t)i;
+    int64_t s = 0;
+    for (int d = 0; d < h; ++d) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        const bool up = ii >= mid;
+        s = 2 * s + (up ? 1 : 0);
+        lo = up ? mid : lo;
+        hi = up ? hi : mid;
+    }
+    a = lo;
+    e = hi;
     return s;
 }
 
@@ -54,15 +66,6 @@ __global__ void k_init_lists(const int32_t *__restrict__ xorder, const int32_t *
         YLy[r] = (int32_t)r;
         YLx[r] = xrank[yorder[r]];
     }
-}
-
-// Segment s of depth h: its median entry is the one at offset floor(m/2) of
-// the list sorted along the split axis, and an entry of the other list is low
-// iff its rank along that axis is below the median's.
-__device__ inline int32_t seg_threshold(const int32_t *__restrict__ st, const int32_t *__restrict__ med_list,
-                                        int64_t s) {
-    const int32_t a = st[s], e = st[s + 1];
-    return med_list[a + ((e - a) >> 1)];
 }
 
 // Per segment of depth h: split line, child offsets, and (after a y split)
@@ -145,31 +148,27 @@ __global__ void __launch_bounds__(PT) k_part_count(int h, const int32_t *__restr
     __shared__ int32_t wc[PI][PT / WAVE];
     const int64_t base = (int64_t)blockIdx.x * PTILE + threadIdx.x;
     uint64_t bal[PI];
-    int32_t startmask = 0;
+    int32_t segs[PI];  // segment starting at this position, or -1
 #pragma unroll
     for (int r = 0; r < PI; ++r) {
         const int64_t i = base + (int64_t)r * PT;
         bool f = false;
+        segs[r] = -1;
         if (i < n) {
-            const int64_t s = find_seg(st, nseg, n, i);
-            f = key[i] < seg_threshold(st, med_list, s);
-            startmask |= (int32_t)(st[s] == i) << r;
+            int32_t a, e;
+            const int64_t s = seg_of(i, n, h, a, e);
+            f = key[i] < med_list[a + ((e - a) >> 1)];
+            if (a == (int32_t)i) segs[r] = (int32_t)s;
         }
         bal[r] = __ballot(f);
     }
     TileRank tr;
     tile_rank(bal, wc, tr);
-    if (startmask) {
-        const uint64_t below_me = (1ull << lane_id()) - 1ull;
+    const uint64_t below_me = (1ull << lane_id()) - 1ull;
 #pragma unroll
-        for (int r = 0; r < PI; ++r) {
-            if ((startmask >> r) & 1) {
-                const int64_t i = base + (int64_t)r * PT;
-                segbase_local[find_seg(st, nseg, n, i)] =
-                    tr.before_round[r] + tr.wave_off[r] + (int32_t)__popcll(bal[r] & below_me);
-            }
-        }
-    }
+    for (int r = 0; r < PI; ++r)
+        if (segs[r] >= 0)
+            segbase_local[segs[r]] = tr.before_round[r] + tr.wave_off[r] + (int32_t)__popcll(bal[r] & below_me);
     if (threadIdx.x == 0) tcount[blockIdx.x] = tr.total;
 }
 
@@ -178,9 +177,9 @@ __global__ void __launch_bounds__(PT) k_part_count(int h, const int32_t *__restr
 // forms in LDS (ntile <= LOCAL_TILES).
 constexpr int LOCAL_TILES = 1024;
 template <bool LOCAL>
-__global__ void __launch_bounds__(PT) k_part_scatter(const int32_t *__restrict__ R0, const int32_t *__restrict__ R1,
-                                                     int keysel, int64_t n, int ntile, const int32_t *__restrict__ st,
-                                                     int64_t nseg, const int32_t *__restrict__ med_list,
+__global__ void __launch_bounds__(PT) k_part_scatter(int h, const int32_t *__restrict__ R0,
+                                                     const int32_t *__restrict__ R1, int keysel, int64_t n, int ntile,
+                                                     const int32_t *__restrict__ med_list,
                                                      const int32_t *__restrict__ tpre,
                                                      const int32_t *__restrict__ segbase_local,
                                                      int32_t *__restrict__ O0, int32_t *__restrict__ O1) {
@@ -215,11 +214,11 @@ __global__ void __launch_bounds__(PT) k_part_scatter(const int32_t *__restrict__
         v1[r] = 0;
         segs[r] = 0;
         if (i < n) {
-            const int64_t s = find_seg(st, nseg, n, i);
-            segs[r] = (int32_t)s;
+            int32_t a, e;
+            segs[r] = (int32_t)seg_of(i, n, h, a, e);
             v0[r] = R0[i];
             v1[r] = R1[i];
-            f = (keysel ? v1[r] : v0[r]) < seg_threshold(st, med_list, s);
+            f = (keysel ? v1[r] : v0[r]) < med_list[a + ((e - a) >> 1)];
         }
         bal[r] = __ballot(f);
     }
@@ -233,8 +232,9 @@ __global__ void __launch_bounds__(PT) k_part_scatter(const int32_t *__restrict__
         const int64_t i = base + (int64_t)r * PT;
         if (i < n) {
             const int64_t s = segs[r];
-            const int32_t a = st[s];
-            const int32_t k = (st[s + 1] - a) >> 1;
+            int32_t a, e;
+            seg_of(i, n, h, a, e);
+            const int32_t k = (e - a) >> 1;
             const int32_t tile_a = (int32_t)(a / PTILE);
             const int32_t lowbase = (LOCAL ? tp[tile_a] : tpre[tile_a]) + segbase_local[s];
             const int32_t pos = tile_base + tr.before_round[r] + tr.wave_off[r] + (int32_t)__popcll(bal[r] & below_me);
@@ -267,8 +267,7 @@ __global__ void k_geometry(const Rect *__restrict__ rects, int64_t nbox, double4
 
 __global__ void k_gather(const int32_t *__restrict__ XLx, const int32_t *__restrict__ XLy,
                          const int32_t *__restrict__ xorder, const double *__restrict__ xs,
-                         const double *__restrict__ ys, const int32_t *__restrict__ stL, int64_t nleaf, int64_t n,
-                         const double4 *__restrict__ geomL, int32_t *__restrict__ perm, double *__restrict__ px,
+                         const double *__restrict__ ys, int L, int64_t n, const double4 *__restrict__ geomL, int32_t *__restrict__ perm, double *__restrict__ px,
                          double *__restrict__ py, float2 *__restrict__ loc, int32_t *__restrict__ leafid) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -277,7 +276,8 @@ __global__ void k_gather(const int32_t *__restrict__ XLx, const int32_t *__restr
     const double x = xs[xr], y = ys[yr];
     px[i] = x;
     py[i] = y;
-    const int64_t leaf = find_seg(stL, nleaf, n, i);
+    int32_t a, e;
+    const int64_t leaf = seg_of(i, n, 2 * L, a, e);
     leafid[i] = (int32_t)leaf;
     const double4 g = geomL[leaf];
     loc[i] = make_float2((float)(x - g.x), (float)(y - g.y));
@@ -349,12 +349,12 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
                            s.split0.as<double>(), rects);
         FMM2D_TRY(hipGetLastError());
         if (ntile <= LOCAL_TILES) {
-            hipLaunchKernelGGL(k_part_scatter<true>, dim3(ntile), dim3(PT), 0, c->stream, R0, R1, keysel, n, ntile,
-                               st, nseg, med, s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
+            hipLaunchKernelGGL(k_part_scatter<true>, dim3(ntile), dim3(PT), 0, c->stream, h, R0, R1, keysel, n,
+                               ntile, med, s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
         } else {
             FMM2D_TRY(scan_exclusive(c, s.tiles2.as<int32_t>(), ntile, s.tiles2.as<int32_t>()));
-            hipLaunchKernelGGL(k_part_scatter<false>, dim3(ntile), dim3(PT), 0, c->stream, R0, R1, keysel, n, ntile,
-                               st, nseg, med, s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
+            hipLaunchKernelGGL(k_part_scatter<false>, dim3(ntile), dim3(PT), 0, c->stream, h, R0, R1, keysel, n,
+                               ntile, med, s.tiles2.as<int32_t>(), s.segbase.as<int32_t>(), T0, T1);
         }
         FMM2D_TRY(hipGetLastError());
         if (xsplit) {
@@ -371,7 +371,7 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
                        t.geom.as<double4>());
     hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, XLx, XLy,
                        t.xorder.as<int32_t>(), t.xsorted.as<double>(), t.ysorted.as<double>(),
-                       starts + depth_offset(2 * L), nleaf, n, t.geom.as<double4>() + level_offset(L),
+                       L, n, t.geom.as<double4>() + level_offset(L),
                        t.perm.as<int32_t>(), t.px.as<double>(), t.py.as<double>(), t.loc.as<float2>(),
                        t.leafid.as<int32_t>());
     return hipGetLastError();
