@@ -118,6 +118,72 @@ int fmm2d_evaluate(fmm2d_ctx *ctx, const double *q, int p, int mode, double *phi
 int fmm2d_direct(fmm2d_ctx *ctx, const double *x, const double *y, const double *q,
                  int64_t n, const int64_t *targets, int64_t m, double *phi_m);
 
+/* ---- parameter selection -------------------------------------------------- */
+
+/* Density features of a point set (the selector's input), FMM2D_NFEAT floats:
+ *   [0] log10 n, [1] log10 tol, then for each level l = 1..10 of a uniform
+ *   2^l x 2^l grid over the points' tight bounding box, 9 values:
+ *   the fraction of occupied cells, then the fractions of the n points whose
+ *   cell has relative density r = count 4^l / n in bin k = 0..7, where k is
+ *   the number of the edges 1/8, 1/4, 1/2, 1, 2, 4, 8 that are <= r.
+ * A point's cell along x is floor((x - xmin) 1024 / (xmax - xmin)) clamped
+ * to [0, 1023] at level 10 (0 when xmax = xmin), shifted right by 10 - l for
+ * level l; likewise along y.  Counts are exact integers, so the output is
+ * deterministic.
+ * x, y: device double [n]; feat: device float [FMM2D_NFEAT].
+ * 1 <= n <= 2^31 - 1, 0 < tol < 1.  Coordinates are not validated here. */
+#define FMM2D_NFEAT 92
+int fmm2d_features(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, double tol, float *feat);
+
+/* Chooses (levels, p, theta) for tolerance tol on the points x, y.
+ * weights: device float blob of a trained selector, or NULL:
+ *   [0, 92)    mean of each feature
+ *   [92, 184)  1 / standard deviation of each feature (network input is
+ *              (feature - mean) * scale)
+ *   [184, 187) mean of the three targets (levels - L0, p, theta)
+ *   [187, 190) standard deviation of the three targets
+ *   [190, 194) trained range: log10 n low, high, log10 tol low, high
+ *   [194, 194 + fmm2d_mlp_nparams(92)) network parameters (see fmm2d_mlp_forward)
+ * With weights and inputs inside the trained range, the network's outputs
+ * give levels = round(L0 + out0) with L0 = round(log4(n / 16)), p =
+ * ceil(out1) + 1, theta = out2 snapped to {0.35, 0.45, 0.55, 0.65, 0.75}.
+ * Otherwise (NULL weights, n or tol outside the range, non-finite output)
+ * the a-priori rule, the practical choice at the end of Section 4: theta =
+ * 1/2, levels = round(log4(n / 20)) (about 20 points per leaf), p = the least
+ * p with 0.1 theta^(p+1) / (1 - theta)^2 <= tol (the truncation bound of
+ * Section 3 with a calibrated constant).  round() is round-half-up.  levels is clamped to
+ * [1, min(13, floor(log4 n))] and p to [1, 63].
+ * Host outputs levels, p, theta; from_network (may be NULL) is 1 when the
+ * network decided, 0 for the rule.  4 <= n <= 2^31 - 1, 0 < tol < 1.
+ * Returns FMM2D_EINVAL for non-finite coordinates or |v| > 2^500.
+ * Synchronises the context stream. */
+#define FMM2D_SELECT_HEADER 194
+int fmm2d_select(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, double tol, const float *weights,
+                 int *levels, int *p, double *theta, int *from_network);
+
+/* The selector network: d_in -> 64 -> 64 -> 64 -> 3, tanh on the hidden
+ * layers, linear output, FP32.  The flat parameter vector holds each layer
+ * in turn as its weight matrix [fan_out][fan_in] (row-major) followed by its
+ * bias.  Returns the parameter count, or -1 for d_in outside [1, 128]. */
+#define FMM2D_MLP_MAX_IN 128
+int64_t fmm2d_mlp_nparams(int d_in);
+
+/* Y[batch][3] = network(X[batch][d_in]).  All device float, row-major. */
+int fmm2d_mlp_forward(fmm2d_ctx *ctx, const float *params, const float *X, int64_t batch, int d_in, float *Y);
+
+/* Mean-squared error over all batch x 3 outputs against Y, into *loss
+ * (device float [1]), and its gradient with respect to params into grad
+ * (device float [nparams]).  The sum over samples has a fixed order.
+ * batch <= 2^24. */
+int fmm2d_mlp_grad(fmm2d_ctx *ctx, const float *params, const float *X, const float *Y, int64_t batch, int d_in,
+                   float *grad, float *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments;
+ * step counts from 1) on params with moments m, v, all device float
+ * [nparams], updated in place. */
+int fmm2d_mlp_adam(fmm2d_ctx *ctx, float *params, float *m, float *v, const float *grad, int64_t nparams, int step,
+                   float lr);
+
 /* ---- introspection (used by the parity tests) ---------------------------- */
 
 /* Host outputs: number of points, levels and boxes of the current tree. */

@@ -344,7 +344,8 @@ def a_priori(n: int, tol: float, k_const: float, theta: float = 0.5,
     """(levels, p, theta): theta = 1/2, about `per_leaf` sources per leaf, and
     the least p with k_const * theta^(p+1) / (1-theta)^2 <= tol."""
     lmax = int(math.floor(math.log(n, 4) + 1e-12))
-    levels = int(round(math.log(max(n / per_leaf, 1.0), 4)))
+    # round half up (Python's round() would round half to even)
+    levels = int(math.floor(math.log(max(n / per_leaf, 1.0)) / math.log(4.0) + 0.5))
     levels = max(1, min(levels, lmax, 13))
     p = 1
     while k_const * theta ** (p + 1) / (1.0 - theta) ** 2 > tol and p < 63:

@@ -43,9 +43,18 @@ SIGNATURES = [
     ("fmm2d_get_rects", I32, [P, P]),
     ("fmm2d_list_sizes", I32, [P, I32, PI64, PI64]),
     ("fmm2d_get_lists", I32, [P, I32, P, P, P, P]),
+    ("fmm2d_features", I32, [P, P, P, I64, D, P]),
+    ("fmm2d_select", I32, [P, P, P, I64, D, P, PI32, PI32, PD, PI32]),
+    ("fmm2d_mlp_nparams", I64, [I32]),
+    ("fmm2d_mlp_forward", I32, [P, P, P, I64, I32, P]),
+    ("fmm2d_mlp_grad", I32, [P, P, P, P, I64, I32, P, P]),
+    ("fmm2d_mlp_adam", I32, [P, P, P, P, P, I64, I32, F]),
     ("fmm2d_timing", I32, [P, I32]),
     ("fmm2d_get_timings", I32, [P, P, P]),
 ]
+
+NFEAT = 92
+SELECT_HEADER = 194
 
 PHASES = ["tree", "lists", "upward", "m2l", "l2l", "leaf", "other", "judge", "select"]
 

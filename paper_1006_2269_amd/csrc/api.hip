@@ -236,6 +236,84 @@ int fmm2d_direct(fmm2d_ctx *c, const double *x, const double *y, const double *q
     return FMM2D_OK;
 }
 
+int fmm2d_features(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, float *feat) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!x || !y || !feat) return fail(c, FMM2D_EINVAL, "features: NULL pointer");
+    if (n < 1 || n > 2147483647LL) return fail(c, FMM2D_EINVAL, "features: n = %lld not in [1, 2^31-1]", (long long)n);
+    if (!(tol > 0.0 && tol < 1.0)) return fail(c, FMM2D_EINVAL, "features: tol must lie in (0, 1)");
+    DeviceGuard g(c->device);
+    hipError_t e = features_device(c, x, y, n, tol, feat, nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "features");
+    return FMM2D_OK;
+}
+
+int fmm2d_select(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, const float *weights,
+                 int *levels, int *p, double *theta, int *from_network) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!x || !y || !levels || !p || !theta) return fail(c, FMM2D_EINVAL, "select: NULL pointer");
+    if (n < 4 || n > 2147483647LL) return fail(c, FMM2D_EINVAL, "select: n = %lld not in [4, 2^31-1]", (long long)n);
+    if (!(tol > 0.0 && tol < 1.0)) return fail(c, FMM2D_EINVAL, "select: tol must lie in (0, 1)");
+    DeviceGuard g(c->device);
+    int out[4] = {0, 0, 0, 0};
+    double th = 0.0;
+    hipError_t e;
+    {
+        PhaseScope ps(c, PH_SELECT);
+        e = select_device(c, x, y, n, tol, weights, out, &th);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "select");
+    if (out[3]) return fail(c, FMM2D_EINVAL, "select: coordinates must be finite with |v| <= 2^500");
+    *levels = out[0];
+    *p = out[1];
+    *theta = th;
+    if (from_network) *from_network = out[2];
+    return FMM2D_OK;
+}
+
+int64_t fmm2d_mlp_nparams(int d_in) {
+    if (d_in < 1 || d_in > FMM2D_MLP_MAX_IN) return -1;
+    return mlp_nparams(d_in);
+}
+
+int fmm2d_mlp_forward(fmm2d_ctx *c, const float *params, const float *X, int64_t batch, int d_in, float *Y) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!params || !X || !Y) return fail(c, FMM2D_EINVAL, "mlp_forward: NULL pointer");
+    if (d_in < 1 || d_in > FMM2D_MLP_MAX_IN || batch < 1 || batch > (int64_t(1) << 30))
+        return fail(c, FMM2D_EINVAL, "mlp_forward: need 1 <= d_in <= %d and 1 <= batch <= 2^30", FMM2D_MLP_MAX_IN);
+    DeviceGuard g(c->device);
+    hipError_t e = mlp_forward(c, params, X, batch, d_in, Y);
+    if (e != hipSuccess) return hip_fail(c, e, "mlp_forward");
+    return FMM2D_OK;
+}
+
+int fmm2d_mlp_grad(fmm2d_ctx *c, const float *params, const float *X, const float *Y, int64_t batch, int d_in,
+                   float *grad, float *loss) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!params || !X || !Y || !grad || !loss) return fail(c, FMM2D_EINVAL, "mlp_grad: NULL pointer");
+    if (d_in < 1 || d_in > FMM2D_MLP_MAX_IN || batch < 1 || batch > (int64_t(1) << 24))
+        return fail(c, FMM2D_EINVAL, "mlp_grad: need 1 <= d_in <= %d and 1 <= batch <= 2^24", FMM2D_MLP_MAX_IN);
+    DeviceGuard g(c->device);
+    hipError_t e = mlp_grad(c, params, X, Y, batch, d_in, grad, loss);
+    if (e != hipSuccess) return hip_fail(c, e, "mlp_grad");
+    return FMM2D_OK;
+}
+
+int fmm2d_mlp_adam(fmm2d_ctx *c, float *params, float *m, float *v, const float *grad, int64_t nparams, int step,
+                   float lr) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!params || !m || !v || !grad) return fail(c, FMM2D_EINVAL, "mlp_adam: NULL pointer");
+    if (nparams < 1 || step < 1 || !(lr > 0.0f)) return fail(c, FMM2D_EINVAL, "mlp_adam: need nparams >= 1, step >= 1, lr > 0");
+    DeviceGuard g(c->device);
+    hipError_t e = mlp_adam(c, params, m, v, grad, nparams, step, lr);
+    if (e != hipSuccess) return hip_fail(c, e, "mlp_adam");
+    return FMM2D_OK;
+}
+
 int fmm2d_tree_info(const fmm2d_ctx *c, int64_t *n, int *levels, int64_t *nbox) {
     if (!c) return FMM2D_EINVAL;
     if (c->tree.L < 0) return FMM2D_ESTATE;

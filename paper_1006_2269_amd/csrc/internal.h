@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -127,6 +128,7 @@ struct PhaseTimer {
 
 struct Scratch {
     DevBuf keys0, keys1, vals0, vals1, hist, aux, tiles, tiles2, segbase, thr, split0, split1, flag, segcnt;
+    DevBuf sel, sel2;        // selector: counts and features; decision
     int64_t sort_n = -1;     // size of the validated keys waiting in keys0 / vals0, or -1
     uint64_t sort_differ = 0;  // bits in which the keys of either coordinate differ
 };
@@ -156,6 +158,17 @@ hipError_t sort_finish(fmm2d_ctx *c, int64_t n, double *xs, double *ys, int32_t 
                        int32_t *xrank, int32_t *yrank);
 // scan.hip: exclusive scan of int32 in[n] into out[n+1] (out[n] = total)
 hipError_t scan_exclusive(fmm2d_ctx *c, const int32_t *in, int64_t n, int32_t *out);
+// select.hip: density features and the parameter decision (host outputs)
+hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, float *feat,
+                           const float *blob, float *xin, double **box_out);
+hipError_t select_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, const float *blob,
+                         int out[4], double *theta);
+// mlp.hip: the selector network
+int64_t mlp_nparams(int d_in);
+hipError_t mlp_forward(fmm2d_ctx *c, const float *P, const float *X, int64_t batch, int d_in, float *Y);
+hipError_t mlp_grad(fmm2d_ctx *c, const float *P, const float *X, const float *Y, int64_t batch, int d_in,
+                    float *grad, float *loss);
+hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, int64_t np, int step, float lr);
 // the same for k (1 or 2) arrays of one length, in the same launches
 hipError_t scan_exclusive_n(fmm2d_ctx *c, int k, const int32_t *const *in, int64_t n, int32_t *const *out);
 // tree.hip

@@ -1,0 +1,301 @@
+// Parameter selection: density features of the point set, the learned
+// selector's decision, and the a-priori rule it falls back to.
+//
+// Features (NFEAT = 2 + 9 FL floats): log10 N, log10 TOL, then for each
+// level l = 1..FL of a uniform 2^l x 2^l grid over the tight bounding box:
+// the fraction of occupied cells, and an 8-bin histogram of the points by the
+// relative density r = count 4^l / N of their cell (bin k: the number of the
+// edges 1/8, 1/4, 1/2, 1, 2, 4, 8 that are <= r), as fractions of N.  In a
+// median-split tree a box's area is inversely proportional to the density
+// around it, so these histograms describe the spread of box sizes at each
+// level, which sets the list lengths and hence the cost of an (L, p, theta).
+// All counts are integers (cell counts, LDS and global integer atomics), so
+// the features do not depend on scheduling.
+//
+// Decision (after the network, or the rule when no weights are given or the
+// input lies outside the trained range): the rule is the practical choice
+// at the end of Section 4, theta = 1/2 and about 20 points per leaf
+// (L = round(log4(N / 20))), with the least p for which the truncation bound
+// of Section 3, K theta^(p+1) / (1 - theta)^2 with K = 0.1, is <= TOL.  The
+// network predicts L - L0 (L0 = round(log4(N / 16))), p and theta; L is rounded, p rounded up
+// with one extra order as a margin, theta snapped to {0.35, ..., 0.75}.
+#include "devutil.h"
+#include "internal.h"
+
+namespace fmm2d {
+namespace {
+
+constexpr int FL = 10;
+constexpr int NFEAT = 2 + 9 * FL;
+constexpr int HDR = 194;  // weight blob header floats, see fmm2d.h
+constexpr int BT = 256;
+
+// offset of level l (1..FL) in the pyramid of cell counts
+__host__ __device__ inline int64_t cell_off(int l) { return ((int64_t(1) << (2 * l)) - 4) / 3; }
+
+// Per-block min / max of x and y, and whether any coordinate is invalid.
+__global__ void __launch_bounds__(BT) k_bbox_part(const double *__restrict__ x, const double *__restrict__ y,
+                                                  int64_t n, double *__restrict__ part) {
+    __shared__ double s[4][BT];
+    __shared__ int sbad[BT];
+    double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY;
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+        const double a = x[i] + 0.0, b = y[i] + 0.0;
+        bad |= !(fabs(a) <= 0x1p500) || !(fabs(b) <= 0x1p500);
+        xl = fmin(xl, a);
+        xh = fmax(xh, a);
+        yl = fmin(yl, b);
+        yh = fmax(yh, b);
+    }
+    s[0][threadIdx.x] = xl;
+    s[1][threadIdx.x] = xh;
+    s[2][threadIdx.x] = yl;
+    s[3][threadIdx.x] = yh;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = BT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+            sbad[threadIdx.x] |= sbad[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *p = part + 5 * (int64_t)blockIdx.x;
+        p[0] = s[0][0];
+        p[1] = s[1][0];
+        p[2] = s[2][0];
+        p[3] = s[3][0];
+        p[4] = sbad[0] ? 1.0 : 0.0;
+    }
+}
+
+// box = {xmin, xmax, ymin, ymax, sx, sy, bad}: s = 2^FL / extent (0 when the
+// extent is 0, which puts every point in cell 0).
+__global__ void __launch_bounds__(BT) k_bbox_final(const double *__restrict__ part, int nblk,
+                                                   double *__restrict__ box) {
+#pragma clang fp contract(off)
+    __shared__ double s[5][BT];
+    double v[5] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    for (int k = threadIdx.x; k < nblk; k += BT) {
+        const double *p = part + 5 * (int64_t)k;
+        v[0] = fmin(v[0], p[0]);
+        v[1] = fmax(v[1], p[1]);
+        v[2] = fmin(v[2], p[2]);
+        v[3] = fmax(v[3], p[3]);
+        v[4] = fmax(v[4], p[4]);
+    }
+    for (int j = 0; j < 5; ++j) s[j][threadIdx.x] = v[j];
+    __syncthreads();
+    for (int w = BT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+            s[4][threadIdx.x] = fmax(s[4][threadIdx.x], s[4][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double ex = s[1][0] - s[0][0], ey = s[3][0] - s[2][0];
+        box[0] = s[0][0];
+        box[1] = s[1][0];
+        box[2] = s[2][0];
+        box[3] = s[3][0];
+        box[4] = ex > 0.0 ? (double)(1 << FL) / ex : 0.0;
+        box[5] = ey > 0.0 ? (double)(1 << FL) / ey : 0.0;
+        box[6] = s[4][0];
+    }
+}
+
+__global__ void k_zero_i32(int32_t *__restrict__ p, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = 0;
+}
+
+__device__ inline int cell_coord(double v, double lo, double s) {
+#pragma clang fp contract(off)
+    double t = (v - lo) * s;
+    if (!(t >= 0.0)) t = 0.0;  // also NaN
+    if (!(t < (double)(1 << FL))) t = (double)((1 << FL) - 1);
+    return (int)t;
+}
+
+// counts of the finest grid
+__global__ void k_cells(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
+                        const double *__restrict__ box, int32_t *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ix = cell_coord(x[i] + 0.0, box[0], box[4]);
+    const int iy = cell_coord(y[i] + 0.0, box[2], box[5]);
+    atomicAdd(&cnt[((int64_t)iy << FL) + ix], 1);
+}
+
+// level lc from level lc + 1 (2 x 2 sums)
+__global__ void k_pool(const int32_t *__restrict__ fine, int lc, int32_t *__restrict__ coarse) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t side = int64_t(1) << lc;
+    if (c >= side * side) return;
+    const int64_t cy = c >> lc, cx = c & (side - 1);
+    const int lf = lc + 1;
+    const int64_t r0 = (2 * cy) << lf, r1 = (2 * cy + 1) << lf;
+    coarse[c] = fine[r0 + 2 * cx] + fine[r0 + 2 * cx + 1] + fine[r1 + 2 * cx] + fine[r1 + 2 * cx + 1];
+}
+
+// acc[9 (l - 1) + 0]: occupied cells of level l; acc[9 (l - 1) + 1 + k]:
+// points in cells of density class k.
+__global__ void __launch_bounds__(BT) k_feat_hist(const int32_t *__restrict__ cnt, int64_t n,
+                                                  unsigned long long *__restrict__ acc) {
+    __shared__ unsigned long long sh[9 * FL];
+    for (int k = threadIdx.x; k < 9 * FL; k += BT) sh[k] = 0ull;
+    __syncthreads();
+    const int64_t total = cell_off(FL + 1);
+    for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < total; e += (int64_t)gridDim.x * BT) {
+        int l = 1;
+        while (cell_off(l + 1) <= e) ++l;
+        const int32_t cval = cnt[e];
+        if (cval > 0) {
+            // class: edges 2^(j-4), j = 1..7, compared exactly as
+            // count 4^l 16 >= N 2^j
+            const int64_t lhs = (int64_t)cval << (2 * l + 4);
+            int k = 0;
+#pragma unroll
+            for (int j = 1; j <= 7; ++j) k += lhs >= (n << j) ? 1 : 0;
+            atomicAdd(&sh[9 * (l - 1)], 1ull);
+            atomicAdd(&sh[9 * (l - 1) + 1 + k], (unsigned long long)cval);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 9 * FL; k += BT)
+        if (sh[k]) atomicAdd(&acc[k], sh[k]);
+}
+
+// features from the counters; the standardised network input when a blob is
+// given (x = (f - mean) * scale)
+__global__ void k_feat_final(const unsigned long long *__restrict__ acc, int64_t n, double tol,
+                             float *__restrict__ feat, const float *__restrict__ blob, float *__restrict__ xin) {
+    const int k = threadIdx.x;
+    if (k >= NFEAT) return;
+    double f;
+    if (k == 0) f = log10((double)n);
+    else if (k == 1) f = log10(tol);
+    else {
+        const int l = (k - 2) / 9 + 1, j = (k - 2) % 9;
+        f = j == 0 ? (double)acc[k - 2] / (double)(int64_t(1) << (2 * l)) : (double)acc[k - 2] / (double)n;
+    }
+    feat[k] = (float)f;
+    if (blob) xin[k] = ((float)f - blob[k]) * blob[NFEAT + k];
+}
+
+// the a-priori rule
+__device__ inline void rule(int64_t n, double tol, int lmax, int &L, int &p, double &theta) {
+    theta = 0.5;
+    const double x = log((double)n / 20.0 > 1.0 ? (double)n / 20.0 : 1.0) / log(4.0);
+    L = (int)floor(x + 0.5);
+    if (L > lmax) L = lmax;
+    if (L < 1) L = 1;
+    p = 1;
+    double tp = theta * theta;  // theta^(p+1), exact for theta = 1/2
+    while (0.1 * tp / ((1.0 - theta) * (1.0 - theta)) > tol && p < 63) {
+        ++p;
+        tp *= theta;
+    }
+}
+
+// out_i = {levels, p, from_network, bad input}, out_d = {theta}
+__global__ void k_select_final(const float *__restrict__ y, const float *__restrict__ blob, int64_t n, double tol,
+                               const double *__restrict__ box, int *__restrict__ out_i, double *__restrict__ out_d) {
+#pragma clang fp contract(off)
+    const double thetas[5] = {0.35, 0.45, 0.55, 0.65, 0.75};
+    if (threadIdx.x != 0) return;
+    int lmax = 0;
+    while (lmax < FMM2D_MAX_LEVELS && (int64_t(1) << (2 * (lmax + 1))) <= n) ++lmax;
+    int L, p;
+    double theta;
+    bool net = false;
+    if (blob) {
+        const double ln = log10((double)n), lt = log10(tol);
+        const float *rng = blob + 2 * NFEAT + 6;
+        const bool inside = ln >= rng[0] && ln <= rng[1] && lt >= rng[2] && lt <= rng[3];
+        const double dl = (double)y[0] * blob[2 * NFEAT + 3] + blob[2 * NFEAT + 0];
+        const double pp = (double)y[1] * blob[2 * NFEAT + 4] + blob[2 * NFEAT + 1];
+        const double th = (double)y[2] * blob[2 * NFEAT + 5] + blob[2 * NFEAT + 2];
+        if (inside && isfinite(dl) && isfinite(pp) && isfinite(th) && fabs(dl) < 64.0 && fabs(pp) < 1e4) {
+            net = true;
+            const double x0 = log((double)n / 16.0 > 1.0 ? (double)n / 16.0 : 1.0) / log(4.0);
+            const int L0 = (int)floor(x0 + 0.5);
+            L = (int)floor((double)L0 + dl + 0.5);
+            L = L > lmax ? lmax : (L < 1 ? 1 : L);
+            p = (int)ceil(pp) + 1;
+            p = p > FMM2D_MAX_P ? FMM2D_MAX_P : (p < 1 ? 1 : p);
+            int g = (int)floor((th - 0.35) / 0.1 + 0.5);
+            g = g < 0 ? 0 : (g > 4 ? 4 : g);
+            theta = thetas[g];
+        }
+    }
+    if (!net) rule(n, tol, lmax, L, p, theta);
+    out_i[0] = L;
+    out_i[1] = p;
+    out_i[2] = net ? 1 : 0;
+    out_i[3] = box[6] != 0.0 ? 1 : 0;
+    out_d[0] = theta;
+}
+
+}  // namespace
+
+// feat: device float [NFEAT]; blob (nullable): weights, then xin receives the
+// standardised input.  Scratch: c->scr.sel.
+hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, float *feat,
+                           const float *blob, float *xin, double **box_out) {
+    Scratch &s = c->scr;
+    const int nblk = (int)std::min<int64_t>((n + BT - 1) / BT, 1024);
+    const int64_t ncell = cell_off(FL + 1);
+    const size_t bytes = sizeof(double) * (5 * (size_t)nblk + 8) + sizeof(unsigned long long) * 9 * FL +
+                         sizeof(int32_t) * (size_t)ncell + 256;
+    FMM2D_TRY(s.sel.ensure(bytes));
+    char *base = s.sel.as<char>();
+    double *part = reinterpret_cast<double *>(base);
+    double *box = part + 5 * (size_t)nblk;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(box + 8);
+    int32_t *cnt = reinterpret_cast<int32_t *>(acc + 9 * FL);
+    hipLaunchKernelGGL(k_bbox_part, dim3(nblk), dim3(BT), 0, c->stream, x, y, n, part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BT), 0, c->stream, part, nblk, box);
+    const int64_t nfine = int64_t(1) << (2 * FL);
+    int32_t *fine = cnt + cell_off(FL);
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nfine, 256)), dim3(256), 0, c->stream, fine, nfine);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, c->stream, reinterpret_cast<int32_t *>(acc), 2 * 9 * FL);
+    hipLaunchKernelGGL(k_cells, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, x, y, n, box, fine);
+    for (int l = FL - 1; l >= 1; --l)
+        hipLaunchKernelGGL(k_pool, dim3(grid_for(int64_t(1) << (2 * l), 256)), dim3(256), 0, c->stream,
+                           cnt + cell_off(l + 1), l, cnt + cell_off(l));
+    hipLaunchKernelGGL(k_feat_hist, dim3(grid_for(ncell, BT * 8)), dim3(BT), 0, c->stream, cnt, n, acc);
+    hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(128), 0, c->stream, acc, n, tol, feat, blob, xin);
+    if (box_out) *box_out = box;
+    return hipGetLastError();
+}
+
+hipError_t select_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, const float *blob,
+                         int out[4], double *theta) {
+    Scratch &s = c->scr;
+    FMM2D_TRY(s.sel2.ensure(sizeof(float) * (2 * NFEAT + 8) + 64));
+    float *feat = s.sel2.as<float>();
+    float *xin = feat + NFEAT;
+    float *yout = xin + NFEAT;
+    int *oi = reinterpret_cast<int *>(yout + 4);
+    double *od = reinterpret_cast<double *>(s.sel2.as<char>() + sizeof(float) * (2 * NFEAT + 8) + 32);
+    double *box = nullptr;
+    FMM2D_TRY(features_device(c, x, y, n, tol, feat, blob, xin, &box));
+    if (blob) FMM2D_TRY(mlp_forward(c, blob + HDR, xin, 1, NFEAT, yout));
+    hipLaunchKernelGGL(k_select_final, dim3(1), dim3(64), 0, c->stream, yout, blob, n, tol, box, oi, od);
+    FMM2D_TRY(hipGetLastError());
+    FMM2D_TRY(hipMemcpyAsync(out, oi, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream));
+    FMM2D_TRY(hipMemcpyAsync(theta, od, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return hipStreamSynchronize(c->stream);
+}
+
+}  // namespace fmm2d

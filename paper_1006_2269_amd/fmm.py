@@ -115,6 +115,77 @@ class FMM2D:
                                                 ctypes.c_void_p(cnt.ctypes.data)))
         return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(_capi.PHASES)}
 
+    # -- parameter selection ----------------------------------------------
+    def features(self, x: torch.Tensor, y: torch.Tensor, tol: float, out: torch.Tensor | None = None):
+        _require(x, torch.float64, self.device, "x")
+        _require(y, torch.float64, self.device, "y")
+        if out is None:
+            out = torch.empty(_capi.NFEAT, dtype=torch.float32, device=self.device)
+        _require(out, torch.float32, self.device, "out")
+        if out.numel() < _capi.NFEAT:
+            raise ValueError("out holds fewer than %d floats" % _capi.NFEAT)
+        self._check(self._lib.fmm2d_features(self._h, _ptr(x), _ptr(y), x.numel(), float(tol), _ptr(out)))
+        return out
+
+    def select(self, x: torch.Tensor, y: torch.Tensor, tol: float, weights: torch.Tensor | None = None):
+        """(levels, p, theta, from_network); weights is the device blob of a trained selector."""
+        _require(x, torch.float64, self.device, "x")
+        _require(y, torch.float64, self.device, "y")
+        wp = None
+        if weights is not None:
+            _require(weights, torch.float32, self.device, "weights")
+            need = _capi.SELECT_HEADER + self._lib.fmm2d_mlp_nparams(_capi.NFEAT)
+            if weights.numel() != need:
+                raise ValueError("weights must hold %d floats" % need)
+            wp = _ptr(weights)
+        L, p, net = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        th = ctypes.c_double()
+        self._check(self._lib.fmm2d_select(self._h, _ptr(x), _ptr(y), x.numel(), float(tol), wp, ctypes.byref(L),
+                                           ctypes.byref(p), ctypes.byref(th), ctypes.byref(net)))
+        return L.value, p.value, th.value, bool(net.value)
+
+    def mlp_nparams(self, d_in: int) -> int:
+        return int(self._lib.fmm2d_mlp_nparams(int(d_in)))
+
+    def mlp_forward(self, params: torch.Tensor, X: torch.Tensor, out: torch.Tensor | None = None):
+        _require(params, torch.float32, self.device, "params")
+        _require(X, torch.float32, self.device, "X")
+        batch, d_in = X.shape
+        if params.numel() != self.mlp_nparams(d_in):
+            raise ValueError("params must hold %d floats" % self.mlp_nparams(d_in))
+        if out is None:
+            out = torch.empty((batch, 3), dtype=torch.float32, device=self.device)
+        _require(out, torch.float32, self.device, "out")
+        self._check(self._lib.fmm2d_mlp_forward(self._h, _ptr(params), _ptr(X), batch, d_in, _ptr(out)))
+        return out
+
+    def mlp_grad(self, params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, grad: torch.Tensor | None = None,
+                 loss: torch.Tensor | None = None):
+        _require(params, torch.float32, self.device, "params")
+        _require(X, torch.float32, self.device, "X")
+        _require(Y, torch.float32, self.device, "Y")
+        batch, d_in = X.shape
+        if params.numel() != self.mlp_nparams(d_in) or tuple(Y.shape) != (batch, 3):
+            raise ValueError("params or Y has the wrong size")
+        if grad is None:
+            grad = torch.empty_like(params)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _require(grad, torch.float32, self.device, "grad")
+        _require(loss, torch.float32, self.device, "loss")
+        self._check(self._lib.fmm2d_mlp_grad(self._h, _ptr(params), _ptr(X), _ptr(Y), batch, d_in, _ptr(grad),
+                                             _ptr(loss)))
+        return grad, loss
+
+    def mlp_adam(self, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor, step: int,
+                 lr: float):
+        for t, nm in ((params, "params"), (m, "m"), (v, "v"), (grad, "grad")):
+            _require(t, torch.float32, self.device, nm)
+            if t.numel() != params.numel():
+                raise ValueError("%s differs in size from params" % nm)
+        self._check(self._lib.fmm2d_mlp_adam(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(),
+                                             int(step), float(lr)))
+
     # -- introspection ------------------------------------------------------
     def tree_info(self):
         n, nb = ctypes.c_int64(), ctypes.c_int64()

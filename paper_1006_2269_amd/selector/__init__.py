@@ -1,0 +1,28 @@
+"""The learned parameter selector: its shipped weights and the scripts that
+made them (run table on the GPU, training with the library's own network
+kernels, held-out gain measurement)."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS_PATH = os.path.join(HERE, "weights.f32")
+NFEAT = 92
+HEADER = 194
+THETAS = (0.35, 0.45, 0.55, 0.65, 0.75)
+
+
+def load_weights(path: str = WEIGHTS_PATH):
+    """The weight blob (float32, fmm2d_select layout) or None if absent."""
+    if not os.path.exists(path):
+        return None
+    return np.fromfile(path, dtype="<f4")
+
+
+def weights_tensor(device, path: str = WEIGHTS_PATH):
+    import torch
+
+    b = load_weights(path)
+    return None if b is None else torch.from_numpy(b.copy()).to(device)

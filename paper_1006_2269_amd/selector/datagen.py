@@ -1,0 +1,119 @@
+"""Run table for training the parameter selector (needs the GPU).
+
+For each layout (``workloads.selector_layout``): its density features, the
+binary64 judge at 1000 sampled targets, and for every level count L in
+{L0 - 1, ..., L0 + 2} (L0 = round(log4(N / 16))) and theta in
+{0.35, ..., 0.75} the GPU times of build_tree and connectivity, then for
+p = 4, 5, ... the time of evaluate (mode fp32_acc64) and the normwise error
+against the judge, until the error drops below 5e-8 or stops improving (the
+FP32 near field sets a floor).
+
+    python -m paper_1006_2269_amd.selector.datagen --first 50000 --count 400 --out gpurun_out/runs.npz
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import sys
+import time
+
+import numpy as np
+
+THETAS = (0.35, 0.45, 0.55, 0.65, 0.75)
+P_MIN, P_MAX = 4, 30
+E_STOP = 5e-8      # below every tolerance the selector is trained for
+PLATEAU = 3        # stop after this many orders without a 10% gain
+MODE = "fp32_acc64"
+
+
+def L0_of(n: int) -> int:
+    return int(math.floor(math.log(max(n / 16.0, 1.0)) / math.log(4.0) + 0.5))
+
+
+def candidate_levels(n: int):
+    L0 = L0_of(n)
+    return [L for L in range(L0 - 1, L0 + 3) if 1 <= L <= 13 and 4 ** L <= n]
+
+
+def phase_ms(f, names):
+    t = f.timings()
+    return sum(t[k][0] for k in names)
+
+
+def run_layout(f, ps, torch, samples=1000):
+    from paper_1006_2269_amd import workloads as W
+    from paper_1006_2269_amd.fmm import FMM2DError
+
+    dev = f.device
+    x = torch.from_numpy(ps.x).to(dev)
+    y = torch.from_numpy(ps.y).to(dev)
+    q = torch.from_numpy(ps.q).to(dev)
+    tg = torch.from_numpy(W.sample_targets(ps.n, samples, seed=4242)).to(dev)
+    exact = f.direct(x, y, q, tg)
+    scale = float(exact.abs().max())
+    feat = f.features(x, y, 1e-6).cpu().numpy()
+    out = torch.empty_like(q)
+    rows = []
+    for L in candidate_levels(ps.n):
+        f.timing(True)
+        f.build_tree(x, y, L)
+        t_tree = phase_ms(f, ["tree"])
+        for th in THETAS:
+            f.timing(True)
+            try:
+                f.connectivity(th)
+            except FMM2DError:
+                continue  # a level's lists exceed the int32 entry limit
+            t_lists = phase_ms(f, ["lists"])
+            best, stale = math.inf, 0
+            for p in range(P_MIN, P_MAX + 1):
+                f.evaluate(q, p, MODE, out=out)   # warm (allocations)
+                f.timing(True)
+                f.evaluate(q, p, MODE, out=out)
+                t_eval = phase_ms(f, ["upward", "m2l", "l2l", "leaf", "other"])
+                e = float((out[tg] - exact).abs().max()) / scale
+                rows.append((L, th, p, t_tree, t_lists, t_eval, e))
+                stale = stale + 1 if e > 0.9 * best else 0
+                best = min(best, e)
+                if e <= E_STOP or stale >= PLATEAU:
+                    break  # below the tolerances of interest, or at the FP32 error floor
+    f.timing(False)
+    return feat, rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--first", type=int, default=50000)
+    ap.add_argument("--count", type=int, default=400)
+    ap.add_argument("--lo", type=float, default=4.0)
+    ap.add_argument("--hi", type=float, default=6.0)
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    import torch
+
+    from paper_1006_2269_amd import workloads as W
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    f = FMM2D(0)
+    feats, ns, table = [], [], []
+    t0 = time.time()
+    for i in range(args.count):
+        seed = args.first + i
+        ps = W.selector_layout(seed, args.lo, args.hi)
+        feat, rows = run_layout(f, ps, torch)
+        feats.append(feat)
+        ns.append(ps.n)
+        table.extend((i,) + r for r in rows)
+        print("[datagen] layout %d seed %d n=%d runs=%d  %.0f s" % (i, seed, ps.n, len(rows), time.time() - t0),
+              flush=True)
+        if (i + 1) % 25 == 0 or i + 1 == args.count:
+            np.savez(args.out, feats=np.array(feats, dtype=np.float32), n=np.array(ns, dtype=np.int64),
+                     seeds=np.arange(args.first, args.first + i + 1), runs=np.array(table, dtype=np.float64),
+                     columns=np.array(["layout", "L", "theta", "p", "t_tree_ms", "t_lists_ms", "t_eval_ms",
+                                       "e_inf"]))
+    f.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

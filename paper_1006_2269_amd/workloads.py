@@ -157,6 +157,25 @@ def random_mixture(n: int, seed: int) -> PointSet:
     return PointSet("random_mixture", x, y, _charges_uniform(g, n))
 
 
+def selector_layout(seed: int, log10_lo: float = 4.0, log10_hi: float = 6.3) -> PointSet:
+    """Layouts for training and testing the parameter selector: N =
+    round(10^U[lo, hi]), a random_mixture of 1-8 Gaussian clusters, and with
+    probability 1/2 a uniform background holding a U[0.2, 0.8] share of the
+    points (the benchmark sets mix clusters with a uniform background)."""
+    g = rng(2 * seed + 1)
+    n = int(round(10.0 ** g.uniform(log10_lo, log10_hi)))
+    share = g.uniform(0.2, 0.8) if g.random() < 0.5 else 0.0
+    nu = int(round(share * n))
+    ps = random_mixture(n - nu, seed) if n - nu > 0 else None
+    if nu == 0:
+        return PointSet("selector_layout", ps.x, ps.y, ps.q)
+    xu, yu = _uniform_square(g, nu)
+    x = np.concatenate([ps.x, xu]) if ps is not None else xu
+    y = np.concatenate([ps.y, yu]) if ps is not None else yu
+    x, y = _shuffle(g, x, y)
+    return PointSet("selector_layout", x, y, _charges_uniform(g, n))
+
+
 def unit_disc(n: int, seed: int, radial_inverse: bool = False) -> PointSet:
     """Unit-disc layouts of the error-vs-p experiment: uniform density, or
     radial density proportional to 1/r (radius uniform in [0,1]).  Total
