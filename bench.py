@@ -3,20 +3,24 @@
 
 Workload (default): the 1M-point mixed set -- 500,000 uniform points in
 [0,1]^2 plus 4 x 125,000 Gaussian points (sigma 0.1, 0.03, 0.01, 0.003),
-charges U[-1,1] -- on an 8-level tree with theta = 1/2, tolerance 1e-6.
+charges U[-1,1] -- at tolerance 1e-6; the plain form uses 8 levels and
+theta = 1/2.
 
-A step is one pass of the whole hot path: tree, lists and evaluation of all
-potentials, with inputs already in device memory.  Two forms are timed:
+A step is one pass of the whole hot path with inputs already in device
+memory.  Two forms are timed:
 
-* plain FP64 (``fp64``): p is the least order whose error passes the judge;
-* reduced precision (``fp32_acc64``): FP32 near field and FP32 M2L products
-  with binary64 power scaling and accumulation; its order comes from the
-  parameter selector and must pass the judge.
+* learned (``value``): parameter selection by the trained selector (its
+  density features and network run on the GPU inside the step), then tree,
+  lists and evaluation in mode ``fp32_acc64`` (FP32 near field and FP32 M2L
+  products, binary64 power scaling and accumulation);
+* plain FP64 (``config.fp64_points_per_s``): 8 levels, theta = 1/2, and the
+  least p whose error passes the judge.
 
 The judge is the binary64 direct sum (compensated) at 1000 seeded targets; a
 form counts only when its normwise relative error there is <= the tolerance.
-``value`` is the reduced-precision form's points/s.  One JSON line goes to
-stdout; phase timings and list statistics go to stderr.
+If the learned choice misses the judge, the reduced-precision form falls
+back to the judge-verified order at 8 levels (and says so in ``config``).
+One JSON line goes to stdout; phase timings and list statistics to stderr.
 """
 from __future__ import annotations
 
@@ -126,15 +130,60 @@ def main():
         return dt, tm, rel_err(out)
 
     results = {}
-    forms = [("fp32_acc64", "reduced")] + ([("fp64", "plain")] if args.fp64 else [])
+
+    # -- learned form: select + tree + lists + evaluate per step ------------
+    from paper_1006_2269_amd import selector
+
+    weights = selector.weights_tensor(dev)
+    learned = None
+    if weights is not None:
+        def step_learned():
+            Ls, ps_, th, net = f.select(x, y, tol, weights)
+            f.build_tree(x, y, Ls)
+            f.connectivity(th)
+            f.evaluate(q, ps_, "fp32_acc64", out=out)
+            return Ls, ps_, th, net
+
+        for _ in range(args.warmup):
+            cfg = step_learned()
+        torch.cuda.synchronize()
+        f.timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cfg = step_learned()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        tm = f.timings()
+        f.timing(False)
+        e = rel_err(out)
+        Ls, ps_, th, net = cfg
+        log("[bench] learned: levels=%d p=%d theta=%.2f (network=%s)  %.2f ms/step  %.3e pts/s  e_inf=%.2e"
+            % (Ls, ps_, th, net, dt * 1e3, n / dt, e))
+        for ph, (ms, cnt) in tm.items():
+            if cnt:
+                log("   %-7s %9.3f ms/step  (%d intervals)" % (ph, ms / args.steps, cnt))
+        learned = {"levels": Ls, "p": ps_, "theta": th, "network": net, "s_per_step": dt, "points_per_s": n / dt,
+                   "e_inf": e, "phases": tm}
+        if e <= tol:
+            results["fp32_acc64"] = dict(learned, selector="learned")
+        else:
+            log("[bench] the learned choice misses the judge (%.2e > %.1e)" % (e, tol))
+    else:
+        log("[bench] no trained selector weights at %s" % selector.WEIGHTS_PATH)
+
+    forms = ([] if "fp32_acc64" in results else [("fp32_acc64", "reduced")]) + \
+        ([("fp64", "plain")] if args.fp64 else [])
     for mode, label in forms:
+        f.build_tree(x, y, L)
+        f.connectivity(theta)
         found = search_p(mode)
         if found is None:
             log("[bench] %s: no p <= 40 passes the judge" % mode)
             continue
         p, _ = found
         dt, tm, e = timed(p, mode)
-        results[mode] = {"p": p, "s_per_step": dt, "points_per_s": n / dt, "e_inf": e, "phases": tm}
+        results[mode] = {"levels": L, "theta": theta, "p": p, "s_per_step": dt, "points_per_s": n / dt, "e_inf": e,
+                         "phases": tm, "selector": "judge-verified order"}
         log("[bench] %s p=%d  %.2f ms/step  %.3e pts/s  e_inf=%.2e" % (mode, p, dt * 1e3, n / dt, e))
         for ph, (ms, cnt) in tm.items():
             if cnt:
@@ -145,10 +194,13 @@ def main():
     roof = None
     if main_form:
         p = main_form["p"]
+        Lm = main_form["levels"]
+        f.build_tree(x, y, Lm)
+        f.connectivity(main_form["theta"])
         ph = main_form["phases"]
         leaf_ms = ph["leaf"][0] / max(ph["leaf"][1], 1)          # one launch per evaluation
         m2l_ms = ph["m2l"][0] / args.steps                       # all levels of one evaluation
-        sptr, sidx, _, _ = f.lists(L)
+        sptr, sidx, _, _ = f.lists(Lm)
         st = f.leaf_start().cpu().numpy().astype(np.int64)
         cnt = np.diff(st)
         sp = sptr.cpu().numpy().astype(np.int64)
@@ -156,7 +208,7 @@ def main():
         src_per_leaf = np.add.reduceat(cnt[si], sp[:-1]) if si.size else np.zeros_like(cnt)
         src_per_leaf[np.diff(sp) == 0] = 0
         pairs = float((cnt * src_per_leaf).sum())
-        weak_pairs = float(sum(f.list_sizes(l)[1] for l in range(L + 1)))
+        weak_pairs = float(sum(f.list_sizes(l)[1] for l in range(Lm + 1)))
         flop_pair = 8.0   # 2 sub, mul, fma (2), log2, fma (2) per FP32 pair interaction
         leaf_flops = pairs * flop_pair + n * (p + 1) * 8.0
         m2l_flops = weak_pairs * 4.0 * (p + 1) ** 2               # useful product flops per weak pair
@@ -180,17 +232,19 @@ def main():
         import oracle
 
         cps = W.WORKLOADS[args.workload](scale=args.cpu_scale)
-        cl = max(1, int(round(math.log(cps.n / (n / 4 ** L), 4))))
+        Lc = main_form["levels"] if main_form else L
+        thc = main_form["theta"] if main_form else theta
+        cl = max(1, int(round(math.log(cps.n / (n / 4 ** Lc), 4))))   # same points per leaf
         p = main_form["p"] if main_form else 12
         t0 = time.perf_counter()
         tr = oracle.tree(cps.x, cps.y, cl)
-        ls = oracle.lists(tr, theta)
+        ls = oracle.lists(tr, thc)
         oracle.fmm_eval(cps.x, cps.y, cps.q, tr, ls, p)
         dt = time.perf_counter() - t0
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cpu = {"value": round(cps.n / dt, 1), "unit": "target points/s", "cores": threads, "kind": "oracle",
                "sample": "%s at size factor %g (%d points, %d levels, p=%d, theta=%.2f): tree + lists + FP64 FMM"
-                         % (args.workload, args.cpu_scale, cps.n, cl, p, theta)}
+                         % (args.workload, args.cpu_scale, cps.n, cl, p, thc)}
         log("[bench] cpu oracle: %.1f s for %d points" % (dt, cps.n))
 
     if main_form is None:
@@ -209,8 +263,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "%s (n=%d)" % (args.workload, n), "levels": L, "theta": theta, "tol": tol,
-                   "p": main_form["p"], "mode": "fp32_acc64", "selector": "judge-verified order",
+        "config": {"workload": "%s (n=%d)" % (args.workload, n), "levels": main_form["levels"],
+                   "theta": main_form["theta"], "tol": tol, "p": main_form["p"], "mode": "fp32_acc64",
+                   "selector": main_form["selector"],
+                   "learned_choice": None if learned is None else
+                   {k: learned[k] for k in ("levels", "p", "theta", "network", "e_inf")},
                    "e_inf": main_form["e_inf"], "judge_samples": args.samples,
                    "fp64_points_per_s": round(results["fp64"]["points_per_s"], 1) if "fp64" in results else None,
                    "fp64_p": results["fp64"]["p"] if "fp64" in results else None},

@@ -156,7 +156,10 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
     if (t.L < 0) return fail(c, FMM2D_ESTATE, "connectivity: no tree (call fmm2d_build_tree first)");
     DeviceGuard g(c->device);
     const int64_t nbox = level_offset(t.L + 1);
-    int64_t cap_s = 32 * nbox + 64, cap_w = 96 * nbox + 64;
+    // start from the pool sizes that sufficed for the previous call (repeated
+    // calls on similar point sets then build the lists in one pass)
+    int64_t cap_s = std::max<int64_t>(32 * nbox + 64, c->cap_hint_s);
+    int64_t cap_w = std::max<int64_t>(96 * nbox + 64, c->cap_hint_w);
     const int64_t pool_max = int64_t(1) << 34;  // entries per pool, all levels together
     for (int attempt = 0; attempt < 16; ++attempt) {
         int overflow = 0;
@@ -173,12 +176,14 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
         if (overflow == 0) {
             {
                 PhaseScope ps(c, PH_LISTS);
-                e = near_records(c);
-                if (e == hipSuccess) e = build_schedules(c);
+                t.nrec_valid = true;  // written by the finest level's fill pass
+                e = build_schedules(c);
             }
             if (e != hipSuccess) return hip_fail(c, e, "connectivity");
             t.has_lists = true;
             t.theta = theta;
+            c->cap_hint_s = cap_s;
+            c->cap_hint_w = cap_w;
             return FMM2D_OK;
         }
         if (overflow == 2) {

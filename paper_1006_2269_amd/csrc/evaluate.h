@@ -14,8 +14,6 @@ hipError_t m2l_level(fmm2d_ctx *c, int l, int p, int mode);
 // L2P plus the near field at the leaves in precision `mode`; writes the
 // leaf-ordered potentials to ev.phi_leaf (near.hip).
 hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode);
-// per-entry records of the finest strong lists, used by leaf_pass (near.hip)
-hipError_t near_records(fmm2d_ctx *c);
 // list segments for the M2L and near-field kernels (sched.hip)
 hipError_t build_schedules(fmm2d_ctx *c);
 

@@ -138,6 +138,7 @@ struct Scratch {
 struct fmm2d_ctx {
     int device = 0;
     int64_t list_limit = 2147483647LL;  // entries per level and list (FMM2D_LIST_LIMIT lowers it)
+    int64_t cap_hint_s = 0, cap_hint_w = 0;  // list pool sizes that sufficed last time
     hipStream_t stream = nullptr;
     std::string err;
     fmm2d::TreeState tree;
@@ -149,7 +150,6 @@ struct fmm2d_ctx {
 namespace fmm2d {
 
 // ---- launchers (each returns the launch's hipError_t) ---------------------
-// sort.hip
 // sort.hip: stable sort of both coordinates by (value, index).  sort_prepare
 // validates (finite, |v| <= 2^500) and touches scratch memory only;
 // sort_finish completes the sort of the keys sort_prepare left.
@@ -158,6 +158,8 @@ hipError_t sort_finish(fmm2d_ctx *c, int64_t n, double *xs, double *ys, int32_t 
                        int32_t *xrank, int32_t *yrank);
 // scan.hip: exclusive scan of int32 in[n] into out[n+1] (out[n] = total)
 hipError_t scan_exclusive(fmm2d_ctx *c, const int32_t *in, int64_t n, int32_t *out);
+// the same for k (1 or 2) arrays of one length, in the same launches
+hipError_t scan_exclusive_n(fmm2d_ctx *c, int k, const int32_t *const *in, int64_t n, int32_t *const *out);
 // select.hip: density features and the parameter decision (host outputs)
 hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, float *feat,
                            const float *blob, float *xin, double **box_out);
@@ -169,8 +171,6 @@ hipError_t mlp_forward(fmm2d_ctx *c, const float *P, const float *X, int64_t bat
 hipError_t mlp_grad(fmm2d_ctx *c, const float *P, const float *X, const float *Y, int64_t batch, int d_in,
                     float *grad, float *loss);
 hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, int64_t np, int step, float lr);
-// the same for k (1 or 2) arrays of one length, in the same launches
-hipError_t scan_exclusive_n(fmm2d_ctx *c, int k, const int32_t *const *in, int64_t n, int32_t *const *out);
 // tree.hip
 hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y);
 // lists.hip

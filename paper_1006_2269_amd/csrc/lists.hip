@@ -11,11 +11,11 @@
 // the host reads the offsets (and an overflow flag) at the end.
 //
 // Row pointers are int32.  A level's candidates number 16 |S_{l-1}| (four
-// children of each of the four children's parents' strong boxes).  The host
-// carries an upper bound of |S_{l-1}| (16^(l-1) until a level's exact total
-// has been read) and reads the exact total back only when 16 times the bound
-// exceeds the entry limit; it refuses a level whose candidate count could
-// exceed the limit before launching it, so no int32 prefix sum can wrap.
+// children of each of the four children's parents' strong boxes), and each
+// becomes one entry of S or W.  After each level a one-thread kernel checks
+// the next level's candidate count against the entry limit and the free pool
+// space and raises a flag that stops all later levels, so no int32 prefix
+// sum can wrap; the host reads the flag with the pool offsets at the end.
 #include "devutil.h"
 #include "internal.h"
 
@@ -41,7 +41,11 @@ __device__ inline bool theta_separated(double theta, double4 gb, double4 gc) {
     return lhs <= rhs && rhs > 0.0;
 }
 
-__global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool, int64_t *pool_state, int L) {
+// Level 0: S_0(root) = {root}, W_0(root) empty; for a one-level tree
+// (L = 0) also the near-field record of that single strong entry, written
+// as the finest fill pass writes the others.
+__global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool, int64_t *pool_state, int L,
+                             const int32_t *stL, const double4 *geom0, int2 *recj, float4 *recd) {
     sptr0[0] = 0;
     sptr0[1] = 1;
     wptr0[0] = 0;
@@ -49,6 +53,13 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool,
     sidx_pool[0] = 0;
     for (int k = 0; k < 2 * L + 5; ++k) pool_state[k] = 0;
     pool_state[1] = 1;  // S offset of level 1
+    if (L == 0) {
+        const double4 g = geom0[0];
+        const float dxc = (float)(g.x - g.x), dyc = (float)(g.y - g.y);
+        const float mag = fabsf(dxc) + fabsf(dyc) + (float)g.z + (float)g.z;
+        recj[0] = make_int2(stL[0], stL[1]);
+        recd[0] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+    }
 }
 
 // First word of box b's decision bits: candidates of b are preceded by
@@ -72,7 +83,9 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
                                                         uint64_t *__restrict__ bits,
                                                         const int32_t *__restrict__ sptr_cur,
                                                         const int32_t *__restrict__ wptr_cur,
-                                                        int32_t *__restrict__ sidx_out, int32_t *__restrict__ widx_out) {
+                                                        int32_t *__restrict__ sidx_out, int32_t *__restrict__ widx_out,
+                                                        const int32_t *__restrict__ stL, int2 *__restrict__ recj,
+                                                        float4 *__restrict__ recd) {
     const int64_t b = (int64_t)blockIdx.x * LW + threadIdx.x / 64;
     const uint32_t lane = lane_id();
     if (b >= nb) return;
@@ -86,8 +99,12 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
     const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
     const int32_t ncand = 4 * (s1 - s0);
     uint64_t *bw = bits + bits_base(b, s0, s1);
+    // finest level, fill pass: also the near-field record of each strong
+    // entry (source leaf's point range; FP32 centre offset c_b - c_c and the
+    // coincidence threshold (2^-20 of the magnitudes)^2 for the FP32 path)
+    const bool records = FILL && l == L && recj != nullptr;
     double4 gb;
-    if (!FILL) gb = geomL[b];
+    if (!FILL || records) gb = geomL[b];
     int32_t cs = 0, cw = 0;
     int32_t *so = nullptr, *wo = nullptr;
     if (FILL) {
@@ -114,8 +131,20 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
         const uint64_t okm = __ballot(ok);
         const uint64_t ms = okm & ~mw;
         if (FILL && ok) {
-            if ((mw >> lane) & 1) wo[cw + (int32_t)popc_below(mw)] = cbox;
-            else so[cs + (int32_t)popc_below(ms)] = cbox;
+            if ((mw >> lane) & 1) {
+                wo[cw + (int32_t)popc_below(mw)] = cbox;
+            } else {
+                const int32_t pos = cs + (int32_t)popc_below(ms);
+                so[pos] = cbox;
+                if (records) {
+                    const int32_t t = sptr_cur[b] + pos;
+                    const double4 gc = geomL[cbox];
+                    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
+                    const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
+                    recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
+                    recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+                }
+            }
         }
         cw += (int32_t)__popcll(mw);
         cs += (int32_t)__popcll(ms);
@@ -126,14 +155,28 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
     }
 }
 
+// Pool offsets of level l + 1, and the checks that guard the next level:
+// flag 1 when a pool is too small (the host retries with larger pools),
+// flag 2 when level l + 1's candidates, 16 |S_l| (each becomes one entry of
+// S or W), exceed the entry limit.  A flagged level is not examined, so no
+// int32 prefix sum can wrap and no decision bit lies beyond the buffer
+// (sized for cap_s + cap_w candidates).
 __global__ void k_lists_advance(int l, int L, int64_t nb, const int32_t *sptr_cur, const int32_t *wptr_cur,
-                                int64_t *pool_state, int64_t cap_s, int64_t cap_w) {
+                                int64_t *pool_state, int64_t cap_s, int64_t cap_w, int64_t limit) {
     if (pool_state[2 * L + 4]) return;
     const int64_t so = pool_state[l] + sptr_cur[nb];
     const int64_t wo = pool_state[(L + 2) + l] + wptr_cur[nb];
     pool_state[l + 1] = so;
     pool_state[(L + 2) + l + 1] = wo;
-    if (so > cap_s || wo > cap_w) pool_state[2 * L + 4] = 1;
+    if (so > cap_s || wo > cap_w) {
+        pool_state[2 * L + 4] = 1;
+        return;
+    }
+    if (l < L) {
+        const int64_t cand = 16 * (int64_t)sptr_cur[nb];
+        if (cand > limit) pool_state[2 * L + 4] = 2;
+        else if (cand > (cap_s - so) + (cap_w - wo)) pool_state[2 * L + 4] = 1;
+    }
 }
 
 }  // namespace
@@ -153,51 +196,46 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     FMM2D_TRY(t.pool_state.ensure(sizeof(int64_t) * (2 * L + 5)));
     int32_t *sptr = t.sptr.as<int32_t>(), *wptr = t.wptr.as<int32_t>();
     int64_t *ps = t.pool_state.as<int64_t>();
-    hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L);
     const double4 *geom = t.geom.as<double4>();
-    // Upper bound of the entries of S at level l-1 (exact at level 0: the
-    // root).  |S_l| <= 16 |S_{l-1}|, so the bound grows by 16 per level; only
-    // when it reaches the limit is the exact total read back (one copy and a
-    // synchronisation).
-    int64_t s_prev = 1;
+    // Level 1 has 16 candidates (the root's children, four per box); later
+    // levels are guarded on the device by k_lists_advance, so the host never
+    // waits inside the level loop.
+    if (L >= 1 && 16 > limit) {
+        *overflow = 2;
+        return hipSuccess;
+    }
+    FMM2D_TRY(t.bits.ensure(sizeof(uint64_t) * (size_t)((cap_s + cap_w) / 64 + maxnb + 2)));
+    uint64_t *bits = t.bits.as<uint64_t>();
+    // near-field records of the finest level's strong entries (<= cap_s)
+    FMM2D_TRY(t.nrec_j.ensure(sizeof(int2) * cap_s));
+    FMM2D_TRY(t.nrec_d.ensure(sizeof(float4) * cap_s));
+    const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
+    hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L, stL,
+                       geom, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
     for (int l = 1; l <= L; ++l) {
         const int64_t nb = int64_t(1) << (2 * l);
         int32_t *sp_prev = sptr + ptr_offset(l - 1), *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
-        if (16 * s_prev > limit) {
-            int32_t tot = 0;
-            FMM2D_TRY(hipMemcpyAsync(&tot, sp_prev + (nb >> 2), sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-            FMM2D_TRY(hipStreamSynchronize(c->stream));
-            s_prev = tot;
-            if (16 * s_prev > limit) {
-                *overflow = 2;
-                return hipSuccess;
-            }
-        }
         const double4 *gL = geom + level_offset(l);
         const unsigned grid = grid_for(nb, LW);
-        // decision words: at most 16 s_prev candidates / 64 + one spare per box
-        FMM2D_TRY(t.bits.ensure(sizeof(uint64_t) * (size_t)((16 * s_prev) / 64 + nb + 1)));
-        uint64_t *bits = t.bits.as<uint64_t>();
         hipLaunchKernelGGL(k_lists_level<false>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
                            t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), bits, sp_cur, wp_cur,
-                           t.sidx.as<int32_t>(), t.widx.as<int32_t>());
+                           t.sidx.as<int32_t>(), t.widx.as<int32_t>(), stL, nullptr, nullptr);
         {
             const int32_t *ins[2] = {t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>()};
             int32_t *outs[2] = {sp_cur, wp_cur};
             FMM2D_TRY(scan_exclusive_n(c, 2, ins, nb, outs));
         }
-        s_prev *= 16;
         hipLaunchKernelGGL(k_lists_advance, dim3(1), dim3(1), 0, c->stream, l, L, nb, sp_cur, wp_cur, ps, cap_s,
-                           cap_w);
+                           cap_w, limit);
         hipLaunchKernelGGL(k_lists_level<true>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
                            t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), bits, sp_cur, wp_cur,
-                           t.sidx.as<int32_t>(), t.widx.as<int32_t>());
+                           t.sidx.as<int32_t>(), t.widx.as<int32_t>(), stL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
         FMM2D_TRY(hipGetLastError());
     }
     std::vector<int64_t> h(2 * L + 5);
     FMM2D_TRY(hipMemcpyAsync(h.data(), ps, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
     FMM2D_TRY(hipStreamSynchronize(c->stream));
-    *overflow = h[2 * L + 4] != 0 ? 1 : 0;
+    *overflow = (int)h[2 * L + 4];
     t.s_off.assign(h.begin(), h.begin() + (L + 2));
     t.w_off.assign(h.begin() + (L + 2), h.begin() + (2 * L + 4));
     return hipSuccess;

@@ -20,8 +20,11 @@
 // each lane then post-scales its output elements by T' and accumulates its
 // coefficient l.  A cross-lane reduction adds the box's total into B.
 //
-// Variants: the product in FP32 (f32 matrix instruction) or binary64 (f64
-// matrix instruction); accumulation of B in FP32 or binary64.
+// Variants: the product in FP32 (f32 matrix instruction), in three BF16
+// products (bf16 matrix instruction), or binary64 (f64 matrix instruction);
+// power tables and accumulation of B in FP32 or binary64.
+#include <type_traits>
+
 #include "evaluate.h"
 
 namespace fmm2d {
@@ -66,7 +69,49 @@ __device__ inline cd cpow_int(cd z, int n) {
     return r;
 }
 
-template <int NT, typename G, typename ACC>
+// complex arithmetic in the precision of the power tables
+template <typename T>
+struct cx {
+    T re, im;
+};
+template <typename T>
+__device__ inline cx<T> cxmul(cx<T> a, cx<T> b) {
+    return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ inline cx<T> cxpow(cx<T> z, int n) {
+    cx<T> r{(T)1, (T)0};
+    while (n) {
+        if (n & 1) r = cxmul(r, z);
+        z = cxmul(z, z);
+        n >>= 1;
+    }
+    return r;
+}
+
+// Two-way BF16 split of an FP32 value, x ~ hi + lo, each rounded to nearest
+// even (the usual rounding of the upper half of the FP32 bit pattern).
+typedef short v4s __attribute__((ext_vector_type(4)));
+__device__ inline short bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ inline float bf16_value(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+__device__ inline void bf16_split(float x, short &hi, short &lo) {
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_value(hi));
+}
+
+// Modes: G is the LDS / matrix-operand type, ACC the accumulation type, PT
+// the power-table type (binary64 unless the mode accumulates in FP32), and
+// BF3 replaces each FP32 product by three BF16 products of the split
+// operands (hi hi + hi lo + lo hi; the lo lo term, ~2^-16 relative, is
+// dropped), on the 16x16x16 BF16 matrix instruction: operand A lane i
+// supplies A[i % 16][4 (i / 16) + j], operand B lane i supplies
+// B[4 (i / 16) + j][i % 16], j = 0..3; the accumulator layout is that of
+// the 16x16x4 FP32 instruction.
+template <int NT, typename G, typename ACC, bool BF3>
 __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ geomL, const int32_t *__restrict__ wptr,
                                             const int32_t *__restrict__ widx, const cd *__restrict__ AL,
                                             const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
@@ -89,14 +134,34 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
     const int ks_n = (P1 + 3) / 4;
     const int KR = (P1 + LPP - 1) / LPP;  // LPP * KR == 4 * ks_n <= KP: every padded k is written
     const double4 gb = geomL[b];
-    G mreg[KSMAX][NT];
+    using PT = typename std::conditional<std::is_same<ACC, float>::value, float, double>::type;
+    G mreg[BF3 ? 1 : KSMAX][NT];
+    v4s mbh[BF3 ? NT : 1][NT], mbl[BF3 ? NT : 1][NT];
+    if constexpr (BF3) {
 #pragma unroll
-    for (int ks = 0; ks < KSMAX; ++ks)
+        for (int kb = 0; kb < NT; ++kb)
 #pragma unroll
-        for (int tl = 0; tl < NT; ++tl) {
-            const int k = 4 * ks + lane / 16, l = 16 * tl + lane % 16;
-            mreg[ks][tl] = (k < P1 && l < P1) ? (G)Mhat[l * 64 + k] : (G)0;
-        }
+            for (int tl = 0; tl < NT; ++tl) {
+                const int l = 16 * tl + lane % 16;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 16 * kb + 4 * (lane / 16) + j;
+                    const float m = (k < P1 && l < P1) ? (float)Mhat[l * 64 + k] : 0.0f;
+                    short h, lo;
+                    bf16_split(m, h, lo);
+                    mbh[kb][tl][j] = h;
+                    mbl[kb][tl][j] = lo;
+                }
+            }
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks)
+#pragma unroll
+            for (int tl = 0; tl < NT; ++tl) {
+                const int k = 4 * ks + lane / 16, l = 16 * tl + lane % 16;
+                mreg[ks][tl] = (k < P1 && l < P1) ? (G)Mhat[l * 64 + k] : (G)0;
+            }
+    }
     ACC accr[NT], acci[NT];
 #pragma unroll
     for (int tl = 0; tl < NT; ++tl) { accr[tl] = 0; acci[tl] = 0; }
@@ -149,27 +214,28 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
             // s_c / z0 with one division; the scaled division where |z0|^2 could underflow
             const cd rs = d2 > 0x1p-960 ? cd{z0.re * inv, -z0.im * inv} : cdiv(cd{gc.w, 0.0}, z0);
             const cd rt = cscale(rs, gb.w / gc.w);            // s_b / z0
-            cd ws = cpow_int(rs, k0), wt = cpow_int(rt, k0);
-            double sc2 = ldexp(1.0, k0);
+            const cx<PT> rsp{(PT)rs.re, (PT)rs.im}, rtp{(PT)rt.re, (PT)rt.im};
+            cx<PT> ws = cxpow(rsp, k0), wt = cxpow(rtp, k0);
+            PT sc2 = (PT)ldexp(1.0, k0);
 #pragma unroll
             for (int kk = 0; kk < KRMAX; ++kk) {
                 if (kk < KR) {
                     const int k = k0 + kk;
                     if (k < P1) {
-                        const cd u = cmul(a_cur[kk], ws);
+                        const cx<PT> u = cxmul(cx<PT>{(PT)a_cur[kk].re, (PT)a_cur[kk].im}, ws);
                         Ur[q][k] = (G)(u.re * sc2);
                         Ui[q][k] = (G)(u.im * sc2);
-                        Tr[q][k] = wt.re * sc2;
-                        Ti[q][k] = wt.im * sc2;
+                        Tr[q][k] = (double)(wt.re * sc2);
+                        Ti[q][k] = (double)(wt.im * sc2);
                     } else if (k < KP) {
                         Ur[q][k] = (G)0;
                         Ui[q][k] = (G)0;
                         Tr[q][k] = 0.0;
                         Ti[q][k] = 0.0;
                     }
-                    ws = cmul(ws, rs);
-                    wt = cmul(wt, rt);
-                    sc2 *= 2.0;
+                    ws = cxmul(ws, rsp);
+                    wt = cxmul(wt, rtp);
+                    sc2 *= (PT)2;
                 }
             }
             if (slot == 0) ext0 += a_cur[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im)));
@@ -195,9 +261,30 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
 #pragma unroll
             for (int tl = 0; tl < NT; ++tl) {
                 V d = {0, 0, 0, 0};
+                if constexpr (BF3) {
 #pragma unroll
-                for (int ks = 0; ks < KSMAX; ++ks)
-                    if (ks < ks_n) d = MF::run(urow[4 * ks + g], mreg[ks][tl], d);
+                    for (int kb = 0; kb < NT; ++kb) {
+                        if (16 * kb < P1) {
+                            v4s ah, al;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                // entries past the K steps of the FP32 path are not written
+                                const int k = 16 * kb + 4 * g + j;
+                                short h, lo;
+                                bf16_split(k < P1 ? (float)urow[k] : 0.0f, h, lo);
+                                ah[j] = h;
+                                al[j] = lo;
+                            }
+                            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, mbh[kb][tl], d, 0, 0, 0);
+                            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, mbl[kb][tl], d, 0, 0, 0);
+                            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, mbh[kb][tl], d, 0, 0, 0);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < KSMAX; ++ks)
+                        if (ks < ks_n) d = MF::run(urow[4 * ks + g], mreg[ks][tl], d);
+                }
                 const int l = 16 * tl + row;
                 if (l < P1) {
 #pragma unroll
@@ -230,6 +317,162 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
             const int l = 16 * tl + lane;
             if (l < P1) part[seg * P1 + l] = cd{(double)accr[tl] + (l == 0 ? ext0 : 0.0), (double)acci[tl]};
         }
+    }
+}
+
+// Orders with p + 1 <= 16: one lane per pair, 64 pairs per chunk.  Each lane
+// computes its pair's geometry, power table and pre-scaled row u' (stored in
+// LDS as two operand rows, real and imaginary part); the matrix instruction
+// multiplies the 128 rows by M^T block by block, each block's result
+// replacing its own rows in LDS; the lane then post-scales its pair's
+// outputs by T'_l and accumulates them in registers.  At the end of the
+// segment a transposing butterfly reduction (each stage halves the values a
+// lane carries) sums the 64 lanes' accumulators in a fixed order.
+template <typename G, typename ACC, bool BF3>
+__global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict__ geomL,
+                                               const int32_t *__restrict__ wptr, const int32_t *__restrict__ widx,
+                                               const cd *__restrict__ AL, const int2 *__restrict__ segtab,
+                                               const int32_t *__restrict__ nseg_ptr, cd *__restrict__ part,
+                                               const double *__restrict__ Mhat) {
+    using MF = Mfma<G>;
+    using V = typename MF::V;
+    using PT = typename std::conditional<std::is_same<ACC, float>::value, float, double>::type;
+    constexpr int KP = 17;  // padded row length
+    __shared__ G U[64][2][KP];
+    const int64_t seg = blockIdx.x;
+    if (seg >= *nseg_ptr) return;  // the block is one wavefront: uniform exit
+    const int lane = threadIdx.x;
+    const int2 se = segtab[seg];
+    const int64_t b = se.x;
+    const int32_t t0 = se.y;
+    const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
+    const int P1 = p + 1;
+    const int ks_n = (P1 + 3) / 4;
+    const int row = lane % 16, g = lane / 16;
+    const double4 gb = geomL[b];
+    G mreg[4];
+    v4s mbh, mbl;
+    if constexpr (BF3) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            const float m = (k < P1 && row < P1) ? (float)Mhat[row * 64 + k] : 0.0f;
+            short h, lo;
+            bf16_split(m, h, lo);
+            mbh[j] = h;
+            mbl[j] = lo;
+        }
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + g;
+            mreg[ks] = (k < P1 && row < P1) ? (G)Mhat[row * 64 + k] : (G)0;
+        }
+    }
+    ACC acc[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = (ACC)0;
+    ACC ext0 = (ACC)0;
+    for (int32_t t = t0; t < t1; t += 64) {
+        const int np = (t1 - t) < 64 ? (t1 - t) : 64;
+        const bool act = lane < np;
+        cx<PT> rtp{(PT)0, (PT)0};
+        if (act) {
+            const int32_t c = widx[t + lane];
+            const double4 gc = geomL[c];
+            const cd *Ac = AL + (int64_t)c * P1;
+            const cd z0{gc.x - gb.x, gc.y - gb.y};
+            const double d2 = z0.re * z0.re + z0.im * z0.im;  // > 0 for a weak pair
+            const double inv = gc.w / d2;
+            const cd rs = d2 > 0x1p-960 ? cd{z0.re * inv, -z0.im * inv} : cdiv(cd{gc.w, 0.0}, z0);
+            const cd rt = cscale(rs, gb.w / gc.w);
+            ext0 += (ACC)(Ac[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im))));
+            const cx<PT> rsp{(PT)rs.re, (PT)rs.im};
+            rtp = cx<PT>{(PT)rt.re, (PT)rt.im};
+            cx<PT> w{(PT)1, (PT)0};
+            PT sc = (PT)1;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < P1) {
+                    const cd a = Ac[k];
+                    const cx<PT> u = cxmul(cx<PT>{(PT)a.re, (PT)a.im}, w);
+                    U[lane][0][k] = (G)(u.re * sc);
+                    U[lane][1][k] = (G)(u.im * sc);
+                    w = cxmul(w, rsp);
+                    sc *= (PT)2;
+                } else {
+                    U[lane][0][k] = (G)0;  // K padding read by the products
+                    U[lane][1][k] = (G)0;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb) {
+            if (8 * rb >= np) break;
+            const int pa = 8 * rb + MF::pair_of_row(row);
+            const G *ur = U[pa][MF::part_of_row(row)];
+            V d = {0, 0, 0, 0};
+            if constexpr (BF3) {
+                v4s ah, al;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    short h, lo;
+                    bf16_split((float)ur[4 * g + j], h, lo);
+                    ah[j] = h;
+                    al[j] = lo;
+                }
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, mbh, d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, mbl, d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, mbh, d, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+                    if (ks < ks_n) d = MF::run(ur[4 * ks + g], mreg[ks], d);
+            }
+            // element r of lane group g is pair 8 rb + 2 g + r / 2, part r % 2,
+            // coefficient l = row: those rows of U belong to this block only
+#pragma unroll
+            for (int r = 0; r < 4; ++r) U[8 * rb + 2 * g + r / 2][r % 2][row] = (G)d[r];
+        }
+        __syncthreads();
+        if (act) {
+            cx<PT> tp{(PT)1, (PT)0};
+            PT sc = (PT)1;
+#pragma unroll
+            for (int l = 0; l < 16; ++l) {
+                if (l < P1) {
+                    const ACC wr = (ACC)U[lane][0][l], wi = (ACC)U[lane][1][l];
+                    const ACC tr = (ACC)(tp.re * sc), ti = (ACC)(tp.im * sc);
+                    acc[2 * l] += tr * wr - ti * wi;
+                    acc[2 * l + 1] += tr * wi + ti * wr;
+                    tp = cxmul(tp, rtp);
+                    sc *= (PT)2;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // transposing butterfly: after the stage with mask m a lane carries half
+    // as many values; at the end lane i holds the total of value i / 2
+#pragma unroll
+    for (int h = 16, m = 32; h >= 1; h >>= 1, m >>= 1) {
+        const bool hi = (lane & m) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const ACC send = hi ? acc[i] : acc[i + h];
+            const ACC keep = hi ? acc[i + h] : acc[i];
+            acc[i] = keep + __shfl_xor(send, m, 64);
+        }
+    }
+    acc[0] += __shfl_xor(acc[0], 1, 64);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ext0 += __shfl_xor(ext0, off, 64);
+    const int idx = lane >> 1, l = idx >> 1, comp = idx & 1;
+    if ((lane & 1) == 0 && l < P1) {
+        double v = (double)acc[0];
+        if (l == 0 && comp == 0) v += (double)ext0;
+        reinterpret_cast<double *>(part)[2 * (seg * P1 + l) + comp] = v;
     }
 }
 
@@ -275,12 +518,31 @@ hipError_t launch_m2l(fmm2d_ctx *c, int l, int p, int mode) {
     const int2 *tab = sc.table.as<int2>();
     const int32_t *nsp = sc.segoff.as<int32_t>() + nb;
     const dim3 grid((unsigned)sc.bound), block(64);
-    if (mode == FMM2D_MODE_FP64)
-        hipLaunchKernelGGL((k_m2l<NT, double, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp, part, Mh);
+    if (NT == 1) {
+        if (mode == FMM2D_MODE_FP64)
+            hipLaunchKernelGGL((k_m2l_lp<double, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab,
+                               nsp, part, Mh);
+        else if (mode == FMM2D_MODE_FP32_ACC64)
+            hipLaunchKernelGGL((k_m2l_lp<float, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab,
+                               nsp, part, Mh);
+        else if (mode == FMM2D_MODE_BF16X3)
+            hipLaunchKernelGGL((k_m2l_lp<float, float, true>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                               part, Mh);
+        else
+            hipLaunchKernelGGL((k_m2l_lp<float, float, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab,
+                               nsp, part, Mh);
+    } else if (mode == FMM2D_MODE_FP64)
+        hipLaunchKernelGGL((k_m2l<NT, double, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
     else if (mode == FMM2D_MODE_FP32_ACC64)
-        hipLaunchKernelGGL((k_m2l<NT, float, double>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp, part, Mh);
+        hipLaunchKernelGGL((k_m2l<NT, float, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
+    else if (mode == FMM2D_MODE_BF16X3)
+        hipLaunchKernelGGL((k_m2l<NT, float, float, true>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
     else
-        hipLaunchKernelGGL((k_m2l<NT, float, float>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp, part, Mh);
+        hipLaunchKernelGGL((k_m2l<NT, float, float, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
     FMM2D_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_m2l_reduce, dim3(grid_for(nb * (p + 1), 256)), dim3(256), 0, c->stream, p, nb,
                        sc.segoff.as<int32_t>(), part, BL);

@@ -24,30 +24,6 @@ namespace {
 constexpr double HALF_LN2_D = 0.34657359027997264;  // ln(2)/2
 constexpr int NWB = 4;                                // wavefronts per block
 
-// Per strong-list entry of the finest level: the source leaf's point range
-// and, for the FP32 path, the FP32 centre difference c_b - c_c and the
-// coincidence threshold.  Depends on the tree and lists only.
-__global__ void __launch_bounds__(256) k_near_records(int64_t nleaf, const int32_t *__restrict__ stL,
-                                                      const double4 *__restrict__ geomL,
-                                                      const int32_t *__restrict__ sptr,
-                                                      const int32_t *__restrict__ sidx, int2 *__restrict__ recj,
-                                                      float4 *__restrict__ recd) {
-    // one wavefront per leaf, lanes over its strong entries (coalesced)
-    const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    if (b >= nleaf) return;
-    const int lane = threadIdx.x % 64;
-    const double4 g = geomL[b];
-    const int32_t t1 = sptr[b + 1];
-    for (int32_t t = sptr[b] + lane; t < t1; t += 64) {
-        const int32_t c = sidx[t];
-        const double4 gc = geomL[c];
-        const float dxc = (float)(g.x - gc.x), dyc = (float)(g.y - gc.y);
-        const float mag = fabsf(dxc) + fabsf(dyc) + (float)g.z + (float)gc.z;
-        recj[t] = make_int2(stL[c], stL[c + 1]);
-        recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
-    }
-}
-
 // FP32 near field.  Pipelined: while step s is evaluated, the source points
 // of step s+1 and the records of step s+2 are in flight.  Requires the
 // largest leaf to fit in GL lanes.
@@ -375,24 +351,6 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf) {
 
 }  // namespace
 
-// Records of the finest-level strong entries (after the lists are built).
-hipError_t near_records(fmm2d_ctx *c) {
-    TreeState &t = c->tree;
-    const int L = t.L;
-    const int64_t nleaf = int64_t(1) << (2 * L);
-    const int64_t ns = t.s_off[L + 1] - t.s_off[L];
-    FMM2D_TRY(t.nrec_j.ensure(sizeof(int2) * (ns > 0 ? ns : 1)));
-    FMM2D_TRY(t.nrec_d.ensure(sizeof(float4) * (ns > 0 ? ns : 1)));
-    const int64_t offL = level_offset(L);
-    hipLaunchKernelGGL(k_near_records, dim3(grid_for(nleaf, 4)), dim3(256), 0, c->stream, nleaf,
-                       t.starts.as<int32_t>() + depth_offset(2 * L), t.geom.as<double4>() + offL,
-                       t.sptr.as<int32_t>() + ptr_offset(L), t.sidx.as<int32_t>() + t.s_off[L], t.nrec_j.as<int2>(),
-                       t.nrec_d.as<float4>());
-    FMM2D_TRY(hipGetLastError());
-    t.nrec_valid = true;
-    return hipSuccess;
-}
-
 // L2P plus the near field for every point; writes ev.phi_leaf (leaf order).
 hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode) {
     TreeState &t = c->tree;
@@ -401,7 +359,7 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode) {
     const int L = t.L;
     const int64_t nleaf = int64_t(1) << (2 * L);
     const int64_t maxleaf = (n + nleaf - 1) >> (2 * L);  // ceil(n / 4^L)
-    if (!t.nrec_valid) FMM2D_TRY(near_records(c));
+    if (!t.nrec_valid) return hipErrorInvalidValue;  // records come with the lists
     if (mode != FMM2D_MODE_FP64) {
         FMM2D_TRY(e.src.ensure(sizeof(float4) * n));
         hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.loc.as<float2>(),

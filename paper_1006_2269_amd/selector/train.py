@@ -1,0 +1,175 @@
+"""Training of the parameter selector on a run table (needs the GPU: the
+network's forward pass, gradient and Adam steps are the library's kernels).
+
+Samples.  For a layout of the run table and a tolerance TOL = 10^U[-7, -3]
+(several per layout, seeded), the label is the cheapest measured
+(L, theta, p) whose error meets TOL, the cost being the measured GPU time of
+build_tree + connectivity + evaluate.  The input is the layout's feature
+vector with its second entry set to log10 TOL.  Pairs for which no measured
+configuration meets TOL (below the FP32 error floor) are left out.
+
+Targets (L - L0, p, theta) with L0 = round(log4(N / 16)) and the inputs are
+standardised; mean and scale go into the weight blob's header together with
+the trained range of log10 N and log10 TOL.
+
+    python -m paper_1006_2269_amd.selector.train --runs a.npz b.npz --out weights.f32
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+
+import numpy as np
+
+NFEAT = 92
+HEADER = 194
+TOL_LO, TOL_HI = -7.0, -3.0
+
+
+def L0_of(n: int) -> int:
+    return int(math.floor(math.log(max(n / 16.0, 1.0)) / math.log(4.0) + 0.5))
+
+
+def load_runs(paths):
+    feats, ns, runs, off = [], [], [], 0
+    for p in paths:
+        d = np.load(p)
+        r = d["runs"].copy()
+        r[:, 0] += off
+        feats.append(d["feats"])
+        ns.append(d["n"])
+        runs.append(r)
+        off += d["n"].shape[0]
+    return np.concatenate(feats), np.concatenate(ns), np.concatenate(runs)
+
+
+def best_config(R, tol):
+    """Cheapest (cost_ms, L, theta, p) of one layout's runs meeting tol."""
+    best = None
+    keys = np.unique(R[:, 1:3], axis=0)
+    for L, th in keys:
+        S = R[(R[:, 1] == L) & (R[:, 2] == th)]
+        S = S[np.argsort(S[:, 3])]
+        ok = np.nonzero(S[:, 7] <= tol)[0]
+        if ok.size == 0:
+            continue
+        row = S[ok[0]]
+        cost = row[4] + row[5] + row[6]
+        if best is None or cost < best[0]:
+            best = (float(cost), int(L), float(th), int(row[3]))
+    return best
+
+
+def make_samples(feats, ns, runs, layouts, per_layout, seed):
+    rng = np.random.default_rng(seed)
+    X, Y = [], []
+    for i in layouts:
+        R = runs[runs[:, 0] == i]
+        if R.shape[0] == 0:
+            continue
+        for lt in rng.uniform(TOL_LO, TOL_HI, per_layout):
+            b = best_config(R, 10.0 ** lt)
+            if b is None:
+                continue
+            x = feats[i].astype(np.float64).copy()
+            x[1] = lt
+            X.append(x)
+            Y.append((b[1] - L0_of(int(ns[i])), b[3], b[2]))
+    return np.array(X), np.array(Y, dtype=np.float64)
+
+
+def init_params(d_in, seed):
+    rng = np.random.default_rng(seed)
+    dims = [d_in, 64, 64, 64, 3]
+    parts = []
+    for i in range(4):
+        fan_in, fan_out = dims[i], dims[i + 1]
+        parts.append(rng.normal(0.0, 1.0 / math.sqrt(fan_in), fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--runs", nargs="+", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--per-layout", type=int, default=32)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--val-frac", type=float, default=0.1)
+    ap.add_argument("--seed", type=int, default=7)
+    args = ap.parse_args()
+    import torch
+
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    feats, ns, runs = load_runs(args.runs)
+    nl = ns.shape[0]
+    order = np.random.default_rng(args.seed).permutation(nl)
+    nval = max(1, int(round(args.val_frac * nl)))
+    val_l, tr_l = order[:nval], order[nval:]
+    Xtr, Ytr = make_samples(feats, ns, runs, tr_l, args.per_layout, args.seed)
+    Xva, Yva = make_samples(feats, ns, runs, val_l, args.per_layout, args.seed + 1)
+    print("[train] layouts %d (val %d), samples %d (val %d)" % (nl, nval, Xtr.shape[0], Xva.shape[0]), flush=True)
+
+    xm = Xtr.mean(axis=0)
+    xs = Xtr.std(axis=0)
+    xscale = np.where(xs > 1e-6, 1.0 / np.maximum(xs, 1e-12), 1.0)
+    ym, ysd = Ytr.mean(axis=0), Ytr.std(axis=0)
+    ysd = np.where(ysd > 1e-6, ysd, 1.0)
+    norm_x = lambda X: ((X - xm) * xscale).astype(np.float32)
+    norm_y = lambda Y: ((Y - ym) / ysd).astype(np.float32)
+
+    dev = torch.device("cuda", 0)
+    f = FMM2D(0)
+    params = torch.from_numpy(init_params(NFEAT, args.seed)).to(dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    Xt, Yt = torch.from_numpy(norm_x(Xtr)).to(dev), torch.from_numpy(norm_y(Ytr)).to(dev)
+    Xv, Yv = torch.from_numpy(norm_x(Xva)).to(dev), torch.from_numpy(norm_y(Yva)).to(dev)
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device="cpu").manual_seed(args.seed)
+    ntr = Xt.shape[0]
+    for step in range(1, args.steps + 1):
+        idx = torch.randint(0, ntr, (min(args.batch, ntr),), generator=gen).to(dev)
+        xb, yb = Xt[idx].contiguous(), Yt[idx].contiguous()
+        lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * step / args.steps))  # cosine decay
+        f.mlp_grad(params, xb, yb, grad, loss)
+        f.mlp_adam(params, m, v, grad, step=step, lr=max(lr, 1e-5))
+        if step % 500 == 0 or step == args.steps:
+            _, lv = f.mlp_grad(params, Xv, Yv) if Xv.shape[0] else (None, loss)
+            print("[train] step %d  batch loss %.4f  val loss %.4f" % (step, float(loss.cpu()), float(lv.cpu())),
+                  flush=True)
+
+    # decision quality on the validation layouts (labels vs rounded predictions)
+    pred = f.mlp_forward(params, Xv).cpu().numpy().astype(np.float64) * ysd + ym
+    dl_ok = np.mean(np.floor(pred[:, 0] + 0.5) == Yva[:, 0])
+    p_ok = np.mean(np.ceil(pred[:, 1]) + 1 >= Yva[:, 1])
+    print("[train] val: levels exact %.3f, p (with margin) >= label %.3f" % (dl_ok, p_ok), flush=True)
+
+    blob = np.zeros(HEADER + params.numel(), dtype=np.float32)
+    blob[:NFEAT] = xm
+    blob[NFEAT:2 * NFEAT] = xscale
+    blob[2 * NFEAT:2 * NFEAT + 3] = ym
+    blob[2 * NFEAT + 3:2 * NFEAT + 6] = ysd
+    lnn = np.log10(ns.astype(np.float64))
+    blob[2 * NFEAT + 6:2 * NFEAT + 10] = (lnn.min(), lnn.max(), TOL_LO, TOL_HI)
+    blob[HEADER:] = params.cpu().numpy()
+    blob.astype("<f4").tofile(args.out)
+    meta = {"layouts": int(nl), "val_layouts": int(nval), "samples": int(Xtr.shape[0]),
+            "val_samples": int(Xva.shape[0]), "steps": args.steps, "batch": args.batch, "lr": args.lr,
+            "val_levels_exact": float(dl_ok), "val_p_covers_label": float(p_ok),
+            "log10_n_range": [float(lnn.min()), float(lnn.max())], "log10_tol_range": [TOL_LO, TOL_HI]}
+    with open(args.out + ".json", "w") as fh:
+        json.dump(meta, fh, indent=1)
+    print("[train] wrote %s (%d floats)" % (args.out, blob.size), flush=True)
+    f.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -92,7 +92,7 @@ FP64_CASES = ["uniform_1k_L3", "clustered_scaled_30k_L6", "ties_3k_L4", "ragged_
 
 
 @pytest.mark.parametrize("case", FP64_CASES)
-@pytest.mark.parametrize("p", [3, 17, 40])
+@pytest.mark.parametrize("p", [3, 12, 15, 17, 40])
 def test_fp64_potentials_match_oracle_fmm(fmm, orc, case, p):
     theta = 0.5
     _skip_faulted(case, theta)
@@ -133,6 +133,25 @@ def test_reduced_modes_error(fmm, orc, case, mode, tol):
     ex = orc.direct(ps.x, ps.y, ps.q)
     e, _ = orc.rel_errors(phi, ex)
     assert e <= tol
+
+
+@pytest.mark.parametrize("p", [12, 20])
+def test_bf16x3_product_differs_from_fp32(fmm, p):
+    # the BF16X3 M2L keeps about 16 bits per product (the dropped lo x lo term
+    # is ~2^-16 relative), FP32 about 24: against the binary64 result its
+    # error must be larger than FP32's yet within 1e-3 (one and two 16-wide
+    # coefficient tiles: p + 1 = 13 and 21)
+    maker, L = TREE_CASES["uniform_10k_L5"]
+    ps = maker()
+    _announce("bf16x3 vs fp32", p)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity(0.5)
+    q = _dev(ps.q)
+    ref = fmm.evaluate(q, p, "fp64").cpu().numpy()
+    e32 = np.abs(fmm.evaluate(q, p, "fp32").cpu().numpy() - ref).max() / np.abs(ref).max()
+    eb = np.abs(fmm.evaluate(q, p, "bf16x3").cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert eb <= 1e-3
+    assert eb > 1.5 * e32
 
 
 def test_call_order_and_argument_errors(fmm):
