@@ -140,13 +140,16 @@ int fmm2d_features(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, 
  *   [0, 92)    mean of each feature
  *   [92, 184)  1 / standard deviation of each feature (network input is
  *              (feature - mean) * scale)
- *   [184, 187) mean of the three targets (levels - L0, p, theta)
+ *   [184, 187) mean of the three targets (levels - L0, log10 C, theta)
  *   [187, 190) standard deviation of the three targets
  *   [190, 194) trained range: log10 n low, high, log10 tol low, high
  *   [194, 194 + fmm2d_mlp_nparams(92)) network parameters (see fmm2d_mlp_forward)
  * With weights and inputs inside the trained range, the network's outputs
- * give levels = round(L0 + out0) with L0 = round(log4(n / 16)), p =
- * ceil(out1) + 1, theta = out2 snapped to {0.35, 0.45, 0.55, 0.65, 0.75}.
+ * (de-standardised) give levels = round(L0 + out0) with L0 =
+ * round(log4(n / 16)), theta = out2 snapped to {0.35, 0.45, 0.55, 0.65,
+ * 0.75}, and, with out1 = log10 C of an error model e(p) = C theta^(p+1)
+ * (the form of the truncation bound of Section 3), p = ceil((log10 tol -
+ * out1) / log10 theta): the least order the model says meets tol, plus one.
  * Otherwise (NULL weights, n or tol outside the range, non-finite output)
  * the a-priori rule, the practical choice at the end of Section 4: theta =
  * 1/2, levels = round(log4(n / 20)) (about 20 points per leaf), p = the least

@@ -20,9 +20,12 @@ Plain numpy reference of what the GPU library's parameter selection computes
                        truncation bound of Section 3 with constant 0.1.
 * ``decide``        -- the mapping from the network's three raw outputs to
                        (levels, p, theta).  The network's targets are an
-                       encoding chosen here (levels - round(log4(N/16)), p,
-                       theta); the paper has no learned selector, so this is
-                       parity unpinned against the paper.
+                       encoding chosen here: levels - round(log4(N/16)),
+                       log10 C of the error model C theta^(p+1) (the form of
+                       the truncation bound of Section 3), and theta; p is
+                       the least order the model says meets TOL, plus one.
+                       The paper has no learned selector, so this is parity
+                       unpinned against the paper.
 """
 from __future__ import annotations
 
@@ -111,13 +114,17 @@ def decide(out3, blob, n: int, tol: float):
     inside = r[0] <= ln <= r[1] and r[2] <= lt <= r[3]
     mean = blob[2 * NFEAT: 2 * NFEAT + 3].astype(np.float64)
     std = blob[2 * NFEAT + 3: 2 * NFEAT + 6].astype(np.float64)
-    dl, pp, th = (float(np.float64(out3[i]) * std[i] + mean[i]) for i in range(3))
-    ok = inside and all(math.isfinite(v) for v in (dl, pp, th)) and abs(dl) < 64.0 and abs(pp) < 1e4
+    dl, lc, th = (float(np.float64(out3[i]) * std[i] + mean[i]) for i in range(3))
+    ok = inside and all(math.isfinite(v) for v in (dl, lc, th)) and abs(dl) < 64.0 and abs(lc) < 1e4
     if not ok:
         L, p, theta = rule(n, tol)
         return L, p, theta, False
     L0 = round_half_up(math.log(max(n / 16.0, 1.0)) / math.log(4.0))
     L = max(1, min(round_half_up(L0 + dl), levels_max(n)))
-    p = max(1, min(math.ceil(pp) + 1, MAX_P))
     g = max(0, min(round_half_up((th - 0.35) / 0.1), 4))
-    return L, p, THETAS[g], True
+    theta = THETAS[g]
+    # error model e(p) = C theta^(p+1): the least p meeting tol has
+    # p + 1 = ceil(log(tol / C) / log theta); one more order as a margin
+    q = math.ceil((lt - lc) / math.log10(theta))
+    p = max(1, min(q, MAX_P))
+    return L, p, theta, True

@@ -17,8 +17,10 @@
 // at the end of Section 4, theta = 1/2 and about 20 points per leaf
 // (L = round(log4(N / 20))), with the least p for which the truncation bound
 // of Section 3, K theta^(p+1) / (1 - theta)^2 with K = 0.1, is <= TOL.  The
-// network predicts L - L0 (L0 = round(log4(N / 16))), p and theta; L is rounded, p rounded up
-// with one extra order as a margin, theta snapped to {0.35, ..., 0.75}.
+// network predicts L - L0 (L0 = round(log4(N / 16))), log10 C of the error
+// model e(p) ~ C theta^(p+1), and theta; L is rounded, theta snapped to
+// {0.35, ..., 0.75}, and p is the least order the model says meets TOL, plus
+// one as a margin.
 #include "devutil.h"
 #include "internal.h"
 
@@ -223,19 +225,21 @@ __global__ void k_select_final(const float *__restrict__ y, const float *__restr
         const float *rng = blob + 2 * NFEAT + 6;
         const bool inside = ln >= rng[0] && ln <= rng[1] && lt >= rng[2] && lt <= rng[3];
         const double dl = (double)y[0] * blob[2 * NFEAT + 3] + blob[2 * NFEAT + 0];
-        const double pp = (double)y[1] * blob[2 * NFEAT + 4] + blob[2 * NFEAT + 1];
+        const double lc = (double)y[1] * blob[2 * NFEAT + 4] + blob[2 * NFEAT + 1];
         const double th = (double)y[2] * blob[2 * NFEAT + 5] + blob[2 * NFEAT + 2];
-        if (inside && isfinite(dl) && isfinite(pp) && isfinite(th) && fabs(dl) < 64.0 && fabs(pp) < 1e4) {
+        if (inside && isfinite(dl) && isfinite(lc) && isfinite(th) && fabs(dl) < 64.0 && fabs(lc) < 1e4) {
             net = true;
             const double x0 = log((double)n / 16.0 > 1.0 ? (double)n / 16.0 : 1.0) / log(4.0);
             const int L0 = (int)floor(x0 + 0.5);
             L = (int)floor((double)L0 + dl + 0.5);
             L = L > lmax ? lmax : (L < 1 ? 1 : L);
-            p = (int)ceil(pp) + 1;
-            p = p > FMM2D_MAX_P ? FMM2D_MAX_P : (p < 1 ? 1 : p);
             int g = (int)floor((th - 0.35) / 0.1 + 0.5);
             g = g < 0 ? 0 : (g > 4 ? 4 : g);
             theta = thetas[g];
+            // error model e(p) ~ C theta^(p+1): p + 1 = ceil(log(TOL / C) / log theta),
+            // and one more order as a margin
+            const double q = ceil((lt - lc) / log10(theta));
+            p = q > (double)FMM2D_MAX_P ? FMM2D_MAX_P : (q < 1.0 ? 1 : (int)q);
         }
     }
     if (!net) rule(n, tol, lmax, L, p, theta);

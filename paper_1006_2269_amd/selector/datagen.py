@@ -107,7 +107,7 @@ def main():
         print("[datagen] layout %d seed %d n=%d runs=%d  %.0f s" % (i, seed, ps.n, len(rows), time.time() - t0),
               flush=True)
         if (i + 1) % 25 == 0 or i + 1 == args.count:
-            np.savez(args.out, feats=np.array(feats, dtype=np.float32), n=np.array(ns, dtype=np.int64),
+            np.savez_compressed(args.out, feats=np.array(feats, dtype=np.float32), n=np.array(ns, dtype=np.int64),
                      seeds=np.arange(args.first, args.first + i + 1), runs=np.array(table, dtype=np.float64),
                      columns=np.array(["layout", "L", "theta", "p", "t_tree_ms", "t_lists_ms", "t_eval_ms",
                                        "e_inf"]))
