@@ -148,8 +148,9 @@ int fmm2d_features(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, 
  * (de-standardised) give levels = round(L0 + out0) with L0 =
  * round(log4(n / 16)), theta = out2 snapped to {0.35, 0.45, 0.55, 0.65,
  * 0.75}, and, with out1 = log10 C of an error model e(p) = C theta^(p+1)
- * (the form of the truncation bound of Section 3), p = ceil((log10 tol -
- * out1) / log10 theta): the least order the model says meets tol, plus one.
+ * (the form of the truncation bound of Section 3), p = ceil((log10(tol / 3)
+ * - out1) / log10 theta) - 1: the least order the model says meets tol / 3
+ * (a safety factor of 3 on the error).
  * Otherwise (NULL weights, n or tol outside the range, non-finite output)
  * the a-priori rule, the practical choice at the end of Section 4: theta =
  * 1/2, levels = round(log4(n / 20)) (about 20 points per leaf), p = the least

@@ -328,16 +328,19 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
 // outputs by T'_l and accumulates them in registers.  At the end of the
 // segment a transposing butterfly reduction (each stage halves the values a
 // lane carries) sums the 64 lanes' accumulators in a fixed order.
-template <typename G, typename ACC, bool BF3>
-__global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict__ geomL,
-                                               const int32_t *__restrict__ wptr, const int32_t *__restrict__ widx,
-                                               const cd *__restrict__ AL, const int2 *__restrict__ segtab,
-                                               const int32_t *__restrict__ nseg_ptr, cd *__restrict__ part,
-                                               const double *__restrict__ Mhat) {
+template <int P1, typename G, typename ACC, bool BF3>
+__global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geomL, const int32_t *__restrict__ wptr,
+                                               const int32_t *__restrict__ widx, const cd *__restrict__ AL,
+                                               const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
+                                               cd *__restrict__ part, const double *__restrict__ Mhat) {
+    static_assert(P1 >= 1 && P1 <= 16, "one 16-wide coefficient tile");
     using MF = Mfma<G>;
     using V = typename MF::V;
     using PT = typename std::conditional<std::is_same<ACC, float>::value, float, double>::type;
-    constexpr int KP = 17;  // padded row length
+    constexpr int KP = 17;                                   // padded row length
+    constexpr int KS = (P1 + 3) / 4;                         // K steps of the FP32/FP64 instruction
+    constexpr int NV = P1 <= 4 ? 8 : (P1 <= 8 ? 16 : 32);    // accumulated values (Re, Im), power of two
+    constexpr int SPREAD = 64 / NV;                          // lanes sharing one value after the halving stages
     __shared__ G U[64][2][KP];
     const int64_t seg = blockIdx.x;
     if (seg >= *nseg_ptr) return;  // the block is one wavefront: uniform exit
@@ -346,11 +349,9 @@ __global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict_
     const int64_t b = se.x;
     const int32_t t0 = se.y;
     const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
-    const int P1 = p + 1;
-    const int ks_n = (P1 + 3) / 4;
     const int row = lane % 16, g = lane / 16;
     const double4 gb = geomL[b];
-    G mreg[4];
+    G mreg[KS];
     v4s mbh, mbl;
     if constexpr (BF3) {
 #pragma unroll
@@ -364,14 +365,14 @@ __global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict_
         }
     } else {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
+        for (int ks = 0; ks < KS; ++ks) {
             const int k = 4 * ks + g;
             mreg[ks] = (k < P1 && row < P1) ? (G)Mhat[row * 64 + k] : (G)0;
         }
     }
-    ACC acc[32];
+    ACC acc[NV];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) acc[i] = (ACC)0;
+    for (int i = 0; i < NV; ++i) acc[i] = (ACC)0;
     ACC ext0 = (ACC)0;
     for (int32_t t = t0; t < t1; t += 64) {
         const int np = (t1 - t) < 64 ? (t1 - t) : 64;
@@ -381,29 +382,31 @@ __global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict_
             const int32_t c = widx[t + lane];
             const double4 gc = geomL[c];
             const cd *Ac = AL + (int64_t)c * P1;
+            cd a[P1];
+#pragma unroll
+            for (int k = 0; k < P1; ++k) a[k] = Ac[k];  // all loads in flight together
             const cd z0{gc.x - gb.x, gc.y - gb.y};
             const double d2 = z0.re * z0.re + z0.im * z0.im;  // > 0 for a weak pair
             const double inv = gc.w / d2;
             const cd rs = d2 > 0x1p-960 ? cd{z0.re * inv, -z0.im * inv} : cdiv(cd{gc.w, 0.0}, z0);
             const cd rt = cscale(rs, gb.w / gc.w);
-            ext0 += (ACC)(Ac[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im))));
+            ext0 += (ACC)(a[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im))));
             const cx<PT> rsp{(PT)rs.re, (PT)rs.im};
             rtp = cx<PT>{(PT)rt.re, (PT)rt.im};
             cx<PT> w{(PT)1, (PT)0};
             PT sc = (PT)1;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (k < P1) {
-                    const cd a = Ac[k];
-                    const cx<PT> u = cxmul(cx<PT>{(PT)a.re, (PT)a.im}, w);
-                    U[lane][0][k] = (G)(u.re * sc);
-                    U[lane][1][k] = (G)(u.im * sc);
-                    w = cxmul(w, rsp);
-                    sc *= (PT)2;
-                } else {
-                    U[lane][0][k] = (G)0;  // K padding read by the products
-                    U[lane][1][k] = (G)0;
-                }
+            for (int k = 0; k < P1; ++k) {
+                const cx<PT> u = cxmul(cx<PT>{(PT)a[k].re, (PT)a[k].im}, w);
+                U[lane][0][k] = (G)(u.re * sc);
+                U[lane][1][k] = (G)(u.im * sc);
+                w = cxmul(w, rsp);
+                sc *= (PT)2;
+            }
+#pragma unroll
+            for (int k = P1; k < 4 * KS || (BF3 && k < 16); ++k) {
+                U[lane][0][k] = (G)0;  // K padding read by the products
+                U[lane][1][k] = (G)0;
             }
         }
         __syncthreads();
@@ -427,8 +430,7 @@ __global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict_
                 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, mbh, d, 0, 0, 0);
             } else {
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks)
-                    if (ks < ks_n) d = MF::run(ur[4 * ks + g], mreg[ks], d);
+                for (int ks = 0; ks < KS; ++ks) d = MF::run(ur[4 * ks + g], mreg[ks], d);
             }
             // element r of lane group g is pair 8 rb + 2 g + r / 2, part r % 2,
             // coefficient l = row: those rows of U belong to this block only
@@ -440,23 +442,22 @@ __global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict_
             cx<PT> tp{(PT)1, (PT)0};
             PT sc = (PT)1;
 #pragma unroll
-            for (int l = 0; l < 16; ++l) {
-                if (l < P1) {
-                    const ACC wr = (ACC)U[lane][0][l], wi = (ACC)U[lane][1][l];
-                    const ACC tr = (ACC)(tp.re * sc), ti = (ACC)(tp.im * sc);
-                    acc[2 * l] += tr * wr - ti * wi;
-                    acc[2 * l + 1] += tr * wi + ti * wr;
-                    tp = cxmul(tp, rtp);
-                    sc *= (PT)2;
-                }
+            for (int l = 0; l < P1; ++l) {
+                const ACC wr = (ACC)U[lane][0][l], wi = (ACC)U[lane][1][l];
+                const ACC tr = (ACC)(tp.re * sc), ti = (ACC)(tp.im * sc);
+                acc[2 * l] += tr * wr - ti * wi;
+                acc[2 * l + 1] += tr * wi + ti * wr;
+                tp = cxmul(tp, rtp);
+                sc *= (PT)2;
             }
         }
         __syncthreads();
     }
-    // transposing butterfly: after the stage with mask m a lane carries half
-    // as many values; at the end lane i holds the total of value i / 2
+    // transposing butterfly: each stage with mask m halves the values a lane
+    // carries; then the SPREAD lanes holding the same value are added; lane i
+    // ends with the total of value i / SPREAD
 #pragma unroll
-    for (int h = 16, m = 32; h >= 1; h >>= 1, m >>= 1) {
+    for (int h = NV / 2, m = 32; h >= 1; h >>= 1, m >>= 1) {
         const bool hi = (lane & m) != 0;
 #pragma unroll
         for (int i = 0; i < h; ++i) {
@@ -465,15 +466,34 @@ __global__ void __launch_bounds__(64) k_m2l_lp(int p, const double4 *__restrict_
             acc[i] = keep + __shfl_xor(send, m, 64);
         }
     }
-    acc[0] += __shfl_xor(acc[0], 1, 64);
+#pragma unroll
+    for (int m = SPREAD / 2; m >= 1; m >>= 1) acc[0] += __shfl_xor(acc[0], m, 64);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) ext0 += __shfl_xor(ext0, off, 64);
-    const int idx = lane >> 1, l = idx >> 1, comp = idx & 1;
-    if ((lane & 1) == 0 && l < P1) {
+    const int idx = lane / SPREAD, l = idx >> 1, comp = idx & 1;
+    if (lane % SPREAD == 0 && l < P1) {
         double v = (double)acc[0];
         if (l == 0 && comp == 0) v += (double)ext0;
         reinterpret_cast<double *>(part)[2 * (seg * P1 + l) + comp] = v;
     }
+}
+
+template <int P1>
+void launch_m2l_lp(fmm2d_ctx *c, int mode, dim3 grid, const double4 *gL, const int32_t *wp, const int32_t *wi,
+                   const cd *AL, const int2 *tab, const int32_t *nsp, cd *part, const double *Mh) {
+    const dim3 block(64);
+    if (mode == FMM2D_MODE_FP64)
+        hipLaunchKernelGGL((k_m2l_lp<P1, double, double, false>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
+    else if (mode == FMM2D_MODE_FP32_ACC64)
+        hipLaunchKernelGGL((k_m2l_lp<P1, float, double, false>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
+    else if (mode == FMM2D_MODE_BF16X3)
+        hipLaunchKernelGGL((k_m2l_lp<P1, float, float, true>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
+    else
+        hipLaunchKernelGGL((k_m2l_lp<P1, float, float, false>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
+                           part, Mh);
 }
 
 // B_l(b) += the segments' partial sums, in segment order.
@@ -519,18 +539,15 @@ hipError_t launch_m2l(fmm2d_ctx *c, int l, int p, int mode) {
     const int32_t *nsp = sc.segoff.as<int32_t>() + nb;
     const dim3 grid((unsigned)sc.bound), block(64);
     if (NT == 1) {
-        if (mode == FMM2D_MODE_FP64)
-            hipLaunchKernelGGL((k_m2l_lp<double, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab,
-                               nsp, part, Mh);
-        else if (mode == FMM2D_MODE_FP32_ACC64)
-            hipLaunchKernelGGL((k_m2l_lp<float, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab,
-                               nsp, part, Mh);
-        else if (mode == FMM2D_MODE_BF16X3)
-            hipLaunchKernelGGL((k_m2l_lp<float, float, true>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                               part, Mh);
-        else
-            hipLaunchKernelGGL((k_m2l_lp<float, float, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab,
-                               nsp, part, Mh);
+        switch (p + 1) {
+#define FMM2D_M2L_LP(P1) \
+    case P1: launch_m2l_lp<P1>(c, mode, grid, gL, wp, wi, AL, tab, nsp, part, Mh); break;
+            FMM2D_M2L_LP(2) FMM2D_M2L_LP(3) FMM2D_M2L_LP(4) FMM2D_M2L_LP(5) FMM2D_M2L_LP(6) FMM2D_M2L_LP(7)
+            FMM2D_M2L_LP(8) FMM2D_M2L_LP(9) FMM2D_M2L_LP(10) FMM2D_M2L_LP(11) FMM2D_M2L_LP(12)
+            FMM2D_M2L_LP(13) FMM2D_M2L_LP(14) FMM2D_M2L_LP(15) FMM2D_M2L_LP(16)
+#undef FMM2D_M2L_LP
+            default: return hipErrorInvalidValue;
+        }
     } else if (mode == FMM2D_MODE_FP64)
         hipLaunchKernelGGL((k_m2l<NT, double, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
                            part, Mh);

@@ -9,9 +9,13 @@ vector with its second entry set to log10 TOL.  Pairs for which no measured
 configuration meets TOL (below the FP32 error floor) are left out.
 
 Targets (L - L0, log10 C, theta) with L0 = round(log4(N / 16)) and C the
-constant of the error model C theta^(p+1) placed so that decoding returns the
-label's p plus a one-order margin; targets and inputs are standardised; mean and scale go into the weight blob's header together with
-the trained range of log10 N and log10 TOL.
+constant of the error model C theta^(p+1), placed in the middle of the
+label's order (log10 TOL = log10 C + (p + 1/2) log10 theta); decoding adds a
+safety factor of 3 on the error.  Targets and inputs are standardised; mean
+and scale go into the weight blob's header together with the trained range
+of log10 N (widened by 0.1 decade below and 0.15 above) and log10 TOL.  The
+parameters kept are those of the lowest validation loss (layouts held out
+from training), checked every 100 steps.
 
     python -m paper_1006_2269_amd.selector.train --runs a.npz b.npz --out weights.f32
 """
@@ -73,8 +77,7 @@ def best_config(R, tol):
 def make_samples(feats, ns, runs, layouts, per_layout, seed):
     """Inputs and targets (L - L0, log10 C, theta), where log10 C puts the
     label's order in the middle of the error model's interval:
-    log10 TOL = log10 C + (p + 1/2) log10 theta, so that decoding returns
-    the label's p plus the one-order margin."""
+    log10 TOL = log10 C + (p + 1/2) log10 theta."""
     rng = np.random.default_rng(seed)
     X, Y = [], []
     for i in layouts:
@@ -109,7 +112,7 @@ def main():
     ap.add_argument("--runs", nargs="+", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--per-layout", type=int, default=32)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--val-frac", type=float, default=0.1)
@@ -147,23 +150,29 @@ def main():
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     gen = torch.Generator(device="cpu").manual_seed(args.seed)
     ntr = Xt.shape[0]
+    best = (math.inf, 0, params.clone())
     for step in range(1, args.steps + 1):
         idx = torch.randint(0, ntr, (min(args.batch, ntr),), generator=gen).to(dev)
         xb, yb = Xt[idx].contiguous(), Yt[idx].contiguous()
         lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * step / args.steps))  # cosine decay
         f.mlp_grad(params, xb, yb, grad, loss)
         f.mlp_adam(params, m, v, grad, step=step, lr=max(lr, 1e-5))
-        if step % 500 == 0 or step == args.steps:
-            _, lv = f.mlp_grad(params, Xv, Yv) if Xv.shape[0] else (None, loss)
-            print("[train] step %d  batch loss %.4f  val loss %.4f" % (step, float(loss.cpu()), float(lv.cpu())),
-                  flush=True)
+        if step % 100 == 0 or step == args.steps:
+            _, lv = f.mlp_grad(params, Xv, Yv)
+            lv = float(lv.cpu())
+            if lv < best[0]:
+                best = (lv, step, params.clone())
+            if step % 500 == 0 or step == args.steps:
+                print("[train] step %d  batch loss %.4f  val loss %.4f  (best %.4f at %d)"
+                      % (step, float(loss.cpu()), lv, best[0], best[1]), flush=True)
+    params = best[2]
 
     # decision quality on the validation layouts: decoded (levels, theta, p)
     # against the labels
     pred = f.mlp_forward(params, Xv).cpu().numpy().astype(np.float64) * ysd + ym
     thetas = np.array([0.35, 0.45, 0.55, 0.65, 0.75])
     th_p = thetas[np.clip(np.floor((pred[:, 2] - 0.35) / 0.1 + 0.5), 0, 4).astype(int)]
-    p_dec = np.ceil((Xva[:, 1] - pred[:, 1]) / np.log10(th_p))
+    p_dec = np.ceil((Xva[:, 1] - math.log10(3.0) - pred[:, 1]) / np.log10(th_p)) - 1
     p_lab = np.round((Xva[:, 1] - Yva[:, 1]) / np.log10(Yva[:, 2]) - 0.5)
     dl_ok = np.mean(np.floor(pred[:, 0] + 0.5) == Yva[:, 0])
     th_ok = np.mean(np.isclose(th_p, Yva[:, 2]))
@@ -177,13 +186,14 @@ def main():
     blob[2 * NFEAT:2 * NFEAT + 3] = ym
     blob[2 * NFEAT + 3:2 * NFEAT + 6] = ysd
     lnn = np.log10(ns.astype(np.float64))
-    blob[2 * NFEAT + 6:2 * NFEAT + 10] = (lnn.min(), lnn.max(), TOL_LO, TOL_HI)
+    blob[2 * NFEAT + 6:2 * NFEAT + 10] = (lnn.min() - 0.1, lnn.max() + 0.15, TOL_LO, TOL_HI)
     blob[HEADER:] = params.cpu().numpy()
     blob.astype("<f4").tofile(args.out)
     meta = {"layouts": int(nl), "val_layouts": int(nval), "samples": int(Xtr.shape[0]),
             "val_samples": int(Xva.shape[0]), "steps": args.steps, "batch": args.batch, "lr": args.lr,
             "val_levels_exact": float(dl_ok), "val_theta_exact": float(th_ok), "val_p_covers_label": float(p_ok),
-            "log10_n_range": [float(lnn.min()), float(lnn.max())], "log10_tol_range": [TOL_LO, TOL_HI]}
+            "best_step": int(best[1]), "best_val_loss": float(best[0]),
+            "log10_n_range": [float(lnn.min()) - 0.1, float(lnn.max()) + 0.15], "log10_tol_range": [TOL_LO, TOL_HI]}
     with open(args.out + ".json", "w") as fh:
         json.dump(meta, fh, indent=1)
     print("[train] wrote %s (%d floats)" % (args.out, blob.size), flush=True)
