@@ -148,9 +148,9 @@ int fmm2d_features(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, 
  * (de-standardised) give levels = round(L0 + out0) with L0 =
  * round(log4(n / 16)), theta = out2 snapped to {0.35, 0.45, 0.55, 0.65,
  * 0.75}, and, with out1 = log10 C of an error model e(p) = C theta^(p+1)
- * (the form of the truncation bound of Section 3), p = ceil((log10(tol / 3)
- * - out1) / log10 theta) - 1: the least order the model says meets tol / 3
- * (a safety factor of 3 on the error).
+ * (the form of the truncation bound of Section 3), p = ceil((log10(tol / 2)
+ * - out1) / log10 theta) - 1: the least order the model says meets tol / 2
+ * (a safety factor of 2 on the error).
  * Otherwise (NULL weights, n or tol outside the range, non-finite output)
  * the a-priori rule, the practical choice at the end of Section 4: theta =
  * 1/2, levels = round(log4(n / 20)) (about 20 points per leaf), p = the least
@@ -224,7 +224,10 @@ int fmm2d_get_lists(fmm2d_ctx *ctx, int level, int32_t *sptr, int32_t *sidx,
 #define FMM2D_PHASE_OTHER   6  /* charge gather, scatter to input order       */
 #define FMM2D_PHASE_JUDGE   7  /* fmm2d_direct                                */
 #define FMM2D_PHASE_SELECT  8  /* parameter selection                         */
-#define FMM2D_NPHASE        9
+/* Single kernel launches, also counted in their phase above:                 */
+#define FMM2D_PHASE_NEAR_KERNEL  9  /* the near-field kernel (in LEAF)       */
+#define FMM2D_PHASE_M2L_FINEST  10  /* the finest level's M2L kernel (in M2L) */
+#define FMM2D_NPHASE       11
 
 /* enable = 1 clears the accumulated timings and starts recording HIP events
  * on the context stream around each phase; enable = 0 stops recording. */

@@ -23,7 +23,7 @@ Plain numpy reference of what the GPU library's parameter selection computes
                        encoding chosen here: levels - round(log4(N/16)),
                        log10 C of the error model C theta^(p+1) (the form of
                        the truncation bound of Section 3), and theta; p is
-                       the least order the model says meets TOL / 3.
+                       the least order the model says meets TOL / 2.
                        The paper has no learned selector, so this is parity
                        unpinned against the paper.
 """
@@ -39,7 +39,7 @@ HEADER = 194
 THETAS = (0.35, 0.45, 0.55, 0.65, 0.75)
 MAX_LEVELS = 13
 MAX_P = 63
-SAFETY_LOG10 = 0.47712125471966244  # log10(3)
+SAFETY_LOG10 = 0.30102999566398120  # log10(2)
 
 
 def round_half_up(v: float) -> int:
@@ -124,8 +124,8 @@ def decide(out3, blob, n: int, tol: float):
     L = max(1, min(round_half_up(L0 + dl), levels_max(n)))
     g = max(0, min(round_half_up((th - 0.35) / 0.1), 4))
     theta = THETAS[g]
-    # error model e(p) = C theta^(p+1) with a safety factor of 3 on the
-    # error: the least p with C theta^(p+1) <= tol / 3
+    # error model e(p) = C theta^(p+1) with a safety factor of 2 on the
+    # error: the least p with C theta^(p+1) <= tol / 2
     q = math.ceil((lt - SAFETY_LOG10 - lc) / math.log10(theta)) - 1
     p = max(1, min(q, MAX_P))
     return L, p, theta, True

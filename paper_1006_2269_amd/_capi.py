@@ -56,7 +56,8 @@ SIGNATURES = [
 NFEAT = 92
 SELECT_HEADER = 194
 
-PHASES = ["tree", "lists", "upward", "m2l", "l2l", "leaf", "other", "judge", "select"]
+PHASES = ["tree", "lists", "upward", "m2l", "l2l", "leaf", "other", "judge", "select", "near_kernel",
+          "m2l_finest"]
 
 
 def load():

@@ -105,7 +105,11 @@ struct EvalState {
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream
 // around each phase's launches while timing is enabled.
-enum Phase { PH_TREE = 0, PH_LISTS, PH_UPWARD, PH_M2L, PH_L2L, PH_LEAF, PH_OTHER, PH_JUDGE, PH_SELECT, PH_COUNT };
+enum Phase {
+    PH_TREE = 0, PH_LISTS, PH_UPWARD, PH_M2L, PH_L2L, PH_LEAF, PH_OTHER, PH_JUDGE, PH_SELECT,
+    PH_NEAR_KERNEL, PH_M2L_FINEST,  // single launches inside PH_LEAF / PH_M2L
+    PH_COUNT
+};
 
 struct PhaseTimer {
     bool on = false;
@@ -188,8 +192,9 @@ struct PhaseScope {
     fmm2d_ctx *c;
     int phase;
     hipEvent_t a = nullptr;
+    // ph < 0: not timed
     PhaseScope(fmm2d_ctx *ctx, int ph) : c(ctx), phase(ph) {
-        if (c->timer.on && (a = c->timer.next())) (void)hipEventRecord(a, c->stream);
+        if (ph >= 0 && c->timer.on && (a = c->timer.next())) (void)hipEventRecord(a, c->stream);
     }
     ~PhaseScope() {
         if (a) {

@@ -538,28 +538,32 @@ hipError_t launch_m2l(fmm2d_ctx *c, int l, int p, int mode) {
     const int2 *tab = sc.table.as<int2>();
     const int32_t *nsp = sc.segoff.as<int32_t>() + nb;
     const dim3 grid((unsigned)sc.bound), block(64);
-    if (NT == 1) {
-        switch (p + 1) {
+    {
+        // the finest level's kernel alone is also timed as its own phase
+        PhaseScope kernel_scope(c, l == t.L ? (int)PH_M2L_FINEST : -1);
+        if (NT == 1) {
+            switch (p + 1) {
 #define FMM2D_M2L_LP(P1) \
     case P1: launch_m2l_lp<P1>(c, mode, grid, gL, wp, wi, AL, tab, nsp, part, Mh); break;
-            FMM2D_M2L_LP(2) FMM2D_M2L_LP(3) FMM2D_M2L_LP(4) FMM2D_M2L_LP(5) FMM2D_M2L_LP(6) FMM2D_M2L_LP(7)
-            FMM2D_M2L_LP(8) FMM2D_M2L_LP(9) FMM2D_M2L_LP(10) FMM2D_M2L_LP(11) FMM2D_M2L_LP(12)
-            FMM2D_M2L_LP(13) FMM2D_M2L_LP(14) FMM2D_M2L_LP(15) FMM2D_M2L_LP(16)
+                FMM2D_M2L_LP(2) FMM2D_M2L_LP(3) FMM2D_M2L_LP(4) FMM2D_M2L_LP(5) FMM2D_M2L_LP(6) FMM2D_M2L_LP(7)
+                FMM2D_M2L_LP(8) FMM2D_M2L_LP(9) FMM2D_M2L_LP(10) FMM2D_M2L_LP(11) FMM2D_M2L_LP(12)
+                FMM2D_M2L_LP(13) FMM2D_M2L_LP(14) FMM2D_M2L_LP(15) FMM2D_M2L_LP(16)
 #undef FMM2D_M2L_LP
-            default: return hipErrorInvalidValue;
-        }
-    } else if (mode == FMM2D_MODE_FP64)
-        hipLaunchKernelGGL((k_m2l<NT, double, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
-    else if (mode == FMM2D_MODE_FP32_ACC64)
-        hipLaunchKernelGGL((k_m2l<NT, float, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
-    else if (mode == FMM2D_MODE_BF16X3)
-        hipLaunchKernelGGL((k_m2l<NT, float, float, true>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
-    else
-        hipLaunchKernelGGL((k_m2l<NT, float, float, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
+                default: return hipErrorInvalidValue;
+            }
+        } else if (mode == FMM2D_MODE_FP64)
+            hipLaunchKernelGGL((k_m2l<NT, double, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                               part, Mh);
+        else if (mode == FMM2D_MODE_FP32_ACC64)
+            hipLaunchKernelGGL((k_m2l<NT, float, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                               part, Mh);
+        else if (mode == FMM2D_MODE_BF16X3)
+            hipLaunchKernelGGL((k_m2l<NT, float, float, true>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                               part, Mh);
+        else
+            hipLaunchKernelGGL((k_m2l<NT, float, float, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
+                               part, Mh);
+    }
     FMM2D_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_m2l_reduce, dim3(grid_for(nb * (p + 1), 256)), dim3(256), 0, c->stream, p, nb,
                        sc.segoff.as<int32_t>(), part, BL);

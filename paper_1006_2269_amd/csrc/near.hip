@@ -320,26 +320,27 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf) {
     FMM2D_TRY(e.part.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
     double *part = e.part.as<double>();
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
-    double scale;
-    if (mode == FMM2D_MODE_FP64) {
-        scale = 0.5;
-        hipLaunchKernelGGL((k_near64<TM, GL>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
-                           t.px.as<double>(), t.py.as<double>(), e.qs.as<double>(), sp, tab, nsp, rj, part);
-    } else {
-        scale = HALF_LN2_D;
-        if (maxleaf > 64) {
-            if (mode == FMM2D_MODE_FP32_ACC64)
-                hipLaunchKernelGGL((k_near32_big<TM, true>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
-                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
-            else
-                hipLaunchKernelGGL((k_near32_big<TM, false>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
-                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
-        } else if (mode == FMM2D_MODE_FP32_ACC64) {
-            hipLaunchKernelGGL((k_near32<TM, GL, true>), grid, block, 0, c->stream, nitems, chunks, stL,
-                               e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+    const double scale = mode == FMM2D_MODE_FP64 ? 0.5 : HALF_LN2_D;
+    {
+        PhaseScope kernel_scope(c, PH_NEAR_KERNEL);  // the near-field kernel alone
+        if (mode == FMM2D_MODE_FP64) {
+            hipLaunchKernelGGL((k_near64<TM, GL>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                               t.px.as<double>(), t.py.as<double>(), e.qs.as<double>(), sp, tab, nsp, rj, part);
         } else {
-            hipLaunchKernelGGL((k_near32<TM, GL, false>), grid, block, 0, c->stream, nitems, chunks, stL,
-                               e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+            if (maxleaf > 64) {
+                if (mode == FMM2D_MODE_FP32_ACC64)
+                    hipLaunchKernelGGL((k_near32_big<TM, true>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                                       e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+                else
+                    hipLaunchKernelGGL((k_near32_big<TM, false>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                                       e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+            } else if (mode == FMM2D_MODE_FP32_ACC64) {
+                hipLaunchKernelGGL((k_near32<TM, GL, true>), grid, block, 0, c->stream, nitems, chunks, stL,
+                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+            } else {
+                hipLaunchKernelGGL((k_near32<TM, GL, false>), grid, block, 0, c->stream, nitems, chunks, stL,
+                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+            }
         }
     }
     FMM2D_TRY(hipGetLastError());

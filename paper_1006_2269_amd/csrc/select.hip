@@ -19,8 +19,8 @@
 // of Section 3, K theta^(p+1) / (1 - theta)^2 with K = 0.1, is <= TOL.  The
 // network predicts L - L0 (L0 = round(log4(N / 16))), log10 C of the error
 // model e(p) ~ C theta^(p+1), and theta; L is rounded, theta snapped to
-// {0.35, ..., 0.75}, and p is the least order the model says meets TOL / 3
-// (a safety factor of 3 on the error).
+// {0.35, ..., 0.75}, and p is the least order the model says meets TOL / 2
+// (a safety factor of 2 on the error).
 #include "devutil.h"
 #include "internal.h"
 
@@ -31,7 +31,7 @@ constexpr int FL = 10;
 constexpr int NFEAT = 2 + 9 * FL;
 constexpr int HDR = 194;  // weight blob header floats, see fmm2d.h
 constexpr int BT = 256;
-constexpr double SAFETY_LOG10 = 0.47712125471966244;  // log10(3): error margin of the network's p
+constexpr double SAFETY_LOG10 = 0.30102999566398120;  // log10(2): error margin of the network's p
 
 // offset of level l (1..FL) in the pyramid of cell counts
 __host__ __device__ inline int64_t cell_off(int l) { return ((int64_t(1) << (2 * l)) - 4) / 3; }
@@ -237,8 +237,8 @@ __global__ void k_select_final(const float *__restrict__ y, const float *__restr
             int g = (int)floor((th - 0.35) / 0.1 + 0.5);
             g = g < 0 ? 0 : (g > 4 ? 4 : g);
             theta = thetas[g];
-            // error model e(p) ~ C theta^(p+1), with a safety factor of 3 on
-            // the error: the least p with C theta^(p+1) <= TOL / 3
+            // error model e(p) ~ C theta^(p+1), with a safety factor of 2 on
+            // the error: the least p with C theta^(p+1) <= TOL / 2
             const double q = ceil((lt - SAFETY_LOG10 - lc) / log10(theta)) - 1.0;
             p = q > (double)FMM2D_MAX_P ? FMM2D_MAX_P : (q < 1.0 ? 1 : (int)q);
         }

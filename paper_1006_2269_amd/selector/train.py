@@ -11,11 +11,11 @@ configuration meets TOL (below the FP32 error floor) are left out.
 Targets (L - L0, log10 C, theta) with L0 = round(log4(N / 16)) and C the
 constant of the error model C theta^(p+1), placed in the middle of the
 label's order (log10 TOL = log10 C + (p + 1/2) log10 theta); decoding adds a
-safety factor of 3 on the error.  Targets and inputs are standardised; mean
+safety factor of 2 on the error.  Targets and inputs are standardised; mean
 and scale go into the weight blob's header together with the trained range
 of log10 N (widened by 0.1 decade below and 0.15 above) and log10 TOL.  The
 parameters kept are those of the lowest validation loss (layouts held out
-from training), checked every 100 steps.
+from training), checked every 50 steps.
 
     python -m paper_1006_2269_amd.selector.train --runs a.npz b.npz --out weights.f32
 """
@@ -50,13 +50,14 @@ def load_runs(paths):
     return np.concatenate(feats), np.concatenate(ns), np.concatenate(runs)
 
 
-TIE = 1.03  # configurations within 3% of the cheapest count as ties
+TIE = 1.10  # configurations within 10% of the cheapest count as ties
 
 
 def best_config(R, tol):
     """Cheapest (cost_ms, L, theta, p) of one layout's runs meeting tol.
-    Near-ties (timing noise) go to theta nearest 0.55, then fewer levels,
-    so that the label does not flip between equivalent choices."""
+    Near-ties (within 10%: the cost is flat across theta for most layouts,
+    and timing noise would flip the label) go to theta nearest 0.55, then
+    fewer levels."""
     cands = []
     keys = np.unique(R[:, 1:3], axis=0)
     for L, th in keys:
@@ -114,7 +115,7 @@ def main():
     ap.add_argument("--per-layout", type=int, default=32)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--val-frac", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=7)
     args = ap.parse_args()
@@ -157,7 +158,7 @@ def main():
         lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * step / args.steps))  # cosine decay
         f.mlp_grad(params, xb, yb, grad, loss)
         f.mlp_adam(params, m, v, grad, step=step, lr=max(lr, 1e-5))
-        if step % 100 == 0 or step == args.steps:
+        if step % 50 == 0 or step == args.steps:
             _, lv = f.mlp_grad(params, Xv, Yv)
             lv = float(lv.cpu())
             if lv < best[0]:
@@ -172,7 +173,7 @@ def main():
     pred = f.mlp_forward(params, Xv).cpu().numpy().astype(np.float64) * ysd + ym
     thetas = np.array([0.35, 0.45, 0.55, 0.65, 0.75])
     th_p = thetas[np.clip(np.floor((pred[:, 2] - 0.35) / 0.1 + 0.5), 0, 4).astype(int)]
-    p_dec = np.ceil((Xva[:, 1] - math.log10(3.0) - pred[:, 1]) / np.log10(th_p)) - 1
+    p_dec = np.ceil((Xva[:, 1] - math.log10(2.0) - pred[:, 1]) / np.log10(th_p)) - 1
     p_lab = np.round((Xva[:, 1] - Yva[:, 1]) / np.log10(Yva[:, 2]) - 0.5)
     dl_ok = np.mean(np.floor(pred[:, 0] + 0.5) == Yva[:, 0])
     th_ok = np.mean(np.isclose(th_p, Yva[:, 2]))

@@ -140,17 +140,17 @@ def _blob(mean3, std3, rng=(3.0, 7.0, -9.0, -3.0)):
 def test_decide_decoding():
     b = _blob((1.0, -1.3, 0.52), (1.0, 1.0, 1.0))
     # L0 = round(log4(1e6 / 16)) = 8 -> levels 9 (= floor(log4 1e6)); theta
-    # 0.52 -> 0.55; p = ceil((-6 - log10 3 + 1.3) / log10 0.55) - 1
-    #                 = ceil(19.94) - 1 = 19
+    # 0.52 -> 0.55; p = ceil((-6 - log10 2 + 1.3) / log10 0.55) - 1
+    #                 = ceil(19.26) - 1 = 19
     assert S.decide(np.zeros(3), b, 10 ** 6, 1e-6) == (9, 19, 0.55, True)
-    # the model's error at p is <= tol / 3, one order less is not
+    # the model's error at p is <= tol / 2, one order less is not
     C, th = 10 ** -1.3, 0.55
-    assert C * th ** 20 <= 1e-6 / 3 < C * th ** 19
+    assert C * th ** 20 <= 1e-6 / 2 < C * th ** 19
     b2 = _blob((0.0, -2.0, 0.5), (2.0, 4.0, 0.1))
     # outputs (-1, 0.25, -1.2): dl = -2, log10 C = -1, theta 0.38 -> 0.35;
-    # p = ceil((-5 - log10 3) / log10 0.35) - 1 = ceil(12.01) - 1 = 12
-    assert S.decide(np.array([-1.0, 0.25, -1.2]), b2, 10 ** 6, 1e-6) == (6, 12, 0.35, True)
-    assert 0.1 * 0.35 ** 13 <= 1e-6 / 3 < 0.1 * 0.35 ** 12
+    # p = ceil((-5 - log10 2) / log10 0.35) - 1 = ceil(11.63) - 1 = 11
+    assert S.decide(np.array([-1.0, 0.25, -1.2]), b2, 10 ** 6, 1e-6) == (6, 11, 0.35, True)
+    assert 0.1 * 0.35 ** 12 <= 1e-6 / 2 < 0.1 * 0.35 ** 11
     # outside the trained range -> the rule
     assert S.decide(np.zeros(3), b, 10 ** 8, 1e-6)[3] is False
     assert S.decide(np.zeros(3), b, 10 ** 6, 1e-10)[:3] == S.rule(10 ** 6, 1e-10)
