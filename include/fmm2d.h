@@ -128,8 +128,10 @@ int fmm2d_direct(fmm2d_ctx *ctx, const double *x, const double *y, const double 
  *   the number of the edges 1/8, 1/4, 1/2, 1, 2, 4, 8 that are <= r.
  * A point's cell along x is floor((x - xmin) 1024 / (xmax - xmin)) clamped
  * to [0, 1023] at level 10 (0 when xmax = xmin), shifted right by 10 - l for
- * level l; likewise along y.  Counts are exact integers, so the output is
- * deterministic.
+ * level l; likewise along y (bounding box of all points).  Cells are counted
+ * over every s-th point, s = ceil(n / 2^18) (all points when n <= 2^18); the
+ * densities and fractions then refer to that sample's size.  Counts are
+ * exact integers, so the output is deterministic.
  * x, y: device double [n]; feat: device float [FMM2D_NFEAT].
  * 1 <= n <= 2^31 - 1, 0 < tol < 1.  Coordinates are not validated here. */
 #define FMM2D_NFEAT 92

@@ -8,7 +8,10 @@ Plain numpy reference of what the GPU library's parameter selection computes
                        and for each level l = 1..10 of a uniform 2^l x 2^l
                        grid over the tight bounding box the occupied-cell
                        fraction and an 8-bin histogram of the points by the
-                       relative density count 4^l / N of their cell.  The
+                       relative density count 4^l / N of their cell, the
+                       cells counted over every ceil(N / 2^18)-th point (all
+                       points when N <= 2^18; N then means the sample size
+                       in the densities and fractions).  The
                        paper fixes no features; these describe the spread of
                        box sizes of the median-split pyramid (Section 4),
                        whose boxes shrink where points crowd.  Parity
@@ -71,9 +74,20 @@ def density_class(count: np.ndarray, n: int, level: int) -> np.ndarray:
     return k
 
 
+SAMPLE_MAX = 1 << 18
+
+
+def sample_stride(n: int) -> int:
+    """Cells are counted over every stride-th point (at most 2^18 points)."""
+    return -(-n // SAMPLE_MAX) if n > SAMPLE_MAX else 1
+
+
 def features(x, y, tol: float) -> np.ndarray:
     n = len(x)
-    ix, iy = finest_cells(x, y)
+    ix, iy = finest_cells(x, y)          # bounding box of all points
+    stride = sample_stride(n)
+    ix, iy = ix[::stride], iy[::stride]
+    ns = len(ix)
     f = np.zeros(NFEAT, dtype=np.float64)
     f[0] = math.log10(n)
     f[1] = math.log10(tol)
@@ -84,9 +98,9 @@ def features(x, y, tol: float) -> np.ndarray:
         occ = counts[counts > 0]
         base = 2 + 9 * (l - 1)
         f[base] = occ.size / float(4 ** l)
-        cls = density_class(occ, n, l)
+        cls = density_class(occ, ns, l)
         for k in range(8):
-            f[base + 1 + k] = float(occ[cls == k].sum()) / float(n)
+            f[base + 1 + k] = float(occ[cls == k].sum()) / float(ns)
     return f.astype(np.float32)
 
 

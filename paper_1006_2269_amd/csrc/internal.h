@@ -58,7 +58,7 @@ struct Schedule {
     DevBuf table;           // int2 [bound]: (row, first entry) of each segment
     int64_t bound = 0;      // upper bound of the segment count (launch size)
 };
-constexpr int M2L_SEG = 128;   // weak-list entries per M2L segment
+constexpr int M2L_SEG = 256;   // weak-list entries per M2L segment
 constexpr int NEAR_SEG = 64;   // strong-list entries per near-field segment
 
 // Everything a tree and its lists leave on the device.

@@ -391,17 +391,16 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geomL
             const cd rs = d2 > 0x1p-960 ? cd{z0.re * inv, -z0.im * inv} : cdiv(cd{gc.w, 0.0}, z0);
             const cd rt = cscale(rs, gb.w / gc.w);
             ext0 += (ACC)(a[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im))));
-            const cx<PT> rsp{(PT)rs.re, (PT)rs.im};
-            rtp = cx<PT>{(PT)rt.re, (PT)rt.im};
+            // 2 rho: the exact factors 2^k of the rescaled matrix ride on the powers
+            const cx<PT> rsp{(PT)(2.0 * rs.re), (PT)(2.0 * rs.im)};
+            rtp = cx<PT>{(PT)(2.0 * rt.re), (PT)(2.0 * rt.im)};
             cx<PT> w{(PT)1, (PT)0};
-            PT sc = (PT)1;
 #pragma unroll
             for (int k = 0; k < P1; ++k) {
                 const cx<PT> u = cxmul(cx<PT>{(PT)a[k].re, (PT)a[k].im}, w);
-                U[lane][0][k] = (G)(u.re * sc);
-                U[lane][1][k] = (G)(u.im * sc);
+                U[lane][0][k] = (G)u.re;
+                U[lane][1][k] = (G)u.im;
                 w = cxmul(w, rsp);
-                sc *= (PT)2;
             }
 #pragma unroll
             for (int k = P1; k < 4 * KS || (BF3 && k < 16); ++k) {
@@ -439,16 +438,14 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geomL
         }
         __syncthreads();
         if (act) {
-            cx<PT> tp{(PT)1, (PT)0};
-            PT sc = (PT)1;
+            cx<PT> tp{(PT)1, (PT)0};  // (2 rho_t)^l
 #pragma unroll
             for (int l = 0; l < P1; ++l) {
                 const ACC wr = (ACC)U[lane][0][l], wi = (ACC)U[lane][1][l];
-                const ACC tr = (ACC)(tp.re * sc), ti = (ACC)(tp.im * sc);
+                const ACC tr = (ACC)tp.re, ti = (ACC)tp.im;
                 acc[2 * l] += tr * wr - ti * wi;
                 acc[2 * l + 1] += tr * wi + ti * wr;
                 tp = cxmul(tp, rtp);
-                sc *= (PT)2;
             }
         }
         __syncthreads();

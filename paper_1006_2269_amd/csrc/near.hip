@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
             const float dx = tx[k] - sx, dy = ty[k] - sy;
             const float r2 = dx * dx + dy * dy;
             const float lg = __log2f(r2);
-            acc[k] += (r2 > thr) ? q * lg : 0.f;
+            acc[k] = fmaf(q, (r2 > thr) ? lg : 0.f, acc[k]);  // coincident: log is masked, never multiplied
         }
         if (ACC64 && (step & 7) == 7) {
 #pragma unroll
@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32_big(int64_t nitems, int chu
                 const float dx = tx[k] - sx, dy = ty[k] - sy;
                 const float r2 = dx * dx + dy * dy;
                 const float lg = __log2f(r2);
-                acc[k] += (r2 > rd.z) ? q * lg : 0.f;
+                acc[k] = fmaf(q, (r2 > rd.z) ? lg : 0.f, acc[k]);
             }
         }
         if (ACC64) {

@@ -9,8 +9,11 @@
 // median-split tree a box's area is inversely proportional to the density
 // around it, so these histograms describe the spread of box sizes at each
 // level, which sets the list lengths and hence the cost of an (L, p, theta).
-// All counts are integers (cell counts, LDS and global integer atomics), so
-// the features do not depend on scheduling.
+// Cells are counted over a fixed sample of at most 2^18 points (every
+// ceil(N / 2^18)-th point; all points when N <= 2^18), and densities and
+// fractions refer to the sample size; the bounding box is that of all
+// points.  All counts are integers (cell counts, LDS and global integer
+// atomics), so the features do not depend on scheduling.
 //
 // Decision (after the network, or the rule when no weights are given or the
 // input lies outside the trained range): the rule is the practical choice
@@ -31,10 +34,8 @@ constexpr int FL = 10;
 constexpr int NFEAT = 2 + 9 * FL;
 constexpr int HDR = 194;  // weight blob header floats, see fmm2d.h
 constexpr int BT = 256;
+constexpr int64_t SAMPLE_MAX = int64_t(1) << 18;  // points counted into cells
 constexpr double SAFETY_LOG10 = 0.30102999566398120;  // log10(2): error margin of the network's p
-
-// offset of level l (1..FL) in the pyramid of cell counts
-__host__ __device__ inline int64_t cell_off(int l) { return ((int64_t(1) << (2 * l)) - 4) / 3; }
 
 // Per-block min / max of x and y, and whether any coordinate is invalid.
 __global__ void __launch_bounds__(BT) k_bbox_part(const double *__restrict__ x, const double *__restrict__ y,
@@ -116,9 +117,11 @@ __global__ void __launch_bounds__(BT) k_bbox_final(const double *__restrict__ pa
     }
 }
 
-__global__ void k_zero_i32(int32_t *__restrict__ p, int64_t m) {
+// zero the finest grid (blocks [0, nfine / 256)) and the counters (last block)
+__global__ void k_zero_grid(int32_t *__restrict__ fine, int64_t nfine, unsigned long long *__restrict__ acc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) p[i] = 0;
+    if (i < nfine) fine[i] = 0;
+    else if (i - nfine < 9 * FL) acc[i - nfine] = 0ull;
 }
 
 __device__ inline int cell_coord(double v, double lo, double s) {
@@ -129,70 +132,108 @@ __device__ inline int cell_coord(double v, double lo, double s) {
     return (int)t;
 }
 
-// counts of the finest grid
-__global__ void k_cells(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
+// counts of the finest grid over the sample (every stride-th point)
+__global__ void k_cells(const double *__restrict__ x, const double *__restrict__ y, int64_t ns, int64_t stride,
                         const double *__restrict__ box, int32_t *__restrict__ cnt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ns) return;
+    const int64_t i = j * stride;
     const int ix = cell_coord(x[i] + 0.0, box[0], box[4]);
     const int iy = cell_coord(y[i] + 0.0, box[2], box[5]);
     atomicAdd(&cnt[((int64_t)iy << FL) + ix], 1);
 }
 
-// level lc from level lc + 1 (2 x 2 sums)
-__global__ void k_pool(const int32_t *__restrict__ fine, int lc, int32_t *__restrict__ coarse) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t side = int64_t(1) << lc;
-    if (c >= side * side) return;
-    const int64_t cy = c >> lc, cx = c & (side - 1);
-    const int lf = lc + 1;
-    const int64_t r0 = (2 * cy) << lf, r1 = (2 * cy + 1) << lf;
-    coarse[c] = fine[r0 + 2 * cx] + fine[r0 + 2 * cx + 1] + fine[r1 + 2 * cx] + fine[r1 + 2 * cx + 1];
-}
-
-// acc[9 (l - 1) + 0]: occupied cells of level l; acc[9 (l - 1) + 1 + k]:
-// points in cells of density class k.
-__global__ void __launch_bounds__(BT) k_feat_hist(const int32_t *__restrict__ cnt, int64_t n,
-                                                  unsigned long long *__restrict__ acc) {
-    __shared__ unsigned long long sh[9 * FL];
-    for (int k = threadIdx.x; k < 9 * FL; k += BT) sh[k] = 0ull;
-    __syncthreads();
-    const int64_t total = cell_off(FL + 1);
-    for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < total; e += (int64_t)gridDim.x * BT) {
-        int l = 1;
-        while (cell_off(l + 1) <= e) ++l;
-        const int32_t cval = cnt[e];
-        if (cval > 0) {
-            // class: edges 2^(j-4), j = 1..7, compared exactly as
-            // count 4^l 16 >= N 2^j
-            const int64_t lhs = (int64_t)cval << (2 * l + 4);
-            int k = 0;
+// occupied count and density class of one cell of level l into sh (the
+// level's 9 counters): class = number of edges 2^(j-4), j = 1..7, with
+// count 4^l / ns >= edge, compared exactly as count 4^l 16 >= ns 2^j
+__device__ inline void hist_cell(int32_t c, int l, int64_t ns, unsigned long long *sh) {
+    if (c <= 0) return;
+    const int64_t lhs = (int64_t)c << (2 * l + 4);
+    int k = 0;
 #pragma unroll
-            for (int j = 1; j <= 7; ++j) k += lhs >= (n << j) ? 1 : 0;
-            atomicAdd(&sh[9 * (l - 1)], 1ull);
-            atomicAdd(&sh[9 * (l - 1) + 1 + k], (unsigned long long)cval);
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < 9 * FL; k += BT)
-        if (sh[k]) atomicAdd(&acc[k], sh[k]);
+    for (int j = 1; j <= 7; ++j) k += lhs >= (ns << j) ? 1 : 0;
+    atomicAdd(&sh[0], 1ull);
+    atomicAdd(&sh[1 + k], (unsigned long long)c);
 }
 
-// features from the counters; the standardised network input when a blob is
-// given (x = (f - mean) * scale)
-__global__ void k_feat_final(const unsigned long long *__restrict__ acc, int64_t n, double tol,
-                             float *__restrict__ feat, const float *__restrict__ blob, float *__restrict__ xin) {
-    const int k = threadIdx.x;
-    if (k >= NFEAT) return;
-    double f;
-    if (k == 0) f = log10((double)n);
-    else if (k == 1) f = log10(tol);
-    else {
-        const int l = (k - 2) / 9 + 1, j = (k - 2) % 9;
-        f = j == 0 ? (double)acc[k - 2] / (double)(int64_t(1) << (2 * l)) : (double)acc[k - 2] / (double)n;
+// One block per 32 x 32 tile of the finest grid: the histograms of levels
+// 10..5 of the tile's cells, pooling 2 x 2 in LDS; the tile's level-5 count
+// goes to cnt5 (a 32 x 32 grid) and the counters to acc.
+__global__ void __launch_bounds__(BT) k_pool_hist_hi(const int32_t *__restrict__ fine, int64_t ns,
+                                                     unsigned long long *__restrict__ acc, int32_t *__restrict__ cnt5) {
+    __shared__ int32_t ga[1024], gb[256];
+    __shared__ unsigned long long sh[9 * 6];
+    const int t = threadIdx.x;
+    const int tx = blockIdx.x % 32, ty = blockIdx.x / 32;
+    if (t < 9 * 6) sh[t] = 0ull;
+    for (int k = t; k < 1024; k += BT) ga[k] = fine[((int64_t)(ty * 32 + k / 32) << FL) + tx * 32 + k % 32];
+    __syncthreads();
+    int32_t *cur = ga, *nxt = gb;
+    int side = 32;
+    for (int l = FL; l >= 5; --l) {
+        for (int k = t; k < side * side; k += BT) hist_cell(cur[k], l, ns, sh + 9 * (FL - l));
+        if (l > 5) {
+            const int h = side / 2;
+            for (int k = t; k < h * h; k += BT) {
+                const int i = k % h, j = k / h;
+                nxt[k] = cur[2 * j * side + 2 * i] + cur[2 * j * side + 2 * i + 1] + cur[(2 * j + 1) * side + 2 * i] +
+                         cur[(2 * j + 1) * side + 2 * i + 1];
+            }
+            side = h;
+            int32_t *tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+        } else if (t == 0) {
+            cnt5[ty * 32 + tx] = cur[0];
+        }
+        __syncthreads();
     }
-    feat[k] = (float)f;
-    if (blob) xin[k] = ((float)f - blob[k]) * blob[NFEAT + k];
+    if (t < 9 * 6) {
+        const int l = FL - t / 9, j = t % 9;
+        if (sh[t]) atomicAdd(&acc[9 * (l - 1) + j], sh[t]);
+    }
+}
+
+// One block: levels 4..1 from the level-5 grid, then the features (and the
+// standardised network input x = (f - mean) * scale when a blob is given).
+__global__ void __launch_bounds__(BT) k_pool_hist_lo(const int32_t *__restrict__ cnt5, int64_t n, int64_t ns,
+                                                     double tol, const unsigned long long *__restrict__ acc,
+                                                     float *__restrict__ feat, const float *__restrict__ blob,
+                                                     float *__restrict__ xin) {
+    __shared__ int32_t ga[1024], gb[256];
+    __shared__ unsigned long long sh[9 * 4];
+    const int t = threadIdx.x;
+    if (t < 9 * 4) sh[t] = 0ull;
+    for (int k = t; k < 1024; k += BT) ga[k] = cnt5[k];
+    __syncthreads();
+    int32_t *cur = ga, *nxt = gb;
+    int side = 32;
+    for (int l = 4; l >= 1; --l) {
+        const int h = side / 2;
+        for (int k = t; k < h * h; k += BT) {
+            const int i = k % h, j = k / h;
+            nxt[k] = cur[2 * j * side + 2 * i] + cur[2 * j * side + 2 * i + 1] + cur[(2 * j + 1) * side + 2 * i] +
+                     cur[(2 * j + 1) * side + 2 * i + 1];
+        }
+        __syncthreads();
+        for (int k = t; k < h * h; k += BT) hist_cell(nxt[k], l, ns, sh + 9 * (l - 1));
+        side = h;
+        int32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        __syncthreads();
+    }
+    if (t >= NFEAT) return;
+    double f;
+    if (t == 0) f = log10((double)n);
+    else if (t == 1) f = log10(tol);
+    else {
+        const int l = (t - 2) / 9 + 1, j = (t - 2) % 9;
+        const unsigned long long v = l <= 4 ? sh[9 * (l - 1) + j] : acc[t - 2];
+        f = j == 0 ? (double)v / (double)(int64_t(1) << (2 * l)) : (double)v / (double)ns;
+    }
+    feat[t] = (float)f;
+    if (blob) xin[t] = ((float)f - blob[t]) * blob[NFEAT + t];
 }
 
 // the a-priori rule
@@ -259,27 +300,24 @@ hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64
                            const float *blob, float *xin, double **box_out) {
     Scratch &s = c->scr;
     const int nblk = (int)std::min<int64_t>((n + BT - 1) / BT, 1024);
-    const int64_t ncell = cell_off(FL + 1);
+    const int64_t nfine = int64_t(1) << (2 * FL);
+    const int64_t stride = n > SAMPLE_MAX ? (n + SAMPLE_MAX - 1) / SAMPLE_MAX : 1;
+    const int64_t ns = (n + stride - 1) / stride;
     const size_t bytes = sizeof(double) * (5 * (size_t)nblk + 8) + sizeof(unsigned long long) * 9 * FL +
-                         sizeof(int32_t) * (size_t)ncell + 256;
+                         sizeof(int32_t) * (size_t)(nfine + 1024) + 256;
     FMM2D_TRY(s.sel.ensure(bytes));
     char *base = s.sel.as<char>();
     double *part = reinterpret_cast<double *>(base);
     double *box = part + 5 * (size_t)nblk;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(box + 8);
-    int32_t *cnt = reinterpret_cast<int32_t *>(acc + 9 * FL);
+    int32_t *fine = reinterpret_cast<int32_t *>(acc + 9 * FL);
+    int32_t *cnt5 = fine + nfine;
     hipLaunchKernelGGL(k_bbox_part, dim3(nblk), dim3(BT), 0, c->stream, x, y, n, part);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BT), 0, c->stream, part, nblk, box);
-    const int64_t nfine = int64_t(1) << (2 * FL);
-    int32_t *fine = cnt + cell_off(FL);
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nfine, 256)), dim3(256), 0, c->stream, fine, nfine);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, c->stream, reinterpret_cast<int32_t *>(acc), 2 * 9 * FL);
-    hipLaunchKernelGGL(k_cells, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, x, y, n, box, fine);
-    for (int l = FL - 1; l >= 1; --l)
-        hipLaunchKernelGGL(k_pool, dim3(grid_for(int64_t(1) << (2 * l), 256)), dim3(256), 0, c->stream,
-                           cnt + cell_off(l + 1), l, cnt + cell_off(l));
-    hipLaunchKernelGGL(k_feat_hist, dim3(grid_for(ncell, BT * 8)), dim3(BT), 0, c->stream, cnt, n, acc);
-    hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(128), 0, c->stream, acc, n, tol, feat, blob, xin);
+    hipLaunchKernelGGL(k_zero_grid, dim3(grid_for(nfine + 9 * FL, 256)), dim3(256), 0, c->stream, fine, nfine, acc);
+    hipLaunchKernelGGL(k_cells, dim3(grid_for(ns, 256)), dim3(256), 0, c->stream, x, y, ns, stride, box, fine);
+    hipLaunchKernelGGL(k_pool_hist_hi, dim3(1024), dim3(BT), 0, c->stream, fine, ns, acc, cnt5);
+    hipLaunchKernelGGL(k_pool_hist_lo, dim3(1), dim3(BT), 0, c->stream, cnt5, n, ns, tol, acc, feat, blob, xin);
     if (box_out) *box_out = box;
     return hipGetLastError();
 }

@@ -50,6 +50,7 @@ def _layouts():
     return {
         "uniform_10k": W.uniform_10k(),
         "mixed_1m_scaled_50k": W.mixed_1m(scale=0.05),
+        "mixed_1m_scaled_400k": W.mixed_1m(scale=0.4),  # above 2^18: sampled cell counts
         "clustered_scaled_30k": W.clustered_10m(scale=0.003),
         "grid_64x64": W.PointSet("grid", X.ravel().copy(), Y.ravel().copy(), np.ones(4096)),
         "coincident_100": W.PointSet("coincident", np.full(100, 0.25), np.full(100, -3.0), np.ones(100)),
@@ -204,3 +205,24 @@ def test_mlp_training_reduces_loss(fmm):
         fmm.mlp_adam(tp, tm, tv, g, step=step, lr=3e-3)
     _, l1 = fmm.mlp_grad(tp, Xd, Yd)
     assert float(l1.cpu()) < 0.1 * l0
+
+
+def test_shipped_weights_decode_like_the_oracle(fmm):
+    # the trained blob that ships with the package: right size, the network
+    # decides inside its range, and the decision equals the oracle's decoding
+    # of the network's own outputs
+    from paper_1006_2269_amd import selector
+
+    blob = selector.load_weights()
+    assert blob is not None and blob.size == S.HEADER + fmm.mlp_nparams(S.NFEAT)
+    assert np.all(np.isfinite(blob))
+    ps = LAYOUTS["mixed_1m_scaled_50k"]
+    x, y = _dev(ps.x), _dev(ps.y)
+    for tol in (1e-4, 1e-6):
+        L, p, th, net = fmm.select(x, y, tol, _dev(blob))
+        feat = fmm.features(x, y, tol).cpu().numpy()
+        xin = (feat - blob[:S.NFEAT]) * blob[S.NFEAT:2 * S.NFEAT]
+        out = fmm.mlp_forward(_dev(blob[S.HEADER:]), _dev(xin[None, :])).cpu().numpy()[0]
+        assert net is True
+        assert (L, p, th, net) == S.decide(out, blob, ps.n, tol)
+        assert 1 <= L <= S.levels_max(ps.n) and 1 <= p <= 63 and th in S.THETAS

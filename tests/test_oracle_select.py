@@ -10,10 +10,11 @@ from paper_1006_2269_amd import workloads as W
 
 
 def brute_features(x, y, tol):
-    """Point-by-point loops over the definition (small inputs only)."""
-    n = len(x)
+    """Point-by-point loops over the definition (small or sampled inputs)."""
+    n_all = len(x)
     xs = [float(v) + 0.0 for v in x]
     ys = [float(v) + 0.0 for v in y]
+    stride = -(-n_all // 2 ** 18) if n_all > 2 ** 18 else 1
 
     def cell(v, lo, hi):
         ext = hi - lo
@@ -25,9 +26,10 @@ def brute_features(x, y, tol):
             t = 1023.0
         return int(t)
 
-    xl, xh, yl, yh = min(xs), max(xs), min(ys), max(ys)
-    fine = [(cell(a, xl, xh), cell(b, yl, yh)) for a, b in zip(xs, ys)]
-    out = [math.log10(n), math.log10(tol)]
+    xl, xh, yl, yh = min(xs), max(xs), min(ys), max(ys)   # box of all points
+    fine = [(cell(xs[i], xl, xh), cell(ys[i], yl, yh)) for i in range(0, n_all, stride)]
+    n = len(fine)
+    out = [math.log10(n_all), math.log10(tol)]
     for l in range(1, 11):
         counts = {}
         for cx, cy in fine:
@@ -51,6 +53,14 @@ def test_features_match_brute_force(seed):
     b = brute_features(ps.x, ps.y, 1e-6)
     assert f.shape == (S.NFEAT,)
     np.testing.assert_array_equal(f, b)
+
+
+@pytest.mark.slow
+def test_features_sampled_match_brute_force():
+    # above 2^18 points the cells are counted over every ceil(n / 2^18)-th point
+    ps = W.random_mixture(300_000, 4)
+    assert S.sample_stride(ps.n) == 2
+    np.testing.assert_array_equal(S.features(ps.x, ps.y, 1e-5), brute_features(ps.x, ps.y, 1e-5))
 
 
 def test_features_regular_grid_closed_form():
