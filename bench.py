@@ -42,6 +42,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mixed_1m.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when there is none or the
+    kernel's source file has changed since the counters were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        entry = json.load(fh).get(kernel)
+    if not entry:
+        return None
+    with open(os.path.join(ROOT, entry["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != entry["source_sha256"]:
+            return None
+    return entry["bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +252,9 @@ def main():
                     "launch_ms": round(near_ms, 4)}
         log("[bench] near kernel %.4f ms (%.3e pairs/s), finest M2L kernel %.4f ms (%.3e weak pairs/s)"
             % (near_ms, pairs / (near_ms * 1e-3), m2l_ms, weak_top / (m2l_ms * 1e-3)))
+
+    if roof is not None:
+        roof["traffic"] = measured_traffic(roof["kernel"])
 
     cpu = None
     if args.cpu_baseline:
