@@ -26,16 +26,31 @@ constexpr int LW = 4;  // wavefronts (boxes) per block
 
 // pool_state layout: [0, L+2): S pool offsets, [L+2, 2L+4): W pool offsets,
 // [2L+4]: overflow flag.
-__device__ inline bool theta_separated(double theta, double4 gb, double4 gc) {
+// Criterion 2.1, R + theta r <= theta d, evaluated exactly as written
+// (binary64, no contraction, correctly rounded sqrt).  Most candidates are
+// decided without the square root: with L = R + theta r and s = d^2 as
+// computed, L^2 and theta^2 s differ from L^2 and (theta d)^2 of the exact
+// expression by a few units of the last place, so when they differ by more
+// than a relative 1e-14 the exact comparison cannot come out differently;
+// the narrow band in between, and magnitudes near the underflow range, take
+// the exact path.
+__device__ inline bool theta_separated(double theta, double theta2, double4 gb, double4 gc) {
 #pragma clang fp contract(off)
     const double dx = gb.x - gc.x;
     const double dy = gb.y - gc.y;
     const double dx2 = dx * dx;
     const double dy2 = dy * dy;
-    const double d = sqrt(dx2 + dy2);
+    const double s = dx2 + dy2;
     const double R = gb.z > gc.z ? gb.z : gc.z;
     const double r = gb.z > gc.z ? gc.z : gb.z;
     const double lhs = R + theta * r;
+    const double L2 = lhs * lhs;
+    const double S2 = theta2 * s;
+    if (s >= 0x1p-900 && L2 >= 0x1p-900) {
+        if (L2 <= S2 * (1.0 - 1e-14)) return true;
+        if (L2 >= S2 * (1.0 + 1e-14)) return false;
+    }
+    const double d = sqrt(s);
     const double rhs = theta * d;
     // balls must be disjoint: two zero-size boxes at one point (d = 0) never are
     return lhs <= rhs && rhs > 0.0;
@@ -123,7 +138,7 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
             bool weak = false;
             if (ok) {
                 cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
-                weak = theta_separated(theta, gb, geomL[cbox]);
+                weak = theta_separated(theta, theta * theta, gb, geomL[cbox]);
             }
             mw = __ballot(ok && weak);
             if (lane == 0) bw[base >> 6] = mw;
