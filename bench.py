@@ -215,8 +215,8 @@ def main():
 
     main_form = results.get("fp32_acc64")
     # roofline of the dominant single kernel launch of the reduced form: the
-    # near-field kernel, or the finest level's M2L kernel (both timed alone
-    # with HIP events on the library's stream during the timed steps)
+    # near-field kernel, or the M2L kernel (all levels; both timed alone with
+    # HIP events on the library's stream during the timed steps)
     roof = None
     if main_form:
         p = main_form["p"]
@@ -225,7 +225,7 @@ def main():
         f.connectivity(main_form["theta"])
         ph = main_form["phases"]
         near_ms = ph["near_kernel"][0] / max(ph["near_kernel"][1], 1)
-        m2l_ms = ph["m2l_finest"][0] / max(ph["m2l_finest"][1], 1)
+        m2l_ms = ph["m2l_kernel"][0] / max(ph["m2l_kernel"][1], 1)
         sptr, sidx, _, _ = f.lists(Lm)
         st = f.leaf_start().cpu().numpy().astype(np.int64)
         cnt = np.diff(st)
@@ -234,24 +234,24 @@ def main():
         src_per_leaf = np.add.reduceat(cnt[si], sp[:-1]) if si.size else np.zeros_like(cnt)
         src_per_leaf[np.diff(sp) == 0] = 0
         pairs = float((cnt * src_per_leaf).sum())
-        weak_top = float(f.list_sizes(Lm)[1])
+        weak_all = float(sum(f.list_sizes(l)[1] for l in range(Lm + 1)))
         flop_pair = 8.0   # 2 sub, mul, fma (2), log2, fma (2) per FP32 pair interaction
         near_flops = pairs * flop_pair
-        m2l_flops = weak_top * 4.0 * (p + 1) ** 2               # useful product flops per weak pair
+        m2l_flops = weak_all * 4.0 * (p + 1) ** 2               # useful product flops per weak pair
         if m2l_ms >= near_ms:
             ach = m2l_flops / (m2l_ms * 1e-3) / 1e12
-            roof = {"kernel": "k_m2l_lp (M2L, finest level, one launch)", "bound": "mfma", "achieved": round(ach, 3),
+            roof = {"kernel": "k_m2l_lp (M2L, all levels, one launch)", "bound": "mfma", "achieved": round(ach, 3),
                     "peak": MI355X["fp32_mfma_TFLOPs"], "unit": "TFLOP/s",
                     "frac": round(ach / MI355X["fp32_mfma_TFLOPs"], 5), "traffic": None,
-                    "work": "%d weak pairs x 4(p+1)^2 flops" % weak_top, "launch_ms": round(m2l_ms, 4)}
+                    "work": "%d weak pairs x 4(p+1)^2 flops" % weak_all, "launch_ms": round(m2l_ms, 4)}
         else:
             ach = near_flops / (near_ms * 1e-3) / 1e12
             roof = {"kernel": "k_near32 (near field, one launch)", "bound": "alu", "achieved": round(ach, 3),
                     "peak": MI355X["fp32_TFLOPs"], "unit": "TFLOP/s", "frac": round(ach / MI355X["fp32_TFLOPs"], 5),
                     "traffic": None, "work": "%d pairs x %g flops" % (pairs, flop_pair),
                     "launch_ms": round(near_ms, 4)}
-        log("[bench] near kernel %.4f ms (%.3e pairs/s), finest M2L kernel %.4f ms (%.3e weak pairs/s)"
-            % (near_ms, pairs / (near_ms * 1e-3), m2l_ms, weak_top / (m2l_ms * 1e-3)))
+        log("[bench] near kernel %.4f ms (%.3e pairs/s), M2L kernel %.4f ms (%.3e weak pairs/s)"
+            % (near_ms, pairs / (near_ms * 1e-3), m2l_ms, weak_all / (m2l_ms * 1e-3)))
 
     if roof is not None:
         roof["traffic"] = measured_traffic(roof["kernel"])

@@ -221,14 +221,14 @@ int fmm2d_get_lists(fmm2d_ctx *ctx, int level, int32_t *sptr, int32_t *sidx,
 #define FMM2D_PHASE_LISTS   1  /* connectivity                                */
 #define FMM2D_PHASE_UPWARD  2  /* P2M and M2M                                 */
 #define FMM2D_PHASE_M2L     3  /* M2L along the weak lists (all levels)       */
-#define FMM2D_PHASE_L2L     4  /* L2L                                         */
+#define FMM2D_PHASE_L2L     4  /* L2L, with the M2L sums added into B         */
 #define FMM2D_PHASE_LEAF    5  /* L2P plus the near field (one launch)        */
 #define FMM2D_PHASE_OTHER   6  /* charge gather, scatter to input order       */
 #define FMM2D_PHASE_JUDGE   7  /* fmm2d_direct                                */
 #define FMM2D_PHASE_SELECT  8  /* parameter selection                         */
 /* Single kernel launches, also counted in their phase above:                 */
 #define FMM2D_PHASE_NEAR_KERNEL  9  /* the near-field kernel (in LEAF)       */
-#define FMM2D_PHASE_M2L_FINEST  10  /* the finest level's M2L kernel (in M2L) */
+#define FMM2D_PHASE_M2L_KERNEL  10  /* the M2L kernel, all levels (in M2L)   */
 #define FMM2D_NPHASE       11
 
 /* enable = 1 clears the accumulated timings and starts recording HIP events

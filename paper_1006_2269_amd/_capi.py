@@ -57,7 +57,7 @@ NFEAT = 92
 SELECT_HEADER = 194
 
 PHASES = ["tree", "lists", "upward", "m2l", "l2l", "leaf", "other", "judge", "select", "near_kernel",
-          "m2l_finest"]
+          "m2l_kernel"]
 
 
 def load():

@@ -86,7 +86,8 @@ int fmm2d_destroy(fmm2d_ctx *c) {
                           &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d})
             b->release();
         EvalState &e = c->ev;
-        for (Schedule &sc : c->tree.m2l_seg) { sc.segoff.release(); sc.table.release(); }
+        c->tree.m2l_all.segoff.release();
+        c->tree.m2l_all.table.release();
         c->tree.near_seg.segoff.release();
         c->tree.near_seg.table.release();
         for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();

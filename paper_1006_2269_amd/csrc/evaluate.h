@@ -9,8 +9,9 @@ namespace fmm2d {
 hipError_t ensure_binomials(fmm2d_ctx *c);
 // constant M2L matrix (m2l.hip)
 hipError_t ensure_mhat(fmm2d_ctx *c);
-// M2L of level l along its weak lists, in precision `mode` (m2l.hip).
-hipError_t m2l_level(fmm2d_ctx *c, int l, int p, int mode);
+// M2L of all levels along their weak lists, in precision `mode`, into the
+// segment partial sums ev.part that the L2L pass adds into B (m2l.hip).
+hipError_t m2l_all(fmm2d_ctx *c, int p, int mode);
 // L2P plus the near field at the leaves in precision `mode`; writes the
 // leaf-ordered potentials to ev.phi_leaf (near.hip).
 hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode);

@@ -120,8 +120,12 @@ __global__ void __launch_bounds__(64) k_m2m(int l, int p, const double4 *__restr
 }
 
 // ---- L2L: one wavefront per child box, lane l = coefficient ----------------
+// B(child) = the parent's local expansion re-centred at the child, plus the
+// child's M2L segment sums (segments of global box g are
+// [segoff[g], segoff[g + 1]) in part), added in segment order.
 __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restrict__ geom, cd *__restrict__ B,
-                                            const double *__restrict__ binom) {
+                                            const double *__restrict__ binom, const int32_t *__restrict__ segoff,
+                                            const cd *__restrict__ part) {
     __shared__ cd Bp[64];
     __shared__ cd dp[64];
     const int64_t cidx = blockIdx.x;  // child within level l+1
@@ -139,7 +143,14 @@ __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restr
     if (lane <= p) {
         cd t{0.0, 0.0};
         for (int k = lane; k <= p; ++k) t = cadd(t, cscale(cmul(Bp[k], dp[k - lane]), binom[k * BN + lane]));
-        B[cbox * (p + 1) + lane] = cscale(t, tpow);
+        cd v = cscale(t, tpow);
+        const int32_t s0 = segoff[cbox], s1 = segoff[cbox + 1];
+        if (s1 > s0) {
+            cd acc{0.0, 0.0};
+            for (int32_t sg = s0; sg < s1; ++sg) acc = cadd(acc, part[(int64_t)sg * (p + 1) + lane]);
+            v = cadd(v, acc);
+        }
+        B[cbox * (p + 1) + lane] = v;
     }
 }
 
@@ -214,7 +225,8 @@ hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     hipLaunchKernelGGL(k_l2l, dim3((unsigned)(int64_t(1) << (2 * (l + 1)))), dim3(64), 0, c->stream, l, p,
-                       t.geom.as<double4>(), e.B.as<cd>(), e.binom.as<double>());
+                       t.geom.as<double4>(), e.B.as<cd>(), e.binom.as<double>(), t.m2l_all.segoff.as<int32_t>(),
+                       e.part.as<cd>());
     return hipGetLastError();
 }
 
@@ -239,15 +251,14 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
         PhaseScope ps(c, PH_UPWARD);
         FMM2D_TRY(upward_pass(c, p));
     }
-    for (int l = 0; l <= L; ++l) {
-        if (l >= 1) {
-            PhaseScope ps(c, PH_M2L);
-            FMM2D_TRY(m2l_level(c, l, p, mode));
-        }
-        if (l < L) {
-            PhaseScope ps(c, PH_L2L);
-            FMM2D_TRY(l2l_level(c, l, p));
-        }
+    {
+        PhaseScope ps(c, PH_M2L);
+        FMM2D_TRY(m2l_all(c, p, mode));  // every level at once, into segment sums
+    }
+    FMM2D_TRY(e.part.ensure(sizeof(cd)));  // a valid pointer also when there is no weak pair
+    for (int l = 0; l < L; ++l) {
+        PhaseScope ps(c, PH_L2L);
+        FMM2D_TRY(l2l_level(c, l, p));  // parent's expansion plus the level's M2L sums
     }
     {
         PhaseScope ps(c, PH_LEAF);

@@ -18,6 +18,12 @@ constexpr int WAVE = 64;
 __host__ __device__ inline int64_t level_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
 // Offset of level l in an array holding (4^m + 1) entries per level m.
 __host__ __device__ inline int64_t ptr_offset(int l) { return level_offset(l) + l; }
+// Level of global box id g (levels stored one after the other).
+__host__ __device__ inline int level_of(int64_t g) {
+    int l = 0;
+    while (level_offset(l + 1) <= g) ++l;
+    return l;
+}
 // Offset of depth d in an array holding (2^e + 1) entries per depth e.
 __host__ __device__ inline int64_t depth_offset(int d) { return ((int64_t(1) << d) - 1) + d; }
 
@@ -83,7 +89,7 @@ struct TreeState {
     DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
     DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range, FP32 centre offset, threshold
     bool nrec_valid = false;
-    std::vector<Schedule> m2l_seg;  // per level
+    Schedule m2l_all;               // weak lists of all levels (rows = global box ids)
     Schedule near_seg;              // finest-level strong lists
     std::vector<int64_t> s_off, w_off;  // host copy: pool offset of each level
     bool has_lists = false;
@@ -107,7 +113,7 @@ struct EvalState {
 // around each phase's launches while timing is enabled.
 enum Phase {
     PH_TREE = 0, PH_LISTS, PH_UPWARD, PH_M2L, PH_L2L, PH_LEAF, PH_OTHER, PH_JUDGE, PH_SELECT,
-    PH_NEAR_KERNEL, PH_M2L_FINEST,  // single launches inside PH_LEAF / PH_M2L
+    PH_NEAR_KERNEL, PH_M2L_KERNEL,  // single launches inside PH_LEAF / PH_M2L
     PH_COUNT
 };
 

@@ -11,8 +11,10 @@
 // u'_k = 2^k u_k, T'_l = 2^l rho_t^l, keeps every matrix entry below one.
 //
 // One wavefront per segment of a target box's weak list (at most M2L_SEG
-// pairs, so heavy-tailed lists do not serialise; a second kernel adds the
-// segments' sums into B in order) walks it in chunks of 16 pairs.
+// pairs, so heavy-tailed lists do not serialise; the L2L pass adds the
+// segments' sums into B in order).  The segments of all levels run in one
+// launch; each finds its level from its box's global id.  This kernel (p + 1
+// > 16) walks a segment in chunks of 16 pairs.
 // Four lanes per pair build that pair's power tables in binary64 (binary
 // exponentiation to the lane's first power, then successive products) into
 // LDS, while the next chunk's geometry and coefficients are being loaded.  The 16x16x4 matrix instruction multiplies a 16-row block (8 pairs x
@@ -112,10 +114,12 @@ __device__ inline void bf16_split(float x, short &hi, short &lo) {
 // B[4 (i / 16) + j][i % 16], j = 0..3; the accumulator layout is that of
 // the 16x16x4 FP32 instruction.
 template <int NT, typename G, typename ACC, bool BF3>
-__global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ geomL, const int32_t *__restrict__ wptr,
-                                            const int32_t *__restrict__ widx, const cd *__restrict__ AL,
-                                            const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
-                                            cd *__restrict__ part, const double *__restrict__ Mhat) {
+__global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ geom,
+                                            const int32_t *__restrict__ wptr_all,
+                                            const int32_t *__restrict__ widx_pool, const int64_t *__restrict__ woff,
+                                            const cd *__restrict__ A, const int2 *__restrict__ segtab,
+                                            const int32_t *__restrict__ nseg_ptr, cd *__restrict__ part,
+                                            const double *__restrict__ Mhat) {
     using MF = Mfma<G>;
     using V = typename MF::V;
     constexpr int KSMAX = 4 * NT;   // K steps when p + 1 = 16 NT
@@ -127,7 +131,13 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
     if (seg >= *nseg_ptr) return;  // the block is one wavefront: uniform exit
     const int lane = threadIdx.x;
     const int2 se = segtab[seg];
-    const int64_t b = se.x;
+    // the segment's level: its target box, lists and multipoles
+    const int lvl = level_of(se.x);
+    const int64_t b = se.x - level_offset(lvl);
+    const double4 *geomL = geom + level_offset(lvl);
+    const int32_t *wptr = wptr_all + ptr_offset(lvl);
+    const int32_t *widx = widx_pool + woff[lvl];
+    const cd *AL = A + level_offset(lvl) * (int64_t)(p + 1);
     const int32_t t0 = se.y;
     const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
     const int P1 = p + 1;
@@ -329,8 +339,9 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
 // segment a transposing butterfly reduction (each stage halves the values a
 // lane carries) sums the 64 lanes' accumulators in a fixed order.
 template <int P1, typename G, typename ACC, bool BF3>
-__global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geomL, const int32_t *__restrict__ wptr,
-                                               const int32_t *__restrict__ widx, const cd *__restrict__ AL,
+__global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom, const int32_t *__restrict__ wptr_all,
+                                               const int32_t *__restrict__ widx_pool,
+                                               const int64_t *__restrict__ woff, const cd *__restrict__ A,
                                                const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
                                                cd *__restrict__ part, const double *__restrict__ Mhat) {
     static_assert(P1 >= 1 && P1 <= 16, "one 16-wide coefficient tile");
@@ -346,7 +357,13 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geomL
     if (seg >= *nseg_ptr) return;  // the block is one wavefront: uniform exit
     const int lane = threadIdx.x;
     const int2 se = segtab[seg];
-    const int64_t b = se.x;
+    // the segment's level: its target box, lists and multipoles
+    const int lvl = level_of(se.x);
+    const int64_t b = se.x - level_offset(lvl);
+    const double4 *geomL = geom + level_offset(lvl);
+    const int32_t *wptr = wptr_all + ptr_offset(lvl);
+    const int32_t *widx = widx_pool + woff[lvl];
+    const cd *AL = A + level_offset(lvl) * (int64_t)P1;
     const int32_t t0 = se.y;
     const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
     const int row = lane % 16, g = lane / 16;
@@ -476,36 +493,21 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geomL
 }
 
 template <int P1>
-void launch_m2l_lp(fmm2d_ctx *c, int mode, dim3 grid, const double4 *gL, const int32_t *wp, const int32_t *wi,
-                   const cd *AL, const int2 *tab, const int32_t *nsp, cd *part, const double *Mh) {
+void launch_m2l_lp(fmm2d_ctx *c, int mode, dim3 grid, const double4 *geom, const int32_t *wp, const int32_t *wi,
+                   const int64_t *woff, const cd *A, const int2 *tab, const int32_t *nsp, cd *part, const double *Mh) {
     const dim3 block(64);
     if (mode == FMM2D_MODE_FP64)
-        hipLaunchKernelGGL((k_m2l_lp<P1, double, double, false>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
+        hipLaunchKernelGGL((k_m2l_lp<P1, double, double, false>), grid, block, 0, c->stream, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
     else if (mode == FMM2D_MODE_FP32_ACC64)
-        hipLaunchKernelGGL((k_m2l_lp<P1, float, double, false>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
+        hipLaunchKernelGGL((k_m2l_lp<P1, float, double, false>), grid, block, 0, c->stream, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
     else if (mode == FMM2D_MODE_BF16X3)
-        hipLaunchKernelGGL((k_m2l_lp<P1, float, float, true>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
+        hipLaunchKernelGGL((k_m2l_lp<P1, float, float, true>), grid, block, 0, c->stream, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
     else
-        hipLaunchKernelGGL((k_m2l_lp<P1, float, float, false>), grid, block, 0, c->stream, gL, wp, wi, AL, tab, nsp,
-                           part, Mh);
-}
-
-// B_l(b) += the segments' partial sums, in segment order.
-__global__ void k_m2l_reduce(int p, int64_t nb, const int32_t *__restrict__ segoff, const cd *__restrict__ part,
-                             cd *__restrict__ BL) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int P1 = p + 1;
-    if (e >= nb * P1) return;
-    const int64_t b = e / P1;
-    const int l = (int)(e - b * P1);
-    const int32_t s0 = segoff[b], s1 = segoff[b + 1];
-    if (s1 == s0) return;
-    cd acc{0.0, 0.0};
-    for (int32_t sg = s0; sg < s1; ++sg) acc = cadd(acc, part[(int64_t)sg * P1 + l]);
-    BL[e] = cadd(BL[e], acc);
+        hipLaunchKernelGGL((k_m2l_lp<P1, float, float, false>), grid, block, 0, c->stream, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
 }
 
 // M^ table in binary64: M^[l][k] = M_lk / 2^(l+k), 64 x 64.
@@ -518,52 +520,49 @@ __global__ void k_make_mhat(double *Mhat, const double *binom) {
     Mhat[l * 64 + k] = ldexp(m, -(l + k));
 }
 
+// M2L of every level in one launch (the segments of all levels' weak lists);
+// the partial sums are added into B by the L2L pass.
 template <int NT>
-hipError_t launch_m2l(fmm2d_ctx *c, int l, int p, int mode) {
+hipError_t launch_m2l_all(fmm2d_ctx *c, int p, int mode) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
-    const Schedule &sc = t.m2l_seg[l];
-    const int64_t nb = int64_t(1) << (2 * l);
-    const double4 *gL = t.geom.as<double4>() + level_offset(l);
-    const int32_t *wp = t.wptr.as<int32_t>() + ptr_offset(l);
-    const int32_t *wi = t.widx.as<int32_t>() + t.w_off[l];
-    const cd *AL = e.A.as<cd>() + level_offset(l) * (p + 1);
-    cd *BL = e.B.as<cd>() + level_offset(l) * (p + 1);
+    const Schedule &sc = t.m2l_all;
+    const int64_t nbox = level_offset(t.L + 1);
+    const double4 *geom = t.geom.as<double4>();
+    const int32_t *wp = t.wptr.as<int32_t>();
+    const int32_t *wi = t.widx.as<int32_t>();
+    const int64_t *woff = t.pool_state.as<int64_t>() + (t.L + 2);  // W pool offset of each level
+    const cd *A = e.A.as<cd>();
     const double *Mh = e.mhat.as<double>();
-    FMM2D_TRY(e.part.ensure(sizeof(cd) * sc.bound * (p + 1)));
+    FMM2D_TRY(e.part.ensure(sizeof(cd) * (sc.bound > 0 ? sc.bound : 1) * (p + 1)));
     cd *part = e.part.as<cd>();
     const int2 *tab = sc.table.as<int2>();
-    const int32_t *nsp = sc.segoff.as<int32_t>() + nb;
-    const dim3 grid((unsigned)sc.bound), block(64);
-    {
-        // the finest level's kernel alone is also timed as its own phase
-        PhaseScope kernel_scope(c, l == t.L ? (int)PH_M2L_FINEST : -1);
-        if (NT == 1) {
-            switch (p + 1) {
+    const int32_t *nsp = sc.segoff.as<int32_t>() + nbox;
+    const dim3 grid((unsigned)(sc.bound > 0 ? sc.bound : 1)), block(64);
+    PhaseScope kernel_scope(c, PH_M2L_KERNEL);  // the kernel alone
+    if (NT == 1) {
+        switch (p + 1) {
 #define FMM2D_M2L_LP(P1) \
-    case P1: launch_m2l_lp<P1>(c, mode, grid, gL, wp, wi, AL, tab, nsp, part, Mh); break;
-                FMM2D_M2L_LP(2) FMM2D_M2L_LP(3) FMM2D_M2L_LP(4) FMM2D_M2L_LP(5) FMM2D_M2L_LP(6) FMM2D_M2L_LP(7)
-                FMM2D_M2L_LP(8) FMM2D_M2L_LP(9) FMM2D_M2L_LP(10) FMM2D_M2L_LP(11) FMM2D_M2L_LP(12)
-                FMM2D_M2L_LP(13) FMM2D_M2L_LP(14) FMM2D_M2L_LP(15) FMM2D_M2L_LP(16)
+    case P1: launch_m2l_lp<P1>(c, mode, grid, geom, wp, wi, woff, A, tab, nsp, part, Mh); break;
+            FMM2D_M2L_LP(2) FMM2D_M2L_LP(3) FMM2D_M2L_LP(4) FMM2D_M2L_LP(5) FMM2D_M2L_LP(6) FMM2D_M2L_LP(7)
+            FMM2D_M2L_LP(8) FMM2D_M2L_LP(9) FMM2D_M2L_LP(10) FMM2D_M2L_LP(11) FMM2D_M2L_LP(12)
+            FMM2D_M2L_LP(13) FMM2D_M2L_LP(14) FMM2D_M2L_LP(15) FMM2D_M2L_LP(16)
 #undef FMM2D_M2L_LP
-                default: return hipErrorInvalidValue;
-            }
-        } else if (mode == FMM2D_MODE_FP64)
-            hipLaunchKernelGGL((k_m2l<NT, double, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                               part, Mh);
-        else if (mode == FMM2D_MODE_FP32_ACC64)
-            hipLaunchKernelGGL((k_m2l<NT, float, double, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                               part, Mh);
-        else if (mode == FMM2D_MODE_BF16X3)
-            hipLaunchKernelGGL((k_m2l<NT, float, float, true>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                               part, Mh);
-        else
-            hipLaunchKernelGGL((k_m2l<NT, float, float, false>), grid, block, 0, c->stream, p, gL, wp, wi, AL, tab, nsp,
-                               part, Mh);
+            default: return hipErrorInvalidValue;
+        }
+    } else if (mode == FMM2D_MODE_FP64) {
+        hipLaunchKernelGGL((k_m2l<NT, double, double, false>), grid, block, 0, c->stream, p, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
+    } else if (mode == FMM2D_MODE_FP32_ACC64) {
+        hipLaunchKernelGGL((k_m2l<NT, float, double, false>), grid, block, 0, c->stream, p, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
+    } else if (mode == FMM2D_MODE_BF16X3) {
+        hipLaunchKernelGGL((k_m2l<NT, float, float, true>), grid, block, 0, c->stream, p, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
+    } else {
+        hipLaunchKernelGGL((k_m2l<NT, float, float, false>), grid, block, 0, c->stream, p, geom, wp, wi, woff, A, tab,
+                           nsp, part, Mh);
     }
-    FMM2D_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_m2l_reduce, dim3(grid_for(nb * (p + 1), 256)), dim3(256), 0, c->stream, p, nb,
-                       sc.segoff.as<int32_t>(), part, BL);
     return hipGetLastError();
 }
 
@@ -580,15 +579,15 @@ hipError_t ensure_mhat(fmm2d_ctx *c) {
     return hipSuccess;
 }
 
-hipError_t m2l_level(fmm2d_ctx *c, int l, int p, int mode) {
+hipError_t m2l_all(fmm2d_ctx *c, int p, int mode) {
     TreeState &t = c->tree;
-    if (t.w_off[l + 1] == t.w_off[l]) return hipSuccess;
+    if (t.L < 1 || t.w_off[t.L + 1] == t.w_off[1]) return hipSuccess;  // no weak pairs
     const int nt = (p + 1 + 15) / 16;
     switch (nt) {
-        case 1: return launch_m2l<1>(c, l, p, mode);
-        case 2: return launch_m2l<2>(c, l, p, mode);
-        case 3: return launch_m2l<3>(c, l, p, mode);
-        default: return launch_m2l<4>(c, l, p, mode);
+        case 1: return launch_m2l_all<1>(c, p, mode);
+        case 2: return launch_m2l_all<2>(c, p, mode);
+        case 3: return launch_m2l_all<3>(c, p, mode);
+        default: return launch_m2l_all<4>(c, p, mode);
     }
 }
 
