@@ -86,9 +86,69 @@ __device__ inline int64_t bits_base(int64_t b, int32_t s0, int32_t s1) {
     return (cand >> 6) + b;
 }
 
-// Count pass (FILL = false): one wavefront per box tests its candidates,
-// stores the decisions (bit set: weak) and the two counts.  Fill pass: the
-// same candidates, the stored decisions, ballot compaction into the lists.
+// One wavefront, box b of level l (candidates: the four children of each box
+// of S_{l-1}(parent)).  Count pass (FILL = false): the theta test of every
+// candidate, the two counts, and (BITS) the decisions stored as bits (set:
+// weak).  Fill pass: the same candidates, their decisions (from the bits, or
+// the test again), ballot compaction into the lists; on the finest level
+// also the near-field record of each strong entry (source leaf's point
+// range; FP32 centre offset c_b - c_c and the coincidence threshold
+// (2^-20 of the magnitudes)^2 for the FP32 path).
+template <bool FILL, bool BITS>
+__device__ inline void box_lists(int l, int L, double theta, const double4 *__restrict__ geomL, int64_t b,
+                                 const int32_t *__restrict__ sptr_prev, const int32_t *__restrict__ sidx_prev,
+                                 uint64_t *__restrict__ bits, int32_t &cs, int32_t &cw, int32_t tS,
+                                 int32_t *__restrict__ so, int32_t *__restrict__ wo, const int32_t *__restrict__ stL,
+                                 int2 *__restrict__ recj, float4 *__restrict__ recd) {
+    const uint32_t lane = lane_id();
+    const int64_t P = b >> 2;
+    const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
+    const int32_t ncand = 4 * (s1 - s0);
+    uint64_t *bw = BITS ? bits + bits_base(b, s0, s1) : nullptr;
+    const bool records = FILL && l == L && recj != nullptr;
+    const bool test = !FILL || !BITS;
+    double4 gb;
+    if (test || records) gb = geomL[b];
+    cs = 0;
+    cw = 0;
+    for (int32_t base = 0; base < ncand; base += 64) {
+        const int32_t j = base + (int32_t)lane;
+        const bool ok = j < ncand;
+        int32_t cbox = 0;
+        if (ok) cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
+        uint64_t mw;
+        if (test) {
+            const bool weak = ok && theta_separated(theta, theta * theta, gb, geomL[cbox]);
+            mw = __ballot(weak);
+            if (BITS && !FILL && lane == 0) bw[base >> 6] = mw;
+        } else {
+            mw = bw[base >> 6];
+        }
+        const uint64_t okm = __ballot(ok);
+        const uint64_t ms = okm & ~mw;
+        if (FILL && ok) {
+            if ((mw >> lane) & 1) {
+                wo[cw + (int32_t)popc_below(mw)] = cbox;
+            } else {
+                const int32_t pos = cs + (int32_t)popc_below(ms);
+                so[pos] = cbox;
+                if (records) {
+                    const int32_t t = tS + pos;
+                    const double4 gc = geomL[cbox];
+                    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
+                    const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
+                    recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
+                    recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+                }
+            }
+        }
+        cw += (int32_t)__popcll(mw);
+        cs += (int32_t)__popcll(ms);
+    }
+}
+
+// One level, one wavefront per box.  The count pass stores the decisions as
+// bits, the fill pass replays them.
 template <bool FILL>
 __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double theta, const double4 *__restrict__ geomL,
                                                         const int32_t *__restrict__ sptr_prev,
@@ -110,63 +170,18 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
         return;
     }
     const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
-    const int64_t P = b >> 2;
-    const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
-    const int32_t ncand = 4 * (s1 - s0);
-    uint64_t *bw = bits + bits_base(b, s0, s1);
-    // finest level, fill pass: also the near-field record of each strong
-    // entry (source leaf's point range; FP32 centre offset c_b - c_c and the
-    // coincidence threshold (2^-20 of the magnitudes)^2 for the FP32 path)
-    const bool records = FILL && l == L && recj != nullptr;
-    double4 gb;
-    if (!FILL || records) gb = geomL[b];
-    int32_t cs = 0, cw = 0;
-    int32_t *so = nullptr, *wo = nullptr;
+    int32_t cs, cw;
     if (FILL) {
-        so = sidx_out + pool_state[l] + sptr_cur[b];
-        wo = widx_out + pool_state[(L + 2) + l] + wptr_cur[b];
-    }
-    for (int32_t base = 0; base < ncand; base += 64) {
-        const int32_t j = base + (int32_t)lane;
-        const bool ok = j < ncand;
-        int32_t cbox = 0;
-        uint64_t mw;
-        if (FILL) {
-            mw = bw[base >> 6];
-            if (ok) cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
-        } else {
-            bool weak = false;
-            if (ok) {
-                cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
-                weak = theta_separated(theta, theta * theta, gb, geomL[cbox]);
-            }
-            mw = __ballot(ok && weak);
-            if (lane == 0) bw[base >> 6] = mw;
+        box_lists<true, true>(l, L, theta, geomL, b, sptr_prev, sidx_prev, bits, cs, cw, sptr_cur[b],
+                              sidx_out + pool_state[l] + sptr_cur[b], widx_out + pool_state[(L + 2) + l] + wptr_cur[b],
+                              stL, recj, recd);
+    } else {
+        box_lists<false, true>(l, L, theta, geomL, b, sptr_prev, sidx_prev, bits, cs, cw, 0, nullptr, nullptr, stL,
+                               nullptr, nullptr);
+        if (lane == 0) {
+            ns[b] = cs;
+            nw[b] = cw;
         }
-        const uint64_t okm = __ballot(ok);
-        const uint64_t ms = okm & ~mw;
-        if (FILL && ok) {
-            if ((mw >> lane) & 1) {
-                wo[cw + (int32_t)popc_below(mw)] = cbox;
-            } else {
-                const int32_t pos = cs + (int32_t)popc_below(ms);
-                so[pos] = cbox;
-                if (records) {
-                    const int32_t t = sptr_cur[b] + pos;
-                    const double4 gc = geomL[cbox];
-                    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
-                    const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
-                    recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
-                    recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
-                }
-            }
-        }
-        cw += (int32_t)__popcll(mw);
-        cs += (int32_t)__popcll(ms);
-    }
-    if (!FILL && lane == 0) {
-        ns[b] = cs;
-        nw[b] = cw;
     }
 }
 
@@ -176,8 +191,8 @@ __global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double th
 // S or W), exceed the entry limit.  A flagged level is not examined, so no
 // int32 prefix sum can wrap and no decision bit lies beyond the buffer
 // (sized for cap_s + cap_w candidates).
-__global__ void k_lists_advance(int l, int L, int64_t nb, const int32_t *sptr_cur, const int32_t *wptr_cur,
-                                int64_t *pool_state, int64_t cap_s, int64_t cap_w, int64_t limit) {
+__device__ inline void advance_pools(int l, int L, int64_t nb, const int32_t *sptr_cur, const int32_t *wptr_cur,
+                                     int64_t *pool_state, int64_t cap_s, int64_t cap_w, int64_t limit) {
     if (pool_state[2 * L + 4]) return;
     const int64_t so = pool_state[l] + sptr_cur[nb];
     const int64_t wo = pool_state[(L + 2) + l] + wptr_cur[nb];
@@ -191,6 +206,85 @@ __global__ void k_lists_advance(int l, int L, int64_t nb, const int32_t *sptr_cu
         const int64_t cand = 16 * (int64_t)sptr_cur[nb];
         if (cand > limit) pool_state[2 * L + 4] = 2;
         else if (cand > (cap_s - so) + (cap_w - wo)) pool_state[2 * L + 4] = 1;
+    }
+}
+
+__global__ void k_lists_advance(int l, int L, int64_t nb, const int32_t *sptr_cur, const int32_t *wptr_cur,
+                                int64_t *pool_state, int64_t cap_s, int64_t cap_w, int64_t limit) {
+    advance_pools(l, L, nb, sptr_cur, wptr_cur, pool_state, cap_s, cap_w, limit);
+}
+
+// Levels 1..K (4^K <= SMALL_BOXES boxes each) in one workgroup, which saves
+// the launches of the coarse levels: the geometry of levels 0..K staged in
+// LDS, and per level a count pass over the boxes (one wavefront per box), the
+// two row-pointer scans in LDS, the pool offsets and checks, and a fill pass
+// that tests the candidates again (cheaper here than storing the decisions).
+constexpr int SMALL_THREADS = 1024;
+constexpr int SMALL_BOXES = 64;
+constexpr int SMALL_GEOM = 85;  // boxes of levels 0..3
+__global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, double theta,
+                                                              const double4 *__restrict__ geom,
+                                                              int32_t *__restrict__ sptr, int32_t *__restrict__ wptr,
+                                                              int32_t *__restrict__ sidx_pool,
+                                                              int32_t *__restrict__ widx_pool,
+                                                              int64_t *__restrict__ pool_state, int64_t cap_s,
+                                                              int64_t cap_w, int64_t limit,
+                                                              const int32_t *__restrict__ stL, int2 *__restrict__ recj,
+                                                              float4 *__restrict__ recd) {
+    __shared__ int32_t ns[SMALL_BOXES], nw[SMALL_BOXES];
+    __shared__ int32_t tmp[SMALL_THREADS / 64];
+    __shared__ int flag;
+    __shared__ double4 g_s[SMALL_GEOM];
+    const int t = threadIdx.x, wv = t / 64;
+    constexpr int NWV = SMALL_THREADS / 64;
+    if (t < level_offset(K + 1)) g_s[t] = geom[t];
+    for (int l = 1; l <= K; ++l) {
+        if (t == 0) flag = (int)pool_state[2 * L + 4];
+        __syncthreads();
+        if (flag) return;  // uniform: every thread read the same flag
+        const int64_t nb = int64_t(1) << (2 * l);
+        const double4 *gL = g_s + level_offset(l);
+        const int32_t *sp_prev = sptr + ptr_offset(l - 1);
+        int32_t *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
+        const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
+        for (int64_t b = wv; b < nb; b += NWV) {
+            int32_t cs, cw;
+            box_lists<false, false>(l, L, theta, gL, b, sp_prev, sidx_prev, nullptr, cs, cw, 0, nullptr, nullptr,
+                                    stL, nullptr, nullptr);
+            if (lane_id() == 0) {
+                ns[b] = cs;
+                nw[b] = cw;
+            }
+        }
+        __syncthreads();
+        int32_t tot_s, tot_w;
+        const int32_t vs = t < nb ? ns[t] : 0, vw = t < nb ? nw[t] : 0;
+        const int32_t es = block_excl_scan<SMALL_THREADS>(vs, tmp, tot_s);
+        const int32_t ew = block_excl_scan<SMALL_THREADS>(vw, tmp, tot_w);
+        if (t < nb) {
+            sp_cur[t] = es;
+            wp_cur[t] = ew;
+        }
+        if (t == 0) {
+            sp_cur[nb] = tot_s;
+            wp_cur[nb] = tot_w;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (t == 0) {
+            advance_pools(l, L, nb, sp_cur, wp_cur, pool_state, cap_s, cap_w, limit);
+            flag = (int)pool_state[2 * L + 4];
+        }
+        __syncthreads();
+        // a flagged level is not filled (the host discards or retries the lists)
+        if (flag) return;
+        const int64_t so0 = pool_state[l], wo0 = pool_state[(L + 2) + l];
+        for (int64_t b = wv; b < nb; b += NWV) {
+            int32_t cs, cw;
+            box_lists<true, false>(l, L, theta, gL, b, sp_prev, sidx_prev, nullptr, cs, cw, sp_cur[b],
+                                   sidx_pool + so0 + sp_cur[b], widx_pool + wo0 + wp_cur[b], stL, recj, recd);
+        }
+        __syncthreads();
     }
 }
 
@@ -227,7 +321,14 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L, stL,
                        geom, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
-    for (int l = 1; l <= L; ++l) {
+    // levels of at most 1024 boxes: one workgroup, one launch
+    int K = 0;
+    while (K < L && (int64_t(1) << (2 * (K + 1))) <= SMALL_BOXES) ++K;
+    if (K >= 1)
+        hipLaunchKernelGGL(k_lists_small, dim3(1), dim3(SMALL_THREADS), 0, c->stream, K, L, theta, geom, sptr, wptr,
+                           t.sidx.as<int32_t>(), t.widx.as<int32_t>(), ps, cap_s, cap_w, limit, stL,
+                           t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
+    for (int l = K + 1; l <= L; ++l) {
         const int64_t nb = int64_t(1) << (2 * l);
         int32_t *sp_prev = sptr + ptr_offset(l - 1), *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
         const double4 *gL = geom + level_offset(l);

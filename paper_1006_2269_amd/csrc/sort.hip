@@ -175,6 +175,11 @@ __global__ void __launch_bounds__(256) k_colscan(int32_t *__restrict__ hist, int
 // Stable rank within the tile, staged in LDS in digit order, then written out
 // as runs: element at LDS position s with digit d goes to
 // digit_base[d] + column_offset[d][tile] + (s - tile_digit_start[d]).
+// Each wavefront ranks its own 1024 consecutive keys (16 rounds of 64) with
+// private digit counters, so the rounds need no block barrier: within a
+// round, lanes of equal digit are ranked by ballot matching and the round's
+// leader advances the wave's counter.  The tile order (wave, round, lane) is
+// the input order, so the sort stays stable.
 __global__ void __launch_bounds__(SORT_THREADS) k_scatter(SortBufs B, int ping, int64_t n, int shift,
                                                           const int32_t *__restrict__ hist, int nblk,
                                                           const int32_t *__restrict__ tot) {
@@ -182,8 +187,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_scatter(SortBufs B, int ping, 
     __shared__ int32_t lv[SORT_TILE];
     __shared__ int32_t gpos[RADIX];    // global first position of this tile's digit d
     __shared__ int32_t lstart[RADIX];  // first LDS position of digit d
-    __shared__ int32_t running[RADIX];
-    __shared__ int32_t wcnt[NW][RADIX];
+    __shared__ int32_t wcnt[NW][RADIX];  // per-wave digit counts, then per-wave offsets
     __shared__ int32_t tmp[SORT_THREADS / 64];
     const int c = blockIdx.y;
     const uint64_t *kin = B.keys[c][ping];
@@ -191,18 +195,19 @@ __global__ void __launch_bounds__(SORT_THREADS) k_scatter(SortBufs B, int ping, 
     uint64_t *kout = B.keys[c][ping ^ 1];
     int32_t *vout = B.vals[c][ping ^ 1];
     const int t = threadIdx.x, w = t / WAVE;
+    const uint32_t lane = lane_id();
     // digit bases of this coordinate: exclusive scan of the 256 totals
     int32_t total;
     const int32_t dbase = block_excl_scan<SORT_THREADS>(tot[c * RADIX + t], tmp, total);
     gpos[t] = dbase + hist[((int64_t)c * RADIX + t) * nblk + blockIdx.x];
-    running[t] = 0;
     for (int k = 0; k < NW; ++k) wcnt[k][t] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * (SORT_ITEMS * WAVE);
     uint64_t kr[SORT_ITEMS];
     int32_t vr[SORT_ITEMS], rk[SORT_ITEMS];
+#pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
-        const int64_t i = base + (int64_t)r * SORT_THREADS + t;
+        const int64_t i = base + (int64_t)r * WAVE + lane;
         const bool ok = i < n;
         const uint64_t k = ok ? kin[i] : 0ull;
         kr[r] = k;
@@ -210,33 +215,28 @@ __global__ void __launch_bounds__(SORT_THREADS) k_scatter(SortBufs B, int ping, 
         const uint32_t d = (uint32_t)((k >> shift) & 0xff);
         const uint64_t valid = __ballot(ok);
         const uint64_t peers = match_digit(d, valid);
-        const int32_t rank = (int32_t)popc_below(peers);
-        if (ok && rank == 0) wcnt[w][d] = (int32_t)__popcll(peers);
-        __syncthreads();
-        int32_t off = -1;
-        if (ok) {
-            off = running[d] + rank;
-            for (int q = 0; q < w; ++q) off += wcnt[q][d];
-        }
-        rk[r] = off;  // rank of the element among the tile's digit-d elements
-        __syncthreads();
-        int32_t add = 0;
-        for (int q = 0; q < NW; ++q) {
-            add += wcnt[q][t];
-            wcnt[q][t] = 0;
-        }
-        running[t] += add;
-        __syncthreads();
+        const int32_t before = ok ? wcnt[w][d] : 0;  // read by every lane before the leader writes
+        rk[r] = ok ? before + (int32_t)popc_below(peers) : -1;
+        if (ok && popc_below(peers) == 0) wcnt[w][d] = before + (int32_t)__popcll(peers);
     }
-    // running[d] is now the tile's count of digit d
+    __syncthreads();
+    // per digit: wave offsets (exclusive over waves) and the tile's count
+    int32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int32_t v = wcnt[k][t];
+        wcnt[k][t] = cnt;
+        cnt += v;
+    }
     int32_t ntile;
-    const int32_t ls = block_excl_scan<SORT_THREADS>(running[t], tmp, ntile);
+    const int32_t ls = block_excl_scan<SORT_THREADS>(cnt, tmp, ntile);
     lstart[t] = ls;
     __syncthreads();
+#pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         if (rk[r] >= 0) {
             const uint32_t d = (uint32_t)((kr[r] >> shift) & 0xff);
-            const int32_t s = lstart[d] + rk[r];
+            const int32_t s = lstart[d] + wcnt[w][d] + rk[r];
             lk[s] = kr[r];
             lv[s] = vr[r];
         }
