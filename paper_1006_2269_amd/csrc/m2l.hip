@@ -330,14 +330,107 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
     }
 }
 
+// Cross-lane exchanges of 32-bit words for the transposing butterfly.
+// permlane32_swap exchanges lanes 32..63 of its first operand with lanes
+// 0..31 of its second; permlane16_swap the odd 16-lane rows of the first with
+// the even rows of the second.  DPP row_mirror pairs lane i with i ^ 15
+// within its row, row_half_mirror with i ^ 7 within its 8 lanes, and the quad
+// permutations with i ^ 2 and i ^ 1.
+template <int M>
+__device__ inline uint32_t dpp_partner(uint32_t v) {
+    constexpr int ctrl = M == 8 ? 0x140 : (M == 4 ? 0x141 : (M == 2 ? 0x4E : 0xB1));
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+}
+template <int M>
+__device__ inline float partner(float x) {
+    return __uint_as_float(dpp_partner<M>(__float_as_uint(x)));
+}
+template <int M>
+__device__ inline double partner(double x) {
+    return __hiloint2double((int)dpp_partner<M>((uint32_t)__double2hiint(x)),
+                            (int)dpp_partner<M>((uint32_t)__double2loint(x)));
+}
+template <int M>
+__device__ inline void swap_halves(uint32_t &x, uint32_t &y) {
+    if constexpr (M == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    }
+}
+template <int M>
+__device__ inline void swap_halves(float &x, float &y) {
+    uint32_t a = __float_as_uint(x), b = __float_as_uint(y);
+    swap_halves<M>(a, b);
+    x = __uint_as_float(a);
+    y = __uint_as_float(b);
+}
+template <int M>
+__device__ inline void swap_halves(double &x, double &y) {
+    uint32_t xh = (uint32_t)__double2hiint(x), xl = (uint32_t)__double2loint(x);
+    uint32_t yh = (uint32_t)__double2hiint(y), yl = (uint32_t)__double2loint(y);
+    swap_halves<M>(xh, yh);
+    swap_halves<M>(xl, yl);
+    x = __hiloint2double((int)xh, (int)xl);
+    y = __hiloint2double((int)yh, (int)yl);
+}
+
+// One stage of the transposing butterfly over lane bit M: of the 2h values
+// a lane carries, the lanes with bit M clear keep (and total) values 0..h-1,
+// the others values h..2h-1, each adding its partner's copy.
+template <int M, int H, typename T>
+__device__ inline void butterfly_stage(T *v, int lane) {
+    if constexpr (M >= 16) {
+        // after the swap, lanes with bit M clear hold (own v_i, partner's v_i)
+        // and the others (partner's v_{i+h}, own v_{i+h})
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            swap_halves<M>(v[i], v[i + H]);
+            v[i] = v[i] + v[i + H];
+        }
+    } else {
+        const bool hi = (lane & M) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const T send = hi ? v[i] : v[i + H];
+            const T keep = hi ? v[i + H] : v[i];
+            v[i] = keep + partner<M>(send);
+        }
+    }
+}
+
+// Sum of the 64 lanes' NV values (NV a power of two, 8 <= NV <= 32); lane i
+// receives the total of value i / (64 / NV).  The additions follow a fixed
+// tree, so the result does not depend on timing.
+template <int NV, typename T>
+__device__ inline T wave_transpose_sum(T *v, int lane) {
+    static_assert(NV == 8 || NV == 16 || NV == 32, "value count");
+    butterfly_stage<32, NV / 2>(v, lane);
+    butterfly_stage<16, NV / 4>(v, lane);
+    butterfly_stage<8, NV / 8>(v, lane);
+    if constexpr (NV >= 16) butterfly_stage<4, NV / 16>(v, lane);
+    if constexpr (NV >= 32) butterfly_stage<2, 1>(v, lane);
+    // lanes that now hold the same value: groups of 64 / NV neighbours
+    T t = v[0];
+    if constexpr (NV <= 8) t += partner<4>(t);
+    if constexpr (NV <= 16) t += partner<2>(t);
+    t += partner<1>(t);
+    return t;
+}
+
 // Orders with p + 1 <= 16: one lane per pair, 64 pairs per chunk.  Each lane
 // computes its pair's geometry, power table and pre-scaled row u' (stored in
 // LDS as two operand rows, real and imaginary part); the matrix instruction
 // multiplies the 128 rows by M^T block by block, each block's result
 // replacing its own rows in LDS; the lane then post-scales its pair's
-// outputs by T'_l and accumulates them in registers.  At the end of the
-// segment a transposing butterfly reduction (each stage halves the values a
-// lane carries) sums the 64 lanes' accumulators in a fixed order.
+// outputs by T'_l, and a transposing butterfly (each stage halves the values
+// a lane carries) sums the chunk's 64 pairs in a fixed order, leaving each
+// lane one running total per pass of at most 16 values.  The post-scaled
+// values live only for one pass, which keeps the register count low.
 template <int P1, typename G, typename ACC, bool BF3>
 __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom, const int32_t *__restrict__ wptr_all,
                                                const int32_t *__restrict__ widx_pool,
@@ -350,7 +443,10 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
     using PT = typename std::conditional<std::is_same<ACC, float>::value, float, double>::type;
     constexpr int KP = 17;                                   // padded row length
     constexpr int KS = (P1 + 3) / 4;                         // K steps of the FP32/FP64 instruction
-    constexpr int NV = P1 <= 4 ? 8 : (P1 <= 8 ? 16 : 32);    // accumulated values (Re, Im), power of two
+    // the post-scaled values (Re, Im) are summed in at most two passes of
+    // NV values (l < 8, then l >= 8), which bounds the live registers
+    constexpr int NH = P1 <= 8 ? 1 : 2;                      // passes
+    constexpr int NV = P1 <= 4 ? 8 : 16;                     // values per pass, power of two
     constexpr int SPREAD = 64 / NV;                          // lanes sharing one value after the halving stages
     __shared__ G U[64][2][KP];
     const int64_t seg = blockIdx.x;
@@ -387,9 +483,9 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
             mreg[ks] = (k < P1 && row < P1) ? (G)Mhat[row * 64 + k] : (G)0;
         }
     }
-    ACC acc[NV];
+    ACC tot[NH];  // running totals of value lane / SPREAD of each pass
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = (ACC)0;
+    for (int hf = 0; hf < NH; ++hf) tot[hf] = (ACC)0;
     ACC ext0 = (ACC)0;
     for (int32_t t = t0; t < t1; t += 64) {
         const int np = (t1 - t) < 64 ? (t1 - t) : 64;
@@ -454,41 +550,40 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
             for (int r = 0; r < 4; ++r) U[8 * rb + 2 * g + r / 2][r % 2][row] = (G)d[r];
         }
         __syncthreads();
-        if (act) {
-            cx<PT> tp{(PT)1, (PT)0};  // (2 rho_t)^l
+        cx<PT> tp{(PT)1, (PT)0};  // (2 rho_t)^l
 #pragma unroll
-            for (int l = 0; l < P1; ++l) {
-                const ACC wr = (ACC)U[lane][0][l], wi = (ACC)U[lane][1][l];
-                const ACC tr = (ACC)tp.re, ti = (ACC)tp.im;
-                acc[2 * l] += tr * wr - ti * wi;
-                acc[2 * l + 1] += tr * wi + ti * wr;
-                tp = cxmul(tp, rtp);
+        for (int hf = 0; hf < NH; ++hf) {
+            ACC acc[NV];
+#pragma unroll
+            for (int j = 0; j < NV / 2; ++j) {
+                const int l = hf * (NV / 2) + j;
+                if (l < P1) {
+                    // rows of lanes without a pair hold stale values: zero them
+                    const ACC wr = act ? (ACC)U[lane][0][l] : (ACC)0, wi = act ? (ACC)U[lane][1][l] : (ACC)0;
+                    const ACC tr = (ACC)tp.re, ti = (ACC)tp.im;
+                    acc[2 * j] = fma(tr, wr, -ti * wi);
+                    acc[2 * j + 1] = fma(tr, wi, ti * wr);
+                    tp = cxmul(tp, rtp);
+                } else {
+                    acc[2 * j] = (ACC)0;
+                    acc[2 * j + 1] = (ACC)0;
+                }
             }
+            tot[hf] += wave_transpose_sum<NV>(acc, lane);
         }
         __syncthreads();
     }
-    // transposing butterfly: each stage with mask m halves the values a lane
-    // carries; then the SPREAD lanes holding the same value are added; lane i
-    // ends with the total of value i / SPREAD
-#pragma unroll
-    for (int h = NV / 2, m = 32; h >= 1; h >>= 1, m >>= 1) {
-        const bool hi = (lane & m) != 0;
-#pragma unroll
-        for (int i = 0; i < h; ++i) {
-            const ACC send = hi ? acc[i] : acc[i + h];
-            const ACC keep = hi ? acc[i + h] : acc[i];
-            acc[i] = keep + __shfl_xor(send, m, 64);
-        }
-    }
-#pragma unroll
-    for (int m = SPREAD / 2; m >= 1; m >>= 1) acc[0] += __shfl_xor(acc[0], m, 64);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) ext0 += __shfl_xor(ext0, off, 64);
-    const int idx = lane / SPREAD, l = idx >> 1, comp = idx & 1;
-    if (lane % SPREAD == 0 && l < P1) {
-        double v = (double)acc[0];
-        if (l == 0 && comp == 0) v += (double)ext0;
-        reinterpret_cast<double *>(part)[2 * (seg * P1 + l) + comp] = v;
+    const int idx = lane / SPREAD, comp = idx & 1;
+#pragma unroll
+    for (int hf = 0; hf < NH; ++hf) {
+        const int l = hf * (NV / 2) + (idx >> 1);
+        if (lane % SPREAD == 0 && l < P1) {
+            double v = (double)tot[hf];
+            if (l == 0 && comp == 0) v += (double)ext0;
+            reinterpret_cast<double *>(part)[2 * (seg * P1 + l) + comp] = v;
+        }
     }
 }
 
