@@ -154,6 +154,134 @@ __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restr
     }
 }
 
+// ---- M2M and L2L for p + 1 <= 16: one lane per box, coefficients in registers
+// With C(n, k) = n! / (k! (n - k)!) the binomial sums are convolutions:
+//   M2M (parent coefficient l >= 1, from one child):
+//     (l - 1)! sum_{k=0..l} a'_k e_{l-k},  a'_0 = -A_0, a'_k = A_k sigma^k / (k - 1)!,
+//   L2L (child coefficient l):
+//     (tau^l / l!) sum_{k=l..p} b'_k e_{k-l},  b'_k = B_k k!,
+// with e_j = delta^j / j!, delta the centre offset over the parent's scale,
+// sigma and tau the ratios of the scales.  P1 is a compile-time constant,
+// so every factorial is a constant and the loops unroll completely.
+template <int N>
+struct Fact {
+    double f[N], inv[N];
+    constexpr Fact() : f(), inv() {
+        double v = 1.0;
+        for (int i = 0; i < N; ++i) {
+            if (i > 0) v *= i;
+            f[i] = v;
+            inv[i] = 1.0 / v;
+        }
+    }
+};
+
+// e_j = delta^j / j!, j < P1
+template <int P1>
+__device__ inline void scaled_powers(cd delta, cd *e) {
+    constexpr Fact<P1> F;
+    e[0] = cd{1.0, 0.0};
+    cd w = delta;
+#pragma unroll
+    for (int j = 1; j < P1; ++j) {
+        e[j] = cscale(w, F.inv[j]);
+        if (j + 1 < P1) w = cmul(w, delta);
+    }
+}
+
+template <int P1>
+__global__ void __launch_bounds__(64) k_m2m_box(int l, int64_t nparent, const double4 *__restrict__ geom,
+                                                cd *__restrict__ A) {
+    constexpr Fact<P1> F;
+    const int64_t P = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (P >= nparent) return;
+    const int64_t pbox = level_offset(l) + P;
+    const double4 gp = geom[pbox];
+    const double is = 1.0 / gp.w;
+    cd acc[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) acc[k] = cd{0.0, 0.0};
+    for (int c = 0; c < 4; ++c) {
+        const int64_t cbox = level_offset(l + 1) + 4 * P + c;
+        const double4 gc = geom[cbox];
+        cd a[P1];
+#pragma unroll
+        for (int k = 0; k < P1; ++k) a[k] = A[cbox * P1 + k];
+        cd e[P1];
+        scaled_powers<P1>(cd{(gc.x - gp.x) * is, (gc.y - gp.y) * is}, e);
+        const double sigma = gc.w * is;
+        acc[0] = cadd(acc[0], a[0]);
+        // a'_k in place
+        a[0] = cd{-a[0].re, -a[0].im};
+        double sk = 1.0;
+#pragma unroll
+        for (int k = 1; k < P1; ++k) {
+            sk *= sigma;
+            a[k] = cscale(a[k], sk * F.inv[k - 1]);
+        }
+#pragma unroll
+        for (int lo = 1; lo < P1; ++lo) {
+            cd t{0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k <= lo; ++k) {
+                t.re = fma(a[k].re, e[lo - k].re, t.re);
+                t.re = fma(-a[k].im, e[lo - k].im, t.re);
+                t.im = fma(a[k].re, e[lo - k].im, t.im);
+                t.im = fma(a[k].im, e[lo - k].re, t.im);
+            }
+            acc[lo] = cadd(acc[lo], cscale(t, F.f[lo - 1]));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < P1; ++k) A[pbox * P1 + k] = acc[k];
+}
+
+// B(child) = the parent's local expansion re-centred at the child, plus the
+// child's M2L segment sums in segment order.
+template <int P1>
+__global__ void __launch_bounds__(64) k_l2l_box(int l, int64_t nchild, const double4 *__restrict__ geom,
+                                                cd *__restrict__ B, const int32_t *__restrict__ segoff,
+                                                const cd *__restrict__ part) {
+    constexpr Fact<P1> F;
+    const int64_t cidx = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (cidx >= nchild) return;
+    const int64_t cbox = level_offset(l + 1) + cidx;
+    const int64_t pbox = level_offset(l) + (cidx >> 2);
+    const double4 gc = geom[cbox], gp = geom[pbox];
+    const double is = 1.0 / gp.w;
+    cd bp[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        const cd v = B[pbox * P1 + k];
+        bp[k] = cscale(v, F.f[k]);
+    }
+    cd e[P1];
+    scaled_powers<P1>(cd{(gc.x - gp.x) * is, (gc.y - gp.y) * is}, e);
+    const double tau = gc.w * is;
+    cd out[P1];
+    double tl = 1.0;
+#pragma unroll
+    for (int lo = 0; lo < P1; ++lo) {
+        cd t{0.0, 0.0};
+#pragma unroll
+        for (int k = lo; k < P1; ++k) {
+            t.re = fma(bp[k].re, e[k - lo].re, t.re);
+            t.re = fma(-bp[k].im, e[k - lo].im, t.re);
+            t.im = fma(bp[k].re, e[k - lo].im, t.im);
+            t.im = fma(bp[k].im, e[k - lo].re, t.im);
+        }
+        out[lo] = cscale(t, tl * F.inv[lo]);
+        tl *= tau;
+    }
+    const int32_t s0 = segoff[cbox], s1 = segoff[cbox + 1];
+    for (int32_t sg = s0; sg < s1; ++sg) {
+#pragma unroll
+        for (int k = 0; k < P1; ++k) out[k] = cadd(out[k], part[(int64_t)sg * P1 + k]);
+    }
+#pragma unroll
+    for (int k = 0; k < P1; ++k) B[cbox * P1 + k] = out[k];
+}
+
 __global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restrict__ perm, int64_t n,
                            double *__restrict__ qs) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -214,9 +342,23 @@ hipError_t upward_pass(fmm2d_ctx *c, int p) {
     else if (p < 48) r = launch_p2m<48>(c, p, A);
     else r = launch_p2m<64>(c, p, A);
     FMM2D_TRY(r);
+    const double4 *geom = t.geom.as<double4>();
     for (int l = L - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(k_m2m, dim3((unsigned)(int64_t(1) << (2 * l))), dim3(64), 0, c->stream, l, p,
-                           t.geom.as<double4>(), A, binom);
+        const int64_t np = int64_t(1) << (2 * l);
+        if (p + 1 <= 16) {
+            const dim3 grid(grid_for(np, 64)), block(64);
+            switch (p + 1) {
+#define FMM2D_M2M(P1) \
+    case P1: hipLaunchKernelGGL(k_m2m_box<P1>, grid, block, 0, c->stream, l, np, geom, A); break;
+                FMM2D_M2M(2) FMM2D_M2M(3) FMM2D_M2M(4) FMM2D_M2M(5) FMM2D_M2M(6) FMM2D_M2M(7) FMM2D_M2M(8)
+                FMM2D_M2M(9) FMM2D_M2M(10) FMM2D_M2M(11) FMM2D_M2M(12) FMM2D_M2M(13) FMM2D_M2M(14)
+                FMM2D_M2M(15) FMM2D_M2M(16)
+#undef FMM2D_M2M
+                default: return hipErrorInvalidValue;
+            }
+        } else {
+            hipLaunchKernelGGL(k_m2m, dim3((unsigned)np), dim3(64), 0, c->stream, l, p, geom, A, binom);
+        }
     }
     return hipGetLastError();
 }
@@ -224,9 +366,27 @@ hipError_t upward_pass(fmm2d_ctx *c, int p) {
 hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
-    hipLaunchKernelGGL(k_l2l, dim3((unsigned)(int64_t(1) << (2 * (l + 1)))), dim3(64), 0, c->stream, l, p,
-                       t.geom.as<double4>(), e.B.as<cd>(), e.binom.as<double>(), t.m2l_all.segoff.as<int32_t>(),
-                       e.part.as<cd>());
+    const int64_t nc = int64_t(1) << (2 * (l + 1));
+    const double4 *geom = t.geom.as<double4>();
+    const int32_t *segoff = t.m2l_all.segoff.as<int32_t>();
+    if (p + 1 <= 16) {
+        const dim3 grid(grid_for(nc, 64)), block(64);
+        switch (p + 1) {
+#define FMM2D_L2L(P1)                                                                                            \
+    case P1:                                                                                                     \
+        hipLaunchKernelGGL(k_l2l_box<P1>, grid, block, 0, c->stream, l, nc, geom, e.B.as<cd>(), segoff,         \
+                           e.part.as<cd>());                                                                     \
+        break;
+            FMM2D_L2L(2) FMM2D_L2L(3) FMM2D_L2L(4) FMM2D_L2L(5) FMM2D_L2L(6) FMM2D_L2L(7) FMM2D_L2L(8)
+            FMM2D_L2L(9) FMM2D_L2L(10) FMM2D_L2L(11) FMM2D_L2L(12) FMM2D_L2L(13) FMM2D_L2L(14) FMM2D_L2L(15)
+            FMM2D_L2L(16)
+#undef FMM2D_L2L
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL(k_l2l, dim3((unsigned)nc), dim3(64), 0, c->stream, l, p, geom, e.B.as<cd>(),
+                           e.binom.as<double>(), segoff, e.part.as<cd>());
+    }
     return hipGetLastError();
 }
 
