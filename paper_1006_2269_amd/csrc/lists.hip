@@ -100,6 +100,11 @@ __device__ inline void box_lists(int l, int L, double theta, const double4 *__re
                                  uint64_t *__restrict__ bits, int32_t &cs, int32_t &cw, int32_t tS,
                                  int32_t *__restrict__ so, int32_t *__restrict__ wo, const int32_t *__restrict__ stL,
                                  int2 *__restrict__ recj, float4 *__restrict__ recd) {
+    // Chunks of 64 candidates are taken CB at a time: the loads of a batch
+    // (box numbers, then geometry, leaf ranges or decision words) are all
+    // issued before any is waited for, so a box costs a few memory round trips
+    // rather than two per chunk.
+    constexpr int CB = 4;
     const uint32_t lane = lane_id();
     const int64_t P = b >> 2;
     const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
@@ -107,43 +112,66 @@ __device__ inline void box_lists(int l, int L, double theta, const double4 *__re
     uint64_t *bw = BITS ? bits + bits_base(b, s0, s1) : nullptr;
     const bool records = FILL && l == L && recj != nullptr;
     const bool test = !FILL || !BITS;
-    double4 gb;
+    double4 gb = make_double4(0.0, 0.0, 0.0, 0.0);
     if (test || records) gb = geomL[b];
     cs = 0;
     cw = 0;
-    for (int32_t base = 0; base < ncand; base += 64) {
-        const int32_t j = base + (int32_t)lane;
-        const bool ok = j < ncand;
-        int32_t cbox = 0;
-        if (ok) cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
-        uint64_t mw;
-        if (test) {
-            const bool weak = ok && theta_separated(theta, theta * theta, gb, geomL[cbox]);
-            mw = __ballot(weak);
-            if (BITS && !FILL && lane == 0) bw[base >> 6] = mw;
-        } else {
-            mw = bw[base >> 6];
+    for (int32_t base = 0; base < ncand; base += 64 * CB) {
+        int32_t cbox[CB];
+        bool ok[CB];
+        uint64_t mw[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int32_t j = base + 64 * u + (int32_t)lane;
+            ok[u] = j < ncand;
+            cbox[u] = ok[u] ? 4 * sidx_prev[s0 + (j >> 2)] + (j & 3) : 0;
+            if (!test) mw[u] = base + 64 * u < ncand ? bw[(base >> 6) + u] : 0;
         }
-        const uint64_t okm = __ballot(ok);
-        const uint64_t ms = okm & ~mw;
-        if (FILL && ok) {
-            if ((mw >> lane) & 1) {
-                wo[cw + (int32_t)popc_below(mw)] = cbox;
-            } else {
-                const int32_t pos = cs + (int32_t)popc_below(ms);
-                so[pos] = cbox;
-                if (records) {
-                    const int32_t t = tS + pos;
-                    const double4 gc = geomL[cbox];
-                    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
-                    const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
-                    recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
-                    recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
-                }
+        if (test) {
+            double4 gc[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) gc[u] = ok[u] ? geomL[cbox[u]] : gb;
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const bool weak = ok[u] && theta_separated(theta, theta * theta, gb, gc[u]);
+                mw[u] = __ballot(weak);
+                if (BITS && !FILL && lane == 0 && base + 64 * u < ncand) bw[(base >> 6) + u] = mw[u];
             }
         }
-        cw += (int32_t)__popcll(mw);
-        cs += (int32_t)__popcll(ms);
+        // records of the finest level: geometry and leaf range of the strong entries
+        double4 gr[CB];
+        int2 rr[CB];
+        if (records) {
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const bool strong = ok[u] && !((mw[u] >> lane) & 1);
+                gr[u] = strong ? geomL[cbox[u]] : gb;
+                rr[u] = strong ? make_int2(stL[cbox[u]], stL[cbox[u] + 1]) : make_int2(0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const uint64_t okm = __ballot(ok[u]);
+            const uint64_t ms = okm & ~mw[u];
+            if (FILL && ok[u]) {
+                if ((mw[u] >> lane) & 1) {
+                    wo[cw + (int32_t)popc_below(mw[u])] = cbox[u];
+                } else {
+                    const int32_t pos = cs + (int32_t)popc_below(ms);
+                    so[pos] = cbox[u];
+                    if (records) {
+                        const int32_t t = tS + pos;
+                        const double4 gc = gr[u];
+                        const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
+                        const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
+                        recj[t] = rr[u];
+                        recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+                    }
+                }
+            }
+            cw += (int32_t)__popcll(mw[u]);
+            cs += (int32_t)__popcll(ms);
+        }
     }
 }
 
