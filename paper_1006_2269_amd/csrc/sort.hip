@@ -19,7 +19,7 @@ namespace fmm2d {
 namespace {
 
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 16;
+constexpr int SORT_ITEMS = 8;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
 constexpr int RADIX = 256;
 constexpr int NW = SORT_THREADS / WAVE;
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_colscan(int32_t *__restrict__ hist, int
 // Stable rank within the tile, staged in LDS in digit order, then written out
 // as runs: element at LDS position s with digit d goes to
 // digit_base[d] + column_offset[d][tile] + (s - tile_digit_start[d]).
-// Each wavefront ranks its own 1024 consecutive keys (16 rounds of 64) with
+// Each wavefront ranks its own SORT_ITEMS x 64 consecutive keys (rounds of 64) with
 // private digit counters, so the rounds need no block barrier: within a
 // round, lanes of equal digit are ranked by ballot matching and the round's
 // leader advances the wave's counter.  The tile order (wave, round, lane) is
