@@ -248,6 +248,156 @@ __global__ void __launch_bounds__(PT) k_part_scatter(int h, const int32_t *__res
     }
 }
 
+// Depths h0 .. 2L-1 of one segment of depth h0 (at most LOC_M points) in one
+// workgroup, with the two lists in LDS: per depth the same median split and
+// stable partition as above (flags, one block-wide scan, scatter within each
+// sub-segment), and the same segment records (split lines kept in LDS, so no
+// workgroup reads another's).  Replaces two launches per depth on the fine
+// depths.  The final XL lists are written back in place.
+constexpr int LOC_T = 1024;
+constexpr int LOC_PER = 4;
+constexpr int LOC_M = LOC_T * LOC_PER;
+constexpr int LOC_SEGS = 256;  // sub-segments tracked per depth (2^(2L - h0) <= LOC_SEGS)
+
+__device__ inline int32_t seg_local(int32_t i, int32_t m, int d, int32_t &a, int32_t &e) {
+    int32_t lo = 0, hi = m, s = 0;
+    for (int k = 0; k < d; ++k) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        const bool up = i >= mid;
+        s = 2 * s + (up ? 1 : 0);
+        lo = up ? mid : lo;
+        hi = up ? hi : mid;
+    }
+    a = lo;
+    e = hi;
+    return s;
+}
+
+__global__ void __launch_bounds__(LOC_T) k_part_local(int h0, int L, int64_t n, int32_t *__restrict__ gXLx,
+                                                      int32_t *__restrict__ gXLy, const int32_t *__restrict__ gYLx,
+                                                      const int32_t *__restrict__ gYLy, int32_t *__restrict__ starts,
+                                                      const double *__restrict__ xsorted,
+                                                      const double *__restrict__ ysorted,
+                                                      const double *__restrict__ split_x_prev,
+                                                      Rect *__restrict__ rects) {
+    __shared__ int32_t buf[6][LOC_M];
+    __shared__ int32_t segpre[LOC_SEGS];
+    __shared__ double spl[2][LOC_SEGS];  // split lines of the previous and the current depth
+    __shared__ int32_t tmp[LOC_T / 64];
+    const int64_t S = blockIdx.x;  // segment of depth h0
+    const int t = threadIdx.x;
+    // range [A, E) of segment S of depth h0: its bits from the root, first
+    // split first
+    int32_t A = 0, E = (int32_t)n;
+    for (int d = h0 - 1; d >= 0; --d) {
+        const int32_t mid = A + ((E - A) >> 1);
+        if ((S >> d) & 1) A = mid;
+        else E = mid;
+    }
+    const int32_t m = E - A;
+    int32_t *XLx = buf[0], *XLy = buf[1], *YLx = buf[2], *YLy = buf[3], *T0 = buf[4], *T1 = buf[5];
+    for (int i = t; i < m; i += LOC_T) {
+        XLx[i] = gXLx[A + i];
+        XLy[i] = gXLy[A + i];
+        YLx[i] = gYLx[A + i];
+        YLy[i] = gYLy[A + i];
+    }
+    __syncthreads();
+    int cur = 0;  // spl[cur]: split lines of the previous depth
+    for (int h = h0; h < 2 * L; ++h) {
+        const int d = h - h0;
+        const bool xsplit = (h & 1) == 0;
+        const int32_t *med = xsplit ? XLx : YLy;
+        int32_t *R0 = xsplit ? YLx : XLx, *R1 = xsplit ? YLy : XLy;
+        const int32_t *key = xsplit ? R0 : R1;
+        // flags of this thread's positions 4t .. 4t+3 and their prefix
+        bool f[LOC_PER];
+        int32_t sa[LOC_PER], sk[LOC_PER], ss[LOC_PER], cnt = 0;
+#pragma unroll
+        for (int r = 0; r < LOC_PER; ++r) {
+            const int32_t i = LOC_PER * t + r;
+            f[r] = false;
+            sa[r] = 0;
+            sk[r] = 0;
+            ss[r] = 0;
+            if (i < m) {
+                int32_t a, e;
+                ss[r] = seg_local(i, m, d, a, e);
+                sa[r] = a;
+                sk[r] = (e - a) >> 1;
+                f[r] = key[i] < med[a + sk[r]];
+                cnt += f[r] ? 1 : 0;
+            }
+        }
+        int32_t total;
+        int32_t run = block_excl_scan<LOC_T>(cnt, tmp, total);
+        int32_t pre[LOC_PER];
+#pragma unroll
+        for (int r = 0; r < LOC_PER; ++r) {
+            pre[r] = run;
+            run += f[r] ? 1 : 0;
+            const int32_t i = LOC_PER * t + r;
+            if (i < m && i == sa[r]) segpre[ss[r]] = pre[r];
+        }
+        // segment records of this depth (one thread per sub-segment)
+        const int64_t nseg = int64_t(1) << h;
+        const int32_t nsub = 1 << d;
+        int32_t *st1 = starts + depth_offset(h + 1);
+        if (t < nsub) {
+            // range of sub-segment t: its bits from the segment's root
+            int32_t a = 0, e = m;
+            for (int q = d - 1; q >= 0; --q) {
+                const int32_t mid = a + ((e - a) >> 1);
+                if ((t >> q) & 1) a = mid;
+                else e = mid;
+            }
+            const int32_t k = (e - a) >> 1;
+            const double *coord = xsplit ? xsorted : ysorted;
+            const double sp = 0.5 * (coord[med[a + k - 1]] + coord[med[a + k]]);
+            spl[cur ^ 1][t] = sp;
+            const int64_t g = (S << d) + t;
+            st1[2 * g] = A + a;
+            st1[2 * g + 1] = A + a + k;
+            if (g == nseg - 1) st1[2 * nseg] = (int32_t)n;
+            if (h & 1) {
+                const int l = (h - 1) >> 1;
+                const int64_t b = g >> 1;
+                const int xside = (int)(g & 1);
+                const Rect Rb = rects[level_offset(l) + b];
+                const double sx = d >= 1 ? spl[cur][t >> 1] : split_x_prev[b];
+                const double xlo = xside ? sx : Rb.xlo;
+                const double xhi = xside ? Rb.xhi : sx;
+                const int64_t c0 = level_offset(l + 1) + 4 * b + 2 * xside;
+                rects[c0] = Rect{xlo, xhi, Rb.ylo, sp};
+                rects[c0 + 1] = Rect{xlo, xhi, sp, Rb.yhi};
+            }
+        }
+        __syncthreads();  // segpre, spl and the rectangles of this depth
+        // stable partition of (R0, R1) within each sub-segment
+#pragma unroll
+        for (int r = 0; r < LOC_PER; ++r) {
+            const int32_t i = LOC_PER * t + r;
+            if (i < m) {
+                const int32_t below = pre[r] - segpre[ss[r]];
+                const int32_t dst = f[r] ? sa[r] + below : sa[r] + sk[r] + ((i - sa[r]) - below);
+                T0[dst] = R0[i];
+                T1[dst] = R1[i];
+            }
+        }
+        __syncthreads();
+        if (xsplit) {
+            YLx = T0; YLy = T1; T0 = R0; T1 = R1;
+        } else {
+            XLx = T0; XLy = T1; T0 = R0; T1 = R1;
+        }
+        cur ^= 1;
+    }
+    for (int i = t; i < m; i += LOC_T) {
+        gXLx[A + i] = XLx[i];
+        gXLy[A + i] = XLy[i];
+    }
+}
+
 // Centre and radius (half diagonal) of every box, each expression one
 // correctly rounded binary64 operation, no contraction.
 __global__ void k_geometry(const Rect *__restrict__ rects, int64_t nbox, double4 *__restrict__ geom) {
@@ -331,7 +481,12 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
     int32_t *XLx = t.XLx.as<int32_t>(), *XLy = t.XLy.as<int32_t>();
     int32_t *YLx = t.YLx.as<int32_t>(), *YLy = t.YLy.as<int32_t>();
     int32_t *T0 = t.T0.as<int32_t>(), *T1 = t.T1.as<int32_t>();
-    for (int h = 0; h < 2 * L; ++h) {
+    // the fine depths in LDS, from the first depth whose segments (sizes
+    // floor or ceil of n / 2^h) fit one workgroup
+    int hloc = 0;
+    while (hloc < 2 * L && ((n + (int64_t(1) << hloc) - 1) >> hloc) > LOC_M) ++hloc;
+    if (2 * L - hloc > 8) hloc = 2 * L - 8;  // at most 2^8 sub-segments per workgroup
+    for (int h = 0; h < hloc; ++h) {
         const int64_t nseg = int64_t(1) << h;
         const int32_t *st = starts + depth_offset(h);
         int32_t *st1 = starts + depth_offset(h + 1);
@@ -363,8 +518,12 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
             XLx = T0; XLy = T1; T0 = R0; T1 = R1;
         }
     }
-    // remember where the final lists live
-    (void)YLx; (void)YLy;
+    if (hloc < 2 * L) {
+        hipLaunchKernelGGL(k_part_local, dim3((unsigned)(int64_t(1) << hloc)), dim3(LOC_T), 0, c->stream, hloc, L, n,
+                           XLx, XLy, YLx, YLy, starts, t.xsorted.as<double>(), t.ysorted.as<double>(),
+                           s.split0.as<double>(), rects);
+        FMM2D_TRY(hipGetLastError());
+    }
 
     // 4. geometry of all boxes, leaf-ordered points and local offsets
     hipLaunchKernelGGL(k_geometry, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, rects, nbox,

@@ -54,6 +54,9 @@ TREE_CASES = {
     "negzero_2k_L4": (lambda: _negative_zero(2000, 11), 4),
     "single_box_L0": (lambda: W.uniform(7, 12), 0),
     "uniform_10k_L5": (lambda: W.uniform_10k(), 5),
+    # fine depths finished in LDS from depth 3 (odd: the x split lines of
+    # depth 2 come from the global passes)
+    "uniform_20k_L5": (lambda: W.uniform(20000, 13), 5),
     "mixed_scaled_20k_L6": (lambda: W.mixed_1m(scale=0.02), 6),
     "clustered_scaled_20k_L6": (lambda: W.clustered_10m(scale=0.002), 6),
     "clustered_scaled_30k_L6": (lambda: W.clustered_10m(scale=0.003, seed=2003), 6),
