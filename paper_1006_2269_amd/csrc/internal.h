@@ -86,6 +86,7 @@ struct TreeState {
     // lists: row pointers of every level (ptr_offset), index pools
     DevBuf sptr, wptr, sidx, widx, cnt_s, cnt_w;
     DevBuf bits;            // uint64: theta decisions of one level's candidates
+    DevBuf owner0, owner1;  // int32: row (box) of each S entry of a level, by level parity
     DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
     DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range, FP32 centre offset, threshold
     bool nrec_valid = false;

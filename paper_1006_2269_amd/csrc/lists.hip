@@ -2,27 +2,37 @@
 // theta-criterion (Criterion 2.1).
 //
 // For box b at level l with parent P, the candidates are the four children of
-// every box in S_{l-1}(P); they are visited in ascending order by the 64
-// lanes of one wavefront, tested, and compacted with ballots into S_l(b)
-// (criterion false) or W_l(b) (criterion true), so both lists come out
-// ascending.  Each level is a count pass, an exclusive scan of the counts
-// (the CSR row pointers) and a fill pass.  The index lists of all levels live
-// in two pools; the pool offset of each level is advanced on the device, and
-// the host reads the offsets (and an overflow flag) at the end.
+// every box in S_{l-1}(P), in ascending order; each is tested and goes to
+// S_l(b) (criterion false) or W_l(b) (criterion true), so both lists come out
+// ascending.  The index lists of all levels live in two pools; the pool
+// offset of each level is advanced on the device, and the host reads the
+// offsets (and an overflow flag) at the end.
 //
-// Row pointers are int32.  A level's candidates number 16 |S_{l-1}| (four
-// children of each of the four children's parents' strong boxes), and each
-// becomes one entry of S or W.  After each level a one-thread kernel checks
-// the next level's candidate count against the entry limit and the free pool
-// space and raises a flag that stops all later levels, so no int32 prefix
-// sum can wrap; the host reads the flag with the pool offsets at the end.
+// Levels of at most 64 boxes run in one workgroup (one launch).  Finer levels
+// are flat passes over the level's candidate space: candidate q of parent P
+// is q = 16 sptr_{l-1}[P] + 4 |S_{l-1}(P)| c + j for child box b = 4P + c and
+// its j-th candidate, so the candidates of consecutive boxes are consecutive
+// and, with the owner of every entry of S_{l-1} (its row), q decodes in a few
+// loads.  A count pass writes the decisions as one bit per candidate and the
+// per-word counts; a scan over the words gives, for every candidate, the
+// number of strong and weak candidates before it, which is its position in
+// the level's S or W pool and, at a box's first candidate, the box's row
+// pointer.  The work per wavefront is the same for every word, so boxes with
+// very long lists (clustered inputs) do not serialise a pass.
+//
+// Row pointers are int32.  A level's candidates number 16 |S_{l-1}|, and each
+// becomes one entry of S or W.  After each level a check compares the next
+// level's candidate count with the entry limit and the free pool space and
+// raises a flag that stops all later levels, so no int32 prefix sum can wrap;
+// the host reads the flag with the pool offsets at the end.
+#include <algorithm>
+
 #include "devutil.h"
 #include "internal.h"
 
 namespace fmm2d {
 namespace {
 
-constexpr int LW = 4;  // wavefronts (boxes) per block
 
 // pool_state layout: [0, L+2): S pool offsets, [L+2, 2L+4): W pool offsets,
 // [2L+4]: overflow flag.
@@ -77,139 +87,59 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool,
     }
 }
 
-// First word of box b's decision bits: candidates of b are preceded by
-// cand(b) = 16 sptr_prev[P] + (b mod 4) 4 |S_{l-1}(P)| candidates of the
-// level, and b needs ceil(ncand / 64) words, so floor(cand(b) / 64) + b never
-// overlaps the words of box b - 1.
-__device__ inline int64_t bits_base(int64_t b, int32_t s0, int32_t s1) {
-    const int64_t cand = 16 * (int64_t)s0 + (b & 3) * 4 * (int64_t)(s1 - s0);
-    return (cand >> 6) + b;
-}
-
 // One wavefront, box b of level l (candidates: the four children of each box
-// of S_{l-1}(parent)).  Count pass (FILL = false): the theta test of every
-// candidate, the two counts, and (BITS) the decisions stored as bits (set:
-// weak).  Fill pass: the same candidates, their decisions (from the bits, or
-// the test again), ballot compaction into the lists; on the finest level
-// also the near-field record of each strong entry (source leaf's point
-// range; FP32 centre offset c_b - c_c and the coincidence threshold
-// (2^-20 of the magnitudes)^2 for the FP32 path).
-template <bool FILL, bool BITS>
+// of S_{l-1}(parent)), for the levels done in one workgroup.  Count pass
+// (FILL = false): the theta test of every candidate and the two counts.  Fill
+// pass: the same tests, ballot compaction into the lists, the owner (row) of
+// every strong entry when the next level needs it, and on the finest level
+// the near-field record of each strong entry (source leaf's point range; FP32
+// centre offset c_b - c_c and the coincidence threshold (2^-20 of the
+// magnitudes)^2 for the FP32 path).
+template <bool FILL>
 __device__ inline void box_lists(int l, int L, double theta, const double4 *__restrict__ geomL, int64_t b,
                                  const int32_t *__restrict__ sptr_prev, const int32_t *__restrict__ sidx_prev,
-                                 uint64_t *__restrict__ bits, int32_t &cs, int32_t &cw, int32_t tS,
-                                 int32_t *__restrict__ so, int32_t *__restrict__ wo, const int32_t *__restrict__ stL,
-                                 int2 *__restrict__ recj, float4 *__restrict__ recd) {
-    // Chunks of 64 candidates are taken CB at a time: the loads of a batch
-    // (box numbers, then geometry, leaf ranges or decision words) are all
-    // issued before any is waited for, so a box costs a few memory round trips
-    // rather than two per chunk.
-    constexpr int CB = 4;
+                                 int32_t &cs, int32_t &cw, int32_t tS, int32_t *__restrict__ so,
+                                 int32_t *__restrict__ wo, int32_t *__restrict__ own,
+                                 const int32_t *__restrict__ stL, int2 *__restrict__ recj,
+                                 float4 *__restrict__ recd) {
     const uint32_t lane = lane_id();
     const int64_t P = b >> 2;
     const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
     const int32_t ncand = 4 * (s1 - s0);
-    uint64_t *bw = BITS ? bits + bits_base(b, s0, s1) : nullptr;
     const bool records = FILL && l == L && recj != nullptr;
-    const bool test = !FILL || !BITS;
-    double4 gb = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (test || records) gb = geomL[b];
+    const double4 gb = geomL[b];
     cs = 0;
     cw = 0;
-    for (int32_t base = 0; base < ncand; base += 64 * CB) {
-        int32_t cbox[CB];
-        bool ok[CB];
-        uint64_t mw[CB];
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-            const int32_t j = base + 64 * u + (int32_t)lane;
-            ok[u] = j < ncand;
-            cbox[u] = ok[u] ? 4 * sidx_prev[s0 + (j >> 2)] + (j & 3) : 0;
-            if (!test) mw[u] = base + 64 * u < ncand ? bw[(base >> 6) + u] : 0;
+    for (int32_t base = 0; base < ncand; base += 64) {
+        const int32_t j = base + (int32_t)lane;
+        const bool ok = j < ncand;
+        int32_t cbox = 0;
+        double4 gc = gb;
+        if (ok) {
+            cbox = 4 * sidx_prev[s0 + (j >> 2)] + (j & 3);
+            gc = geomL[cbox];
         }
-        if (test) {
-            double4 gc[CB];
-#pragma unroll
-            for (int u = 0; u < CB; ++u) gc[u] = ok[u] ? geomL[cbox[u]] : gb;
-#pragma unroll
-            for (int u = 0; u < CB; ++u) {
-                const bool weak = ok[u] && theta_separated(theta, theta * theta, gb, gc[u]);
-                mw[u] = __ballot(weak);
-                if (BITS && !FILL && lane == 0 && base + 64 * u < ncand) bw[(base >> 6) + u] = mw[u];
-            }
-        }
-        // records of the finest level: geometry and leaf range of the strong entries
-        double4 gr[CB];
-        int2 rr[CB];
-        if (records) {
-#pragma unroll
-            for (int u = 0; u < CB; ++u) {
-                const bool strong = ok[u] && !((mw[u] >> lane) & 1);
-                gr[u] = strong ? geomL[cbox[u]] : gb;
-                rr[u] = strong ? make_int2(stL[cbox[u]], stL[cbox[u] + 1]) : make_int2(0, 0);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-            const uint64_t okm = __ballot(ok[u]);
-            const uint64_t ms = okm & ~mw[u];
-            if (FILL && ok[u]) {
-                if ((mw[u] >> lane) & 1) {
-                    wo[cw + (int32_t)popc_below(mw[u])] = cbox[u];
-                } else {
-                    const int32_t pos = cs + (int32_t)popc_below(ms);
-                    so[pos] = cbox[u];
-                    if (records) {
-                        const int32_t t = tS + pos;
-                        const double4 gc = gr[u];
-                        const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
-                        const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
-                        recj[t] = rr[u];
-                        recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
-                    }
+        const bool weak = ok && theta_separated(theta, theta * theta, gb, gc);
+        const uint64_t mw = __ballot(weak);
+        const uint64_t ms = __ballot(ok) & ~mw;
+        if (FILL && ok) {
+            if (weak) {
+                wo[cw + (int32_t)popc_below(mw)] = cbox;
+            } else {
+                const int32_t pos = cs + (int32_t)popc_below(ms);
+                so[pos] = cbox;
+                if (own) own[tS + pos] = (int32_t)b;
+                if (records) {
+                    const int32_t t = tS + pos;
+                    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
+                    const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
+                    recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
+                    recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
                 }
             }
-            cw += (int32_t)__popcll(mw[u]);
-            cs += (int32_t)__popcll(ms);
         }
-    }
-}
-
-// One level, one wavefront per box.  The count pass stores the decisions as
-// bits, the fill pass replays them.
-template <bool FILL>
-__global__ void __launch_bounds__(LW * 64) k_lists_level(int l, int L, double theta, const double4 *__restrict__ geomL,
-                                                        const int32_t *__restrict__ sptr_prev,
-                                                        const int32_t *__restrict__ sidx_pool,
-                                                        const int64_t *__restrict__ pool_state, int64_t nb,
-                                                        int32_t *__restrict__ ns, int32_t *__restrict__ nw,
-                                                        uint64_t *__restrict__ bits,
-                                                        const int32_t *__restrict__ sptr_cur,
-                                                        const int32_t *__restrict__ wptr_cur,
-                                                        int32_t *__restrict__ sidx_out, int32_t *__restrict__ widx_out,
-                                                        const int32_t *__restrict__ stL, int2 *__restrict__ recj,
-                                                        float4 *__restrict__ recd) {
-    const int64_t b = (int64_t)blockIdx.x * LW + threadIdx.x / 64;
-    const uint32_t lane = lane_id();
-    if (b >= nb) return;
-    const bool overflow = pool_state[2 * L + 4] != 0;
-    if (overflow) {
-        if (!FILL && lane == 0) { ns[b] = 0; nw[b] = 0; }
-        return;
-    }
-    const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
-    int32_t cs, cw;
-    if (FILL) {
-        box_lists<true, true>(l, L, theta, geomL, b, sptr_prev, sidx_prev, bits, cs, cw, sptr_cur[b],
-                              sidx_out + pool_state[l] + sptr_cur[b], widx_out + pool_state[(L + 2) + l] + wptr_cur[b],
-                              stL, recj, recd);
-    } else {
-        box_lists<false, true>(l, L, theta, geomL, b, sptr_prev, sidx_prev, bits, cs, cw, 0, nullptr, nullptr, stL,
-                               nullptr, nullptr);
-        if (lane == 0) {
-            ns[b] = cs;
-            nw[b] = cw;
-        }
+        cw += (int32_t)__popcll(mw);
+        cs += (int32_t)__popcll(ms);
     }
 }
 
@@ -258,7 +188,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
                                                               int64_t *__restrict__ pool_state, int64_t cap_s,
                                                               int64_t cap_w, int64_t limit,
                                                               const int32_t *__restrict__ stL, int2 *__restrict__ recj,
-                                                              float4 *__restrict__ recd) {
+                                                              float4 *__restrict__ recd, int32_t *__restrict__ owner) {
     __shared__ int32_t ns[SMALL_BOXES], nw[SMALL_BOXES];
     __shared__ int32_t tmp[SMALL_THREADS / 64];
     __shared__ int flag;
@@ -277,8 +207,8 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
         const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
         for (int64_t b = wv; b < nb; b += NWV) {
             int32_t cs, cw;
-            box_lists<false, false>(l, L, theta, gL, b, sp_prev, sidx_prev, nullptr, cs, cw, 0, nullptr, nullptr,
-                                    stL, nullptr, nullptr);
+            box_lists<false>(l, L, theta, gL, b, sp_prev, sidx_prev, cs, cw, 0, nullptr, nullptr, nullptr, stL,
+                             nullptr, nullptr);
             if (lane_id() == 0) {
                 ns[b] = cs;
                 nw[b] = cw;
@@ -309,10 +239,255 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
         const int64_t so0 = pool_state[l], wo0 = pool_state[(L + 2) + l];
         for (int64_t b = wv; b < nb; b += NWV) {
             int32_t cs, cw;
-            box_lists<true, false>(l, L, theta, gL, b, sp_prev, sidx_prev, nullptr, cs, cw, sp_cur[b],
-                                   sidx_pool + so0 + sp_cur[b], widx_pool + wo0 + wp_cur[b], stL, recj, recd);
+            box_lists<true>(l, L, theta, gL, b, sp_prev, sidx_prev, cs, cw, sp_cur[b], sidx_pool + so0 + sp_cur[b],
+                            widx_pool + wo0 + wp_cur[b], l == K && K < L ? owner : nullptr, stL, recj, recd);
         }
         __syncthreads();
+    }
+}
+
+// ---- flat passes (levels with more than 64 boxes) -----------------------
+constexpr int FB = 4;                 // words (chunks of 64 candidates) per wavefront step
+constexpr unsigned FLAT_BLOCKS = 2048;  // 8192 wavefronts
+constexpr int WS_T = 256, WS_PER = 16, WS_TILE = WS_T * WS_PER;  // word scan tiles
+
+// Decodes FB words of candidates: box b, candidate box cbox, and whether q
+// is its box's first candidate.  The loads of each step are issued for all
+// FB words before any is used.
+struct FlatCand {
+    bool ok[FB], first[FB];
+    int32_t b[FB], cbox[FB];
+};
+__device__ inline void flat_decode(int64_t w0, int64_t NC, const int32_t *__restrict__ owner_prev,
+                                   const int32_t *__restrict__ sptr_prev, const int32_t *__restrict__ sidx_prev,
+                                   FlatCand &fc) {
+    const uint32_t lane = lane_id();
+    int32_t P[FB], s0[FB], s1[FB], ent[FB], child[FB];
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+        const int64_t q = (w0 + u) * 64 + lane;
+        fc.ok[u] = q < NC;
+        P[u] = fc.ok[u] ? owner_prev[q >> 4] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+        s0[u] = fc.ok[u] ? sptr_prev[P[u]] : 0;
+        s1[u] = fc.ok[u] ? sptr_prev[P[u] + 1] : 1;
+    }
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+        const int64_t q = (w0 + u) * 64 + lane;
+        const int32_t r = fc.ok[u] ? (int32_t)(q - 16 * (int64_t)s0[u]) : 0;
+        const int32_t m4 = 4 * (s1[u] - s0[u]);  // candidates per child box
+        const int c = (r >= m4 ? 1 : 0) + (r >= 2 * m4 ? 1 : 0) + (r >= 3 * m4 ? 1 : 0);
+        const int32_t j = r - c * m4;
+        fc.b[u] = 4 * P[u] + c;
+        fc.first[u] = fc.ok[u] && j == 0;
+        child[u] = j & 3;
+        ent[u] = fc.ok[u] ? sidx_prev[s0[u] + (j >> 2)] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < FB; ++u) fc.cbox[u] = 4 * ent[u] + child[u];
+}
+
+// Candidates of level l: 16 |S_{l-1}| (the previous level's total).
+__device__ inline int64_t level_candidates(const int32_t *sptr_prev, int64_t nb_prev) {
+    return 16 * (int64_t)sptr_prev[nb_prev];
+}
+
+__global__ void __launch_bounds__(256) k_flat_count(int l, int L, double theta, const double4 *__restrict__ geomL,
+                                                    const int32_t *__restrict__ sptr_prev, int64_t nb_prev,
+                                                    const int32_t *__restrict__ sidx_pool,
+                                                    const int32_t *__restrict__ owner_prev,
+                                                    const int64_t *__restrict__ pool_state,
+                                                    uint64_t *__restrict__ bits, int32_t *__restrict__ cnt_s,
+                                                    int32_t *__restrict__ cnt_w) {
+    if (pool_state[2 * L + 4]) return;  // uniform
+    const int64_t NC = level_candidates(sptr_prev, nb_prev);
+    const int64_t nwords = (NC + 63) >> 6;
+    const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
+    const uint32_t lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t w0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * FB; w0 < nwords;
+         w0 += nwaves * FB) {
+        FlatCand fc;
+        flat_decode(w0, NC, owner_prev, sptr_prev, sidx_prev, fc);
+        double4 gb[FB], gc[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            gb[u] = fc.ok[u] ? geomL[fc.b[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+            gc[u] = fc.ok[u] ? geomL[fc.cbox[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            const bool weak = fc.ok[u] && theta_separated(theta, theta * theta, gb[u], gc[u]);
+            const uint64_t mw = __ballot(weak);
+            const uint64_t okm = __ballot(fc.ok[u]);
+            if (lane == (uint32_t)u && w0 + u < nwords) {
+                bits[w0 + u] = mw;
+                cnt_s[w0 + u] = (int32_t)__popcll(okm & ~mw);
+                cnt_w[w0 + u] = (int32_t)__popcll(mw);
+            }
+        }
+    }
+}
+
+// Exclusive scan of the per-word counts over the level's words (a length
+// known on the device): tile sums, one block over the tile sums (which also
+// writes the level totals as the last row pointers), and the tiles in place.
+__device__ inline int64_t level_words(const int32_t *sptr_prev, int64_t nb_prev) {
+    return (level_candidates(sptr_prev, nb_prev) + 63) >> 6;
+}
+
+__global__ void __launch_bounds__(WS_T) k_wscan_tiles(int L, const int32_t *__restrict__ sptr_prev, int64_t nb_prev,
+                                                      const int64_t *__restrict__ pool_state,
+                                                      const int32_t *__restrict__ cnt_s,
+                                                      const int32_t *__restrict__ cnt_w, int32_t *__restrict__ tsum,
+                                                      int ntile) {
+    __shared__ int32_t tmp[WS_T / 64];
+    const bool dead = pool_state[2 * L + 4] != 0;
+    const int64_t nwords = dead ? 0 : level_words(sptr_prev, nb_prev);
+    const int64_t base = (int64_t)blockIdx.x * WS_TILE + threadIdx.x * WS_PER;
+    int32_t a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < WS_PER; ++k) {
+        if (base + k < nwords) {
+            a += cnt_s[base + k];
+            b += cnt_w[base + k];
+        }
+    }
+    int32_t ta, tb;
+    block_excl_scan<WS_T>(a, tmp, ta);
+    block_excl_scan<WS_T>(b, tmp, tb);
+    if (threadIdx.x == 0) {
+        tsum[blockIdx.x] = ta;
+        tsum[ntile + blockIdx.x] = tb;
+    }
+}
+
+constexpr int WT_T = 1024;
+__global__ void __launch_bounds__(WT_T) k_wscan_top(int L, int ntile, const int64_t *__restrict__ pool_state,
+                                                    int32_t *__restrict__ tsum, int32_t *__restrict__ sptr_cur,
+                                                    int32_t *__restrict__ wptr_cur, int64_t nb) {
+    __shared__ int32_t tmp[WT_T / 64];
+    if (pool_state[2 * L + 4]) return;  // uniform
+    const int per = (ntile + WT_T - 1) / WT_T;
+    for (int arr = 0; arr < 2; ++arr) {
+        int32_t *ts = tsum + (int64_t)arr * ntile;
+        const int k0 = threadIdx.x * per;
+        int32_t sum = 0;
+        for (int k = k0; k < k0 + per && k < ntile; ++k) sum += ts[k];
+        int32_t total;
+        int32_t run = block_excl_scan<WT_T>(sum, tmp, total);
+        for (int k = k0; k < k0 + per && k < ntile; ++k) {
+            const int32_t v = ts[k];
+            ts[k] = run;
+            run += v;
+        }
+        if (threadIdx.x == 0) (arr ? wptr_cur : sptr_cur)[nb] = total;
+    }
+}
+
+__global__ void __launch_bounds__(WS_T) k_wscan_apply(int L, const int32_t *__restrict__ sptr_prev, int64_t nb_prev,
+                                                      const int64_t *__restrict__ pool_state,
+                                                      int32_t *__restrict__ cnt_s, int32_t *__restrict__ cnt_w,
+                                                      const int32_t *__restrict__ tsum, int ntile) {
+    __shared__ int32_t tmp[WS_T / 64];
+    if (pool_state[2 * L + 4]) return;  // uniform
+    const int64_t nwords = level_words(sptr_prev, nb_prev);
+    if ((int64_t)blockIdx.x * WS_TILE >= nwords) return;  // uniform
+    const int64_t base = (int64_t)blockIdx.x * WS_TILE + threadIdx.x * WS_PER;
+    for (int arr = 0; arr < 2; ++arr) {
+        int32_t *cnt = arr ? cnt_w : cnt_s;
+        int32_t v[WS_PER], sum = 0;
+#pragma unroll
+        for (int k = 0; k < WS_PER; ++k) {
+            v[k] = base + k < nwords ? cnt[base + k] : 0;
+            sum += v[k];
+        }
+        int32_t total;
+        int32_t run = block_excl_scan<WS_T>(sum, tmp, total) + tsum[(int64_t)arr * ntile + blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < WS_PER; ++k) {
+            if (base + k < nwords) cnt[base + k] = run;
+            run += v[k];
+        }
+    }
+}
+
+// Fill pass: every candidate's pool position from the word prefixes and its
+// bit; row pointers at each box's first candidate; owners for the next level;
+// near-field records on the finest level.
+__global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *__restrict__ geomL,
+                                                   const int32_t *__restrict__ sptr_prev, int64_t nb_prev,
+                                                   int32_t *__restrict__ sidx_pool, int32_t *__restrict__ widx_pool,
+                                                   const int32_t *__restrict__ owner_prev,
+                                                   int32_t *__restrict__ owner_cur,
+                                                   const int64_t *__restrict__ pool_state,
+                                                   const uint64_t *__restrict__ bits,
+                                                   const int32_t *__restrict__ pre_s, const int32_t *__restrict__ pre_w,
+                                                   int32_t *__restrict__ sptr_cur, int32_t *__restrict__ wptr_cur,
+                                                   const int32_t *__restrict__ stL, int2 *__restrict__ recj,
+                                                   float4 *__restrict__ recd) {
+    if (pool_state[2 * L + 4]) return;  // uniform
+    const int64_t NC = level_candidates(sptr_prev, nb_prev);
+    const int64_t nwords = (NC + 63) >> 6;
+    const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
+    int32_t *sout = sidx_pool + pool_state[l];
+    int32_t *wout = widx_pool + pool_state[(L + 2) + l];
+    const bool records = l == L;
+    const uint32_t lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t w0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * FB; w0 < nwords;
+         w0 += nwaves * FB) {
+        FlatCand fc;
+        flat_decode(w0, NC, owner_prev, sptr_prev, sidx_prev, fc);
+        uint64_t mw[FB];
+        int32_t ps[FB], pw[FB];
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            const bool wk = w0 + u < nwords;
+            mw[u] = wk ? bits[w0 + u] : 0ull;
+            ps[u] = wk ? pre_s[w0 + u] : 0;
+            pw[u] = wk ? pre_w[w0 + u] : 0;
+        }
+        double4 gb[FB], gc[FB];
+        int2 rr[FB];
+        if (records) {
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                const bool strong = fc.ok[u] && !((mw[u] >> lane) & 1);
+                gb[u] = strong ? geomL[fc.b[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+                gc[u] = strong ? geomL[fc.cbox[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+                rr[u] = strong ? make_int2(stL[fc.cbox[u]], stL[fc.cbox[u] + 1]) : make_int2(0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < FB; ++u) {
+            const uint64_t okm = __ballot(fc.ok[u]);
+            const uint64_t ms = okm & ~mw[u];
+            const int32_t posS = ps[u] + (int32_t)popc_below(ms);
+            const int32_t posW = pw[u] + (int32_t)popc_below(mw[u]);
+            if (fc.ok[u]) {
+                if ((mw[u] >> lane) & 1) {
+                    wout[posW] = fc.cbox[u];
+                } else {
+                    sout[posS] = fc.cbox[u];
+                    if (owner_cur) owner_cur[posS] = fc.b[u];
+                    if (records) {
+                        const double4 B = gb[u], C = gc[u];
+                        const float dxc = (float)(B.x - C.x), dyc = (float)(B.y - C.y);
+                        const float mag = fabsf(dxc) + fabsf(dyc) + (float)B.z + (float)C.z;
+                        recj[posS] = rr[u];
+                        recd[posS] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+                    }
+                }
+                if (fc.first[u]) {
+                    sptr_cur[fc.b[u]] = posS;
+                    wptr_cur[fc.b[u]] = posW;
+                }
+            }
+        }
     }
 }
 
@@ -323,58 +498,78 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     TreeState &t = c->tree;
     const int L = t.L;
     const int64_t nptr = ptr_offset(L + 1);
-    const int64_t maxnb = int64_t(1) << (2 * L);
     FMM2D_TRY(t.sptr.ensure(sizeof(int32_t) * nptr));
     FMM2D_TRY(t.wptr.ensure(sizeof(int32_t) * nptr));
     FMM2D_TRY(t.sidx.ensure(sizeof(int32_t) * cap_s));
     FMM2D_TRY(t.widx.ensure(sizeof(int32_t) * cap_w));
-    FMM2D_TRY(t.cnt_s.ensure(sizeof(int32_t) * maxnb));
-    FMM2D_TRY(t.cnt_w.ensure(sizeof(int32_t) * maxnb));
     FMM2D_TRY(t.pool_state.ensure(sizeof(int64_t) * (2 * L + 5)));
     int32_t *sptr = t.sptr.as<int32_t>(), *wptr = t.wptr.as<int32_t>();
     int64_t *ps = t.pool_state.as<int64_t>();
     const double4 *geom = t.geom.as<double4>();
     // Level 1 has 16 candidates (the root's children, four per box); later
-    // levels are guarded on the device by k_lists_advance, so the host never
-    // waits inside the level loop.
+    // levels are guarded on the device, so the host never waits inside the
+    // level loop.
     if (L >= 1 && 16 > limit) {
         *overflow = 2;
         return hipSuccess;
     }
-    FMM2D_TRY(t.bits.ensure(sizeof(uint64_t) * (size_t)((cap_s + cap_w) / 64 + maxnb + 2)));
-    uint64_t *bits = t.bits.as<uint64_t>();
     // near-field records of the finest level's strong entries (<= cap_s)
     FMM2D_TRY(t.nrec_j.ensure(sizeof(int2) * cap_s));
     FMM2D_TRY(t.nrec_d.ensure(sizeof(float4) * cap_s));
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L, stL,
                        geom, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
-    // levels of at most 1024 boxes: one workgroup, one launch
+    // levels of at most 64 boxes: one workgroup, one launch
     int K = 0;
     while (K < L && (int64_t(1) << (2 * (K + 1))) <= SMALL_BOXES) ++K;
+    // owners (rows) of the S entries of a level, for the next level's
+    // decoding; two buffers by level parity
+    int32_t *owner[2] = {nullptr, nullptr};
+    if (K < L) {
+        FMM2D_TRY(t.owner0.ensure(sizeof(int32_t) * cap_s));
+        FMM2D_TRY(t.owner1.ensure(sizeof(int32_t) * cap_s));
+        owner[0] = t.owner0.as<int32_t>();
+        owner[1] = t.owner1.as<int32_t>();
+    }
     if (K >= 1)
         hipLaunchKernelGGL(k_lists_small, dim3(1), dim3(SMALL_THREADS), 0, c->stream, K, L, theta, geom, sptr, wptr,
                            t.sidx.as<int32_t>(), t.widx.as<int32_t>(), ps, cap_s, cap_w, limit, stL,
-                           t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
-    for (int l = K + 1; l <= L; ++l) {
-        const int64_t nb = int64_t(1) << (2 * l);
-        int32_t *sp_prev = sptr + ptr_offset(l - 1), *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
-        const double4 *gL = geom + level_offset(l);
-        const unsigned grid = grid_for(nb, LW);
-        hipLaunchKernelGGL(k_lists_level<false>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
-                           t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), bits, sp_cur, wp_cur,
-                           t.sidx.as<int32_t>(), t.widx.as<int32_t>(), stL, nullptr, nullptr);
-        {
-            const int32_t *ins[2] = {t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>()};
-            int32_t *outs[2] = {sp_cur, wp_cur};
-            FMM2D_TRY(scan_exclusive_n(c, 2, ins, nb, outs));
+                           t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[K & 1]);
+    FMM2D_TRY(hipGetLastError());
+    if (K < L) {
+        // a level's candidates never exceed the free pool space (checked on
+        // the device before the level runs), so cap_s + cap_w bounds the words
+        const int64_t words = (cap_s + cap_w + 63) / 64 + 1;
+        const int ntile = (int)((words + WS_TILE - 1) / WS_TILE);
+        FMM2D_TRY(t.bits.ensure(sizeof(uint64_t) * (size_t)words));
+        FMM2D_TRY(t.cnt_s.ensure(sizeof(int32_t) * (size_t)words));
+        FMM2D_TRY(t.cnt_w.ensure(sizeof(int32_t) * (size_t)words));
+        FMM2D_TRY(c->scr.tiles.ensure(sizeof(int32_t) * 2 * (size_t)ntile));
+        uint64_t *bits = t.bits.as<uint64_t>();
+        int32_t *cs = t.cnt_s.as<int32_t>(), *cw = t.cnt_w.as<int32_t>(), *tsum = c->scr.tiles.as<int32_t>();
+        const int64_t wv_needed = (words + FB - 1) / FB;
+        const unsigned fgrid = (unsigned)std::min<int64_t>(FLAT_BLOCKS, (wv_needed + 3) / 4);
+        for (int l = K + 1; l <= L; ++l) {
+            const int64_t nb = int64_t(1) << (2 * l), nb_prev = nb >> 2;
+            const int32_t *sp_prev = sptr + ptr_offset(l - 1);
+            int32_t *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
+            const double4 *gL = geom + level_offset(l);
+            const int32_t *own_prev = owner[(l - 1) & 1];
+            int32_t *own_cur = l < L ? owner[l & 1] : nullptr;
+            hipLaunchKernelGGL(k_flat_count, dim3(fgrid), dim3(256), 0, c->stream, l, L, theta, gL, sp_prev, nb_prev,
+                               t.sidx.as<int32_t>(), own_prev, ps, bits, cs, cw);
+            hipLaunchKernelGGL(k_wscan_tiles, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps, cs, cw,
+                               tsum, ntile);
+            hipLaunchKernelGGL(k_wscan_top, dim3(1), dim3(WT_T), 0, c->stream, L, ntile, ps, tsum, sp_cur, wp_cur, nb);
+            hipLaunchKernelGGL(k_wscan_apply, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps, cs, cw,
+                               tsum, ntile);
+            hipLaunchKernelGGL(k_lists_advance, dim3(1), dim3(1), 0, c->stream, l, L, nb, sp_cur, wp_cur, ps, cap_s,
+                               cap_w, limit);
+            hipLaunchKernelGGL(k_flat_fill, dim3(fgrid), dim3(256), 0, c->stream, l, L, gL, sp_prev, nb_prev,
+                               t.sidx.as<int32_t>(), t.widx.as<int32_t>(), own_prev, own_cur, ps, bits, cs, cw,
+                               sp_cur, wp_cur, stL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
+            FMM2D_TRY(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_lists_advance, dim3(1), dim3(1), 0, c->stream, l, L, nb, sp_cur, wp_cur, ps, cap_s,
-                           cap_w, limit);
-        hipLaunchKernelGGL(k_lists_level<true>, dim3(grid), dim3(LW * 64), 0, c->stream, l, L, theta, gL, sp_prev,
-                           t.sidx.as<int32_t>(), ps, nb, t.cnt_s.as<int32_t>(), t.cnt_w.as<int32_t>(), bits, sp_cur, wp_cur,
-                           t.sidx.as<int32_t>(), t.widx.as<int32_t>(), stL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
-        FMM2D_TRY(hipGetLastError());
     }
     std::vector<int64_t> h(2 * L + 5);
     FMM2D_TRY(hipMemcpyAsync(h.data(), ps, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, c->stream));
