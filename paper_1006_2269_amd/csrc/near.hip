@@ -24,18 +24,26 @@ namespace {
 constexpr double HALF_LN2_D = 0.34657359027997264;  // ln(2)/2
 constexpr int NWB = 4;                                // wavefronts per block
 
-// FP32 near field.  Pipelined: while step s is evaluated, the source points
-// of step s+1 and the records of step s+2 are in flight.  Requires the
-// largest leaf to fit in GL lanes.
+// FP32 near field.  The segment's records (at most NEAR_SEG = 64, one per
+// lane) are staged in the wavefront's LDS slice once; each step reads its
+// record from LDS and the source points of the next step are loaded while the
+// current step is evaluated (two steps per loop iteration, so the pipeline
+// registers alternate instead of being copied).  Loads are unconditional
+// (clamped to a valid point, then masked) so the loop has no branches.
+// Requires the largest leaf to fit in GL lanes.
 template <int TM, int GL, bool ACC64>
 __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks, const int32_t *__restrict__ stL,
                                                      const float4 *__restrict__ src, const int32_t *__restrict__ sptr,
                                                      const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
                                                      const int2 *__restrict__ recj, const float4 *__restrict__ recd,
                                                      double *__restrict__ part) {
+    static_assert(NEAR_SEG <= 64, "one record per lane");
     constexpr int LPI = 64 / GL;  // source leaves per step
+    __shared__ int2 s_rj[NWB][64];
+    __shared__ float4 s_rd[NWB][64];
     const int64_t item = (int64_t)blockIdx.x * NWB + threadIdx.x / 64;
     if (item >= nitems) return;  // uniform per wavefront
+    const int wv = threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
     const int64_t sg = item / chunks;
     if (sg >= *nseg_ptr) return;
@@ -46,6 +54,16 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
     const int32_t a = stL[b] + ch * TM;
     if (a >= le) return;
     const int nt = (le - a) < TM ? (le - a) : TM;
+    const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
+    // records of this segment; lanes past its end hold empty records
+    {
+        const bool ok = t0 + lane < t1;
+        const int32_t tr = ok ? t0 + lane : t0;
+        const int2 rj = recj[tr];
+        const float4 rd = recd[tr];
+        s_rj[wv][lane] = ok ? rj : make_int2(0, 0);
+        s_rd[wv][lane] = rd;
+    }
     float tx[TM], ty[TM], acc[TM];
     double acc64[TM];
 #pragma unroll
@@ -56,38 +74,19 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
         acc[k] = 0.f;
         acc64[k] = 0.0;
     }
+    __builtin_amdgcn_wave_barrier();
     const int grp = lane / GL, jj = lane % GL;
-    const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
-    const float4 far = make_float4(1e18f, 1e18f, 0.f, 0.f);
-    int2 rj2 = make_int2(0, 0);
-    float4 rd1 = make_float4(0.f, 0.f, 0.f, 0.f), rd2 = rd1;
-    float4 sv1 = far;
-    {
-        const int32_t ta = t0 + grp, tb = t0 + LPI + grp;
-        if (ta < t1) {
-            const int2 rj1 = recj[ta];
-            rd1 = recd[ta];
-            if (jj < rj1.y - rj1.x) sv1 = src[rj1.x + jj];
-        }
-        if (tb < t1) {
-            rj2 = recj[tb];
-            rd2 = recd[tb];
-        }
-    }
-    int step = 0;
-    for (int32_t t = t0; t < t1; t += LPI, ++step) {
-        // issue: records of step s+2, sources of step s+1
-        const int32_t tc = t + 2 * LPI + grp;
-        int2 rj3 = make_int2(0, 0);
-        float4 rd3 = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (tc < t1) {
-            rj3 = recj[tc];
-            rd3 = recd[tc];
-        }
-        float4 sv2 = far;
-        if (jj < rj2.y - rj2.x) sv2 = src[rj2.x + jj];
-        // evaluate step s
-        const float sx = sv1.x - rd1.x, sy = sv1.y - rd1.y, q = sv1.z, thr = rd1.z;
+    const int nsteps = (t1 - t0 + LPI - 1) / LPI;
+    // source point of lane jj in the record of step st (far away when absent)
+    auto load_src = [&](int st) {
+        const int2 rj = s_rj[wv][st * LPI + grp];
+        const bool ok = jj < rj.y - rj.x;
+        const float4 v = src[ok ? rj.x + jj : 0];
+        return ok ? v : make_float4(1e18f, 1e18f, 0.f, 0.f);
+    };
+    auto eval = [&](float4 sv, int st) {
+        const float4 rd = s_rd[wv][st * LPI + grp];
+        const float sx = sv.x - rd.x, sy = sv.y - rd.y, q = sv.z, thr = rd.z;
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
             const float dx = tx[k] - sx, dy = ty[k] - sy;
@@ -95,17 +94,23 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
             const float lg = __log2f(r2);
             acc[k] = fmaf(q, (r2 > thr) ? lg : 0.f, acc[k]);  // coincident: log is masked, never multiplied
         }
-        if (ACC64 && (step & 7) == 7) {
+    };
+    float4 svA = load_src(0), svB;
+    for (int st = 0; st < nsteps; st += 2) {
+        const bool two = st + 1 < nsteps;
+        if (two) svB = load_src(st + 1);
+        eval(svA, st);
+        if (two) {
+            if (st + 2 < nsteps) svA = load_src(st + 2);
+            eval(svB, st + 1);
+        }
+        if (ACC64 && (st & 7) == 6) {  // binary64 flush every 8 steps
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
                 acc64[k] += (double)acc[k];
                 acc[k] = 0.f;
             }
         }
-        sv1 = sv2;
-        rd1 = rd2;
-        rj2 = rj3;
-        rd2 = rd3;
     }
     double mine = 0.0;
 #pragma unroll
