@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
             if (st + 2 < nsteps) svA = load_src(st + 2);
             eval(svB, st + 1);
         }
-        if (ACC64 && (st & 7) == 6) {  // binary64 flush every 8 steps
+        if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
                 acc64[k] += (double)acc[k];
