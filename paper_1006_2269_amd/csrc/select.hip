@@ -117,11 +117,16 @@ __global__ void __launch_bounds__(BT) k_bbox_final(const double *__restrict__ pa
     }
 }
 
+// Histogram totals of levels 5..10 are added by 1024 blocks; to keep the
+// same-address chains of those (integer, order-independent) atomics short,
+// block b adds into copy b % ACC_COPIES, and the final kernel sums the copies.
+constexpr int ACC_COPIES = 32;
+
 // zero the finest grid (blocks [0, nfine / 256)) and the counters (last block)
 __global__ void k_zero_grid(int32_t *__restrict__ fine, int64_t nfine, unsigned long long *__restrict__ acc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nfine) fine[i] = 0;
-    else if (i - nfine < 9 * FL) acc[i - nfine] = 0ull;
+    else if (i - nfine < ACC_COPIES * 9 * FL) acc[i - nfine] = 0ull;
 }
 
 __device__ inline int cell_coord(double v, double lo, double s) {
@@ -190,7 +195,7 @@ __global__ void __launch_bounds__(BT) k_pool_hist_hi(const int32_t *__restrict__
     }
     if (t < 9 * 6) {
         const int l = FL - t / 9, j = t % 9;
-        if (sh[t]) atomicAdd(&acc[9 * (l - 1) + j], sh[t]);
+        if (sh[t]) atomicAdd(&acc[(blockIdx.x % ACC_COPIES) * (9 * FL) + 9 * (l - 1) + j], sh[t]);
     }
 }
 
@@ -229,7 +234,12 @@ __global__ void __launch_bounds__(BT) k_pool_hist_lo(const int32_t *__restrict__
     else if (t == 1) f = log10(tol);
     else {
         const int l = (t - 2) / 9 + 1, j = (t - 2) % 9;
-        const unsigned long long v = l <= 4 ? sh[9 * (l - 1) + j] : acc[t - 2];
+        unsigned long long v = 0ull;
+        if (l <= 4) {
+            v = sh[9 * (l - 1) + j];
+        } else {
+            for (int k = 0; k < ACC_COPIES; ++k) v += acc[k * (9 * FL) + t - 2];
+        }
         f = j == 0 ? (double)v / (double)(int64_t(1) << (2 * l)) : (double)v / (double)ns;
     }
     feat[t] = (float)f;
@@ -303,18 +313,19 @@ hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64
     const int64_t nfine = int64_t(1) << (2 * FL);
     const int64_t stride = n > SAMPLE_MAX ? (n + SAMPLE_MAX - 1) / SAMPLE_MAX : 1;
     const int64_t ns = (n + stride - 1) / stride;
-    const size_t bytes = sizeof(double) * (5 * (size_t)nblk + 8) + sizeof(unsigned long long) * 9 * FL +
+    const size_t bytes = sizeof(double) * (5 * (size_t)nblk + 8) + sizeof(unsigned long long) * ACC_COPIES * 9 * FL +
                          sizeof(int32_t) * (size_t)(nfine + 1024) + 256;
     FMM2D_TRY(s.sel.ensure(bytes));
     char *base = s.sel.as<char>();
     double *part = reinterpret_cast<double *>(base);
     double *box = part + 5 * (size_t)nblk;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(box + 8);
-    int32_t *fine = reinterpret_cast<int32_t *>(acc + 9 * FL);
+    int32_t *fine = reinterpret_cast<int32_t *>(acc + ACC_COPIES * 9 * FL);
     int32_t *cnt5 = fine + nfine;
     hipLaunchKernelGGL(k_bbox_part, dim3(nblk), dim3(BT), 0, c->stream, x, y, n, part);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BT), 0, c->stream, part, nblk, box);
-    hipLaunchKernelGGL(k_zero_grid, dim3(grid_for(nfine + 9 * FL, 256)), dim3(256), 0, c->stream, fine, nfine, acc);
+    hipLaunchKernelGGL(k_zero_grid, dim3(grid_for(nfine + ACC_COPIES * 9 * FL, 256)), dim3(256), 0, c->stream, fine,
+                       nfine, acc);
     hipLaunchKernelGGL(k_cells, dim3(grid_for(ns, 256)), dim3(256), 0, c->stream, x, y, ns, stride, box, fine);
     hipLaunchKernelGGL(k_pool_hist_hi, dim3(1024), dim3(BT), 0, c->stream, fine, ns, acc, cnt5);
     hipLaunchKernelGGL(k_pool_hist_lo, dim3(1), dim3(BT), 0, c->stream, cnt5, n, ns, tol, acc, feat, blob, xin);
