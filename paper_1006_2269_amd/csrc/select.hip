@@ -121,12 +121,16 @@ __global__ void __launch_bounds__(BT) k_bbox_final(const double *__restrict__ pa
 // same-address chains of those (integer, order-independent) atomics short,
 // block b adds into copy b % ACC_COPIES, and the final kernel sums the copies.
 constexpr int ACC_COPIES = 32;
+// Likewise the finest counts: dense clusters put hundreds of sampled points
+// into one cell, so block b counts into grid copy b % GRID_COPIES and the
+// pooling kernel adds the copies as it loads them.
+constexpr int GRID_COPIES = 4;
 
-// zero the finest grid (blocks [0, nfine / 256)) and the counters (last block)
+// zero the finest grid copies and the counter copies
 __global__ void k_zero_grid(int32_t *__restrict__ fine, int64_t nfine, unsigned long long *__restrict__ acc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nfine) fine[i] = 0;
-    else if (i - nfine < ACC_COPIES * 9 * FL) acc[i - nfine] = 0ull;
+    if (i < GRID_COPIES * nfine) fine[i] = 0;
+    else if (i - GRID_COPIES * nfine < ACC_COPIES * 9 * FL) acc[i - GRID_COPIES * nfine] = 0ull;
 }
 
 __device__ inline int cell_coord(double v, double lo, double s) {
@@ -145,7 +149,7 @@ __global__ void k_cells(const double *__restrict__ x, const double *__restrict__
     const int64_t i = j * stride;
     const int ix = cell_coord(x[i] + 0.0, box[0], box[4]);
     const int iy = cell_coord(y[i] + 0.0, box[2], box[5]);
-    atomicAdd(&cnt[((int64_t)iy << FL) + ix], 1);
+    atomicAdd(&cnt[(int64_t)(blockIdx.x % GRID_COPIES) * (int64_t(1) << (2 * FL)) + ((int64_t)iy << FL) + ix], 1);
 }
 
 // occupied count and density class of one cell of level l into sh (the
@@ -171,7 +175,13 @@ __global__ void __launch_bounds__(BT) k_pool_hist_hi(const int32_t *__restrict__
     const int t = threadIdx.x;
     const int tx = blockIdx.x % 32, ty = blockIdx.x / 32;
     if (t < 9 * 6) sh[t] = 0ull;
-    for (int k = t; k < 1024; k += BT) ga[k] = fine[((int64_t)(ty * 32 + k / 32) << FL) + tx * 32 + k % 32];
+    for (int k = t; k < 1024; k += BT) {
+        const int64_t cell = ((int64_t)(ty * 32 + k / 32) << FL) + tx * 32 + k % 32;
+        int32_t v = 0;
+#pragma unroll
+        for (int g = 0; g < GRID_COPIES; ++g) v += fine[g * (int64_t(1) << (2 * FL)) + cell];
+        ga[k] = v;
+    }
     __syncthreads();
     int32_t *cur = ga, *nxt = gb;
     int side = 32;
@@ -314,18 +324,18 @@ hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64
     const int64_t stride = n > SAMPLE_MAX ? (n + SAMPLE_MAX - 1) / SAMPLE_MAX : 1;
     const int64_t ns = (n + stride - 1) / stride;
     const size_t bytes = sizeof(double) * (5 * (size_t)nblk + 8) + sizeof(unsigned long long) * ACC_COPIES * 9 * FL +
-                         sizeof(int32_t) * (size_t)(nfine + 1024) + 256;
+                         sizeof(int32_t) * (size_t)(GRID_COPIES * nfine + 1024) + 256;
     FMM2D_TRY(s.sel.ensure(bytes));
     char *base = s.sel.as<char>();
     double *part = reinterpret_cast<double *>(base);
     double *box = part + 5 * (size_t)nblk;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(box + 8);
     int32_t *fine = reinterpret_cast<int32_t *>(acc + ACC_COPIES * 9 * FL);
-    int32_t *cnt5 = fine + nfine;
+    int32_t *cnt5 = fine + GRID_COPIES * nfine;
     hipLaunchKernelGGL(k_bbox_part, dim3(nblk), dim3(BT), 0, c->stream, x, y, n, part);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BT), 0, c->stream, part, nblk, box);
-    hipLaunchKernelGGL(k_zero_grid, dim3(grid_for(nfine + ACC_COPIES * 9 * FL, 256)), dim3(256), 0, c->stream, fine,
-                       nfine, acc);
+    hipLaunchKernelGGL(k_zero_grid, dim3(grid_for(GRID_COPIES * nfine + ACC_COPIES * 9 * FL, 256)), dim3(256), 0,
+                       c->stream, fine, nfine, acc);
     hipLaunchKernelGGL(k_cells, dim3(grid_for(ns, 256)), dim3(256), 0, c->stream, x, y, ns, stride, box, fine);
     hipLaunchKernelGGL(k_pool_hist_hi, dim3(1024), dim3(BT), 0, c->stream, fine, ns, acc, cnt5);
     hipLaunchKernelGGL(k_pool_hist_lo, dim3(1), dim3(BT), 0, c->stream, cnt5, n, ns, tol, acc, feat, blob, xin);
