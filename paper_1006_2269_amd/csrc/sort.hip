@@ -8,7 +8,8 @@
 // 8-bit digits, three kernels per pass: tile histograms, a column scan per
 // (coordinate, digit), and a stable rank-and-scatter that stages each tile in
 // LDS in digit order so that global writes are runs of consecutive
-// addresses.  The key kernel also validates the input (finite, |v| <= 2^500)
+// addresses; the last pass writes the sorted coordinates, the order and the
+// ranks directly.  The key kernel also validates the input (finite, |v| <= 2^500)
 // and reduces the bitwise AND and OR of all keys per block; one small kernel
 // and one host read then give the digits on which all keys agree, whose
 // passes are skipped.
@@ -180,9 +181,16 @@ __global__ void __launch_bounds__(256) k_colscan(int32_t *__restrict__ hist, int
 // round, lanes of equal digit are ranked by ballot matching and the round's
 // leader advances the wave's counter.  The tile order (wave, round, lane) is
 // the input order, so the sort stays stable.
+// FINISH (the last pass): instead of the next key / value arrays, the tile
+// writes the sorted coordinate, the order (sorted position -> index) and the
+// rank (its inverse) directly.
+template <bool FINISH>
 __global__ void __launch_bounds__(SORT_THREADS) k_scatter(SortBufs B, int ping, int64_t n, int shift,
                                                           const int32_t *__restrict__ hist, int nblk,
-                                                          const int32_t *__restrict__ tot) {
+                                                          const int32_t *__restrict__ tot, double *__restrict__ xs,
+                                                          double *__restrict__ ys, int32_t *__restrict__ xorder,
+                                                          int32_t *__restrict__ yorder, int32_t *__restrict__ xrank,
+                                                          int32_t *__restrict__ yrank) {
     __shared__ uint64_t lk[SORT_TILE];
     __shared__ int32_t lv[SORT_TILE];
     __shared__ int32_t gpos[RADIX];    // global first position of this tile's digit d
@@ -246,8 +254,15 @@ __global__ void __launch_bounds__(SORT_THREADS) k_scatter(SortBufs B, int ping, 
         const uint64_t k = lk[s];
         const uint32_t d = (uint32_t)((k >> shift) & 0xff);
         const int64_t dst = (int64_t)gpos[d] + (s - lstart[d]);
-        kout[dst] = k;
-        vout[dst] = lv[s];
+        if (FINISH) {
+            const int32_t v = lv[s];
+            (c ? ys : xs)[dst] = from_key(k);
+            (c ? yorder : xorder)[dst] = v;
+            (c ? yrank : xrank)[v] = (int32_t)dst;
+        } else {
+            kout[dst] = k;
+            vout[dst] = lv[s];
+        }
     }
 }
 
@@ -317,19 +332,27 @@ hipError_t sort_finish(fmm2d_ctx *c, int64_t n, double *xs, double *ys, int32_t 
     sort_bufs(c, n, B);
     int32_t *hist = s.hist.as<int32_t>();
     int32_t *tot = hist + (size_t)2 * RADIX * nblk;
-    int ping = 0;
+    int ping = 0, last = -1;
+    for (int shift = 0; shift < 64; shift += 8)
+        if (((s.sort_differ >> shift) & 0xffull) != 0) last = shift;
     for (int shift = 0; shift < 64; shift += 8) {
         if (((s.sort_differ >> shift) & 0xffull) == 0) continue;
         hipLaunchKernelGGL(k_hist, dim3(nblk, 2), dim3(SORT_THREADS), 0, c->stream, B, ping, n, shift, hist, nblk);
         hipLaunchKernelGGL(k_colscan, dim3(RADIX, 2), dim3(256), 0, c->stream, hist, nblk, tot);
-        hipLaunchKernelGGL(k_scatter, dim3(nblk, 2), dim3(SORT_THREADS), 0, c->stream, B, ping, n, shift, hist, nblk,
-                           tot);
+        if (shift == last)
+            hipLaunchKernelGGL(k_scatter<true>, dim3(nblk, 2), dim3(SORT_THREADS), 0, c->stream, B, ping, n, shift,
+                               hist, nblk, tot, xs, ys, xorder, yorder, xrank, yrank);
+        else
+            hipLaunchKernelGGL(k_scatter<false>, dim3(nblk, 2), dim3(SORT_THREADS), 0, c->stream, B, ping, n, shift,
+                               hist, nblk, tot, xs, ys, xorder, yorder, xrank, yrank);
         FMM2D_TRY(hipGetLastError());
         ping ^= 1;
     }
     s.sort_n = -1;
-    hipLaunchKernelGGL(k_finish, dim3(grid_for(n, 256), 2), dim3(256), 0, c->stream, B, ping, n, xs, ys, xorder,
-                       yorder, xrank, yrank);
+    // every key equal (no pass ran): the input order is the sorted order
+    if (last < 0)
+        hipLaunchKernelGGL(k_finish, dim3(grid_for(n, 256), 2), dim3(256), 0, c->stream, B, ping, n, xs, ys, xorder,
+                           yorder, xrank, yrank);
     return hipGetLastError();
 }
 
