@@ -80,16 +80,28 @@ int fmm2d_destroy(fmm2d_ctx *c) {
     {
         DeviceGuard g(c->device);
         (void)hipStreamSynchronize(c->stream);
+        if (c->side) {
+            (void)hipStreamSynchronize(c->side);
+            (void)hipStreamDestroy(c->side);
+            (void)hipEventDestroy(c->ev_side_in);
+            (void)hipEventDestroy(c->ev_side_out);
+        }
         TreeState &t = c->tree;
         for (DevBuf *b : {&t.xsorted, &t.ysorted, &t.xorder, &t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1,
                           &t.starts, &t.rects, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
-                          &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d})
+                          &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d, &t.bits,
+                          &t.owner0, &t.owner1, &t.selfpos, &t.trans, &t.spart})
             b->release();
         EvalState &e = c->ev;
         c->tree.m2l_all.segoff.release();
         c->tree.m2l_all.table.release();
         c->tree.near_seg.segoff.release();
         c->tree.near_seg.table.release();
+        c->tree.near_up.segoff.release();
+        c->tree.near_up.table.release();
+        c->tree.near_lo.segoff.release();
+        c->tree.near_lo.table.release();
+        c->tree.lsum.release();
         for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();
         Scratch &s = c->scr;
         for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);

@@ -17,5 +17,10 @@ hipError_t m2l_all(fmm2d_ctx *c, int p, int mode);
 hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode);
 // list segments for the M2L and near-field kernels (sched.hip)
 hipError_t build_schedules(fmm2d_ctx *c);
+hipError_t ensure_near_full_schedule(fmm2d_ctx *c);
+// Leaves of 17 to 64 points: the FP32 near field takes each leaf pair once
+// (a leaf pair's 256 to 4096 point pairs then outweigh the per-record cost of
+// the transposed positions); smaller leaves take every ordered pair.
+inline bool pair_once_leaves(int64_t maxleaf) { return maxleaf > 16 && maxleaf <= 64; }
 
 }  // namespace fmm2d

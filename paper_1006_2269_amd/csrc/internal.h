@@ -87,11 +87,18 @@ struct TreeState {
     DevBuf sptr, wptr, sidx, widx, cnt_s, cnt_w;
     DevBuf bits;            // uint64: theta decisions of one level's candidates
     DevBuf owner0, owner1;  // int32: row (box) of each S entry of a level, by level parity
+    DevBuf selfpos;         // int32 [4^L]: position of leaf b in S_L(b) (level-relative)
+    DevBuf trans;           // int32 per S_L record t = (b, c) with c > b: the position of b in S_L(c)
+    DevBuf spart;           // float: source-side near-field partial sums per S_L record and source lane
     DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
     DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range, FP32 centre offset, threshold
     bool nrec_valid = false;
     Schedule m2l_all;               // weak lists of all levels (rows = global box ids)
-    Schedule near_seg;              // finest-level strong lists
+    Schedule near_seg;              // finest-level strong lists (built on first use)
+    bool near_seg_ready = false;
+    Schedule near_up;               // finest-level strong lists from each leaf's own entry on
+    Schedule near_lo;               // the same lists before each leaf's own entry
+    DevBuf lsum;                    // double: per near_lo segment and source lane, its entries' source sums
     std::vector<int64_t> s_off, w_off;  // host copy: pool offset of each level
     bool has_lists = false;
     double theta = 0.0;
@@ -151,6 +158,12 @@ struct fmm2d_ctx {
     int64_t list_limit = 2147483647LL;  // entries per level and list (FMM2D_LIST_LIMIT lowers it)
     int64_t cap_hint_s = 0, cap_hint_w = 0;  // list pool sizes that sufficed last time
     hipStream_t stream = nullptr;
+    // internal stream for work that may overlap the caller's stream (created
+    // on first use, default priority); ev_side_out marks the end of the last
+    // batch, which the caller's stream waits for before using its results
+    hipStream_t side = nullptr;
+    hipEvent_t ev_side_in = nullptr, ev_side_out = nullptr;
+    bool side_pending = false;
     std::string err;
     fmm2d::TreeState tree;
     fmm2d::EvalState ev;
@@ -167,6 +180,12 @@ namespace fmm2d {
 hipError_t sort_prepare(fmm2d_ctx *c, const double *x, const double *y, int64_t n, bool *bad_input);
 hipError_t sort_finish(fmm2d_ctx *c, int64_t n, double *xs, double *ys, int32_t *xorder, int32_t *yorder,
                        int32_t *xrank, int32_t *yrank);
+// sched.hip: the side stream (see fmm2d_ctx): begin a batch after the work
+// queued so far on the caller's stream, end it, and make the caller's stream
+// wait for the last batch
+hipError_t side_begin(fmm2d_ctx *c);
+hipError_t side_end(fmm2d_ctx *c);
+hipError_t side_join(fmm2d_ctx *c);
 // scan.hip: exclusive scan of int32 in[n] into out[n+1] (out[n] = total)
 hipError_t scan_exclusive(fmm2d_ctx *c, const int32_t *in, int64_t n, int32_t *out);
 // the same for k (1 or 2) arrays of one length, in the same launches

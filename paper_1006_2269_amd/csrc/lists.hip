@@ -70,7 +70,8 @@ __device__ inline bool theta_separated(double theta, double theta2, double4 gb, 
 // (L = 0) also the near-field record of that single strong entry, written
 // as the finest fill pass writes the others.
 __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool, int64_t *pool_state, int L,
-                             const int32_t *stL, const double4 *geom0, int2 *recj, float4 *recd) {
+                             const int32_t *stL, const double4 *geom0, int2 *recj, float4 *recd, int32_t *owner0,
+                             int32_t *selfpos) {
     sptr0[0] = 0;
     sptr0[1] = 1;
     wptr0[0] = 0;
@@ -79,6 +80,8 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool,
     for (int k = 0; k < 2 * L + 5; ++k) pool_state[k] = 0;
     pool_state[1] = 1;  // S offset of level 1
     if (L == 0) {
+        owner0[0] = 0;
+        selfpos[0] = 0;
         const double4 g = geom0[0];
         const float dxc = (float)(g.x - g.x), dyc = (float)(g.y - g.y);
         const float mag = fabsf(dxc) + fabsf(dyc) + (float)g.z + (float)g.z;
@@ -100,8 +103,8 @@ __device__ inline void box_lists(int l, int L, double theta, const double4 *__re
                                  const int32_t *__restrict__ sptr_prev, const int32_t *__restrict__ sidx_prev,
                                  int32_t &cs, int32_t &cw, int32_t tS, int32_t *__restrict__ so,
                                  int32_t *__restrict__ wo, int32_t *__restrict__ own,
-                                 const int32_t *__restrict__ stL, int2 *__restrict__ recj,
-                                 float4 *__restrict__ recd) {
+                                 int32_t *__restrict__ self, const int32_t *__restrict__ stL,
+                                 int2 *__restrict__ recj, float4 *__restrict__ recd) {
     const uint32_t lane = lane_id();
     const int64_t P = b >> 2;
     const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
@@ -129,6 +132,7 @@ __device__ inline void box_lists(int l, int L, double theta, const double4 *__re
                 const int32_t pos = cs + (int32_t)popc_below(ms);
                 so[pos] = cbox;
                 if (own) own[tS + pos] = (int32_t)b;
+                if (self && cbox == b) self[b] = tS + pos;
                 if (records) {
                     const int32_t t = tS + pos;
                     const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
@@ -188,7 +192,8 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
                                                               int64_t *__restrict__ pool_state, int64_t cap_s,
                                                               int64_t cap_w, int64_t limit,
                                                               const int32_t *__restrict__ stL, int2 *__restrict__ recj,
-                                                              float4 *__restrict__ recd, int32_t *__restrict__ owner) {
+                                                              float4 *__restrict__ recd, int32_t *__restrict__ owner,
+                                                              int32_t *__restrict__ selfpos) {
     __shared__ int32_t ns[SMALL_BOXES], nw[SMALL_BOXES];
     __shared__ int32_t tmp[SMALL_THREADS / 64];
     __shared__ int flag;
@@ -207,8 +212,8 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
         const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
         for (int64_t b = wv; b < nb; b += NWV) {
             int32_t cs, cw;
-            box_lists<false>(l, L, theta, gL, b, sp_prev, sidx_prev, cs, cw, 0, nullptr, nullptr, nullptr, stL,
-                             nullptr, nullptr);
+            box_lists<false>(l, L, theta, gL, b, sp_prev, sidx_prev, cs, cw, 0, nullptr, nullptr, nullptr, nullptr,
+                             stL, nullptr, nullptr);
             if (lane_id() == 0) {
                 ns[b] = cs;
                 nw[b] = cw;
@@ -240,7 +245,8 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
         for (int64_t b = wv; b < nb; b += NWV) {
             int32_t cs, cw;
             box_lists<true>(l, L, theta, gL, b, sp_prev, sidx_prev, cs, cw, sp_cur[b], sidx_pool + so0 + sp_cur[b],
-                            widx_pool + wo0 + wp_cur[b], l == K && K < L ? owner : nullptr, stL, recj, recd);
+                            widx_pool + wo0 + wp_cur[b], l == K ? owner : nullptr, l == L ? selfpos : nullptr, stL,
+                            recj, recd);
         }
         __syncthreads();
     }
@@ -428,7 +434,7 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
                                                    const int32_t *__restrict__ pre_s, const int32_t *__restrict__ pre_w,
                                                    int32_t *__restrict__ sptr_cur, int32_t *__restrict__ wptr_cur,
                                                    const int32_t *__restrict__ stL, int2 *__restrict__ recj,
-                                                   float4 *__restrict__ recd) {
+                                                   float4 *__restrict__ recd, int32_t *__restrict__ selfpos) {
     if (pool_state[2 * L + 4]) return;  // uniform
     const int64_t NC = level_candidates(sptr_prev, nb_prev);
     const int64_t nwords = (NC + 63) >> 6;
@@ -474,6 +480,7 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
                 } else {
                     sout[posS] = fc.cbox[u];
                     if (owner_cur) owner_cur[posS] = fc.b[u];
+                    if (records && fc.cbox[u] == fc.b[u]) selfpos[fc.b[u]] = posS;
                     if (records) {
                         const double4 B = gb[u], C = gc[u];
                         const float dxc = (float)(B.x - C.x), dyc = (float)(B.y - C.y);
@@ -498,6 +505,7 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     TreeState &t = c->tree;
     const int L = t.L;
     const int64_t nptr = ptr_offset(L + 1);
+    FMM2D_TRY(side_join(c));  // side-stream work still reading the previous lists
     FMM2D_TRY(t.sptr.ensure(sizeof(int32_t) * nptr));
     FMM2D_TRY(t.wptr.ensure(sizeof(int32_t) * nptr));
     FMM2D_TRY(t.sidx.ensure(sizeof(int32_t) * cap_s));
@@ -517,24 +525,23 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     FMM2D_TRY(t.nrec_j.ensure(sizeof(int2) * cap_s));
     FMM2D_TRY(t.nrec_d.ensure(sizeof(float4) * cap_s));
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
+    // owners (rows) of the S entries of a level, for the next level's
+    // decoding and (finest level) the near field; two buffers by level
+    // parity; the position of every leaf in its own list
+    FMM2D_TRY(t.owner0.ensure(sizeof(int32_t) * cap_s));
+    FMM2D_TRY(t.owner1.ensure(sizeof(int32_t) * cap_s));
+    FMM2D_TRY(t.selfpos.ensure(sizeof(int32_t) * (size_t)(int64_t(1) << (2 * L))));
+    int32_t *owner[2] = {t.owner0.as<int32_t>(), t.owner1.as<int32_t>()};
+    int32_t *selfpos = t.selfpos.as<int32_t>();
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L, stL,
-                       geom, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
+                       geom, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[0], selfpos);
     // levels of at most 64 boxes: one workgroup, one launch
     int K = 0;
     while (K < L && (int64_t(1) << (2 * (K + 1))) <= SMALL_BOXES) ++K;
-    // owners (rows) of the S entries of a level, for the next level's
-    // decoding; two buffers by level parity
-    int32_t *owner[2] = {nullptr, nullptr};
-    if (K < L) {
-        FMM2D_TRY(t.owner0.ensure(sizeof(int32_t) * cap_s));
-        FMM2D_TRY(t.owner1.ensure(sizeof(int32_t) * cap_s));
-        owner[0] = t.owner0.as<int32_t>();
-        owner[1] = t.owner1.as<int32_t>();
-    }
     if (K >= 1)
         hipLaunchKernelGGL(k_lists_small, dim3(1), dim3(SMALL_THREADS), 0, c->stream, K, L, theta, geom, sptr, wptr,
                            t.sidx.as<int32_t>(), t.widx.as<int32_t>(), ps, cap_s, cap_w, limit, stL,
-                           t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[K & 1]);
+                           t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[K & 1], selfpos);
     FMM2D_TRY(hipGetLastError());
     if (K < L) {
         // a level's candidates never exceed the free pool space (checked on
@@ -555,7 +562,7 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
             int32_t *sp_cur = sptr + ptr_offset(l), *wp_cur = wptr + ptr_offset(l);
             const double4 *gL = geom + level_offset(l);
             const int32_t *own_prev = owner[(l - 1) & 1];
-            int32_t *own_cur = l < L ? owner[l & 1] : nullptr;
+            int32_t *own_cur = owner[l & 1];
             hipLaunchKernelGGL(k_flat_count, dim3(fgrid), dim3(256), 0, c->stream, l, L, theta, gL, sp_prev, nb_prev,
                                t.sidx.as<int32_t>(), own_prev, ps, bits, cs, cw);
             hipLaunchKernelGGL(k_wscan_tiles, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps, cs, cw,
@@ -567,7 +574,7 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
                                cap_w, limit);
             hipLaunchKernelGGL(k_flat_fill, dim3(fgrid), dim3(256), 0, c->stream, l, L, gL, sp_prev, nb_prev,
                                t.sidx.as<int32_t>(), t.widx.as<int32_t>(), own_prev, own_cur, ps, bits, cs, cw,
-                               sp_cur, wp_cur, stL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>());
+                               sp_cur, wp_cur, stL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), selfpos);
             FMM2D_TRY(hipGetLastError());
         }
     }

@@ -131,6 +131,147 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
     if (lane < TM) part[item * TM + lane] = mine;
 }
 
+// FP32 near field taking each leaf pair once (leaves of 17 to 64 points).
+// Work items cover the strong list of target leaf b from b's own entry on
+// (sources c >= b; the lists are symmetric and ascending).  The log of a pair
+// serves both sides: the target's sum (q_c log r, per target as below) and,
+// when c != b, the source's (q_b log r, summed over the wavefront's targets
+// in the source's lane and written to spart at leaf c's own entry for b, per
+// lane, where leaf c's reduction reads its entries in order).  With CH = 4 chunks of targets
+// per leaf the four wavefronts of a block hold the four chunks of one
+// segment, and their per-step source sums are added in LDS before the write.
+//
+// The segment's records (at most NEAR_SEG = 64, one per lane) are staged in
+// the wavefront's LDS slice once; the source points of the next step are
+// loaded while the current step is evaluated (two steps per loop iteration,
+// so the pipeline registers alternate instead of being copied).
+template <int TM, int GL, int CH, bool ACC64>
+__global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int32_t *__restrict__ stL,
+                                                      const float4 *__restrict__ src, const int32_t *__restrict__ sptr,
+                                                      const int32_t *__restrict__ selfpos,
+                                                      const int32_t *__restrict__ transU,
+                                                      const int2 *__restrict__ segtab,
+                                                      const int32_t *__restrict__ nseg_ptr,
+                                                      const int2 *__restrict__ recj, const float4 *__restrict__ recd,
+                                                      double *__restrict__ part, float *__restrict__ spart) {
+    static_assert(NEAR_SEG <= 64, "one record per lane");
+    static_assert(CH == 1 || CH == NWB, "chunks of one segment fill a block");
+    constexpr int LPI = 64 / GL;  // source leaves per step
+    __shared__ int2 s_rj[NWB][64];
+    __shared__ float4 s_rd[NWB][64];
+    __shared__ int32_t s_tu[NWB][64];
+    __shared__ float s_sp[CH == 1 ? 1 : 2][CH == 1 ? 1 : NWB][64];
+    const int wv = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int64_t item = (int64_t)blockIdx.x * NWB + wv;
+    if (item >= nitems) return;  // CH = 4: uniform per block (nitems is a multiple of NWB)
+    const int64_t sg = item / CH;
+    const int ch = (int)(item - sg * CH);
+    if (sg >= *nseg_ptr) return;  // CH = 4: uniform per block
+    const int2 se = segtab[sg];
+    const int64_t b = se.x;
+    const int32_t lb = stL[b], le = stL[b + 1];
+    const int32_t a = lb + ch * TM;
+    const int nt = (le - a) < 0 ? 0 : ((le - a) < TM ? (le - a) : TM);  // CH = 4: a chunk may be empty
+    const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
+    const int32_t tself = selfpos[b];
+    {
+        const bool ok = t0 + lane < t1;
+        const int32_t tr = ok ? t0 + lane : t0;
+        const int2 rj = recj[tr];
+        const float4 rd = recd[tr];
+        s_rj[wv][lane] = ok ? rj : make_int2(0, 0);
+        s_rd[wv][lane] = rd;
+        s_tu[wv][lane] = (ok && tr != tself) ? transU[tr] : 0;
+    }
+    float tx[TM], ty[TM], tq[TM], acc[TM];
+    double acc64[TM];
+#pragma unroll
+    for (int k = 0; k < TM; ++k) {
+        const float4 s = src[k < nt ? a + k : lb];
+        tx[k] = s.x;
+        ty[k] = s.y;
+        tq[k] = k < nt ? s.z : 0.f;  // absent targets send nothing to the sources
+        acc[k] = 0.f;
+        acc64[k] = 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int grp = lane / GL, jj = lane % GL;
+    const int nsteps = (t1 - t0 + LPI - 1) / LPI;
+    auto load_src = [&](int st) {
+        const int2 rj = s_rj[wv][st * LPI + grp];
+        const bool ok = jj < rj.y - rj.x;
+        const float4 v = src[ok ? rj.x + jj : 0];
+        return ok ? v : make_float4(1e18f, 1e18f, 0.f, 0.f);
+    };
+    // one step: both sides of every pair of this lane's source and the
+    // wavefront's targets; the source side goes out at once
+    auto eval = [&](float4 sv, int st) {
+        const int r = st * LPI + grp;
+        const float4 rd = s_rd[wv][r];
+        const float sx = sv.x - rd.x, sy = sv.y - rd.y, q = sv.z, thr = rd.z;
+        float sacc = 0.f;
+#pragma unroll
+        for (int k = 0; k < TM; ++k) {
+            const float dx = tx[k] - sx, dy = ty[k] - sy;
+            const float r2 = dx * dx + dy * dy;
+            const float lg = (r2 > thr) ? __log2f(r2) : 0.f;  // coincident: log is masked, never multiplied
+            acc[k] = fmaf(q, lg, acc[k]);
+            sacc = fmaf(tq[k], lg, sacc);
+        }
+        const int32_t t = t0 + r;
+        const int2 rj = s_rj[wv][r];
+        const bool out = t < t1 && t != tself && jj < rj.y - rj.x;
+        const int64_t dst = (int64_t)s_tu[wv][r] * GL + jj;  // leaf c's own entry for b
+        if constexpr (CH == 1) {
+            if (out) spart[dst] = sacc;
+        } else {
+            s_sp[st & 1][wv][lane] = sacc;
+            __syncthreads();
+            if (wv == 0 && out) {
+                float v = 0.f;
+#pragma unroll
+                for (int w = 0; w < NWB; ++w) v += s_sp[st & 1][w][lane];
+                spart[dst] = v;
+            }
+        }
+    };
+    float4 svA = load_src(0), svB;
+    for (int st = 0; st < nsteps; st += 2) {
+        const bool two = st + 1 < nsteps;
+        if (two) svB = load_src(st + 1);
+        eval(svA, st);
+        if (two) {
+            if (st + 2 < nsteps) svA = load_src(st + 2);
+            eval(svB, st + 1);
+        }
+        if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps
+#pragma unroll
+            for (int k = 0; k < TM; ++k) {
+                acc64[k] += (double)acc[k];
+                acc[k] = 0.f;
+            }
+        }
+    }
+    double mine = 0.0;
+#pragma unroll
+    for (int k = 0; k < TM; ++k) {
+        double v;
+        if (ACC64) {
+            v = acc64[k] + (double)acc[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        } else {
+            float w = acc[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+            v = (double)w;
+        }
+        if (lane == k) mine = v;
+    }
+    if (lane < TM) part[item * TM + lane] = mine;
+}
+
 // FP32 near field for leaves larger than 64 points: a lane walks its source
 // leaf 64 points at a time (not pipelined).
 template <int TM, bool ACC64>
@@ -304,6 +445,103 @@ __global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale
     phi_leaf[i] = v.re + scale * near;
 }
 
+// Source-side sums of the entries of S_L(c) before c's own (written there by
+// the near field), one wavefront per segment of at most NEAR_SEG entries: lane
+// group g of 64 / GL takes entries g, g + 64/GL, ..., then the groups are
+// added (fixed order) and lane jj < GL writes the segment's sum for point jj.
+template <int GL>
+__global__ void __launch_bounds__(256) k_near_lsum(const int2 *__restrict__ segtab,
+                                                   const int32_t *__restrict__ nseg_ptr,
+                                                   const int32_t *__restrict__ selfpos, const float *__restrict__ spart,
+                                                   double *__restrict__ lsum) {
+    constexpr int LPI = 64 / GL;
+    const int64_t sg = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (sg >= *nseg_ptr) return;  // uniform per wavefront
+    const int lane = threadIdx.x % 64, grp = lane / GL, jj = lane % GL;
+    const int2 se = segtab[sg];
+    const int32_t u1 = (se.y + NEAR_SEG) < selfpos[se.x] ? (se.y + NEAR_SEG) : selfpos[se.x];
+    double v = 0.0;
+    for (int32_t u = se.y + grp; u < u1; u += LPI) v += (double)spart[(int64_t)u * GL + jj];
+#pragma unroll
+    for (int off = GL; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    if (lane < GL) lsum[sg * GL + jj] = v;
+}
+
+// Per point of the pair-once path: its leaf's target-side segment sums, then
+// the source-side sums of the leaves c < b (segment sums of the entries of
+// S_L(b) before b's own), times `scale`, plus L2P.
+__global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, double scale,
+                                  const int32_t *__restrict__ leafid, const int32_t *__restrict__ stL,
+                                  const int32_t *__restrict__ segoff, const double *__restrict__ part,
+                                  const int32_t *__restrict__ losegoff, const double *__restrict__ lsum,
+                                  const double4 *__restrict__ geomL, const double *__restrict__ px,
+                                  const double *__restrict__ py, const cd *__restrict__ BL,
+                                  double *__restrict__ phi_leaf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = leafid[i];
+    const int32_t off = (int32_t)(i - stL[b]);
+    const int ch = off / tm, k = off - ch * tm;
+    double near = 0.0;
+    for (int32_t sg = segoff[b]; sg < segoff[b + 1]; ++sg) near += part[((int64_t)sg * ch_n + ch) * tm + k];
+    for (int32_t sg = losegoff[b]; sg < losegoff[b + 1]; ++sg) near += lsum[(int64_t)sg * gl + off];
+    const double4 g = geomL[b];
+    const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
+    const cd *Bb = BL + (int64_t)b * (p + 1);
+    cd v = Bb[p];
+    for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
+    phi_leaf[i] = v.re + scale * near;
+}
+
+// FP32 paths with leaves of at most 64 points: each leaf pair once.
+template <int TM, int GL, int CH>
+hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode) {
+    TreeState &t = c->tree;
+    EvalState &e = c->ev;
+    const int L = t.L;
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    const Schedule &sc = t.near_up;
+    const int64_t nitems = sc.bound * CH;  // CH = 4: one block per segment
+    const int64_t offL = level_offset(L);
+    const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
+    const double4 *gL = t.geom.as<double4>() + offL;
+    const cd *BL = e.B.as<cd>() + offL * (p + 1);
+    const int32_t *sp = t.sptr.as<int32_t>() + ptr_offset(L);
+    const int64_t ns = t.s_off[L + 1] - t.s_off[L];
+    FMM2D_TRY(e.part.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
+    FMM2D_TRY(t.spart.ensure(sizeof(float) * (size_t)(ns > 0 ? ns : 1) * GL));
+    double *part = e.part.as<double>();
+    float *spart = t.spart.as<float>();
+    const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
+    FMM2D_TRY(side_join(c));  // the transposed positions
+    {
+        PhaseScope kernel_scope(c, PH_NEAR_KERNEL);  // the near-field kernel alone
+        if (mode == FMM2D_MODE_FP32_ACC64)
+            hipLaunchKernelGGL((k_near32s<TM, GL, CH, true>), grid, block, 0, c->stream, nitems, stL,
+                               e.src.as<float4>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
+                               sc.table.as<int2>(),
+                               sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
+                               spart);
+        else
+            hipLaunchKernelGGL((k_near32s<TM, GL, CH, false>), grid, block, 0, c->stream, nitems, stL,
+                               e.src.as<float4>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
+                               sc.table.as<int2>(),
+                               sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
+                               spart);
+    }
+    FMM2D_TRY(hipGetLastError());
+    const Schedule &lo = t.near_lo;
+    FMM2D_TRY(t.lsum.ensure(sizeof(double) * (size_t)(lo.bound > 0 ? lo.bound : 1) * GL));
+    hipLaunchKernelGGL(k_near_lsum<GL>, dim3(grid_for(lo.bound > 0 ? lo.bound : 1, 4)), dim3(256), 0, c->stream,
+                       lo.table.as<int2>(), lo.segoff.as<int32_t>() + nleaf, t.selfpos.as<int32_t>(), spart,
+                       t.lsum.as<double>());
+    hipLaunchKernelGGL(k_near_reduce_sym, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, CH, GL,
+                       HALF_LN2_D, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part,
+                       lo.segoff.as<int32_t>(), t.lsum.as<double>(), gL, t.px.as<double>(), t.py.as<double>(), BL,
+                       e.phi_leaf.as<double>());
+    return hipGetLastError();
+}
+
 template <int TM, int GL>
 hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf) {
     TreeState &t = c->tree;
@@ -374,6 +612,13 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode) {
     // GL lanes per source leaf: the smallest power of two >= the largest leaf
     // (capped at 64; larger leaves take the non-pipelined kernel)
     const int ml = (int)(maxleaf < (int64_t)1 << 30 ? maxleaf : (int64_t)1 << 30);
+    if (mode != FMM2D_MODE_FP64 && pair_once_leaves(ml)) {
+        // each leaf pair once, the four chunks of targets of a leaf in the
+        // four wavefronts of a block
+        if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode);
+        return launch_near_sym<16, 64, 4>(c, p, mode);
+    }
+    FMM2D_TRY(ensure_near_full_schedule(c));
     if (ml <= 8) return launch_near<8, 8>(c, p, mode, ml);
     if (ml <= 16) return launch_near<16, 16>(c, p, mode, ml);
     if (ml <= 32) return launch_near<16, 32>(c, p, mode, ml);

@@ -57,6 +57,10 @@ TREE_CASES = {
     # fine depths finished in LDS from depth 3 (odd: the x split lines of
     # depth 2 come from the global passes)
     "uniform_20k_L5": (lambda: W.uniform(20000, 13), 5),
+    # leaves of 50 and 63 points: the FP32 near field in four chunks of 16
+    # targets per leaf (one block of four wavefronts per list segment)
+    "uniform_3200_L3": (lambda: W.uniform(3200, 14), 3),
+    "duplicates_4k_L3": (lambda: _duplicates(4000, 8), 3),
     "mixed_scaled_20k_L6": (lambda: W.mixed_1m(scale=0.02), 6),
     "clustered_scaled_20k_L6": (lambda: W.clustered_10m(scale=0.002), 6),
     "clustered_scaled_30k_L6": (lambda: W.clustered_10m(scale=0.003, seed=2003), 6),
