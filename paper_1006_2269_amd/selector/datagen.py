@@ -3,12 +3,14 @@
 For each layout (``workloads.selector_layout``): its density features, the
 binary64 judge at 1000 sampled targets, and for every level count L in
 {L0 - 1, ..., L0 + 2} (L0 = round(log4(N / 16))) and theta in
-{0.35, ..., 0.75} the GPU times of build_tree and connectivity, then for
+{0.35, ..., 0.75} the GPU times of build_tree and connectivity (warm: the
+least of three calls after one that may allocate), then for
 p = 4, 5, ... the time of evaluate (mode fp32_acc64) and the normwise error
 against the judge, until the error drops below 5e-8 or stops improving (the
 FP32 near field sets a floor).
 
     python -m paper_1006_2269_amd.selector.datagen --first 50000 --count 400 --out gpurun_out/runs.npz
+    python -m paper_1006_2269_amd.selector.datagen --retime runs.npz --out runs_retimed.npz
 """
 from __future__ import annotations
 
@@ -40,6 +42,32 @@ def phase_ms(f, names):
     return sum(t[k][0] for k in names)
 
 
+REPEATS = 3  # tree and list timings: the least of this many warm calls
+
+
+def time_tree(f, x, y, L):
+    """build_tree time at L, warm: the first call on a layout allocates."""
+    f.build_tree(x, y, L)
+    best = math.inf
+    for _ in range(REPEATS):
+        f.timing(True)
+        f.build_tree(x, y, L)
+        best = min(best, phase_ms(f, ["tree"]))
+    return best
+
+
+def time_lists(f, theta):
+    """connectivity time at theta on the current tree, warm (see time_tree);
+    raises FMM2DError where a level's lists exceed the int32 entry limit."""
+    f.connectivity(theta)
+    best = math.inf
+    for _ in range(REPEATS):
+        f.timing(True)
+        f.connectivity(theta)
+        best = min(best, phase_ms(f, ["lists"]))
+    return best
+
+
 def run_layout(f, ps, torch, samples=1000):
     from paper_1006_2269_amd import workloads as W
     from paper_1006_2269_amd.fmm import FMM2DError
@@ -55,16 +83,12 @@ def run_layout(f, ps, torch, samples=1000):
     out = torch.empty_like(q)
     rows = []
     for L in candidate_levels(ps.n):
-        f.timing(True)
-        f.build_tree(x, y, L)
-        t_tree = phase_ms(f, ["tree"])
+        t_tree = time_tree(f, x, y, L)
         for th in THETAS:
-            f.timing(True)
             try:
-                f.connectivity(th)
+                t_lists = time_lists(f, th)
             except FMM2DError:
                 continue  # a level's lists exceed the int32 entry limit
-            t_lists = phase_ms(f, ["lists"])
             best, stale = math.inf, 0
             for p in range(P_MIN, P_MAX + 1):
                 f.evaluate(q, p, MODE, out=out)   # warm (allocations)
@@ -81,8 +105,38 @@ def run_layout(f, ps, torch, samples=1000):
     return feat, rows
 
 
+def retime(f, src, out, lo, hi, torch):
+    """Re-measure the tree and list columns of an existing run table (warm,
+    least of REPEATS calls), keeping its evaluate times and errors."""
+    from paper_1006_2269_amd import workloads as W
+    from paper_1006_2269_amd.fmm import FMM2DError
+
+    d = np.load(src)
+    runs = d["runs"].copy()
+    t0 = time.time()
+    for i, seed in enumerate(d["seeds"]):
+        ps = W.selector_layout(int(seed), lo, hi)
+        assert ps.n == int(d["n"][i]), "layout %d does not regenerate" % i
+        x = torch.from_numpy(ps.x).to(f.device)
+        y = torch.from_numpy(ps.y).to(f.device)
+        mine = runs[:, 0] == i
+        for L in np.unique(runs[mine, 1]):
+            t_tree = time_tree(f, x, y, int(L))
+            rows_l = mine & (runs[:, 1] == L)
+            runs[rows_l, 4] = t_tree
+            for th in np.unique(runs[rows_l, 2]):
+                try:
+                    t_lists = time_lists(f, float(th))
+                except FMM2DError:
+                    continue
+                runs[rows_l & (runs[:, 2] == th), 5] = t_lists
+        print("[retime] layout %d seed %d n=%d  %.0f s" % (i, seed, ps.n, time.time() - t0), flush=True)
+    np.savez_compressed(out, **{k: d[k] for k in d.files if k != "runs"}, runs=runs)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--retime", help="existing run table whose tree and list times are measured again")
     ap.add_argument("--first", type=int, default=50000)
     ap.add_argument("--count", type=int, default=400)
     ap.add_argument("--lo", type=float, default=4.0)
@@ -95,6 +149,10 @@ def main():
     from paper_1006_2269_amd.fmm import FMM2D
 
     f = FMM2D(0)
+    if args.retime:
+        retime(f, args.retime, args.out, args.lo, args.hi, torch)
+        f.close()
+        return 0
     feats, ns, table = [], [], []
     t0 = time.time()
     for i in range(args.count):
