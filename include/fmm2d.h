@@ -186,9 +186,11 @@ int fmm2d_mlp_grad(fmm2d_ctx *ctx, const float *params, const float *X, const fl
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments;
  * step counts from 1) on params with moments m, v, all device float
- * [nparams], updated in place. */
+ * [nparams], updated in place.  weight_decay >= 0 adds the gradient of the
+ * L2 penalty (weight_decay / 2) |params|^2 before the moments are updated
+ * (0: plain Adam).  FMM2D_EINVAL for lr <= 0, weight_decay < 0 or NaN. */
 int fmm2d_mlp_adam(fmm2d_ctx *ctx, float *params, float *m, float *v, const float *grad, int64_t nparams, int step,
-                   float lr);
+                   float lr, float weight_decay);
 
 /* ---- introspection (used by the parity tests) ---------------------------- */
 

@@ -74,8 +74,10 @@ def grad(theta, X, Y, shapes):
     return L, flat
 
 
-def adam_step(theta, m, v, g, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update; `step` counts from 1.  Returns new (theta, m, v)."""
+def adam_step(theta, m, v, g, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+    """One Adam update; `step` counts from 1.  wd adds the gradient of the L2
+    penalty (wd / 2) |theta|^2 to g first.  Returns new (theta, m, v)."""
+    g = np.asarray(g, dtype=np.float64) + wd * np.asarray(theta, dtype=np.float64)
     m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
     v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
     mhat = m / (1.0 - b1 ** step)

@@ -134,8 +134,8 @@ def decide(out3, blob, n: int, tol: float):
     if not ok:
         L, p, theta = rule(n, tol)
         return L, p, theta, False
-    L0 = round_half_up(math.log(max(n / 16.0, 1.0)) / math.log(4.0))
-    L = max(1, min(round_half_up(L0 + dl), levels_max(n)))
+    # dl is the level count's offset from log4(N / 16)
+    L = max(1, min(round_half_up(math.log(max(n / 16.0, 1.0)) / math.log(4.0) + dl), levels_max(n)))
     g = max(0, min(round_half_up((th - 0.35) / 0.1), 4))
     theta = THETAS[g]
     # error model e(p) = C theta^(p+1) with a safety factor of 2 on the

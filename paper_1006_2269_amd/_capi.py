@@ -48,7 +48,7 @@ SIGNATURES = [
     ("fmm2d_mlp_nparams", I64, [I32]),
     ("fmm2d_mlp_forward", I32, [P, P, P, I64, I32, P]),
     ("fmm2d_mlp_grad", I32, [P, P, P, P, I64, I32, P, P]),
-    ("fmm2d_mlp_adam", I32, [P, P, P, P, P, I64, I32, F]),
+    ("fmm2d_mlp_adam", I32, [P, P, P, P, P, I64, I32, F, F]),
     ("fmm2d_timing", I32, [P, I32]),
     ("fmm2d_get_timings", I32, [P, P, P]),
 ]

@@ -321,13 +321,14 @@ int fmm2d_mlp_grad(fmm2d_ctx *c, const float *params, const float *X, const floa
 }
 
 int fmm2d_mlp_adam(fmm2d_ctx *c, float *params, float *m, float *v, const float *grad, int64_t nparams, int step,
-                   float lr) {
+                   float lr, float weight_decay) {
     if (!c) return FMM2D_EINVAL;
     c->err.clear();
     if (!params || !m || !v || !grad) return fail(c, FMM2D_EINVAL, "mlp_adam: NULL pointer");
-    if (nparams < 1 || step < 1 || !(lr > 0.0f)) return fail(c, FMM2D_EINVAL, "mlp_adam: need nparams >= 1, step >= 1, lr > 0");
+    if (nparams < 1 || step < 1 || !(lr > 0.0f) || !(weight_decay >= 0.0f))
+        return fail(c, FMM2D_EINVAL, "mlp_adam: need nparams >= 1, step >= 1, lr > 0, weight_decay >= 0");
     DeviceGuard g(c->device);
-    hipError_t e = mlp_adam(c, params, m, v, grad, nparams, step, lr);
+    hipError_t e = mlp_adam(c, params, m, v, grad, nparams, step, lr, weight_decay);
     if (e != hipSuccess) return hip_fail(c, e, "mlp_adam");
     return FMM2D_OK;
 }

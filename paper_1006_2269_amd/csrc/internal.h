@@ -200,7 +200,8 @@ int64_t mlp_nparams(int d_in);
 hipError_t mlp_forward(fmm2d_ctx *c, const float *P, const float *X, int64_t batch, int d_in, float *Y);
 hipError_t mlp_grad(fmm2d_ctx *c, const float *P, const float *X, const float *Y, int64_t batch, int d_in,
                     float *grad, float *loss);
-hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, int64_t np, int step, float lr);
+hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, int64_t np, int step, float lr,
+                    float wd);
 // tree.hip
 hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y);
 // lists.hip

@@ -163,11 +163,11 @@ __global__ void __launch_bounds__(MT) k_mlp_grad(const float *__restrict__ P, co
 }
 
 __global__ void k_adam(float *__restrict__ P, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, int64_t np, float lr, float b1, float b2, float eps, float c1,
-                       float c2) {
+                       const float *__restrict__ g, int64_t np, float lr, float wd, float b1, float b2, float eps,
+                       float c1, float c2) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= np) return;
-    const float gk = g[k];
+    const float gk = g[k] + wd * P[k];  // L2 penalty (wd / 2) |P|^2 folded into the gradient
     const float mk = b1 * m[k] + (1.0f - b1) * gk;
     const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
     m[k] = mk;
@@ -191,11 +191,12 @@ hipError_t mlp_grad(fmm2d_ctx *c, const float *P, const float *X, const float *Y
     return hipGetLastError();
 }
 
-hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, int64_t np, int step, float lr) {
+hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, int64_t np, int step, float lr,
+                    float wd) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3(grid_for(np, 256)), dim3(256), 0, c->stream, P, m, v, g, np, lr, b1, b2, eps, c1,
-                       c2);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(np, 256)), dim3(256), 0, c->stream, P, m, v, g, np, lr, wd, b1, b2, eps,
+                       c1, c2);
     return hipGetLastError();
 }
 

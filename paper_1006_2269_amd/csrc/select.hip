@@ -20,8 +20,9 @@
 // at the end of Section 4, theta = 1/2 and about 20 points per leaf
 // (L = round(log4(N / 20))), with the least p for which the truncation bound
 // of Section 3, K theta^(p+1) / (1 - theta)^2 with K = 0.1, is <= TOL.  The
-// network predicts L - L0 (L0 = round(log4(N / 16))), log10 C of the error
-// model e(p) ~ C theta^(p+1), and theta; L is rounded, theta snapped to
+// network predicts L - log4(N / 16) (the level count's offset from 16 points
+// per leaf, continuous in N), log10 C of the error model e(p) ~ C
+// theta^(p+1), and theta; L is rounded, theta snapped to
 // {0.35, ..., 0.75}, and p is the least order the model says meets TOL / 2
 // (a safety factor of 2 on the error).
 #include "devutil.h"
@@ -292,8 +293,7 @@ __global__ void k_select_final(const float *__restrict__ y, const float *__restr
         if (inside && isfinite(dl) && isfinite(lc) && isfinite(th) && fabs(dl) < 64.0 && fabs(lc) < 1e4) {
             net = true;
             const double x0 = log((double)n / 16.0 > 1.0 ? (double)n / 16.0 : 1.0) / log(4.0);
-            const int L0 = (int)floor(x0 + 0.5);
-            L = (int)floor((double)L0 + dl + 0.5);
+            L = (int)floor(x0 + dl + 0.5);
             L = L > lmax ? lmax : (L < 1 ? 1 : L);
             int g = (int)floor((th - 0.35) / 0.1 + 0.5);
             g = g < 0 ? 0 : (g > 4 ? 4 : g);

@@ -178,13 +178,13 @@ class FMM2D:
         return grad, loss
 
     def mlp_adam(self, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor, step: int,
-                 lr: float):
+                 lr: float, weight_decay: float = 0.0):
         for t, nm in ((params, "params"), (m, "m"), (v, "v"), (grad, "grad")):
             _require(t, torch.float32, self.device, nm)
             if t.numel() != params.numel():
                 raise ValueError("%s differs in size from params" % nm)
         self._check(self._lib.fmm2d_mlp_adam(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(),
-                                             int(step), float(lr)))
+                                             int(step), float(lr), float(weight_decay)))
 
     # -- introspection ------------------------------------------------------
     def tree_info(self):

@@ -8,14 +8,20 @@ build_tree + connectivity + evaluate.  The input is the layout's feature
 vector with its second entry set to log10 TOL.  Pairs for which no measured
 configuration meets TOL (below the FP32 error floor) are left out.
 
-Targets (L - L0, log10 C, theta) with L0 = round(log4(N / 16)) and C the
-constant of the error model C theta^(p+1), placed in the middle of the
-label's order (log10 TOL = log10 C + (p + 1/2) log10 theta); decoding adds a
-safety factor of 2 on the error.  Targets and inputs are standardised; mean
-and scale go into the weight blob's header together with the trained range
-of log10 N (widened by 0.1 decade below and 0.15 above) and log10 TOL.  The
-parameters kept are those of the lowest validation loss (layouts held out
-from training), checked every 50 steps.
+Targets (L - log4(N / 16), log10 C, theta), C the constant of the error
+model C theta^(p+1), placed in the middle of the label's order
+(log10 TOL = log10 C + (p + 1/2) log10 theta); decoding adds a safety factor
+of 2 on the error.  The level target is the offset from log4(N / 16) itself:
+the best level count follows the leaf size, which is smooth in N, while an
+offset from round(log4(N / 16)) jumps by one wherever that rounding does and
+is a sawtooth in N that the network fits poorly.  Targets and inputs are
+standardised; mean and scale go into the weight blob's header together with
+the trained range of log10 N (widened by 0.1 decade below and 0.15 above)
+and log10 TOL.  Regularisation: an L2 penalty on the parameters (in the Adam
+kernel) and Gaussian noise on the standardised inputs of each batch; the run
+table has only a few hundred distinct layouts.  The parameters kept are
+those of the lowest validation loss (layouts held out from training),
+checked every 50 steps.
 
     python -m paper_1006_2269_amd.selector.train --runs a.npz b.npz --out weights.f32
 """
@@ -34,7 +40,12 @@ TOL_LO, TOL_HI = -7.0, -3.0
 
 
 def L0_of(n: int) -> int:
-    return int(math.floor(math.log(max(n / 16.0, 1.0)) / math.log(4.0) + 0.5))
+    return int(math.floor(log4_16(n) + 0.5))
+
+
+def log4_16(n) -> float:
+    """log4(N / 16), 0 below 16 points."""
+    return math.log(max(n / 16.0, 1.0)) / math.log(4.0)
 
 
 def load_runs(paths):
@@ -76,7 +87,7 @@ def best_config(R, tol):
 
 
 def make_samples(feats, ns, runs, layouts, per_layout, seed):
-    """Inputs and targets (L - L0, log10 C, theta), where log10 C puts the
+    """Inputs and targets (L - log4(N / 16), log10 C, theta), where log10 C puts the
     label's order in the middle of the error model's interval:
     log10 TOL = log10 C + (p + 1/2) log10 theta."""
     rng = np.random.default_rng(seed)
@@ -93,7 +104,7 @@ def make_samples(feats, ns, runs, layouts, per_layout, seed):
             x[1] = lt
             X.append(x)
             lc = lt - (b[3] + 0.5) * math.log10(b[2])
-            Y.append((b[1] - L0_of(int(ns[i])), lc, b[2]))
+            Y.append((b[1] - log4_16(int(ns[i])), lc, b[2]))
     return np.array(X), np.array(Y, dtype=np.float64)
 
 
@@ -116,6 +127,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--weight-decay", type=float, default=1e-2)
+    ap.add_argument("--input-noise", type=float, default=0.5)
     ap.add_argument("--val-frac", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=7)
     args = ap.parse_args()
@@ -155,9 +168,11 @@ def main():
     for step in range(1, args.steps + 1):
         idx = torch.randint(0, ntr, (min(args.batch, ntr),), generator=gen).to(dev)
         xb, yb = Xt[idx].contiguous(), Yt[idx].contiguous()
+        if args.input_noise > 0.0:
+            xb += (args.input_noise * torch.randn(xb.shape, generator=gen)).to(dev)
         lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * step / args.steps))  # cosine decay
         f.mlp_grad(params, xb, yb, grad, loss)
-        f.mlp_adam(params, m, v, grad, step=step, lr=max(lr, 1e-5))
+        f.mlp_adam(params, m, v, grad, step=step, lr=max(lr, 1e-5), weight_decay=args.weight_decay)
         if step % 50 == 0 or step == args.steps:
             _, lv = f.mlp_grad(params, Xv, Yv)
             lv = float(lv.cpu())
@@ -175,7 +190,8 @@ def main():
     th_p = thetas[np.clip(np.floor((pred[:, 2] - 0.35) / 0.1 + 0.5), 0, 4).astype(int)]
     p_dec = np.ceil((Xva[:, 1] - math.log10(2.0) - pred[:, 1]) / np.log10(th_p)) - 1
     p_lab = np.round((Xva[:, 1] - Yva[:, 1]) / np.log10(Yva[:, 2]) - 0.5)
-    dl_ok = np.mean(np.floor(pred[:, 0] + 0.5) == Yva[:, 0])
+    l4 = np.log(np.maximum(10.0 ** Xva[:, 0] / 16.0, 1.0)) / math.log(4.0)
+    dl_ok = np.mean(np.floor(pred[:, 0] + l4 + 0.5) == np.floor(Yva[:, 0] + l4 + 0.5))
     th_ok = np.mean(np.isclose(th_p, Yva[:, 2]))
     p_ok = np.mean(p_dec >= p_lab)
     print("[train] val: levels exact %.3f, theta exact %.3f, decoded p >= label p %.3f" % (dl_ok, th_ok, p_ok),
@@ -192,6 +208,7 @@ def main():
     blob.astype("<f4").tofile(args.out)
     meta = {"layouts": int(nl), "val_layouts": int(nval), "samples": int(Xtr.shape[0]),
             "val_samples": int(Xva.shape[0]), "steps": args.steps, "batch": args.batch, "lr": args.lr,
+            "weight_decay": args.weight_decay, "input_noise": args.input_noise,
             "val_levels_exact": float(dl_ok), "val_theta_exact": float(th_ok), "val_p_covers_label": float(p_ok),
             "best_step": int(best[1]), "best_val_loss": float(best[0]),
             "log10_n_range": [float(lnn.min()) - 0.1, float(lnn.max()) + 0.15], "log10_tol_range": [TOL_LO, TOL_HI]}

@@ -161,7 +161,8 @@ def test_mlp_gradient(fmm, d_in, batch):
     assert np.abs(g - gref).max() <= 1e-4 * np.abs(gref).max()
 
 
-def test_mlp_adam_step(fmm):
+@pytest.mark.parametrize("wd", [0.0, 0.01])
+def test_mlp_adam_step(fmm, wd):
     rng = np.random.default_rng(3)
     npar = M.n_params(92)
     theta = rng.normal(0, 0.1, npar).astype(np.float32)
@@ -169,17 +170,19 @@ def test_mlp_adam_step(fmm):
     v = rng.uniform(0, 1e-3, npar).astype(np.float32)
     g = rng.normal(0, 0.05, npar).astype(np.float32)
     tp, tm, tv = _dev(theta), _dev(m), _dev(v)
-    fmm.mlp_adam(tp, tm, tv, _dev(g), step=5, lr=1e-3)
+    fmm.mlp_adam(tp, tm, tv, _dev(g), step=5, lr=1e-3, weight_decay=wd)
     # the reference with the kernel's FP32 constants (0.9f, 0.999f, 1e-8f are
     # not the decimal values), so only the rounding of the update remains
     f32 = lambda v_: float(np.float32(v_))
     rt, rm, rv = M.adam_step(theta.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
-                             g.astype(np.float64), 5, 1e-3, b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
+                             g.astype(np.float64), 5, 1e-3, b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8),
+                             wd=f32(wd))
     # FP32 rounding of each update, measured against the size of its terms
     eps = 2.0 ** -24
     gm, gv, gp = (t.cpu().numpy().astype(np.float64) for t in (tm, tv, tp))
-    assert np.all(np.abs(gm - rm) <= 4 * eps * (0.9 * np.abs(m) + 0.1 * np.abs(g)))
-    assert np.all(np.abs(gv - rv) <= 4 * eps * (0.999 * v + 0.001 * g.astype(np.float64) ** 2))
+    ge = np.abs(g.astype(np.float64)) + f32(wd) * np.abs(theta.astype(np.float64))  # |g + wd theta| bound
+    assert np.all(np.abs(gm - rm) <= 4 * eps * (0.9 * np.abs(m) + 0.1 * ge))
+    assert np.all(np.abs(gv - rv) <= 4 * eps * (0.999 * v + 0.001 * ge ** 2))
     step_size = np.abs(theta.astype(np.float64) - rt)
     assert np.all(np.abs(gp - rt) <= 4 * eps * np.abs(theta) + 1e-4 * step_size)
 

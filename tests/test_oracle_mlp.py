@@ -1,6 +1,7 @@
 """Pins of the FP64 selector-network reference: a forward pass with hand-set
 weights against its closed form, gradients against central finite
-differences, and the first Adam step against its closed form."""
+differences, the first Adam step against its closed form, and Adam with the
+L2 term against the ridge minimiser it must reach."""
 import numpy as np
 
 from oracle import mlp
@@ -49,3 +50,16 @@ def test_first_adam_step_closed_form():
     t1, m, v = mlp.adam_step(theta, np.zeros(4), np.zeros(4), g, 1, lr)
     assert np.allclose(t1, theta - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_weight_decay_reaches_ridge_minimiser():
+    # Adam with the L2 term on f(t) = sum (t - a)^2 settles at the minimiser
+    # of f + (wd / 2) |t|^2, which is t* = 2a / (2 + wd) (ridge shrinkage);
+    # without the term it settles at a.
+    a = np.array([1.5, -0.75, 0.25])
+    for wd, want in ((0.5, 2 * a / 2.5), (0.0, a)):
+        t, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+        for step in range(1, 6001):
+            lr = 0.05 * 0.5 * (1 + np.cos(np.pi * step / 6000)) + 1e-6
+            t, m, v = mlp.adam_step(t, m, v, 2 * (t - a), step, lr, wd=wd)
+        assert np.allclose(t, want, atol=1e-4), (wd, t, want)

@@ -149,7 +149,7 @@ def _blob(mean3, std3, rng=(3.0, 7.0, -9.0, -3.0)):
 
 def test_decide_decoding():
     b = _blob((1.0, -1.3, 0.52), (1.0, 1.0, 1.0))
-    # L0 = round(log4(1e6 / 16)) = 8 -> levels 9 (= floor(log4 1e6)); theta
+    # log4(1e6 / 16) = 7.966, + 1 -> levels 9 (= floor(log4 1e6)); theta
     # 0.52 -> 0.55; p = ceil((-6 - log10 2 + 1.3) / log10 0.55) - 1
     #                 = ceil(19.26) - 1 = 19
     assert S.decide(np.zeros(3), b, 10 ** 6, 1e-6) == (9, 19, 0.55, True)
@@ -157,10 +157,16 @@ def test_decide_decoding():
     C, th = 10 ** -1.3, 0.55
     assert C * th ** 20 <= 1e-6 / 2 < C * th ** 19
     b2 = _blob((0.0, -2.0, 0.5), (2.0, 4.0, 0.1))
-    # outputs (-1, 0.25, -1.2): dl = -2, log10 C = -1, theta 0.38 -> 0.35;
+    # outputs (-1, 0.25, -1.2): dl = -2 (7.966 - 2 -> 6), log10 C = -1, theta 0.38 -> 0.35;
     # p = ceil((-5 - log10 2) / log10 0.35) - 1 = ceil(11.63) - 1 = 11
     assert S.decide(np.array([-1.0, 0.25, -1.2]), b2, 10 ** 6, 1e-6) == (6, 11, 0.35, True)
     assert 0.1 * 0.35 ** 12 <= 1e-6 / 2 < 0.1 * 0.35 ** 11
+    # the offset is from log4(N / 16) itself, not from its rounding: at
+    # N = 4e5, log4(25000) = 7.305, so dl = 0.3 gives 7.605 -> 8 levels and
+    # dl = 0.15 gives 7.455 -> 7
+    b3 = _blob((0.0, -1.3, 0.55), (1.0, 1.0, 1.0))
+    assert S.decide(np.array([0.3, 0.0, 0.0]), b3, 400000, 1e-6)[0] == 8
+    assert S.decide(np.array([0.15, 0.0, 0.0]), b3, 400000, 1e-6)[0] == 7
     # outside the trained range -> the rule
     assert S.decide(np.zeros(3), b, 10 ** 8, 1e-6)[3] is False
     assert S.decide(np.zeros(3), b, 10 ** 6, 1e-10)[:3] == S.rule(10 ** 6, 1e-10)
