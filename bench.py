@@ -233,10 +233,25 @@ def main():
         si = sidx.cpu().numpy().astype(np.int64)
         src_per_leaf = np.add.reduceat(cnt[si], sp[:-1]) if si.size else np.zeros_like(cnt)
         src_per_leaf[np.diff(sp) == 0] = 0
-        pairs = float((cnt * src_per_leaf).sum())
+        pairs = float((cnt * src_per_leaf).sum())    # ordered (target, source) point pairs
+        rows = np.repeat(np.arange(cnt.size), np.diff(sp))
+        diag = float((cnt[rows[si == rows]].astype(np.float64) ** 2).sum())  # pairs within one leaf
         weak_all = float(sum(f.list_sizes(l)[1] for l in range(Lm + 1)))
-        flop_pair = 8.0   # 2 sub, mul, fma (2), log2, fma (2) per FP32 pair interaction
-        near_flops = pairs * flop_pair
+        # The library's leaf pass takes each pair of distinct leaves once when
+        # the largest leaf, ceil(N / 4^L) points, holds 17 to 64 (FP32 modes):
+        # one log serves both directions, 2 sub, mul, fma (2), log2, fma (2),
+        # fma (2) = 10 flops per pair of points; pairs within a leaf, and every
+        # pair in the one-sided kernels, need 8 (one fma less).
+        maxleaf = -(-n // 4 ** Lm)
+        if 16 < maxleaf <= 64:
+            near_name = "k_near32s (pair-once near field, one launch)"
+            near_flops = (pairs - diag) / 2.0 * 10.0 + diag * 8.0
+            near_work = "%d point pairs of distinct leaves, each taken once x 10 flops + %d within leaves x 8" % (
+                (pairs - diag) / 2, diag)
+        else:
+            near_name = "%s (near field, one launch)" % ("k_near32_big" if maxleaf > 64 else "k_near32")
+            near_flops = pairs * 8.0
+            near_work = "%d point pairs x 8 flops" % pairs
         m2l_flops = weak_all * 4.0 * (p + 1) ** 2               # useful product flops per weak pair
         if m2l_ms >= near_ms:
             ach = m2l_flops / (m2l_ms * 1e-3) / 1e12
@@ -246,10 +261,9 @@ def main():
                     "work": "%d weak pairs x 4(p+1)^2 flops" % weak_all, "launch_ms": round(m2l_ms, 4)}
         else:
             ach = near_flops / (near_ms * 1e-3) / 1e12
-            roof = {"kernel": "k_near32 (near field, one launch)", "bound": "alu", "achieved": round(ach, 3),
+            roof = {"kernel": near_name, "bound": "alu", "achieved": round(ach, 3),
                     "peak": MI355X["fp32_TFLOPs"], "unit": "TFLOP/s", "frac": round(ach / MI355X["fp32_TFLOPs"], 5),
-                    "traffic": None, "work": "%d pairs x %g flops" % (pairs, flop_pair),
-                    "launch_ms": round(near_ms, 4)}
+                    "traffic": None, "work": near_work, "launch_ms": round(near_ms, 4)}
         log("[bench] near kernel %.4f ms (%.3e pairs/s), M2L kernel %.4f ms (%.3e weak pairs/s)"
             % (near_ms, pairs / (near_ms * 1e-3), m2l_ms, weak_all / (m2l_ms * 1e-3)))
 
