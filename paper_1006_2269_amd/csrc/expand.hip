@@ -17,6 +17,7 @@
 #include "devutil.h"
 #include "internal.h"
 #include "evaluate.h"
+#include "wavesum.h"
 
 namespace fmm2d {
 namespace {
@@ -56,6 +57,54 @@ __global__ void __launch_bounds__(256) k_p2m(int p, const double *__restrict__ p
 #pragma unroll
     for (int k = 1; k < PB; ++k)
         if (k <= p) out[k] = cd{-ar[k] / k, -ai[k] / k};
+}
+
+// ---- P2M for leaves of more than 16 points, orders p + 1 <= 16: one
+// wavefront per leaf, one lane per point (points lane, lane + 64, ... of a
+// larger leaf), and the lanes' 2 PB partial sums (real parts, then imaginary
+// parts) added by a transposing butterfly in a fixed order.  The thread per
+// leaf above leaves most of the chip idle when leaves are few and long.
+template <int PB>
+__global__ void __launch_bounds__(256) k_p2m_wave(int p, const double *__restrict__ px,
+                                                  const double *__restrict__ py, const double *__restrict__ qs,
+                                                  const int32_t *__restrict__ stL, const double4 *__restrict__ geomL,
+                                                  int64_t nleaf, cd *__restrict__ AL) {
+    static_assert(PB == 8 || PB == 16, "2 PB values per lane");
+    const int lane = (int)(threadIdx.x % 64);
+    const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (b >= nleaf) return;  // uniform per wavefront
+    const double4 g = geomL[b];
+    const int32_t a = stL[b], e = stL[b + 1];
+    double v[2 * PB];  // v[k]: sum of q Re w^k, v[PB + k]: sum of q Im w^k
+#pragma unroll
+    for (int k = 0; k < 2 * PB; ++k) v[k] = 0.0;
+    for (int32_t j = a + lane; j < e; j += 64) {
+        const double q = qs[j];
+        const double zr = (px[j] - g.x) / g.w, zi = (py[j] - g.y) / g.w;
+        double wr = zr, wi = zi;
+        v[0] += q;
+#pragma unroll
+        for (int k = 1; k < PB; ++k) {
+            if (k <= p) {
+                v[k] += q * wr;
+                v[PB + k] += q * wi;
+                const double tr = wr * zr - wi * zi;
+                wi = wr * zi + wi * zr;
+                wr = tr;
+            }
+        }
+    }
+    const double s = wave_transpose_sum<2 * PB>(v, lane);  // value lane / G, G lanes each
+    constexpr int G = 32 / PB;
+    if (lane % G == 0) {
+        const int vi = lane / G;
+        const bool im = vi >= PB;
+        const int k = im ? vi - PB : vi;
+        if (k <= p) {
+            double *out = reinterpret_cast<double *>(AL + b * (p + 1)) + 2 * k + (im ? 1 : 0);
+            *out = k == 0 ? (im ? 0.0 : s) : -s / k;
+        }
+    }
 }
 
 // Powers x^lane for every lane, by an inclusive product scan across the wave.
@@ -303,6 +352,16 @@ template <int PB>
 hipError_t launch_p2m(fmm2d_ctx *c, int p, cd *A) {
     TreeState &t = c->tree;
     const int64_t nleaf = int64_t(1) << (2 * t.L);
+    if constexpr (PB <= 16) {
+        const int64_t maxleaf = (t.n + nleaf - 1) >> (2 * t.L);  // ceil(n / 4^L)
+        if (maxleaf > 16) {
+            hipLaunchKernelGGL(k_p2m_wave<PB>, dim3(grid_for(nleaf, 4)), dim3(256), 0, c->stream, p,
+                               t.px.as<double>(), t.py.as<double>(), c->ev.qs.as<double>(),
+                               t.starts.as<int32_t>() + depth_offset(2 * t.L), t.geom.as<double4>() + level_offset(t.L),
+                               nleaf, A + level_offset(t.L) * (p + 1));
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL(k_p2m<PB>, dim3(grid_for(nleaf, 256)), dim3(256), 0, c->stream, p, t.px.as<double>(),
                        t.py.as<double>(), c->ev.qs.as<double>(), t.starts.as<int32_t>() + depth_offset(2 * t.L),
                        t.geom.as<double4>() + level_offset(t.L), nleaf, A + level_offset(t.L) * (p + 1));

@@ -61,6 +61,9 @@ TREE_CASES = {
     # targets per leaf (one block of four wavefronts per list segment)
     "uniform_3200_L3": (lambda: W.uniform(3200, 14), 3),
     "duplicates_4k_L3": (lambda: _duplicates(4000, 8), 3),
+    # leaves of 125 points: more than one point per lane in the
+    # wavefront-per-leaf multipole kernel
+    "uniform_2000_L2": (lambda: W.uniform(2000, 15), 2),
     "mixed_scaled_20k_L6": (lambda: W.mixed_1m(scale=0.02), 6),
     "clustered_scaled_20k_L6": (lambda: W.clustered_10m(scale=0.002), 6),
     "clustered_scaled_30k_L6": (lambda: W.clustered_10m(scale=0.003, seed=2003), 6),

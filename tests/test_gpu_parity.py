@@ -88,7 +88,9 @@ def test_lists_bit_exact(fmm, orc, case, theta):
 
 FP64_CASES = ["uniform_1k_L3", "clustered_scaled_30k_L6", "ties_3k_L4", "ragged_4pow5_plus1", "duplicates_4k_L4", "vertical_2k_L3",
               "scales_3k_L4", "single_box_L0", "uniform_10k_L5", "mixed_scaled_20k_L6",
-              "clustered_scaled_20k_L6", "ring_scaled_20k_L6"]
+              "clustered_scaled_20k_L6", "ring_scaled_20k_L6",
+              # leaves of 20, 50, 63 and 125 points (multipoles by one wavefront per leaf for p + 1 <= 16)
+              "uniform_20k_L5", "uniform_3200_L3", "duplicates_4k_L3", "uniform_2000_L2"]
 
 
 @pytest.mark.parametrize("case", FP64_CASES)
