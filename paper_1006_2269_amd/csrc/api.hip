@@ -102,7 +102,8 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->tree.near_lo.segoff.release();
         c->tree.near_lo.table.release();
         c->tree.lsum.release();
-        for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src}) b->release();
+        for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src})
+            b->release();
         Scratch &s = c->scr;
         for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
         for (DevBuf *b : {&s.keys0, &s.keys1, &s.vals0, &s.vals1, &s.hist, &s.aux, &s.tiles, &s.tiles2, &s.segbase,
@@ -152,7 +153,8 @@ int fmm2d_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, 
     t.L = levels;
     {
         PhaseScope ps(c, PH_TREE);
-        e = build_tree_device(c, x, y);
+        e = side_join(c);  // second-stream work still reading the previous tree or lists
+        if (e == hipSuccess) e = build_tree_device(c, x, y);
     }
     if (e != hipSuccess) {
         t.L = -1;
@@ -429,6 +431,7 @@ int fmm2d_get_timings(fmm2d_ctx *c, double *ms, int64_t *count) {
     c->err.clear();
     DeviceGuard g(c->device);
     hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && c->side) e = hipStreamSynchronize(c->side);  // marks recorded on the second stream
     if (e != hipSuccess) return hip_fail(c, e, "get_timings");
     double acc[PH_COUNT] = {0};
     int64_t cnt[PH_COUNT] = {0};

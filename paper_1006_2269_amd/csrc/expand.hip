@@ -460,11 +460,18 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
     FMM2D_TRY(e.B.ensure(sizeof(cd) * nbox * (p + 1)));
     FMM2D_TRY(e.qs.ensure(sizeof(double) * n));
     FMM2D_TRY(e.phi_leaf.ensure(sizeof(double) * n));
+    FMM2D_TRY(side_join(c));  // second-stream work of an earlier call still reading the charges or sources
     {
         PhaseScope ps(c, PH_OTHER);
         hipLaunchKernelGGL(k_gather_q, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, q, t.perm.as<int32_t>(), n,
                            e.qs.as<double>());
         hipLaunchKernelGGL(k_zero_cd, dim3(1), dim3(64), 0, c->stream, e.B.as<cd>(), (int64_t)(p + 1));
+    }
+    {
+        // the near field needs no expansion: it runs on the second stream
+        // while the upward pass, M2L and L2L run here
+        PhaseScope ps(c, PH_LEAF);
+        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_START));
     }
     {
         PhaseScope ps(c, PH_UPWARD);
@@ -481,7 +488,7 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
     }
     {
         PhaseScope ps(c, PH_LEAF);
-        FMM2D_TRY(leaf_pass(c, p, mode));
+        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_FINISH));
     }
     {
         PhaseScope ps(c, PH_OTHER);

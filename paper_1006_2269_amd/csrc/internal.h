@@ -114,7 +114,8 @@ struct EvalState {
     DevBuf phi_leaf;        // double [n]
     DevBuf work;            // mode-dependent scratch
     DevBuf src;             // float4 [n]: FP32 local offsets and charge
-    DevBuf part;            // partial sums of list segments (M2L and near field)
+    DevBuf part;            // partial sums of the M2L's list segments
+    DevBuf npart;           // near-field partial sums (written on the second stream while the far field runs)
 };
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream
@@ -219,14 +220,16 @@ struct PhaseScope {
     fmm2d_ctx *c;
     int phase;
     hipEvent_t a = nullptr;
-    // ph < 0: not timed
-    PhaseScope(fmm2d_ctx *ctx, int ph) : c(ctx), phase(ph) {
-        if (ph >= 0 && c->timer.on && (a = c->timer.next())) (void)hipEventRecord(a, c->stream);
+    hipStream_t s;
+    // ph < 0: not timed; stream: the context stream unless given
+    PhaseScope(fmm2d_ctx *ctx, int ph, hipStream_t stream = nullptr) : c(ctx), phase(ph), s(stream) {
+        if (!s) s = c->stream;
+        if (ph >= 0 && c->timer.on && (a = c->timer.next())) (void)hipEventRecord(a, s);
     }
     ~PhaseScope() {
         if (a) {
             hipEvent_t b = c->timer.next();
-            if (b && hipEventRecord(b, c->stream) == hipSuccess) c->timer.marks.push_back({phase, a, b});
+            if (b && hipEventRecord(b, s) == hipSuccess) c->timer.marks.push_back({phase, a, b});
         }
     }
 };

@@ -493,9 +493,12 @@ __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, do
     phi_leaf[i] = v.re + scale * near;
 }
 
-// FP32 paths with leaves of at most 64 points: each leaf pair once.
+// FP32 paths with leaves of at most 64 points: each leaf pair once.  Stage
+// NEAR_START queues the pair kernel and the lower-segment sums on the second
+// stream (after the transposed positions, queued there by the list build),
+// NEAR_FINISH the reduction with L2P on the context stream.
 template <int TM, int GL, int CH>
-hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode) {
+hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int L = t.L;
@@ -508,42 +511,50 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode) {
     const cd *BL = e.B.as<cd>() + offL * (p + 1);
     const int32_t *sp = t.sptr.as<int32_t>() + ptr_offset(L);
     const int64_t ns = t.s_off[L + 1] - t.s_off[L];
-    FMM2D_TRY(e.part.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
-    FMM2D_TRY(t.spart.ensure(sizeof(float) * (size_t)(ns > 0 ? ns : 1) * GL));
-    double *part = e.part.as<double>();
+    const Schedule &lo = t.near_lo;
+    if (stage == NEAR_START) {
+        FMM2D_TRY(e.npart.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
+        FMM2D_TRY(t.spart.ensure(sizeof(float) * (size_t)(ns > 0 ? ns : 1) * GL));
+        FMM2D_TRY(t.lsum.ensure(sizeof(double) * (size_t)(lo.bound > 0 ? lo.bound : 1) * GL));
+    }
+    double *part = e.npart.as<double>();
     float *spart = t.spart.as<float>();
+    if (stage == NEAR_FINISH) {
+        FMM2D_TRY(side_join(c));
+        hipLaunchKernelGGL(k_near_reduce_sym, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, CH, GL,
+                           HALF_LN2_D, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part,
+                           lo.segoff.as<int32_t>(), t.lsum.as<double>(), gL, t.px.as<double>(), t.py.as<double>(),
+                           BL, e.phi_leaf.as<double>());
+        return hipGetLastError();
+    }
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
-    FMM2D_TRY(side_join(c));  // the transposed positions
+    FMM2D_TRY(side_begin(c));  // the packed sources
     {
-        PhaseScope kernel_scope(c, PH_NEAR_KERNEL);  // the near-field kernel alone
+        PhaseScope kernel_scope(c, PH_NEAR_KERNEL, c->side);  // the near-field kernel alone
         if (mode == FMM2D_MODE_FP32_ACC64)
-            hipLaunchKernelGGL((k_near32s<TM, GL, CH, true>), grid, block, 0, c->stream, nitems, stL,
+            hipLaunchKernelGGL((k_near32s<TM, GL, CH, true>), grid, block, 0, c->side, nitems, stL,
                                e.src.as<float4>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
                                sc.table.as<int2>(),
                                sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
                                spart);
         else
-            hipLaunchKernelGGL((k_near32s<TM, GL, CH, false>), grid, block, 0, c->stream, nitems, stL,
+            hipLaunchKernelGGL((k_near32s<TM, GL, CH, false>), grid, block, 0, c->side, nitems, stL,
                                e.src.as<float4>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
                                sc.table.as<int2>(),
                                sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
                                spart);
     }
     FMM2D_TRY(hipGetLastError());
-    const Schedule &lo = t.near_lo;
-    FMM2D_TRY(t.lsum.ensure(sizeof(double) * (size_t)(lo.bound > 0 ? lo.bound : 1) * GL));
-    hipLaunchKernelGGL(k_near_lsum<GL>, dim3(grid_for(lo.bound > 0 ? lo.bound : 1, 4)), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_near_lsum<GL>, dim3(grid_for(lo.bound > 0 ? lo.bound : 1, 4)), dim3(256), 0, c->side,
                        lo.table.as<int2>(), lo.segoff.as<int32_t>() + nleaf, t.selfpos.as<int32_t>(), spart,
                        t.lsum.as<double>());
-    hipLaunchKernelGGL(k_near_reduce_sym, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, CH, GL,
-                       HALF_LN2_D, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part,
-                       lo.segoff.as<int32_t>(), t.lsum.as<double>(), gL, t.px.as<double>(), t.py.as<double>(), BL,
-                       e.phi_leaf.as<double>());
-    return hipGetLastError();
+    FMM2D_TRY(hipGetLastError());
+    return side_end(c);
 }
 
+// Every ordered leaf pair (one-sided kernels); stages as in launch_near_sym.
 template <int TM, int GL>
-hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf) {
+hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int L = t.L;
@@ -560,43 +571,48 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf) {
     const float4 *rd = t.nrec_d.as<float4>();
     const int2 *tab = sc.table.as<int2>();
     const int32_t *nsp = sc.segoff.as<int32_t>() + nleaf;
-    FMM2D_TRY(e.part.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
-    double *part = e.part.as<double>();
-    const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
+    if (stage == NEAR_START) FMM2D_TRY(e.npart.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
+    double *part = e.npart.as<double>();
     const double scale = mode == FMM2D_MODE_FP64 ? 0.5 : HALF_LN2_D;
+    if (stage == NEAR_FINISH) {
+        FMM2D_TRY(side_join(c));
+        hipLaunchKernelGGL(k_near_reduce, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, chunks,
+                           scale, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part, gL, t.px.as<double>(),
+                           t.py.as<double>(), BL, e.phi_leaf.as<double>());
+        return hipGetLastError();
+    }
+    const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
+    FMM2D_TRY(side_begin(c));  // the packed sources (charges in leaf order for binary64)
     {
-        PhaseScope kernel_scope(c, PH_NEAR_KERNEL);  // the near-field kernel alone
+        PhaseScope kernel_scope(c, PH_NEAR_KERNEL, c->side);  // the near-field kernel alone
         if (mode == FMM2D_MODE_FP64) {
-            hipLaunchKernelGGL((k_near64<TM, GL>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+            hipLaunchKernelGGL((k_near64<TM, GL>), grid, block, 0, c->side, nitems, chunks, maxleaf, stL,
                                t.px.as<double>(), t.py.as<double>(), e.qs.as<double>(), sp, tab, nsp, rj, part);
         } else {
             if (maxleaf > 64) {
                 if (mode == FMM2D_MODE_FP32_ACC64)
-                    hipLaunchKernelGGL((k_near32_big<TM, true>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                    hipLaunchKernelGGL((k_near32_big<TM, true>), grid, block, 0, c->side, nitems, chunks, maxleaf, stL,
                                        e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
                 else
-                    hipLaunchKernelGGL((k_near32_big<TM, false>), grid, block, 0, c->stream, nitems, chunks, maxleaf, stL,
+                    hipLaunchKernelGGL((k_near32_big<TM, false>), grid, block, 0, c->side, nitems, chunks, maxleaf, stL,
                                        e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
             } else if (mode == FMM2D_MODE_FP32_ACC64) {
-                hipLaunchKernelGGL((k_near32<TM, GL, true>), grid, block, 0, c->stream, nitems, chunks, stL,
+                hipLaunchKernelGGL((k_near32<TM, GL, true>), grid, block, 0, c->side, nitems, chunks, stL,
                                    e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
             } else {
-                hipLaunchKernelGGL((k_near32<TM, GL, false>), grid, block, 0, c->stream, nitems, chunks, stL,
+                hipLaunchKernelGGL((k_near32<TM, GL, false>), grid, block, 0, c->side, nitems, chunks, stL,
                                    e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
             }
         }
     }
     FMM2D_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_near_reduce, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, chunks, scale,
-                       t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part, gL, t.px.as<double>(),
-                       t.py.as<double>(), BL, e.phi_leaf.as<double>());
-    return hipGetLastError();
+    return side_end(c);
 }
 
 }  // namespace
 
 // L2P plus the near field for every point; writes ev.phi_leaf (leaf order).
-hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode) {
+hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int64_t n = t.n;
@@ -604,7 +620,7 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode) {
     const int64_t nleaf = int64_t(1) << (2 * L);
     const int64_t maxleaf = (n + nleaf - 1) >> (2 * L);  // ceil(n / 4^L)
     if (!t.nrec_valid) return hipErrorInvalidValue;  // records come with the lists
-    if (mode != FMM2D_MODE_FP64) {
+    if (stage == NEAR_START && mode != FMM2D_MODE_FP64) {
         FMM2D_TRY(e.src.ensure(sizeof(float4) * n));
         hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.loc.as<float2>(),
                            e.qs.as<double>(), n, e.src.as<float4>());
@@ -615,14 +631,14 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode) {
     if (mode != FMM2D_MODE_FP64 && pair_once_leaves(ml)) {
         // each leaf pair once, the four chunks of targets of a leaf in the
         // four wavefronts of a block
-        if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode);
-        return launch_near_sym<16, 64, 4>(c, p, mode);
+        if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode, stage);
+        return launch_near_sym<16, 64, 4>(c, p, mode, stage);
     }
-    FMM2D_TRY(ensure_near_full_schedule(c));
-    if (ml <= 8) return launch_near<8, 8>(c, p, mode, ml);
-    if (ml <= 16) return launch_near<16, 16>(c, p, mode, ml);
-    if (ml <= 32) return launch_near<16, 32>(c, p, mode, ml);
-    return launch_near<16, 64>(c, p, mode, ml);
+    FMM2D_TRY(ensure_near_full_schedule(c));  // built on the context stream, before the second stream waits
+    if (ml <= 8) return launch_near<8, 8>(c, p, mode, ml, stage);
+    if (ml <= 16) return launch_near<16, 16>(c, p, mode, ml, stage);
+    if (ml <= 32) return launch_near<16, 32>(c, p, mode, ml, stage);
+    return launch_near<16, 64>(c, p, mode, ml, stage);
 }
 
 }  // namespace fmm2d
