@@ -17,6 +17,7 @@
 // contribute nothing, as in binary64.  L2P (binary64 Horner) runs on lane k
 // for target k.
 #include "evaluate.h"
+#include "wavesum.h"
 
 namespace fmm2d {
 namespace {
@@ -65,14 +66,13 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
         s_rd[wv][lane] = rd;
     }
     float tx[TM], ty[TM], acc[TM];
-    double acc64[TM];
+    double tot64 = 0.0;  // ACC64: binary64 total of target lane / (64 / TM), added at each flush
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
         const float4 s = src[a + (k < nt ? k : 0)];
         tx[k] = s.x;
         ty[k] = s.y;
         acc[k] = 0.f;
-        acc64[k] = 0.0;
     }
     __builtin_amdgcn_wave_barrier();
     const int grp = lane / GL, jj = lane % GL;
@@ -104,31 +104,30 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
             if (st + 2 < nsteps) svA = load_src(st + 2);
             eval(svB, st + 1);
         }
-        if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps
+        if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps, summed over the lanes at once
+            double v[TM];
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
-                acc64[k] += (double)acc[k];
+                v[k] = (double)acc[k];
                 acc[k] = 0.f;
             }
+            tot64 += wave_transpose_sum<TM>(v, lane);
         }
     }
-    double mine = 0.0;
+    // the 64 lanes' partial sums of each target, by the transposing
+    // butterfly (fixed order; binary64 with ACC64, else FP32): lane i
+    // receives target i / (64 / TM)
+    double tot;
+    if constexpr (ACC64) {
+        double v[TM];
 #pragma unroll
-    for (int k = 0; k < TM; ++k) {
-        double v;
-        if (ACC64) {
-            v = acc64[k] + (double)acc[k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        } else {
-            float w = acc[k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
-            v = (double)w;
-        }
-        if (lane == k) mine = v;
+        for (int k = 0; k < TM; ++k) v[k] = (double)acc[k];
+        tot = tot64 + wave_transpose_sum<TM>(v, lane);
+    } else {
+        tot = (double)wave_transpose_sum<TM>(acc, lane);
     }
-    if (lane < TM) part[item * TM + lane] = mine;
+    constexpr int G = 64 / TM;
+    if (lane % G == 0) part[item * TM + lane / G] = tot;
 }
 
 // FP32 near field taking each leaf pair once (leaves of 17 to 64 points).
@@ -137,9 +136,13 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
 // serves both sides: the target's sum (q_c log r, per target as below) and,
 // when c != b, the source's (q_b log r, summed over the wavefront's targets
 // in the source's lane and written to spart at leaf c's own entry for b, per
-// lane, where leaf c's reduction reads its entries in order).  With CH = 4 chunks of targets
-// per leaf the four wavefronts of a block hold the four chunks of one
-// segment, and their per-step source sums are added in LDS before the write.
+// lane, where leaf c's reduction reads its entries in order).  The four
+// wavefronts of a block hold the four chunks of targets of one segment; their
+// per-step source sums collect in an LDS ring of RING steps, added across the
+// chunks once per group of steps (one barrier per group).  With ACC64 the
+// FP32 partial sums go to binary64 every 16 steps, summed over the lanes by
+// the transposing butterfly at once, so a lane keeps one binary64 total
+// instead of TM.
 //
 // The segment's records (at most NEAR_SEG = 64, one per lane) are staged in
 // the wavefront's LDS slice once; the source points of the next step are
@@ -155,12 +158,14 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
                                                       const int2 *__restrict__ recj, const float4 *__restrict__ recd,
                                                       double *__restrict__ part, float *__restrict__ spart) {
     static_assert(NEAR_SEG <= 64, "one record per lane");
-    static_assert(CH == 1 || CH == NWB, "chunks of one segment fill a block");
+    static_assert(CH == NWB, "the chunks of one segment fill a block");
+    static_assert(TM == 8 || TM == 16, "targets per wavefront");
     constexpr int LPI = 64 / GL;  // source leaves per step
+    constexpr int RING = 8;       // steps of source sums per exchange
     __shared__ int2 s_rj[NWB][64];
     __shared__ float4 s_rd[NWB][64];
     __shared__ int32_t s_tu[NWB][64];
-    __shared__ float s_sp[CH == 1 ? 1 : 2][CH == 1 ? 1 : NWB][64];
+    __shared__ float s_ring[2][RING][NWB][64];
     const int wv = threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
     const int64_t item = (int64_t)blockIdx.x * NWB + wv;
@@ -172,7 +177,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
     const int64_t b = se.x;
     const int32_t lb = stL[b], le = stL[b + 1];
     const int32_t a = lb + ch * TM;
-    const int nt = (le - a) < 0 ? 0 : ((le - a) < TM ? (le - a) : TM);  // CH = 4: a chunk may be empty
+    const int nt = (le - a) < 0 ? 0 : ((le - a) < TM ? (le - a) : TM);  // a chunk may be empty
     const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
     const int32_t tself = selfpos[b];
     {
@@ -185,7 +190,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
         s_tu[wv][lane] = (ok && tr != tself) ? transU[tr] : 0;
     }
     float tx[TM], ty[TM], tq[TM], acc[TM];
-    double acc64[TM];
+    double tot64 = 0.0;  // ACC64: binary64 total of target lane / (64 / TM), added at each flush
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
         const float4 s = src[k < nt ? a + k : lb];
@@ -193,7 +198,6 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
         ty[k] = s.y;
         tq[k] = k < nt ? s.z : 0.f;  // absent targets send nothing to the sources
         acc[k] = 0.f;
-        acc64[k] = 0.0;
     }
     __builtin_amdgcn_wave_barrier();
     const int grp = lane / GL, jj = lane % GL;
@@ -204,8 +208,33 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
         const float4 v = src[ok ? rj.x + jj : 0];
         return ok ? v : make_float4(1e18f, 1e18f, 0.f, 0.f);
     };
+    // The source sums of RING steps collect in one half of s_ring; at the
+    // last step of the group (or of the segment) the block meets once, and
+    // each wavefront adds the four chunks' sums of RING / NWB of the steps
+    // (chunk order, as one block-wide sum would) and writes them to spart at
+    // leaf c's own entry for b.  The other half takes the next group, so one
+    // barrier per group suffices.
+    auto exchange = [&](int st_last) {
+        __syncthreads();
+        const int base = st_last & ~(RING - 1);
+        const int half = (st_last / RING) & 1;
+#pragma unroll
+        for (int u = 0; u < RING / NWB; ++u) {
+            const int st = base + wv * (RING / NWB) + u;
+            if (st > st_last) break;  // uniform per wavefront
+            const int r = st * LPI + grp;
+            const int32_t t = t0 + r;
+            const int2 rj = s_rj[wv][r];
+            if (t < t1 && t != tself && jj < rj.y - rj.x) {
+                float v = 0.f;
+#pragma unroll
+                for (int w = 0; w < NWB; ++w) v += s_ring[half][st & (RING - 1)][w][lane];
+                spart[(int64_t)s_tu[wv][r] * GL + jj] = v;  // leaf c's own entry for b
+            }
+        }
+    };
     // one step: both sides of every pair of this lane's source and the
-    // wavefront's targets; the source side goes out at once
+    // wavefront's targets
     auto eval = [&](float4 sv, int st) {
         const int r = st * LPI + grp;
         const float4 rd = s_rd[wv][r];
@@ -219,22 +248,8 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
             acc[k] = fmaf(q, lg, acc[k]);
             sacc = fmaf(tq[k], lg, sacc);
         }
-        const int32_t t = t0 + r;
-        const int2 rj = s_rj[wv][r];
-        const bool out = t < t1 && t != tself && jj < rj.y - rj.x;
-        const int64_t dst = (int64_t)s_tu[wv][r] * GL + jj;  // leaf c's own entry for b
-        if constexpr (CH == 1) {
-            if (out) spart[dst] = sacc;
-        } else {
-            s_sp[st & 1][wv][lane] = sacc;
-            __syncthreads();
-            if (wv == 0 && out) {
-                float v = 0.f;
-#pragma unroll
-                for (int w = 0; w < NWB; ++w) v += s_sp[st & 1][w][lane];
-                spart[dst] = v;
-            }
-        }
+        s_ring[(st / RING) & 1][st & (RING - 1)][wv][lane] = sacc;
+        if ((st & (RING - 1)) == RING - 1 || st == nsteps - 1) exchange(st);  // uniform per block
     };
     float4 svA = load_src(0), svB;
     for (int st = 0; st < nsteps; st += 2) {
@@ -245,31 +260,30 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
             if (st + 2 < nsteps) svA = load_src(st + 2);
             eval(svB, st + 1);
         }
-        if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps
+        if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps, summed over the lanes at once
+            double v[TM];
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
-                acc64[k] += (double)acc[k];
+                v[k] = (double)acc[k];
                 acc[k] = 0.f;
             }
+            tot64 += wave_transpose_sum<TM>(v, lane);
         }
     }
-    double mine = 0.0;
+    // the 64 lanes' partial sums of each target, by the transposing
+    // butterfly (fixed order; binary64 with ACC64, else FP32): lane i
+    // receives target i / (64 / TM)
+    double tot;
+    if constexpr (ACC64) {
+        double v[TM];
 #pragma unroll
-    for (int k = 0; k < TM; ++k) {
-        double v;
-        if (ACC64) {
-            v = acc64[k] + (double)acc[k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        } else {
-            float w = acc[k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
-            v = (double)w;
-        }
-        if (lane == k) mine = v;
+        for (int k = 0; k < TM; ++k) v[k] = (double)acc[k];
+        tot = tot64 + wave_transpose_sum<TM>(v, lane);
+    } else {
+        tot = (double)wave_transpose_sum<TM>(acc, lane);
     }
-    if (lane < TM) part[item * TM + lane] = mine;
+    constexpr int G = 64 / TM;
+    if (lane % G == 0) part[item * TM + lane / G] = tot;
 }
 
 // FP32 near field for leaves larger than 64 points: a lane walks its source
