@@ -12,6 +12,7 @@
 // level from the root down, M2L along that level's weak lists (m2l.hip)
 // followed by L2L to the next level; finally L2P and the near-field sum over
 // the finest strong lists (near.hip), and the scatter back to input order.
+#include <algorithm>
 #include <vector>
 
 #include "devutil.h"
@@ -238,12 +239,10 @@ __device__ inline void scaled_powers(cd delta, cd *e) {
     }
 }
 
+// M2M into parent P of level l from its four children.
 template <int P1>
-__global__ void __launch_bounds__(64) k_m2m_box(int l, int64_t nparent, const double4 *__restrict__ geom,
-                                                cd *__restrict__ A) {
+__device__ inline void m2m_one(int l, int64_t P, const double4 *__restrict__ geom, cd *__restrict__ A) {
     constexpr Fact<P1> F;
-    const int64_t P = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (P >= nparent) return;
     const int64_t pbox = level_offset(l) + P;
     const double4 gp = geom[pbox];
     const double is = 1.0 / gp.w;
@@ -288,12 +287,32 @@ __global__ void __launch_bounds__(64) k_m2m_box(int l, int64_t nparent, const do
 // B(child) = the parent's local expansion re-centred at the child, plus the
 // child's M2L segment sums in segment order.
 template <int P1>
-__global__ void __launch_bounds__(64) k_l2l_box(int l, int64_t nchild, const double4 *__restrict__ geom,
-                                                cd *__restrict__ B, const int32_t *__restrict__ segoff,
-                                                const cd *__restrict__ part) {
+__global__ void __launch_bounds__(64) k_m2m_box(int l, int64_t nparent, const double4 *__restrict__ geom,
+                                                cd *__restrict__ A) {
+    const int64_t P = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (P < nparent) m2m_one<P1>(l, P, geom, A);
+}
+
+// M2M of the coarse levels lc, lc - 1, ..., 0 (at most COARSE boxes each) in
+// one workgroup: these levels are too small to fill the chip, and one launch
+// per level would leave the pass launch-bound.  A device-scope fence before
+// each barrier makes a level's stores visible to the next level's loads.
+constexpr int COARSE = 256;
+template <int P1>
+__global__ void __launch_bounds__(COARSE) k_m2m_coarse(int lc, const double4 *__restrict__ geom, cd *__restrict__ A) {
+    for (int l = lc; l >= 0; --l) {
+        if ((int64_t)threadIdx.x < (int64_t(1) << (2 * l))) m2m_one<P1>(l, threadIdx.x, geom, A);
+        __threadfence();
+        __syncthreads();
+    }
+}
+
+// L2L into child cidx of level l + 1 from its parent, plus the child's M2L
+// segment sums in segment order.
+template <int P1>
+__device__ inline void l2l_one(int l, int64_t cidx, const double4 *__restrict__ geom, cd *__restrict__ B,
+                               const int32_t *__restrict__ segoff, const cd *__restrict__ part) {
     constexpr Fact<P1> F;
-    const int64_t cidx = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (cidx >= nchild) return;
     const int64_t cbox = level_offset(l + 1) + cidx;
     const int64_t pbox = level_offset(l) + (cidx >> 2);
     const double4 gc = geom[cbox], gp = geom[pbox];
@@ -329,6 +348,27 @@ __global__ void __launch_bounds__(64) k_l2l_box(int l, int64_t nchild, const dou
     }
 #pragma unroll
     for (int k = 0; k < P1; ++k) B[cbox * P1 + k] = out[k];
+}
+
+template <int P1>
+__global__ void __launch_bounds__(64) k_l2l_box(int l, int64_t nchild, const double4 *__restrict__ geom,
+                                                cd *__restrict__ B, const int32_t *__restrict__ segoff,
+                                                const cd *__restrict__ part) {
+    const int64_t cidx = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (cidx < nchild) l2l_one<P1>(l, cidx, geom, B, segoff, part);
+}
+
+// L2L into the children of levels 1, ..., lc + 1 (at most COARSE each) in one
+// workgroup, as k_m2m_coarse.
+template <int P1>
+__global__ void __launch_bounds__(COARSE) k_l2l_coarse(int lc, const double4 *__restrict__ geom, cd *__restrict__ B,
+                                                       const int32_t *__restrict__ segoff,
+                                                       const cd *__restrict__ part) {
+    for (int l = 0; l <= lc; ++l) {
+        if ((int64_t)threadIdx.x < (int64_t(1) << (2 * (l + 1)))) l2l_one<P1>(l, threadIdx.x, geom, B, segoff, part);
+        __threadfence();
+        __syncthreads();
+    }
 }
 
 __global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restrict__ perm, int64_t n,
@@ -402,7 +442,9 @@ hipError_t upward_pass(fmm2d_ctx *c, int p) {
     else r = launch_p2m<64>(c, p, A);
     FMM2D_TRY(r);
     const double4 *geom = t.geom.as<double4>();
-    for (int l = L - 1; l >= 0; --l) {
+    // levels of at most COARSE parents (l <= 4) in one launch, after the finer ones
+    const int lc = p + 1 <= 16 ? std::min(L - 1, 4) : -1;
+    for (int l = L - 1; l > lc; --l) {
         const int64_t np = int64_t(1) << (2 * l);
         if (p + 1 <= 16) {
             const dim3 grid(grid_for(np, 64)), block(64);
@@ -417,6 +459,16 @@ hipError_t upward_pass(fmm2d_ctx *c, int p) {
             }
         } else {
             hipLaunchKernelGGL(k_m2m, dim3((unsigned)np), dim3(64), 0, c->stream, l, p, geom, A, binom);
+        }
+    }
+    if (lc >= 0) {
+        switch (p + 1) {
+#define FMM2D_M2MC(P1)     case P1: hipLaunchKernelGGL(k_m2m_coarse<P1>, dim3(1), dim3(COARSE), 0, c->stream, lc, geom, A); break;
+            FMM2D_M2MC(2) FMM2D_M2MC(3) FMM2D_M2MC(4) FMM2D_M2MC(5) FMM2D_M2MC(6) FMM2D_M2MC(7) FMM2D_M2MC(8)
+            FMM2D_M2MC(9) FMM2D_M2MC(10) FMM2D_M2MC(11) FMM2D_M2MC(12) FMM2D_M2MC(13) FMM2D_M2MC(14)
+            FMM2D_M2MC(15) FMM2D_M2MC(16)
+#undef FMM2D_M2MC
+            default: return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
@@ -447,6 +499,32 @@ hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
                            e.binom.as<double>(), segoff, e.part.as<cd>());
     }
     return hipGetLastError();
+}
+
+// L2L of every level: children of levels 1..4 (at most COARSE each) in one
+// launch, then one launch per finer level.
+hipError_t l2l_pass(fmm2d_ctx *c, int p) {
+    TreeState &t = c->tree;
+    EvalState &e = c->ev;
+    const int L = t.L;
+    int l0 = 0;
+    if (p + 1 <= 16 && L >= 1) {
+        const int lc = std::min(L - 1, 3);
+        const double4 *geom = t.geom.as<double4>();
+        const int32_t *segoff = t.m2l_all.segoff.as<int32_t>();
+        switch (p + 1) {
+#define FMM2D_L2LC(P1)                                                                                                  case P1:                                                                                                                hipLaunchKernelGGL(k_l2l_coarse<P1>, dim3(1), dim3(COARSE), 0, c->stream, lc, geom, e.B.as<cd>(), segoff,                            e.part.as<cd>());                                                                                break;
+            FMM2D_L2LC(2) FMM2D_L2LC(3) FMM2D_L2LC(4) FMM2D_L2LC(5) FMM2D_L2LC(6) FMM2D_L2LC(7) FMM2D_L2LC(8)
+            FMM2D_L2LC(9) FMM2D_L2LC(10) FMM2D_L2LC(11) FMM2D_L2LC(12) FMM2D_L2LC(13) FMM2D_L2LC(14)
+            FMM2D_L2LC(15) FMM2D_L2LC(16)
+#undef FMM2D_L2LC
+            default: return hipErrorInvalidValue;
+        }
+        FMM2D_TRY(hipGetLastError());
+        l0 = lc + 1;
+    }
+    for (int l = l0; l < L; ++l) FMM2D_TRY(l2l_level(c, l, p));  // parent's expansion plus the level's M2L sums
+    return hipSuccess;
 }
 
 hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) {
@@ -482,9 +560,9 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
         FMM2D_TRY(m2l_all(c, p, mode));  // every level at once, into segment sums
     }
     FMM2D_TRY(e.part.ensure(sizeof(cd)));  // a valid pointer also when there is no weak pair
-    for (int l = 0; l < L; ++l) {
+    {
         PhaseScope ps(c, PH_L2L);
-        FMM2D_TRY(l2l_level(c, l, p));  // parent's expansion plus the level's M2L sums
+        FMM2D_TRY(l2l_pass(c, p));
     }
     {
         PhaseScope ps(c, PH_LEAF);
