@@ -103,13 +103,25 @@ __global__ void __launch_bounds__(256) k_make_keys(const double *__restrict__ x,
 __global__ void __launch_bounds__(256) k_reduce_andor(const unsigned long long *__restrict__ part, int nblk,
                                                       unsigned long long *__restrict__ out) {
     __shared__ unsigned long long sa[256], so[256], sb[256];
+    constexpr int U = 8;  // partials per thread in flight
     for (int c = 0; c < 2; ++c) {
         unsigned long long a = ~0ull, o = 0ull, b = 0ull;
-        for (int k = threadIdx.x; k < nblk; k += 256) {
-            const unsigned long long *pp = part + ((int64_t)c * nblk + k) * 3;
-            a &= pp[0];
-            o |= pp[1];
-            b |= pp[2];
+        for (int k0 = threadIdx.x; k0 < nblk; k0 += 256 * U) {
+            unsigned long long pa[U], po[U], pb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {  // clamped indices: no branch around the loads
+                const int k = k0 + u * 256;
+                const unsigned long long *pp = part + ((int64_t)c * nblk + (k < nblk ? k : nblk - 1)) * 3;
+                pa[u] = pp[0];
+                po[u] = pp[1];
+                pb[u] = pp[2];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {  // a repeated partial changes neither AND nor OR
+                a &= pa[u];
+                o |= po[u];
+                b |= pb[u];
+            }
         }
         sa[threadIdx.x] = a;
         so[threadIdx.x] = o;
@@ -141,10 +153,19 @@ __global__ void __launch_bounds__(SORT_THREADS) k_hist(SortBufs B, int ping, int
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    // every load of the tile in flight before the first ranking
+    // (indices clamped into the array, so the loads need no branch)
+    uint64_t kk[SORT_ITEMS];
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = base + (int64_t)r * SORT_THREADS + threadIdx.x;
+        kk[r] = keys[i < n ? i : n - 1];
+    }
+#pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const int64_t i = base + (int64_t)r * SORT_THREADS + threadIdx.x;
         const bool ok = i < n;
-        const uint32_t d = ok ? (uint32_t)((keys[i] >> shift) & 0xff) : 0u;
+        const uint32_t d = ok ? (uint32_t)((kk[r] >> shift) & 0xff) : 0u;
         const uint64_t valid = __ballot(ok);
         const uint64_t peers = match_digit(d, valid);
         if (ok && popc_below(peers) == 0) atomicAdd(&h[d], (int32_t)__popcll(peers));
@@ -213,13 +234,19 @@ __global__ void __launch_bounds__(SORT_THREADS) k_scatter(SortBufs B, int ping, 
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * (SORT_ITEMS * WAVE);
     uint64_t kr[SORT_ITEMS];
     int32_t vr[SORT_ITEMS], rk[SORT_ITEMS];
+    // every load of the wave's keys and values in flight before the first ranking
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const int64_t i = base + (int64_t)r * WAVE + lane;
         const bool ok = i < n;
-        const uint64_t k = ok ? kin[i] : 0ull;
-        kr[r] = k;
+        kr[r] = ok ? kin[i] : 0ull;
         vr[r] = ok ? vin[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int64_t i = base + (int64_t)r * WAVE + lane;
+        const bool ok = i < n;
+        const uint64_t k = kr[r];
         const uint32_t d = (uint32_t)((k >> shift) & 0xff);
         const uint64_t valid = __ballot(ok);
         const uint64_t peers = match_digit(d, valid);

@@ -149,18 +149,23 @@ __global__ void __launch_bounds__(PT) k_part_count(int h, const int32_t *__restr
     const int64_t base = (int64_t)blockIdx.x * PTILE + threadIdx.x;
     uint64_t bal[PI];
     int32_t segs[PI];  // segment starting at this position, or -1
+    int32_t kv[PI], mv[PI];
+    // every load in flight first (positions clamped into the list, so the
+    // loads need no branch); positions >= n are flagged low and start nothing
 #pragma unroll
     for (int r = 0; r < PI; ++r) {
         const int64_t i = base + (int64_t)r * PT;
-        bool f = false;
-        segs[r] = -1;
-        if (i < n) {
-            int32_t a, e;
-            const int64_t s = seg_of(i, n, h, a, e);
-            f = key[i] < med_list[a + ((e - a) >> 1)];
-            if (a == (int32_t)i) segs[r] = (int32_t)s;
-        }
-        bal[r] = __ballot(f);
+        const int64_t ic = i < n ? i : n - 1;
+        int32_t a, e;
+        const int64_t s = seg_of(ic, n, h, a, e);
+        kv[r] = key[ic];
+        mv[r] = med_list[a + ((e - a) >> 1)];
+        segs[r] = (i < n && a == (int32_t)i) ? (int32_t)s : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {
+        const int64_t i = base + (int64_t)r * PT;
+        bal[r] = __ballot(i < n && kv[r] < mv[r]);
     }
     TileRank tr;
     tile_rank(bal, wc, tr);
@@ -205,40 +210,48 @@ __global__ void __launch_bounds__(PT) k_part_scatter(int h, const int32_t *__res
     }
     const int64_t base = (int64_t)blockIdx.x * PTILE + threadIdx.x;
     uint64_t bal[PI];
-    int32_t v0[PI], v1[PI], segs[PI];
+    int32_t v0[PI], v1[PI], segs[PI], mv[PI];
+    // every load in flight first (positions clamped into the list, so the
+    // loads need no branch); positions >= n are flagged low and not written
 #pragma unroll
     for (int r = 0; r < PI; ++r) {
         const int64_t i = base + (int64_t)r * PT;
-        bool f = false;
-        v0[r] = 0;
-        v1[r] = 0;
-        segs[r] = 0;
-        if (i < n) {
-            int32_t a, e;
-            segs[r] = (int32_t)seg_of(i, n, h, a, e);
-            v0[r] = R0[i];
-            v1[r] = R1[i];
-            f = (keysel ? v1[r] : v0[r]) < med_list[a + ((e - a) >> 1)];
-        }
-        bal[r] = __ballot(f);
+        const int64_t ic = i < n ? i : n - 1;
+        int32_t a, e;
+        segs[r] = (int32_t)seg_of(ic, n, h, a, e);
+        v0[r] = R0[ic];
+        v1[r] = R1[ic];
+        mv[r] = med_list[a + ((e - a) >> 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {
+        const int64_t i = base + (int64_t)r * PT;
+        bal[r] = __ballot(i < n && (keysel ? v1[r] : v0[r]) < mv[r]);
     }
     TileRank tr;
     tile_rank(bal, wc, tr);  // its barrier also publishes tp
     const uint64_t below_me = (1ull << lane_id()) - 1ull;
     const uint64_t me = 1ull << lane_id();
     const int32_t tile_base = LOCAL ? tp[blockIdx.x] : tpre[blockIdx.x];
+    int32_t lowbase[PI];
+#pragma unroll
+    for (int r = 0; r < PI; ++r) {  // the segments' low bases, loads first
+        const int64_t i = base + (int64_t)r * PT;
+        const int64_t ic = i < n ? i : n - 1;
+        int32_t a, e;
+        seg_of(ic, n, h, a, e);
+        const int32_t tile_a = (int32_t)(a / PTILE);
+        lowbase[r] = (LOCAL ? tp[tile_a] : tpre[tile_a]) + segbase_local[segs[r]];
+    }
 #pragma unroll
     for (int r = 0; r < PI; ++r) {
         const int64_t i = base + (int64_t)r * PT;
         if (i < n) {
-            const int64_t s = segs[r];
             int32_t a, e;
             seg_of(i, n, h, a, e);
             const int32_t k = (e - a) >> 1;
-            const int32_t tile_a = (int32_t)(a / PTILE);
-            const int32_t lowbase = (LOCAL ? tp[tile_a] : tpre[tile_a]) + segbase_local[s];
             const int32_t pos = tile_base + tr.before_round[r] + tr.wave_off[r] + (int32_t)__popcll(bal[r] & below_me);
-            const int32_t below = pos - lowbase;  // low flags of the segment before i
+            const int32_t below = pos - lowbase[r];  // low flags of the segment before i
             int64_t dst;
             if (bal[r] & me) dst = (int64_t)a + below;
             else dst = (int64_t)a + k + ((int32_t)(i - a) - below);
