@@ -354,12 +354,18 @@ __global__ void __launch_bounds__(WS_T) k_wscan_tiles(int L, const int32_t *__re
     const bool dead = pool_state[2 * L + 4] != 0;
     const int64_t nwords = dead ? 0 : level_words(sptr_prev, nb_prev);
     const int64_t base = (int64_t)blockIdx.x * WS_TILE + threadIdx.x * WS_PER;
-    int32_t a = 0, b = 0;
+    int32_t a = 0, b = 0, va[WS_PER], vb[WS_PER];
+#pragma unroll
+    for (int k = 0; k < WS_PER; ++k) {  // all loads in flight first (word 0 always exists)
+        const int64_t i = base + k < nwords ? base + k : 0;
+        va[k] = cnt_s[i];
+        vb[k] = cnt_w[i];
+    }
 #pragma unroll
     for (int k = 0; k < WS_PER; ++k) {
         if (base + k < nwords) {
-            a += cnt_s[base + k];
-            b += cnt_w[base + k];
+            a += va[k];
+            b += vb[k];
         }
     }
     int32_t ta, tb;

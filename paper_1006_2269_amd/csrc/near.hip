@@ -77,12 +77,15 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
     __builtin_amdgcn_wave_barrier();
     const int grp = lane / GL, jj = lane % GL;
     const int nsteps = (t1 - t0 + LPI - 1) / LPI;
-    // source point of lane jj in the record of step st (far away when absent)
+    // source point of lane jj in the record of step st; a lane past the end
+    // of its source leaf loads a point of the array and carries no charge, so
+    // the load needs no branch and its pairs add exactly zero
     auto load_src = [&](int st) {
         const int2 rj = s_rj[wv][st * LPI + grp];
         const bool ok = jj < rj.y - rj.x;
-        const float4 v = src[ok ? rj.x + jj : 0];
-        return ok ? v : make_float4(1e18f, 1e18f, 0.f, 0.f);
+        float4 v = src[ok ? rj.x + jj : 0];
+        v.z = ok ? v.z : 0.f;
+        return v;
     };
     auto eval = [&](float4 sv, int st) {
         const float4 rd = s_rd[wv][st * LPI + grp];
@@ -202,11 +205,12 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
     __builtin_amdgcn_wave_barrier();
     const int grp = lane / GL, jj = lane % GL;
     const int nsteps = (t1 - t0 + LPI - 1) / LPI;
-    auto load_src = [&](int st) {
+    auto load_src = [&](int st) {  // as in k_near32 (its source sum is not written either)
         const int2 rj = s_rj[wv][st * LPI + grp];
         const bool ok = jj < rj.y - rj.x;
-        const float4 v = src[ok ? rj.x + jj : 0];
-        return ok ? v : make_float4(1e18f, 1e18f, 0.f, 0.f);
+        float4 v = src[ok ? rj.x + jj : 0];
+        v.z = ok ? v.z : 0.f;
+        return v;
     };
     // The source sums of RING steps collect in one half of s_ring; at the
     // last step of the group (or of the segment) the block meets once, and
