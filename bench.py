@@ -162,8 +162,8 @@ def main():
     learned = None
     if weights is not None:
         def step_learned():
-            Ls, ps_, th, net = f.select(x, y, tol, weights)
-            f.build_tree(x, y, Ls)
+            # select + build_tree in one call (the sort overlaps the selector)
+            Ls, ps_, th, net = f.select_build_tree(x, y, tol, weights)
             f.connectivity(th)
             f.evaluate(q, ps_, "fp32_acc64", out=out)
             return Ls, ps_, th, net

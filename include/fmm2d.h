@@ -167,6 +167,23 @@ int fmm2d_features(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, 
 int fmm2d_select(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, double tol, const float *weights,
                  int *levels, int *p, double *theta, int *from_network);
 
+/* fmm2d_select followed by fmm2d_build_tree(x, y, n, *levels): the same
+ * decision and the same tree (Section 2's partition at the selected level
+ * count), in one call.  The sort of the coordinates, which does not depend on
+ * the level count, runs on the context stream while the features and the
+ * network run on the context's second stream, and the host waits once, for
+ * the decision and the validation together (pinned host words owned by the
+ * context); then the partition is queued.  All eight radix digits are sorted
+ * (fmm2d_build_tree skips digits on which all keys agree, which it learns
+ * from an extra wait).  Arguments and outputs as fmm2d_select; 4 <= n <=
+ * 2^31 - 1, 0 < tol < 1.  FMM2D_EINVAL for non-finite coordinates or
+ * |v| > 2^500: unlike fmm2d_build_tree, the previous tree is then discarded
+ * (the sort has already overwritten its sorted arrays), and connectivity or
+ * evaluate fail until a tree is built.  Returns with the partition queued on
+ * the context stream. */
+int fmm2d_select_build_tree(fmm2d_ctx *ctx, const double *x, const double *y, int64_t n, double tol,
+                            const float *weights, int *levels, int *p, double *theta, int *from_network);
+
 /* The selector network: d_in -> 64 -> 64 -> 64 -> 3, tanh on the hidden
  * layers, linear output, FP32.  The flat parameter vector holds each layer
  * in turn as its weight matrix [fan_out][fan_in] (row-major) followed by its

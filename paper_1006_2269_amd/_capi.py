@@ -45,6 +45,7 @@ SIGNATURES = [
     ("fmm2d_get_lists", I32, [P, I32, P, P, P, P]),
     ("fmm2d_features", I32, [P, P, P, I64, D, P]),
     ("fmm2d_select", I32, [P, P, P, I64, D, P, PI32, PI32, PD, PI32]),
+    ("fmm2d_select_build_tree", I32, [P, P, P, I64, D, P, PI32, PI32, PD, PI32]),
     ("fmm2d_mlp_nparams", I64, [I32]),
     ("fmm2d_mlp_forward", I32, [P, P, P, I64, I32, P]),
     ("fmm2d_mlp_grad", I32, [P, P, P, P, I64, I32, P, P]),

@@ -86,6 +86,11 @@ int fmm2d_destroy(fmm2d_ctx *c) {
             (void)hipEventDestroy(c->ev_side_in);
             (void)hipEventDestroy(c->ev_side_out);
         }
+        if (c->hpin) {
+            (void)hipEventDestroy(c->ev_keys);
+            (void)hipEventDestroy(c->ev_sel);
+            (void)hipHostFree(c->hpin);
+        }
         TreeState &t = c->tree;
         for (DevBuf *b : {&t.xsorted, &t.ysorted, &t.xorder, &t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1,
                           &t.starts, &t.rects, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
@@ -160,6 +165,70 @@ int fmm2d_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, 
         t.L = -1;
         return hip_fail(c, e, "build_tree");
     }
+    return FMM2D_OK;
+}
+
+int fmm2d_select_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol,
+                            const float *weights, int *levels, int *p, double *theta, int *from_network) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!x || !y || !levels || !p || !theta) return fail(c, FMM2D_EINVAL, "select_build_tree: NULL pointer");
+    if (n < 4 || n > 2147483647LL)
+        return fail(c, FMM2D_EINVAL, "select_build_tree: n = %lld not in [4, 2^31-1]", (long long)n);
+    if (!(tol > 0.0 && tol < 1.0)) return fail(c, FMM2D_EINVAL, "select_build_tree: tol must lie in (0, 1)");
+    DeviceGuard g(c->device);
+    TreeState &t = c->tree;
+    hipError_t e = hipSuccess;
+    if (!c->hpin) {
+        if ((e = hipHostMalloc(&c->hpin, 128, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&c->ev_keys, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&c->ev_sel, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(c, e, "select_build_tree");
+    }
+    unsigned long long *h_andor = static_cast<unsigned long long *>(c->hpin);  // 6 words
+    int *h_out = reinterpret_cast<int *>(static_cast<char *>(c->hpin) + 64);      // levels, p, network, bad
+    double *h_theta = reinterpret_cast<double *>(static_cast<char *>(c->hpin) + 80);
+    // The tree's sorted arrays are overwritten before the validation is read:
+    // the current tree is given up from here on.
+    t.has_lists = false;
+    t.nrec_valid = false;
+    t.L = -1;
+    // second-stream work of earlier calls first; then the selector on the
+    // second stream while the keys and all eight radix passes run here
+    e = side_join(c);
+    if (e == hipSuccess) e = side_begin(c);
+    if (e == hipSuccess) {
+        PhaseScope ps(c, PH_SELECT, c->side);
+        e = select_launch(c, c->side, x, y, n, tol, weights, h_out, h_theta);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->ev_sel, c->side);
+    if (e == hipSuccess) e = side_end(c);
+    if (e == hipSuccess) {
+        PhaseScope ps(c, PH_TREE);
+        e = sort_prepare_async(c, x, y, n, h_andor, c->ev_keys);
+        if (e == hipSuccess) e = tree_sort(c, n);
+    }
+    // one wait for the two small copies; the sort keeps running meanwhile
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev_keys);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev_sel);
+    if (e != hipSuccess) return hip_fail(c, e, "select_build_tree");
+    if ((h_andor[2] | h_andor[5]) != 0 || h_out[3])
+        return fail(c, FMM2D_EINVAL, "select_build_tree: coordinates must be finite with |v| <= 2^500");
+    const int L = h_out[0];
+    t.n = n;
+    t.L = L;
+    {
+        PhaseScope ps(c, PH_TREE);
+        e = build_tree_device(c, x, y, true);
+    }
+    if (e != hipSuccess) {
+        t.L = -1;
+        return hip_fail(c, e, "select_build_tree");
+    }
+    *levels = L;
+    *p = h_out[1];
+    *theta = *h_theta;
+    if (from_network) *from_network = h_out[2];
     return FMM2D_OK;
 }
 

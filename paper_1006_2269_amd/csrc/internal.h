@@ -165,6 +165,10 @@ struct fmm2d_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_side_in = nullptr, ev_side_out = nullptr;
     bool side_pending = false;
+    // fmm2d_select_build_tree: pinned host words for the two decisions read
+    // back without a stream-wide wait, and the events after their copies
+    void *hpin = nullptr;
+    hipEvent_t ev_keys = nullptr, ev_sel = nullptr;
     std::string err;
     fmm2d::TreeState tree;
     fmm2d::EvalState ev;
@@ -181,6 +185,12 @@ namespace fmm2d {
 hipError_t sort_prepare(fmm2d_ctx *c, const double *x, const double *y, int64_t n, bool *bad_input);
 hipError_t sort_finish(fmm2d_ctx *c, int64_t n, double *xs, double *ys, int32_t *xorder, int32_t *yorder,
                        int32_t *xrank, int32_t *yrank);
+// The keys and the validation without waiting: the AND / OR / bad words of
+// both coordinates (6 x u64) are copied to host memory h_andor and event ev
+// recorded after the copy; then every digit is treated as differing, so that
+// sort_finish can be queued before the host has read them.
+hipError_t sort_prepare_async(fmm2d_ctx *c, const double *x, const double *y, int64_t n,
+                              unsigned long long *h_andor, hipEvent_t ev);
 // sched.hip: the side stream (see fmm2d_ctx): begin a batch after the work
 // queued so far on the caller's stream, end it, and make the caller's stream
 // wait for the last batch
@@ -193,18 +203,23 @@ hipError_t scan_exclusive(fmm2d_ctx *c, const int32_t *in, int64_t n, int32_t *o
 hipError_t scan_exclusive_n(fmm2d_ctx *c, int k, const int32_t *const *in, int64_t n, int32_t *const *out);
 // select.hip: density features and the parameter decision (host outputs)
 hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, float *feat,
-                           const float *blob, float *xin, double **box_out);
+                           const float *blob, float *xin, double **box_out, hipStream_t st = nullptr);
 hipError_t select_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, const float *blob,
                          int out[4], double *theta);
+hipError_t select_launch(fmm2d_ctx *c, hipStream_t st, const double *x, const double *y, int64_t n, double tol,
+                         const float *blob, int *h_out, double *h_theta);
 // mlp.hip: the selector network
 int64_t mlp_nparams(int d_in);
-hipError_t mlp_forward(fmm2d_ctx *c, const float *P, const float *X, int64_t batch, int d_in, float *Y);
+hipError_t mlp_forward(fmm2d_ctx *c, const float *P, const float *X, int64_t batch, int d_in, float *Y,
+                       hipStream_t st = nullptr);
 hipError_t mlp_grad(fmm2d_ctx *c, const float *P, const float *X, const float *Y, int64_t batch, int d_in,
                     float *grad, float *loss);
 hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, int64_t np, int step, float lr,
                     float wd);
-// tree.hip
-hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y);
+// tree.hip: the tree at t.n points and t.L levels; `sorted`: tree_sort(c,
+// t.n) is already queued on the context stream
+hipError_t tree_sort(fmm2d_ctx *c, int64_t n);
+hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y, bool sorted = false);
 // lists.hip
 // overflow: 0 ok, 1 a pool was too small (grow and retry), 2 a level exceeds `limit` entries
 hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t cap_w, int64_t limit,

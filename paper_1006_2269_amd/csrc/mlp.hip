@@ -179,9 +179,10 @@ __global__ void k_adam(float *__restrict__ P, float *__restrict__ m, float *__re
 
 int64_t mlp_nparams(int d_in) { return nparams(d_in); }
 
-hipError_t mlp_forward(fmm2d_ctx *c, const float *P, const float *X, int64_t batch, int d_in, float *Y) {
+hipError_t mlp_forward(fmm2d_ctx *c, const float *P, const float *X, int64_t batch, int d_in, float *Y,
+                       hipStream_t st) {
     const unsigned grid = (unsigned)((batch + TS - 1) / TS);
-    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(MT), 0, c->stream, P, X, batch, d_in, Y);
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(MT), 0, st ? st : c->stream, P, X, batch, d_in, Y);
     return hipGetLastError();
 }
 

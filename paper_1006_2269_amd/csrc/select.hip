@@ -317,8 +317,9 @@ __global__ void k_select_final(const float *__restrict__ y, const float *__restr
 // feat: device float [NFEAT]; blob (nullable): weights, then xin receives the
 // standardised input.  Scratch: c->scr.sel.
 hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, float *feat,
-                           const float *blob, float *xin, double **box_out) {
+                           const float *blob, float *xin, double **box_out, hipStream_t st) {
     Scratch &s = c->scr;
+    if (!st) st = c->stream;
     const int nblk = (int)std::min<int64_t>((n + BT - 1) / BT, 1024);
     const int64_t nfine = int64_t(1) << (2 * FL);
     const int64_t stride = n > SAMPLE_MAX ? (n + SAMPLE_MAX - 1) / SAMPLE_MAX : 1;
@@ -332,19 +333,23 @@ hipError_t features_device(fmm2d_ctx *c, const double *x, const double *y, int64
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(box + 8);
     int32_t *fine = reinterpret_cast<int32_t *>(acc + ACC_COPIES * 9 * FL);
     int32_t *cnt5 = fine + GRID_COPIES * nfine;
-    hipLaunchKernelGGL(k_bbox_part, dim3(nblk), dim3(BT), 0, c->stream, x, y, n, part);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BT), 0, c->stream, part, nblk, box);
+    hipLaunchKernelGGL(k_bbox_part, dim3(nblk), dim3(BT), 0, st, x, y, n, part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BT), 0, st, part, nblk, box);
     hipLaunchKernelGGL(k_zero_grid, dim3(grid_for(GRID_COPIES * nfine + ACC_COPIES * 9 * FL, 256)), dim3(256), 0,
-                       c->stream, fine, nfine, acc);
-    hipLaunchKernelGGL(k_cells, dim3(grid_for(ns, 256)), dim3(256), 0, c->stream, x, y, ns, stride, box, fine);
-    hipLaunchKernelGGL(k_pool_hist_hi, dim3(1024), dim3(BT), 0, c->stream, fine, ns, acc, cnt5);
-    hipLaunchKernelGGL(k_pool_hist_lo, dim3(1), dim3(BT), 0, c->stream, cnt5, n, ns, tol, acc, feat, blob, xin);
+                       st, fine, nfine, acc);
+    hipLaunchKernelGGL(k_cells, dim3(grid_for(ns, 256)), dim3(256), 0, st, x, y, ns, stride, box, fine);
+    hipLaunchKernelGGL(k_pool_hist_hi, dim3(1024), dim3(BT), 0, st, fine, ns, acc, cnt5);
+    hipLaunchKernelGGL(k_pool_hist_lo, dim3(1), dim3(BT), 0, st, cnt5, n, ns, tol, acc, feat, blob, xin);
     if (box_out) *box_out = box;
     return hipGetLastError();
 }
 
-hipError_t select_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, const float *blob,
-                         int out[4], double *theta) {
+// Queues the features, the network and the decision on stream st, and the
+// copies of the decision into host memory h_out (levels, p, from_network, bad
+// input) and h_theta; nothing waits.  Host memory that is not pinned makes
+// the copies wait.
+hipError_t select_launch(fmm2d_ctx *c, hipStream_t st, const double *x, const double *y, int64_t n, double tol,
+                         const float *blob, int *h_out, double *h_theta) {
     Scratch &s = c->scr;
     FMM2D_TRY(s.sel2.ensure(sizeof(float) * (2 * NFEAT + 8) + 64));
     float *feat = s.sel2.as<float>();
@@ -353,12 +358,17 @@ hipError_t select_device(fmm2d_ctx *c, const double *x, const double *y, int64_t
     int *oi = reinterpret_cast<int *>(yout + 4);
     double *od = reinterpret_cast<double *>(s.sel2.as<char>() + sizeof(float) * (2 * NFEAT + 8) + 32);
     double *box = nullptr;
-    FMM2D_TRY(features_device(c, x, y, n, tol, feat, blob, xin, &box));
-    if (blob) FMM2D_TRY(mlp_forward(c, blob + HDR, xin, 1, NFEAT, yout));
-    hipLaunchKernelGGL(k_select_final, dim3(1), dim3(64), 0, c->stream, yout, blob, n, tol, box, oi, od);
+    FMM2D_TRY(features_device(c, x, y, n, tol, feat, blob, xin, &box, st));
+    if (blob) FMM2D_TRY(mlp_forward(c, blob + HDR, xin, 1, NFEAT, yout, st));
+    hipLaunchKernelGGL(k_select_final, dim3(1), dim3(64), 0, st, yout, blob, n, tol, box, oi, od);
     FMM2D_TRY(hipGetLastError());
-    FMM2D_TRY(hipMemcpyAsync(out, oi, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream));
-    FMM2D_TRY(hipMemcpyAsync(theta, od, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FMM2D_TRY(hipMemcpyAsync(h_out, oi, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+    return hipMemcpyAsync(h_theta, od, sizeof(double), hipMemcpyDeviceToHost, st);
+}
+
+hipError_t select_device(fmm2d_ctx *c, const double *x, const double *y, int64_t n, double tol, const float *blob,
+                         int out[4], double *theta) {
+    FMM2D_TRY(select_launch(c, c->stream, x, y, n, tol, blob, out, theta));
     return hipStreamSynchronize(c->stream);
 }
 

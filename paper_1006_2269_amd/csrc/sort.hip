@@ -347,6 +347,30 @@ hipError_t sort_prepare(fmm2d_ctx *c, const double *x, const double *y, int64_t 
     return hipSuccess;
 }
 
+hipError_t sort_prepare_async(fmm2d_ctx *c, const double *x, const double *y, int64_t n,
+                              unsigned long long *h_andor, hipEvent_t ev) {
+    Scratch &s = c->scr;
+    const int nkb = (int)((n + 255) / 256);
+    FMM2D_TRY(s.keys0.ensure(sizeof(uint64_t) * 2 * n));
+    FMM2D_TRY(s.keys1.ensure(sizeof(uint64_t) * 2 * n));
+    FMM2D_TRY(s.vals0.ensure(sizeof(int32_t) * 2 * n));
+    FMM2D_TRY(s.vals1.ensure(sizeof(int32_t) * 2 * n));
+    FMM2D_TRY(s.flag.ensure(sizeof(unsigned long long) * 3 * 2 * (size_t)nkb + 64));
+    FMM2D_TRY(s.aux.ensure(4096));
+    SortBufs B;
+    sort_bufs(c, n, B);
+    unsigned long long *part = s.flag.as<unsigned long long>();
+    unsigned long long *andor = s.aux.as<unsigned long long>();
+    hipLaunchKernelGGL(k_make_keys, dim3(nkb, 2), dim3(256), 0, c->stream, x, y, n, B, part, nkb);
+    hipLaunchKernelGGL(k_reduce_andor, dim3(1), dim3(256), 0, c->stream, part, nkb, andor);
+    FMM2D_TRY(hipGetLastError());
+    FMM2D_TRY(hipMemcpyAsync(h_andor, andor, sizeof(unsigned long long) * 6, hipMemcpyDeviceToHost, c->stream));
+    FMM2D_TRY(hipEventRecord(ev, c->stream));
+    s.sort_n = n;
+    s.sort_differ = ~0ull;  // all eight passes: the skipped digits are known only after the host reads
+    return hipSuccess;
+}
+
 // Second half: the radix passes over the digits that differ, then the sorted
 // coordinates, their original indices and the ranks of the points.
 hipError_t sort_finish(fmm2d_ctx *c, int64_t n, double *xs, double *ys, int32_t *xorder, int32_t *yorder,

@@ -448,18 +448,33 @@ __global__ void k_gather(const int32_t *__restrict__ XLx, const int32_t *__restr
 
 }  // namespace
 
-hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
+// The tree's arrays of n entries (the sort writes into some of them).
+static hipError_t tree_point_buffers(TreeState &t, int64_t n) {
+    FMM2D_TRY(t.xsorted.ensure(sizeof(double) * n));
+    FMM2D_TRY(t.ysorted.ensure(sizeof(double) * n));
+    FMM2D_TRY(t.xorder.ensure(sizeof(int32_t) * n));
+    for (DevBuf *b : {&t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1, &t.perm, &t.leafid})
+        FMM2D_TRY(b->ensure(sizeof(int32_t) * n));
+    return hipSuccess;
+}
+
+// Step 1 of the build: sort each coordinate by (value, index), with the
+// ranks of the points (yorder is kept in YLx until the lists are made).
+hipError_t tree_sort(fmm2d_ctx *c, int64_t n) {
+    TreeState &t = c->tree;
+    FMM2D_TRY(tree_point_buffers(t, n));
+    return sort_finish(c, n, t.xsorted.as<double>(), t.ysorted.as<double>(), t.xorder.as<int32_t>(),
+                       t.YLx.as<int32_t>(), t.T0.as<int32_t>(), t.T1.as<int32_t>());
+}
+
+hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y, bool sorted) {
     TreeState &t = c->tree;
     Scratch &s = c->scr;
     const int64_t n = t.n;
     const int L = t.L;
     const int64_t nbox = level_offset(L + 1);
     const int64_t nleaf = int64_t(1) << (2 * L);
-    FMM2D_TRY(t.xsorted.ensure(sizeof(double) * n));
-    FMM2D_TRY(t.ysorted.ensure(sizeof(double) * n));
-    FMM2D_TRY(t.xorder.ensure(sizeof(int32_t) * n));
-    for (DevBuf *b : {&t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1, &t.perm, &t.leafid})
-        FMM2D_TRY(b->ensure(sizeof(int32_t) * n));
+    FMM2D_TRY(tree_point_buffers(t, n));
     FMM2D_TRY(t.starts.ensure(sizeof(int32_t) * (depth_offset(2 * L + 1) + 1)));
     FMM2D_TRY(t.rects.ensure(sizeof(Rect) * nbox));
     FMM2D_TRY(t.geom.ensure(sizeof(double4) * nbox));
@@ -473,11 +488,11 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y) {
     const int ntile = (int)((n + PTILE - 1) / PTILE);
     FMM2D_TRY(s.tiles2.ensure(sizeof(int32_t) * (ntile + 1)));
 
-    // 1. sort each coordinate by (value, index); ranks of the points
+    // 1. sort each coordinate by (value, index); ranks of the points (already
+    // queued by the caller when `sorted`)
     int32_t *yorder = t.YLx.as<int32_t>();  // borrowed until the lists are initialised
     int32_t *xrank = t.T0.as<int32_t>(), *yrank = t.T1.as<int32_t>();
-    FMM2D_TRY(sort_finish(c, n, t.xsorted.as<double>(), t.ysorted.as<double>(), t.xorder.as<int32_t>(), yorder,
-                          xrank, yrank));
+    if (!sorted) FMM2D_TRY(tree_sort(c, n));
     // 2. the two rank lists
     // YLx is overwritten last: read yorder (== YLx storage) before writing it.
     // k_init_lists reads yorder[r] and writes YLx[r] for the same r only.

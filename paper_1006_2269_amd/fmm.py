@@ -144,6 +144,28 @@ class FMM2D:
                                            ctypes.byref(p), ctypes.byref(th), ctypes.byref(net)))
         return L.value, p.value, th.value, bool(net.value)
 
+    def select_build_tree(self, x: torch.Tensor, y: torch.Tensor, tol: float, weights: torch.Tensor | None = None):
+        """select() then build_tree() at the selected level count, in one call
+        (the sort overlaps the selector); returns (levels, p, theta, from_network)."""
+        _require(x, torch.float64, self.device, "x")
+        _require(y, torch.float64, self.device, "y")
+        if x.numel() != y.numel():
+            raise ValueError("x and y differ in length")
+        wp = None
+        if weights is not None:
+            _require(weights, torch.float32, self.device, "weights")
+            need = _capi.SELECT_HEADER + self._lib.fmm2d_mlp_nparams(_capi.NFEAT)
+            if weights.numel() != need:
+                raise ValueError("weights must hold %d floats" % need)
+            wp = _ptr(weights)
+        L, p, net = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        th = ctypes.c_double()
+        self._check(self._lib.fmm2d_select_build_tree(self._h, _ptr(x), _ptr(y), x.numel(), float(tol), wp,
+                                                      ctypes.byref(L), ctypes.byref(p), ctypes.byref(th),
+                                                      ctypes.byref(net)))
+        self.n, self.levels = x.numel(), L.value
+        return L.value, p.value, th.value, bool(net.value)
+
     def mlp_nparams(self, d_in: int) -> int:
         return int(self._lib.fmm2d_mlp_nparams(int(d_in)))
 

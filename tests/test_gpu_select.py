@@ -229,3 +229,69 @@ def test_shipped_weights_decode_like_the_oracle(fmm):
         assert net is True
         assert (L, p, th, net) == S.decide(out, blob, ps.n, tol)
         assert 1 <= L <= S.levels_max(ps.n) and 1 <= p <= 63 and th in S.THETAS
+
+
+def _tree_arrays(fmm):
+    torch.cuda.synchronize()
+    return (fmm.perm().cpu().numpy().copy(), fmm.leaf_start().cpu().numpy().copy(),
+            fmm.rects().cpu().numpy().view(np.int64).copy())
+
+
+@pytest.mark.parametrize("name", sorted(LAYOUTS))
+@pytest.mark.parametrize("with_net", [True, False])
+def test_select_build_tree_equals_separate_calls(fmm, name, with_net):
+    # one call = select, then build_tree at the selected level count: the same
+    # decision and a bit-identical tree (grid_64x64 and coincident_100 have
+    # digits on which all keys agree, which build_tree skips and the combined
+    # call sorts anyway)
+    from paper_1006_2269_amd import selector
+
+    ps = LAYOUTS[name]
+    tol = 1e-6
+    w = selector.weights_tensor(torch.device("cuda", 0)) if with_net else None
+    if with_net and w is None:
+        pytest.skip("no shipped weights")
+    _announce("select_build_tree", name, ps.n, with_net)
+    x, y = _dev(ps.x), _dev(ps.y)
+    dec = fmm.select(x, y, tol, w)
+    fmm.build_tree(x, y, dec[0])
+    ref = _tree_arrays(fmm)
+    got_dec = fmm.select_build_tree(x, y, tol, w)
+    assert got_dec == dec
+    for a, b in zip(_tree_arrays(fmm), ref):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_select_build_tree_then_evaluate(fmm):
+    # the rest of the path runs on the combined call's tree exactly as on
+    # build_tree's (binary64 potentials bit-identical)
+    ps = LAYOUTS["mixed_1m_scaled_50k"]
+    _announce("select_build_tree evaluate", ps.n)
+    x, y, q = _dev(ps.x), _dev(ps.y), _dev(ps.q)
+    L, p, th, _ = fmm.select(x, y, 1e-6)
+    fmm.build_tree(x, y, L)
+    fmm.connectivity(th)
+    ref = fmm.evaluate(q, p, "fp64").cpu().numpy()
+    assert fmm.select_build_tree(x, y, 1e-6) == (L, p, th, False)
+    fmm.connectivity(th)
+    np.testing.assert_array_equal(fmm.evaluate(q, p, "fp64").cpu().numpy(), ref)
+
+
+def test_select_build_tree_rejects_bad_input(fmm):
+    from paper_1006_2269_amd.fmm import FMM2DError
+
+    ps = LAYOUTS["uniform_10k"]
+    x, y = ps.x.copy(), ps.y.copy()
+    fmm.build_tree(_dev(x), _dev(y), 4)
+    fmm.connectivity(0.5)
+    x[123] = np.nan
+    _announce("select_build_tree nan")
+    with pytest.raises(FMM2DError):
+        fmm.select_build_tree(_dev(x), _dev(y), 1e-6)
+    # the previous tree is given up: nothing to connect until a tree is built
+    with pytest.raises(FMM2DError):
+        fmm.connectivity(0.5)
+    L, p, th, _ = fmm.select_build_tree(_dev(ps.x), _dev(ps.y), 1e-6)
+    fmm.connectivity(th)
+    phi = fmm.evaluate(_dev(ps.q), p, "fp64").cpu().numpy()
+    assert np.all(np.isfinite(phi))
