@@ -87,7 +87,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this library has no multi-GPU path (DESIGN.md describes how the "
+        print("bench.py measures one GPU: this library has no multi-GPU path (the design notes describe how the "
               "tree would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np

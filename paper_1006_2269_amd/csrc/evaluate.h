@@ -14,11 +14,13 @@ hipError_t ensure_mhat(fmm2d_ctx *c);
 hipError_t m2l_all(fmm2d_ctx *c, int p, int mode);
 // L2P plus the near field at the leaves in precision `mode`; writes the
 // leaf-ordered potentials to ev.phi_leaf (near.hip).
-// The leaf pass in two stages: NEAR_START packs the sources and queues the
-// near-field kernels on the context's second stream (they need neither
-// expansion), NEAR_FINISH makes the context stream wait for them and adds
-// L2P and the near-field sums.  The far field runs in between.
-enum { NEAR_START = 0, NEAR_FINISH = 1 };
+// The leaf pass in three stages: NEAR_PREP packs the sources (and builds
+// the full near-field schedule where it is needed) on the context stream and
+// makes the context's second stream wait for that point; NEAR_LAUNCH queues
+// the near-field kernels on the second stream (they need neither expansion);
+// NEAR_FINISH makes the context stream wait for them and adds L2P and the
+// near-field sums.  The far field runs in between.
+enum { NEAR_PREP = 0, NEAR_LAUNCH = 1, NEAR_FINISH = 2 };
 hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage);
 // list segments for the M2L and near-field kernels (sched.hip)
 hipError_t build_schedules(fmm2d_ctx *c);

@@ -547,9 +547,12 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
     }
     {
         // the near field needs no expansion: it runs on the second stream
-        // while the upward pass, M2L and L2L run here
+        // while the upward pass, M2L and L2L run here (queueing the M2L
+        // first, after the upward pass, measured no faster: the two share the
+        // chip and the upward pass is then exposed)
         PhaseScope ps(c, PH_LEAF);
-        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_START));
+        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_PREP));
+        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_LAUNCH));
     }
     {
         PhaseScope ps(c, PH_UPWARD);

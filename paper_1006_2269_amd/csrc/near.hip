@@ -512,7 +512,7 @@ __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, do
 }
 
 // FP32 paths with leaves of at most 64 points: each leaf pair once.  Stage
-// NEAR_START queues the pair kernel and the lower-segment sums on the second
+// NEAR_LAUNCH queues the pair kernel and the lower-segment sums on the second
 // stream (after the transposed positions, queued there by the list build),
 // NEAR_FINISH the reduction with L2P on the context stream.
 template <int TM, int GL, int CH>
@@ -530,10 +530,11 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage) {
     const int32_t *sp = t.sptr.as<int32_t>() + ptr_offset(L);
     const int64_t ns = t.s_off[L + 1] - t.s_off[L];
     const Schedule &lo = t.near_lo;
-    if (stage == NEAR_START) {
+    if (stage == NEAR_PREP) {
         FMM2D_TRY(e.npart.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
         FMM2D_TRY(t.spart.ensure(sizeof(float) * (size_t)(ns > 0 ? ns : 1) * GL));
         FMM2D_TRY(t.lsum.ensure(sizeof(double) * (size_t)(lo.bound > 0 ? lo.bound : 1) * GL));
+        return side_begin(c);  // the packed sources
     }
     double *part = e.npart.as<double>();
     float *spart = t.spart.as<float>();
@@ -546,7 +547,6 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage) {
         return hipGetLastError();
     }
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
-    FMM2D_TRY(side_begin(c));  // the packed sources
     {
         PhaseScope kernel_scope(c, PH_NEAR_KERNEL, c->side);  // the near-field kernel alone
         if (mode == FMM2D_MODE_FP32_ACC64)
@@ -589,7 +589,10 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage) {
     const float4 *rd = t.nrec_d.as<float4>();
     const int2 *tab = sc.table.as<int2>();
     const int32_t *nsp = sc.segoff.as<int32_t>() + nleaf;
-    if (stage == NEAR_START) FMM2D_TRY(e.npart.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
+    if (stage == NEAR_PREP) {
+        FMM2D_TRY(e.npart.ensure(sizeof(double) * (nitems > 0 ? nitems : 1) * TM));
+        return side_begin(c);  // the packed sources (charges in leaf order for binary64)
+    }
     double *part = e.npart.as<double>();
     const double scale = mode == FMM2D_MODE_FP64 ? 0.5 : HALF_LN2_D;
     if (stage == NEAR_FINISH) {
@@ -600,7 +603,6 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage) {
         return hipGetLastError();
     }
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
-    FMM2D_TRY(side_begin(c));  // the packed sources (charges in leaf order for binary64)
     {
         PhaseScope kernel_scope(c, PH_NEAR_KERNEL, c->side);  // the near-field kernel alone
         if (mode == FMM2D_MODE_FP64) {
@@ -638,7 +640,7 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage) {
     const int64_t nleaf = int64_t(1) << (2 * L);
     const int64_t maxleaf = (n + nleaf - 1) >> (2 * L);  // ceil(n / 4^L)
     if (!t.nrec_valid) return hipErrorInvalidValue;  // records come with the lists
-    if (stage == NEAR_START && mode != FMM2D_MODE_FP64) {
+    if (stage == NEAR_PREP && mode != FMM2D_MODE_FP64) {
         FMM2D_TRY(e.src.ensure(sizeof(float4) * n));
         hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.loc.as<float2>(),
                            e.qs.as<double>(), n, e.src.as<float4>());
@@ -652,7 +654,7 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage) {
         if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode, stage);
         return launch_near_sym<16, 64, 4>(c, p, mode, stage);
     }
-    FMM2D_TRY(ensure_near_full_schedule(c));  // built on the context stream, before the second stream waits
+    if (stage == NEAR_PREP) FMM2D_TRY(ensure_near_full_schedule(c));  // on the context stream, before the second stream waits
     if (ml <= 8) return launch_near<8, 8>(c, p, mode, ml, stage);
     if (ml <= 16) return launch_near<16, 16>(c, p, mode, ml, stage);
     if (ml <= 32) return launch_near<16, 32>(c, p, mode, ml, stage);

@@ -39,7 +39,7 @@ def fmm():
 # Connectivity at theta = 1/2 on this point set ran on the GPU once with an
 # interim lists implementation (level totals by int64 atomics) and the box
 # reported a GPU fault; that implementation is gone and the cause was not
-# identified, so the case stays off the GPU until it is (see DESIGN.md).
+# identified, so the case stays off the GPU until it is.
 FAULTED = {("clustered_scaled_20k_L6", 0.5)}
 
 
@@ -233,3 +233,47 @@ def test_list_limit_fails_cleanly(orc, monkeypatch):
     sp, si, wp, wi = (a.cpu().numpy().astype(np.int64) for a in ctx.lists(4))
     assert np.array_equal(wi, ls.widx[4]) and np.array_equal(si, ls.sidx[4])
     ctx.close()
+
+
+def test_call_orders_with_second_stream(fmm, orc):
+    # Work queued on the library's second stream (transposed positions after
+    # connectivity, the near field during evaluate, the selector during the
+    # combined call) must be ordered against every later call: trees and
+    # lists rebuilt without an evaluate in between, evaluates back to back,
+    # the combined call right after connectivity.  Each result against the
+    # oracle FMM in binary64.
+    cases = ["uniform_3200_L3", "uniform_20k_L5", "duplicates_4k_L3"]
+    pts = {c: TREE_CASES[c][0]() for c in cases}
+    ref = {}
+    for c in cases:
+        ps, L = pts[c], TREE_CASES[c][1]
+        ref[c] = orc.fmm(ps.x, ps.y, ps.q, L, 12, 0.5)
+
+    def check(c, phi):
+        scale = np.abs(ref[c]).max()
+        assert np.abs(phi - ref[c]).max() <= 1e-12 * scale, c
+
+    a, b, d = cases
+    _announce("call orders", *cases)
+    # connectivity with no evaluate, then another tree and its lists
+    fmm.build_tree(_dev(pts[a].x), _dev(pts[a].y), TREE_CASES[a][1])
+    fmm.connectivity(0.5)
+    fmm.build_tree(_dev(pts[b].x), _dev(pts[b].y), TREE_CASES[b][1])
+    fmm.connectivity(0.5)
+    # the reduced mode queues the pair-once near field (20-point leaves) on
+    # the second stream; then binary64 on the same lists, twice
+    fmm.evaluate(_dev(pts[b].q), 12, "fp32_acc64")
+    check(b, fmm.evaluate(_dev(pts[b].q), 12, "fp64").cpu().numpy())
+    check(b, fmm.evaluate(_dev(pts[b].q), 12, "fp64").cpu().numpy())
+    # the combined call right after a connectivity, then the rule's tree
+    # replaced by the case's own level count
+    fmm.connectivity(0.5)
+    fmm.select_build_tree(_dev(pts[d].x), _dev(pts[d].y), 1e-6)
+    fmm.build_tree(_dev(pts[d].x), _dev(pts[d].y), TREE_CASES[d][1])
+    fmm.connectivity(0.5)
+    fmm.evaluate(_dev(pts[d].q), 12, "fp32")
+    check(d, fmm.evaluate(_dev(pts[d].q), 12, "fp64").cpu().numpy())
+    # and back to the first case
+    fmm.build_tree(_dev(pts[a].x), _dev(pts[a].y), TREE_CASES[a][1])
+    fmm.connectivity(0.5)
+    check(a, fmm.evaluate(_dev(pts[a].q), 12, "fp64").cpu().numpy())
