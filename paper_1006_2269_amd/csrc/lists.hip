@@ -377,39 +377,30 @@ __global__ void __launch_bounds__(WS_T) k_wscan_tiles(int L, const int32_t *__re
     }
 }
 
-constexpr int WT_T = 1024;
-__global__ void __launch_bounds__(WT_T) k_wscan_top(int L, int ntile, const int64_t *__restrict__ pool_state,
-                                                    int32_t *__restrict__ tsum, int32_t *__restrict__ sptr_cur,
-                                                    int32_t *__restrict__ wptr_cur, int64_t nb) {
-    __shared__ int32_t tmp[WT_T / 64];
-    if (pool_state[2 * L + 4]) return;  // uniform
-    const int per = (ntile + WT_T - 1) / WT_T;
-    for (int arr = 0; arr < 2; ++arr) {
-        int32_t *ts = tsum + (int64_t)arr * ntile;
-        const int k0 = threadIdx.x * per;
-        int32_t sum = 0;
-        for (int k = k0; k < k0 + per && k < ntile; ++k) sum += ts[k];
-        int32_t total;
-        int32_t run = block_excl_scan<WT_T>(sum, tmp, total);
-        for (int k = k0; k < k0 + per && k < ntile; ++k) {
-            const int32_t v = ts[k];
-            ts[k] = run;
-            run += v;
-        }
-        if (threadIdx.x == 0) (arr ? wptr_cur : sptr_cur)[nb] = total;
-    }
-}
-
+// Exclusive scan of the word counts of one level in place: each tile adds
+// the sum of the tile sums before it (formed by the block itself: a level has
+// a few hundred tiles at most) to its own scan.  The last tile of the level
+// writes the level totals as the last row pointers; tile 0 runs even when the
+// level has no word, so that the totals are 0 then.
 __global__ void __launch_bounds__(WS_T) k_wscan_apply(int L, const int32_t *__restrict__ sptr_prev, int64_t nb_prev,
                                                       const int64_t *__restrict__ pool_state,
                                                       int32_t *__restrict__ cnt_s, int32_t *__restrict__ cnt_w,
-                                                      const int32_t *__restrict__ tsum, int ntile) {
+                                                      const int32_t *__restrict__ tsum, int ntile,
+                                                      int32_t *__restrict__ sptr_cur, int32_t *__restrict__ wptr_cur,
+                                                      int64_t nb) {
     __shared__ int32_t tmp[WS_T / 64];
     if (pool_state[2 * L + 4]) return;  // uniform
     const int64_t nwords = level_words(sptr_prev, nb_prev);
-    if ((int64_t)blockIdx.x * WS_TILE >= nwords) return;  // uniform
+    const int64_t nact = (nwords + WS_TILE - 1) / WS_TILE;
+    const int64_t last = nact > 1 ? nact - 1 : 0;
+    if ((int64_t)blockIdx.x > last) return;  // uniform
     const int64_t base = (int64_t)blockIdx.x * WS_TILE + threadIdx.x * WS_PER;
     for (int arr = 0; arr < 2; ++arr) {
+        const int32_t *ts = tsum + (int64_t)arr * ntile;
+        int32_t s = 0;
+        for (int k = threadIdx.x; k < (int)blockIdx.x; k += WS_T) s += ts[k];
+        int32_t before;
+        (void)block_excl_scan<WS_T>(s, tmp, before);  // the tile sums before this tile
         int32_t *cnt = arr ? cnt_w : cnt_s;
         int32_t v[WS_PER], sum = 0;
 #pragma unroll
@@ -418,12 +409,13 @@ __global__ void __launch_bounds__(WS_T) k_wscan_apply(int L, const int32_t *__re
             sum += v[k];
         }
         int32_t total;
-        int32_t run = block_excl_scan<WS_T>(sum, tmp, total) + tsum[(int64_t)arr * ntile + blockIdx.x];
+        int32_t run = block_excl_scan<WS_T>(sum, tmp, total) + before;
 #pragma unroll
         for (int k = 0; k < WS_PER; ++k) {
             if (base + k < nwords) cnt[base + k] = run;
             run += v[k];
         }
+        if ((int64_t)blockIdx.x == last && threadIdx.x == 0) (arr ? wptr_cur : sptr_cur)[nb] = before + total;
     }
 }
 
@@ -573,9 +565,8 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
                                t.sidx.as<int32_t>(), own_prev, ps, bits, cs, cw);
             hipLaunchKernelGGL(k_wscan_tiles, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps, cs, cw,
                                tsum, ntile);
-            hipLaunchKernelGGL(k_wscan_top, dim3(1), dim3(WT_T), 0, c->stream, L, ntile, ps, tsum, sp_cur, wp_cur, nb);
             hipLaunchKernelGGL(k_wscan_apply, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps, cs, cw,
-                               tsum, ntile);
+                               tsum, ntile, sp_cur, wp_cur, nb);
             hipLaunchKernelGGL(k_lists_advance, dim3(1), dim3(1), 0, c->stream, l, L, nb, sp_cur, wp_cur, ps, cap_s,
                                cap_w, limit);
             hipLaunchKernelGGL(k_flat_fill, dim3(fgrid), dim3(256), 0, c->stream, l, L, gL, sp_prev, nb_prev,
