@@ -87,6 +87,12 @@ def _load():
     lib.orc_m2p.restype = None
     lib.orc_fmm_eval.argtypes = [i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P]
     lib.orc_fmm_eval.restype = i32
+    lib.orc_fmm_eval_field.argtypes = [i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_fmm_eval_field.restype = i32
+    lib.orc_direct_field.argtypes = [i64, P, P, P, i64, P, P, P]
+    lib.orc_direct_field.restype = None
+    lib.orc_l2p_grad.argtypes = [P, d, d, d, i32, i64, P, P, P, P]
+    lib.orc_l2p_grad.restype = None
     _lib = lib
     return lib
 
@@ -122,6 +128,20 @@ def direct(x, y, q, targets=None) -> np.ndarray:
     out = np.empty(t.shape[0], dtype=np.float64)
     lib.orc_direct(n, _p(x), _p(y), _p(q), t.shape[0], _p(t), _p(out))
     return out
+
+
+def direct_field(x, y, q, targets=None):
+    """(d Phi/dx, d Phi/dy) at the given target indices: the gradient of the
+    sum (1.1), sum over j with (x_j, y_j) != (x_i, y_i) of q_j (z_i - z_j) /
+    |z_i - z_j|^2 componentwise, binary64 with compensated summation."""
+    lib = _load()
+    x, y, q = _f64(x), _f64(y), _f64(q)
+    n = x.shape[0]
+    t = _i64(np.arange(n) if targets is None else targets)
+    gx = np.empty(t.shape[0], dtype=np.float64)
+    gy = np.empty(t.shape[0], dtype=np.float64)
+    lib.orc_direct_field(n, _p(x), _p(y), _p(q), t.shape[0], _p(t), _p(gx), _p(gy))
+    return gx, gy
 
 
 # --------------------------------------------------------------------------
@@ -321,6 +341,35 @@ def fmm(x, y, q, levels: int, p: int, theta: float) -> np.ndarray:
     """Tree, lists and evaluation in one call."""
     t = tree(x, y, levels)
     return fmm_eval(x, y, q, t, lists(t, theta), p)
+
+
+def fmm_field(x, y, q, levels: int, p: int, theta: float):
+    """(phi, d phi/dx, d phi/dy) by the FMM: as fmm(), and at the leaves the
+    derivative of the local expansion plus the direct gradient over the
+    strong list.  Original order."""
+    lib = _load()
+    x, y, q = _f64(x), _f64(y), _f64(q)
+    t = tree(x, y, levels)
+    ls = lists(t, theta)
+    L = t.levels
+    wptr_off = np.zeros(L + 1, dtype=np.int64)
+    widx_off = np.zeros(L + 1, dtype=np.int64)
+    for l in range(1, L + 1):
+        wptr_off[l] = wptr_off[l - 1] + ls.wptr[l - 1].shape[0]
+        widx_off[l] = widx_off[l - 1] + ls.widx[l - 1].shape[0]
+    wptr = _i64(np.concatenate(ls.wptr))
+    widx = _i64(np.concatenate(ls.widx)) if sum(w.shape[0] for w in ls.widx) else np.zeros(1, np.int64)
+    geom = _f64(t.geom)
+    n = x.shape[0]
+    phi, gx, gy = (np.empty(n, dtype=np.float64) for _ in range(3))
+    rc = lib.orc_fmm_eval_field(n, _p(x), _p(y), _p(q), L, p, _p(_i64(t.perm)),
+                                _p(_i64(t.leaf_start)), _p(geom), _p(wptr), _p(widx),
+                                _p(wptr_off), _p(widx_off), _p(_i64(ls.sptr[L])),
+                                _p(_i64(ls.sidx[L]) if ls.sidx[L].shape[0] else np.zeros(1, np.int64)),
+                                _p(phi), _p(gx), _p(gy))
+    if rc != 0:
+        raise RuntimeError("orc_fmm_eval_field failed: %d" % rc)
+    return phi, gx, gy
 
 
 # --------------------------------------------------------------------------

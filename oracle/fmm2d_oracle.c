@@ -57,6 +57,30 @@ void orc_direct(int64_t n, const double *x, const double *y, const double *q,
     }
 }
 
+/* The gradient of the interaction sum (1.1) at each target, written as the
+ * plain definition: d/dx and d/dy of q_j log|x - x_j| are q_j (x - x_j)/r^2
+ * and q_j (y - y_j)/r^2 with r = |x - x_j|; coincident pairs contribute
+ * nothing.  Neumaier-compensated sums over j.                               */
+void orc_direct_field(int64_t n, const double *x, const double *y, const double *q,
+                      int64_t m, const int64_t *targets, double *gx, double *gy)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < m; ++t) {
+        int64_t i = targets[t];
+        double sx = 0.0, cx = 0.0, sy = 0.0, cy = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (x[j] == x[i] && y[j] == y[i])
+                continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j];
+            double r2 = dx * dx + dy * dy;
+            neumaier_add(&sx, &cx, q[j] * dx / r2);
+            neumaier_add(&sy, &cy, q[j] * dy / r2);
+        }
+        gx[t] = sx + cx;
+        gy[t] = sy + cy;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* O2: the balanced pyramid of median splits (Section 4, Fig. 1.1).
  *
@@ -359,6 +383,22 @@ void orc_l2p(const double *B, double cx, double cy, double s, int p,
     }
 }
 
+/* The gradient of the local expansion's potential at each point: with
+ * F(z) = sum_l B_l ((z - c)/s)^l analytic, d/dx Re F = Re F'(z) and
+ * d/dy Re F = -Im F'(z), F'(z) = sum_{l>=1} l B_l ((z - c)/s)^(l-1) / s.     */
+void orc_l2p_grad(const double *B, double cx, double cy, double s, int p,
+                  int64_t n, const double *x, const double *y, double *gx, double *gy)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        cplx zeta = ((x[i] - cx) + I * (y[i] - cy)) / s;
+        cplx d = 0.0;
+        for (int l = p; l >= 1; --l) d = d * zeta + (double)l * (B[2 * l] + I * B[2 * l + 1]);
+        d /= s;
+        gx[i] += creal(d);
+        gy[i] -= cimag(d);
+    }
+}
+
 /* Multipole expansion evaluated at points (used by the operator pins).      */
 void orc_m2p(const double *A, double cx, double cy, double s, int p,
              int64_t n, const double *x, const double *y, double *phi)
@@ -386,11 +426,12 @@ void orc_m2p(const double *A, double cx, double cy, double s, int p,
 /* ------------------------------------------------------------------------ */
 static double box_scale(const double *g) { return g[2] > 0.0 ? g[2] : 1.0; }
 
-int orc_fmm_eval(int64_t n, const double *x, const double *y, const double *q,
-                 int L, int p, const int64_t *perm, const int64_t *leaf_start,
-                 const double *geom, const int64_t *wptr, const int64_t *widx,
-                 const int64_t *wptr_off, const int64_t *widx_off,
-                 const int64_t *sptr_L, const int64_t *sidx_L, double *phi)
+static int fmm_eval_impl(int64_t n, const double *x, const double *y, const double *q,
+                         int L, int p, const int64_t *perm, const int64_t *leaf_start,
+                         const double *geom, const int64_t *wptr, const int64_t *widx,
+                         const int64_t *wptr_off, const int64_t *widx_off,
+                         const int64_t *sptr_L, const int64_t *sidx_L, double *phi,
+                         double *gx, double *gy)
 {
     if (p < 1 || p > 64) return -1;
     int64_t nbox = level_offset(L + 1);
@@ -402,8 +443,10 @@ int orc_fmm_eval(int64_t n, const double *x, const double *y, const double *q,
     double *ys = (double *)malloc(sizeof(double) * (size_t)n);
     double *qs = (double *)malloc(sizeof(double) * (size_t)n);
     double *ps = (double *)calloc((size_t)n, sizeof(double));
-    if (!A || !B || !xs || !ys || !qs || !ps) {
-        free(A); free(B); free(xs); free(ys); free(qs); free(ps);
+    double *gxs = gx ? (double *)calloc((size_t)n, sizeof(double)) : NULL;
+    double *gys = gx ? (double *)calloc((size_t)n, sizeof(double)) : NULL;
+    if (!A || !B || !xs || !ys || !qs || !ps || (gx && (!gxs || !gys))) {
+        free(A); free(B); free(xs); free(ys); free(qs); free(ps); free(gxs); free(gys);
         return -2;
     }
     for (int64_t i = 0; i < n; ++i) { xs[i] = x[perm[i]]; ys[i] = y[perm[i]]; qs[i] = q[perm[i]]; }
@@ -467,20 +510,60 @@ int orc_fmm_eval(int64_t n, const double *x, const double *y, const double *q,
         int64_t a = leaf_start[b], e = leaf_start[b + 1];
         orc_l2p(B + stride * (off_L + b), g[0], g[1], box_scale(g), p, e - a,
                 xs + a, ys + a, ps + a);
+        if (gx)
+            orc_l2p_grad(B + stride * (off_L + b), g[0], g[1], box_scale(g), p, e - a,
+                         xs + a, ys + a, gxs + a, gys + a);
         for (int64_t i = a; i < e; ++i) {
-            double s = 0.0, c = 0.0;
+            double s = 0.0, c = 0.0, sx = 0.0, cx = 0.0, sy = 0.0, cy = 0.0;
             for (int64_t t = sptr_L[b]; t < sptr_L[b + 1]; ++t) {
                 int64_t cb = sidx_L[t];
                 for (int64_t j = leaf_start[cb]; j < leaf_start[cb + 1]; ++j) {
                     if (xs[j] == xs[i] && ys[j] == ys[i])
                         continue;
                     neumaier_add(&s, &c, qs[j] * log(hypot(xs[i] - xs[j], ys[i] - ys[j])));
+                    if (gx) {
+                        double dx = xs[i] - xs[j], dy = ys[i] - ys[j];
+                        double r2 = dx * dx + dy * dy;
+                        neumaier_add(&sx, &cx, qs[j] * dx / r2);
+                        neumaier_add(&sy, &cy, qs[j] * dy / r2);
+                    }
                 }
             }
             ps[i] += s + c;
+            if (gx) {
+                gxs[i] += sx + cx;
+                gys[i] += sy + cy;
+            }
         }
     }
     for (int64_t i = 0; i < n; ++i) phi[perm[i]] = ps[i];
-    free(A); free(B); free(xs); free(ys); free(qs); free(ps);
+    if (gx)
+        for (int64_t i = 0; i < n; ++i) { gx[perm[i]] = gxs[i]; gy[perm[i]] = gys[i]; }
+    free(A); free(B); free(xs); free(ys); free(qs); free(ps); free(gxs); free(gys);
     return 0;
+}
+
+int orc_fmm_eval(int64_t n, const double *x, const double *y, const double *q,
+                 int L, int p, const int64_t *perm, const int64_t *leaf_start,
+                 const double *geom, const int64_t *wptr, const int64_t *widx,
+                 const int64_t *wptr_off, const int64_t *widx_off,
+                 const int64_t *sptr_L, const int64_t *sidx_L, double *phi)
+{
+    return fmm_eval_impl(n, x, y, q, L, p, perm, leaf_start, geom, wptr, widx, wptr_off, widx_off,
+                         sptr_L, sidx_L, phi, NULL, NULL);
+}
+
+/* The FMM with the gradient of the potential as well (the field of
+ * Section 5's first experiment, here for the logarithmic kernel): at the
+ * leaves the derivative of the local expansion plus the direct sum of the
+ * gradient over the strong list.                                            */
+int orc_fmm_eval_field(int64_t n, const double *x, const double *y, const double *q,
+                       int L, int p, const int64_t *perm, const int64_t *leaf_start,
+                       const double *geom, const int64_t *wptr, const int64_t *widx,
+                       const int64_t *wptr_off, const int64_t *widx_off,
+                       const int64_t *sptr_L, const int64_t *sidx_L, double *phi,
+                       double *gx, double *gy)
+{
+    return fmm_eval_impl(n, x, y, q, L, p, perm, leaf_start, geom, wptr, widx, wptr_off, widx_off,
+                         sptr_L, sidx_L, phi, gx, gy);
 }
