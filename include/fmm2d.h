@@ -111,6 +111,17 @@ int fmm2d_connectivity(fmm2d_ctx *ctx, double theta);
  * Asynchronous on the stream. */
 int fmm2d_evaluate(fmm2d_ctx *ctx, const double *q, int p, int mode, double *phi);
 
+/* As fmm2d_evaluate, and the gradient of phi at every point: gx = d phi/dx,
+ * gy = d phi/dy, i.e. sum over j with z_j != z_i of q_j (z_i - z_j) /
+ * |z_i - z_j|^2 componentwise (the field of the logarithmic kernel; Section
+ * 5's first experiment measures the corresponding force kernel).  The far
+ * part is the derivative of each leaf's local expansion, the near part the
+ * direct sum over the finest strong list.  Binary64 only: mode must be
+ * FMM2D_MODE_FP64 (FMM2D_EINVAL otherwise).  q, phi, gx, gy: device binary64
+ * [n], input order; phi equals what fmm2d_evaluate writes.  Needs tree and
+ * lists.  Asynchronous on the stream. */
+int fmm2d_evaluate_field(fmm2d_ctx *ctx, const double *q, int p, int mode, double *phi, double *gx, double *gy);
+
 /* Direct binary64 sum (eq. (1.1)) at m target indices, with compensated
  * summation: the error judge.  x, y, q: device binary64 [n]; targets: device
  * int64 [m] with values in [0, n); phi_m: device binary64 [m].  Independent

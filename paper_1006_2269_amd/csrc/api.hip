@@ -107,7 +107,8 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->tree.near_lo.segoff.release();
         c->tree.near_lo.table.release();
         c->tree.lsum.release();
-        for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work, &e.src})
+        for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work,
+                          &e.src})
             b->release();
         Scratch &s = c->scr;
         for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
@@ -296,6 +297,22 @@ int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) 
     DeviceGuard g(c->device);
     hipError_t e = evaluate_device(c, q, p, mode, phi);
     if (e != hipSuccess) return hip_fail(c, e, "evaluate");
+    return FMM2D_OK;
+}
+
+int fmm2d_evaluate_field(fmm2d_ctx *c, const double *q, int p, int mode, double *phi, double *gx, double *gy) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!q || !phi || !gx || !gy) return fail(c, FMM2D_EINVAL, "evaluate_field: q, phi, gx and gy must be device pointers");
+    if (p < 1 || p > FMM2D_MAX_P) return fail(c, FMM2D_EINVAL, "evaluate_field: p = %d not in [1, 63]", p);
+    if (mode != FMM2D_MODE_FP64)
+        return fail(c, FMM2D_EINVAL, "evaluate_field: the gradient is computed in binary64 only (FMM2D_MODE_FP64)");
+    if (c->tree.L < 0 || !c->tree.has_lists)
+        return fail(c, FMM2D_ESTATE, "evaluate_field: needs a tree and its lists (build_tree, connectivity)");
+    DeviceGuard g(c->device);
+    hipError_t e = evaluate_device(c, q, p, mode, phi);
+    if (e == hipSuccess) e = gradient_device(c, p, gx, gy);
+    if (e != hipSuccess) return hip_fail(c, e, "evaluate_field");
     return FMM2D_OK;
 }
 

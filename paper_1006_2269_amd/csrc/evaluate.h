@@ -22,6 +22,9 @@ hipError_t m2l_all(fmm2d_ctx *c, int p, int mode);
 // near-field sums.  The far field runs in between.
 enum { NEAR_PREP = 0, NEAR_LAUNCH = 1, NEAR_FINISH = 2 };
 hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage);
+// the gradient of the potential at every point, input order, after a
+// binary64 evaluation with the same p (field.hip)
+hipError_t gradient_device(fmm2d_ctx *c, int p, double *gx, double *gy);
 // list segments for the M2L and near-field kernels (sched.hip)
 hipError_t build_schedules(fmm2d_ctx *c);
 hipError_t ensure_near_full_schedule(fmm2d_ctx *c);

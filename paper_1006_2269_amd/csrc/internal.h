@@ -116,6 +116,7 @@ struct EvalState {
     DevBuf src;             // float4 [n]: FP32 local offsets and charge
     DevBuf part;            // partial sums of the M2L's list segments
     DevBuf npart;           // near-field partial sums (written on the second stream while the far field runs)
+    DevBuf gpart;           // near-field gradient partial sums (fmm2d_evaluate_field)
 };
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream

@@ -91,6 +91,16 @@ class FMM2D:
         self._check(self._lib.fmm2d_evaluate(self._h, _ptr(q), int(p), _capi.MODES[mode], _ptr(out)))
         return out
 
+    def evaluate_field(self, q: torch.Tensor, p: int, mode: str = "fp64"):
+        """(phi, d phi/dx, d phi/dy) at every point, input order (binary64 only)."""
+        _require(q, torch.float64, self.device, "q")
+        if self.n is not None and q.numel() != self.n:
+            raise ValueError("q has %d entries, the tree %d" % (q.numel(), self.n))
+        phi, gx, gy = (torch.empty_like(q) for _ in range(3))
+        self._check(self._lib.fmm2d_evaluate_field(self._h, _ptr(q), int(p), _capi.MODES[mode], _ptr(phi), _ptr(gx),
+                                                   _ptr(gy)))
+        return phi, gx, gy
+
     def direct(self, x, y, q, targets: torch.Tensor, out: torch.Tensor | None = None):
         for t, nm in ((x, "x"), (y, "y"), (q, "q")):
             _require(t, torch.float64, self.device, nm)
