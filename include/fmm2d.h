@@ -125,9 +125,17 @@ int fmm2d_evaluate_field(fmm2d_ctx *ctx, const double *q, int p, int mode, doubl
 /* Direct binary64 sum (eq. (1.1)) at m target indices, with compensated
  * summation: the error judge.  x, y, q: device binary64 [n]; targets: device
  * int64 [m] with values in [0, n); phi_m: device binary64 [m].  Independent
- * of any tree.  Asynchronous on the stream. */
+ * of any tree.  Synchronises the stream once (the target check: FMM2D_EINVAL
+ * for an index outside [0, n)); the sum itself is queued. */
 int fmm2d_direct(fmm2d_ctx *ctx, const double *x, const double *y, const double *q,
                  int64_t n, const int64_t *targets, int64_t m, double *phi_m);
+
+/* The direct gradient of the same sum at m target indices, the judge of
+ * fmm2d_evaluate_field: gx_m, gy_m (device binary64 [m]) receive the sums over
+ * j with z_j != z_i of q_j (x_i - x_j) / |z_i - z_j|^2 and q_j (y_i - y_j) /
+ * |z_i - z_j|^2, compensated.  Arguments and errors as fmm2d_direct. */
+int fmm2d_direct_field(fmm2d_ctx *ctx, const double *x, const double *y, const double *q,
+                       int64_t n, const int64_t *targets, int64_t m, double *gx_m, double *gy_m);
 
 /* ---- parameter selection -------------------------------------------------- */
 

@@ -316,6 +316,22 @@ int fmm2d_evaluate_field(fmm2d_ctx *c, const double *q, int p, int mode, double 
     return FMM2D_OK;
 }
 
+// Checks (on the device, one host read) that every target index lies in
+// [0, n); FMM2D_OK or the error code with the message set.
+static int check_targets(fmm2d_ctx *c, const int64_t *targets, int64_t m, int64_t n, const char *who) {
+    hipError_t e;
+    if ((e = c->scr.aux.ensure(4096)) != hipSuccess) return hip_fail(c, e, who);
+    int *flags = reinterpret_cast<int *>(c->scr.aux.as<char>() + 2048);
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(1), 0, c->stream, flags);
+    hipLaunchKernelGGL(k_check_targets, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, targets, m, n, flags);
+    int hf[2] = {0, 0};
+    if ((e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return hip_fail(c, e, who);
+    if (hf[1]) return fail(c, FMM2D_EINVAL, "%s: a target index is outside [0, n)", who);
+    return FMM2D_OK;
+}
+
 int fmm2d_direct(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n, const int64_t *targets,
                  int64_t m, double *phi_m) {
     if (!c) return FMM2D_EINVAL;
@@ -325,20 +341,31 @@ int fmm2d_direct(fmm2d_ctx *c, const double *x, const double *y, const double *q
     if (m == 0) return FMM2D_OK;
     DeviceGuard g(c->device);
     hipError_t e;
-    if ((e = c->scr.aux.ensure(4096)) != hipSuccess) return hip_fail(c, e, "direct");
-    int *flags = reinterpret_cast<int *>(c->scr.aux.as<char>() + 2048);
-    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(1), 0, c->stream, flags);
-    hipLaunchKernelGGL(k_check_targets, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, targets, m, n, flags);
-    int hf[2] = {0, 0};
-    if ((e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
-        return hip_fail(c, e, "direct");
-    if (hf[1]) return fail(c, FMM2D_EINVAL, "direct: a target index is outside [0, n)");
+    if (int rc = check_targets(c, targets, m, n, "direct")) return rc;
     {
         PhaseScope ps(c, PH_JUDGE);
         e = direct_device(c, x, y, q, n, targets, m, phi_m);
     }
     if (e != hipSuccess) return hip_fail(c, e, "direct");
+    return FMM2D_OK;
+}
+
+int fmm2d_direct_field(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                       const int64_t *targets, int64_t m, double *gx_m, double *gy_m) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!x || !y || !q || (m > 0 && (!targets || !gx_m || !gy_m)))
+        return fail(c, FMM2D_EINVAL, "direct_field: NULL pointer");
+    if (n < 1 || m < 0) return fail(c, FMM2D_EINVAL, "direct_field: need n >= 1 and m >= 0");
+    if (m == 0) return FMM2D_OK;
+    DeviceGuard g(c->device);
+    if (int rc = check_targets(c, targets, m, n, "direct_field")) return rc;
+    hipError_t e;
+    {
+        PhaseScope ps(c, PH_JUDGE);
+        e = direct_grad_device(c, x, y, q, n, targets, m, gx_m, gy_m);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "direct_field");
     return FMM2D_OK;
 }
 

@@ -230,6 +230,8 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
 // judge.hip
 hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
                          const int64_t *targets, int64_t m, double *phi);
+hipError_t direct_grad_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                              const int64_t *targets, int64_t m, double *gx, double *gy);
 
 // Brackets the launches of one phase with two events when timing is on.
 struct PhaseScope {

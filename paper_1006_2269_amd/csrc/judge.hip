@@ -62,16 +62,88 @@ __global__ void k_direct_reduce(const double2 *__restrict__ part, int64_t m, int
     phi[t] = s + (c + corr);
 }
 
-}  // namespace
+// The gradient of the same sum, (d/dx, d/dy) of q_j log|z_i - z_j| =
+// q_j (z_i - z_j) / |z_i - z_j|^2 componentwise; the same blocking and
+// compensated sums, two components per target.
+__global__ void __launch_bounds__(JT) k_direct_grad_part(const double *__restrict__ x, const double *__restrict__ y,
+                                                         const double *__restrict__ q, int64_t n,
+                                                         const int64_t *__restrict__ targets, int64_t m, int64_t chunk,
+                                                         double4 *__restrict__ part) {
+    __shared__ double sx[JS], sy[JS], sq[JS];
+    const int64_t t = (int64_t)blockIdx.x * JT + threadIdx.x;
+    const bool ok = t < m;
+    const int64_t i = ok ? targets[t] : 0;
+    const double xi = x[i], yi = y[i];
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+    for (int64_t base = j0; base < j1; base += JS) {
+        const int64_t cnt = (j1 - base) < JS ? (j1 - base) : JS;
+        for (int k = threadIdx.x; k < cnt; k += JT) {
+            sx[k] = x[base + k];
+            sy[k] = y[base + k];
+            sq[k] = q[base + k];
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            const double dx = xi - sx[k], dy = yi - sy[k];
+            if (dx != 0.0 || dy != 0.0) {
+                const double r2 = dx * dx + dy * dy;
+                neumaier(s1, c1, sq[k] * dx / r2);
+                neumaier(s2, c2, sq[k] * dy / r2);
+            }
+        }
+        __syncthreads();
+    }
+    if (ok) part[(int64_t)blockIdx.y * m + t] = make_double4(s1, c1, s2, c2);
+}
 
-hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
-                         const int64_t *targets, int64_t m, double *phi) {
+__global__ void k_direct_grad_reduce(const double4 *__restrict__ part, int64_t m, int nchunk, double *__restrict__ gx,
+                                     double *__restrict__ gy) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    double s1 = 0.0, c1 = 0.0, k1 = 0.0, s2 = 0.0, c2 = 0.0, k2 = 0.0;
+    for (int k = 0; k < nchunk; ++k) {
+        const double4 v = part[(int64_t)k * m + t];
+        neumaier(s1, c1, v.x);
+        k1 += v.y;
+        neumaier(s2, c2, v.z);
+        k2 += v.w;
+    }
+    gx[t] = s1 + (c1 + k1);
+    gy[t] = s2 + (c2 + k2);
+}
+
+static int64_t judge_chunks(int64_t n, int64_t m) {
     const int64_t groups = (m + JT - 1) / JT;
     int64_t nchunk = (2048 + groups - 1) / groups;
     const int64_t maxchunk = (n + 1023) / 1024;
     if (nchunk > maxchunk) nchunk = maxchunk;
     if (nchunk < 1) nchunk = 1;
     if (nchunk > 65535) nchunk = 65535;
+    return nchunk;
+}
+
+}  // namespace
+
+hipError_t direct_grad_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                              const int64_t *targets, int64_t m, double *gx, double *gy) {
+    const int64_t groups = (m + JT - 1) / JT;
+    const int64_t nchunk = judge_chunks(n, m);
+    const int64_t chunk = (n + nchunk - 1) / nchunk;
+    FMM2D_TRY(c->scr.flag.ensure(sizeof(double4) * nchunk * m));
+    double4 *part = c->scr.flag.as<double4>();
+    hipLaunchKernelGGL(k_direct_grad_part, dim3((unsigned)groups, (unsigned)nchunk), dim3(JT), 0, c->stream, x, y, q,
+                       n, targets, m, chunk, part);
+    hipLaunchKernelGGL(k_direct_grad_reduce, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, part, m, (int)nchunk,
+                       gx, gy);
+    return hipGetLastError();
+}
+
+hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                         const int64_t *targets, int64_t m, double *phi) {
+    const int64_t groups = (m + JT - 1) / JT;
+    const int64_t nchunk = judge_chunks(n, m);
     const int64_t chunk = (n + nchunk - 1) / nchunk;
     FMM2D_TRY(c->scr.flag.ensure(sizeof(double2) * nchunk * m));
     double2 *part = c->scr.flag.as<double2>();

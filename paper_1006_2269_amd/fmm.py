@@ -111,6 +111,17 @@ class FMM2D:
                                            targets.numel(), _ptr(out)))
         return out
 
+    def direct_field(self, x, y, q, targets: torch.Tensor):
+        """(d phi/dx, d phi/dy) by the direct binary64 sum at the target indices."""
+        for t, nm in ((x, "x"), (y, "y"), (q, "q")):
+            _require(t, torch.float64, self.device, nm)
+        _require(targets, torch.int64, self.device, "targets")
+        gx = torch.empty(targets.numel(), dtype=torch.float64, device=self.device)
+        gy = torch.empty_like(gx)
+        self._check(self._lib.fmm2d_direct_field(self._h, _ptr(x), _ptr(y), _ptr(q), x.numel(), _ptr(targets),
+                                                 targets.numel(), _ptr(gx), _ptr(gy)))
+        return gx, gy
+
     # -- timing -------------------------------------------------------------
     def timing(self, enable: bool):
         self._check(self._lib.fmm2d_timing(self._h, 1 if enable else 0))

@@ -65,3 +65,17 @@ def test_field_needs_binary64(fmm):
     fmm.connectivity(0.5)
     with pytest.raises(FMM2DError):
         fmm.evaluate_field(_dev(ps.q), 12, "fp32")
+
+
+@pytest.mark.parametrize("case", ["uniform_10k_L5", "duplicates_4k_L4", "clustered_scaled_30k_L6"])
+def test_direct_field_matches_oracle(fmm, orc, case):
+    ps = TREE_CASES[case][0]()
+    rng = np.random.default_rng(17)
+    t = rng.choice(ps.n, min(ps.n, 700), replace=False).astype(np.int64)
+    _announce("direct_field", case, ps.n)
+    gx, gy = (a.cpu().numpy() for a in fmm.direct_field(_dev(ps.x), _dev(ps.y), _dev(ps.q), _dev(t)))
+    rx, ry = orc.direct_field(ps.x, ps.y, ps.q, t)
+    scale = max(np.abs(rx).max(), np.abs(ry).max())
+    # both compensated: they differ in the summation order only
+    assert np.abs(gx - rx).max() <= 1e-13 * scale
+    assert np.abs(gy - ry).max() <= 1e-13 * scale
