@@ -188,6 +188,33 @@ def unit_disc(n: int, seed: int, radial_inverse: bool = False) -> PointSet:
     return PointSet("disc_1r" if radial_inverse else "disc_uniform", x, y, np.full(n, 1.0 / n))
 
 
+def normal_corner(n: int, seed: int, sigma: float = 0.1) -> PointSet:
+    """The 'normal' layout of Section 5's second and third experiments:
+    N(0, sigma^2 I) forced into the unit square by rejection, so the points
+    cluster at the origin corner.  Charges U[-1,1]."""
+    g = rng(seed)
+    x, y = _gaussian_in_square(g, n, (0.0, 0.0), sigma)
+    return PointSet("normal", x, y, _charges_uniform(g, n))
+
+
+def layer(n: int, seed: int, sigma: float = 0.1) -> PointSet:
+    """The 'layer' layout of the same experiments: x uniform in [0,1] and y
+    from N(0, sigma^2) forced into [0,1] by rejection, so the points cluster
+    along the x-axis.  Charges U[-1,1]."""
+    g = rng(seed)
+    x = g.random(n)
+    y = np.empty(n)
+    filled = 0
+    while filled < n:
+        m = max(16, int(2.2 * (n - filled)) + 16)
+        py = g.normal(0.0, sigma, m)
+        py = py[(py >= 0.0) & (py <= 1.0)]
+        take = min(n - filled, py.shape[0])
+        y[filled:filled + take] = py[:take]
+        filled += take
+    return PointSet("layer", x, y, _charges_uniform(g, n))
+
+
 def grid(levels: int, per_axis_factor: int = 2, seed: int = 7) -> PointSet:
     """Cell centres ((i + 1/2) / m, (j + 1/2) / m) of an m x m grid with
     m = per_axis_factor * 2^levels, listed in a seeded random order, with
