@@ -107,7 +107,7 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->tree.near_lo.segoff.release();
         c->tree.near_lo.table.release();
         c->tree.lsum.release();
-        for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.phi_leaf, &e.work,
+        for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.work,
                           &e.src})
             b->release();
         Scratch &s = c->scr;

@@ -13,7 +13,7 @@ hipError_t ensure_mhat(fmm2d_ctx *c);
 // segment partial sums ev.part that the L2L pass adds into B (m2l.hip).
 hipError_t m2l_all(fmm2d_ctx *c, int p, int mode);
 // L2P plus the near field at the leaves in precision `mode`; writes the
-// leaf-ordered potentials to ev.phi_leaf (near.hip).
+// potentials to phi in input order (near.hip).
 // The leaf pass in three stages: NEAR_PREP packs the sources (and builds
 // the full near-field schedule where it is needed) on the context stream and
 // makes the context's second stream wait for that point; NEAR_LAUNCH queues
@@ -21,7 +21,7 @@ hipError_t m2l_all(fmm2d_ctx *c, int p, int mode);
 // NEAR_FINISH makes the context stream wait for them and adds L2P and the
 // near-field sums.  The far field runs in between.
 enum { NEAR_PREP = 0, NEAR_LAUNCH = 1, NEAR_FINISH = 2 };
-hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage);
+hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage, double *phi);
 // the gradient of the potential at every point, input order, after a
 // binary64 evaluation with the same p (field.hip)
 hipError_t gradient_device(fmm2d_ctx *c, int p, double *gx, double *gy);

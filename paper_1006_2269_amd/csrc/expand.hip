@@ -377,12 +377,6 @@ __global__ void k_gather_q(const double *__restrict__ q, const int32_t *__restri
     if (i < n) qs[i] = q[perm[i]];
 }
 
-__global__ void k_unpermute(const double *__restrict__ phi_leaf, const int32_t *__restrict__ perm, int64_t n,
-                            double *__restrict__ phi) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) phi[perm[i]] = phi_leaf[i];
-}
-
 __global__ void k_zero_cd(cd *p, int64_t m) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) p[i] = cd{0.0, 0.0};
@@ -537,7 +531,6 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
     FMM2D_TRY(e.A.ensure(sizeof(cd) * nbox * (p + 1)));
     FMM2D_TRY(e.B.ensure(sizeof(cd) * nbox * (p + 1)));
     FMM2D_TRY(e.qs.ensure(sizeof(double) * n));
-    FMM2D_TRY(e.phi_leaf.ensure(sizeof(double) * n));
     FMM2D_TRY(side_join(c));  // second-stream work of an earlier call still reading the charges or sources
     {
         PhaseScope ps(c, PH_OTHER);
@@ -551,8 +544,8 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
         // first, after the upward pass, measured no faster: the two share the
         // chip and the upward pass is then exposed)
         PhaseScope ps(c, PH_LEAF);
-        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_PREP));
-        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_LAUNCH));
+        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_PREP, phi));
+        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_LAUNCH, phi));
     }
     {
         PhaseScope ps(c, PH_UPWARD);
@@ -569,12 +562,7 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
     }
     {
         PhaseScope ps(c, PH_LEAF);
-        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_FINISH));
-    }
-    {
-        PhaseScope ps(c, PH_OTHER);
-        hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, e.phi_leaf.as<double>(),
-                           t.perm.as<int32_t>(), n, phi);
+        FMM2D_TRY(leaf_pass(c, p, mode, NEAR_FINISH, phi));
     }
     return hipGetLastError();
 }

@@ -111,7 +111,6 @@ struct EvalState {
     bool mhat_ready = false;
     DevBuf A, B;            // expansions, complex<double> [nbox][p+1]
     DevBuf qs;              // double [n] charges in leaf order
-    DevBuf phi_leaf;        // double [n]
     DevBuf work;            // mode-dependent scratch
     DevBuf src;             // float4 [n]: FP32 local offsets and charge
     DevBuf part;            // partial sums of the M2L's list segments

@@ -447,7 +447,8 @@ __global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale
                               const int32_t *__restrict__ stL, const int32_t *__restrict__ segoff,
                               const double *__restrict__ part, const double4 *__restrict__ geomL,
                               const double *__restrict__ px, const double *__restrict__ py,
-                              const cd *__restrict__ BL, double *__restrict__ phi_leaf) {
+                              const cd *__restrict__ BL, const int32_t *__restrict__ perm,
+                              double *__restrict__ phi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t b = leafid[i];
@@ -460,7 +461,7 @@ __global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale
     const cd *Bb = BL + (int64_t)b * (p + 1);
     cd v = Bb[p];
     for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
-    phi_leaf[i] = v.re + scale * near;
+    phi[perm[i]] = v.re + scale * near;  // input order
 }
 
 // Source-side sums of the entries of S_L(c) before c's own (written there by
@@ -494,7 +495,7 @@ __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, do
                                   const int32_t *__restrict__ losegoff, const double *__restrict__ lsum,
                                   const double4 *__restrict__ geomL, const double *__restrict__ px,
                                   const double *__restrict__ py, const cd *__restrict__ BL,
-                                  double *__restrict__ phi_leaf) {
+                                  const int32_t *__restrict__ perm, double *__restrict__ phi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t b = leafid[i];
@@ -508,7 +509,7 @@ __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, do
     const cd *Bb = BL + (int64_t)b * (p + 1);
     cd v = Bb[p];
     for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
-    phi_leaf[i] = v.re + scale * near;
+    phi[perm[i]] = v.re + scale * near;  // input order
 }
 
 // FP32 paths with leaves of at most 64 points: each leaf pair once.  Stage
@@ -516,7 +517,7 @@ __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, do
 // stream (after the transposed positions, queued there by the list build),
 // NEAR_FINISH the reduction with L2P on the context stream.
 template <int TM, int GL, int CH>
-hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage) {
+hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage, double *phi) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int L = t.L;
@@ -543,7 +544,7 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage) {
         hipLaunchKernelGGL(k_near_reduce_sym, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, CH, GL,
                            HALF_LN2_D, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part,
                            lo.segoff.as<int32_t>(), t.lsum.as<double>(), gL, t.px.as<double>(), t.py.as<double>(),
-                           BL, e.phi_leaf.as<double>());
+                           BL, t.perm.as<int32_t>(), phi);
         return hipGetLastError();
     }
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
@@ -572,7 +573,7 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage) {
 
 // Every ordered leaf pair (one-sided kernels); stages as in launch_near_sym.
 template <int TM, int GL>
-hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage) {
+hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage, double *phi) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int L = t.L;
@@ -599,7 +600,7 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage) {
         FMM2D_TRY(side_join(c));
         hipLaunchKernelGGL(k_near_reduce, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, chunks,
                            scale, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part, gL, t.px.as<double>(),
-                           t.py.as<double>(), BL, e.phi_leaf.as<double>());
+                           t.py.as<double>(), BL, t.perm.as<int32_t>(), phi);
         return hipGetLastError();
     }
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
@@ -631,8 +632,8 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage) {
 
 }  // namespace
 
-// L2P plus the near field for every point; writes ev.phi_leaf (leaf order).
-hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage) {
+// L2P plus the near field for every point; writes phi (input order).
+hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage, double *phi) {
     TreeState &t = c->tree;
     EvalState &e = c->ev;
     const int64_t n = t.n;
@@ -651,14 +652,14 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage) {
     if (mode != FMM2D_MODE_FP64 && pair_once_leaves(ml)) {
         // each leaf pair once, the four chunks of targets of a leaf in the
         // four wavefronts of a block
-        if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode, stage);
-        return launch_near_sym<16, 64, 4>(c, p, mode, stage);
+        if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode, stage, phi);
+        return launch_near_sym<16, 64, 4>(c, p, mode, stage, phi);
     }
     if (stage == NEAR_PREP) FMM2D_TRY(ensure_near_full_schedule(c));  // on the context stream, before the second stream waits
-    if (ml <= 8) return launch_near<8, 8>(c, p, mode, ml, stage);
-    if (ml <= 16) return launch_near<16, 16>(c, p, mode, ml, stage);
-    if (ml <= 32) return launch_near<16, 32>(c, p, mode, ml, stage);
-    return launch_near<16, 64>(c, p, mode, ml, stage);
+    if (ml <= 8) return launch_near<8, 8>(c, p, mode, ml, stage, phi);
+    if (ml <= 16) return launch_near<16, 16>(c, p, mode, ml, stage, phi);
+    if (ml <= 32) return launch_near<16, 32>(c, p, mode, ml, stage, phi);
+    return launch_near<16, 64>(c, p, mode, ml, stage, phi);
 }
 
 }  // namespace fmm2d
