@@ -66,6 +66,23 @@ __device__ inline bool theta_separated(double theta, double theta2, double4 gb, 
     return lhs <= rhs && rhs > 0.0;
 }
 
+// The FP32 near-field record of target leaf b and source leaf c: the centre
+// offset c_b - c_c rounded to FP32 and the squared distance below which a
+// pair counts as coincident.  In b's own leaf both sides of a pair subtract
+// the same rounded offsets, so duplicates give exactly r^2 = 0 and only r^2
+// below the smallest normal float is masked (the logarithm's argument stays
+// normal).  Across leaves a coincident pair shows a rounding distance: with
+// u = 2^-24, the offsets x - c_b and x - c_c, the FP32 c_b - c_c, the source
+// offset in b's frame and the difference are each rounded once, so
+// |dx| + |dy| <= u (2 sqrt2 R_b + sqrt2 R_c + |dxc| + |dyc|) <= 3 u mag;
+// the threshold 2^-21 mag = 8 u mag keeps a factor above 2 on that bound.
+__device__ inline float4 near_record(double4 gb, double4 gc, bool self) {
+    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
+    const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
+    const float thr = self ? 0x1p-126f : (mag * 0x1p-21f) * (mag * 0x1p-21f);
+    return make_float4(dxc, dyc, thr, 0.f);
+}
+
 // Level 0: S_0(root) = {root}, W_0(root) empty; for a one-level tree
 // (L = 0) also the near-field record of that single strong entry, written
 // as the finest fill pass writes the others.
@@ -82,11 +99,8 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool,
     if (L == 0) {
         owner0[0] = 0;
         selfpos[0] = 0;
-        const double4 g = geom0[0];
-        const float dxc = (float)(g.x - g.x), dyc = (float)(g.y - g.y);
-        const float mag = fabsf(dxc) + fabsf(dyc) + (float)g.z + (float)g.z;
         recj[0] = make_int2(stL[0], stL[1]);
-        recd[0] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+        recd[0] = near_record(geom0[0], geom0[0], true);
     }
 }
 
@@ -95,9 +109,8 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool,
 // (FILL = false): the theta test of every candidate and the two counts.  Fill
 // pass: the same tests, ballot compaction into the lists, the owner (row) of
 // every strong entry when the next level needs it, and on the finest level
-// the near-field record of each strong entry (source leaf's point range; FP32
-// centre offset c_b - c_c and the coincidence threshold (2^-20 of the
-// magnitudes)^2 for the FP32 path).
+// the near-field record of each strong entry (source leaf's point range and
+// near_record's offset and threshold for the FP32 path).
 template <bool FILL>
 __device__ inline void box_lists(int l, int L, double theta, const double4 *__restrict__ geomL, int64_t b,
                                  const int32_t *__restrict__ sptr_prev, const int32_t *__restrict__ sidx_prev,
@@ -135,10 +148,8 @@ __device__ inline void box_lists(int l, int L, double theta, const double4 *__re
                 if (self && cbox == b) self[b] = tS + pos;
                 if (records) {
                     const int32_t t = tS + pos;
-                    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
-                    const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
                     recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
-                    recd[t] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+                    recd[t] = near_record(gb, gc, cbox == b);
                 }
             }
         }
@@ -480,11 +491,8 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
                     if (owner_cur) owner_cur[posS] = fc.b[u];
                     if (records && fc.cbox[u] == fc.b[u]) selfpos[fc.b[u]] = posS;
                     if (records) {
-                        const double4 B = gb[u], C = gc[u];
-                        const float dxc = (float)(B.x - C.x), dyc = (float)(B.y - C.y);
-                        const float mag = fabsf(dxc) + fabsf(dyc) + (float)B.z + (float)C.z;
                         recj[posS] = rr[u];
-                        recd[posS] = make_float4(dxc, dyc, (mag * 0x1p-20f) * (mag * 0x1p-20f), 0.f);
+                        recd[posS] = near_record(gb[u], gc[u], fc.cbox[u] == fc.b[u]);
                     }
                 }
                 if (fc.first[u]) {

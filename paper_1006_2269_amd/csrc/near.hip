@@ -11,11 +11,11 @@
 //
 // FP32 path: targets and sources are offsets from their own leaf centres;
 // the centre difference c_b - c_c is formed in binary64 and rounded once per
-// (lane, source leaf).  A pair whose FP32 distance is below the rounding
-// error of that computation (2^-20 of the magnitudes involved) is treated as
-// coincident, which makes exactly coincident points in different leaves
-// contribute nothing, as in binary64.  L2P (binary64 Horner) runs on lane k
-// for target k.
+// (lane, source leaf).  Coincident pairs contribute nothing, as in binary64:
+// within a leaf they give exactly r^2 = 0, and across leaves a pair whose
+// FP32 distance is below the rounding error of its own computation (a
+// bound on it, carried in the record) counts as coincident.  L2P (binary64
+// Horner) runs on lane k for target k.
 #include "evaluate.h"
 #include "wavesum.h"
 

@@ -277,3 +277,42 @@ def test_call_orders_with_second_stream(fmm, orc):
     fmm.build_tree(_dev(pts[a].x), _dev(pts[a].y), TREE_CASES[a][1])
     fmm.connectivity(0.5)
     check(a, fmm.evaluate(_dev(pts[a].q), 12, "fp64").cpu().numpy())
+
+
+@pytest.mark.parametrize("mode,tol", [("fp32", 2e-5), ("fp32_acc64", 2e-5), ("bf16x3", 1e-3)])
+@pytest.mark.parametrize("per_leaf", [12, 24, 48, 100])
+def test_reduced_modes_close_pair_in_sparse_leaf(fmm, orc, mode, tol, per_leaf):
+    # Two distinct points 2^-19.5 R apart in one leaf of half diagonal R
+    # (leaf sizes 12, 24, 48, 100 take the one-sided, both pair-once and the
+    # large-leaf FP32 kernels).  Within a leaf only exact duplicates may be
+    # masked: the pair's log r is resolved to |dlog r| <= d / (r - d), with
+    # d = 2 sqrt2 2^-24 R the rounding of the two FP32 offsets; masking it
+    # would cost |log r| ~ 15 at both points.
+    L = 1
+    g = np.random.default_rng(4242 + per_leaf)
+    n = 4 * per_leaf
+    x, y = g.random(n), g.random(n)
+    q = g.uniform(-1.0, 1.0, n)
+    x[0], y[0] = 0.2, 0.3
+    q[0] = q[1] = 1.0
+    r_pair = 4e-7
+    x[1], y[1] = 0.2 + r_pair * math.cos(0.7), 0.3 + r_pair * math.sin(0.7)
+    r_pair = math.hypot(x[1] - x[0], y[1] - y[0])
+    t = orc.tree(x, y, L)
+    pos = np.empty(n, dtype=np.int64)
+    pos[np.asarray(t.perm)] = np.arange(n)
+    leaf = np.searchsorted(np.asarray(t.leaf_start), pos[:2], side="right") - 1
+    assert leaf[0] == leaf[1], "the pair must share a leaf"
+    R = float(np.asarray(t.geom)[orc.level_offset(L) + leaf[0], 2])
+    assert 2.0 ** -21 * R < r_pair < 2.0 ** -19 * R  # resolvable in FP32, below the old self threshold
+    _announce("close_pair", per_leaf, mode)
+    fmm.build_tree(_dev(x), _dev(y), L)
+    fmm.connectivity(0.5)
+    phi = fmm.evaluate(_dev(q), 20, mode).cpu().numpy()
+    ex = orc.direct(x, y, q)
+    scale = np.abs(ex).max()
+    d = 2.0 * math.sqrt(2.0) * 2.0 ** -24 * R
+    bound = abs(q[1]) * d / (r_pair - d) + tol * scale
+    err = np.abs(phi - ex)
+    assert err[0] <= bound and err[1] <= bound, (err[:2], bound)
+    assert err[2:].max() <= tol * scale
