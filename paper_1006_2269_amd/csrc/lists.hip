@@ -76,19 +76,27 @@ __device__ inline bool theta_separated(double theta, double theta2, double4 gb, 
 // offset in b's frame and the difference are each rounded once, so
 // |dx| + |dy| <= u (2 sqrt2 R_b + sqrt2 R_c + |dxc| + |dyc|) <= 3 u mag;
 // the threshold 2^-21 mag = 8 u mag keeps a factor above 2 on that bound.
-__device__ inline float4 near_record(double4 gb, double4 gc, bool self) {
+// The fourth component flags a separated pair of leaves: when the gap
+// between the two rectangles (rb, rc: xlo, xhi, ylo, yhi) along x or y
+// exceeds 2^-20 mag = 16 u mag, every pair is at least that far apart, its
+// FP32 offsets are off by at most u (2 R_b + 4 R_c + 2 |dxc| + 2 |dyc|)
+// <= 4 u mag, so its FP32 r^2 exceeds (12 u mag)^2 > threshold and the near
+// kernels may skip the coincidence test for the record.
+__device__ inline float4 near_record(double4 gb, double4 gc, double4 rb, double4 rc, bool self) {
     const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
     const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
     const float thr = self ? 0x1p-126f : (mag * 0x1p-21f) * (mag * 0x1p-21f);
-    return make_float4(dxc, dyc, thr, 0.f);
+    const double gap = fmax(fmax(rb.x - rc.y, rc.x - rb.y), fmax(rb.z - rc.w, rc.z - rb.w));
+    const bool sep = !self && gap > 0x1p-20 * (double)mag;
+    return make_float4(dxc, dyc, thr, sep ? 1.f : 0.f);
 }
 
 // Level 0: S_0(root) = {root}, W_0(root) empty; for a one-level tree
 // (L = 0) also the near-field record of that single strong entry, written
 // as the finest fill pass writes the others.
 __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool, int64_t *pool_state, int L,
-                             const int32_t *stL, const double4 *geom0, int2 *recj, float4 *recd, int32_t *owner0,
-                             int32_t *selfpos) {
+                             const int32_t *stL, const double4 *geom0, const double4 *rect0, int2 *recj, float4 *recd,
+                             int32_t *owner0, int32_t *selfpos) {
     sptr0[0] = 0;
     sptr0[1] = 1;
     wptr0[0] = 0;
@@ -100,7 +108,7 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *sidx_pool,
         owner0[0] = 0;
         selfpos[0] = 0;
         recj[0] = make_int2(stL[0], stL[1]);
-        recd[0] = near_record(geom0[0], geom0[0], true);
+        recd[0] = near_record(geom0[0], geom0[0], rect0[0], rect0[0], true);
     }
 }
 
@@ -117,7 +125,8 @@ __device__ inline void box_lists(int l, int L, double theta, const double4 *__re
                                  int32_t &cs, int32_t &cw, int32_t tS, int32_t *__restrict__ so,
                                  int32_t *__restrict__ wo, int32_t *__restrict__ own,
                                  int32_t *__restrict__ self, const int32_t *__restrict__ stL,
-                                 int2 *__restrict__ recj, float4 *__restrict__ recd) {
+                                 const double4 *__restrict__ rectL, int2 *__restrict__ recj,
+                                 float4 *__restrict__ recd) {
     const uint32_t lane = lane_id();
     const int64_t P = b >> 2;
     const int32_t s0 = sptr_prev[P], s1 = sptr_prev[P + 1];
@@ -149,7 +158,7 @@ __device__ inline void box_lists(int l, int L, double theta, const double4 *__re
                 if (records) {
                     const int32_t t = tS + pos;
                     recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
-                    recd[t] = near_record(gb, gc, cbox == b);
+                    recd[t] = near_record(gb, gc, rectL[b], rectL[cbox], cbox == b);
                 }
             }
         }
@@ -202,8 +211,10 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
                                                               int32_t *__restrict__ widx_pool,
                                                               int64_t *__restrict__ pool_state, int64_t cap_s,
                                                               int64_t cap_w, int64_t limit,
-                                                              const int32_t *__restrict__ stL, int2 *__restrict__ recj,
-                                                              float4 *__restrict__ recd, int32_t *__restrict__ owner,
+                                                              const int32_t *__restrict__ stL,
+                                                              const double4 *__restrict__ rectL,
+                                                              int2 *__restrict__ recj, float4 *__restrict__ recd,
+                                                              int32_t *__restrict__ owner,
                                                               int32_t *__restrict__ selfpos) {
     __shared__ int32_t ns[SMALL_BOXES], nw[SMALL_BOXES];
     __shared__ int32_t tmp[SMALL_THREADS / 64];
@@ -224,7 +235,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
         for (int64_t b = wv; b < nb; b += NWV) {
             int32_t cs, cw;
             box_lists<false>(l, L, theta, gL, b, sp_prev, sidx_prev, cs, cw, 0, nullptr, nullptr, nullptr, nullptr,
-                             stL, nullptr, nullptr);
+                             stL, nullptr, nullptr, nullptr);
             if (lane_id() == 0) {
                 ns[b] = cs;
                 nw[b] = cw;
@@ -257,7 +268,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists_small(int K, int L, dou
             int32_t cs, cw;
             box_lists<true>(l, L, theta, gL, b, sp_prev, sidx_prev, cs, cw, sp_cur[b], sidx_pool + so0 + sp_cur[b],
                             widx_pool + wo0 + wp_cur[b], l == K ? owner : nullptr, l == L ? selfpos : nullptr, stL,
-                            recj, recd);
+                            rectL, recj, recd);
         }
         __syncthreads();
     }
@@ -442,7 +453,8 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
                                                    const uint64_t *__restrict__ bits,
                                                    const int32_t *__restrict__ pre_s, const int32_t *__restrict__ pre_w,
                                                    int32_t *__restrict__ sptr_cur, int32_t *__restrict__ wptr_cur,
-                                                   const int32_t *__restrict__ stL, int2 *__restrict__ recj,
+                                                   const int32_t *__restrict__ stL,
+                                                   const double4 *__restrict__ rectL, int2 *__restrict__ recj,
                                                    float4 *__restrict__ recd, int32_t *__restrict__ selfpos) {
     if (pool_state[2 * L + 4]) return;  // uniform
     const int64_t NC = level_candidates(sptr_prev, nb_prev);
@@ -466,7 +478,7 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
             ps[u] = wk ? pre_s[w0 + u] : 0;
             pw[u] = wk ? pre_w[w0 + u] : 0;
         }
-        double4 gb[FB], gc[FB];
+        double4 gb[FB], gc[FB], rb[FB], rc[FB];
         int2 rr[FB];
         if (records) {
 #pragma unroll
@@ -474,6 +486,8 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
                 const bool strong = fc.ok[u] && !((mw[u] >> lane) & 1);
                 gb[u] = strong ? geomL[fc.b[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
                 gc[u] = strong ? geomL[fc.cbox[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+                rb[u] = strong ? rectL[fc.b[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+                rc[u] = strong ? rectL[fc.cbox[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
                 rr[u] = strong ? make_int2(stL[fc.cbox[u]], stL[fc.cbox[u] + 1]) : make_int2(0, 0);
             }
         }
@@ -492,7 +506,7 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
                     if (records && fc.cbox[u] == fc.b[u]) selfpos[fc.b[u]] = posS;
                     if (records) {
                         recj[posS] = rr[u];
-                        recd[posS] = near_record(gb[u], gc[u], fc.cbox[u] == fc.b[u]);
+                        recd[posS] = near_record(gb[u], gc[u], rb[u], rc[u], fc.cbox[u] == fc.b[u]);
                     }
                 }
                 if (fc.first[u]) {
@@ -539,14 +553,15 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
     FMM2D_TRY(t.selfpos.ensure(sizeof(int32_t) * (size_t)(int64_t(1) << (2 * L))));
     int32_t *owner[2] = {t.owner0.as<int32_t>(), t.owner1.as<int32_t>()};
     int32_t *selfpos = t.selfpos.as<int32_t>();
+    const double4 *rectL = t.rects.as<double4>() + level_offset(L);  // (xlo, xhi, ylo, yhi) per leaf
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, t.sidx.as<int32_t>(), ps, L, stL,
-                       geom, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[0], selfpos);
+                       geom, rectL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[0], selfpos);
     // levels of at most 64 boxes: one workgroup, one launch
     int K = 0;
     while (K < L && (int64_t(1) << (2 * (K + 1))) <= SMALL_BOXES) ++K;
     if (K >= 1)
         hipLaunchKernelGGL(k_lists_small, dim3(1), dim3(SMALL_THREADS), 0, c->stream, K, L, theta, geom, sptr, wptr,
-                           t.sidx.as<int32_t>(), t.widx.as<int32_t>(), ps, cap_s, cap_w, limit, stL,
+                           t.sidx.as<int32_t>(), t.widx.as<int32_t>(), ps, cap_s, cap_w, limit, stL, rectL,
                            t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[K & 1], selfpos);
     FMM2D_TRY(hipGetLastError());
     if (K < L) {
@@ -579,7 +594,7 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t
                                cap_w, limit);
             hipLaunchKernelGGL(k_flat_fill, dim3(fgrid), dim3(256), 0, c->stream, l, L, gL, sp_prev, nb_prev,
                                t.sidx.as<int32_t>(), t.widx.as<int32_t>(), own_prev, own_cur, ps, bits, cs, cw,
-                               sp_cur, wp_cur, stL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), selfpos);
+                               sp_cur, wp_cur, stL, rectL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), selfpos);
             FMM2D_TRY(hipGetLastError());
         }
     }

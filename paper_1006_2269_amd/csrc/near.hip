@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
         const int2 rj = s_rj[wv][st * LPI + grp];
         const bool ok = jj < rj.y - rj.x;
         float4 v = src[ok ? rj.x + jj : 0];
+        v.x = ok ? v.x : 0x1p60f;  // far from every target: finite log on the unmasked path
         v.z = ok ? v.z : 0.f;
         return v;
     };
@@ -243,14 +244,25 @@ __global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int3
         const int r = st * LPI + grp;
         const float4 rd = s_rd[wv][r];
         const float sx = sv.x - rd.x, sy = sv.y - rd.y, q = sv.z, thr = rd.z;
-        float sacc = 0.f;
+        float sacc = 0.f, lg[TM];
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
             const float dx = tx[k] - sx, dy = ty[k] - sy;
-            const float r2 = dx * dx + dy * dy;
-            const float lg = (r2 > thr) ? __log2f(r2) : 0.f;  // coincident: log is masked, never multiplied
-            acc[k] = fmaf(q, lg, acc[k]);
-            sacc = fmaf(tq[k], lg, sacc);
+            lg[k] = __log2f(dx * dx + dy * dy);
+        }
+        // separated leaves only (every r^2 exceeds its threshold): the
+        // coincidence mask would change nothing and is skipped
+        if (!__all(rd.w != 0.f)) {
+#pragma unroll
+            for (int k = 0; k < TM; ++k) {
+                const float dx = tx[k] - sx, dy = ty[k] - sy;
+                lg[k] = (dx * dx + dy * dy > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TM; ++k) {
+            acc[k] = fmaf(q, lg[k], acc[k]);
+            sacc = fmaf(tq[k], lg[k], sacc);
         }
         s_ring[(st / RING) & 1][st & (RING - 1)][wv][lane] = sacc;
         if ((st & (RING - 1)) == RING - 1 || st == nsteps - 1) exchange(st);  // uniform per block
