@@ -78,25 +78,36 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
     const int grp = lane / GL, jj = lane % GL;
     const int nsteps = (t1 - t0 + LPI - 1) / LPI;
     // source point of lane jj in the record of step st; a lane past the end
-    // of its source leaf loads a point of the array and carries no charge, so
-    // the load needs no branch and its pairs add exactly zero
+    // of its source leaf loads a point of the array, moved far from every
+    // target, and carries no charge, so the load needs no branch and its
+    // pairs add exactly zero
     auto load_src = [&](int st) {
         const int2 rj = s_rj[wv][st * LPI + grp];
         const bool ok = jj < rj.y - rj.x;
         float4 v = src[ok ? rj.x + jj : 0];
+        v.x = ok ? v.x : 0x1p60f;
         v.z = ok ? v.z : 0.f;
         return v;
     };
     auto eval = [&](float4 sv, int st) {
         const float4 rd = s_rd[wv][st * LPI + grp];
         const float sx = sv.x - rd.x, sy = sv.y - rd.y, q = sv.z, thr = rd.z;
+        float lg[TM];
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
             const float dx = tx[k] - sx, dy = ty[k] - sy;
-            const float r2 = dx * dx + dy * dy;
-            const float lg = __log2f(r2);
-            acc[k] = fmaf(q, (r2 > thr) ? lg : 0.f, acc[k]);  // coincident: log is masked, never multiplied
+            lg[k] = __log2f(dx * dx + dy * dy);
         }
+        // every record of the step separated: the mask would change nothing
+        if (!__all(rd.w != 0.f)) {
+#pragma unroll
+            for (int k = 0; k < TM; ++k) {
+                const float dx = tx[k] - sx, dy = ty[k] - sy;
+                lg[k] = (dx * dx + dy * dy > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TM; ++k) acc[k] = fmaf(q, lg[k], acc[k]);
     };
     float4 svA = load_src(0), svB;
     for (int st = 0; st < nsteps; st += 2) {
