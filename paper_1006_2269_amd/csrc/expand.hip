@@ -539,17 +539,17 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
         hipLaunchKernelGGL(k_zero_cd, dim3(1), dim3(64), 0, c->stream, e.B.as<cd>(), (int64_t)(p + 1));
     }
     {
+        PhaseScope ps(c, PH_UPWARD);
+        FMM2D_TRY(upward_pass(c, p));
+    }
+    {
         // the near field needs no expansion: it runs on the second stream
-        // while the upward pass, M2L and L2L run here (queueing the M2L
-        // first, after the upward pass, measured no faster: the two share the
-        // chip and the upward pass is then exposed)
+        // while M2L and L2L run here.  It is released after the upward pass,
+        // whose short per-level launches would otherwise wait for compute
+        // units behind the near kernel's blocks.
         PhaseScope ps(c, PH_LEAF);
         FMM2D_TRY(leaf_pass(c, p, mode, NEAR_PREP, phi));
         FMM2D_TRY(leaf_pass(c, p, mode, NEAR_LAUNCH, phi));
-    }
-    {
-        PhaseScope ps(c, PH_UPWARD);
-        FMM2D_TRY(upward_pass(c, p));
     }
     {
         PhaseScope ps(c, PH_M2L);

@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
 // loaded while the current step is evaluated (two steps per loop iteration,
 // so the pipeline registers alternate instead of being copied).
 template <int TM, int GL, int CH, bool ACC64>
-__global__ void __launch_bounds__(64 * NWB) k_near32s(int64_t nitems, const int32_t *__restrict__ stL,
+__global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(4))) k_near32s(int64_t nitems, const int32_t *__restrict__ stL,
                                                       const float4 *__restrict__ src, const int32_t *__restrict__ sptr,
                                                       const int32_t *__restrict__ selfpos,
                                                       const int32_t *__restrict__ transU,
