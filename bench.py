@@ -81,7 +81,139 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU baseline until this much time has passed")
     ap.add_argument("--fp64", type=int, default=1, help="also time the plain FP64 form")
+    ap.add_argument("--sweep", choices=["field", "robustness"],
+                    help="run a measurement sweep instead of the benchmark (JSON table to --out)")
+    ap.add_argument("--out", help="output file of a sweep")
+    ap.add_argument("--sizes", help="robustness sweep: comma-separated N")
+    ap.add_argument("--sweep-n", type=int, default=0, help="field sweep: points (default 10^6)")
+    ap.add_argument("--sweep-levels", type=int, default=8, help="field sweep: levels")
     return ap.parse_args()
+
+
+def sweep_field(args):
+    """Relative error of the FMM field (the gradient of the potential) against
+    the direct field versus the expansion order, for theta in {0.25, 0.5,
+    sqrt(1/2)}: the shape of Section 5's first experiment, for the gradient
+    q_j (z_i - z_j)/|z_i - z_j|^2 of the logarithmic kernel (the complex
+    conjugate of that experiment's force kernel q_j/(z_i - z_j)).  10^6 points
+    of total mass 1 in the unit disc, uniform and 1/r radial density, 8 levels,
+    error at 1000 sampled targets against fmm2d_direct_field; the time of one
+    fmm2d_evaluate_field by HIP events on the library stream."""
+    args.n = args.sweep_n or 1_000_000
+    args.pmax = 30
+    THETAS = (0.25, 0.5, math.sqrt(0.5))
+    import numpy as np
+    import torch
+
+    from paper_1006_2269_amd import workloads as W
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    f = FMM2D(0)
+    dev = f.device
+    rows = []
+    for radial in (False, True):
+        ps = W.unit_disc(args.n, 501 + int(radial), radial_inverse=radial)
+        x, y, q = (torch.from_numpy(a).to(dev) for a in (ps.x, ps.y, ps.q))
+        tg = torch.from_numpy(W.sample_targets(ps.n, args.samples, seed=4242)).to(dev)
+        ex, ey = (a.cpu().numpy() for a in f.direct_field(x, y, q, tg))
+        emag = np.hypot(ex, ey).max()
+        f.build_tree(x, y, args.sweep_levels)
+        for th in THETAS:
+            f.connectivity(th)
+            for p in range(2, args.pmax + 1, 2):
+                f.evaluate_field(q, p)  # warm (allocations)
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(f.stream)
+                phi, gx, gy = f.evaluate_field(q, p)
+                b.record(f.stream)
+                b.synchronize()
+                ms = a.elapsed_time(b)
+                gxs, gys = gx[tg].cpu().numpy(), gy[tg].cpu().numpy()
+                err = float(np.hypot(gxs - ex, gys - ey).max() / emag)
+                rows.append({"layout": ps.name, "theta": th, "p": p, "e_inf": err, "ms": ms})
+                print("[field] %s theta=%.3f p=%2d  e_inf=%.3e  %.2f ms" % (ps.name, th, p, err, ms), flush=True)
+    with open(args.out, "w") as fh:
+        json.dump({"n": args.n, "levels": args.sweep_levels, "samples": args.samples, "rows": rows}, fh, indent=1)
+    f.close()
+    return 0
+
+
+def sweep_robustness(args):
+    """Time of the whole path versus N on three layouts at TOL = 1e-6: the shape
+    of Section 5's third experiment (uniform in the unit square, and the
+    'normal' and 'layer' layouts of the second, sigma = 0.1).  Per layout and
+    N: the reduced form (fmm2d_select_build_tree, connectivity, evaluate in
+    FP32_ACC64) and plain binary64 at the a-priori rule's parameters; time =
+    median of 3 after a warm-up (HIP events on the library stream), e_inf
+    against the binary64 direct sum at 1000 sampled targets."""
+    SIZES = (10_000, 30_000, 100_000, 300_000, 1_000_000, 2_000_000, 5_000_000)
+    TOL = 1e-6
+    sizes = args.sizes or ",".join(str(s) for s in SIZES)
+    import numpy as np
+    import torch
+
+    from paper_1006_2269_amd import selector
+    from paper_1006_2269_amd import workloads as W
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    f = FMM2D(0)
+    dev = f.device
+    wts = selector.weights_tensor(dev)
+    makers = {"uniform": lambda n, s: W.uniform(n, s), "normal": W.normal_corner, "layer": W.layer}
+    rows = []
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(f.stream)
+            r = fn()
+            b.record(f.stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return r, float(np.median(ts))
+
+    for name, mk in makers.items():
+        for n in (int(s) for s in sizes.split(",")):
+            ps = mk(n, 7000 + n % 997)
+            x, y, q = (torch.from_numpy(a).to(dev) for a in (ps.x, ps.y, ps.q))
+            tg = torch.from_numpy(W.sample_targets(ps.n, 1000, seed=4242)).to(dev)
+            exact = f.direct(x, y, q, tg)
+            scale = float(exact.abs().max())
+            out = torch.empty_like(q)
+
+            def reduced():
+                L, p, th, net = f.select_build_tree(x, y, TOL, wts)
+                f.connectivity(th)
+                f.evaluate(q, p, "fp32_acc64", out=out)
+                return L, p, th, net
+
+            (L, p, th, net), ms = timed(reduced)
+            e = float((out[tg] - exact).abs().max()) / scale
+            rec = {"layout": name, "n": n, "reduced": {"levels": L, "p": p, "theta": th, "network": net, "ms": ms,
+                                                       "e_inf": e}}
+            Lr, pr, thr, _ = f.select(x, y, TOL)  # the rule (no weights)
+
+            def plain():
+                f.build_tree(x, y, Lr)
+                f.connectivity(thr)
+                f.evaluate(q, pr, "fp64", out=out)
+
+            _, ms64 = timed(plain)
+            e64 = float((out[tg] - exact).abs().max()) / scale
+            rec["fp64_rule"] = {"levels": Lr, "p": pr, "theta": thr, "ms": ms64, "e_inf": e64}
+            rows.append(rec)
+            print("[robust] %-7s n=%8d  reduced (L=%d p=%d th=%.2f net=%d) %.2f ms e=%.1e | fp64 rule (L=%d p=%d) "
+                  "%.2f ms e=%.1e" % (name, n, L, p, th, net, ms, e, Lr, pr, ms64, e64), flush=True)
+    with open(args.out, "w") as fh:
+        json.dump({"tol": TOL, "rows": rows}, fh, indent=1)
+    f.close()
+    return 0
+
 
 
 def main():
@@ -90,6 +222,11 @@ def main():
         print("bench.py measures one GPU: this library has no multi-GPU path (the design notes describe how the "
               "tree would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        if not args.out:
+            print("--sweep needs --out", file=sys.stderr)
+            sys.exit(2)
+        sys.exit({"field": sweep_field, "robustness": sweep_robustness}[args.sweep](args))
     import numpy as np
     import torch
 

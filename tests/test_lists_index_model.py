@@ -1,0 +1,209 @@
+"""A CPU replay of the index arithmetic of the GPU list build, checked for
+bounds on every parity input.
+
+The GPU builds the interaction lists (Section 4's connectivity rule under
+Criterion 2.1) in flat passes over each level's candidate space, with pool
+sizes chosen on the host and grown on retry.  This module re-derives, in
+NumPy, every index those kernels form -- the decoding of a candidate number
+into (box, candidate box) through the owner table, the row pointers and
+source-list reads, the word counts and tile sums of the scan, the pool
+positions, owners, near-field records and self positions that the fill pass
+writes -- for the list sizes the oracle's lists give, including the host's
+retry loop and the device-side guards (pool space, entry limit).  Every index
+is checked against the size of the buffer it addresses, and the lists the
+replay assembles must equal the oracle's.  The decisions themselves are taken
+from the oracle's lists; what is modelled is where each decision goes.
+
+This is test infrastructure: it models the kernels' indexing only and holds
+none of the method's arithmetic.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_cases import TREE_CASES
+
+WS_TILE = 256 * 16        # words per scan tile
+SMALL_BOXES = 64          # levels of at most this many boxes run in one workgroup
+SMALL_GEOM = 85           # geometry of levels 0..3 staged in LDS
+POOL_MAX = 1 << 34
+INT32_MAX = (1 << 31) - 1
+
+
+def level_offset(l):
+    return (4 ** l - 1) // 3
+
+
+class Bounds:
+    """Largest index used per buffer, against its size."""
+
+    def __init__(self):
+        self.used = {}
+
+    def touch(self, name, idx, size):
+        idx = np.asarray(idx)
+        if idx.size == 0:
+            return
+        lo, hi = int(idx.min()), int(idx.max())
+        assert lo >= 0, "%s: index %d < 0" % (name, lo)
+        assert hi < size, "%s: index %d >= size %d" % (name, hi, size)
+        prev = self.used.get(name, (-1, size))
+        self.used[name] = (max(prev[0], hi), size)
+
+
+def _attempt(ls, L, cap_s, cap_w, limit, bd):
+    """One build_lists_device call; returns (overflow flag, pool offsets,
+    replayed S and W lists per level)."""
+    nS = [int(ls.sptr[l][-1]) for l in range(L + 1)]
+    nW = [int(ls.wptr[l][-1]) for l in range(L + 1)]
+    s_off = [0] * (L + 2)
+    w_off = [0] * (L + 2)
+    s_off[1] = 1
+    flag = 0
+    got_s, got_w = {0: np.array([0])}, {0: np.zeros(0, np.int64)}
+    n_leaf = 4 ** L
+    leaf_rows = n_leaf + 1
+    # buffers as sized by the host
+    if L >= 1 and 16 > limit:
+        return 2, s_off, got_s, got_w
+    words_cap = (cap_s + cap_w + 63) // 64 + 1
+    ntile = (words_cap + WS_TILE - 1) // WS_TILE
+    K = 0
+    while K < L and 4 ** (K + 1) <= SMALL_BOXES:
+        K += 1
+
+    def advance(l):
+        nonlocal flag
+        if flag:
+            return
+        so = s_off[l] + nS[l]
+        wo = w_off[l] + nW[l]
+        s_off[l + 1] = so
+        w_off[l + 1] = wo
+        if so > cap_s or wo > cap_w:
+            flag = 1
+            return
+        if l < L:
+            cand = 16 * nS[l]
+            if cand > limit:
+                flag = 2
+            elif cand > (cap_s - so) + (cap_w - wo):
+                flag = 1
+
+    for l in range(1, L + 1):
+        if flag:
+            break
+        nb, nb_prev = 4 ** l, 4 ** (l - 1)
+        sp_prev = np.asarray(ls.sptr[l - 1], np.int64)
+        si_prev = np.asarray(ls.sidx[l - 1], np.int64)
+        # candidates of level l in the order both passes number them
+        P_of_entry = np.repeat(np.arange(nb_prev), np.diff(sp_prev))   # owner table of S_{l-1}
+        NC = 16 * nS[l - 1]
+        q = np.arange(NC, dtype=np.int64)
+        if l > K:
+            nwords = (NC + 63) // 64
+            bd.touch("bits/cnt (words)", np.arange(nwords), words_cap)
+            bd.touch("scan tiles", np.arange((nwords + WS_TILE - 1) // WS_TILE), ntile)
+            bd.touch("owner_prev", q >> 4, cap_s)
+            bd.touch("owner_prev written", q >> 4, nS[l - 1])
+        P = P_of_entry[q >> 4]
+        bd.touch("sptr_prev", P + 1, nb_prev + 1)
+        s0, s1 = sp_prev[P], sp_prev[P + 1]
+        r = q - 16 * s0
+        m4 = 4 * (s1 - s0)
+        c = (r >= m4).astype(np.int64) + (r >= 2 * m4) + (r >= 3 * m4)
+        j = r - c * m4
+        assert np.all((j >= 0) & (j < m4)), "candidate decodes outside its box"
+        b = 4 * P + c
+        ent_pos = s0 + (j >> 2)
+        assert np.all(ent_pos < s1)
+        bd.touch("sidx (previous level)", s_off[l - 1] + ent_pos, cap_s)
+        cbox = 4 * si_prev[ent_pos] + (j & 3)
+        bd.touch("geom b", b, nb)
+        bd.touch("geom cbox", cbox, nb)
+        if l <= K:
+            bd.touch("geometry in LDS", level_offset(l) + np.concatenate([b, cbox]), SMALL_GEOM)
+        # decisions from the oracle's lists: candidate weak iff in W_l(b)
+        wp, wi = np.asarray(ls.wptr[l], np.int64), np.asarray(ls.widx[l], np.int64)
+        wkeys = np.repeat(np.arange(nb, dtype=np.int64), np.diff(wp)) * nb + wi
+        weak = np.isin(b * nb + cbox, wkeys)
+        strong = ~weak
+        # scans: pool positions and row pointers
+        posS = np.cumsum(strong) - strong
+        posW = np.cumsum(weak) - weak
+        advance(l)
+        if flag:
+            break
+        bd.touch("sidx pool (level %d)" % l, s_off[l] + posS[strong], cap_s)
+        bd.touch("widx pool (level %d)" % l, w_off[l] + posW[weak], cap_w)
+        bd.touch("owner_cur", posS[strong], cap_s)
+        first = np.zeros(NC, bool)
+        first[np.flatnonzero(j == 0)] = True
+        bd.touch("sptr_cur", b[first], nb + 1)
+        if l == L:
+            bd.touch("near records", posS[strong], cap_s)
+            bd.touch("leaf starts", cbox[strong] + 1, leaf_rows)
+            selfb = b[strong & (cbox == b)]
+            bd.touch("selfpos", selfb, n_leaf)
+            assert np.array_equal(np.sort(selfb), np.arange(nb)), "a leaf without its own entry"
+        # the lists the fill pass writes
+        S = np.empty(nS[l], np.int64)
+        S[posS[strong]] = cbox[strong]
+        W = np.empty(nW[l], np.int64)
+        W[posW[weak]] = cbox[weak]
+        got_s[l], got_w[l] = S, W
+    return flag, s_off, got_s, got_w
+
+
+def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX):
+    """fmm2d_connectivity's retry loop around the replayed build.  Returns
+    (status, attempts, bounds, caps)."""
+    nbox = level_offset(L + 1)
+    cap_s = max(32 * nbox + 64, hint_s)
+    cap_w = max(96 * nbox + 64, hint_w)
+    bd = Bounds()
+    for attempt in range(16):
+        flag, s_off, got_s, got_w = _attempt(ls, L, cap_s, cap_w, limit, bd)
+        if flag == 0:
+            for l in range(L + 1):
+                assert np.array_equal(got_s[l], ls.sidx[l]), "replayed S list of level %d differs" % l
+                assert np.array_equal(got_w[l], ls.widx[l]), "replayed W list of level %d differs" % l
+            return "ok", attempt + 1, bd, (cap_s, cap_w)
+        if flag == 2:
+            return "capacity", attempt + 1, bd, (cap_s, cap_w)
+        if cap_s >= POOL_MAX and cap_w >= POOL_MAX:
+            break
+        cap_s = min(cap_s * 4, POOL_MAX)
+        cap_w = min(cap_w * 4, POOL_MAX)
+    return "nomem", 16, bd, (cap_s, cap_w)
+
+
+@pytest.mark.parametrize("case", sorted(TREE_CASES))
+@pytest.mark.parametrize("theta", [0.5, 0.3, 0.75])
+def test_list_indices_in_bounds(orc, case, theta):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    ls = orc.lists(orc.tree(ps.x, ps.y, L), theta)
+    # a fresh context, and one whose pools were left large by earlier inputs
+    for hint in (0, 1 << 22):
+        status, attempts, bd, caps = replay_connectivity(ls, L, hint, 3 * hint)
+        assert status == "ok"
+
+
+def test_clustered_case_grows_pools_in_bounds(orc):
+    """The clustered 20k-point input at theta = 1/2 needs larger pools than
+    the first attempt's: the replay takes the retry and stays in bounds."""
+    maker, L = TREE_CASES["clustered_scaled_20k_L6"]
+    ps = maker()
+    ls = orc.lists(orc.tree(ps.x, ps.y, L), 0.5)
+    status, attempts, bd, caps = replay_connectivity(ls, L)
+    assert status == "ok" and attempts >= 2
+    for name, (hi, size) in sorted(bd.used.items()):
+        assert hi < size
+
+
+def test_entry_limit_reported_before_any_level_overflows(orc):
+    maker, L = TREE_CASES["clustered_scaled_20k_L6"]
+    ps = maker()
+    ls = orc.lists(orc.tree(ps.x, ps.y, L), 0.5)
+    status, _, _, _ = replay_connectivity(ls, L, limit=50000)
+    assert status == "capacity"
