@@ -25,8 +25,16 @@
  *    before reading them on the host).  Pointers documented as "host" are
  *    ordinary host memory, read or written before the call returns.
  *  - A context is not thread-safe; use one context per host thread.
- *  - The context owns its scratch memory (hipMalloc, kept and reused across
- *    calls, freed by fmm2d_destroy).
+ *  - Device memory.  Every device byte the context uses (its tree, lists,
+ *    expansions and scratch, kept and reused across calls) comes from the
+ *    allocator given to fmm2d_create (e.g. a framework's caching allocator),
+ *    or from hipMalloc when none is given; it is returned by fmm2d_destroy
+ *    or when a buffer has to grow.  The only other memory is 128 bytes of
+ *    pinned host memory (fmm2d_select_build_tree).
+ *  - FMM2D_ENOMEM (an allocation failed) discards the results of the failing
+ *    call's stage (a failing build_tree discards the tree, a failing
+ *    connectivity the lists); earlier stages stay valid and the context
+ *    stays usable.
  */
 #ifndef FMM2D_H
 #define FMM2D_H
@@ -44,6 +52,9 @@ extern "C" {
 #define FMM2D_ENOMEM     -2  /* a device allocation failed                    */
 #define FMM2D_EDEVICE    -3  /* a HIP runtime error; see fmm2d_last_error()   */
 #define FMM2D_ESTATE     -4  /* wrong call order (e.g. evaluate before lists) */
+#define FMM2D_ECAPACITY  -5  /* a level's list exceeds what int32 list       */
+                             /* offsets can address (fewer levels, or another */
+                             /* theta, for this point set)                    */
 
 /* Precision modes of fmm2d_evaluate.  In every mode the tree, the lists,
  * P2M, M2M, L2L and L2P run in binary64; the modes differ in the two hot
@@ -69,12 +80,29 @@ typedef struct fmm2d_ctx fmm2d_ctx;
 /* Library version (major*10000 + minor*100 + patch). */
 int fmm2d_version(void);
 
-/* Creates a context on HIP device `device` that enqueues all work on
- * `stream` (a hipStream_t; NULL means the device's null stream).  *out
- * receives the context. */
-int fmm2d_create(fmm2d_ctx **out, int device, void *stream);
+/* Device memory callbacks.  alloc returns `bytes` of device memory on the
+ * context's device, aligned to at least 256 bytes, or NULL when it cannot
+ * (the call then fails with FMM2D_ENOMEM).  free returns a block alloc gave
+ * (with the same size) in stream order: work the context queued on its
+ * stream before the call may still be using it, so the block may be handed
+ * out again only for work ordered after that point of the context stream
+ * (the rule of a stream-ordered caching allocator that allocates on that
+ * stream).  Work of the context's internal second stream is always ordered
+ * before the context stream when free is called.  user is passed through. */
+typedef void *(*fmm2d_alloc_fn)(size_t bytes, void *user);
+typedef void (*fmm2d_free_fn)(void *ptr, size_t bytes, void *user);
 
-/* Frees the context and all its device memory.  Synchronises its stream. */
+/* Creates a context on HIP device `device` that enqueues all work on
+ * `stream` (a hipStream_t; NULL means the device's null stream).  alloc and
+ * free: both NULL (hipMalloc and hipFree, the host waiting for the
+ * context's streams before a block is freed) or both set (see
+ * fmm2d_alloc_fn).  *out receives the context.  FMM2D_EINVAL for a NULL
+ * out, one callback without the other, or a device that does not exist. */
+int fmm2d_create(fmm2d_ctx **out, int device, void *stream, fmm2d_alloc_fn alloc, fmm2d_free_fn free,
+                 void *user);
+
+/* Frees the context and returns all its device memory.  Synchronises its
+ * streams first. */
 int fmm2d_destroy(fmm2d_ctx *ctx);
 
 /* Message of the last failing call on ctx (owned by ctx, valid until the
@@ -82,7 +110,8 @@ int fmm2d_destroy(fmm2d_ctx *ctx);
  * ctx is NULL. */
 const char *fmm2d_last_error(const fmm2d_ctx *ctx);
 
-/* Replaces the stream used by later calls. */
+/* Replaces the stream used by later calls; the new stream is made to wait
+ * for the work queued so far on the old one. */
 int fmm2d_set_stream(fmm2d_ctx *ctx, void *stream);
 
 /* Builds the balanced pyramid (Section 4 and Fig. 1.1).  x, y: device,
@@ -101,7 +130,10 @@ int fmm2d_build_tree(fmm2d_ctx *ctx, const double *x, const double *y,
 /* Builds the strong and weak interaction lists of every level (Section 4)
  * with the theta-criterion R + theta r <= theta d on the boxes' enclosing
  * balls (centre of the rectangle, half its diagonal).  0 < theta < 1.
- * Needs a tree.  Synchronises the stream once (to size the lists). */
+ * Needs a tree.  Synchronises the stream once (to size the lists), more
+ * often when the lists outgrow the pools of earlier calls.
+ * FMM2D_ECAPACITY when a level's candidates (16 times the previous level's
+ * strong entries) exceed 2^31 - 1, or all lists together 2^34 entries. */
 int fmm2d_connectivity(fmm2d_ctx *ctx, double theta);
 
 /* Evaluates phi (eq. (1.1)) with expansion order p (degrees 0..p, so p + 1

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmm2d.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECAPACITY = 0, -1, -2, -3, -4, -5
 MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32_acc64": 3}
 
 _lib = None
@@ -29,7 +29,7 @@ PD = ctypes.POINTER(ctypes.c_double)
 
 SIGNATURES = [
     ("fmm2d_version", I32, []),
-    ("fmm2d_create", I32, [PP, I32, P]),
+    ("fmm2d_create", I32, [PP, I32, P, P, P, P]),
     ("fmm2d_destroy", I32, [P]),
     ("fmm2d_last_error", ctypes.c_char_p, [P]),
     ("fmm2d_set_stream", I32, [P, P]),
@@ -55,6 +55,10 @@ SIGNATURES = [
     ("fmm2d_timing", I32, [P, I32]),
     ("fmm2d_get_timings", I32, [P, P, P]),
 ]
+
+# fmm2d_alloc_fn / fmm2d_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 
 NFEAT = 92
 SELECT_HEADER = 194

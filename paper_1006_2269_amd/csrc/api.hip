@@ -14,13 +14,20 @@ using namespace fmm2d;
 
 namespace {
 
-struct DeviceGuard {
+// Makes ctx's device current and ctx the owner of the device buffers that
+// grow during the call (DevBuf::ensure); both are restored on exit.
+thread_local fmm2d_ctx *tl_ctx = nullptr;
+
+struct CtxScope {
     int prev = -1;
-    explicit DeviceGuard(int d) {
+    fmm2d_ctx *prev_ctx;
+    explicit CtxScope(fmm2d_ctx *c) : prev_ctx(tl_ctx) {
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != d) (void)hipSetDevice(d);
+        if (prev != c->device) (void)hipSetDevice(c->device);
+        tl_ctx = c;
     }
-    ~DeviceGuard() {
+    ~CtxScope() {
+        tl_ctx = prev_ctx;
         if (prev >= 0) (void)hipSetDevice(prev);
     }
 };
@@ -54,19 +61,76 @@ __global__ void k_zero_flags(int *flags) {
 
 }  // namespace
 
+namespace fmm2d {
+
+static hipError_t dev_alloc(fmm2d_ctx *c, void **p, size_t bytes) {
+    if (c->alloc) {
+        *p = c->alloc(bytes, c->user);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+static hipError_t dev_free(fmm2d_ctx *c, void *p, size_t bytes) {
+    if (c->free) {
+        // stream order: the context stream waits for the second stream's
+        // last batch, and the callback returns the memory at that point
+        const hipError_t e = side_join(c);
+        c->free(p, bytes, c->user);
+        return e;
+    }
+    hipError_t e = c->side ? hipStreamSynchronize(c->side) : hipSuccess;
+    const hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = e2;
+    const hipError_t e3 = hipFree(p);
+    return e != hipSuccess ? e : e3;
+}
+
+hipError_t DevBuf::ensure(size_t bytes) {
+    if (bytes <= cap && ptr) return hipSuccess;
+    fmm2d_ctx *c = tl_ctx;
+    if (!c) return hipErrorInvalidContext;
+    if (ptr) {
+        const hipError_t e = dev_free(c, ptr, cap);
+        ptr = nullptr;
+        cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    const size_t b = bytes < 256 ? 256 : bytes;
+    void *q = nullptr;
+    const hipError_t e = dev_alloc(c, &q, b);
+    if (e != hipSuccess) return e;
+    ptr = q;
+    cap = b;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (ptr && tl_ctx) (void)dev_free(tl_ctx, ptr, cap);
+    ptr = nullptr;
+    cap = 0;
+}
+
+}  // namespace fmm2d
+
 extern "C" {
 
 int fmm2d_version(void) { return 100; }
 
-int fmm2d_create(fmm2d_ctx **out, int device, void *stream) {
+int fmm2d_create(fmm2d_ctx **out, int device, void *stream, fmm2d_alloc_fn alloc, fmm2d_free_fn free_fn,
+                 void *user) {
     if (!out) return FMM2D_EINVAL;
     *out = nullptr;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return FMM2D_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FMM2D_EINVAL;
     fmm2d_ctx *c = new (std::nothrow) fmm2d_ctx;
     if (!c) return FMM2D_ENOMEM;
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
+    c->alloc = alloc;
+    c->free = free_fn;
+    c->user = user;
     if (const char *lim = getenv("FMM2D_LIST_LIMIT")) {
         const long long v = atoll(lim);
         if (v > 0 && v < c->list_limit) c->list_limit = v;
@@ -78,13 +142,15 @@ int fmm2d_create(fmm2d_ctx **out, int device, void *stream) {
 int fmm2d_destroy(fmm2d_ctx *c) {
     if (!c) return FMM2D_EINVAL;
     {
-        DeviceGuard g(c->device);
+        CtxScope g(c);
         (void)hipStreamSynchronize(c->stream);
         if (c->side) {
             (void)hipStreamSynchronize(c->side);
             (void)hipStreamDestroy(c->side);
             (void)hipEventDestroy(c->ev_side_in);
             (void)hipEventDestroy(c->ev_side_out);
+            c->side = nullptr;
+            c->side_pending = false;
         }
         if (c->hpin) {
             (void)hipEventDestroy(c->ev_keys);
@@ -128,7 +194,19 @@ const char *fmm2d_last_error(const fmm2d_ctx *c) {
 int fmm2d_set_stream(fmm2d_ctx *c, void *stream) {
     if (!c) return FMM2D_EINVAL;
     c->err.clear();
-    c->stream = static_cast<hipStream_t>(stream);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (s == c->stream) return FMM2D_OK;
+    // the new stream starts after everything queued on the old one (and on
+    // the second stream), so buffers handed back in stream order stay safe
+    CtxScope g(c);
+    hipEvent_t ev = nullptr;
+    hipError_t e = side_join(c);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+    if (ev) (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(c, e, "set_stream");
+    c->stream = s;
     return FMM2D_OK;
 }
 
@@ -141,7 +219,7 @@ int fmm2d_build_tree(fmm2d_ctx *c, const double *x, const double *y, int64_t n, 
     if (n < (int64_t(1) << (2 * levels)))
         return fail(c, FMM2D_EINVAL, "build_tree: n = %lld < 4^levels = %lld", (long long)n,
                     (long long)(int64_t(1) << (2 * levels)));
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e;
     // validate the coordinates (and make the sort keys) before touching the
     // current tree
@@ -177,7 +255,7 @@ int fmm2d_select_build_tree(fmm2d_ctx *c, const double *x, const double *y, int6
     if (n < 4 || n > 2147483647LL)
         return fail(c, FMM2D_EINVAL, "select_build_tree: n = %lld not in [4, 2^31-1]", (long long)n);
     if (!(tol > 0.0 && tol < 1.0)) return fail(c, FMM2D_EINVAL, "select_build_tree: tol must lie in (0, 1)");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     TreeState &t = c->tree;
     hipError_t e = hipSuccess;
     if (!c->hpin) {
@@ -239,7 +317,7 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
     if (!(theta > 0.0 && theta < 1.0)) return fail(c, FMM2D_EINVAL, "connectivity: theta must lie in (0, 1)");
     TreeState &t = c->tree;
     if (t.L < 0) return fail(c, FMM2D_ESTATE, "connectivity: no tree (call fmm2d_build_tree first)");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     const int64_t nbox = level_offset(t.L + 1);
     // start from the pool sizes that sufficed for the previous call (repeated
     // calls on similar point sets then build the lists in one pass)
@@ -273,7 +351,7 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
         }
         if (overflow == 2) {
             t.has_lists = false;
-            return fail(c, FMM2D_ENOMEM,
+            return fail(c, FMM2D_ECAPACITY,
                         "connectivity: a level's strong or weak list exceeds %lld entries (choose fewer levels or "
                         "another theta for this point set)",
                         (long long)c->list_limit);
@@ -283,7 +361,7 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
         cap_w = cap_w * 4 < pool_max ? cap_w * 4 : pool_max;
     }
     t.has_lists = false;
-    return fail(c, FMM2D_ENOMEM, "connectivity: interaction lists exceed 2^34 entries");
+    return fail(c, FMM2D_ECAPACITY, "connectivity: interaction lists exceed 2^34 entries");
 }
 
 int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) {
@@ -294,7 +372,7 @@ int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) 
     if (mode < FMM2D_MODE_FP64 || mode > FMM2D_MODE_FP32_ACC64) return fail(c, FMM2D_EINVAL, "evaluate: unknown mode %d", mode);
     if (c->tree.L < 0 || !c->tree.has_lists)
         return fail(c, FMM2D_ESTATE, "evaluate: needs a tree and its lists (build_tree, connectivity)");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = evaluate_device(c, q, p, mode, phi);
     if (e != hipSuccess) return hip_fail(c, e, "evaluate");
     return FMM2D_OK;
@@ -309,7 +387,7 @@ int fmm2d_evaluate_field(fmm2d_ctx *c, const double *q, int p, int mode, double 
         return fail(c, FMM2D_EINVAL, "evaluate_field: the gradient is computed in binary64 only (FMM2D_MODE_FP64)");
     if (c->tree.L < 0 || !c->tree.has_lists)
         return fail(c, FMM2D_ESTATE, "evaluate_field: needs a tree and its lists (build_tree, connectivity)");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = evaluate_device(c, q, p, mode, phi);
     if (e == hipSuccess) e = gradient_device(c, p, gx, gy);
     if (e != hipSuccess) return hip_fail(c, e, "evaluate_field");
@@ -339,7 +417,7 @@ int fmm2d_direct(fmm2d_ctx *c, const double *x, const double *y, const double *q
     if (!x || !y || !q || (m > 0 && (!targets || !phi_m))) return fail(c, FMM2D_EINVAL, "direct: NULL pointer");
     if (n < 1 || m < 0) return fail(c, FMM2D_EINVAL, "direct: need n >= 1 and m >= 0");
     if (m == 0) return FMM2D_OK;
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e;
     if (int rc = check_targets(c, targets, m, n, "direct")) return rc;
     {
@@ -358,7 +436,7 @@ int fmm2d_direct_field(fmm2d_ctx *c, const double *x, const double *y, const dou
         return fail(c, FMM2D_EINVAL, "direct_field: NULL pointer");
     if (n < 1 || m < 0) return fail(c, FMM2D_EINVAL, "direct_field: need n >= 1 and m >= 0");
     if (m == 0) return FMM2D_OK;
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     if (int rc = check_targets(c, targets, m, n, "direct_field")) return rc;
     hipError_t e;
     {
@@ -375,7 +453,7 @@ int fmm2d_features(fmm2d_ctx *c, const double *x, const double *y, int64_t n, do
     if (!x || !y || !feat) return fail(c, FMM2D_EINVAL, "features: NULL pointer");
     if (n < 1 || n > 2147483647LL) return fail(c, FMM2D_EINVAL, "features: n = %lld not in [1, 2^31-1]", (long long)n);
     if (!(tol > 0.0 && tol < 1.0)) return fail(c, FMM2D_EINVAL, "features: tol must lie in (0, 1)");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = features_device(c, x, y, n, tol, feat, nullptr, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "features");
     return FMM2D_OK;
@@ -388,7 +466,7 @@ int fmm2d_select(fmm2d_ctx *c, const double *x, const double *y, int64_t n, doub
     if (!x || !y || !levels || !p || !theta) return fail(c, FMM2D_EINVAL, "select: NULL pointer");
     if (n < 4 || n > 2147483647LL) return fail(c, FMM2D_EINVAL, "select: n = %lld not in [4, 2^31-1]", (long long)n);
     if (!(tol > 0.0 && tol < 1.0)) return fail(c, FMM2D_EINVAL, "select: tol must lie in (0, 1)");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     int out[4] = {0, 0, 0, 0};
     double th = 0.0;
     hipError_t e;
@@ -416,7 +494,7 @@ int fmm2d_mlp_forward(fmm2d_ctx *c, const float *params, const float *X, int64_t
     if (!params || !X || !Y) return fail(c, FMM2D_EINVAL, "mlp_forward: NULL pointer");
     if (d_in < 1 || d_in > FMM2D_MLP_MAX_IN || batch < 1 || batch > (int64_t(1) << 30))
         return fail(c, FMM2D_EINVAL, "mlp_forward: need 1 <= d_in <= %d and 1 <= batch <= 2^30", FMM2D_MLP_MAX_IN);
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = mlp_forward(c, params, X, batch, d_in, Y);
     if (e != hipSuccess) return hip_fail(c, e, "mlp_forward");
     return FMM2D_OK;
@@ -429,7 +507,7 @@ int fmm2d_mlp_grad(fmm2d_ctx *c, const float *params, const float *X, const floa
     if (!params || !X || !Y || !grad || !loss) return fail(c, FMM2D_EINVAL, "mlp_grad: NULL pointer");
     if (d_in < 1 || d_in > FMM2D_MLP_MAX_IN || batch < 1 || batch > (int64_t(1) << 24))
         return fail(c, FMM2D_EINVAL, "mlp_grad: need 1 <= d_in <= %d and 1 <= batch <= 2^24", FMM2D_MLP_MAX_IN);
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = mlp_grad(c, params, X, Y, batch, d_in, grad, loss);
     if (e != hipSuccess) return hip_fail(c, e, "mlp_grad");
     return FMM2D_OK;
@@ -442,7 +520,7 @@ int fmm2d_mlp_adam(fmm2d_ctx *c, float *params, float *m, float *v, const float 
     if (!params || !m || !v || !grad) return fail(c, FMM2D_EINVAL, "mlp_adam: NULL pointer");
     if (nparams < 1 || step < 1 || !(lr > 0.0f) || !(weight_decay >= 0.0f))
         return fail(c, FMM2D_EINVAL, "mlp_adam: need nparams >= 1, step >= 1, lr > 0, weight_decay >= 0");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = mlp_adam(c, params, m, v, grad, nparams, step, lr, weight_decay);
     if (e != hipSuccess) return hip_fail(c, e, "mlp_adam");
     return FMM2D_OK;
@@ -462,7 +540,7 @@ int fmm2d_get_perm(fmm2d_ctx *c, int32_t *perm) {
     c->err.clear();
     if (!perm) return fail(c, FMM2D_EINVAL, "get_perm: NULL pointer");
     if (c->tree.L < 0) return fail(c, FMM2D_ESTATE, "get_perm: no tree");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = hipMemcpyAsync(perm, c->tree.perm.ptr, sizeof(int32_t) * c->tree.n, hipMemcpyDeviceToDevice, c->stream);
     return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_perm");
 }
@@ -472,7 +550,7 @@ int fmm2d_get_leaf_start(fmm2d_ctx *c, int32_t *start) {
     c->err.clear();
     if (!start) return fail(c, FMM2D_EINVAL, "get_leaf_start: NULL pointer");
     if (c->tree.L < 0) return fail(c, FMM2D_ESTATE, "get_leaf_start: no tree");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     const int L = c->tree.L;
     hipError_t e = hipMemcpyAsync(start, c->tree.starts.as<int32_t>() + depth_offset(2 * L),
                                   sizeof(int32_t) * ((int64_t(1) << (2 * L)) + 1), hipMemcpyDeviceToDevice, c->stream);
@@ -484,7 +562,7 @@ int fmm2d_get_rects(fmm2d_ctx *c, double *rects) {
     c->err.clear();
     if (!rects) return fail(c, FMM2D_EINVAL, "get_rects: NULL pointer");
     if (c->tree.L < 0) return fail(c, FMM2D_ESTATE, "get_rects: no tree");
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = hipMemcpyAsync(rects, c->tree.rects.ptr, sizeof(double) * 4 * level_offset(c->tree.L + 1),
                                   hipMemcpyDeviceToDevice, c->stream);
     return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_rects");
@@ -506,7 +584,7 @@ int fmm2d_get_lists(fmm2d_ctx *c, int level, int32_t *sptr, int32_t *sidx, int32
     TreeState &t = c->tree;
     if (t.L < 0 || !t.has_lists) return fail(c, FMM2D_ESTATE, "get_lists: no lists");
     if (level < 0 || level > t.L) return fail(c, FMM2D_EINVAL, "get_lists: level %d not in [0, %d]", level, t.L);
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     const int64_t nb = int64_t(1) << (2 * level);
     const int64_t ns = t.s_off[level + 1] - t.s_off[level], nw = t.w_off[level + 1] - t.w_off[level];
     hipError_t e = hipSuccess;
@@ -528,7 +606,7 @@ int fmm2d_get_lists(fmm2d_ctx *c, int level, int32_t *sptr, int32_t *sidx, int32
 int fmm2d_timing(fmm2d_ctx *c, int enable) {
     if (!c) return FMM2D_EINVAL;
     c->err.clear();
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     if (enable) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "timing");
@@ -542,7 +620,7 @@ int fmm2d_timing(fmm2d_ctx *c, int enable) {
 int fmm2d_get_timings(fmm2d_ctx *c, double *ms, int64_t *count) {
     if (!c) return FMM2D_EINVAL;
     c->err.clear();
-    DeviceGuard g(c->device);
+    CtxScope g(c);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess && c->side) e = hipStreamSynchronize(c->side);  // marks recorded on the second stream
     if (e != hipSuccess) return hip_fail(c, e, "get_timings");

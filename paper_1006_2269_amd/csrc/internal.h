@@ -27,34 +27,18 @@ __host__ __device__ inline int level_of(int64_t g) {
 // Offset of depth d in an array holding (2^e + 1) entries per depth e.
 __host__ __device__ inline int64_t depth_offset(int d) { return ((int64_t(1) << d) - 1) + d; }
 
-// Growable device buffer owned by the context.
+// Growable device buffer owned by the context.  Its memory comes from the
+// allocator of the context whose API call is running on this thread (the
+// callbacks given to fmm2d_create, else hipMalloc); see CtxScope in api.hip.
+// A regrown buffer's old memory is returned only after all work queued on
+// either stream that may still use it: with callbacks, the context stream
+// first waits for the second stream and the memory is handed back in stream
+// order; with hipMalloc, the host waits for both streams before hipFree.
 struct DevBuf {
     void *ptr = nullptr;
     size_t cap = 0;
-    // Growing frees the old allocation only after the device is idle, so a
-    // kernel still queued on any stream can never touch freed memory.
-    hipError_t ensure(size_t bytes) {
-        if (bytes <= cap && ptr) return hipSuccess;
-        if (ptr) {
-            hipError_t e = hipDeviceSynchronize();
-            if (e == hipSuccess) e = hipFree(ptr);
-            ptr = nullptr;
-            cap = 0;
-            if (e != hipSuccess) return e;
-        }
-        size_t b = bytes < 256 ? 256 : bytes;
-        hipError_t e = hipMalloc(&ptr, b);
-        if (e == hipSuccess) cap = b;
-        return e;
-    }
-    void release() {
-        if (ptr) {
-            (void)hipDeviceSynchronize();
-            (void)hipFree(ptr);
-        }
-        ptr = nullptr;
-        cap = 0;
-    }
+    hipError_t ensure(size_t bytes);  // at least `bytes`; old contents are not kept
+    void release();
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
@@ -156,6 +140,10 @@ struct Scratch {
 
 struct fmm2d_ctx {
     int device = 0;
+    // device memory: the caller's callbacks, or hipMalloc / hipFree when NULL
+    fmm2d_alloc_fn alloc = nullptr;
+    fmm2d_free_fn free = nullptr;
+    void *user = nullptr;
     int64_t list_limit = 2147483647LL;  // entries per level and list (FMM2D_LIST_LIMIT lowers it)
     int64_t cap_hint_s = 0, cap_hint_w = 0;  // list pool sizes that sufficed last time
     hipStream_t stream = nullptr;

@@ -140,17 +140,25 @@ hipError_t direct_grad_device(fmm2d_ctx *c, const double *x, const double *y, co
     return hipGetLastError();
 }
 
-hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
-                         const int64_t *targets, int64_t m, double *phi) {
+// The two judge launches with the chunk partials in `part` (double2
+// [direct_part_count(n, m)]).
+static hipError_t direct_launch(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                                const int64_t *targets, int64_t m, double *phi, double2 *part) {
     const int64_t groups = (m + JT - 1) / JT;
     const int64_t nchunk = judge_chunks(n, m);
     const int64_t chunk = (n + nchunk - 1) / nchunk;
-    FMM2D_TRY(c->scr.flag.ensure(sizeof(double2) * nchunk * m));
-    double2 *part = c->scr.flag.as<double2>();
     hipLaunchKernelGGL(k_direct_part, dim3((unsigned)groups, (unsigned)nchunk), dim3(JT), 0, c->stream, x, y, q, n,
                        targets, m, chunk, part);
     hipLaunchKernelGGL(k_direct_reduce, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, part, m, (int)nchunk, phi);
     return hipGetLastError();
+}
+
+int64_t direct_part_count(int64_t n, int64_t m) { return judge_chunks(n, m) * m; }
+
+hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                         const int64_t *targets, int64_t m, double *phi) {
+    FMM2D_TRY(c->scr.flag.ensure(sizeof(double2) * direct_part_count(n, m)));
+    return direct_launch(c, x, y, q, n, targets, m, phi, c->scr.flag.as<double2>());
 }
 
 }  // namespace fmm2d

@@ -27,15 +27,63 @@ def _require(t, dtype, device, name):
         raise TypeError("%s must be a contiguous %s tensor on %s" % (name, dtype, device))
 
 
-class FMM2D:
-    """A context: one device, one stream, one tree and its lists."""
+class TorchAllocator:
+    """Device memory of a context from PyTorch's caching allocator: each block
+    is a uint8 tensor allocated on the context's stream and kept alive until
+    the library hands it back (stream-ordered, as the allocator expects).
+    ``refuse_after`` (tests) makes every allocation after that many more fail."""
 
-    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+    def __init__(self, device: torch.device, stream: torch.cuda.Stream):
+        self.device = device
+        self.stream = stream
+        self.blocks = {}
+        self.refuse_after = None
+        self.c_alloc = _capi.ALLOC_FN(self._alloc)
+        self.c_free = _capi.FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            if self.refuse_after is not None:
+                if self.refuse_after <= 0:
+                    return None
+                self.refuse_after -= 1
+            with torch.cuda.stream(self.stream):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            self.blocks[t.data_ptr()] = t
+            return t.data_ptr()
+        except Exception:  # out of memory: the library reports FMM2D_ENOMEM
+            return None
+
+    def _free(self, ptr, nbytes, user):
+        self.blocks.pop(ptr, None)
+
+    def bytes_held(self) -> int:
+        return sum(t.numel() for t in self.blocks.values())
+
+
+class FMM2D:
+    """A context: one device, one stream, one tree and its lists.
+
+    allocator="torch" (default): every device byte the library uses comes
+    from PyTorch's caching allocator (``TorchAllocator``); "hip": the library
+    calls hipMalloc itself."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None, allocator: str = "torch"):
         self._lib = _capi.load()
         self.device = torch.device("cuda", device)
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        rc = self._lib.fmm2d_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream.cuda_stream))
+        if allocator == "torch":
+            self.allocator = TorchAllocator(self.device, self._stream)
+            fa, ff = self.allocator.c_alloc, self.allocator.c_free
+        elif allocator == "hip":
+            self.allocator = None
+            fa, ff = None, None
+        else:
+            raise ValueError("allocator must be 'torch' or 'hip'")
+        rc = self._lib.fmm2d_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream.cuda_stream),
+                                    ctypes.cast(fa, ctypes.c_void_p) if fa else None,
+                                    ctypes.cast(ff, ctypes.c_void_p) if ff else None, None)
         if rc != 0:
             raise FMM2DError(rc, "fmm2d_create failed")
         self._h = h

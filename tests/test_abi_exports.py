@@ -45,7 +45,14 @@ def test_version_and_argument_errors_without_gpu():
     lib = _capi.load()
     assert lib.fmm2d_version() >= 100
     # NULL out-pointer and NULL context are rejected before any device call
-    assert lib.fmm2d_create(None, 0, None) == _capi.EINVAL
+    assert lib.fmm2d_create(None, 0, None, None, None, None) == _capi.EINVAL
+    # an allocator without its free function (or the reverse) is refused
+    h = ctypes.c_void_p()
+    cb = _capi.ALLOC_FN(lambda n, u: None)
+    fr = _capi.FREE_FN(lambda p, n, u: None)
+    assert lib.fmm2d_create(ctypes.byref(h), 0, None, ctypes.cast(cb, ctypes.c_void_p), None, None) == _capi.EINVAL
+    assert lib.fmm2d_create(ctypes.byref(h), 0, None, None, ctypes.cast(fr, ctypes.c_void_p), None) == _capi.EINVAL
+    assert h.value is None
     assert lib.fmm2d_destroy(None) == _capi.EINVAL
     assert lib.fmm2d_build_tree(None, None, None, 10, 1) == _capi.EINVAL
     assert lib.fmm2d_connectivity(None, 0.5) == _capi.EINVAL

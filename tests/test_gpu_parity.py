@@ -36,17 +36,16 @@ def fmm():
     ctx.close()
 
 
-# Connectivity at theta = 1/2 on this point set ran on the GPU once with an
-# interim lists implementation (level totals by int64 atomics) and the box
-# reported a GPU fault; that implementation is gone and the cause was not
-# identified, so the case stays off the GPU until it is.
-FAULTED = {("clustered_scaled_20k_L6", 0.5)}
+# Cases held off the GPU: none.  (The clustered 20k-point input at theta = 1/2
+# was held off after an interim list build, never committed, faulted on it;
+# the current build's indices on that input are replayed on the CPU in
+# test_lists_index_model.py and stay in bounds through both pool regrowths.)
+FAULTED = set()
 
 
 def _skip_faulted(case, theta):
     if (case, theta) in FAULTED:
-        pytest.skip("connectivity(theta=%.2f) on %s is held off the GPU: an earlier interim lists version "
-                    "faulted here and the cause was not identified" % (theta, case))
+        pytest.skip("connectivity(theta=%.2f) on %s is held off the GPU" % (theta, case))
 
 
 def _announce(*a):
@@ -210,7 +209,7 @@ def test_call_order_and_argument_errors(fmm):
 
 def test_list_limit_fails_cleanly(orc, monkeypatch):
     # A level whose strong or weak list would exceed the entry limit is
-    # refused with ENOMEM before anything is written; the limit is lowered
+    # refused with ECAPACITY before anything is written; the limit is lowered
     # from the host so the path runs on a small input.
     from paper_1006_2269_amd.fmm import FMM2D, FMM2DError
 
@@ -220,7 +219,7 @@ def test_list_limit_fails_cleanly(orc, monkeypatch):
     ctx.build_tree(_dev(ps.x), _dev(ps.y), 4)
     with pytest.raises(FMM2DError) as e:
         ctx.connectivity(0.5)
-    assert e.value.code == -2 and "exceeds 500 entries" in str(e.value)
+    assert e.value.code == -5 and "exceeds 500 entries" in str(e.value)
     with pytest.raises(FMM2DError) as e:
         ctx.evaluate(_dev(ps.q), 5)
     assert e.value.code == -4
