@@ -162,6 +162,19 @@ int fmm2d_evaluate_field(fmm2d_ctx *ctx, const double *q, int p, int mode, doubl
 int fmm2d_direct(fmm2d_ctx *ctx, const double *x, const double *y, const double *q,
                  int64_t n, const int64_t *targets, int64_t m, double *phi_m);
 
+/* fmm2d_direct without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid it).  Same arguments, results and target check as
+ * fmm2d_direct (the same kernels, so bit-identical results); the chunk
+ * partials and the check flag live in a fixed device array of 4 MiB + 256
+ * bytes that the library holds on every device it runs on until the process
+ * ends.  m <= 262144 (FMM2D_EINVAL beyond).  Every call on a device
+ * shares that device's array: calls that overlap on one device (several
+ * contexts or streams) race and must be serialised by the caller.  No
+ * timing is recorded.  Synchronises the stream once (the target check). */
+int fmm2d_direct_noalloc(fmm2d_ctx *ctx, const double *x, const double *y, const double *q,
+                         int64_t n, const int64_t *targets, int64_t m, double *phi_m);
+
 /* The direct gradient of the same sum at m target indices, the judge of
  * fmm2d_evaluate_field: gx_m, gy_m (device binary64 [m]) receive the sums over
  * j with z_j != z_i of q_j (x_i - x_j) / |z_i - z_j|^2 and q_j (y_i - y_j) /

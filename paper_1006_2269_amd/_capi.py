@@ -39,6 +39,7 @@ SIGNATURES = [
     ("fmm2d_evaluate_field", I32, [P, P, I32, I32, P, P, P]),
     ("fmm2d_direct", I32, [P, P, P, P, I64, P, I64, P]),
     ("fmm2d_direct_field", I32, [P, P, P, P, I64, P, I64, P, P]),
+    ("fmm2d_direct_noalloc", I32, [P, P, P, P, I64, P, I64, P]),
     ("fmm2d_tree_info", I32, [P, PI64, PI32, PI64]),
     ("fmm2d_get_perm", I32, [P, P]),
     ("fmm2d_get_leaf_start", I32, [P, P]),

@@ -428,6 +428,26 @@ int fmm2d_direct(fmm2d_ctx *c, const double *x, const double *y, const double *q
     return FMM2D_OK;
 }
 
+int fmm2d_direct_noalloc(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
+                         const int64_t *targets, int64_t m, double *phi_m) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!x || !y || !q || (m > 0 && (!targets || !phi_m))) return fail(c, FMM2D_EINVAL, "direct_noalloc: NULL pointer");
+    if (n < 1 || m < 0) return fail(c, FMM2D_EINVAL, "direct_noalloc: need n >= 1 and m >= 0");
+    if (m == 0) return FMM2D_OK;
+    if (m > (int64_t(1) << 18) || !noalloc_fits(n, m))
+        return fail(c, FMM2D_EINVAL, "direct_noalloc: m = %lld exceeds 262144 targets (the fixed 4 MiB scratch)",
+                    (long long)m);
+    CtxScope g(c);
+    void *scr = nullptr;
+    hipError_t e = noalloc_scratch(c->device, &scr);
+    bool bad = false;
+    if (e == hipSuccess) e = direct_noalloc_device(c, scr, x, y, q, n, targets, m, phi_m, &bad);
+    if (e != hipSuccess) return hip_fail(c, e, "direct_noalloc");
+    if (bad) return fail(c, FMM2D_EINVAL, "direct_noalloc: a target index is outside [0, %lld)", (long long)n);
+    return FMM2D_OK;
+}
+
 int fmm2d_direct_field(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
                        const int64_t *targets, int64_t m, double *gx_m, double *gy_m) {
     if (!c) return FMM2D_EINVAL;

@@ -217,6 +217,14 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
 // judge.hip
 hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
                          const int64_t *targets, int64_t m, double *phi);
+// the judge on the fixed per-device array (fmm2d_direct_noalloc): its
+// address on `device` (looked up on first use, that device current), whether
+// the partials of n sources and m targets fit, and the launches (target check first:
+// *bad_target and nothing queued when an index is outside [0, n))
+hipError_t noalloc_scratch(int device, void **ptr);
+bool noalloc_fits(int64_t n, int64_t m);
+hipError_t direct_noalloc_device(fmm2d_ctx *c, void *scr, const double *x, const double *y, const double *q,
+                                 int64_t n, const int64_t *targets, int64_t m, double *phi, bool *bad_target);
 hipError_t direct_grad_device(fmm2d_ctx *c, const double *x, const double *y, const double *q, int64_t n,
                               const int64_t *targets, int64_t m, double *gx, double *gy);
 

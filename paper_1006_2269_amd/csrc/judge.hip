@@ -5,6 +5,8 @@
 // through LDS and every lane keeps a compensated (sum, correction) pair.  The
 // chunk partials are combined per target by a second kernel in chunk order,
 // so the result does not depend on scheduling.
+#include <mutex>
+
 #include "devutil.h"
 #include "internal.h"
 
@@ -159,6 +161,58 @@ hipError_t direct_device(fmm2d_ctx *c, const double *x, const double *y, const d
                          const int64_t *targets, int64_t m, double *phi) {
     FMM2D_TRY(c->scr.flag.ensure(sizeof(double2) * direct_part_count(n, m)));
     return direct_launch(c, x, y, q, n, targets, m, phi, c->scr.flag.as<double2>());
+}
+
+// ---- the judge without allocations -----------------------------------------
+// A fixed device array holds the chunk partials and the target-check flags,
+// so fmm2d_direct_noalloc calls no allocator.  Each device holds its own copy;
+// its address is looked up once per device (with that device current) and
+// only that address is passed to kernels and copies.
+constexpr size_t NOALLOC_PART_BYTES = size_t(4) << 20;
+constexpr size_t NOALLOC_BYTES = NOALLOC_PART_BYTES + 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+__global__ void k_flags_clear(int *flags) { flags[0] = 0; }
+__global__ void k_flags_targets(const int64_t *__restrict__ t, int64_t m, int64_t n, int *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m && (t[i] < 0 || t[i] >= n)) flags[0] = 1;
+}
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        FMM2D_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+bool noalloc_fits(int64_t n, int64_t m) {
+    // judge_chunks gives at most ceil(2048 / ceil(m / 64)) chunks, so the
+    // partials number at most 2048 * 64 + m: every m <= 2^18 fits in 4 MiB
+    return (size_t)direct_part_count(n, m) * sizeof(double2) <= NOALLOC_PART_BYTES;
+}
+
+hipError_t direct_noalloc_device(fmm2d_ctx *c, void *scr, const double *x, const double *y, const double *q,
+                                 int64_t n, const int64_t *targets, int64_t m, double *phi, bool *bad_target) {
+    int *flags = reinterpret_cast<int *>(static_cast<unsigned char *>(scr) + NOALLOC_PART_BYTES);
+    hipLaunchKernelGGL(k_flags_clear, dim3(1), dim3(1), 0, c->stream, flags);
+    hipLaunchKernelGGL(k_flags_targets, dim3(grid_for(m, 256)), dim3(256), 0, c->stream, targets, m, n, flags);
+    int hf = 0;
+    FMM2D_TRY(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    FMM2D_TRY(hipStreamSynchronize(c->stream));
+    *bad_target = hf != 0;
+    if (hf) return hipSuccess;
+    return direct_launch(c, x, y, q, n, targets, m, phi, static_cast<double2 *>(scr));
 }
 
 }  // namespace fmm2d

@@ -159,6 +159,19 @@ class FMM2D:
                                            targets.numel(), _ptr(out)))
         return out
 
+    def direct_noalloc(self, x, y, q, targets: torch.Tensor, out: torch.Tensor):
+        """fmm2d_direct on the library's fixed device array: no allocation by
+        the library (the caller provides out)."""
+        for t, nm in ((x, "x"), (y, "y"), (q, "q")):
+            _require(t, torch.float64, self.device, nm)
+        _require(targets, torch.int64, self.device, "targets")
+        _require(out, torch.float64, self.device, "out")
+        if out.numel() < targets.numel():
+            raise ValueError("out holds %d values, %d targets" % (out.numel(), targets.numel()))
+        self._check(self._lib.fmm2d_direct_noalloc(self._h, _ptr(x), _ptr(y), _ptr(q), x.numel(), _ptr(targets),
+                                                   targets.numel(), _ptr(out)))
+        return out
+
     def direct_field(self, x, y, q, targets: torch.Tensor):
         """(d phi/dx, d phi/dy) by the direct binary64 sum at the target indices."""
         for t, nm in ((x, "x"), (y, "y"), (q, "q")):
