@@ -16,6 +16,9 @@ multipole methods":
                     Criterion 2.1.
 * ``lists``      -- the recursive strong/weak connectivity rule (Section 4)
                     with the theta-criterion (Criterion 2.1).
+* ``lists_opt``  -- the same with the structural optimisations of Section 4:
+                    interaction via the parent box, and exchanged roles
+                    (P2L / M2P) for boxes of very different radii.
 * ``fmm``        -- upward pass, M2L along weak lists, downward pass, direct
                     sum along the finest strong lists (Section 4) in the
                     complex multipole representation (Section 5).
@@ -73,6 +76,14 @@ def _load():
     lib.orc_theta_test.restype = i32
     lib.orc_lists_level.argtypes = [i32, d, P, P, P, P, P, P, P, i64]
     lib.orc_lists_level.restype = i32
+    lib.orc_swap_test.argtypes = [d, P, P]
+    lib.orc_swap_test.restype = i32
+    lib.orc_lists_level_opt.argtypes = [i32, d, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i64]
+    lib.orc_lists_level_opt.restype = i32
+    lib.orc_p2l.argtypes = [i64, P, P, P, d, d, d, i32, P]
+    lib.orc_p2l.restype = None
+    lib.orc_fmm_eval_opt.argtypes = [i64, P, P, P, i32, i32] + [P] * 17
+    lib.orc_fmm_eval_opt.restype = i32
     lib.orc_p2m.argtypes = [i64, P, P, P, d, d, d, i32, P]
     lib.orc_p2m.restype = None
     lib.orc_m2m.argtypes = [P, d, d, d, d, d, d, i32, P]
@@ -238,6 +249,59 @@ def lists(t: Tree, theta: float) -> Lists:
     return Lists(theta, sptr, sidx, wptr, widx)
 
 
+def swap_test(theta: float, gb, gc) -> bool:
+    """The criterion with the roles of the radii exchanged (Section 4's
+    structural optimisation): r + theta R <= theta d, balls disjoint."""
+    lib = _load()
+    gb, gc = _f64(gb), _f64(gc)
+    return bool(lib.orc_swap_test(theta, _p(gb), _p(gc)))
+
+
+@dataclass
+class ListsOpt(Lists):
+    vptr: list = None   # per level: int64 [4^l + 1]; V entries are boxes of level l - 1
+    vidx: list = None
+    xptr: list = None   # per level: exchanged-roles entries (boxes of level l)
+    xidx: list = None
+    parent: bool = False
+    swap_levels: tuple = ()
+
+
+def lists_opt(t: Tree, theta: float, parent: bool = True, swap_levels=None) -> ListsOpt:
+    """Lists with the structural optimisations of Section 4: interaction via
+    the parent box (``parent``) and exchanged roles at the levels in
+    ``swap_levels`` (default: the finest level only, as in the paper).  An
+    exchanged pair is not refined further."""
+    if not (0.0 < theta < 1.0):
+        raise ValueError("theta must lie in (0, 1)")
+    if swap_levels is None:
+        swap_levels = (t.levels,)
+    swap_levels = tuple(sorted(set(int(l) for l in swap_levels)))
+    lib = _load()
+    z = lambda: np.zeros(0, dtype=np.int64)
+    sptr, sidx = [np.array([0, 1], dtype=np.int64)], [np.array([0], dtype=np.int64)]
+    wptr, widx = [np.array([0, 0], dtype=np.int64)], [z()]
+    vptr, vidx = [np.array([0, 0], dtype=np.int64)], [z()]
+    xptr, xidx = [np.array([0, 0], dtype=np.int64)], [z()]
+    for l in range(1, t.levels + 1):
+        nb = 4 ** l
+        cap = 16 * int(sidx[-1].shape[0])
+        arrs = [np.empty(nb + 1, dtype=np.int64) if k % 2 == 0 else np.empty(max(cap, 1), dtype=np.int64)
+                for k in range(8)]
+        g = np.ascontiguousarray(t.level_geom(l))
+        gp = np.ascontiguousarray(t.level_geom(l - 1))
+        rc = lib.orc_lists_level_opt(l, theta, int(parent), int(l in swap_levels), _p(g), _p(gp),
+                                     _p(sptr[-1]), _p(sidx[-1]), *[_p(a) for a in arrs], cap)
+        if rc != 0:
+            raise RuntimeError("orc_lists_level_opt overflow")
+        sp, si, wp, wi, vp, vi, xp, xi = arrs
+        sptr.append(sp); sidx.append(si[:sp[-1]].copy())
+        wptr.append(wp); widx.append(wi[:wp[-1]].copy())
+        vptr.append(vp); vidx.append(vi[:vp[-1]].copy())
+        xptr.append(xp); xidx.append(xi[:xp[-1]].copy())
+    return ListsOpt(theta, sptr, sidx, wptr, widx, vptr, vidx, xptr, xidx, bool(parent), swap_levels)
+
+
 # --------------------------------------------------------------------------
 # O4: expansion operators and the whole FMM
 # --------------------------------------------------------------------------
@@ -303,6 +367,15 @@ def l2p(B, center, scale, x, y) -> np.ndarray:
     return out
 
 
+def p2l(x, y, q, center, scale, p) -> np.ndarray:
+    """Local expansion about (center, scale) of sources outside its ball."""
+    lib = _load()
+    x, y, q = _f64(x), _f64(y), _f64(q)
+    B = _cplx_out(p)
+    lib.orc_p2l(x.shape[0], _p(x), _p(y), _p(q), center[0], center[1], scale, p, _p(B))
+    return _as_cplx(B)
+
+
 def m2p(A, center, scale, x, y) -> np.ndarray:
     lib = _load()
     p = len(A) - 1
@@ -334,6 +407,40 @@ def fmm_eval(x, y, q, t: Tree, ls: Lists, p: int) -> np.ndarray:
                           _p(phi))
     if rc != 0:
         raise RuntimeError("orc_fmm_eval failed: %d" % rc)
+    return phi
+
+
+def _concat(per_level):
+    L = len(per_level) - 1
+    off = np.zeros(L + 1, dtype=np.int64)
+    for l in range(1, L + 1):
+        off[l] = off[l - 1] + per_level[l - 1].shape[0]
+    cat = np.concatenate(per_level) if sum(a.shape[0] for a in per_level) else np.zeros(1, np.int64)
+    return _i64(cat), off
+
+
+def fmm_eval_opt(x, y, q, t: Tree, ls: ListsOpt, p: int) -> np.ndarray:
+    """The FMM potentials with the optimised lists (V via the parent, X with
+    exchanged roles), original order."""
+    lib = _load()
+    x, y, q = _f64(x), _f64(y), _f64(q)
+    L = t.levels
+    wptr, wptr_off = _concat(ls.wptr)
+    widx, widx_off = _concat(ls.widx)
+    vptr, vptr_off = _concat(ls.vptr)
+    vidx, vidx_off = _concat(ls.vidx)
+    xptr, xptr_off = _concat(ls.xptr)
+    xidx, xidx_off = _concat(ls.xidx)
+    geom = _f64(t.geom)
+    phi = np.empty(x.shape[0], dtype=np.float64)
+    rc = lib.orc_fmm_eval_opt(x.shape[0], _p(x), _p(y), _p(q), L, p, _p(_i64(t.perm)),
+                              _p(_i64(t.leaf_start)), _p(geom), _p(wptr), _p(widx),
+                              _p(wptr_off), _p(widx_off), _p(_i64(ls.sptr[L])),
+                              _p(_i64(ls.sidx[L]) if ls.sidx[L].shape[0] else np.zeros(1, np.int64)),
+                              _p(vptr), _p(vidx), _p(vptr_off), _p(vidx_off),
+                              _p(xptr), _p(xidx), _p(xptr_off), _p(xidx_off), _p(phi))
+    if rc != 0:
+        raise RuntimeError("orc_fmm_eval_opt failed: %d" % rc)
     return phi
 
 

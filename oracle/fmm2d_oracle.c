@@ -247,6 +247,89 @@ int orc_lists_level(int l, double theta, const double *geom_l,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The structural optimisations of Section 4 (optional).
+ *
+ * Interaction via the parent: when all four children of a box q in
+ * S(parent(b)) pass the theta-criterion against b, and so does q itself,
+ * b interacts with q (one conversion from the coarser level) instead of
+ * with its four children.  The criterion between b (level l) and q (level
+ * l-1) is Criterion 2.1 on their two balls.
+ *
+ * Exchanged roles: a strongly coupled pair whose criterion holds once the
+ * roles of the radii are exchanged, r + theta R <= theta d (R the larger
+ * radius), with the two balls disjoint (d > R + r).  Then the sources of the
+ * larger box become a local expansion about the smaller (P2L) and the
+ * multipole of the smaller is evaluated at the points of the larger (M2P).
+ * The paper applies it at the finest level; `swap` enables it at the level
+ * being built, and an exchanged pair is not refined further.            */
+int orc_swap_test(double theta, const double *gb, const double *gc)
+{
+    double dx = gb[0] - gc[0];
+    double dy = gb[1] - gc[1];
+    double dx2 = dx * dx;
+    double dy2 = dy * dy;
+    double d = sqrt(dx2 + dy2);
+    double R = gb[2] > gc[2] ? gb[2] : gc[2];
+    double r = gb[2] > gc[2] ? gc[2] : gb[2];
+    double lhs = r + theta * R;
+    double rhs = theta * d;
+    double sum = R + r;
+    return lhs <= rhs && d > sum;
+}
+
+/* One level of the optimised lists.  For box b with parent P and every q in
+ * S(P) (ascending): if `parent` is set, all four children of q are weak for
+ * b and the criterion holds between b and q, q joins V(b) (a level l-1 box);
+ * otherwise each child c joins W(b) when weak, else X(b) when `swap` is set
+ * and the exchanged criterion holds, else S(b).  All four lists come out
+ * ascending.  geom_l / geom_prev: (cx, cy, r) of the boxes of levels l and
+ * l-1.  Returns 0, or -1 if a capacity is exceeded.                       */
+int orc_lists_level_opt(int l, double theta, int parent, int swap, const double *geom_l,
+                        const double *geom_prev, const int64_t *sptr_prev, const int64_t *sidx_prev,
+                        int64_t *sptr, int64_t *sidx, int64_t *wptr, int64_t *widx,
+                        int64_t *vptr, int64_t *vidx, int64_t *xptr, int64_t *xidx, int64_t cap)
+{
+    int64_t nb = ((int64_t)1) << (2 * l);
+    int64_t ns = 0, nw = 0, nv = 0, nx = 0;
+    sptr[0] = 0; wptr[0] = 0; vptr[0] = 0; xptr[0] = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t P = b / 4;
+        const double *gb = geom_l + 3 * b;
+        for (int64_t t = sptr_prev[P]; t < sptr_prev[P + 1]; ++t) {
+            int64_t qbox = sidx_prev[t];
+            int weak[4], nweak = 0;
+            for (int k = 0; k < 4; ++k) {
+                weak[k] = orc_theta_test(theta, gb, geom_l + 3 * (4 * qbox + k));
+                nweak += weak[k];
+            }
+            if (parent && nweak == 4 && orc_theta_test(theta, gb, geom_prev + 3 * qbox)) {
+                if (nv >= cap) return -1;
+                vidx[nv++] = qbox;
+                continue;
+            }
+            for (int k = 0; k < 4; ++k) {
+                int64_t c = 4 * qbox + k;
+                if (weak[k]) {
+                    if (nw >= cap) return -1;
+                    widx[nw++] = c;
+                } else if (swap && orc_swap_test(theta, gb, geom_l + 3 * c)) {
+                    if (nx >= cap) return -1;
+                    xidx[nx++] = c;
+                } else {
+                    if (ns >= cap) return -1;
+                    sidx[ns++] = c;
+                }
+            }
+        }
+        sptr[b + 1] = ns;
+        wptr[b + 1] = nw;
+        vptr[b + 1] = nv;
+        xptr[b + 1] = nx;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* O4: the expansion operators in the classical complex representation
  * (Section 5), with every expansion normalised by its box scale s.
  *
@@ -399,6 +482,27 @@ void orc_l2p_grad(const double *B, double cx, double cy, double s, int p,
     }
 }
 
+/* P2L: the local expansion about (c, s) of the potential of sources z_j
+ * that lie outside the ball |z - c| < |z_j - c|, added to B:
+ *   log(z - z_j) = log(c - z_j) - sum_{l>=1} (1/l) ((z - c)/(z_j - c))^l, so
+ *   B_0 += sum q_j log|c - z_j|,  B_l += -(q_j / l) (s / (z_j - c))^l.     */
+void orc_p2l(int64_t n, const double *x, const double *y, const double *q,
+             double cx, double cy, double s, int p, double *B /* 2(p+1) */)
+{
+    cplx acc[64 + 1];
+    for (int k = 0; k <= p; ++k) acc[k] = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        cplx w = (x[j] - cx) + I * (y[j] - cy);
+        cplx rho = s / w, pw = 1.0;
+        acc[0] += q[j] * log(cabs(w));
+        for (int k = 1; k <= p; ++k) {
+            pw *= rho;
+            acc[k] += -(q[j] / k) * pw;
+        }
+    }
+    for (int k = 0; k <= p; ++k) { B[2 * k] += creal(acc[k]); B[2 * k + 1] += cimag(acc[k]); }
+}
+
 /* Multipole expansion evaluated at points (used by the operator pins).      */
 void orc_m2p(const double *A, double cx, double cy, double s, int p,
              int64_t n, const double *x, const double *y, double *phi)
@@ -426,14 +530,31 @@ void orc_m2p(const double *A, double cx, double cy, double s, int p,
 /* ------------------------------------------------------------------------ */
 static double box_scale(const double *g) { return g[2] > 0.0 ? g[2] : 1.0; }
 
+/* Optional lists of the structural optimisations, per level l = 0..L
+ * concatenated like W (NULL when absent): V (interaction via the parent:
+ * boxes of level l-1) and X (exchanged roles).                              */
+typedef struct {
+    const int64_t *vptr, *vidx, *vptr_off, *vidx_off;
+    const int64_t *xptr, *xidx, *xptr_off, *xidx_off;
+} opt_lists;
+
+/* Points of box b of level l: the leaves b 4^(L-l) .. (b+1) 4^(L-l) - 1.   */
+static void box_points(const int64_t *leaf_start, int L, int l, int64_t b, int64_t *a, int64_t *e)
+{
+    int64_t sh = 2 * (int64_t)(L - l);
+    *a = leaf_start[b << sh];
+    *e = leaf_start[(b + 1) << sh];
+}
+
 static int fmm_eval_impl(int64_t n, const double *x, const double *y, const double *q,
                          int L, int p, const int64_t *perm, const int64_t *leaf_start,
                          const double *geom, const int64_t *wptr, const int64_t *widx,
                          const int64_t *wptr_off, const int64_t *widx_off,
                          const int64_t *sptr_L, const int64_t *sidx_L, double *phi,
-                         double *gx, double *gy)
+                         double *gx, double *gy, const opt_lists *opt)
 {
     if (p < 1 || p > 64) return -1;
+    if (opt && gx) return -3;  /* the field is not formed with the optimised lists */
     int64_t nbox = level_offset(L + 1);
     int64_t nleaf = ((int64_t)1) << (2 * L);
     int64_t stride = 2 * (p + 1);
@@ -489,6 +610,41 @@ static int fmm_eval_impl(int64_t n, const double *x, const double *y, const doub
                         gt[0], gt[1], box_scale(gt), p, B + stride * (off + b));
             }
         }
+        if (opt && opt->vptr) {
+            /* interaction via the parent: multipoles of level l-1 boxes */
+            const int64_t *vp = opt->vptr + opt->vptr_off[l];
+            const int64_t *vi = opt->vidx + opt->vidx_off[l];
+            int64_t offp = level_offset(l - 1);
+#pragma omp parallel for schedule(dynamic, 64)
+            for (int64_t b = 0; b < nb; ++b) {
+                const double *gt = geom + 3 * (off + b);
+                for (int64_t t = vp[b]; t < vp[b + 1]; ++t) {
+                    int64_t qb = vi[t];
+                    const double *gs = geom + 3 * (offp + qb);
+                    orc_m2l(A + stride * (offp + qb), gs[0], gs[1], box_scale(gs),
+                            gt[0], gt[1], box_scale(gt), p, B + stride * (off + b));
+                }
+            }
+        }
+        if (opt && opt->xptr) {
+            /* exchanged roles, target the smaller box: the sources of the
+             * larger box as a local expansion about the target (P2L) */
+            const int64_t *xp = opt->xptr + opt->xptr_off[l];
+            const int64_t *xi = opt->xidx + opt->xidx_off[l];
+#pragma omp parallel for schedule(dynamic, 64)
+            for (int64_t b = 0; b < nb; ++b) {
+                const double *gt = geom + 3 * (off + b);
+                for (int64_t t = xp[b]; t < xp[b + 1]; ++t) {
+                    int64_t c = xi[t];
+                    const double *gs = geom + 3 * (off + c);
+                    if (!(gt[2] < gs[2])) continue;
+                    int64_t a, e;
+                    box_points(leaf_start, L, l, c, &a, &e);
+                    orc_p2l(e - a, xs + a, ys + a, qs + a, gt[0], gt[1], box_scale(gt), p,
+                            B + stride * (off + b));
+                }
+            }
+        }
         if (l < L) {
             int64_t offc = level_offset(l + 1);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -536,6 +692,28 @@ static int fmm_eval_impl(int64_t n, const double *x, const double *y, const doub
             }
         }
     }
+    if (opt && opt->xptr) {
+        /* exchanged roles, target the larger box: the smaller box's
+         * multipole evaluated at every point of the target (M2P) */
+        for (int l = 1; l <= L; ++l) {
+            int64_t nb = ((int64_t)1) << (2 * l), off = level_offset(l);
+            const int64_t *xp = opt->xptr + opt->xptr_off[l];
+            const int64_t *xi = opt->xidx + opt->xidx_off[l];
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t b = 0; b < nb; ++b) {
+                const double *gt = geom + 3 * (off + b);
+                int64_t a, e;
+                box_points(leaf_start, L, l, b, &a, &e);
+                for (int64_t t = xp[b]; t < xp[b + 1]; ++t) {
+                    int64_t c = xi[t];
+                    const double *gs = geom + 3 * (off + c);
+                    if (!(gt[2] > gs[2])) continue;
+                    orc_m2p(A + stride * (off + c), gs[0], gs[1], box_scale(gs), p, e - a, xs + a, ys + a,
+                            ps + a);
+                }
+            }
+        }
+    }
     for (int64_t i = 0; i < n; ++i) phi[perm[i]] = ps[i];
     if (gx)
         for (int64_t i = 0; i < n; ++i) { gx[perm[i]] = gxs[i]; gy[perm[i]] = gys[i]; }
@@ -550,7 +728,23 @@ int orc_fmm_eval(int64_t n, const double *x, const double *y, const double *q,
                  const int64_t *sptr_L, const int64_t *sidx_L, double *phi)
 {
     return fmm_eval_impl(n, x, y, q, L, p, perm, leaf_start, geom, wptr, widx, wptr_off, widx_off,
-                         sptr_L, sidx_L, phi, NULL, NULL);
+                         sptr_L, sidx_L, phi, NULL, NULL, NULL);
+}
+
+/* orc_fmm_eval with the lists of the structural optimisations: V (via the
+ * parent) and X (exchanged roles), per level, concatenated like W.          */
+int orc_fmm_eval_opt(int64_t n, const double *x, const double *y, const double *q,
+                     int L, int p, const int64_t *perm, const int64_t *leaf_start,
+                     const double *geom, const int64_t *wptr, const int64_t *widx,
+                     const int64_t *wptr_off, const int64_t *widx_off,
+                     const int64_t *sptr_L, const int64_t *sidx_L,
+                     const int64_t *vptr, const int64_t *vidx, const int64_t *vptr_off, const int64_t *vidx_off,
+                     const int64_t *xptr, const int64_t *xidx, const int64_t *xptr_off, const int64_t *xidx_off,
+                     double *phi)
+{
+    opt_lists o = {vptr, vidx, vptr_off, vidx_off, xptr, xidx, xptr_off, xidx_off};
+    return fmm_eval_impl(n, x, y, q, L, p, perm, leaf_start, geom, wptr, widx, wptr_off, widx_off,
+                         sptr_L, sidx_L, phi, NULL, NULL, &o);
 }
 
 /* The FMM with the gradient of the potential as well (the field of
@@ -565,5 +759,5 @@ int orc_fmm_eval_field(int64_t n, const double *x, const double *y, const double
                        double *gx, double *gy)
 {
     return fmm_eval_impl(n, x, y, q, L, p, perm, leaf_start, geom, wptr, widx, wptr_off, widx_off,
-                         sptr_L, sidx_L, phi, gx, gy);
+                         sptr_L, sidx_L, phi, gx, gy, NULL);
 }

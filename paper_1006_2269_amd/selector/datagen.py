@@ -7,9 +7,11 @@ binary64 judge at 1000 sampled targets, and for every level count L in
 least of three calls after one that may allocate), then for
 p = 4, 5, ... the time of evaluate (mode fp32_acc64) and the normwise error
 against the judge, until the error drops below 5e-8 or stops improving (the
-FP32 near field sets a floor).
+FP32 near field sets a floor).  Evaluate times are the GPU phases of one call
+(HIP events), so growing buffers do not count.
 
     python -m paper_1006_2269_amd.selector.datagen --first 50000 --count 400 --out gpurun_out/runs.npz
+    python -m paper_1006_2269_amd.selector.datagen --first 60000 --count 40 --lo 6 --hi 7 --out gpurun_out/big.npz
     python -m paper_1006_2269_amd.selector.datagen --retime runs.npz --out runs_retimed.npz
 """
 from __future__ import annotations
@@ -91,7 +93,8 @@ def run_layout(f, ps, torch, samples=1000):
                 continue  # a level's lists exceed the int32 entry limit
             best, stale = math.inf, 0
             for p in range(P_MIN, P_MAX + 1):
-                f.evaluate(q, p, MODE, out=out)   # warm (allocations)
+                # HIP events bracket the GPU work only (buffers that grow come
+                # from the caching allocator), so no warm-up call is needed
                 f.timing(True)
                 f.evaluate(q, p, MODE, out=out)
                 t_eval = phase_ms(f, ["upward", "m2l", "l2l", "leaf", "other"])
@@ -101,6 +104,7 @@ def run_layout(f, ps, torch, samples=1000):
                 best = min(best, e)
                 if e <= E_STOP or stale >= PLATEAU:
                     break  # below the tolerances of interest, or at the FP32 error floor
+        print("[datagen]   n=%d L=%d done (%d rows)" % (ps.n, L, len(rows)), flush=True)
     f.timing(False)
     return feat, rows
 
@@ -142,6 +146,7 @@ def main():
     ap.add_argument("--lo", type=float, default=4.0)
     ap.add_argument("--hi", type=float, default=6.0)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--save-every", type=int, default=5, help="write the table every this many layouts")
     args = ap.parse_args()
     import torch
 
@@ -164,9 +169,10 @@ def main():
         table.extend((i,) + r for r in rows)
         print("[datagen] layout %d seed %d n=%d runs=%d  %.0f s" % (i, seed, ps.n, len(rows), time.time() - t0),
               flush=True)
-        if (i + 1) % 25 == 0 or i + 1 == args.count:
+        if (i + 1) % args.save_every == 0 or i + 1 == args.count:
             np.savez_compressed(args.out, feats=np.array(feats, dtype=np.float32), n=np.array(ns, dtype=np.int64),
                      seeds=np.arange(args.first, args.first + i + 1), runs=np.array(table, dtype=np.float64),
+                     log10_range=np.array([args.lo, args.hi]),
                      columns=np.array(["layout", "L", "theta", "p", "t_tree_ms", "t_lists_ms", "t_eval_ms",
                                        "e_inf"]))
     f.close()
