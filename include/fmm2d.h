@@ -136,6 +136,35 @@ int fmm2d_build_tree(fmm2d_ctx *ctx, const double *x, const double *y,
  * strong entries) exceed 2^31 - 1, or all lists together 2^34 entries. */
 int fmm2d_connectivity(fmm2d_ctx *ctx, double theta);
 
+/* Structural options of the connectivity (Section 4's optional
+ * optimisations), combined with |:
+ *   FMM2D_OPT_PARENT       a box b for which all four children of a box q of
+ *                          S(parent(b)) pass the criterion, and q itself
+ *                          passes it against b, interacts with q (a box of
+ *                          the level above) instead of the four children:
+ *                          the weak list of b then holds q | FMM2D_VFLAG.
+ *   FMM2D_OPT_SWAP_FINEST  at the finest level, a strong pair of boxes whose
+ *                          criterion holds with the radii's roles exchanged,
+ *                          r + theta R <= theta d (R the larger radius), on
+ *                          disjoint balls (d > R + r), leaves the strong list
+ *                          for the exchanged list X: the sources of the larger
+ *                          box become a local expansion about the smaller
+ *                          (P2L) and the multipole of the smaller is evaluated
+ *                          at the points of the larger (M2P).
+ *   FMM2D_OPT_SWAP_ALL     the same at every level; an exchanged pair is not
+ *                          refined further (its children are no candidates).
+ * Every list stays ascending (a V entry sorts as its box q among the
+ * children of the level above's boxes). */
+#define FMM2D_OPT_PARENT       1
+#define FMM2D_OPT_SWAP_FINEST  2
+#define FMM2D_OPT_SWAP_ALL     4
+#define FMM2D_VFLAG            0x40000000
+
+/* fmm2d_connectivity with structural options `opt` (FMM2D_OPT_*, 0 gives
+ * exactly fmm2d_connectivity).  Later evaluations use the extra lists.
+ * FMM2D_EINVAL for unknown bits.  fmm2d_evaluate_field needs opt = 0. */
+int fmm2d_connectivity_opt(fmm2d_ctx *ctx, double theta, int opt);
+
 /* Evaluates phi (eq. (1.1)) with expansion order p (degrees 0..p, so p + 1
  * coefficients per expansion), 1 <= p <= 63, in precision `mode`
  * (FMM2D_MODE_*).  q: device binary64 [n] charges in input order.  phi:
@@ -293,9 +322,17 @@ int fmm2d_list_sizes(const fmm2d_ctx *ctx, int level, int64_t *n_strong, int64_t
 
 /* Device outputs for one level: CSR row pointers int32 [4^level + 1] and
  * column indices (box numbers within the level, ascending per row) of the
- * strong list S and the weak list W.  Any pointer may be NULL to skip it. */
+ * strong list S and the weak list W (with FMM2D_OPT_PARENT, entries with
+ * FMM2D_VFLAG set are boxes of level - 1).  Any pointer may be NULL to skip
+ * it. */
 int fmm2d_get_lists(fmm2d_ctx *ctx, int level, int32_t *sptr, int32_t *sidx,
                     int32_t *wptr, int32_t *widx);
+
+/* Exchanged-roles list of one level (empty unless the lists were built with
+ * a swap option): host output *nx (entry count); device outputs xptr int32
+ * [4^level + 1] and xidx (box numbers within the level, ascending per row),
+ * either may be NULL. */
+int fmm2d_get_xlists(fmm2d_ctx *ctx, int level, int64_t *nx, int32_t *xptr, int32_t *xidx);
 
 /* ---- per-phase GPU timing ------------------------------------------------ */
 
@@ -312,7 +349,8 @@ int fmm2d_get_lists(fmm2d_ctx *ctx, int level, int32_t *sptr, int32_t *sidx,
 /* Single kernel launches, also counted in their phase above:                 */
 #define FMM2D_PHASE_NEAR_KERNEL  9  /* the near-field kernel (in LEAF)       */
 #define FMM2D_PHASE_M2L_KERNEL  10  /* the M2L kernel, all levels (in M2L)   */
-#define FMM2D_NPHASE       11
+#define FMM2D_PHASE_EXCHANGE    11  /* P2L and M2P of exchanged-roles pairs  */
+#define FMM2D_NPHASE       12
 
 /* enable = 1 clears the accumulated timings and starts recording HIP events
  * on the context stream around each phase; enable = 0 stops recording. */

@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(HERE, "libfmm2d.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECAPACITY = 0, -1, -2, -3, -4, -5
 MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32_acc64": 3}
+OPT_PARENT, OPT_SWAP_FINEST, OPT_SWAP_ALL = 1, 2, 4
+VFLAG = 0x40000000
 
 _lib = None
 
@@ -35,6 +37,7 @@ SIGNATURES = [
     ("fmm2d_set_stream", I32, [P, P]),
     ("fmm2d_build_tree", I32, [P, P, P, I64, I32]),
     ("fmm2d_connectivity", I32, [P, D]),
+    ("fmm2d_connectivity_opt", I32, [P, D, I32]),
     ("fmm2d_evaluate", I32, [P, P, I32, I32, P]),
     ("fmm2d_evaluate_field", I32, [P, P, I32, I32, P, P, P]),
     ("fmm2d_direct", I32, [P, P, P, P, I64, P, I64, P]),
@@ -46,6 +49,7 @@ SIGNATURES = [
     ("fmm2d_get_rects", I32, [P, P]),
     ("fmm2d_list_sizes", I32, [P, I32, PI64, PI64]),
     ("fmm2d_get_lists", I32, [P, I32, P, P, P, P]),
+    ("fmm2d_get_xlists", I32, [P, I32, PI64, P, P]),
     ("fmm2d_features", I32, [P, P, P, I64, D, P]),
     ("fmm2d_select", I32, [P, P, P, I64, D, P, PI32, PI32, PD, PI32]),
     ("fmm2d_select_build_tree", I32, [P, P, P, I64, D, P, PI32, PI32, PD, PI32]),
@@ -65,7 +69,7 @@ NFEAT = 92
 SELECT_HEADER = 194
 
 PHASES = ["tree", "lists", "upward", "m2l", "l2l", "leaf", "other", "judge", "select", "near_kernel",
-          "m2l_kernel"]
+          "m2l_kernel", "exchange"]
 
 
 def load():

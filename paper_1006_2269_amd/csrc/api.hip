@@ -160,7 +160,7 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         TreeState &t = c->tree;
         for (DevBuf *b : {&t.xsorted, &t.ysorted, &t.xorder, &t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1,
                           &t.starts, &t.rects, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
-                          &t.sidx, &t.widx, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d, &t.bits,
+                          &t.sidx, &t.widx, &t.xptr, &t.xidx, &t.cnt_x, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d, &t.bits,
                           &t.owner0, &t.owner1, &t.selfpos, &t.trans, &t.spart})
             b->release();
         EvalState &e = c->ev;
@@ -173,6 +173,9 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->tree.near_lo.segoff.release();
         c->tree.near_lo.table.release();
         c->tree.lsum.release();
+        c->tree.x_items.release();
+        c->tree.x_itemoff.release();
+        c->ev.xpart.release();
         for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.work,
                           &e.src})
             b->release();
@@ -311,18 +314,22 @@ int fmm2d_select_build_tree(fmm2d_ctx *c, const double *x, const double *y, int6
     return FMM2D_OK;
 }
 
-int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
+int fmm2d_connectivity_opt(fmm2d_ctx *c, double theta, int opt) {
     if (!c) return FMM2D_EINVAL;
     c->err.clear();
     if (!(theta > 0.0 && theta < 1.0)) return fail(c, FMM2D_EINVAL, "connectivity: theta must lie in (0, 1)");
+    if (opt & ~(FMM2D_OPT_PARENT | FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL))
+        return fail(c, FMM2D_EINVAL, "connectivity: unknown option bits 0x%x", opt);
     TreeState &t = c->tree;
     if (t.L < 0) return fail(c, FMM2D_ESTATE, "connectivity: no tree (call fmm2d_build_tree first)");
     CtxScope g(c);
     const int64_t nbox = level_offset(t.L + 1);
+    const bool swaps = (opt & (FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL)) != 0;
     // start from the pool sizes that sufficed for the previous call (repeated
     // calls on similar point sets then build the lists in one pass)
     int64_t cap_s = std::max<int64_t>(32 * nbox + 64, c->cap_hint_s);
     int64_t cap_w = std::max<int64_t>(96 * nbox + 64, c->cap_hint_w);
+    int64_t cap_x = swaps ? std::max<int64_t>(16 * nbox + 64, c->cap_hint_x) : 0;
     const int64_t pool_max = int64_t(1) << 34;  // entries per pool, all levels together
     for (int attempt = 0; attempt < 16; ++attempt) {
         int overflow = 0;
@@ -330,7 +337,7 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
         {
             PhaseScope ps(c, PH_LISTS);
             t.nrec_valid = false;
-            e = build_lists_device(c, theta, cap_s, cap_w, c->list_limit, &overflow);
+            e = build_lists_device(c, theta, opt, cap_s, cap_w, cap_x, c->list_limit, &overflow);
         }
         if (e != hipSuccess) {
             t.has_lists = false;
@@ -347,6 +354,7 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
             t.theta = theta;
             c->cap_hint_s = cap_s;
             c->cap_hint_w = cap_w;
+            if (swaps) c->cap_hint_x = cap_x;
             return FMM2D_OK;
         }
         if (overflow == 2) {
@@ -356,13 +364,16 @@ int fmm2d_connectivity(fmm2d_ctx *c, double theta) {
                         "another theta for this point set)",
                         (long long)c->list_limit);
         }
-        if (cap_s >= pool_max && cap_w >= pool_max) break;
+        if (cap_s >= pool_max && cap_w >= pool_max && (!swaps || cap_x >= pool_max)) break;
         cap_s = cap_s * 4 < pool_max ? cap_s * 4 : pool_max;
         cap_w = cap_w * 4 < pool_max ? cap_w * 4 : pool_max;
+        if (swaps) cap_x = cap_x * 4 < pool_max ? cap_x * 4 : pool_max;
     }
     t.has_lists = false;
     return fail(c, FMM2D_ECAPACITY, "connectivity: interaction lists exceed 2^34 entries");
 }
+
+int fmm2d_connectivity(fmm2d_ctx *c, double theta) { return fmm2d_connectivity_opt(c, theta, 0); }
 
 int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) {
     if (!c) return FMM2D_EINVAL;
@@ -385,6 +396,8 @@ int fmm2d_evaluate_field(fmm2d_ctx *c, const double *q, int p, int mode, double 
     if (p < 1 || p > FMM2D_MAX_P) return fail(c, FMM2D_EINVAL, "evaluate_field: p = %d not in [1, 63]", p);
     if (mode != FMM2D_MODE_FP64)
         return fail(c, FMM2D_EINVAL, "evaluate_field: the gradient is computed in binary64 only (FMM2D_MODE_FP64)");
+    if (c->tree.opt != 0)
+        return fail(c, FMM2D_EINVAL, "evaluate_field: needs the plain lists (fmm2d_connectivity without options)");
     if (c->tree.L < 0 || !c->tree.has_lists)
         return fail(c, FMM2D_ESTATE, "evaluate_field: needs a tree and its lists (build_tree, connectivity)");
     CtxScope g(c);
@@ -621,6 +634,30 @@ int fmm2d_get_lists(fmm2d_ctx *c, int level, int32_t *sptr, int32_t *sidx, int32
         e = hipMemcpyAsync(widx, t.widx.as<int32_t>() + t.w_off[level], sizeof(int32_t) * nw, hipMemcpyDeviceToDevice,
                            c->stream);
     return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_lists");
+}
+
+int fmm2d_get_xlists(fmm2d_ctx *c, int level, int64_t *nx, int32_t *xptr, int32_t *xidx) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    const TreeState &t = c->tree;
+    if (!t.has_lists) return fail(c, FMM2D_ESTATE, "get_xlists: no lists");
+    if (level < 0 || level > t.L) return fail(c, FMM2D_EINVAL, "get_xlists: level %d not in [0, %d]", level, t.L);
+    const int64_t n = t.x_off[level + 1] - t.x_off[level];
+    if (nx) *nx = n;
+    CtxScope g(c);
+    hipError_t e = hipSuccess;
+    const int64_t rows = (int64_t(1) << (2 * level)) + 1;
+    if (xptr) {
+        const bool swaps = (t.opt & (FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL)) != 0;
+        e = swaps ? hipMemcpyAsync(xptr, t.xptr.as<int32_t>() + ptr_offset(level), sizeof(int32_t) * rows,
+                                   hipMemcpyDeviceToDevice, c->stream)
+                  : hipMemsetAsync(xptr, 0, sizeof(int32_t) * rows, c->stream);
+    }
+    if (xidx && n > 0 && e == hipSuccess)
+        e = hipMemcpyAsync(xidx, t.xidx.as<int32_t>() + t.x_off[level], sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "get_xlists");
+    return FMM2D_OK;
 }
 
 int fmm2d_timing(fmm2d_ctx *c, int enable) {

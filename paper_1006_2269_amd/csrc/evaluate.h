@@ -25,6 +25,15 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage, double *phi);
 // the gradient of the potential at every point, input order, after a
 // binary64 evaluation with the same p (field.hip)
 hipError_t gradient_device(fmm2d_ctx *c, int p, double *gx, double *gy);
+// Exchanged roles (structural option, exchange.hip): the work items of the
+// P2L side (target box, source box, point range), built with the schedules;
+// per global box the range of its items (nullptr when the lists have no
+// exchanged pair); P2L partials into ev.xpart (before the L2L pass, which
+// adds them into B); M2P of the smaller boxes' multipoles added into phi.
+hipError_t exchange_schedule(fmm2d_ctx *c);
+const int32_t *exchange_item_offsets(fmm2d_ctx *c);
+hipError_t p2l_all(fmm2d_ctx *c, int p);
+hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi);
 // list segments for the M2L and near-field kernels (sched.hip)
 hipError_t build_schedules(fmm2d_ctx *c);
 hipError_t ensure_near_full_schedule(fmm2d_ctx *c);

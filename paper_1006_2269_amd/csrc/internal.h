@@ -69,12 +69,16 @@ struct TreeState {
     DevBuf loc;             // float2 [n], offsets from the leaf centre
     // lists: row pointers of every level (ptr_offset), index pools
     DevBuf sptr, wptr, sidx, widx, cnt_s, cnt_w;
+    // exchanged-roles lists (structural option): row pointers of every level,
+    // index pool, per-word counts
+    DevBuf xptr, xidx, cnt_x;
+    int opt = 0;            // FMM2D_OPT_* flags the lists were built with
     DevBuf bits;            // uint64: theta decisions of one level's candidates
     DevBuf owner0, owner1;  // int32: row (box) of each S entry of a level, by level parity
     DevBuf selfpos;         // int32 [4^L]: position of leaf b in S_L(b) (level-relative)
     DevBuf trans;           // int32 per S_L record t = (b, c) with c > b: the position of b in S_L(c)
     DevBuf spart;           // float: source-side near-field partial sums per S_L record and source lane
-    DevBuf pool_state;      // int64 [2 (L+2) + 1]: s offsets, w offsets, overflow
+    DevBuf pool_state;      // int64 [3 (L+2) + 1]: s, w, x offsets, overflow
     DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range, FP32 centre offset, threshold
     bool nrec_valid = false;
     Schedule m2l_all;               // weak lists of all levels (rows = global box ids)
@@ -82,8 +86,13 @@ struct TreeState {
     bool near_seg_ready = false;
     Schedule near_up;               // finest-level strong lists from each leaf's own entry on
     Schedule near_lo;               // the same lists before each leaf's own entry
+    // exchanged roles: P2L work items int4 (target box, source box, first
+    // point, end point), global ids; per global box its first item (+ count)
+    DevBuf x_items, x_itemoff;
+    int64_t x_item_bound = 0;       // upper bound of the item count (launch size)
+    bool x_ready = false;
     DevBuf lsum;                    // double: per near_lo segment and source lane, its entries' source sums
-    std::vector<int64_t> s_off, w_off;  // host copy: pool offset of each level
+    std::vector<int64_t> s_off, w_off, x_off;  // host copy: pool offset of each level
     bool has_lists = false;
     double theta = 0.0;
 };
@@ -100,6 +109,7 @@ struct EvalState {
     DevBuf part;            // partial sums of the M2L's list segments
     DevBuf npart;           // near-field partial sums (written on the second stream while the far field runs)
     DevBuf gpart;           // near-field gradient partial sums (fmm2d_evaluate_field)
+    DevBuf xpart;           // P2L partial expansions of the exchanged-roles items
 };
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream
@@ -107,6 +117,7 @@ struct EvalState {
 enum Phase {
     PH_TREE = 0, PH_LISTS, PH_UPWARD, PH_M2L, PH_L2L, PH_LEAF, PH_OTHER, PH_JUDGE, PH_SELECT,
     PH_NEAR_KERNEL, PH_M2L_KERNEL,  // single launches inside PH_LEAF / PH_M2L
+    PH_EXCHANGE,                    // P2L and M2P of the exchanged-roles pairs
     PH_COUNT
 };
 
@@ -145,7 +156,7 @@ struct fmm2d_ctx {
     fmm2d_free_fn free = nullptr;
     void *user = nullptr;
     int64_t list_limit = 2147483647LL;  // entries per level and list (FMM2D_LIST_LIMIT lowers it)
-    int64_t cap_hint_s = 0, cap_hint_w = 0;  // list pool sizes that sufficed last time
+    int64_t cap_hint_s = 0, cap_hint_w = 0, cap_hint_x = 0;  // list pool sizes that sufficed last time
     hipStream_t stream = nullptr;
     // internal stream for work that may overlap the caller's stream (created
     // on first use, default priority); ev_side_out marks the end of the last
@@ -209,9 +220,10 @@ hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, 
 hipError_t tree_sort(fmm2d_ctx *c, int64_t n);
 hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y, bool sorted = false);
 // lists.hip
-// overflow: 0 ok, 1 a pool was too small (grow and retry), 2 a level exceeds `limit` entries
-hipError_t build_lists_device(fmm2d_ctx *c, double theta, int64_t cap_s, int64_t cap_w, int64_t limit,
-                              int *overflow);
+// overflow: 0 ok, 1 a pool was too small (grow and retry), 2 a level exceeds `limit` entries;
+// opt: FMM2D_OPT_* (0: the plain lists)
+hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s, int64_t cap_w, int64_t cap_x,
+                              int64_t limit, int *overflow);
 // expand.hip
 hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, double *phi);
 // judge.hip

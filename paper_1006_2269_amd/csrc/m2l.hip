@@ -33,6 +33,14 @@
 namespace fmm2d {
 namespace {
 
+// Global box id of a weak-list entry of level lvl: a box of that level, or,
+// with FMM2D_VFLAG set, a box of the level above (interaction via the
+// parent box, Section 4's structural option).
+__device__ inline int64_t m2l_source(int32_t w, int lvl) {
+    return (w & FMM2D_VFLAG) ? level_offset(lvl - 1) + (w & (FMM2D_VFLAG - 1)) : level_offset(lvl) + w;
+}
+
+
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -138,7 +146,6 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
     const double4 *geomL = geom + level_offset(lvl);
     const int32_t *wptr = wptr_all + ptr_offset(lvl);
     const int32_t *widx = widx_pool + woff[lvl];
-    const cd *AL = A + level_offset(lvl) * (int64_t)(p + 1);
     const int32_t t0 = se.y;
     const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
     const int P1 = p + 1;
@@ -190,11 +197,12 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
         if (q < np0) c_n1 = widx[t0 + q];
         if (t0 + CP + q < t1) c_n2 = widx[t0 + CP + q];
         if (q < np0) {
-            g_n1 = geomL[c_n1];
+            const int64_t cg = m2l_source(c_n1, lvl);
+            g_n1 = geom[cg];
 #pragma unroll
             for (int kk = 0; kk < KRMAX; ++kk) {
                 const int k = k0 + kk;
-                a_n1[kk] = (kk < KR && k < P1) ? AL[(int64_t)c_n1 * P1 + k] : cd{0.0, 0.0};
+                a_n1[kk] = (kk < KR && k < P1) ? A[cg * P1 + k] : cd{0.0, 0.0};
             }
         }
     }
@@ -208,12 +216,12 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
         {
             const int32_t tn = t + CP;
             if (tn + q < t1) {
-                const int32_t cn = c_n2;
-                g_n1 = geomL[cn];
+                const int64_t cg = m2l_source(c_n2, lvl);
+                g_n1 = geom[cg];
 #pragma unroll
                 for (int kk = 0; kk < KRMAX; ++kk) {
                     const int k = k0 + kk;
-                    a_n1[kk] = (kk < KR && k < P1) ? AL[(int64_t)cn * P1 + k] : cd{0.0, 0.0};
+                    a_n1[kk] = (kk < KR && k < P1) ? A[cg * P1 + k] : cd{0.0, 0.0};
                 }
             }
             if (tn + CP + q < t1) c_n2 = widx[tn + CP + q];
@@ -368,7 +376,6 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
     const double4 *geomL = geom + level_offset(lvl);
     const int32_t *wptr = wptr_all + ptr_offset(lvl);
     const int32_t *widx = widx_pool + woff[lvl];
-    const cd *AL = A + level_offset(lvl) * (int64_t)P1;
     const int32_t t0 = se.y;
     const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
     const int row = lane % 16, g = lane / 16;
@@ -401,9 +408,9 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
         const bool act = lane < np;
         cx<PT> rtp{(PT)0, (PT)0};
         if (act) {
-            const int32_t c = widx[t + lane];
-            const double4 gc = geomL[c];
-            const cd *Ac = AL + (int64_t)c * P1;
+            const int64_t cg = m2l_source(widx[t + lane], lvl);
+            const double4 gc = geom[cg];
+            const cd *Ac = A + cg * P1;
             cd a[P1];
 #pragma unroll
             for (int k = 0; k < P1; ++k) a[k] = Ac[k];  // all loads in flight together

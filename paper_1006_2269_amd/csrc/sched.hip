@@ -180,6 +180,7 @@ __global__ void k_near_trans(const int32_t *__restrict__ sptr, const int32_t *__
 hipError_t build_schedules(fmm2d_ctx *c) {
     TreeState &t = c->tree;
     const int L = t.L;
+    FMM2D_TRY(exchange_schedule(c));  // P2L work items of the exchanged-roles lists (structural option)
     const int64_t nbox = level_offset(L + 1);
     const int64_t nleaf = int64_t(1) << (2 * L);
     // all levels' weak lists (rows of levels >= 1)

@@ -126,8 +126,14 @@ class FMM2D:
         self._check(self._lib.fmm2d_build_tree(self._h, _ptr(x), _ptr(y), n, int(levels)))
         self.n, self.levels = n, int(levels)
 
-    def connectivity(self, theta: float):
-        self._check(self._lib.fmm2d_connectivity(self._h, float(theta)))
+    def connectivity(self, theta: float, parent: bool = False, swap: str | None = None):
+        """Strong/weak lists under the theta-criterion.  Section 4's
+        structural options: ``parent`` (interaction via the parent box) and
+        ``swap`` = "finest" or "all" (exchanged roles for boxes of very
+        different radii at the finest level, or at every level)."""
+        opt = (_capi.OPT_PARENT if parent else 0) | {None: 0, "finest": _capi.OPT_SWAP_FINEST,
+                                                     "all": _capi.OPT_SWAP_ALL}[swap]
+        self._check(self._lib.fmm2d_connectivity_opt(self._h, float(theta), opt))
 
     def evaluate(self, q: torch.Tensor, p: int, mode: str = "fp64", out: torch.Tensor | None = None):
         _require(q, torch.float64, self.device, "q")
@@ -328,3 +334,13 @@ class FMM2D:
         wi = torch.empty(max(nw, 1), dtype=torch.int32, device=dev)
         self._check(self._lib.fmm2d_get_lists(self._h, level, _ptr(sp), _ptr(si), _ptr(wp), _ptr(wi)))
         return sp, si[:ns], wp, wi[:nw]
+
+    def xlists(self, level: int):
+        """(xptr, xidx) of the exchanged-roles list of one level."""
+        nx = ctypes.c_int64()
+        self._check(self._lib.fmm2d_get_xlists(self._h, level, ctypes.byref(nx), None, None))
+        nb = 4 ** level
+        xp = torch.empty(nb + 1, dtype=torch.int32, device=self.device)
+        xi = torch.empty(max(nx.value, 1), dtype=torch.int32, device=self.device)
+        self._check(self._lib.fmm2d_get_xlists(self._h, level, ctypes.byref(nx), _ptr(xp), _ptr(xi)))
+        return xp, xi[:nx.value]

@@ -50,16 +50,24 @@ class Bounds:
         self.used[name] = (max(prev[0], hi), size)
 
 
-def _attempt(ls, L, cap_s, cap_w, limit, bd):
+VFLAG = 1 << 30
+
+
+def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0):
     """One build_lists_device call; returns (overflow flag, pool offsets,
-    replayed S and W lists per level)."""
+    replayed S and W lists per level).  With optimised lists (``ls.vptr``
+    present) the W output holds V entries (flagged) and an X pool is used."""
+    opt = getattr(ls, "vptr", None) is not None
     nS = [int(ls.sptr[l][-1]) for l in range(L + 1)]
-    nW = [int(ls.wptr[l][-1]) for l in range(L + 1)]
+    nW = [int(ls.wptr[l][-1]) + (int(ls.vptr[l][-1]) if opt else 0) for l in range(L + 1)]
+    nX = [int(ls.xptr[l][-1]) if opt else 0 for l in range(L + 1)]
     s_off = [0] * (L + 2)
     w_off = [0] * (L + 2)
+    x_off = [0] * (L + 2)
     s_off[1] = 1
     flag = 0
     got_s, got_w = {0: np.array([0])}, {0: np.zeros(0, np.int64)}
+    got_x = {0: np.zeros(0, np.int64)}
     n_leaf = 4 ** L
     leaf_rows = n_leaf + 1
     # buffers as sized by the host
@@ -77,9 +85,11 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd):
             return
         so = s_off[l] + nS[l]
         wo = w_off[l] + nW[l]
+        xo = x_off[l] + nX[l]
         s_off[l + 1] = so
         w_off[l + 1] = wo
-        if so > cap_s or wo > cap_w:
+        x_off[l + 1] = xo
+        if so > cap_s or wo > cap_w or xo > cap_x:
             flag = 1
             return
         if l < L:
@@ -102,6 +112,8 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd):
         if l > K:
             nwords = (NC + 63) // 64
             bd.touch("bits/cnt (words)", np.arange(nwords), words_cap)
+            if opt:  # exchanged and group-head masks at wcap and 2 wcap
+                bd.touch("bits (three masks)", 2 * words_cap + np.arange(nwords), 3 * words_cap)
             bd.touch("scan tiles", np.arange((nwords + WS_TILE - 1) // WS_TILE), ntile)
             bd.touch("owner_prev", q >> 4, cap_s)
             bd.touch("owner_prev written", q >> 4, nS[l - 1])
@@ -123,18 +135,38 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd):
         if l <= K:
             bd.touch("geometry in LDS", level_offset(l) + np.concatenate([b, cbox]), SMALL_GEOM)
         # decisions from the oracle's lists: candidate weak iff in W_l(b)
+        # (a member of a parent group iff its parent is in V_l(b), the
+        # group's first child then writes the V entry), exchanged iff in X_l(b)
         wp, wi = np.asarray(ls.wptr[l], np.int64), np.asarray(ls.widx[l], np.int64)
         wkeys = np.repeat(np.arange(nb, dtype=np.int64), np.diff(wp)) * nb + wi
         weak = np.isin(b * nb + cbox, wkeys)
-        strong = ~weak
+        head = np.zeros(NC, bool)
+        exch = np.zeros(NC, bool)
+        member = np.zeros(NC, bool)
+        if opt:
+            vp, vi = np.asarray(ls.vptr[l], np.int64), np.asarray(ls.vidx[l], np.int64)
+            vkeys = np.repeat(np.arange(nb, dtype=np.int64), np.diff(vp)) * nb + vi
+            member = np.isin(b * nb + (cbox >> 2), vkeys)
+            head = member & ((cbox & 3) == 0)
+            xp, xi = np.asarray(ls.xptr[l], np.int64), np.asarray(ls.xidx[l], np.int64)
+            xkeys = np.repeat(np.arange(nb, dtype=np.int64), np.diff(xp)) * nb + xi
+            exch = np.isin(b * nb + cbox, xkeys)
+            assert not np.any(weak & (member | exch)) and not np.any(member & exch)
+        wout = weak | head
+        strong = ~(weak | member | exch)
         # scans: pool positions and row pointers
         posS = np.cumsum(strong) - strong
-        posW = np.cumsum(weak) - weak
+        posW = np.cumsum(wout) - wout
+        posX = np.cumsum(exch) - exch
         advance(l)
         if flag:
             break
         bd.touch("sidx pool (level %d)" % l, s_off[l] + posS[strong], cap_s)
-        bd.touch("widx pool (level %d)" % l, w_off[l] + posW[weak], cap_w)
+        bd.touch("widx pool (level %d)" % l, w_off[l] + posW[wout], cap_w)
+        if opt:
+            bd.touch("xidx pool (level %d)" % l, x_off[l] + posX[exch], max(cap_x, 1))
+            if l > 1:
+                bd.touch("parent geometry", (cbox >> 2)[head], 4 ** (l - 1))
         bd.touch("owner_cur", posS[strong], cap_s)
         first = np.zeros(NC, bool)
         first[np.flatnonzero(j == 0)] = True
@@ -150,31 +182,49 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd):
         S[posS[strong]] = cbox[strong]
         W = np.empty(nW[l], np.int64)
         W[posW[weak]] = cbox[weak]
-        got_s[l], got_w[l] = S, W
-    return flag, s_off, got_s, got_w
+        W[posW[head]] = (cbox[head] >> 2) | VFLAG
+        X = np.empty(nX[l], np.int64)
+        X[posX[exch]] = cbox[exch]
+        got_s[l], got_w[l], got_x[l] = S, W, X
+    return flag, s_off, got_s, got_w, got_x
 
 
-def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX):
+def split_w(W):
+    """A W output list with parent entries flagged -> (W entries, V entries)."""
+    W = np.asarray(W, np.int64)
+    flagged = (W & VFLAG) != 0
+    return W[~flagged], W[flagged] & (VFLAG - 1)
+
+
+def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX, swaps=False, hint_x=0):
     """fmm2d_connectivity's retry loop around the replayed build.  Returns
     (status, attempts, bounds, caps)."""
     nbox = level_offset(L + 1)
     cap_s = max(32 * nbox + 64, hint_s)
     cap_w = max(96 * nbox + 64, hint_w)
+    cap_x = max(16 * nbox + 64, hint_x) if swaps else 0
     bd = Bounds()
+    opt = getattr(ls, "vptr", None) is not None
     for attempt in range(16):
-        flag, s_off, got_s, got_w = _attempt(ls, L, cap_s, cap_w, limit, bd)
+        flag, s_off, got_s, got_w, got_x = _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x)
         if flag == 0:
             for l in range(L + 1):
                 assert np.array_equal(got_s[l], ls.sidx[l]), "replayed S list of level %d differs" % l
-                assert np.array_equal(got_w[l], ls.widx[l]), "replayed W list of level %d differs" % l
-            return "ok", attempt + 1, bd, (cap_s, cap_w)
+                w, v = split_w(got_w[l])
+                assert np.array_equal(w, ls.widx[l]), "replayed W list of level %d differs" % l
+                if opt:
+                    assert np.array_equal(v, ls.vidx[l]), "replayed V list of level %d differs" % l
+                    assert np.array_equal(got_x[l], ls.xidx[l]), "replayed X list of level %d differs" % l
+            return "ok", attempt + 1, bd, (cap_s, cap_w, cap_x)
         if flag == 2:
-            return "capacity", attempt + 1, bd, (cap_s, cap_w)
-        if cap_s >= POOL_MAX and cap_w >= POOL_MAX:
+            return "capacity", attempt + 1, bd, (cap_s, cap_w, cap_x)
+        if cap_s >= POOL_MAX and cap_w >= POOL_MAX and (not swaps or cap_x >= POOL_MAX):
             break
         cap_s = min(cap_s * 4, POOL_MAX)
         cap_w = min(cap_w * 4, POOL_MAX)
-    return "nomem", 16, bd, (cap_s, cap_w)
+        if swaps:
+            cap_x = min(cap_x * 4, POOL_MAX)
+    return "nomem", 16, bd, (cap_s, cap_w, cap_x)
 
 
 @pytest.mark.parametrize("case", sorted(TREE_CASES))
@@ -207,3 +257,18 @@ def test_entry_limit_reported_before_any_level_overflows(orc):
     ls = orc.lists(orc.tree(ps.x, ps.y, L), 0.5)
     status, _, _, _ = replay_connectivity(ls, L, limit=50000)
     assert status == "capacity"
+
+
+@pytest.mark.parametrize("case", ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "uniform_20k_L5",
+                                  "duplicates_4k_L4", "scales_3k_L4", "single_box_L0", "uniform_1k_L3"])
+@pytest.mark.parametrize("parent,swap", [(True, "finest"), (True, "all"), (False, "all"), (True, "none")])
+def test_opt_list_indices_in_bounds(orc, case, parent, swap):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    t = orc.tree(ps.x, ps.y, L)
+    levels = {"finest": (L,), "all": tuple(range(1, L + 1)), "none": ()}[swap]
+    ls = orc.lists_opt(t, 0.5, parent=parent, swap_levels=levels)
+    for hint in (0, 1 << 22):
+        status, attempts, bd, caps = replay_connectivity(ls, L, hint, 3 * hint, swaps=swap != "none",
+                                                         hint_x=hint)
+        assert status == "ok"
