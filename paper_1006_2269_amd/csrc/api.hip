@@ -176,6 +176,7 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->tree.x_items.release();
         c->tree.x_itemoff.release();
         c->ev.xpart.release();
+        c->ev.xsum.release();
         for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.work,
                           &e.src})
             b->release();
@@ -364,10 +365,18 @@ int fmm2d_connectivity_opt(fmm2d_ctx *c, double theta, int opt) {
                         "another theta for this point set)",
                         (long long)c->list_limit);
         }
-        if (cap_s >= pool_max && cap_w >= pool_max && (!swaps || cap_x >= pool_max)) break;
-        cap_s = cap_s * 4 < pool_max ? cap_s * 4 : pool_max;
-        cap_w = cap_w * 4 < pool_max ? cap_w * 4 : pool_max;
-        if (swaps) cap_x = cap_x * 4 < pool_max ? cap_x * 4 : pool_max;
+        // grow only the pools that were too small, to at least twice what the
+        // levels built so far needed (the pool offsets read back with the flag)
+        const int64_t need_s = *std::max_element(t.s_off.begin(), t.s_off.end());
+        const int64_t need_w = *std::max_element(t.w_off.begin(), t.w_off.end());
+        const int64_t need_x = *std::max_element(t.x_off.begin(), t.x_off.end());
+        auto grown = [&](int64_t cap, int64_t need) { return std::min(pool_max, std::max(4 * cap, 2 * need)); };
+        const int64_t old_s = cap_s, old_w = cap_w, old_x = cap_x;
+        if (overflow & LIST_GROW_S) cap_s = grown(cap_s, need_s);
+        if (overflow & LIST_GROW_W) cap_w = grown(cap_w, need_w);
+        if (overflow & LIST_GROW_X) cap_x = grown(cap_x, need_x);
+        if (overflow & LIST_GROW_CAND) cap_w = grown(cap_w, need_w);
+        if (cap_s == old_s && cap_w == old_w && cap_x == old_x) break;  // at the 2^34 ceiling
     }
     t.has_lists = false;
     return fail(c, FMM2D_ECAPACITY, "connectivity: interaction lists exceed 2^34 entries");

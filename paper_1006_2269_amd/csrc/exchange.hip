@@ -5,25 +5,36 @@
 //
 //  * target the smaller box (r_b < r_c): the sources of c become a local
 //    expansion about b (P2L), added into B_b before the L2L pass carries it
-//    down:  B_0 += sum q_j log|z_j - c_b|,  B_k += -(q_j / k) (s_b / (z_j - c_b))^k;
+//    down:  B_0 += sum q_j log|z_j - c_b|,  B_k += -(1/k) sum q_j (s_b / (z_j - c_b))^k;
 //  * target the larger box (r_b > r_c): the multipole of c is evaluated at
 //    every point z of b (M2P):  phi(z) += Re[A_0 log(z - c_c) + sum_k A_k (s_c / (z - c_c))^k].
 //
-// Both run in binary64 in every precision mode.
+// Both run in binary64 in every precision mode.  All boxes of a level hold
+// floor or ceil of n / 4^l points, so the work per entry is known per level.
 //
-// P2L is cut into work items of at most PCH source points (a coarse box can
-// hold millions), one wavefront each; the items of a target box are
-// consecutive, and the L2L pass adds their partial expansions in item order,
-// so the result does not depend on scheduling.  M2P gathers per point: one
-// wavefront per leaf walks the X lists of the leaf's ancestors (the same for
-// all its lanes), so every point is written once.
+// P2L work items: on levels of boxes of at most SMALLN points, an item takes
+// up to XE of a target box's P2L entries, one lane per entry walking the
+// entry's points (the entries' loads are issued side by side); on levels of
+// larger boxes, an item takes one entry's points in chunks (at most 32 per
+// entry), one lane per point.  The lanes' sums meet in a transposing
+// butterfly, the items of a box are consecutive and summed per box in item
+// order, and the L2L pass adds that sum into B: results do not depend on
+// scheduling.  M2P gathers per leaf: one wavefront per leaf, one lane per
+// M2P entry of the leaf's ancestors (all levels flattened), the leaf's
+// points taken 16 at a time, each point's sum over the lanes formed by the
+// butterfly; every point is written once.  Orders above 15 (p + 1 > 16) use
+// one lane per point instead.
 #include "evaluate.h"
+#include "wavesum.h"
 
 namespace fmm2d {
 namespace {
 
-constexpr int PCH = 512;   // source points per P2L work item
-constexpr int XT = 16;     // coefficients per pass of the P2L accumulators
+constexpr int SMALLN = 256;  // boxes of at most this many points: one lane per entry
+constexpr int XE = 256;      // P2L entries per item on such levels
+constexpr int PCH = 512;     // least points per chunk on levels of larger boxes
+constexpr int XT = 16;       // coefficients per pass (orders above 15)
+constexpr int MPC = 16;      // leaf points per M2P pass
 
 // Point range [a, e) of box b of level l (its leaves are b 4^(L-l) onwards).
 __device__ inline void box_range(const int32_t *__restrict__ stL, int L, int l, int64_t b, int32_t &a, int32_t &e) {
@@ -32,12 +43,26 @@ __device__ inline void box_range(const int32_t *__restrict__ stL, int L, int l, 
     e = stL[(b + 1) << sh];
 }
 
-// Work items per global box g: for each P2L entry of X(g), ceil(points / PCH).
+// Largest box of level l: ceil(n / 4^l) points.
+__host__ __device__ inline int64_t level_box_max(int64_t n, int l) {
+    return (n + (int64_t(1) << (2 * l)) - 1) >> (2 * l);
+}
+
+// Points per P2L chunk on a level of boxes above SMALLN points: at most 32
+// chunks per entry, at least PCH points each.
+__host__ __device__ inline int64_t level_chunk(int64_t n, int l) {
+    const int64_t m = level_box_max(n, l), c = (m + 31) / 32;
+    return c > PCH ? c : PCH;
+}
+
+// Work items per global box g (P2L entries of X(g): those whose source box
+// is the larger).  An item is int4 (target box, first row position, end row
+// position, first point or -1): -1 covers whole entries of the row range.
 template <bool FILL>
-__global__ void k_x_items(int L, int64_t nbox, const int32_t *__restrict__ xptr_all, const int32_t *__restrict__ xidx,
-                          const int64_t *__restrict__ xoff, const double4 *__restrict__ geom,
-                          const int32_t *__restrict__ stL, int32_t *__restrict__ cnt,
-                          const int32_t *__restrict__ itemoff, int4 *__restrict__ items) {
+__global__ void k_x_items(int L, int64_t n, int64_t nbox, const int32_t *__restrict__ xptr_all,
+                          const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
+                          const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
+                          int32_t *__restrict__ cnt, const int32_t *__restrict__ itemoff, int4 *__restrict__ items) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nbox) return;
     const int l = level_of(g);
@@ -49,31 +74,187 @@ __global__ void k_x_items(int L, int64_t nbox, const int32_t *__restrict__ xptr_
     const int32_t *ptr = xptr_all + ptr_offset(l);
     const int32_t *row = xidx + xoff[l];
     const double4 gb = geom[g];
+    const bool small = level_box_max(n, l) <= SMALLN;
+    const int32_t chunk = (int32_t)level_chunk(n, l);
     int32_t k = FILL ? itemoff[g] : 0;
+    int32_t run = 0, first = -1;  // small boxes: P2L entries in the open item, its first row position
     for (int32_t t = ptr[b]; t < ptr[b + 1]; ++t) {
         const int64_t cg = level_offset(l) + row[t];
         if (!(gb.z < geom[cg].z)) continue;  // M2P entry: handled per point
-        int32_t a, e;
-        box_range(stL, L, l, row[t], a, e);
-        for (int32_t j = a; j < e; j += PCH) {
-            if (FILL) items[k] = make_int4((int32_t)g, (int32_t)cg, j, e < j + PCH ? e : j + PCH);
-            ++k;
+        if (small) {
+            if (run == 0) first = t;
+            if (++run == XE) {
+                if (FILL) items[k] = make_int4((int32_t)g, first, t + 1, -1);
+                ++k;
+                run = 0;
+            }
+        } else {
+            int32_t a, e;
+            box_range(stL, L, l, row[t], a, e);
+            for (int32_t j = a; j < e; j += chunk) {
+                if (FILL) items[k] = make_int4((int32_t)g, t, t + 1, j);
+                ++k;
+            }
         }
+    }
+    if (small && run > 0) {
+        if (FILL) items[k] = make_int4((int32_t)g, first, ptr[b + 1], -1);
+        ++k;
     }
     if (!FILL) cnt[g] = k;
 }
 
-// One wavefront per P2L item: lanes over the item's source points, each lane
-// accumulating XT coefficients at a time, the lanes summed by a butterfly.
-__global__ void __launch_bounds__(256) k_p2l(int p, const int4 *__restrict__ items, const int32_t *__restrict__ nitem,
-                                             const double4 *__restrict__ geom, const double *__restrict__ px,
+// rho = s / w for w = (dx, dy) != 0, and log|w|; the scaled division where
+// |w|^2 could underflow.
+__device__ inline cd recip_scaled(double s, double dx, double dy, double &logw) {
+    const double d2 = dx * dx + dy * dy;
+    if (d2 > 0x1p-960) {
+        logw = 0.5 * log(d2);
+        const double inv = s / d2;
+        return cd{dx * inv, -dy * inv};
+    }
+    logw = log(hypot(dx, dy));
+    return cdiv(cd{s, 0.0}, cd{dx, dy});
+}
+
+// P2L sums of one source point about the target (gb): s[0] += q log|w|,
+// s[k] += q rho^k (k >= 1); the factors -1/k are applied once per item.
+template <int P1>
+__device__ inline void p2l_sums(double x, double y, double q, double4 gb, cd *s) {
+    double lw;
+    const cd rho = recip_scaled(gb.w, x - gb.x, y - gb.y, lw);
+    s[0].re = fma(q, lw, s[0].re);
+    cd pw = rho;
+#pragma unroll
+    for (int k = 1; k < P1; ++k) {
+        s[k].re = fma(q, pw.re, s[k].re);
+        s[k].im = fma(q, pw.im, s[k].im);
+        if (k + 1 < P1) pw = cmul(pw, rho);
+    }
+}
+
+// One wavefront per P2L item, orders p + 1 <= 16.
+template <int P1>
+__global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__restrict__ items,
+                                             const int32_t *__restrict__ nitem, const int32_t *__restrict__ xidx,
+                                             const int64_t *__restrict__ xoff, const double4 *__restrict__ geom,
+                                             const int32_t *__restrict__ stL, const double *__restrict__ px,
                                              const double *__restrict__ py, const double *__restrict__ qs,
-                                             cd *__restrict__ xpart) {
+                                             double *__restrict__ xpart) {
+    static_assert(P1 >= 2 && P1 <= 16, "one pass of 2 P1 <= 32 values");
+    const int64_t it = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (it >= *nitem) return;  // uniform per wavefront
+    __shared__ int32_t x_queue[4][128];
+    const int lane = threadIdx.x % 64;
+    const int4 w = items[it];
+    const double4 gb = geom[w.x];
+    const int l = level_of(w.x);
+    const int32_t *row = xidx + xoff[l];
+    cd s[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) s[k] = cd{0.0, 0.0};
+    if (w.w >= 0) {
+        // one entry, points [w.w, w.w + chunk) of its box, one lane per point
+        int32_t a, e;
+        box_range(stL, L, l, row[w.y], a, e);
+        const int32_t ch = (int32_t)level_chunk(n, l);
+        const int32_t j1 = e < w.w + ch ? e : w.w + ch;
+        for (int32_t j = w.w + lane; j < j1; j += 64) p2l_sums<P1>(px[j], py[j], qs[j], gb, s);
+    } else {
+        // the item's P2L entries (M2P entries in between left out), compacted
+        // 64 at a time through the wavefront's LDS queue, one lane per entry;
+        // each lane walks its entry's points with the next point's loads
+        // issued before the current point is used
+        int32_t *queue = x_queue[threadIdx.x / 64];
+        int32_t qn = 0;
+        for (int32_t t0 = w.y; t0 < w.z || qn > 0; t0 += 64) {
+            if (t0 < w.z) {
+                const int32_t t = t0 + lane;
+                int32_t c = 0;
+                bool ok = false;
+                if (t < w.z) {
+                    c = row[t];
+                    ok = gb.z < geom[level_offset(l) + c].z;
+                }
+                const uint64_t m = __ballot(ok);
+                if (ok) queue[qn + (int)popc_below(m)] = c;
+                qn += (int)__popcll(m);
+                __builtin_amdgcn_wave_barrier();
+                if (qn < 64 && t0 + 64 < w.z) continue;  // fill the queue further
+            }
+            const int take = qn < 64 ? qn : 64;
+            if (lane < take) {
+                int32_t a, e;
+                box_range(stL, L, l, queue[lane], a, e);
+                double xn = px[a], yn = py[a], qn_ = qs[a];
+                for (int32_t j = a; j < e; ++j) {
+                    const double x0 = xn, y0 = yn, q0 = qn_;
+                    const int32_t jn = j + 1 < e ? j + 1 : j;
+                    xn = px[jn];
+                    yn = py[jn];
+                    qn_ = qs[jn];
+                    p2l_sums<P1>(x0, y0, q0, gb, s);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // keep the entries beyond the first 64
+            const int rest = qn - take;
+            const int32_t keep = lane < rest ? queue[take + lane] : 0;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < rest) queue[lane] = keep;
+            qn = rest;
+            __builtin_amdgcn_wave_barrier();
+            if (t0 >= w.z && qn == 0) break;
+        }
+    }
+    double v[32];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[2 * k] = k < P1 ? s[k].re : 0.0;
+        v[2 * k + 1] = k < P1 ? s[k].im : 0.0;
+    }
+    // lane i receives the total of value i / 2: coefficient i / 4, part (i / 2) % 2
+    const double tot = wave_transpose_sum<32>(v, lane);
+    const int vi = lane / 2, k = vi / 2;
+    if ((lane & 1) == 0 && k < P1) xpart[it * 2 * P1 + vi] = k == 0 ? tot : -tot / (double)k;
+}
+
+// The same for orders p + 1 > 16: XT coefficients per pass, one lane per
+// point (entries of an item taken one after the other).
+__device__ inline void p2l_point(double px_, double py_, double q, double4 gb, int k0, int p, double *ar,
+                                 double *ai) {
+    double lw;
+    const cd rho = recip_scaled(gb.w, px_ - gb.x, py_ - gb.y, lw);
+    cd pw{1.0, 0.0};
+    for (int k = 0; k < k0; ++k) pw = cmul(pw, rho);  // rho^k0
+#pragma unroll
+    for (int k = 0; k < XT; ++k) {
+        const int kk = k0 + k;
+        if (kk <= p) {
+            if (kk == 0) {
+                ar[0] = fma(q, lw, ar[0]);
+            } else {
+                ar[k] = fma(q, pw.re, ar[k]);
+                ai[k] = fma(q, pw.im, ai[k]);
+            }
+        }
+        pw = cmul(pw, rho);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_p2l_gen(int p, int L, int64_t n, const int4 *__restrict__ items,
+                                                 const int32_t *__restrict__ nitem, const int32_t *__restrict__ xidx,
+                                                 const int64_t *__restrict__ xoff, const double4 *__restrict__ geom,
+                                                 const int32_t *__restrict__ stL, const double *__restrict__ px,
+                                                 const double *__restrict__ py, const double *__restrict__ qs,
+                                                 double *__restrict__ xpart) {
     const int64_t it = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (it >= *nitem) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
     const int4 w = items[it];
     const double4 gb = geom[w.x];
+    const int l = level_of(w.x);
+    const int32_t *row = xidx + xoff[l];
     const int P1 = p + 1;
     for (int k0 = 0; k0 < P1; k0 += XT) {
         double ar[XT], ai[XT];
@@ -82,27 +263,18 @@ __global__ void __launch_bounds__(256) k_p2l(int p, const int4 *__restrict__ ite
             ar[k] = 0.0;
             ai[k] = 0.0;
         }
-        for (int32_t j = w.z + lane; j < w.w; j += 64) {
-            const double dx = px[j] - gb.x, dy = py[j] - gb.y, q = qs[j];
-            const double d2 = dx * dx + dy * dy;  // > 0: the source lies outside the target's ball
-            const double inv = gb.w / d2;
-            const cd rho = d2 > 0x1p-960 ? cd{dx * inv, -dy * inv} : cdiv(cd{gb.w, 0.0}, cd{dx, dy});
-            cd pw{1.0, 0.0};
-            for (int k = 0; k < k0; ++k) pw = cmul(pw, rho);  // rho^k0
-#pragma unroll
-            for (int k = 0; k < XT; ++k) {
-                const int kk = k0 + k;
-                if (kk <= p) {
-                    if (kk == 0) {
-                        ar[0] += q * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(dx, dy)));
-                    } else {
-                        const double f = -q / (double)kk;
-                        ar[k] = fma(f, pw.re, ar[k]);
-                        ai[k] = fma(f, pw.im, ai[k]);
-                    }
-                }
-                pw = cmul(pw, rho);
+        const int32_t t_end = w.w >= 0 ? w.y + 1 : w.z;
+        for (int32_t t = w.y; t < t_end; ++t) {
+            const int32_t c = row[t];
+            if (!(gb.z < geom[level_offset(l) + c].z)) continue;
+            int32_t a, e;
+            box_range(stL, L, l, c, a, e);
+            if (w.w >= 0) {
+                const int32_t ch = (int32_t)level_chunk(n, l);
+                a = w.w;
+                e = e < w.w + ch ? e : w.w + ch;
             }
+            for (int32_t j = a + lane; j < e; j += 64) p2l_point(px[j], py[j], qs[j], gb, k0, p, ar, ai);
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -113,20 +285,171 @@ __global__ void __launch_bounds__(256) k_p2l(int p, const int4 *__restrict__ ite
             }
         }
 #pragma unroll
-        for (int k = 0; k < XT; ++k)
-            if (lane == k && k0 + k <= p) xpart[it * P1 + k0 + k] = cd{ar[k], ai[k]};
+        for (int k = 0; k < XT; ++k) {
+            const int kk = k0 + k;
+            if (lane == k && kk <= p) {
+                xpart[(it * P1 + kk) * 2] = kk == 0 ? ar[k] : -ar[k] / (double)kk;
+                xpart[(it * P1 + kk) * 2 + 1] = kk == 0 ? ai[k] : -ai[k] / (double)kk;
+            }
+        }
     }
 }
 
-// One wavefront per leaf, one lane per point: the multipoles of the smaller
-// boxes on the X lists of the leaf's ancestors at every level, evaluated at
-// the point and added to its potential (input order).
-__global__ void __launch_bounds__(256) k_m2p(int p, int L, int64_t nleaf, const int32_t *__restrict__ stL,
+// Per target box with items: the sum of its items' partial expansions in
+// item order, one lane per coefficient.
+__global__ void __launch_bounds__(64) k_x_reduce(int p, int64_t nbox, const int32_t *__restrict__ itemoff,
+                                                 const cd *__restrict__ xpart, cd *__restrict__ xsum) {
+    const int64_t g = blockIdx.x;
+    if (g >= nbox) return;
+    const int32_t i0 = itemoff[g], i1 = itemoff[g + 1];
+    if (i0 == i1) return;  // uniform: a box without P2L entries
+    const int lane = threadIdx.x;
+    if (lane > p) return;
+    cd acc{0.0, 0.0};
+    for (int32_t it = i0; it < i1; ++it) acc = cadd(acc, xpart[(int64_t)it * (p + 1) + lane]);
+    xsum[g * (p + 1) + lane] = acc;
+}
+
+// Row ranges of the X lists of a leaf's ancestors (levels 1..L), flattened:
+// entry k of the leaf's stream lies at level lv with pre[lv] <= k <
+// pre[lv + 1], row position start[lv] + k - pre[lv].  The arrays are indexed
+// only by unrolled constants, so they stay in registers.
+constexpr int ML = FMM2D_MAX_LEVELS;
+struct AncestorRows {
+    int32_t start[ML + 1], pre[ML + 2];
+};
+__device__ inline void ancestor_rows(int L, int64_t leaf, const int32_t *__restrict__ xptr_all, AncestorRows &r) {
+    r.pre[0] = 0;
+    r.pre[1] = 0;
+    r.start[0] = 0;
+#pragma unroll
+    for (int l = 1; l <= ML; ++l) {
+        int32_t p0 = 0, p1 = 0;
+        if (l <= L) {
+            const int64_t b = leaf >> (2 * (L - l));
+            const int32_t *ptr = xptr_all + ptr_offset(l);
+            p0 = ptr[b];
+            p1 = ptr[b + 1];
+        }
+        r.start[l] = p0;
+        r.pre[l + 1] = r.pre[l] + (p1 - p0);
+    }
+}
+// The level of stream entry k and its row position.
+__device__ inline int ancestor_entry(const AncestorRows &r, int L, int32_t k, int32_t &t) {
+    int lv = 1;
+    int32_t st = r.start[1], pr = r.pre[1];
+#pragma unroll
+    for (int l = 2; l <= ML; ++l) {
+        if (l <= L && k >= r.pre[l]) {
+            lv = l;
+            st = r.start[l];
+            pr = r.pre[l];
+        }
+    }
+    t = st + (k - pr);
+    return lv;
+}
+
+// M2P, orders p + 1 <= 16: one wavefront per leaf.  The M2P entries of the
+// leaf's ancestors' X lists (P2L entries left out) are compacted 64 at a time
+// through the wavefront's LDS queue, one lane per entry holding its
+// multipole; for each such round the leaf's points are taken MPC at a time,
+// each point's sum over the lanes formed by the butterfly and added to the
+// point's accumulator in LDS (leaves of at most MLEAF points).
+constexpr int MLEAF = 256;
+template <int P1>
+__global__ void __launch_bounds__(256) k_m2p(int L, int64_t nleaf, const int32_t *__restrict__ stL,
                                              const int32_t *__restrict__ xptr_all, const int32_t *__restrict__ xidx,
                                              const int64_t *__restrict__ xoff, const double4 *__restrict__ geom,
                                              const cd *__restrict__ A, const double *__restrict__ px,
                                              const double *__restrict__ py, const int32_t *__restrict__ perm,
                                              double *__restrict__ phi) {
+    __shared__ int64_t m_queue[4][128];
+    __shared__ double m_acc[4][MLEAF];
+    const int64_t leaf = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (leaf >= nleaf) return;  // uniform per wavefront
+    const int lane = threadIdx.x % 64;
+    int64_t *queue = m_queue[threadIdx.x / 64];
+    double *acc = m_acc[threadIdx.x / 64];
+    AncestorRows r;
+    ancestor_rows(L, leaf, xptr_all, r);
+    const int32_t K = r.pre[ML + 1];
+    if (K == 0) return;
+    const int32_t a = stL[leaf], e = stL[leaf + 1];
+    for (int32_t i = lane; i < e - a; i += 64) acc[i] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    int qn = 0;
+    for (int32_t k0 = 0; k0 < K || qn > 0; k0 += 64) {
+        if (k0 < K) {
+            const int32_t k = k0 + lane;
+            int32_t t;
+            const int lv = ancestor_entry(r, L, k, t);
+            bool ok = false;
+            int64_t cg = 0;
+            if (k < K) {
+                cg = level_offset(lv) + xidx[xoff[lv] + t];
+                const double rb = geom[level_offset(lv) + (leaf >> (2 * (L - lv)))].z;
+                ok = rb > geom[cg].z;  // the target box is the larger: M2P (else P2L, handled by k_p2l)
+            }
+            const uint64_t m = __ballot(ok);
+            if (ok) queue[qn + (int)popc_below(m)] = cg;
+            qn += (int)__popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            if (qn < 64 && k0 + 64 < K) continue;  // fill the queue further
+        }
+        const int take = qn < 64 ? qn : 64;
+        const bool act = lane < take;
+        cd Ac[P1];
+        double4 gc = make_double4(0.0, 0.0, 1.0, 1.0);
+        if (act) {
+            const int64_t cg = queue[lane];
+            gc = geom[cg];
+#pragma unroll
+            for (int q = 0; q < P1; ++q) Ac[q] = A[cg * P1 + q];
+        }
+        for (int32_t pc = a; pc < e; pc += MPC) {
+            double v[MPC];
+#pragma unroll
+            for (int j = 0; j < MPC; ++j) {
+                const int32_t i = pc + j < e ? pc + j : e - 1;  // points past the leaf repeat its last
+                double val = 0.0;
+                if (act) {
+                    double lw;
+                    const cd rho = recip_scaled(gc.w, px[i] - gc.x, py[i] - gc.y, lw);
+                    cd sacc = Ac[P1 - 1];
+#pragma unroll
+                    for (int q = P1 - 2; q >= 1; --q) sacc = cadd(cmul(sacc, rho), Ac[q]);
+                    sacc = cmul(sacc, rho);
+                    val = Ac[0].re * lw + sacc.re;
+                }
+                v[j] = val;
+            }
+            // lane i receives the sum over the lanes of point i / 4
+            const double tot = wave_transpose_sum<MPC>(v, lane);
+            const int j = lane / 4;
+            if ((lane & 3) == 0 && pc + j < e) acc[pc - a + j] += tot;
+            __builtin_amdgcn_wave_barrier();
+        }
+        // keep the entries beyond the first 64
+        const int rest = qn - take;
+        const int64_t keep = lane < rest ? queue[take + lane] : 0;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) queue[lane] = keep;
+        qn = rest;
+        __builtin_amdgcn_wave_barrier();
+        if (k0 >= K && qn == 0) break;
+    }
+    for (int32_t i = lane; i < e - a; i += 64) phi[perm[a + i]] += acc[i];
+}
+
+// M2P for orders p + 1 > 16: one lane per point of the leaf.
+__global__ void __launch_bounds__(256) k_m2p_gen(int p, int L, int64_t nleaf, const int32_t *__restrict__ stL,
+                                                 const int32_t *__restrict__ xptr_all,
+                                                 const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
+                                                 const double4 *__restrict__ geom, const cd *__restrict__ A,
+                                                 const double *__restrict__ px, const double *__restrict__ py,
+                                                 const int32_t *__restrict__ perm, double *__restrict__ phi) {
     const int64_t leaf = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (leaf >= nleaf) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
@@ -145,17 +468,15 @@ __global__ void __launch_bounds__(256) k_m2p(int p, int L, int64_t nleaf, const 
             for (int32_t t = ptr[b]; t < ptr[b + 1]; ++t) {
                 const int64_t cg = level_offset(l) + row[t];
                 const double4 gc = geom[cg];
-                if (!(gb.z > gc.z)) continue;  // P2L entry: handled by k_p2l
+                if (!(gb.z > gc.z)) continue;  // P2L entry
                 const cd *Ac = A + cg * P1;
                 // inactive lanes evaluate at a point one scale away (finite)
-                const double dx = act ? zx - gc.x : gc.w, dy = act ? zy - gc.y : 0.0;
-                const double d2 = dx * dx + dy * dy;
-                const double inv = gc.w / d2;
-                const cd rho = d2 > 0x1p-960 ? cd{dx * inv, -dy * inv} : cdiv(cd{gc.w, 0.0}, cd{dx, dy});
+                double lw;
+                const cd rho = recip_scaled(gc.w, act ? zx - gc.x : gc.w, act ? zy - gc.y : 0.0, lw);
                 cd s = Ac[p];
                 for (int k = p - 1; k >= 1; --k) s = cadd(cmul(s, rho), Ac[k]);
-                s = p >= 1 ? cmul(s, rho) : cd{0.0, 0.0};
-                acc += Ac[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(dx, dy))) + s.re;
+                s = cmul(s, rho);
+                acc += Ac[0].re * lw + s.re;
             }
         }
         if (act) phi[perm[i]] += acc;
@@ -171,11 +492,12 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     if (!(t.opt & (FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL)) || L < 1) return hipSuccess;
     if (t.x_off[L + 1] == t.x_off[1]) return hipSuccess;  // no exchanged pair
     const int64_t nbox = level_offset(L + 1);
-    // every box of level l holds floor or ceil of n / 4^l points
+    // at most one item per entry on levels of small boxes, the chunks of one
+    // entry on the others
     int64_t bound = 0;
     for (int l = 1; l <= L; ++l) {
-        const int64_t maxpts = (t.n + (int64_t(1) << (2 * l)) - 1) >> (2 * l);
-        bound += (t.x_off[l + 1] - t.x_off[l]) * ((maxpts + PCH - 1) / PCH);
+        const int64_t maxpts = level_box_max(t.n, l), ch = level_chunk(t.n, l);
+        bound += (t.x_off[l + 1] - t.x_off[l]) * (maxpts <= SMALLN ? 1 : (maxpts + ch - 1) / ch);
     }
     FMM2D_TRY(c->scr.segcnt.ensure(sizeof(int32_t) * nbox));
     FMM2D_TRY(t.x_itemoff.ensure(sizeof(int32_t) * (nbox + 1)));
@@ -184,12 +506,12 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);  // X pool offset of each level
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     const double4 *geom = t.geom.as<double4>();
-    hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, nbox, xptr, xidx,
-                       xoff, geom, stL, c->scr.segcnt.as<int32_t>(), nullptr, nullptr);
+    hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
+                       xidx, xoff, geom, stL, c->scr.segcnt.as<int32_t>(), nullptr, nullptr);
     FMM2D_TRY(hipGetLastError());
     FMM2D_TRY(scan_exclusive(c, c->scr.segcnt.as<int32_t>(), nbox, t.x_itemoff.as<int32_t>()));
-    hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, nbox, xptr, xidx,
-                       xoff, geom, stL, nullptr, t.x_itemoff.as<int32_t>(), t.x_items.as<int4>());
+    hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
+                       xidx, xoff, geom, stL, nullptr, t.x_itemoff.as<int32_t>(), t.x_items.as<int4>());
     FMM2D_TRY(hipGetLastError());
     t.x_item_bound = bound;
     t.x_ready = true;
@@ -205,11 +527,32 @@ hipError_t p2l_all(fmm2d_ctx *c, int p) {
     if (!t.x_ready) return hipSuccess;
     EvalState &e = c->ev;
     const int64_t bound = t.x_item_bound > 0 ? t.x_item_bound : 1;
-    FMM2D_TRY(e.xpart.ensure(sizeof(cd) * bound * (p + 1)));
     const int64_t nbox = level_offset(t.L + 1);
-    hipLaunchKernelGGL(k_p2l, dim3(grid_for(bound, 4)), dim3(256), 0, c->stream, p, t.x_items.as<int4>(),
-                       t.x_itemoff.as<int32_t>() + nbox, t.geom.as<double4>(), t.px.as<double>(), t.py.as<double>(),
-                       e.qs.as<double>(), e.xpart.as<cd>());
+    FMM2D_TRY(e.xpart.ensure(sizeof(cd) * bound * (p + 1)));
+    FMM2D_TRY(e.xsum.ensure(sizeof(cd) * nbox * (p + 1)));
+    const dim3 grid(grid_for(bound, 4)), block(256);
+    const int32_t *nitem = t.x_itemoff.as<int32_t>() + nbox;
+    const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (t.L + 2);
+    const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * t.L);
+    double *xpart = reinterpret_cast<double *>(e.xpart.as<cd>());
+    switch (p + 1) {
+#define FMM2D_P2L(P1)                                                                                             \
+    case P1:                                                                                                      \
+        hipLaunchKernelGGL(k_p2l<P1>, grid, block, 0, c->stream, t.L, t.n, t.x_items.as<int4>(), nitem,           \
+                           t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), stL, t.px.as<double>(),              \
+                           t.py.as<double>(), e.qs.as<double>(), xpart);                                          \
+        break;
+        FMM2D_P2L(2) FMM2D_P2L(3) FMM2D_P2L(4) FMM2D_P2L(5) FMM2D_P2L(6) FMM2D_P2L(7) FMM2D_P2L(8) FMM2D_P2L(9)
+        FMM2D_P2L(10) FMM2D_P2L(11) FMM2D_P2L(12) FMM2D_P2L(13) FMM2D_P2L(14) FMM2D_P2L(15) FMM2D_P2L(16)
+#undef FMM2D_P2L
+        default:
+            hipLaunchKernelGGL(k_p2l_gen, grid, block, 0, c->stream, p, t.L, t.n, t.x_items.as<int4>(), nitem,
+                               t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), stL, t.px.as<double>(),
+                               t.py.as<double>(), e.qs.as<double>(), xpart);
+    }
+    FMM2D_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_x_reduce, dim3((unsigned)nbox), dim3(64), 0, c->stream, p, nbox, t.x_itemoff.as<int32_t>(),
+                       e.xpart.as<cd>(), e.xsum.as<cd>());
     return hipGetLastError();
 }
 
@@ -218,10 +561,25 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
     if (!t.x_ready) return hipSuccess;
     const int L = t.L;
     const int64_t nleaf = int64_t(1) << (2 * L);
-    hipLaunchKernelGGL(k_m2p, dim3(grid_for(nleaf, 4)), dim3(256), 0, c->stream, p, L, nleaf,
-                       t.starts.as<int32_t>() + depth_offset(2 * L), t.xptr.as<int32_t>(), t.xidx.as<int32_t>(),
-                       t.pool_state.as<int64_t>() + 2 * (L + 2), t.geom.as<double4>(), c->ev.A.as<cd>(),
-                       t.px.as<double>(), t.py.as<double>(), t.perm.as<int32_t>(), phi);
+    const dim3 grid(grid_for(nleaf, 4)), block(256);
+    const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
+    const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);
+    const int64_t maxleaf = level_box_max(t.n, L);
+    switch (maxleaf <= MLEAF ? p + 1 : 0) {
+#define FMM2D_M2P(P1)                                                                                             \
+    case P1:                                                                                                      \
+        hipLaunchKernelGGL(k_m2p<P1>, grid, block, 0, c->stream, L, nleaf, stL, t.xptr.as<int32_t>(),            \
+                           t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), c->ev.A.as<cd>(), t.px.as<double>(), \
+                           t.py.as<double>(), t.perm.as<int32_t>(), phi);                                         \
+        break;
+        FMM2D_M2P(2) FMM2D_M2P(3) FMM2D_M2P(4) FMM2D_M2P(5) FMM2D_M2P(6) FMM2D_M2P(7) FMM2D_M2P(8) FMM2D_M2P(9)
+        FMM2D_M2P(10) FMM2D_M2P(11) FMM2D_M2P(12) FMM2D_M2P(13) FMM2D_M2P(14) FMM2D_M2P(15) FMM2D_M2P(16)
+#undef FMM2D_M2P
+        default:
+            hipLaunchKernelGGL(k_m2p_gen, grid, block, 0, c->stream, p, L, nleaf, stL, t.xptr.as<int32_t>(),
+                               t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), c->ev.A.as<cd>(),
+                               t.px.as<double>(), t.py.as<double>(), t.perm.as<int32_t>(), phi);
+    }
     return hipGetLastError();
 }
 

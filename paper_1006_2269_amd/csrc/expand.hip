@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(64) k_m2m(int l, int p, const double4 *__restr
 __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restrict__ geom, cd *__restrict__ B,
                                             const double *__restrict__ binom, const int32_t *__restrict__ segoff,
                                             const cd *__restrict__ part, const int32_t *__restrict__ xoff,
-                                            const cd *__restrict__ xpart) {
+                                            const cd *__restrict__ xsum) {
     __shared__ cd Bp[64];
     __shared__ cd dp[64];
     const int64_t cidx = blockIdx.x;  // child within level l+1
@@ -201,10 +201,8 @@ __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restr
             for (int32_t sg = s0; sg < s1; ++sg) acc = cadd(acc, part[(int64_t)sg * (p + 1) + lane]);
             v = cadd(v, acc);
         }
-        if (xoff) {
-            // P2L partials of the exchanged-roles pairs, in item order
-            for (int32_t it = xoff[cbox]; it < xoff[cbox + 1]; ++it) v = cadd(v, xpart[(int64_t)it * (p + 1) + lane]);
-        }
+        // the P2L sum of the exchanged-roles pairs (boxes with P2L items)
+        if (xoff && xoff[cbox + 1] > xoff[cbox]) v = cadd(v, xsum[cbox * (p + 1) + lane]);
         B[cbox * (p + 1) + lane] = v;
     }
 }
@@ -317,7 +315,7 @@ __global__ void __launch_bounds__(COARSE) k_m2m_coarse(int lc, const double4 *__
 template <int P1>
 __device__ inline void l2l_one(int l, int64_t cidx, const double4 *__restrict__ geom, cd *__restrict__ B,
                                const int32_t *__restrict__ segoff, const cd *__restrict__ part,
-                               const int32_t *__restrict__ xoff, const cd *__restrict__ xpart) {
+                               const int32_t *__restrict__ xoff, const cd *__restrict__ xsum) {
     constexpr Fact<P1> F;
     const int64_t cbox = level_offset(l + 1) + cidx;
     const int64_t pbox = level_offset(l) + (cidx >> 2);
@@ -352,12 +350,10 @@ __device__ inline void l2l_one(int l, int64_t cidx, const double4 *__restrict__ 
 #pragma unroll
         for (int k = 0; k < P1; ++k) out[k] = cadd(out[k], part[(int64_t)sg * P1 + k]);
     }
-    if (xoff) {
-        // P2L partials of the exchanged-roles pairs, in item order
-        for (int32_t it = xoff[cbox]; it < xoff[cbox + 1]; ++it) {
+    // the P2L sum of the exchanged-roles pairs (boxes with P2L items)
+    if (xoff && xoff[cbox + 1] > xoff[cbox]) {
 #pragma unroll
-            for (int k = 0; k < P1; ++k) out[k] = cadd(out[k], xpart[(int64_t)it * P1 + k]);
-        }
+        for (int k = 0; k < P1; ++k) out[k] = cadd(out[k], xsum[cbox * P1 + k]);
     }
 #pragma unroll
     for (int k = 0; k < P1; ++k) B[cbox * P1 + k] = out[k];
@@ -367,9 +363,9 @@ template <int P1>
 __global__ void __launch_bounds__(64) k_l2l_box(int l, int64_t nchild, const double4 *__restrict__ geom,
                                                 cd *__restrict__ B, const int32_t *__restrict__ segoff,
                                                 const cd *__restrict__ part, const int32_t *__restrict__ xoff,
-                                                const cd *__restrict__ xpart) {
+                                                const cd *__restrict__ xsum) {
     const int64_t cidx = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (cidx < nchild) l2l_one<P1>(l, cidx, geom, B, segoff, part, xoff, xpart);
+    if (cidx < nchild) l2l_one<P1>(l, cidx, geom, B, segoff, part, xoff, xsum);
 }
 
 // L2L into the children of levels 1, ..., lc + 1 (at most COARSE each) in one
@@ -378,10 +374,10 @@ template <int P1>
 __global__ void __launch_bounds__(COARSE) k_l2l_coarse(int lc, const double4 *__restrict__ geom, cd *__restrict__ B,
                                                        const int32_t *__restrict__ segoff,
                                                        const cd *__restrict__ part, const int32_t *__restrict__ xoff,
-                                                       const cd *__restrict__ xpart) {
+                                                       const cd *__restrict__ xsum) {
     for (int l = 0; l <= lc; ++l) {
         if ((int64_t)threadIdx.x < (int64_t(1) << (2 * (l + 1))))
-            l2l_one<P1>(l, threadIdx.x, geom, B, segoff, part, xoff, xpart);
+            l2l_one<P1>(l, threadIdx.x, geom, B, segoff, part, xoff, xsum);
         __threadfence();
         __syncthreads();
     }
@@ -491,14 +487,14 @@ hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
     const double4 *geom = t.geom.as<double4>();
     const int32_t *segoff = t.m2l_all.segoff.as<int32_t>();
     const int32_t *xoff = exchange_item_offsets(c);
-    const cd *xpart = xoff ? e.xpart.as<cd>() : nullptr;
+    const cd *xsum = xoff ? e.xsum.as<cd>() : nullptr;
     if (p + 1 <= 16) {
         const dim3 grid(grid_for(nc, 64)), block(64);
         switch (p + 1) {
 #define FMM2D_L2L(P1)                                                                                            \
     case P1:                                                                                                     \
         hipLaunchKernelGGL(k_l2l_box<P1>, grid, block, 0, c->stream, l, nc, geom, e.B.as<cd>(), segoff,         \
-                           e.part.as<cd>(), xoff, xpart);                                                        \
+                           e.part.as<cd>(), xoff, xsum);                                                        \
         break;
             FMM2D_L2L(2) FMM2D_L2L(3) FMM2D_L2L(4) FMM2D_L2L(5) FMM2D_L2L(6) FMM2D_L2L(7) FMM2D_L2L(8)
             FMM2D_L2L(9) FMM2D_L2L(10) FMM2D_L2L(11) FMM2D_L2L(12) FMM2D_L2L(13) FMM2D_L2L(14) FMM2D_L2L(15)
@@ -508,7 +504,7 @@ hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
         }
     } else {
         hipLaunchKernelGGL(k_l2l, dim3((unsigned)nc), dim3(64), 0, c->stream, l, p, geom, e.B.as<cd>(),
-                           e.binom.as<double>(), segoff, e.part.as<cd>(), xoff, xpart);
+                           e.binom.as<double>(), segoff, e.part.as<cd>(), xoff, xsum);
     }
     return hipGetLastError();
 }
@@ -525,9 +521,9 @@ hipError_t l2l_pass(fmm2d_ctx *c, int p) {
         const double4 *geom = t.geom.as<double4>();
         const int32_t *segoff = t.m2l_all.segoff.as<int32_t>();
         const int32_t *xoff = exchange_item_offsets(c);
-        const cd *xpart = xoff ? e.xpart.as<cd>() : nullptr;
+        const cd *xsum = xoff ? e.xsum.as<cd>() : nullptr;
         switch (p + 1) {
-#define FMM2D_L2LC(P1)                                                                                                  case P1:                                                                                                                hipLaunchKernelGGL(k_l2l_coarse<P1>, dim3(1), dim3(COARSE), 0, c->stream, lc, geom, e.B.as<cd>(), segoff,                            e.part.as<cd>(), xoff, xpart);                                                                                break;
+#define FMM2D_L2LC(P1)                                                                                                  case P1:                                                                                                                hipLaunchKernelGGL(k_l2l_coarse<P1>, dim3(1), dim3(COARSE), 0, c->stream, lc, geom, e.B.as<cd>(), segoff,                            e.part.as<cd>(), xoff, xsum);                                                                                break;
             FMM2D_L2LC(2) FMM2D_L2LC(3) FMM2D_L2LC(4) FMM2D_L2LC(5) FMM2D_L2LC(6) FMM2D_L2LC(7) FMM2D_L2LC(8)
             FMM2D_L2LC(9) FMM2D_L2LC(10) FMM2D_L2LC(11) FMM2D_L2LC(12) FMM2D_L2LC(13) FMM2D_L2LC(14)
             FMM2D_L2LC(15) FMM2D_L2LC(16)

@@ -110,6 +110,7 @@ struct EvalState {
     DevBuf npart;           // near-field partial sums (written on the second stream while the far field runs)
     DevBuf gpart;           // near-field gradient partial sums (fmm2d_evaluate_field)
     DevBuf xpart;           // P2L partial expansions of the exchanged-roles items
+    DevBuf xsum;            // their sum per target box (boxes with items)
 };
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream
@@ -220,8 +221,10 @@ hipError_t mlp_adam(fmm2d_ctx *c, float *P, float *m, float *v, const float *g, 
 hipError_t tree_sort(fmm2d_ctx *c, int64_t n);
 hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y, bool sorted = false);
 // lists.hip
-// overflow: 0 ok, 1 a pool was too small (grow and retry), 2 a level exceeds `limit` entries;
+// overflow: 0 ok, 2 a level exceeds `limit` entries, else the LIST_GROW_* bits of the pools
+// to grow before a retry;
 // opt: FMM2D_OPT_* (0: the plain lists)
+constexpr int LIST_GROW_S = 4, LIST_GROW_W = 8, LIST_GROW_X = 16, LIST_GROW_CAND = 32;
 hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s, int64_t cap_w, int64_t cap_x,
                               int64_t limit, int *overflow);
 // expand.hip

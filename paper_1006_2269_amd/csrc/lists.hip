@@ -247,9 +247,10 @@ __device__ inline void box_lists(int l, int L, int opt, double theta, const doub
 }
 
 // Pool offsets of level l + 1, and the checks that guard the next level:
-// flag 1 when a pool is too small (the host retries with larger pools),
-// flag 2 when level l + 1's candidates, 16 |S_l| (each becomes one entry of
-// S or W), exceed the entry limit.  A flagged level is not examined, so no
+// the LIST_GROW_* bits of the pools that are too small (the host retries
+// with larger ones; LIST_GROW_CAND: level l + 1's candidates exceed the free
+// space, which bounds the decision words), 2 when level l + 1's candidates,
+// 16 |S_l| (each becomes at most one entry), exceed the entry limit.  A flagged level is not examined, so no
 // int32 prefix sum can wrap and no decision bit lies beyond the buffer
 // (sized for cap_s + cap_w candidates).
 __device__ inline void advance_pools(int l, int L, int64_t nb, const int32_t *sptr_cur, const int32_t *wptr_cur,
@@ -262,14 +263,18 @@ __device__ inline void advance_pools(int l, int L, int64_t nb, const int32_t *sp
     pool_state[l + 1] = so;
     pool_state[(L + 2) + l + 1] = wo;
     pool_state[slot_x(L, l + 1)] = xo;
-    if (so > cap_s || wo > cap_w || xo > cap_x) {
-        pool_state[slot_flag(L)] = 1;
+    // which pool is too small (the host grows only those), or the next
+    // level's candidates exceed the entry limit (2)
+    const int64_t grow = (so > cap_s ? LIST_GROW_S : 0) | (wo > cap_w ? LIST_GROW_W : 0) |
+                         (xo > cap_x ? LIST_GROW_X : 0);
+    if (grow) {
+        pool_state[slot_flag(L)] = grow;
         return;
     }
     if (l < L) {
         const int64_t cand = 16 * (int64_t)sptr_cur[nb];
         if (cand > limit) pool_state[slot_flag(L)] = 2;
-        else if (cand > (cap_s - so) + (cap_w - wo)) pool_state[slot_flag(L)] = 1;
+        else if (cand > (cap_s - so) + (cap_w - wo)) pool_state[slot_flag(L)] = LIST_GROW_CAND;
     }
 }
 

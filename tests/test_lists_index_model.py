@@ -51,6 +51,7 @@ class Bounds:
 
 
 VFLAG = 1 << 30
+GROW_S, GROW_W, GROW_X, GROW_CAND = 4, 8, 16, 32
 
 
 def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0):
@@ -72,7 +73,7 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0):
     leaf_rows = n_leaf + 1
     # buffers as sized by the host
     if L >= 1 and 16 > limit:
-        return 2, s_off, got_s, got_w
+        return 2, s_off, got_s, got_w, got_x, (s_off, w_off, x_off)
     words_cap = (cap_s + cap_w + 63) // 64 + 1
     ntile = (words_cap + WS_TILE - 1) // WS_TILE
     K = 0
@@ -89,15 +90,16 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0):
         s_off[l + 1] = so
         w_off[l + 1] = wo
         x_off[l + 1] = xo
-        if so > cap_s or wo > cap_w or xo > cap_x:
-            flag = 1
+        grow = (GROW_S if so > cap_s else 0) | (GROW_W if wo > cap_w else 0) | (GROW_X if xo > cap_x else 0)
+        if grow:
+            flag = grow
             return
         if l < L:
             cand = 16 * nS[l]
             if cand > limit:
                 flag = 2
             elif cand > (cap_s - so) + (cap_w - wo):
-                flag = 1
+                flag = GROW_CAND
 
     for l in range(1, L + 1):
         if flag:
@@ -186,7 +188,7 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0):
         X = np.empty(nX[l], np.int64)
         X[posX[exch]] = cbox[exch]
         got_s[l], got_w[l], got_x[l] = S, W, X
-    return flag, s_off, got_s, got_w, got_x
+    return flag, s_off, got_s, got_w, got_x, (s_off, w_off, x_off)
 
 
 def split_w(W):
@@ -206,7 +208,7 @@ def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX, swaps=False,
     bd = Bounds()
     opt = getattr(ls, "vptr", None) is not None
     for attempt in range(16):
-        flag, s_off, got_s, got_w, got_x = _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x)
+        flag, s_off, got_s, got_w, got_x, offs = _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x)
         if flag == 0:
             for l in range(L + 1):
                 assert np.array_equal(got_s[l], ls.sidx[l]), "replayed S list of level %d differs" % l
@@ -218,12 +220,18 @@ def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX, swaps=False,
             return "ok", attempt + 1, bd, (cap_s, cap_w, cap_x)
         if flag == 2:
             return "capacity", attempt + 1, bd, (cap_s, cap_w, cap_x)
-        if cap_s >= POOL_MAX and cap_w >= POOL_MAX and (not swaps or cap_x >= POOL_MAX):
+        # only the flagged pools grow, to at least twice the entries so far
+        need_s, need_w, need_x = (max(o) for o in offs)
+        grown = lambda cap, need: min(POOL_MAX, max(4 * cap, 2 * need))
+        old = (cap_s, cap_w, cap_x)
+        if flag & GROW_S:
+            cap_s = grown(cap_s, need_s)
+        if flag & (GROW_W | GROW_CAND):
+            cap_w = grown(cap_w, need_w)
+        if flag & GROW_X:
+            cap_x = grown(cap_x, need_x)
+        if (cap_s, cap_w, cap_x) == old:
             break
-        cap_s = min(cap_s * 4, POOL_MAX)
-        cap_w = min(cap_w * 4, POOL_MAX)
-        if swaps:
-            cap_x = min(cap_x * 4, POOL_MAX)
     return "nomem", 16, bd, (cap_s, cap_w, cap_x)
 
 
