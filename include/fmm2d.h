@@ -114,6 +114,19 @@ const char *fmm2d_last_error(const fmm2d_ctx *ctx);
  * for the work queued so far on the old one. */
 int fmm2d_set_stream(fmm2d_ctx *ctx, void *stream);
 
+/* Options of the trees built from now on (fmm2d_build_tree,
+ * fmm2d_select_build_tree), combined with |:
+ *   FMM2D_TREE_SHRINK  the ball of each box in Criterion 2.1, and the centre
+ *                      and scale of its expansions, are those of its points'
+ *                      bounding box (centre, half diagonal) instead of its
+ *                      tiling rectangle: the smallest axis-aligned box
+ *                      around the points (Criterion 2.1 is stated for any
+ *                      balls enclosing the two sets).  The boxes and their
+ *                      points are unchanged.
+ * FMM2D_EINVAL for unknown bits. */
+#define FMM2D_TREE_SHRINK 1
+int fmm2d_set_tree_options(fmm2d_ctx *ctx, int flags);
+
 /* Builds the balanced pyramid (Section 4 and Fig. 1.1).  x, y: device,
  * binary64 [n], every value finite with |value| <= 2^500.  levels: 0..13,
  * with n >= 4^levels (every box must split) and n <= 2^31 - 1.
@@ -169,6 +182,9 @@ int fmm2d_connectivity_opt(fmm2d_ctx *ctx, double theta, int opt);
  * coefficients per expansion), 1 <= p <= 63, in precision `mode`
  * (FMM2D_MODE_*).  q: device binary64 [n] charges in input order.  phi:
  * device binary64 [n] output in input order.  Needs tree and lists.
+ * The FP32 modes (FP32, BF16X3, FP32_ACC64) compute on offsets from leaf
+ * centres and need the root box's half diagonal in [2^-60, 2^56] (or 0):
+ * FMM2D_EINVAL otherwise (FMM2D_MODE_FP64 has no such limit).
  * Asynchronous on the stream. */
 int fmm2d_evaluate(fmm2d_ctx *ctx, const double *q, int p, int mode, double *phi);
 
@@ -317,6 +333,11 @@ int fmm2d_get_leaf_start(fmm2d_ctx *ctx, int32_t *start);
  * by level, level l starting at box (4^l - 1)/3. */
 int fmm2d_get_rects(fmm2d_ctx *ctx, double *rects);
 
+/* Device output binary64 [nbox][4]: (cx, cy, r, scale) of every box: the
+ * centre and radius of its ball (Criterion 2.1) and the scale of its
+ * expansions (r, or 1 for a box of zero size). */
+int fmm2d_get_geometry(fmm2d_ctx *ctx, double *geom);
+
 /* Host outputs: number of strong and weak list entries at `level`. */
 int fmm2d_list_sizes(const fmm2d_ctx *ctx, int level, int64_t *n_strong, int64_t *n_weak);
 
@@ -350,7 +371,9 @@ int fmm2d_get_xlists(fmm2d_ctx *ctx, int level, int64_t *nx, int32_t *xptr, int3
 #define FMM2D_PHASE_NEAR_KERNEL  9  /* the near-field kernel (in LEAF)       */
 #define FMM2D_PHASE_M2L_KERNEL  10  /* the M2L kernel, all levels (in M2L)   */
 #define FMM2D_PHASE_EXCHANGE    11  /* P2L and M2P of exchanged-roles pairs  */
-#define FMM2D_NPHASE       12
+#define FMM2D_PHASE_P2L_KERNEL  12  /* the P2L kernel (in EXCHANGE)          */
+#define FMM2D_PHASE_M2P_KERNEL  13  /* the M2P kernel (in EXCHANGE)          */
+#define FMM2D_NPHASE       14
 
 /* enable = 1 clears the accumulated timings and starts recording HIP events
  * on the context stream around each phase; enable = 0 stops recording. */

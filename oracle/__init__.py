@@ -12,6 +12,9 @@ multipole methods":
 
 * ``direct``     -- the interaction sum (1.1) with charges and G = log|x - y|.
 * ``tree``       -- the balanced median-split pyramid (Section 4, Fig. 1.1).
+* ``shrink``     -- the same boxes with the balls of Criterion 2.1 drawn
+                    around each box's points (their bounding box) instead of
+                    the tiling rectangle.
 * ``geometry``   -- centre / enclosing-ball radius of each box, the balls of
                     Criterion 2.1.
 * ``lists``      -- the recursive strong/weak connectivity rule (Section 4)
@@ -190,6 +193,30 @@ def tree(x, y, levels: int) -> Tree:
         raise RuntimeError("orc_tree failed: %d" % rc)
     geom = geometry(rects)
     return Tree(n, levels, perm, start, rects, geom)
+
+
+def point_rects(t: Tree, x, y) -> np.ndarray:
+    """(xmin, xmax, ymin, ymax) of the points of every box of every level
+    (a box's points are the leaves b 4^(L-l) .. (b+1) 4^(L-l) - 1)."""
+    x, y = _f64(x)[t.perm], _f64(y)[t.perm]
+    out = np.empty((level_offset(t.levels + 1), 4), dtype=np.float64)
+    for l in range(t.levels + 1):
+        nb, span = 4 ** l, 4 ** (t.levels - l)
+        st = t.leaf_start[::span]
+        for b in range(nb):
+            a, e = st[b], st[b + 1]
+            out[level_offset(l) + b] = (x[a:e].min(), x[a:e].max(), y[a:e].min(), y[a:e].max())
+    return out
+
+
+def shrink(t: Tree, x, y) -> Tree:
+    """The tree with each box's ball drawn around its points: centre and half
+    diagonal of the points' bounding box (the rectangles stay the tiling
+    ones).  Criterion 2.1 holds for any balls enclosing the two point sets;
+    the tiling rectangle's ball is one choice, this one is the smallest
+    axis-aligned one."""
+    pr = point_rects(t, x, y)
+    return Tree(t.n, t.levels, t.perm, t.leaf_start, t.rects, geometry(pr))
 
 
 def geometry(rects) -> np.ndarray:

@@ -15,6 +15,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECAPACITY = 0, -1, -2, -3, -4, -5
 MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp32_acc64": 3}
 OPT_PARENT, OPT_SWAP_FINEST, OPT_SWAP_ALL = 1, 2, 4
 VFLAG = 0x40000000
+TREE_SHRINK = 1
 
 _lib = None
 
@@ -47,6 +48,8 @@ SIGNATURES = [
     ("fmm2d_get_perm", I32, [P, P]),
     ("fmm2d_get_leaf_start", I32, [P, P]),
     ("fmm2d_get_rects", I32, [P, P]),
+    ("fmm2d_get_geometry", I32, [P, P]),
+    ("fmm2d_set_tree_options", I32, [P, I32]),
     ("fmm2d_list_sizes", I32, [P, I32, PI64, PI64]),
     ("fmm2d_get_lists", I32, [P, I32, P, P, P, P]),
     ("fmm2d_get_xlists", I32, [P, I32, PI64, P, P]),
@@ -69,7 +72,7 @@ NFEAT = 92
 SELECT_HEADER = 194
 
 PHASES = ["tree", "lists", "upward", "m2l", "l2l", "leaf", "other", "judge", "select", "near_kernel",
-          "m2l_kernel", "exchange"]
+          "m2l_kernel", "exchange", "p2l_kernel", "m2p_kernel"]
 
 
 def load():

@@ -159,7 +159,7 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         }
         TreeState &t = c->tree;
         for (DevBuf *b : {&t.xsorted, &t.ysorted, &t.xorder, &t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1,
-                          &t.starts, &t.rects, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
+                          &t.starts, &t.rects, &t.prect, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
                           &t.sidx, &t.widx, &t.xptr, &t.xidx, &t.cnt_x, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d, &t.bits,
                           &t.owner0, &t.owner1, &t.selfpos, &t.trans, &t.spart})
             b->release();
@@ -211,6 +211,14 @@ int fmm2d_set_stream(fmm2d_ctx *c, void *stream) {
     if (ev) (void)hipEventDestroy(ev);
     if (e != hipSuccess) return hip_fail(c, e, "set_stream");
     c->stream = s;
+    return FMM2D_OK;
+}
+
+int fmm2d_set_tree_options(fmm2d_ctx *c, int flags) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (flags & ~FMM2D_TREE_SHRINK) return fail(c, FMM2D_EINVAL, "set_tree_options: unknown bits 0x%x", flags);
+    c->tree_opt = flags;
     return FMM2D_OK;
 }
 
@@ -351,6 +359,13 @@ int fmm2d_connectivity_opt(fmm2d_ctx *c, double theta, int opt) {
                 e = build_schedules(c);
             }
             if (e != hipSuccess) return hip_fail(c, e, "connectivity");
+            // the root box's half diagonal, for the range check of the FP32 modes
+            double4 g0;
+            if ((e = hipMemcpyAsync(&g0, t.geom.as<double4>(), sizeof(g0), hipMemcpyDeviceToHost, c->stream)) !=
+                    hipSuccess ||
+                (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+                return hip_fail(c, e, "connectivity");
+            t.root_r = g0.z;
             t.has_lists = true;
             t.theta = theta;
             c->cap_hint_s = cap_s;
@@ -392,6 +407,15 @@ int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) 
     if (mode < FMM2D_MODE_FP64 || mode > FMM2D_MODE_FP32_ACC64) return fail(c, FMM2D_EINVAL, "evaluate: unknown mode %d", mode);
     if (c->tree.L < 0 || !c->tree.has_lists)
         return fail(c, FMM2D_ESTATE, "evaluate: needs a tree and its lists (build_tree, connectivity)");
+    // The FP32 modes work on offsets from leaf centres: their squares must
+    // neither overflow nor underflow FP32 (a point set spanning zero is fine:
+    // all its points coincide and contribute nothing)
+    const double r0 = c->tree.root_r;
+    if (mode != FMM2D_MODE_FP64 && r0 != 0.0 && !(r0 >= 0x1p-60 && r0 <= 0x1p56))
+        return fail(c, FMM2D_EINVAL,
+                    "evaluate: the FP32 modes need a root box whose half diagonal lies in [2^-60, 2^56] (this one: "
+                    "%.3g); use FMM2D_MODE_FP64",
+                    r0);
     CtxScope g(c);
     hipError_t e = evaluate_device(c, q, p, mode, phi);
     if (e != hipSuccess) return hip_fail(c, e, "evaluate");
@@ -643,6 +667,18 @@ int fmm2d_get_lists(fmm2d_ctx *c, int level, int32_t *sptr, int32_t *sidx, int32
         e = hipMemcpyAsync(widx, t.widx.as<int32_t>() + t.w_off[level], sizeof(int32_t) * nw, hipMemcpyDeviceToDevice,
                            c->stream);
     return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_lists");
+}
+
+int fmm2d_get_geometry(fmm2d_ctx *c, double *geom) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    const TreeState &t = c->tree;
+    if (t.L < 0) return fail(c, FMM2D_ESTATE, "get_geometry: no tree");
+    if (!geom) return fail(c, FMM2D_EINVAL, "get_geometry: NULL pointer");
+    CtxScope g(c);
+    const hipError_t e = hipMemcpyAsync(geom, t.geom.ptr, sizeof(double4) * level_offset(t.L + 1),
+                                        hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? FMM2D_OK : hip_fail(c, e, "get_geometry");
 }
 
 int fmm2d_get_xlists(fmm2d_ctx *c, int level, int64_t *nx, int32_t *xptr, int32_t *xidx) {

@@ -535,6 +535,8 @@ hipError_t p2l_all(fmm2d_ctx *c, int p) {
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (t.L + 2);
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * t.L);
     double *xpart = reinterpret_cast<double *>(e.xpart.as<cd>());
+    {
+    PhaseScope kernel_scope(c, PH_P2L_KERNEL);  // the P2L kernel alone
     switch (p + 1) {
 #define FMM2D_P2L(P1)                                                                                             \
     case P1:                                                                                                      \
@@ -549,6 +551,7 @@ hipError_t p2l_all(fmm2d_ctx *c, int p) {
             hipLaunchKernelGGL(k_p2l_gen, grid, block, 0, c->stream, p, t.L, t.n, t.x_items.as<int4>(), nitem,
                                t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), stL, t.px.as<double>(),
                                t.py.as<double>(), e.qs.as<double>(), xpart);
+    }
     }
     FMM2D_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_x_reduce, dim3((unsigned)nbox), dim3(64), 0, c->stream, p, nbox, t.x_itemoff.as<int32_t>(),
@@ -565,6 +568,7 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);
     const int64_t maxleaf = level_box_max(t.n, L);
+    PhaseScope kernel_scope(c, PH_M2P_KERNEL);  // the M2P kernel alone
     switch (maxleaf <= MLEAF ? p + 1 : 0) {
 #define FMM2D_M2P(P1)                                                                                             \
     case P1:                                                                                                      \

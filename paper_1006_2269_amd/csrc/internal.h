@@ -62,6 +62,8 @@ struct TreeState {
     DevBuf XLx, XLy, YLx, YLy, T0, T1;
     DevBuf starts;          // int32, all depths 0..2L, (2^d + 1) entries each
     DevBuf rects;           // double [nbox][4]
+    DevBuf prect;           // double [nbox][4]: bounding box of each box's points (tree option SHRINK)
+    bool shrink = false;    // geometry (balls, leaf offsets) from the points' bounding boxes
     DevBuf geom;            // double4 [nbox]: cx, cy, r, scale
     DevBuf perm;            // int32 [n]
     DevBuf leafid;          // int32 [n]: leaf of each leaf-ordered point
@@ -95,6 +97,7 @@ struct TreeState {
     std::vector<int64_t> s_off, w_off, x_off;  // host copy: pool offset of each level
     bool has_lists = false;
     double theta = 0.0;
+    double root_r = 0.0;            // half diagonal of the root box (host copy, read with the lists)
 };
 
 struct EvalState {
@@ -119,6 +122,7 @@ enum Phase {
     PH_TREE = 0, PH_LISTS, PH_UPWARD, PH_M2L, PH_L2L, PH_LEAF, PH_OTHER, PH_JUDGE, PH_SELECT,
     PH_NEAR_KERNEL, PH_M2L_KERNEL,  // single launches inside PH_LEAF / PH_M2L
     PH_EXCHANGE,                    // P2L and M2P of the exchanged-roles pairs
+    PH_P2L_KERNEL, PH_M2P_KERNEL,   // single launches inside PH_EXCHANGE
     PH_COUNT
 };
 
@@ -158,6 +162,7 @@ struct fmm2d_ctx {
     void *user = nullptr;
     int64_t list_limit = 2147483647LL;  // entries per level and list (FMM2D_LIST_LIMIT lowers it)
     int64_t cap_hint_s = 0, cap_hint_w = 0, cap_hint_x = 0;  // list pool sizes that sufficed last time
+    int tree_opt = 0;       // FMM2D_TREE_* for the next trees (fmm2d_set_tree_options)
     hipStream_t stream = nullptr;
     // internal stream for work that may overlap the caller's stream (created
     // on first use, default priority); ev_side_out marks the end of the last

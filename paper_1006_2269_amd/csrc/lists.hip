@@ -707,7 +707,9 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s
     FMM2D_TRY(t.selfpos.ensure(sizeof(int32_t) * (size_t)(int64_t(1) << (2 * L))));
     int32_t *owner[2] = {t.owner0.as<int32_t>(), t.owner1.as<int32_t>()};
     int32_t *selfpos = t.selfpos.as<int32_t>();
-    const double4 *rectL = t.rects.as<double4>() + level_offset(L);  // (xlo, xhi, ylo, yhi) per leaf
+    // (xlo, xhi, ylo, yhi) per leaf: the points' bounding boxes when the
+    // balls are drawn around them (the near records' separation test)
+    const double4 *rectL = (t.shrink ? t.prect : t.rects).as<double4>() + level_offset(L);
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, xptr, t.sidx.as<int32_t>(), ps, L,
                        stL, geom, rectL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[0], selfpos);
     // levels of at most 64 boxes: one workgroup, one launch

@@ -446,6 +446,48 @@ __global__ void k_gather(const int32_t *__restrict__ XLx, const int32_t *__restr
     loc[i] = make_float2((float)(x - g.x), (float)(y - g.y));
 }
 
+// Balls drawn around the points (tree option FMM2D_TREE_SHRINK): the
+// bounding box of each leaf's points, then of each box's four children
+// level by level upwards (min / max: exact), and each leaf point's FP32
+// offset from its leaf's new centre.
+__global__ void k_leaf_bbox(const int32_t *__restrict__ stL, const double *__restrict__ px,
+                            const double *__restrict__ py, int64_t nleaf, Rect *__restrict__ prL) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nleaf) return;
+    const int32_t a = stL[b], e = stL[b + 1];  // every leaf holds a point
+    Rect r{px[a], px[a], py[a], py[a]};
+    for (int32_t i = a + 1; i < e; ++i) {
+        r.xlo = fmin(r.xlo, px[i]);
+        r.xhi = fmax(r.xhi, px[i]);
+        r.ylo = fmin(r.ylo, py[i]);
+        r.yhi = fmax(r.yhi, py[i]);
+    }
+    prL[b] = r;
+}
+
+__global__ void k_merge_bbox(int64_t nb, const Rect *__restrict__ child, Rect *__restrict__ parent) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    Rect r = child[4 * b];
+    for (int k = 1; k < 4; ++k) {
+        const Rect c = child[4 * b + k];
+        r.xlo = fmin(r.xlo, c.xlo);
+        r.xhi = fmax(r.xhi, c.xhi);
+        r.ylo = fmin(r.ylo, c.ylo);
+        r.yhi = fmax(r.yhi, c.yhi);
+    }
+    parent[b] = r;
+}
+
+__global__ void k_leaf_offsets(const double *__restrict__ px, const double *__restrict__ py,
+                               const int32_t *__restrict__ leafid, const double4 *__restrict__ geomL, int64_t n,
+                               float2 *__restrict__ loc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 g = geomL[leafid[i]];
+    loc[i] = make_float2((float)(px[i] - g.x), (float)(py[i] - g.y));
+}
+
 }  // namespace
 
 // The tree's arrays of n entries (the sort writes into some of them).
@@ -561,6 +603,27 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y, boo
                        L, n, t.geom.as<double4>() + level_offset(L),
                        t.perm.as<int32_t>(), t.px.as<double>(), t.py.as<double>(), t.loc.as<float2>(),
                        t.leafid.as<int32_t>());
+    FMM2D_TRY(hipGetLastError());
+    t.shrink = (c->tree_opt & FMM2D_TREE_SHRINK) != 0;
+    if (t.shrink) {
+        // balls around the points: their bounding boxes, the geometry from
+        // those, and the leaf offsets from the new centres
+        FMM2D_TRY(t.prect.ensure(sizeof(Rect) * nbox));
+        Rect *pr = t.prect.as<Rect>();
+        hipLaunchKernelGGL(k_leaf_bbox, dim3(grid_for(nleaf, 256)), dim3(256), 0, c->stream,
+                           t.starts.as<int32_t>() + depth_offset(2 * L), t.px.as<double>(), t.py.as<double>(), nleaf,
+                           pr + level_offset(L));
+        for (int l = L - 1; l >= 0; --l) {
+            const int64_t nb = int64_t(1) << (2 * l);
+            hipLaunchKernelGGL(k_merge_bbox, dim3(grid_for(nb, 256)), dim3(256), 0, c->stream, nb,
+                               pr + level_offset(l + 1), pr + level_offset(l));
+        }
+        hipLaunchKernelGGL(k_geometry, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, pr, nbox,
+                           t.geom.as<double4>());
+        hipLaunchKernelGGL(k_leaf_offsets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.px.as<double>(),
+                           t.py.as<double>(), t.leafid.as<int32_t>(), t.geom.as<double4>() + level_offset(L), n,
+                           t.loc.as<float2>());
+    }
     return hipGetLastError();
 }
 

@@ -116,6 +116,11 @@ class FMM2D:
     def stream(self):
         return self._stream
 
+    def set_tree_options(self, shrink: bool = False):
+        """Options of the trees built from now on: ``shrink`` draws each box's
+        ball around its points (bounding box) instead of its tiling rectangle."""
+        self._check(self._lib.fmm2d_set_tree_options(self._h, _capi.TREE_SHRINK if shrink else 0))
+
     # -- the three stages --------------------------------------------------
     def build_tree(self, x: torch.Tensor, y: torch.Tensor, levels: int):
         _require(x, torch.float64, self.device, "x")
@@ -317,6 +322,13 @@ class FMM2D:
         nbox = (4 ** (self.levels + 1) - 1) // 3
         out = torch.empty((nbox, 4), dtype=torch.float64, device=self.device)
         self._check(self._lib.fmm2d_get_rects(self._h, _ptr(out)))
+        return out
+
+    def geometry(self):
+        """(cx, cy, r, scale) of every box, level by level."""
+        nbox = (4 ** (self.levels + 1) - 1) // 3
+        out = torch.empty((nbox, 4), dtype=torch.float64, device=self.device)
+        self._check(self._lib.fmm2d_get_geometry(self._h, _ptr(out)))
         return out
 
     def list_sizes(self, level: int):

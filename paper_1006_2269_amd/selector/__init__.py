@@ -13,6 +13,17 @@ NFEAT = 92
 HEADER = 194
 THETAS = (0.35, 0.45, 0.55, 0.65, 0.75)
 
+# The reduced-precision form the selector is trained for and used with: the
+# lists with both structural options of Section 4 (interaction via the
+# parent box, exchanged roles at every level), and FP32 arithmetic with FP32
+# accumulation where the tolerance allows it (>= 1e-7), binary64
+# accumulation below.
+LIST_OPTIONS = {"parent": True, "swap": "all"}
+
+
+def reduced_mode(tol: float) -> str:
+    return "fp32" if tol >= 1e-7 else "fp32_acc64"
+
 
 def load_weights(path: str = WEIGHTS_PATH):
     """The weight blob (float32, fmm2d_select layout) or None if absent."""

@@ -4,9 +4,10 @@ For each layout (``workloads.selector_layout``): its density features, the
 binary64 judge at 1000 sampled targets, and for every level count L in
 {L0 - 1, ..., L0 + 2} (L0 = round(log4(N / 16))) and theta in
 {0.35, ..., 0.75} the GPU times of build_tree and connectivity (warm: the
-least of three calls after one that may allocate), then for
-p = 4, 5, ... the time of evaluate (mode fp32_acc64) and the normwise error
-against the judge, until the error drops below 5e-8 or stops improving (the
+least of three calls after one that may allocate; the lists with the
+structural options of ``selector.LIST_OPTIONS``), then for p = 4, 5, ... the
+time of evaluate (mode fp32, the reduced form for tolerances >= 1e-7) and
+the normwise error against the judge, until the error drops below 5e-8 or stops improving (the
 FP32 near field sets a floor).  Evaluate times are the GPU phases of one call
 (HIP events), so growing buffers do not count.
 
@@ -27,7 +28,7 @@ THETAS = (0.35, 0.45, 0.55, 0.65, 0.75)
 P_MIN, P_MAX = 4, 30
 E_STOP = 5e-8      # below every tolerance the selector is trained for
 PLATEAU = 3        # stop after this many orders without a 10% gain
-MODE = "fp32_acc64"
+MODE = "fp32"
 
 
 def L0_of(n: int) -> int:
@@ -61,11 +62,13 @@ def time_tree(f, x, y, L):
 def time_lists(f, theta):
     """connectivity time at theta on the current tree, warm (see time_tree);
     raises FMM2DError where a level's lists exceed the int32 entry limit."""
-    f.connectivity(theta)
+    from paper_1006_2269_amd.selector import LIST_OPTIONS
+
+    f.connectivity(theta, **LIST_OPTIONS)
     best = math.inf
     for _ in range(REPEATS):
         f.timing(True)
-        f.connectivity(theta)
+        f.connectivity(theta, **LIST_OPTIONS)
         best = min(best, phase_ms(f, ["lists"]))
     return best
 
@@ -97,7 +100,7 @@ def run_layout(f, ps, torch, samples=1000):
                 # from the caching allocator), so no warm-up call is needed
                 f.timing(True)
                 f.evaluate(q, p, MODE, out=out)
-                t_eval = phase_ms(f, ["upward", "m2l", "l2l", "leaf", "other"])
+                t_eval = phase_ms(f, ["upward", "m2l", "l2l", "leaf", "other", "exchange"])
                 e = float((out[tg] - exact).abs().max()) / scale
                 rows.append((L, th, p, t_tree, t_lists, t_eval, e))
                 stale = stale + 1 if e > 0.9 * best else 0
@@ -152,6 +155,7 @@ def main():
 
     from paper_1006_2269_amd import workloads as W
     from paper_1006_2269_amd.fmm import FMM2D
+    from paper_1006_2269_amd.selector import LIST_OPTIONS
 
     f = FMM2D(0)
     if args.retime:
@@ -172,7 +176,8 @@ def main():
         if (i + 1) % args.save_every == 0 or i + 1 == args.count:
             np.savez_compressed(args.out, feats=np.array(feats, dtype=np.float32), n=np.array(ns, dtype=np.int64),
                      seeds=np.arange(args.first, args.first + i + 1), runs=np.array(table, dtype=np.float64),
-                     log10_range=np.array([args.lo, args.hi]),
+                     log10_range=np.array([args.lo, args.hi]), mode=np.array(MODE),
+                     list_options=np.array(sorted(LIST_OPTIONS.items()), dtype=object).astype(str),
                      columns=np.array(["layout", "L", "theta", "p", "t_tree_ms", "t_lists_ms", "t_eval_ms",
                                        "e_inf"]))
     f.close()

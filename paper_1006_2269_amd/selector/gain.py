@@ -2,10 +2,14 @@
 the GPU).
 
 For each held-out layout (``workloads.selector_layout`` with seeds disjoint
-from training) and TOL (default 1e-6): both forms run the whole path --
-select, build_tree, connectivity, evaluate (mode fp32_acc64) -- timed with
-HIP events on the library's stream after one warm-up, and their normwise
-error is measured against the binary64 judge at 1000 sampled targets.
+from training, N = 10^U[lo, hi]) and TOL (default 1e-6): both forms run the
+whole path -- select, build_tree, connectivity (the lists with
+``selector.LIST_OPTIONS``), evaluate (``selector.reduced_mode(TOL)``) --
+timed with HIP events on the library's stream after one warm-up, and their
+normwise error is measured against the binary64 judge at 1000 sampled
+targets.  A form counts on a layout only where it meets TOL: the summary
+gives each form's fraction meeting TOL and the speed-up over the layouts
+where both do.
 
     python -m paper_1006_2269_amd.selector.gain --first 90000 --count 40 --out gpurun_out/gain.json
 """
@@ -18,15 +22,16 @@ import sys
 
 import numpy as np
 
-MODE = "fp32_acc64"
-
-
 def timed_path(f, torch, x, y, q, tol, weights, out, reps=3):
+    from paper_1006_2269_amd.selector import LIST_OPTIONS, reduced_mode
+
+    mode = reduced_mode(tol)
+
     def once():
         L, p, th, net = f.select(x, y, tol, weights)
         f.build_tree(x, y, L)
-        f.connectivity(th)
-        f.evaluate(q, p, MODE, out=out)
+        f.connectivity(th, **LIST_OPTIONS)
+        f.evaluate(q, p, mode, out=out)
         return L, p, th, net
 
     once()
@@ -48,7 +53,7 @@ def main():
     ap.add_argument("--first", type=int, default=90000)
     ap.add_argument("--count", type=int, default=40)
     ap.add_argument("--lo", type=float, default=4.0)
-    ap.add_argument("--hi", type=float, default=6.0)
+    ap.add_argument("--hi", type=float, default=7.0)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
@@ -92,8 +97,10 @@ def main():
         summ[form] = {"fraction_meeting_tol": float(np.mean(ok)),
                       "points_per_s_total": float(sum(r["n"] for r in rows) / (tot_ms * 1e-3)),
                       "median_points_per_s": float(np.median([r["n"] / (r[form]["ms"] * 1e-3) for r in rows]))}
-    speed = [r["rule"]["ms"] / r["learned"]["ms"] for r in rows]
-    summ["geomean_speedup_learned_over_rule"] = float(math.exp(np.mean(np.log(speed))))
+    both = [r for r in rows if r["learned"]["ok"] and r["rule"]["ok"]]
+    speed = [r["rule"]["ms"] / r["learned"]["ms"] for r in both]
+    summ["layouts_both_meet_tol"] = len(both)
+    summ["geomean_speedup_learned_over_rule"] = float(math.exp(np.mean(np.log(speed)))) if speed else None
     summ["tol"] = args.tol
     summ["layouts"] = len(rows)
     with open(args.out, "w") as fh:

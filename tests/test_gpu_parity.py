@@ -315,3 +315,44 @@ def test_reduced_modes_close_pair_in_sparse_leaf(fmm, orc, mode, tol, per_leaf):
     err = np.abs(phi - ex)
     assert err[0] <= bound and err[1] <= bound, (err[:2], bound)
     assert err[2:].max() <= tol * scale
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp32_acc64", "bf16x3"])
+@pytest.mark.parametrize("s", [1e15, 1e-15])
+def test_reduced_modes_scaled_inputs(fmm, orc, mode, s):
+    # A uniform set scaled by s (root half-diagonal s / sqrt(2)): inside the
+    # FP32 modes' range [2^-60, 2^56], so they run; the potentials shift by
+    # log(s) sum q, the leaf-local offsets scale with s, and the normwise
+    # error stays at the FP32 level of the unscaled set (its log terms are
+    # larger in magnitude by |log s|, so the bound is 5x the unscaled 2e-5;
+    # BF16X3 keeps its 1e-3)
+    ps = W.uniform(3000, seed=41)
+    x, y = ps.x * s, ps.y * s
+    _announce("scaled", s, mode)
+    fmm.build_tree(_dev(x), _dev(y), 4)
+    fmm.connectivity(0.5)
+    phi = fmm.evaluate(_dev(ps.q), 20, mode).cpu().numpy()
+    e, _ = orc.rel_errors(phi, orc.direct(x, y, ps.q))
+    assert e <= (1e-3 if mode == "bf16x3" else 1e-4)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp32_acc64", "bf16x3"])
+def test_reduced_modes_refuse_out_of_range(fmm, orc, mode):
+    # coordinates spanning 1e+-18 (beyond 2^56 for the root half-diagonal):
+    # the FP32 modes refuse, binary64 evaluates
+    from paper_1006_2269_amd.fmm import FMM2DError
+
+    g = W.rng(43)
+    n = 2000
+    x = np.sign(g.uniform(-1, 1, n)) * 10.0 ** g.uniform(-18, 18, n)
+    y = np.sign(g.uniform(-1, 1, n)) * 10.0 ** g.uniform(-18, 18, n)
+    q = g.uniform(-1, 1, n)
+    _announce("out of range", mode)
+    fmm.build_tree(_dev(x), _dev(y), 3)
+    fmm.connectivity(0.5)
+    with pytest.raises(FMM2DError) as e:
+        fmm.evaluate(_dev(q), 12, mode)
+    assert e.value.code == -1 and "2^56" in str(e.value)
+    phi = fmm.evaluate(_dev(q), 12, "fp64").cpu().numpy()
+    ref = orc.fmm(x, y, q, 3, 12, 0.5)
+    assert np.abs(phi - ref).max() <= 1e-12 * np.abs(ref).max()
