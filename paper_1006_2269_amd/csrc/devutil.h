@@ -59,6 +59,42 @@ __device__ inline cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
 __device__ inline cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
 __device__ inline cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
+// a b + c in four fused multiply-adds (a Horner step)
+__device__ inline cd cfma(cd a, cd b, cd c) {
+    return cd{fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+// Natural logarithm of a finite x > 0 in binary64, within a few ulp.  With
+// x = m 2^e, m in [sqrt(1/2), sqrt(2)):  log x = e log 2 + 2 atanh(s),
+// s = (m - 1) / (m + 1), |s| <= 3 - 2 sqrt(2), and the series
+// atanh s = s + s^3/3 + s^5/5 + ... cut after s^19 (the rest is below
+// 2.5e-17 of the sum).  m - 1 is exact; 1 / (m + 1) comes from the hardware
+// reciprocal and two Newton steps.  About half the instructions of the
+// correctly rounded library form, the bulk of a binary64 pair interaction.
+__device__ inline double log_pos(double x) {
+    int e;
+    double m = frexp(x, &e);  // [1/2, 1)
+    if (m < 0x1.6a09e667f3bcdp-1) {
+        m += m;
+        --e;
+    }
+    const double den = m + 1.0;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const double s = (m - 1.0) * r, t = s * s;
+    double q = 1.0 / 19.0;
+    q = fma(q, t, 1.0 / 17.0);
+    q = fma(q, t, 1.0 / 15.0);
+    q = fma(q, t, 1.0 / 13.0);
+    q = fma(q, t, 1.0 / 11.0);
+    q = fma(q, t, 1.0 / 9.0);
+    q = fma(q, t, 1.0 / 7.0);
+    q = fma(q, t, 1.0 / 5.0);
+    q = fma(q, t, 1.0 / 3.0);
+    const double s2 = s + s;
+    return fma((double)e, 0x1.62e42fefa39efp-1, fma(s2 * t, q, s2));  // the double nearest log 2
+}
+
 // a / b, scaled to avoid overflow in |b|^2
 __device__ inline cd cdiv(cd a, cd b) {
     double s = fmax(fabs(b.re), fabs(b.im));

@@ -12,29 +12,33 @@
 // Both run in binary64 in every precision mode.  All boxes of a level hold
 // floor or ceil of n / 4^l points, so the work per entry is known per level.
 //
-// P2L work items: on levels of boxes of at most SMALLN points, an item takes
-// up to XE of a target box's P2L entries, one lane per entry walking the
-// entry's points (the entries' loads are issued side by side); on levels of
-// larger boxes, an item takes one entry's points in chunks (at most 32 per
-// entry), one lane per point.  The lanes' sums meet in a transposing
-// butterfly, the items of a box are consecutive and summed per box in item
-// order, and the L2L pass adds that sum into B: results do not depend on
-// scheduling.  M2P gathers per leaf: one wavefront per leaf, one lane per
-// M2P entry of the leaf's ancestors (all levels flattened), the leaf's
-// points taken 16 at a time, each point's sum over the lanes formed by the
-// butterfly; every point is written once.  Orders above 15 (p + 1 > 16) use
-// one lane per point instead.
+// P2L work items, one per P2L entry on the deepest levels (from the first
+// level whose boxes hold at most LANE_PTS points, or at most LANE_PTS_MANY
+// when the level has LANE_ENTRIES P2L entries or more, onwards): one lane per
+// item walks the entry's source points (the next point's loads issued before
+// the current one is used) and writes the item's partial expansion.  On the
+// coarser levels an item is a chunk of one entry's points (at most 32 chunks
+// of balanced size, at least PCH points each), one wavefront per item, one
+// lane per point, the lanes' sums met in a transposing butterfly.  Items are
+// ordered by target box and summed per box in item order, and the L2L pass
+// adds that sum into B: results do not depend on scheduling.  M2P gathers per
+// leaf: one wavefront per leaf, one lane per M2P entry of the leaf's
+// ancestors (all levels flattened), the leaf's points taken 16 at a time,
+// each point's sum over the lanes formed by the butterfly; every point is
+// written once.  Orders above 15 (p + 1 > 16) use one lane per point
+// instead.
 #include "evaluate.h"
 #include "wavesum.h"
 
 namespace fmm2d {
 namespace {
 
-constexpr int SMALLN = 256;  // boxes of at most this many points: one lane per entry
-constexpr int XE = 256;      // P2L entries per item on such levels
-constexpr int PCH = 512;     // least points per chunk on levels of larger boxes
-constexpr int XT = 16;       // coefficients per pass (orders above 15)
-constexpr int MPC = 16;      // leaf points per M2P pass
+constexpr int LANE_PTS = 256;         // boxes of at most this many points: one lane per P2L entry
+constexpr int LANE_PTS_MANY = 4096;   // ... or this many, on levels with LANE_ENTRIES entries or more
+constexpr int64_t LANE_ENTRIES = 32768;
+constexpr int PCH = 512;  // least points per chunk on the other levels
+constexpr int XT = 16;    // coefficients per pass (orders above 15)
+constexpr int MPC = 16;   // leaf points per M2P pass
 
 // Point range [a, e) of box b of level l (its leaves are b 4^(L-l) onwards).
 __device__ inline void box_range(const int32_t *__restrict__ stL, int L, int l, int64_t b, int32_t &a, int32_t &e) {
@@ -48,18 +52,21 @@ __host__ __device__ inline int64_t level_box_max(int64_t n, int l) {
     return (n + (int64_t(1) << (2 * l)) - 1) >> (2 * l);
 }
 
-// Points per P2L chunk on a level of boxes above SMALLN points: at most 32
-// chunks per entry, at least PCH points each.
+// Points per P2L chunk on a wavefront-per-item level: the largest box split
+// into at most 32 chunks of at least PCH points, as even as they come.
 __host__ __device__ inline int64_t level_chunk(int64_t n, int l) {
-    const int64_t m = level_box_max(n, l), c = (m + 31) / 32;
-    return c > PCH ? c : PCH;
+    const int64_t m = level_box_max(n, l);
+    int64_t k = (m + PCH - 1) / PCH;
+    k = k < 1 ? 1 : (k > 32 ? 32 : k);
+    return (m + k - 1) / k;
 }
 
 // Work items per global box g (P2L entries of X(g): those whose source box
-// is the larger).  An item is int4 (target box, first row position, end row
-// position, first point or -1): -1 covers whole entries of the row range.
+// is the larger).  An item is int4 (target box, row position, row position
+// + 1, first point of the chunk or -1 for the whole entry); levels from
+// `lane_level` on take whole entries.
 template <bool FILL>
-__global__ void k_x_items(int L, int64_t n, int64_t nbox, const int32_t *__restrict__ xptr_all,
+__global__ void k_x_items(int L, int64_t n, int64_t nbox, int lane_level, const int32_t *__restrict__ xptr_all,
                           const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
                           const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
                           int32_t *__restrict__ cnt, const int32_t *__restrict__ itemoff, int4 *__restrict__ items) {
@@ -74,20 +81,15 @@ __global__ void k_x_items(int L, int64_t n, int64_t nbox, const int32_t *__restr
     const int32_t *ptr = xptr_all + ptr_offset(l);
     const int32_t *row = xidx + xoff[l];
     const double4 gb = geom[g];
-    const bool small = level_box_max(n, l) <= SMALLN;
+    const bool whole = l >= lane_level;
     const int32_t chunk = (int32_t)level_chunk(n, l);
     int32_t k = FILL ? itemoff[g] : 0;
-    int32_t run = 0, first = -1;  // small boxes: P2L entries in the open item, its first row position
     for (int32_t t = ptr[b]; t < ptr[b + 1]; ++t) {
         const int64_t cg = level_offset(l) + row[t];
         if (!(gb.z < geom[cg].z)) continue;  // M2P entry: handled per point
-        if (small) {
-            if (run == 0) first = t;
-            if (++run == XE) {
-                if (FILL) items[k] = make_int4((int32_t)g, first, t + 1, -1);
-                ++k;
-                run = 0;
-            }
+        if (whole) {
+            if (FILL) items[k] = make_int4((int32_t)g, t, t + 1, -1);
+            ++k;
         } else {
             int32_t a, e;
             box_range(stL, L, l, row[t], a, e);
@@ -97,24 +99,30 @@ __global__ void k_x_items(int L, int64_t n, int64_t nbox, const int32_t *__restr
             }
         }
     }
-    if (small && run > 0) {
-        if (FILL) items[k] = make_int4((int32_t)g, first, ptr[b + 1], -1);
-        ++k;
-    }
     if (!FILL) cnt[g] = k;
 }
 
-// rho = s / w for w = (dx, dy) != 0, and log|w|; the scaled division where
-// |w|^2 could underflow.
+// The scaled division and hypot for |w|^2 <= 2^-960 (where |w|^2 could
+// underflow), kept out of line: no input of ordinary scale reaches it.
+__device__ __attribute__((noinline)) cd recip_tiny(double s, double dx, double dy, double &logw) {
+    logw = log(hypot(dx, dy));
+    return cdiv(cd{s, 0.0}, cd{dx, dy});
+}
+
+// rho = s / w for w = (dx, dy) != 0, and log|w|.
 __device__ inline cd recip_scaled(double s, double dx, double dy, double &logw) {
     const double d2 = dx * dx + dy * dy;
     if (d2 > 0x1p-960) {
-        logw = 0.5 * log(d2);
-        const double inv = s / d2;
+        logw = 0.5 * log_pos(d2);
+        // 1 / d2 by the hardware reciprocal and two Newton steps (each
+        // squares the relative error; within an ulp or two of the quotient)
+        double r = __builtin_amdgcn_rcp(d2);
+        r = fma(r, fma(-d2, r, 1.0), r);
+        r = fma(r, fma(-d2, r, 1.0), r);
+        const double inv = s * r;
         return cd{dx * inv, -dy * inv};
     }
-    logw = log(hypot(dx, dy));
-    return cdiv(cd{s, 0.0}, cd{dx, dy});
+    return recip_tiny(s, dx, dy, logw);
 }
 
 // P2L sums of one source point about the target (gb): s[0] += q log|w|,
@@ -133,18 +141,21 @@ __device__ inline void p2l_sums(double x, double y, double q, double4 gb, cd *s)
     }
 }
 
-// One wavefront per P2L item, orders p + 1 <= 16.
+// Coefficient k of a P2L partial: the sums times -1/k (k >= 1).
+__device__ inline double p2l_coef(double v, int k) { return k == 0 ? v : -v / (double)k; }
+
+// Wavefront-per-item P2L (chunks of one entry), orders p + 1 <= 16: items
+// [0, *wave_end).
 template <int P1>
 __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__restrict__ items,
-                                             const int32_t *__restrict__ nitem, const int32_t *__restrict__ xidx,
+                                             const int32_t *__restrict__ wave_end, const int32_t *__restrict__ xidx,
                                              const int64_t *__restrict__ xoff, const double4 *__restrict__ geom,
                                              const int32_t *__restrict__ stL, const double *__restrict__ px,
                                              const double *__restrict__ py, const double *__restrict__ qs,
                                              double *__restrict__ xpart) {
     static_assert(P1 >= 2 && P1 <= 16, "one pass of 2 P1 <= 32 values");
     const int64_t it = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    if (it >= *nitem) return;  // uniform per wavefront
-    __shared__ int32_t x_queue[4][128];
+    if (it >= *wave_end) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
     const int4 w = items[it];
     const double4 gb = geom[w.x];
@@ -153,60 +164,11 @@ __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__res
     cd s[P1];
 #pragma unroll
     for (int k = 0; k < P1; ++k) s[k] = cd{0.0, 0.0};
-    if (w.w >= 0) {
-        // one entry, points [w.w, w.w + chunk) of its box, one lane per point
-        int32_t a, e;
-        box_range(stL, L, l, row[w.y], a, e);
-        const int32_t ch = (int32_t)level_chunk(n, l);
-        const int32_t j1 = e < w.w + ch ? e : w.w + ch;
-        for (int32_t j = w.w + lane; j < j1; j += 64) p2l_sums<P1>(px[j], py[j], qs[j], gb, s);
-    } else {
-        // the item's P2L entries (M2P entries in between left out), compacted
-        // 64 at a time through the wavefront's LDS queue, one lane per entry;
-        // each lane walks its entry's points with the next point's loads
-        // issued before the current point is used
-        int32_t *queue = x_queue[threadIdx.x / 64];
-        int32_t qn = 0;
-        for (int32_t t0 = w.y; t0 < w.z || qn > 0; t0 += 64) {
-            if (t0 < w.z) {
-                const int32_t t = t0 + lane;
-                int32_t c = 0;
-                bool ok = false;
-                if (t < w.z) {
-                    c = row[t];
-                    ok = gb.z < geom[level_offset(l) + c].z;
-                }
-                const uint64_t m = __ballot(ok);
-                if (ok) queue[qn + (int)popc_below(m)] = c;
-                qn += (int)__popcll(m);
-                __builtin_amdgcn_wave_barrier();
-                if (qn < 64 && t0 + 64 < w.z) continue;  // fill the queue further
-            }
-            const int take = qn < 64 ? qn : 64;
-            if (lane < take) {
-                int32_t a, e;
-                box_range(stL, L, l, queue[lane], a, e);
-                double xn = px[a], yn = py[a], qn_ = qs[a];
-                for (int32_t j = a; j < e; ++j) {
-                    const double x0 = xn, y0 = yn, q0 = qn_;
-                    const int32_t jn = j + 1 < e ? j + 1 : j;
-                    xn = px[jn];
-                    yn = py[jn];
-                    qn_ = qs[jn];
-                    p2l_sums<P1>(x0, y0, q0, gb, s);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            // keep the entries beyond the first 64
-            const int rest = qn - take;
-            const int32_t keep = lane < rest ? queue[take + lane] : 0;
-            __builtin_amdgcn_wave_barrier();
-            if (lane < rest) queue[lane] = keep;
-            qn = rest;
-            __builtin_amdgcn_wave_barrier();
-            if (t0 >= w.z && qn == 0) break;
-        }
-    }
+    int32_t a, e;
+    box_range(stL, L, l, row[w.y], a, e);
+    const int32_t ch = (int32_t)level_chunk(n, l);
+    const int32_t j1 = e < w.w + ch ? e : w.w + ch;
+    for (int32_t j = w.w + lane; j < j1; j += 64) p2l_sums<P1>(px[j], py[j], qs[j], gb, s);
     double v[32];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -216,7 +178,45 @@ __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__res
     // lane i receives the total of value i / 2: coefficient i / 4, part (i / 2) % 2
     const double tot = wave_transpose_sum<32>(v, lane);
     const int vi = lane / 2, k = vi / 2;
-    if ((lane & 1) == 0 && k < P1) xpart[it * 2 * P1 + vi] = k == 0 ? tot : -tot / (double)k;
+    if ((lane & 1) == 0 && k < P1) xpart[it * 2 * P1 + vi] = p2l_coef(tot, k);
+}
+
+// Lane-per-item P2L (whole entries), orders p + 1 <= 16: items
+// [*wave_end, *nitem).  Each lane walks its entry's source points with the
+// next point's loads issued before the current point is used.
+template <int P1>
+__global__ void __launch_bounds__(256) k_p2l_lane(int L, const int4 *__restrict__ items,
+                                                  const int32_t *__restrict__ wave_end,
+                                                  const int32_t *__restrict__ nitem, const int32_t *__restrict__ xidx,
+                                                  const int64_t *__restrict__ xoff, const double4 *__restrict__ geom,
+                                                  const int32_t *__restrict__ stL, const double *__restrict__ px,
+                                                  const double *__restrict__ py, const double *__restrict__ qs,
+                                                  double *__restrict__ xpart) {
+    const int64_t it = *wave_end + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= *nitem) return;
+    const int4 w = items[it];
+    const double4 gb = geom[w.x];
+    const int l = level_of(w.x);
+    int32_t a, e;
+    box_range(stL, L, l, xidx[xoff[l] + w.y], a, e);
+    cd s[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) s[k] = cd{0.0, 0.0};
+    double xn = px[a], yn = py[a], qn = qs[a];
+    for (int32_t j = a; j < e; ++j) {
+        const double x0 = xn, y0 = yn, q0 = qn;
+        const int32_t jn = j + 1 < e ? j + 1 : j;
+        xn = px[jn];
+        yn = py[jn];
+        qn = qs[jn];
+        p2l_sums<P1>(x0, y0, q0, gb, s);
+    }
+    double *out = xpart + it * 2 * P1;
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        out[2 * k] = p2l_coef(s[k].re, k);
+        out[2 * k + 1] = p2l_coef(s[k].im, k);
+    }
 }
 
 // The same for orders p + 1 > 16: XT coefficients per pass, one lane per
@@ -263,8 +263,7 @@ __global__ void __launch_bounds__(256) k_p2l_gen(int p, int L, int64_t n, const 
             ar[k] = 0.0;
             ai[k] = 0.0;
         }
-        const int32_t t_end = w.w >= 0 ? w.y + 1 : w.z;
-        for (int32_t t = w.y; t < t_end; ++t) {
+        for (int32_t t = w.y; t < w.z; ++t) {
             const int32_t c = row[t];
             if (!(gb.z < geom[level_offset(l) + c].z)) continue;
             int32_t a, e;
@@ -288,8 +287,8 @@ __global__ void __launch_bounds__(256) k_p2l_gen(int p, int L, int64_t n, const 
         for (int k = 0; k < XT; ++k) {
             const int kk = k0 + k;
             if (lane == k && kk <= p) {
-                xpart[(it * P1 + kk) * 2] = kk == 0 ? ar[k] : -ar[k] / (double)kk;
-                xpart[(it * P1 + kk) * 2 + 1] = kk == 0 ? ai[k] : -ai[k] / (double)kk;
+                xpart[(it * P1 + kk) * 2] = p2l_coef(ar[k], kk);
+                xpart[(it * P1 + kk) * 2 + 1] = p2l_coef(ai[k], kk);
             }
         }
     }
@@ -419,9 +418,8 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t nleaf, const int32_t
                     const cd rho = recip_scaled(gc.w, px[i] - gc.x, py[i] - gc.y, lw);
                     cd sacc = Ac[P1 - 1];
 #pragma unroll
-                    for (int q = P1 - 2; q >= 1; --q) sacc = cadd(cmul(sacc, rho), Ac[q]);
-                    sacc = cmul(sacc, rho);
-                    val = Ac[0].re * lw + sacc.re;
+                    for (int q = P1 - 2; q >= 1; --q) sacc = cfma(sacc, rho, Ac[q]);
+                    val = fma(sacc.re, rho.re, fma(-sacc.im, rho.im, Ac[0].re * lw));  // Re(sacc rho) + A_0 log|w|
                 }
                 v[j] = val;
             }
@@ -474,9 +472,8 @@ __global__ void __launch_bounds__(256) k_m2p_gen(int p, int L, int64_t nleaf, co
                 double lw;
                 const cd rho = recip_scaled(gc.w, act ? zx - gc.x : gc.w, act ? zy - gc.y : 0.0, lw);
                 cd s = Ac[p];
-                for (int k = p - 1; k >= 1; --k) s = cadd(cmul(s, rho), Ac[k]);
-                s = cmul(s, rho);
-                acc += Ac[0].re * lw + s.re;
+                for (int k = p - 1; k >= 1; --k) s = cfma(s, rho, Ac[k]);
+                acc += fma(s.re, rho.re, fma(-s.im, rho.im, Ac[0].re * lw));
             }
         }
         if (act) phi[perm[i]] += acc;
@@ -492,13 +489,28 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     if (!(t.opt & (FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL)) || L < 1) return hipSuccess;
     if (t.x_off[L + 1] == t.x_off[1]) return hipSuccess;  // no exchanged pair
     const int64_t nbox = level_offset(L + 1);
-    // at most one item per entry on levels of small boxes, the chunks of one
-    // entry on the others
-    int64_t bound = 0;
-    for (int l = 1; l <= L; ++l) {
-        const int64_t maxpts = level_box_max(t.n, l), ch = level_chunk(t.n, l);
-        bound += (t.x_off[l + 1] - t.x_off[l]) * (maxpts <= SMALLN ? 1 : (maxpts + ch - 1) / ch);
+    // whole entries (one lane each) from the first level of a run down to
+    // the finest in which every level has small boxes, or boxes of moderate
+    // size and many entries; chunks above
+    int lane_level = L + 1;
+    for (int l = L; l >= 1; --l) {
+        const int64_t maxpts = level_box_max(t.n, l), nx = t.x_off[l + 1] - t.x_off[l];
+        if (maxpts <= LANE_PTS || (maxpts <= LANE_PTS_MANY && nx / 2 >= LANE_ENTRIES))
+            lane_level = l;
+        else
+            break;
     }
+    // at most one item per entry on the lane levels, the chunks of one entry
+    // on the others
+    int64_t bw = 0, bl = 0;
+    for (int l = 1; l <= L; ++l) {
+        const int64_t maxpts = level_box_max(t.n, l), ch = level_chunk(t.n, l), nx = t.x_off[l + 1] - t.x_off[l];
+        if (l >= lane_level)
+            bl += nx;
+        else
+            bw += nx * ((maxpts + ch - 1) / ch);
+    }
+    const int64_t bound = bw + bl;
     FMM2D_TRY(c->scr.segcnt.ensure(sizeof(int32_t) * nbox));
     FMM2D_TRY(t.x_itemoff.ensure(sizeof(int32_t) * (nbox + 1)));
     FMM2D_TRY(t.x_items.ensure(sizeof(int4) * (bound > 0 ? bound : 1)));
@@ -506,14 +518,17 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);  // X pool offset of each level
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     const double4 *geom = t.geom.as<double4>();
-    hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
-                       xidx, xoff, geom, stL, c->scr.segcnt.as<int32_t>(), nullptr, nullptr);
+    hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox,
+                       lane_level, xptr, xidx, xoff, geom, stL, c->scr.segcnt.as<int32_t>(), nullptr, nullptr);
     FMM2D_TRY(hipGetLastError());
     FMM2D_TRY(scan_exclusive(c, c->scr.segcnt.as<int32_t>(), nbox, t.x_itemoff.as<int32_t>()));
-    hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
-                       xidx, xoff, geom, stL, nullptr, t.x_itemoff.as<int32_t>(), t.x_items.as<int4>());
+    hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox,
+                       lane_level, xptr, xidx, xoff, geom, stL, nullptr, t.x_itemoff.as<int32_t>(),
+                       t.x_items.as<int4>());
     FMM2D_TRY(hipGetLastError());
-    t.x_item_bound = bound;
+    t.x_bound_wave = bw;
+    t.x_bound_lane = bl;
+    t.x_lane_level = lane_level;
     t.x_ready = true;
     return hipSuccess;
 }
@@ -526,36 +541,45 @@ hipError_t p2l_all(fmm2d_ctx *c, int p) {
     TreeState &t = c->tree;
     if (!t.x_ready) return hipSuccess;
     EvalState &e = c->ev;
-    const int64_t bound = t.x_item_bound > 0 ? t.x_item_bound : 1;
+    const int64_t bound = t.x_bound_wave + t.x_bound_lane > 0 ? t.x_bound_wave + t.x_bound_lane : 1;
     const int64_t nbox = level_offset(t.L + 1);
     FMM2D_TRY(e.xpart.ensure(sizeof(cd) * bound * (p + 1)));
     FMM2D_TRY(e.xsum.ensure(sizeof(cd) * nbox * (p + 1)));
-    const dim3 grid(grid_for(bound, 4)), block(256);
-    const int32_t *nitem = t.x_itemoff.as<int32_t>() + nbox;
+    const int32_t *itemoff = t.x_itemoff.as<int32_t>();
+    const int32_t *nitem = itemoff + nbox;
+    // items of the levels before the lane levels come first
+    const int32_t *wave_end = itemoff + level_offset(t.x_lane_level);
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (t.L + 2);
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * t.L);
     double *xpart = reinterpret_cast<double *>(e.xpart.as<cd>());
+    const int4 *items = t.x_items.as<int4>();
+    const int32_t *xidx = t.xidx.as<int32_t>();
+    const double4 *geom = t.geom.as<double4>();
+    const double *px = t.px.as<double>(), *py = t.py.as<double>(), *qs = e.qs.as<double>();
+    const dim3 block(256);
     {
-    PhaseScope kernel_scope(c, PH_P2L_KERNEL);  // the P2L kernel alone
+    PhaseScope kernel_scope(c, PH_P2L_KERNEL);  // the P2L kernels alone
     switch (p + 1) {
 #define FMM2D_P2L(P1)                                                                                             \
     case P1:                                                                                                      \
-        hipLaunchKernelGGL(k_p2l<P1>, grid, block, 0, c->stream, t.L, t.n, t.x_items.as<int4>(), nitem,           \
-                           t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), stL, t.px.as<double>(),              \
-                           t.py.as<double>(), e.qs.as<double>(), xpart);                                          \
+        if (t.x_bound_wave > 0)                                                                                   \
+            hipLaunchKernelGGL(k_p2l<P1>, dim3(grid_for(t.x_bound_wave, 4)), block, 0, c->stream, t.L, t.n,      \
+                               items, wave_end, xidx, xoff, geom, stL, px, py, qs, xpart);                        \
+        if (t.x_bound_lane > 0)                                                                                   \
+            hipLaunchKernelGGL(k_p2l_lane<P1>, dim3(grid_for(t.x_bound_lane, 256)), block, 0, c->stream, t.L,    \
+                               items, wave_end, nitem, xidx, xoff, geom, stL, px, py, qs, xpart);                 \
         break;
         FMM2D_P2L(2) FMM2D_P2L(3) FMM2D_P2L(4) FMM2D_P2L(5) FMM2D_P2L(6) FMM2D_P2L(7) FMM2D_P2L(8) FMM2D_P2L(9)
         FMM2D_P2L(10) FMM2D_P2L(11) FMM2D_P2L(12) FMM2D_P2L(13) FMM2D_P2L(14) FMM2D_P2L(15) FMM2D_P2L(16)
 #undef FMM2D_P2L
         default:
-            hipLaunchKernelGGL(k_p2l_gen, grid, block, 0, c->stream, p, t.L, t.n, t.x_items.as<int4>(), nitem,
-                               t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), stL, t.px.as<double>(),
-                               t.py.as<double>(), e.qs.as<double>(), xpart);
+            hipLaunchKernelGGL(k_p2l_gen, dim3(grid_for(bound, 4)), block, 0, c->stream, p, t.L, t.n, items, nitem,
+                               xidx, xoff, geom, stL, px, py, qs, xpart);
     }
     }
     FMM2D_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_x_reduce, dim3((unsigned)nbox), dim3(64), 0, c->stream, p, nbox, t.x_itemoff.as<int32_t>(),
-                       e.xpart.as<cd>(), e.xsum.as<cd>());
+    hipLaunchKernelGGL(k_x_reduce, dim3((unsigned)nbox), dim3(64), 0, c->stream, p, nbox, itemoff, e.xpart.as<cd>(),
+                       e.xsum.as<cd>());
     return hipGetLastError();
 }
 

@@ -91,7 +91,9 @@ struct TreeState {
     // exchanged roles: P2L work items int4 (target box, source box, first
     // point, end point), global ids; per global box its first item (+ count)
     DevBuf x_items, x_itemoff;
-    int64_t x_item_bound = 0;       // upper bound of the item count (launch size)
+    int64_t x_bound_wave = 0;       // upper bound of the wavefront-per-item P2L items (launch size)
+    int64_t x_bound_lane = 0;       // ... of the lane-per-item ones
+    int x_lane_level = 0;           // first level of lane-per-item P2L (all deeper levels too)
     bool x_ready = false;
     DevBuf lsum;                    // double: per near_lo segment and source lane, its entries' source sums
     std::vector<int64_t> s_off, w_off, x_off;  // host copy: pool offset of each level

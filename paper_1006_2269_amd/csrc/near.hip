@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near64(int64_t nitems, int chunks,
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
                 const double dx = tx[k] - sx, dy = ty[k] - sy;
-                acc[k] += (ok && (dx != 0.0 || dy != 0.0)) ? q * log(dx * dx + dy * dy) : 0.0;
+                acc[k] += (ok && (dx != 0.0 || dy != 0.0)) ? q * log_pos(dx * dx + dy * dy) : 0.0;
             }
         }
     }

@@ -1,0 +1,100 @@
+"""A CPU replay of the work-item schedule of the exchanged-roles P2L pass,
+checked for bounds and coverage on parity inputs.
+
+The host picks the first level of whole-entry (lane-per-item) items, sizes
+the item array from the X list sizes, and the device enumerates items per
+target box: chunks of one entry's source points on the coarser levels, whole
+entries from that level on.  The replay rebuilds that enumeration from the
+oracle's optimised lists and checks that every index the kernels form lies
+in its buffer, that the wavefront-per-item range precedes the lane-per-item
+range, and that each P2L entry's source points are covered exactly once.
+
+This is test infrastructure: it models the kernels' indexing only and holds
+none of the method's arithmetic.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_cases import TREE_CASES
+
+PCH = 512
+
+
+def level_offset(l):
+    return (4 ** l - 1) // 3
+
+
+def level_box_max(n, l):
+    return -(-n // 4 ** l)
+
+
+def level_chunk(n, l):
+    m = level_box_max(n, l)
+    k = min(32, max(1, -(-m // PCH)))
+    return -(-m // k)
+
+
+def lane_level_of(n, L, nx, lane_pts, lane_pts_many, lane_entries):
+    ll = L + 1
+    for l in range(L, 0, -1):
+        m = level_box_max(n, l)
+        if m <= lane_pts or (m <= lane_pts_many and nx[l] // 2 >= lane_entries):
+            ll = l
+        else:
+            break
+    return ll
+
+
+@pytest.mark.parametrize("case", ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "ring_scaled_20k_L6",
+                                  "duplicates_4k_L4", "uniform_2000_L2", "single_box_L0"])
+@pytest.mark.parametrize("thresholds", [(256, 4096, 32768), (16, 4096, 200), (0, 0, 1 << 40), (1 << 30, 0, 0)])
+def test_p2l_items_cover_and_bound(orc, case, thresholds):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    t = orc.tree(ps.x, ps.y, L)
+    ls = orc.lists_opt(t, 0.5, parent=True, swap_levels=range(1, L + 1))
+    n = ps.n
+    nx = [int(ls.xptr[l][-1]) for l in range(L + 1)]
+    ll = lane_level_of(n, L, nx, *thresholds)
+    bw = sum(nx[l] * -(-level_box_max(n, l) // level_chunk(n, l)) for l in range(1, min(ll, L + 1)))
+    bl = sum(nx[l] for l in range(max(ll, 1), L + 1))
+    bound = max(bw + bl, 1)
+    starts = t.leaf_start
+    items, itemoff, box = [], [0], {}
+    for l in range(L + 1):
+        r = t.geom[level_offset(l):level_offset(l + 1), 2]
+        for b in range(4 ** l):
+            if l >= 1:
+                for pos in range(ls.xptr[l][b], ls.xptr[l][b + 1]):
+                    c = int(ls.xidx[l][pos])
+                    if not r[b] < r[c]:
+                        continue  # M2P entry
+                    a, e = starts[c << 2 * (L - l)], starts[(c + 1) << 2 * (L - l)]
+                    assert 0 <= a < e <= n
+                    box[(level_offset(l) + b, pos)] = (a, e)
+                    if l >= ll:
+                        items.append((level_offset(l) + b, pos, -1, a, e))
+                    else:
+                        ch = level_chunk(n, l)
+                        for j in range(a, e, ch):
+                            items.append((level_offset(l) + b, pos, j, j, min(e, j + ch)))
+            itemoff.append(len(items))
+    nitem = len(items)
+    assert nitem <= bound
+    wave_end = itemoff[level_offset(min(ll, L + 1))]
+    assert all(it[2] >= 0 for it in items[:wave_end]) and all(it[2] == -1 for it in items[wave_end:])
+    assert wave_end <= max(bw, 0) or bw == 0 and wave_end == 0
+    assert nitem - wave_end <= bl
+    # every P2L entry covered once, its chunks disjoint and inside the box
+    cover = {}
+    for g, pos, j, a, e in items:
+        cover.setdefault((g, pos), []).append((a, e))
+    for key, segs in cover.items():
+        segs.sort()
+        assert segs[0][0] == box[key][0] and segs[-1][1] == box[key][1]
+        for (a0, e0), (a1, e1) in zip(segs, segs[1:]):
+            assert e0 == a1
+    assert set(cover) == set(box)
+    # the items of a box are consecutive and the boxes in order
+    gs = [it[0] for it in items]
+    assert gs == sorted(gs)
