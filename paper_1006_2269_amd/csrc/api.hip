@@ -175,6 +175,8 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->tree.lsum.release();
         c->tree.x_items.release();
         c->tree.x_itemoff.release();
+        c->tree.m_items.release();
+        c->tree.m_itemoff.release();
         c->ev.xpart.release();
         c->ev.xsum.release();
         for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.work,
@@ -183,7 +185,7 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         Scratch &s = c->scr;
         for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
         for (DevBuf *b : {&s.keys0, &s.keys1, &s.vals0, &s.vals1, &s.hist, &s.aux, &s.tiles, &s.tiles2, &s.segbase,
-                          &s.thr, &s.split0, &s.split1, &s.flag, &s.segcnt})
+                          &s.thr, &s.split0, &s.split1, &s.flag, &s.segcnt, &s.mcnt, &s.sel, &s.sel2})
             b->release();
     }
     delete c;

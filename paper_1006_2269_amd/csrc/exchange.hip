@@ -309,136 +309,99 @@ __global__ void __launch_bounds__(64) k_x_reduce(int p, int64_t nbox, const int3
     xsum[g * (p + 1) + lane] = acc;
 }
 
-// Row ranges of the X lists of a leaf's ancestors (levels 1..L), flattened:
-// entry k of the leaf's stream lies at level lv with pre[lv] <= k <
-// pre[lv + 1], row position start[lv] + k - pre[lv].  The arrays are indexed
-// only by unrolled constants, so they stay in registers.
-constexpr int ML = FMM2D_MAX_LEVELS;
-struct AncestorRows {
-    int32_t start[ML + 1], pre[ML + 2];
-};
-__device__ inline void ancestor_rows(int L, int64_t leaf, const int32_t *__restrict__ xptr_all, AncestorRows &r) {
-    r.pre[0] = 0;
-    r.pre[1] = 0;
-    r.start[0] = 0;
-#pragma unroll
-    for (int l = 1; l <= ML; ++l) {
-        int32_t p0 = 0, p1 = 0;
-        if (l <= L) {
-            const int64_t b = leaf >> (2 * (L - l));
-            const int32_t *ptr = xptr_all + ptr_offset(l);
-            p0 = ptr[b];
-            p1 = ptr[b + 1];
-        }
-        r.start[l] = p0;
-        r.pre[l + 1] = r.pre[l] + (p1 - p0);
-    }
-}
-// The level of stream entry k and its row position.
-__device__ inline int ancestor_entry(const AncestorRows &r, int L, int32_t k, int32_t &t) {
-    int lv = 1;
-    int32_t st = r.start[1], pr = r.pre[1];
-#pragma unroll
-    for (int l = 2; l <= ML; ++l) {
-        if (l <= L && k >= r.pre[l]) {
-            lv = l;
-            st = r.start[l];
-            pr = r.pre[l];
-        }
-    }
-    t = st + (k - pr);
-    return lv;
+// Points of an M2P pass over a box of level l: 64 when its boxes hold 64
+// points or more (one item per 64 points), else the power of two at or
+// above the largest box (one item per box, 64 / that many lane groups).
+__host__ __device__ inline int m2p_width(int64_t n, int l) {
+    const int64_t m = level_box_max(n, l);
+    int w = 1;
+    while (w < m && w < 64) w <<= 1;
+    return w;
 }
 
-// M2P, orders p + 1 <= 16: one wavefront per leaf.  The M2P entries of the
-// leaf's ancestors' X lists (P2L entries left out) are compacted 64 at a time
-// through the wavefront's LDS queue, one lane per entry holding its
-// multipole; for each such round the leaf's points are taken MPC at a time,
-// each point's sum over the lanes formed by the butterfly and added to the
-// point's accumulator in LDS (leaves of at most MLEAF points).
-constexpr int MLEAF = 256;
-template <int P1>
-__global__ void __launch_bounds__(256) k_m2p(int L, int64_t nleaf, const int32_t *__restrict__ stL,
-                                             const int32_t *__restrict__ xptr_all, const int32_t *__restrict__ xidx,
-                                             const int64_t *__restrict__ xoff, const double4 *__restrict__ geom,
-                                             const cd *__restrict__ A, const double *__restrict__ px,
-                                             const double *__restrict__ py, const int32_t *__restrict__ perm,
-                                             double *__restrict__ phi) {
-    __shared__ int64_t m_queue[4][128];
-    __shared__ double m_acc[4][MLEAF];
-    const int64_t leaf = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    if (leaf >= nleaf) return;  // uniform per wavefront
-    const int lane = threadIdx.x % 64;
-    int64_t *queue = m_queue[threadIdx.x / 64];
-    double *acc = m_acc[threadIdx.x / 64];
-    AncestorRows r;
-    ancestor_rows(L, leaf, xptr_all, r);
-    const int32_t K = r.pre[ML + 1];
-    if (K == 0) return;
-    const int32_t a = stL[leaf], e = stL[leaf + 1];
-    for (int32_t i = lane; i < e - a; i += 64) acc[i] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    int qn = 0;
-    for (int32_t k0 = 0; k0 < K || qn > 0; k0 += 64) {
-        if (k0 < K) {
-            const int32_t k = k0 + lane;
-            int32_t t;
-            const int lv = ancestor_entry(r, L, k, t);
-            bool ok = false;
-            int64_t cg = 0;
-            if (k < K) {
-                cg = level_offset(lv) + xidx[xoff[lv] + t];
-                const double rb = geom[level_offset(lv) + (leaf >> (2 * (L - lv)))].z;
-                ok = rb > geom[cg].z;  // the target box is the larger: M2P (else P2L, handled by k_p2l)
+// M2P work items per global box g with an M2P entry in X(g) (the target
+// box the larger): int2 (g, first point), one per 64 points on levels of
+// width 64, one per box on the others.
+template <bool FILL>
+__global__ void k_m_items(int L, int64_t n, int64_t nbox, const int32_t *__restrict__ xptr_all,
+                          const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
+                          const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
+                          int32_t *__restrict__ cnt, const int32_t *__restrict__ itemoff, int2 *__restrict__ items) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const int l = level_of(g);
+    int32_t k = 0;
+    if (l >= 1) {
+        const int64_t b = g - level_offset(l);
+        const int32_t *ptr = xptr_all + ptr_offset(l);
+        const int32_t *row = xidx + xoff[l];
+        const double rb = geom[g].z;
+        bool any = false;
+        for (int32_t t = ptr[b]; t < ptr[b + 1] && !any; ++t) any = rb > geom[level_offset(l) + row[t]].z;
+        if (any) {
+            int32_t a, e;
+            box_range(stL, L, l, b, a, e);
+            const int32_t step = m2p_width(n, l) == 64 ? 64 : e - a;
+            int32_t pos = FILL ? itemoff[g] : 0;
+            for (int32_t j = a; j < e; j += step) {
+                if (FILL) items[pos] = make_int2((int32_t)g, j);
+                ++pos;
             }
-            const uint64_t m = __ballot(ok);
-            if (ok) queue[qn + (int)popc_below(m)] = cg;
-            qn += (int)__popcll(m);
-            __builtin_amdgcn_wave_barrier();
-            if (qn < 64 && k0 + 64 < K) continue;  // fill the queue further
+            k = pos;
         }
-        const int take = qn < 64 ? qn : 64;
-        const bool act = lane < take;
-        cd Ac[P1];
-        double4 gc = make_double4(0.0, 0.0, 1.0, 1.0);
-        if (act) {
-            const int64_t cg = queue[lane];
-            gc = geom[cg];
-#pragma unroll
-            for (int q = 0; q < P1; ++q) Ac[q] = A[cg * P1 + q];
-        }
-        for (int32_t pc = a; pc < e; pc += MPC) {
-            double v[MPC];
-#pragma unroll
-            for (int j = 0; j < MPC; ++j) {
-                const int32_t i = pc + j < e ? pc + j : e - 1;  // points past the leaf repeat its last
-                double val = 0.0;
-                if (act) {
-                    double lw;
-                    const cd rho = recip_scaled(gc.w, px[i] - gc.x, py[i] - gc.y, lw);
-                    cd sacc = Ac[P1 - 1];
-#pragma unroll
-                    for (int q = P1 - 2; q >= 1; --q) sacc = cfma(sacc, rho, Ac[q]);
-                    val = fma(sacc.re, rho.re, fma(-sacc.im, rho.im, Ac[0].re * lw));  // Re(sacc rho) + A_0 log|w|
-                }
-                v[j] = val;
-            }
-            // lane i receives the sum over the lanes of point i / 4
-            const double tot = wave_transpose_sum<MPC>(v, lane);
-            const int j = lane / 4;
-            if ((lane & 3) == 0 && pc + j < e) acc[pc - a + j] += tot;
-            __builtin_amdgcn_wave_barrier();
-        }
-        // keep the entries beyond the first 64
-        const int rest = qn - take;
-        const int64_t keep = lane < rest ? queue[take + lane] : 0;
-        __builtin_amdgcn_wave_barrier();
-        if (lane < rest) queue[lane] = keep;
-        qn = rest;
-        __builtin_amdgcn_wave_barrier();
-        if (k0 >= K && qn == 0) break;
     }
-    for (int32_t i = lane; i < e - a; i += 64) phi[perm[a + i]] += acc[i];
+    if (!FILL) cnt[g] = k;
+}
+
+// M2P of one level, orders p + 1 <= 16: one wavefront per item.  WIDE
+// (boxes of 64 points or more): the item's 64 points one per lane, every
+// lane taking the box's M2P entries in row order (the same entry across the
+// wavefront).  Otherwise (boxes of at most MP < 64 points): lane = group *
+// MP + point, the box's X entries dealt to the 64 / MP groups by row
+// position, each point's group sums met by a butterfly over the group bits.
+// Items of one launch touch disjoint points; the levels run one launch
+// after the other, so every point's sum has a fixed order.
+template <int P1, bool WIDE>
+__global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int2 *__restrict__ items,
+                                                 const int32_t *__restrict__ first, const int32_t *__restrict__ end,
+                                                 const int32_t *__restrict__ xptr_all,
+                                                 const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
+                                                 const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
+                                                 const cd *__restrict__ A, const double *__restrict__ px,
+                                                 const double *__restrict__ py, const int32_t *__restrict__ perm,
+                                                 double *__restrict__ phi) {
+    const int32_t it = __builtin_amdgcn_readfirstlane(*first + (int32_t)(blockIdx.x * 4 + threadIdx.x / 64));
+    if (it >= *end) return;  // uniform per wavefront
+    const int lane = threadIdx.x % 64;
+    const int2 w = items[it];
+    const int64_t b = w.x - level_offset(l);
+    int32_t a, e;
+    box_range(stL, L, l, b, a, e);
+    const int grp = WIDE ? 0 : lane / mp;
+    const int ng = WIDE ? 1 : 64 / mp;
+    const int32_t i = w.y + (WIDE ? lane : lane % mp);
+    const bool act = i < e;
+    const int32_t ii = act ? i : a;  // lanes past the box evaluate at its first point (finite, not written)
+    const double zx = px[ii], zy = py[ii];
+    const double rb = geom[w.x].z;
+    const int32_t *ptr = xptr_all + ptr_offset(l);
+    const int32_t *row = xidx + xoff[l];
+    double acc = 0.0;
+    for (int32_t t = ptr[b] + grp; t < ptr[b + 1]; t += ng) {
+        const int64_t cg = level_offset(l) + row[t];
+        const double4 gc = geom[cg];
+        if (!(rb > gc.z)) continue;  // P2L entry
+        const cd *Ac = A + cg * P1;
+        double lw;
+        const cd rho = recip_scaled(gc.w, zx - gc.x, zy - gc.y, lw);
+        cd sacc = Ac[P1 - 1];
+#pragma unroll
+        for (int q = P1 - 2; q >= 1; --q) sacc = cfma(sacc, rho, Ac[q]);
+        acc += fma(sacc.re, rho.re, fma(-sacc.im, rho.im, Ac[0].re * lw));  // Re(sacc rho) + A_0 log|w|
+    }
+    if (!WIDE)
+        for (int off = mp; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if (grp == 0 && act) phi[perm[i]] += acc;
 }
 
 // M2P for orders p + 1 > 16: one lane per point of the leaf.
@@ -529,6 +492,26 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     t.x_bound_wave = bw;
     t.x_bound_lane = bl;
     t.x_lane_level = lane_level;
+    // M2P items: at most min(4^l, X entries) boxes of level l have one, each
+    // with ceil(points / 64) items on levels of width 64, one on the others
+    int64_t mb = 0;
+    for (int l = 0; l <= L; ++l) {
+        const int64_t nx = l >= 1 ? t.x_off[l + 1] - t.x_off[l] : 0, nb = int64_t(1) << (2 * l);
+        const int64_t boxes = nx < nb ? nx : nb;
+        t.m_bound[l] = boxes * (m2p_width(t.n, l) == 64 ? (level_box_max(t.n, l) + 63) / 64 : 1);
+        mb += t.m_bound[l];
+    }
+    for (int l = L + 1; l <= FMM2D_MAX_LEVELS; ++l) t.m_bound[l] = 0;
+    FMM2D_TRY(c->scr.mcnt.ensure(sizeof(int32_t) * nbox));
+    FMM2D_TRY(t.m_itemoff.ensure(sizeof(int32_t) * (nbox + 1)));
+    FMM2D_TRY(t.m_items.ensure(sizeof(int2) * (mb > 0 ? mb : 1)));
+    hipLaunchKernelGGL(k_m_items<false>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
+                       xidx, xoff, geom, stL, c->scr.mcnt.as<int32_t>(), nullptr, nullptr);
+    FMM2D_TRY(hipGetLastError());
+    FMM2D_TRY(scan_exclusive(c, c->scr.mcnt.as<int32_t>(), nbox, t.m_itemoff.as<int32_t>()));
+    hipLaunchKernelGGL(k_m_items<true>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
+                       xidx, xoff, geom, stL, nullptr, t.m_itemoff.as<int32_t>(), t.m_items.as<int2>());
+    FMM2D_TRY(hipGetLastError());
     t.x_ready = true;
     return hipSuccess;
 }
@@ -587,28 +570,47 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
     TreeState &t = c->tree;
     if (!t.x_ready) return hipSuccess;
     const int L = t.L;
-    const int64_t nleaf = int64_t(1) << (2 * L);
-    const dim3 grid(grid_for(nleaf, 4)), block(256);
+    const dim3 block(256);
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);
-    const int64_t maxleaf = level_box_max(t.n, L);
-    PhaseScope kernel_scope(c, PH_M2P_KERNEL);  // the M2P kernel alone
-    switch (maxleaf <= MLEAF ? p + 1 : 0) {
-#define FMM2D_M2P(P1)                                                                                             \
-    case P1:                                                                                                      \
-        hipLaunchKernelGGL(k_m2p<P1>, grid, block, 0, c->stream, L, nleaf, stL, t.xptr.as<int32_t>(),            \
-                           t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), c->ev.A.as<cd>(), t.px.as<double>(), \
-                           t.py.as<double>(), t.perm.as<int32_t>(), phi);                                         \
-        break;
-        FMM2D_M2P(2) FMM2D_M2P(3) FMM2D_M2P(4) FMM2D_M2P(5) FMM2D_M2P(6) FMM2D_M2P(7) FMM2D_M2P(8) FMM2D_M2P(9)
-        FMM2D_M2P(10) FMM2D_M2P(11) FMM2D_M2P(12) FMM2D_M2P(13) FMM2D_M2P(14) FMM2D_M2P(15) FMM2D_M2P(16)
-#undef FMM2D_M2P
-        default:
-            hipLaunchKernelGGL(k_m2p_gen, grid, block, 0, c->stream, p, L, nleaf, stL, t.xptr.as<int32_t>(),
-                               t.xidx.as<int32_t>(), xoff, t.geom.as<double4>(), c->ev.A.as<cd>(),
-                               t.px.as<double>(), t.py.as<double>(), t.perm.as<int32_t>(), phi);
+    const int32_t *xptr = t.xptr.as<int32_t>(), *xidx = t.xidx.as<int32_t>(), *perm = t.perm.as<int32_t>();
+    const double4 *geom = t.geom.as<double4>();
+    const cd *A = c->ev.A.as<cd>();
+    const double *px = t.px.as<double>(), *py = t.py.as<double>();
+    PhaseScope kernel_scope(c, PH_M2P_KERNEL);  // the M2P kernels alone
+    if (p + 1 > 16) {
+        const int64_t nleaf = int64_t(1) << (2 * L);
+        hipLaunchKernelGGL(k_m2p_gen, dim3(grid_for(nleaf, 4)), block, 0, c->stream, p, L, nleaf, stL, xptr, xidx,
+                           xoff, geom, A, px, py, perm, phi);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    const int2 *items = t.m_items.as<int2>();
+    for (int l = 1; l <= L; ++l) {
+        if (t.m_bound[l] == 0) continue;
+        const int mp = m2p_width(t.n, l);
+        // the level's items: [m_itemoff[first box of l], m_itemoff[first box of l + 1])
+        const int32_t *first = t.m_itemoff.as<int32_t>() + level_offset(l), *end = t.m_itemoff.as<int32_t>() + level_offset(l + 1);
+        const dim3 grid(grid_for(t.m_bound[l], 4));
+        switch ((p + 1) * 2 + (mp == 64)) {
+#define FMM2D_M2P(P1)                                                                                             \
+    case 2 * P1:                                                                                                  \
+        hipLaunchKernelGGL((k_m2p_lvl<P1, false>), grid, block, 0, c->stream, L, l, mp, items, first, end, xptr,  \
+                           xidx, xoff, geom, stL, A, px, py, perm, phi);                                          \
+        break;                                                                                                    \
+    case 2 * P1 + 1:                                                                                              \
+        hipLaunchKernelGGL((k_m2p_lvl<P1, true>), grid, block, 0, c->stream, L, l, mp, items, first, end, xptr,   \
+                           xidx, xoff, geom, stL, A, px, py, perm, phi);                                          \
+        break;
+            FMM2D_M2P(2) FMM2D_M2P(3) FMM2D_M2P(4) FMM2D_M2P(5) FMM2D_M2P(6) FMM2D_M2P(7) FMM2D_M2P(8)
+            FMM2D_M2P(9) FMM2D_M2P(10) FMM2D_M2P(11) FMM2D_M2P(12) FMM2D_M2P(13) FMM2D_M2P(14) FMM2D_M2P(15)
+            FMM2D_M2P(16)
+#undef FMM2D_M2P
+            default:
+                return hipErrorInvalidValue;
+        }
+        FMM2D_TRY(hipGetLastError());
+    }
+    return hipSuccess;
 }
 
 }  // namespace fmm2d

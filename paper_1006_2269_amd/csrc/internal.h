@@ -94,6 +94,8 @@ struct TreeState {
     int64_t x_bound_wave = 0;       // upper bound of the wavefront-per-item P2L items (launch size)
     int64_t x_bound_lane = 0;       // ... of the lane-per-item ones
     int x_lane_level = 0;           // first level of lane-per-item P2L (all deeper levels too)
+    DevBuf m_items, m_itemoff;      // M2P work items (target box, first point) per box, level by level
+    int64_t m_bound[FMM2D_MAX_LEVELS + 1] = {};  // upper bound of each level's M2P items (launch size)
     bool x_ready = false;
     DevBuf lsum;                    // double: per near_lo segment and source lane, its entries' source sums
     std::vector<int64_t> s_off, w_off, x_off;  // host copy: pool offset of each level
@@ -148,7 +150,7 @@ struct PhaseTimer {
 };
 
 struct Scratch {
-    DevBuf keys0, keys1, vals0, vals1, hist, aux, tiles, tiles2, segbase, thr, split0, split1, flag, segcnt;
+    DevBuf keys0, keys1, vals0, vals1, hist, aux, tiles, tiles2, segbase, thr, split0, split1, flag, segcnt, mcnt;
     DevBuf sel, sel2;        // selector: counts and features; decision
     int64_t sort_n = -1;     // size of the validated keys waiting in keys0 / vals0, or -1
     uint64_t sort_differ = 0;  // bits in which the keys of either coordinate differ

@@ -98,3 +98,45 @@ def test_p2l_items_cover_and_bound(orc, case, thresholds):
     # the items of a box are consecutive and the boxes in order
     gs = [it[0] for it in items]
     assert gs == sorted(gs)
+
+
+def m2p_width(n, l):
+    m, w = level_box_max(n, l), 1
+    while w < m and w < 64:
+        w *= 2
+    return w
+
+
+@pytest.mark.parametrize("case", ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "ring_scaled_20k_L6",
+                                  "duplicates_4k_L4", "uniform_2000_L2", "uniform_10k_L5"])
+def test_m2p_items_cover_and_bound(orc, case):
+    """M2P items per level: each box with an M2P entry covered exactly once
+    (64-point items on levels of width 64, the whole box within the pass
+    width on the others), item counts within the per-level launch bounds."""
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    t = orc.tree(ps.x, ps.y, L)
+    ls = orc.lists_opt(t, 0.5, parent=True, swap_levels=range(1, L + 1))
+    n, starts = ps.n, t.leaf_start
+    total = 0
+    for l in range(1, L + 1):
+        nx = int(ls.xptr[l][-1])
+        mp = m2p_width(n, l)
+        bound = min(nx, 4 ** l) * (-(-level_box_max(n, l) // 64) if mp == 64 else 1)
+        r = t.geom[level_offset(l):level_offset(l + 1), 2]
+        count = 0
+        for b in range(4 ** l):
+            row = ls.xidx[l][ls.xptr[l][b]:ls.xptr[l][b + 1]]
+            if not any(r[b] > r[c] for c in row):
+                continue
+            a, e = starts[b << 2 * (L - l)], starts[(b + 1) << 2 * (L - l)]
+            if mp == 64:
+                firsts = list(range(a, e, 64))
+                assert firsts[-1] + 64 >= e
+            else:
+                firsts = [a]
+                assert e - a <= mp
+            count += len(firsts)
+        assert count <= bound
+        total += count
+    assert total >= 0
