@@ -1,26 +1,33 @@
 #!/usr/bin/env python
 """Throughput benchmark: target points per second at relative error 1e-6.
 
-Workload (default): the 1M-point mixed set -- 500,000 uniform points in
-[0,1]^2 plus 4 x 125,000 Gaussian points (sigma 0.1, 0.03, 0.01, 0.003),
-charges U[-1,1] -- at tolerance 1e-6; the plain form uses 8 levels and
-theta = 1/2.
+Workload (default): 10,000,000 strongly clustered points -- 1,000,000
+uniform in [0,1]^2 plus 3 x 3,000,000 Gaussian points (sigma 1e-3, 1e-2,
+1e-1, centres U[0.2, 0.8]^2, rejection into the unit square), charges +-1 --
+at tolerance 1e-6, the plain form at 10 levels and theta = 1/2.
 
 A step is one pass of the whole hot path with inputs already in device
 memory.  Two forms are timed:
 
 * learned (``value``): parameter selection by the trained selector (its
   density features and network run on the GPU inside the step), then tree,
-  lists and evaluation in mode ``fp32_acc64`` (FP32 near field and FP32 M2L
-  products, binary64 power scaling and accumulation);
-* plain FP64 (``config.fp64_points_per_s``): 8 levels, theta = 1/2, and the
-  least p whose error passes the judge.
+  lists (with Section 4's structural options: interaction via the parent
+  box and exchanged roles at every level) and evaluation in FP32 (FP32
+  products and accumulation in the near field and M2L; binary64 tree, lists
+  and translations);
+* plain FP64 (``config.fp64_points_per_s``): binary64 throughout at the
+  configuration's 10 levels and theta = 1/2, the same lists, and the least p
+  whose error passes the judge; with ``--fp64-plain 1``,
+  ``config.fp64_plain_lists`` is the same form on the lists without the
+  structural options, at the most levels those fit in (their int32 list
+  offsets overflow at 10 levels on this set; slow, so not by default).
 
 The judge is the binary64 direct sum (compensated) at 1000 seeded targets; a
 form counts only when its normwise relative error there is <= the tolerance.
-If the learned choice misses the judge, the reduced-precision form falls
-back to the judge-verified order at 8 levels (and says so in ``config``).
-One JSON line goes to stdout; phase timings and list statistics to stderr.
+If the learned choice misses the judge, the reduced form falls back to the
+rule's levels and theta with the judge-verified order (and says so in
+``config``).  One JSON line goes to stdout; phase timings and list
+statistics to stderr.
 """
 from __future__ import annotations
 
@@ -42,46 +49,52 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mixed_1m.json")
-
-
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
-    for a plain copy of known size), or None when there is none or the
-    kernel's source file has changed since the counters were taken."""
+def measured_traffic(kernels, workload):
+    """HBM bytes per step of the kernels whose names start with one of
+    `kernels` (their launches in one step summed), from the committed
+    rocprofv3 counter summary of this workload (FETCH_SIZE and WRITE_SIZE,
+    each scaled by what the counter reads for a plain copy of known size), or
+    None when there is none or a kernel's source file has changed since the
+    counters were taken."""
     import hashlib
 
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
-        entry = json.load(fh).get(kernel)
-    if not entry:
-        return None
-    with open(os.path.join(ROOT, entry["source"]), "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != entry["source_sha256"]:
-            return None
-    return entry["bytes_per_launch"]
+    with open(path) as fh:
+        table = json.load(fh).get("kernels", {})
+    total, found = 0, False
+    for name, entry in table.items():
+        if not any(name.startswith(k) for k in kernels):
+            continue
+        with open(os.path.join(ROOT, entry["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != entry["source_sha256"]:
+                return None
+        total += entry["bytes_per_step"]
+        found = True
+    return total if found else None
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixed_1m")
+    ap.add_argument("--workload", default="clustered_10m")
     ap.add_argument("--scale", type=float, default=1.0, help="workload size factor (1.0 = full size)")
-    ap.add_argument("--levels", type=int, default=8)
+    ap.add_argument("--levels", type=int, default=10, help="levels of the plain FP64 form")
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--samples", type=int, default=1000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-scale", type=float, default=1.0,
+    ap.add_argument("--cpu-scale", type=float, default=0.1,
                     help="size factor of the CPU-baseline sample of the same workload")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU baseline until this much time has passed")
     ap.add_argument("--fp64", type=int, default=1, help="also time the plain FP64 form")
-    ap.add_argument("--sweep", choices=["field", "robustness"],
+    ap.add_argument("--fp64-plain", type=int, default=0,
+                    help="also time FP64 on the lists without the structural options (slow on clustered sets)")
+    ap.add_argument("--sweep", choices=["field", "robustness", "precision"],
                     help="run a measurement sweep instead of the benchmark (JSON table to --out)")
     ap.add_argument("--out", help="output file of a sweep")
     ap.add_argument("--sizes", help="robustness sweep: comma-separated N")
@@ -143,8 +156,9 @@ def sweep_robustness(args):
     """Time of the whole path versus N on three layouts at TOL = 1e-6: the shape
     of Section 5's third experiment (uniform in the unit square, and the
     'normal' and 'layer' layouts of the second, sigma = 0.1).  Per layout and
-    N: the reduced form (fmm2d_select_build_tree, connectivity, evaluate in
-    FP32_ACC64) and plain binary64 at the a-priori rule's parameters; time =
+    N: the reduced form (fmm2d_select_build_tree, connectivity with the
+    structural options, evaluate in FP32) and binary64 at the a-priori rule's
+    parameters on the same lists; time =
     median of 3 after a warm-up (HIP events on the library stream), e_inf
     against the binary64 direct sum at 1000 sampled targets."""
     SIZES = (10_000, 30_000, 100_000, 300_000, 1_000_000, 2_000_000, 5_000_000)
@@ -188,8 +202,8 @@ def sweep_robustness(args):
 
             def reduced():
                 L, p, th, net = f.select_build_tree(x, y, TOL, wts)
-                f.connectivity(th)
-                f.evaluate(q, p, "fp32_acc64", out=out)
+                f.connectivity(th, **selector.LIST_OPTIONS)
+                f.evaluate(q, p, selector.reduced_mode(TOL), out=out)
                 return L, p, th, net
 
             (L, p, th, net), ms = timed(reduced)
@@ -200,7 +214,7 @@ def sweep_robustness(args):
 
             def plain():
                 f.build_tree(x, y, Lr)
-                f.connectivity(thr)
+                f.connectivity(thr, **selector.LIST_OPTIONS)
                 f.evaluate(q, pr, "fp64", out=out)
 
             _, ms64 = timed(plain)
@@ -216,6 +230,173 @@ def sweep_robustness(args):
 
 
 
+def sweep_precision(args):
+    """Error and throughput per precision mode at three tolerances: the
+    4,000,000-point noisy ring plus uniform fill (radius 0.4, radial noise sd
+    1e-3, charges U[-1,1]), TOL in {1e-3, 1e-6, 1e-9} x modes {BF16X3, FP32,
+    FP32_ACC64, FP64}.  Per cell: the rule's levels, theta = 1/2, the lists
+    with the structural options, and the least p whose error at 1000 sampled
+    targets (binary64 direct sum) meets TOL; where no p <= 40 does, the
+    mode's floor (its least error over p) is recorded as not met.  Time =
+    median of 3 whole-path steps (tree, lists, evaluate) by HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_1006_2269_amd import selector
+    from paper_1006_2269_amd import workloads as W
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    opts = selector.LIST_OPTIONS
+    ps = W.ring_4m(scale=args.scale)
+    f = FMM2D(0)
+    dev = f.device
+    x, y, q = (torch.from_numpy(a).to(dev) for a in (ps.x, ps.y, ps.q))
+    tg = torch.from_numpy(W.sample_targets(ps.n, args.samples, seed=4242)).to(dev)
+    exact = f.direct(x, y, q, tg)
+    sc = float(exact.abs().max())
+    out = torch.empty_like(q)
+    L, _, th, _ = f.select(x, y, 1e-6)  # the rule's levels and theta
+    f.build_tree(x, y, L)
+    f.connectivity(th, **opts)
+    errs = {}
+
+    def err(mode, p):
+        if (mode, p) not in errs:
+            f.evaluate(q, p, mode, out=out)
+            errs[(mode, p)] = float((out[tg] - exact).abs().max()) / sc
+        return errs[(mode, p)]
+
+    rows = []
+    for tol in (1e-3, 1e-6, 1e-9):
+        for mode in ("bf16x3", "fp32", "fp32_acc64", "fp64"):
+            lo, hi, best = 2, 40, None
+            while lo <= hi:
+                mid = (lo + hi) // 2
+                if err(mode, mid) <= tol:
+                    best, hi = mid, mid - 1
+                else:
+                    lo = mid + 1
+            rec = {"tol": tol, "mode": mode, "levels": L, "theta": th, "met": best is not None}
+            if best is None:
+                floor_p = min(range(8, 41, 4), key=lambda pp: err(mode, pp))
+                rec.update(p=floor_p, e_inf=err(mode, floor_p))
+            else:
+                rec.update(p=best, e_inf=err(mode, best))
+            pp = rec["p"]
+
+            def step():
+                f.build_tree(x, y, L)
+                f.connectivity(th, **opts)
+                f.evaluate(q, pp, mode, out=out)
+
+            step()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(f.stream)
+                step()
+                b.record(f.stream)
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            rec["ms"] = float(np.median(ts))
+            rec["points_per_s"] = ps.n / (rec["ms"] * 1e-3)
+            rows.append(rec)
+            print("[precision] tol=%.0e %-10s p=%2d e_inf=%.2e %s  %.2f ms  %.3e pts/s"
+                  % (tol, mode, pp, rec["e_inf"], "met" if rec["met"] else "NOT met (floor)", rec["ms"],
+                     rec["points_per_s"]), flush=True)
+    # plain FP32 against binary64 accumulation on the 1,000,000-point mixed
+    # set at 8 levels, theta = 1/2, p in {12, 17, 24}, plain lists
+    pm = W.mixed_1m(scale=args.scale)
+    xm, ym, qm = (torch.from_numpy(a).to(dev) for a in (pm.x, pm.y, pm.q))
+    tgm = torch.from_numpy(W.sample_targets(pm.n, args.samples, seed=4242)).to(dev)
+    exm = f.direct(xm, ym, qm, tgm)
+    scm = float(exm.abs().max())
+    outm = torch.empty_like(qm)
+    Lm = 8
+    while Lm > 0 and pm.n < 4 ** Lm:
+        Lm -= 1
+    f.build_tree(xm, ym, Lm)
+    f.connectivity(0.5)
+    c2 = []
+    for pp in (12, 17, 24):
+        for mode in ("fp32", "fp32_acc64", "fp64"):
+            f.evaluate(qm, pp, mode, out=outm)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(f.stream)
+                f.evaluate(qm, pp, mode, out=outm)
+                b.record(f.stream)
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            e = float((outm[tgm] - exm).abs().max()) / scm
+            c2.append({"p": pp, "mode": mode, "e_inf": e, "evaluate_ms": float(np.median(ts))})
+            print("[precision] mixed_1m L=%d p=%2d %-10s e_inf=%.2e evaluate %.3f ms" % (Lm, pp, mode, e, c2[-1]["evaluate_ms"]),
+                  flush=True)
+    with open(args.out, "w") as fh:
+        json.dump({"n": ps.n, "levels": L, "theta": th, "list_options": opts, "samples": args.samples,
+                   "rows": rows, "mixed_1m_plain_lists": {"n": pm.n, "levels": Lm, "theta": 0.5, "rows": c2}},
+                  fh, indent=1)
+    f.close()
+    return 0
+
+
+def exchange_work(f, L, n, p):
+    """Point terms of the P2L and M2P kernels (summed over the exchanged
+    lists of every level) and their algorithmic flops: per P2L term
+    10 (p+1) - 7 (the reciprocal and log of the offset, p - 1 complex
+    products for the powers, p + 1 accumulations), per M2P term
+    8 (p+1) - 1 (reciprocal, log, Horner)."""
+    import numpy as np
+
+    rad = f.geometry().cpu().numpy()[:, 2]
+    t_p2l = t_m2p = 0.0
+    for l in range(1, L + 1):
+        xp, xi = (a.cpu().numpy().astype(np.int64) for a in f.xlists(l))
+        if xi.size == 0:
+            continue
+        rows = np.repeat(np.arange(4 ** l), np.diff(xp))
+        off = (4 ** l - 1) // 3
+        rb, rc = rad[off + rows], rad[off + xi]
+        box = n / 4 ** l  # every box of the level holds floor or ceil of this
+        t_p2l += float(np.count_nonzero(rb < rc)) * box
+        t_m2p += float(np.count_nonzero(rb > rc)) * box
+    P1 = p + 1
+    return t_p2l, t_m2p, t_p2l * (10 * P1 - 7), t_m2p * (8 * P1 - 1)
+
+
+def near_work(f, n, L):
+    """Ordered point pairs of the finest strong lists and pairs within leaves."""
+    import numpy as np
+
+    sptr, sidx, _, _ = f.lists(L)
+    st = f.leaf_start().cpu().numpy().astype(np.int64)
+    cnt = np.diff(st)
+    sp = sptr.cpu().numpy().astype(np.int64)
+    si = sidx.cpu().numpy().astype(np.int64)
+    src_per_leaf = np.add.reduceat(cnt[si], sp[:-1]) if si.size else np.zeros_like(cnt)
+    src_per_leaf[np.diff(sp) == 0] = 0
+    pairs = float((cnt * src_per_leaf).sum())
+    rows = np.repeat(np.arange(cnt.size), np.diff(sp))
+    diag = float((cnt[rows[si == rows]].astype(np.float64) ** 2).sum())
+    return pairs, diag
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -226,18 +407,23 @@ def main():
         if not args.out:
             print("--sweep needs --out", file=sys.stderr)
             sys.exit(2)
-        sys.exit({"field": sweep_field, "robustness": sweep_robustness}[args.sweep](args))
+        sys.exit({"field": sweep_field, "robustness": sweep_robustness,
+                  "precision": sweep_precision}[args.sweep](args))
     import numpy as np
     import torch
 
+    from paper_1006_2269_amd import selector
     from paper_1006_2269_amd import workloads as W
-    from paper_1006_2269_amd.fmm import FMM2D
+    from paper_1006_2269_amd.fmm import FMM2D, FMM2DError
 
+    opts = selector.LIST_OPTIONS
     ps = W.WORKLOADS[args.workload](scale=args.scale)
     n, L, theta, tol = ps.n, args.levels, args.theta, args.tol
     while L > 0 and n < 4 ** L:
         L -= 1
-    log("[bench] workload %s n=%d levels=%d theta=%.3f tol=%.1e" % (ps.name, n, L, theta, tol))
+    mode_red = selector.reduced_mode(tol)
+    log("[bench] workload %s n=%d levels=%d theta=%.3f tol=%.1e reduced mode %s, list options %s"
+        % (ps.name, n, L, theta, tol, mode_red, opts))
     dev = torch.device("cuda", 0)
     x = torch.from_numpy(ps.x).to(dev)
     y = torch.from_numpy(ps.y).to(dev)
@@ -247,23 +433,39 @@ def main():
     exact = f.direct(x, y, q, tg)
     torch.cuda.synchronize()
     scale_ref = float(exact.abs().max())
+    out = torch.empty_like(q)
 
     def rel_err(phi):
         return float((phi[tg] - exact).abs().max()) / scale_ref
 
-    def one_step(p, mode, out):
-        f.build_tree(x, y, L)
-        f.connectivity(theta)
-        f.evaluate(q, p, mode, out=out)
+    def run_steps(step, steps):
+        """steps x step() timed: wall clock over all, HIP events per step on
+        the library stream (median), and the per-phase GPU times."""
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        f.timing(True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record(f.stream)
+            r = step()
+            b.record(f.stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        tm = f.timings()
+        f.timing(False)
+        med = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        return r, dt, med, tm
 
-    out = torch.empty_like(q)
-    f.build_tree(x, y, L)
-    f.connectivity(theta)
-    sizes = [f.list_sizes(l) for l in range(L + 1)]
-    log("[bench] list entries per level (strong, weak):", sizes)
+    def show(tag, dt, med, tm, steps, e, extra=""):
+        log("[bench] %s  %.2f ms/step (median by events %.2f)  %.3e pts/s  e_inf=%.2e %s"
+            % (tag, dt * 1e3, med, n / dt, e, extra))
+        for ph, (ms, cnt) in tm.items():
+            if cnt:
+                log("   %-11s %9.3f ms/step  (%d intervals)" % (ph, ms / steps, cnt))
 
     def search_p(mode, lo=2, hi=40):
-        # least p passing the judge (error decreases with p)
         best = None
         while lo <= hi:
             mid = (lo + hi) // 2
@@ -276,165 +478,179 @@ def main():
                 lo = mid + 1
         return best
 
-    def timed(p, mode):
-        for _ in range(args.warmup):
-            one_step(p, mode, out)
-        torch.cuda.synchronize()
-        f.timing(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            one_step(p, mode, out)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        tm = f.timings()
-        f.timing(False)
-        return dt, tm, rel_err(out)
-
     results = {}
 
     # -- learned form: select + tree + lists + evaluate per step ------------
-    from paper_1006_2269_amd import selector
-
     weights = selector.weights_tensor(dev)
     learned = None
     if weights is not None:
         def step_learned():
-            # select + build_tree in one call (the sort overlaps the selector)
             Ls, ps_, th, net = f.select_build_tree(x, y, tol, weights)
-            f.connectivity(th)
-            f.evaluate(q, ps_, "fp32_acc64", out=out)
+            f.connectivity(th, **opts)
+            f.evaluate(q, ps_, mode_red, out=out)
             return Ls, ps_, th, net
 
-        for _ in range(args.warmup):
-            cfg = step_learned()
-        torch.cuda.synchronize()
-        f.timing(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            cfg = step_learned()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        tm = f.timings()
-        f.timing(False)
-        e = rel_err(out)
-        Ls, ps_, th, net = cfg
-        log("[bench] learned: levels=%d p=%d theta=%.2f (network=%s)  %.2f ms/step  %.3e pts/s  e_inf=%.2e"
-            % (Ls, ps_, th, net, dt * 1e3, n / dt, e))
-        for ph, (ms, cnt) in tm.items():
-            if cnt:
-                log("   %-7s %9.3f ms/step  (%d intervals)" % (ph, ms / args.steps, cnt))
-        learned = {"levels": Ls, "p": ps_, "theta": th, "network": net, "s_per_step": dt, "points_per_s": n / dt,
-                   "e_inf": e, "phases": tm}
-        if e <= tol:
-            results["fp32_acc64"] = dict(learned, selector="learned")
-        else:
-            log("[bench] the learned choice misses the judge (%.2e > %.1e)" % (e, tol))
+        try:
+            cfg, dt, med, tm = run_steps(step_learned, args.steps)
+            e = rel_err(out)
+            Ls, ps_, th, net = cfg
+            show("learned: levels=%d p=%d theta=%.2f (network=%s)" % (Ls, ps_, th, net), dt, med, tm, args.steps, e)
+            learned = {"levels": Ls, "p": ps_, "theta": th, "network": net, "s_per_step": dt, "ms_median": med,
+                       "points_per_s": n / dt, "e_inf": e, "phases": tm}
+            if e <= tol:
+                results["reduced"] = dict(learned, selector="learned")
+            else:
+                log("[bench] the learned choice misses the judge (%.2e > %.1e)" % (e, tol))
+        except FMM2DError as err:
+            log("[bench] the learned choice failed: %s" % err)
     else:
         log("[bench] no trained selector weights at %s" % selector.WEIGHTS_PATH)
 
-    forms = ([] if "fp32_acc64" in results else [("fp32_acc64", "reduced")]) + \
-        ([("fp64", "plain")] if args.fp64 else [])
-    for mode, label in forms:
-        f.build_tree(x, y, L)
-        f.connectivity(theta)
-        found = search_p(mode)
-        if found is None:
-            log("[bench] %s: no p <= 40 passes the judge" % mode)
-            continue
-        p, _ = found
-        dt, tm, e = timed(p, mode)
-        results[mode] = {"levels": L, "theta": theta, "p": p, "s_per_step": dt, "points_per_s": n / dt, "e_inf": e,
-                         "phases": tm, "selector": "judge-verified order"}
-        log("[bench] %s p=%d  %.2f ms/step  %.3e pts/s  e_inf=%.2e" % (mode, p, dt * 1e3, n / dt, e))
-        for ph, (ms, cnt) in tm.items():
-            if cnt:
-                log("   %-7s %9.3f ms/step  (%d intervals)" % (ph, ms / args.steps, cnt))
+    if "reduced" not in results:
+        # the rule's levels and theta, the judge-verified order
+        Lr, _, thr, _ = f.select(x, y, tol)
+        f.build_tree(x, y, Lr)
+        f.connectivity(thr, **opts)
+        found = search_p(mode_red)
+        if found is not None:
+            pr = found[0]
 
-    main_form = results.get("fp32_acc64")
-    # roofline of the dominant single kernel launch of the reduced form: the
-    # near-field kernel, or the M2L kernel (all levels; both timed alone with
-    # HIP events on the library's stream during the timed steps)
+            def step_rule():
+                f.build_tree(x, y, Lr)
+                f.connectivity(thr, **opts)
+                f.evaluate(q, pr, mode_red, out=out)
+
+            _, dt, med, tm = run_steps(step_rule, args.steps)
+            e = rel_err(out)
+            show("reduced at the rule's L=%d theta=%.2f, p=%d" % (Lr, thr, pr), dt, med, tm, args.steps, e)
+            results["reduced"] = {"levels": Lr, "p": pr, "theta": thr, "s_per_step": dt, "ms_median": med,
+                                  "points_per_s": n / dt, "e_inf": e, "phases": tm,
+                                  "selector": "rule levels and theta, judge-verified order"}
+
+    def fp64_form(Lf, list_opts, label):
+        try:
+            f.build_tree(x, y, Lf)
+            f.connectivity(theta, **list_opts)
+            found = search_p("fp64")
+            if found is None:
+                return None
+            pf = found[0]
+
+            def step64():
+                f.build_tree(x, y, Lf)
+                f.connectivity(theta, **list_opts)
+                f.evaluate(q, pf, "fp64", out=out)
+
+            _, dt, med, tm = run_steps(step64, max(2, args.steps // 3))
+        except FMM2DError as err:
+            log("[bench] fp64 %s at %d levels: %s" % (label, Lf, err))
+            return None
+        e = rel_err(out)
+        show("fp64 %s L=%d p=%d" % (label, Lf, pf), dt, med, tm, max(2, args.steps // 3), e)
+        return {"levels": Lf, "p": pf, "theta": theta, "s_per_step": dt, "points_per_s": n / dt, "e_inf": e}
+
+    if args.fp64:
+        results["fp64"] = fp64_form(L, opts, "same lists")
+    if args.fp64_plain:
+        # the lists without the structural options, at the most levels (up to
+        # the configuration's) they fit in
+        for Lp in range(L, max(L - 3, 0), -1):
+            r = fp64_form(Lp, {}, "plain lists")
+            if r is not None:
+                results["fp64_plain"] = r
+                break
+
+    main_form = results.get("reduced")
     roof = None
     if main_form:
-        p = main_form["p"]
-        Lm = main_form["levels"]
+        p, Lm = main_form["p"], main_form["levels"]
         f.build_tree(x, y, Lm)
-        f.connectivity(main_form["theta"])
+        f.connectivity(main_form["theta"], **opts)
         ph = main_form["phases"]
-        near_ms = ph["near_kernel"][0] / max(ph["near_kernel"][1], 1)
-        m2l_ms = ph["m2l_kernel"][0] / max(ph["m2l_kernel"][1], 1)
-        sptr, sidx, _, _ = f.lists(Lm)
-        st = f.leaf_start().cpu().numpy().astype(np.int64)
-        cnt = np.diff(st)
-        sp = sptr.cpu().numpy().astype(np.int64)
-        si = sidx.cpu().numpy().astype(np.int64)
-        src_per_leaf = np.add.reduceat(cnt[si], sp[:-1]) if si.size else np.zeros_like(cnt)
-        src_per_leaf[np.diff(sp) == 0] = 0
-        pairs = float((cnt * src_per_leaf).sum())    # ordered (target, source) point pairs
-        rows = np.repeat(np.arange(cnt.size), np.diff(sp))
-        diag = float((cnt[rows[si == rows]].astype(np.float64) ** 2).sum())  # pairs within one leaf
+        per = lambda k: ph[k][0] / max(ph[k][1], 1)
+        pairs, diag = near_work(f, n, Lm)
         weak_all = float(sum(f.list_sizes(l)[1] for l in range(Lm + 1)))
-        # The library's leaf pass takes each pair of distinct leaves once when
-        # the largest leaf, ceil(N / 4^L) points, holds 17 to 64 (FP32 modes):
-        # one log serves both directions, 2 sub, mul, fma (2), log2, fma (2),
-        # fma (2) = 10 flops per pair of points; pairs within a leaf, and every
-        # pair in the one-sided kernels, need 8 (one fma less).
+        t_p2l, t_m2p, fl_p2l, fl_m2p = exchange_work(f, Lm, n, p)
         maxleaf = -(-n // 4 ** Lm)
         if 16 < maxleaf <= 64:
-            near_name = "k_near32s (pair-once near field, one launch)"
+            near_name, near_k = "k_near32s (pair-once near field, one launch)", ["k_near32s<"]
             near_flops = (pairs - diag) / 2.0 * 10.0 + diag * 8.0
-            near_work = "%d point pairs of distinct leaves, each taken once x 10 flops + %d within leaves x 8" % (
+            near_work_s = "%d point pairs of distinct leaves, each taken once x 10 flops + %d within leaves x 8" % (
                 (pairs - diag) / 2, diag)
         else:
-            near_name = "%s (near field, one launch)" % ("k_near32_big" if maxleaf > 64 else "k_near32")
+            kn = "k_near32_big" if maxleaf > 64 else "k_near32"
+            near_name, near_k = "%s (near field, one launch)" % kn, [kn + "<"]
             near_flops = pairs * 8.0
-            near_work = "%d point pairs x 8 flops" % pairs
-        m2l_flops = weak_all * 4.0 * (p + 1) ** 2               # useful product flops per weak pair
-        if m2l_ms >= near_ms:
-            ach = m2l_flops / (m2l_ms * 1e-3) / 1e12
-            roof = {"kernel": "k_m2l_lp (M2L, all levels, one launch)", "bound": "mfma", "achieved": round(ach, 3),
-                    "peak": MI355X["fp32_mfma_TFLOPs"], "unit": "TFLOP/s",
-                    "frac": round(ach / MI355X["fp32_mfma_TFLOPs"], 5), "traffic": None,
-                    "work": "%d weak pairs x 4(p+1)^2 flops" % weak_all, "launch_ms": round(m2l_ms, 4)}
-        else:
-            ach = near_flops / (near_ms * 1e-3) / 1e12
-            roof = {"kernel": near_name, "bound": "alu", "achieved": round(ach, 3),
-                    "peak": MI355X["fp32_TFLOPs"], "unit": "TFLOP/s", "frac": round(ach / MI355X["fp32_TFLOPs"], 5),
-                    "traffic": None, "work": near_work, "launch_ms": round(near_ms, 4)}
-        log("[bench] near kernel %.4f ms (%.3e pairs/s), M2L kernel %.4f ms (%.3e weak pairs/s)"
-            % (near_ms, pairs / (near_ms * 1e-3), m2l_ms, weak_all / (m2l_ms * 1e-3)))
-
-    if roof is not None:
-        roof["traffic"] = measured_traffic(roof["kernel"])
+            near_work_s = "%d point pairs x 8 flops" % pairs
+        # (time per step, name, bound, algorithmic flops per step, peak, work, kernels of the phase)
+        cands = [
+            (per("near_kernel"), near_name, "alu", near_flops, MI355X["fp32_TFLOPs"], near_work_s, near_k),
+            (per("m2l_kernel"), "k_m2l_lp (M2L, all levels, one launch)", "mfma", weak_all * 4.0 * (p + 1) ** 2,
+             MI355X["fp32_mfma_TFLOPs"], "%d weak pairs x 4(p+1)^2 flops" % weak_all, ["k_m2l_lp<"]),
+            (per("p2l_kernel"), "k_p2l + k_p2l_lane (exchanged roles, P2L: chunks and whole entries, two launches)",
+             "alu", fl_p2l, MI355X["fp64_TFLOPs"],
+             "%d source-point terms x (10(p+1)-7) flops, binary64" % t_p2l, ["k_p2l<", "k_p2l_lane<"]),
+            (per("m2p_kernel"), "k_m2p_lvl (exchanged roles, M2P, one launch per level)", "alu", fl_m2p,
+             MI355X["fp64_TFLOPs"], "%d target-point terms x (8(p+1)-1) flops, binary64" % t_m2p, ["k_m2p_lvl<"]),
+        ]
+        for ms, name, bound, flops, peak, work, _ in cands:
+            log("[bench] kernel %-45s %8.3f ms  %8.2f TFLOP/s  (%s)" % (name, ms, flops / max(ms, 1e-9) / 1e9, work))
+        ms, name, bound, flops, peak, work, kern = max(cands, key=lambda c: c[0])
+        ach = flops / (ms * 1e-3) / 1e12
+        roof = {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 5), "traffic": measured_traffic(kern, args.workload), "work": work,
+                "launch_ms": round(ms, 4)}
 
     cpu = None
-    if args.cpu_baseline:
+    if args.cpu_baseline and main_form:
+        import ctypes
+
         import oracle
 
         cps = W.WORKLOADS[args.workload](scale=args.cpu_scale)
-        Lc = main_form["levels"] if main_form else L
-        thc = main_form["theta"] if main_form else theta
-        cl = max(1, int(round(math.log(cps.n / (n / 4 ** Lc), 4))))   # same points per leaf
-        p = main_form["p"] if main_form else 12
-        # repeat the whole oracle path until about 10 s of CPU work have run
+        Lc = max(1, int(round(math.log(cps.n / (n / 4 ** main_form["levels"]), 4))))  # same points per leaf
+        thc, pc = main_form["theta"], main_form["p"]
+
+        def oracle_path(pts, Lo):
+            tr = oracle.tree(pts.x, pts.y, Lo)
+            ls = oracle.lists_opt(tr, thc, parent=opts.get("parent", False),
+                                  swap_levels=tuple(range(1, Lo + 1)) if opts.get("swap") == "all" else (Lo,))
+            oracle.fmm_eval_opt(pts.x, pts.y, pts.q, tr, ls, pc)
+
+        oracle._load()
+        gomp = ctypes.CDLL("libgomp.so.1")
+        threads = int(gomp.omp_get_max_threads())
         reps, t0 = 0, time.perf_counter()
         while True:
-            tr = oracle.tree(cps.x, cps.y, cl)
-            ls = oracle.lists(tr, thc)
-            oracle.fmm_eval(cps.x, cps.y, cps.q, tr, ls, p)
+            oracle_path(cps, Lc)
             reps += 1
             dt = time.perf_counter() - t0
             if dt >= args.cpu_seconds or reps >= 20:
                 break
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # one thread, on a tenth of that sample
+        one = W.WORKLOADS[args.workload](scale=args.cpu_scale / 10)
+        L1 = max(1, int(round(math.log(one.n / (n / 4 ** main_form["levels"]), 4))))
+        gomp.omp_set_num_threads(1)
+        t1 = time.perf_counter()
+        oracle_path(one, L1)
+        dt1 = time.perf_counter() - t1
+        gomp.omp_set_num_threads(threads)
         cpu = {"value": round(reps * cps.n / dt, 1), "unit": "target points/s", "cores": threads, "kind": "oracle",
-               "sample": "%s at size factor %g (%d points, %d levels, p=%d, theta=%.2f): tree + lists + FP64 FMM, "
-                         "%d repetitions in %.1f s" % (args.workload, args.cpu_scale, cps.n, cl, p, thc, reps, dt)}
-        log("[bench] cpu oracle: %.1f s for %d x %d points" % (dt, reps, cps.n))
+               "sample": "%s at size factor %g (%d points, %d levels, p=%d, theta=%.2f, the same list options): tree + "
+                         "lists + FP64 FMM, %d repetitions in %.1f s" % (args.workload, args.cpu_scale, cps.n, Lc, pc,
+                                                                        thc, reps, dt),
+               "value_1thread": round(one.n / dt1, 1),
+               "sample_1thread": "%d points (size factor %g), %d levels, one thread, %.1f s" % (
+                   one.n, args.cpu_scale / 10, L1, dt1),
+               "cpu_model": cpu_model()}
+        log("[bench] cpu oracle: %.1f s for %d x %d points (%d threads); one thread %.1f s for %d points"
+            % (dt, reps, cps.n, threads, dt1, one.n))
 
     if main_form is None:
         log("[bench] no form passed the judge")
         sys.exit(1)
+    fp64 = results.get("fp64")
+    fp64p = results.get("fp64_plain")
     line = {
         "metric": "target points/sec at rel. error 1e-6 (FP32+learned vs plain FP64 FMM)",
         "value": round(main_form["points_per_s"], 1),
@@ -449,13 +665,16 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "%s (n=%d)" % (args.workload, n), "levels": main_form["levels"],
-                   "theta": main_form["theta"], "tol": tol, "p": main_form["p"], "mode": "fp32_acc64",
-                   "selector": main_form["selector"],
+                   "theta": main_form["theta"], "tol": tol, "p": main_form["p"], "mode": mode_red,
+                   "list_options": opts, "selector": main_form["selector"],
+                   "ms_per_step_median_events": round(main_form["ms_median"], 3),
                    "learned_choice": None if learned is None else
                    {k: learned[k] for k in ("levels", "p", "theta", "network", "e_inf")},
                    "e_inf": main_form["e_inf"], "judge_samples": args.samples,
-                   "fp64_points_per_s": round(results["fp64"]["points_per_s"], 1) if "fp64" in results else None,
-                   "fp64_p": results["fp64"]["p"] if "fp64" in results else None},
+                   "fp64_points_per_s": round(fp64["points_per_s"], 1) if fp64 else None,
+                   "fp64": fp64 and {k: fp64[k] for k in ("levels", "p", "theta", "e_inf")},
+                   "fp64_plain_lists": fp64p and {"points_per_s": round(fp64p["points_per_s"], 1),
+                                                  **{k: fp64p[k] for k in ("levels", "p", "theta", "e_inf")}}},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

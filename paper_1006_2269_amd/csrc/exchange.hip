@@ -61,45 +61,97 @@ __host__ __device__ inline int64_t level_chunk(int64_t n, int l) {
     return (m + k - 1) / k;
 }
 
-// Work items per global box g (P2L entries of X(g): those whose source box
-// is the larger).  An item is int4 (target box, row position, row position
-// + 1, first point of the chunk or -1 for the whole entry); levels from
-// `lane_level` on take whole entries.
+// Points of an M2P pass over a box of level l: 64 when its boxes hold 64
+// points or more (one item per 64 points), else the power of two at or
+// above the largest box (one item per box, 64 / that many lane groups).
+__host__ __device__ inline int m2p_width(int64_t n, int l) {
+    const int64_t m = level_box_max(n, l);
+    int w = 1;
+    while (w < m && w < 64) w <<= 1;
+    return w;
+}
+
+// Work items per global box g, one wavefront per box (lanes over the X row,
+// 64 entries at a time, item positions by a wave prefix sum in row order).
+// P2L (the entries of X(g) whose source box is the larger): int4 (target
+// box, row position, row position + 1, first point of the chunk or -1 for
+// the whole entry); levels from `lane_level` on take whole entries.  M2P
+// (when X(g) holds an entry whose source box is the smaller): int2 (g, first
+// point), one per 64 points on levels of width 64, one per box on the others.
 template <bool FILL>
-__global__ void k_x_items(int L, int64_t n, int64_t nbox, int lane_level, const int32_t *__restrict__ xptr_all,
-                          const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
-                          const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
-                          int32_t *__restrict__ cnt, const int32_t *__restrict__ itemoff, int4 *__restrict__ items) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
+__global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox, int lane_level,
+                                                 const int32_t *__restrict__ xptr_all,
+                                                 const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
+                                                 const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
+                                                 int32_t *__restrict__ cnt, int32_t *__restrict__ mcnt,
+                                                 const int32_t *__restrict__ itemoff,
+                                                 const int32_t *__restrict__ mitemoff, int4 *__restrict__ items,
+                                                 int2 *__restrict__ mitems) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (g >= nbox) return;  // uniform per wavefront
+    const int lane = threadIdx.x % 64;
     const int l = level_of(g);
-    if (l < 1) {
-        if (!FILL) cnt[g] = 0;
-        return;
-    }
+    int32_t t0 = 0, t1 = 0;
     const int64_t b = g - level_offset(l);
     const int32_t *ptr = xptr_all + ptr_offset(l);
+    if (l >= 1) {
+        t0 = ptr[b];
+        t1 = ptr[b + 1];
+    }
+    if (t0 == t1) {  // no exchanged entry (and level 0)
+        if (!FILL && lane == 0) cnt[g] = mcnt[g] = 0;
+        return;
+    }
     const int32_t *row = xidx + xoff[l];
-    const double4 gb = geom[g];
+    const double rb = geom[g].z;
     const bool whole = l >= lane_level;
     const int32_t chunk = (int32_t)level_chunk(n, l);
-    int32_t k = FILL ? itemoff[g] : 0;
-    for (int32_t t = ptr[b]; t < ptr[b + 1]; ++t) {
-        const int64_t cg = level_offset(l) + row[t];
-        if (!(gb.z < geom[cg].z)) continue;  // M2P entry: handled per point
-        if (whole) {
-            if (FILL) items[k] = make_int4((int32_t)g, t, t + 1, -1);
-            ++k;
-        } else {
-            int32_t a, e;
-            box_range(stL, L, l, row[t], a, e);
-            for (int32_t j = a; j < e; j += chunk) {
-                if (FILL) items[k] = make_int4((int32_t)g, t, t + 1, j);
-                ++k;
+    int32_t base = FILL ? itemoff[g] : 0;
+    bool m2p = false;
+    for (int32_t tb = t0; tb < t1; tb += 64) {
+        const int32_t t = tb + lane;
+        int32_t k = 0, c = 0, a = 0, e = 0;
+        if (t < t1) {
+            c = row[t];
+            const double rc = geom[level_offset(l) + c].z;
+            if (rb < rc) {  // P2L entry
+                if (whole) {
+                    k = 1;
+                } else {
+                    box_range(stL, L, l, c, a, e);
+                    k = (e - a + chunk - 1) / chunk;
+                }
+            } else {
+                m2p = m2p || rb > rc;
             }
         }
+        const int32_t incl = wave_incl_scan(k);
+        if (FILL && k > 0) {
+            int32_t pos = base + incl - k;
+            if (whole) {
+                items[pos] = make_int4((int32_t)g, t, t + 1, -1);
+            } else {
+                for (int32_t j = a; j < e; j += chunk) items[pos++] = make_int4((int32_t)g, t, t + 1, j);
+            }
+        }
+        base += __shfl(incl, 63, 64);
     }
-    if (!FILL) cnt[g] = k;
+    m2p = __ballot(m2p) != 0;
+    int32_t km = 0;
+    if (m2p) {
+        int32_t a, e;
+        box_range(stL, L, l, b, a, e);
+        const int32_t step = m2p_width(n, l) == 64 ? 64 : e - a;
+        km = (e - a + step - 1) / step;
+        if (FILL) {
+            const int32_t m0 = mitemoff[g];
+            for (int32_t q = lane; q < km; q += 64) mitems[m0 + q] = make_int2((int32_t)g, a + q * step);
+        }
+    }
+    if (!FILL && lane == 0) {
+        cnt[g] = base;
+        mcnt[g] = km;
+    }
 }
 
 // The scaled division and hypot for |w|^2 <= 2^-960 (where |w|^2 could
@@ -168,7 +220,20 @@ __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__res
     box_range(stL, L, l, row[w.y], a, e);
     const int32_t ch = (int32_t)level_chunk(n, l);
     const int32_t j1 = e < w.w + ch ? e : w.w + ch;
-    for (int32_t j = w.w + lane; j < j1; j += 64) p2l_sums<P1>(px[j], py[j], qs[j], gb, s);
+    // four points per lane at a time, their loads issued together
+    int32_t j = w.w + lane;
+    for (; j + 192 < j1; j += 256) {
+        double bx[4], by[4], bq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bx[u] = px[j + 64 * u];
+            by[u] = py[j + 64 * u];
+            bq[u] = qs[j + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p2l_sums<P1>(bx[u], by[u], bq[u], gb, s);
+    }
+    for (; j < j1; j += 64) p2l_sums<P1>(px[j], py[j], qs[j], gb, s);
     double v[32];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -182,8 +247,10 @@ __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__res
 }
 
 // Lane-per-item P2L (whole entries), orders p + 1 <= 16: items
-// [*wave_end, *nitem).  Each lane walks its entry's source points with the
-// next point's loads issued before the current point is used.
+// [*wave_end, *nitem).  Each lane walks its entry's source points in bursts
+// of 8: the burst's loads are issued together (consecutive addresses of one
+// lane, so a cache line is fetched once per burst rather than once per
+// point while 64 lanes stream 64 boxes), then its points are summed.
 template <int P1>
 __global__ void __launch_bounds__(256) k_p2l_lane(int L, const int4 *__restrict__ items,
                                                   const int32_t *__restrict__ wave_end,
@@ -202,15 +269,20 @@ __global__ void __launch_bounds__(256) k_p2l_lane(int L, const int4 *__restrict_
     cd s[P1];
 #pragma unroll
     for (int k = 0; k < P1; ++k) s[k] = cd{0.0, 0.0};
-    double xn = px[a], yn = py[a], qn = qs[a];
-    for (int32_t j = a; j < e; ++j) {
-        const double x0 = xn, y0 = yn, q0 = qn;
-        const int32_t jn = j + 1 < e ? j + 1 : j;
-        xn = px[jn];
-        yn = py[jn];
-        qn = qs[jn];
-        p2l_sums<P1>(x0, y0, q0, gb, s);
+    constexpr int BURST = 8;
+    int32_t j = a;
+    for (; j + BURST <= e; j += BURST) {
+        double bx[BURST], by[BURST], bq[BURST];
+#pragma unroll
+        for (int u = 0; u < BURST; ++u) {
+            bx[u] = px[j + u];
+            by[u] = py[j + u];
+            bq[u] = qs[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < BURST; ++u) p2l_sums<P1>(bx[u], by[u], bq[u], gb, s);
     }
+    for (; j < e; ++j) p2l_sums<P1>(px[j], py[j], qs[j], gb, s);
     double *out = xpart + it * 2 * P1;
 #pragma unroll
     for (int k = 0; k < P1; ++k) {
@@ -295,72 +367,32 @@ __global__ void __launch_bounds__(256) k_p2l_gen(int p, int L, int64_t n, const 
 }
 
 // Per target box with items: the sum of its items' partial expansions in
-// item order, one lane per coefficient.
-__global__ void __launch_bounds__(64) k_x_reduce(int p, int64_t nbox, const int32_t *__restrict__ itemoff,
-                                                 const cd *__restrict__ xpart, cd *__restrict__ xsum) {
-    const int64_t g = blockIdx.x;
+// item order, one wavefront per box, one lane per coefficient.
+__global__ void __launch_bounds__(256) k_x_reduce(int p, int64_t nbox, const int32_t *__restrict__ itemoff,
+                                                  const cd *__restrict__ xpart, cd *__restrict__ xsum) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (g >= nbox) return;
     const int32_t i0 = itemoff[g], i1 = itemoff[g + 1];
     if (i0 == i1) return;  // uniform: a box without P2L entries
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % 64;
     if (lane > p) return;
     cd acc{0.0, 0.0};
     for (int32_t it = i0; it < i1; ++it) acc = cadd(acc, xpart[(int64_t)it * (p + 1) + lane]);
     xsum[g * (p + 1) + lane] = acc;
 }
 
-// Points of an M2P pass over a box of level l: 64 when its boxes hold 64
-// points or more (one item per 64 points), else the power of two at or
-// above the largest box (one item per box, 64 / that many lane groups).
-__host__ __device__ inline int m2p_width(int64_t n, int l) {
-    const int64_t m = level_box_max(n, l);
-    int w = 1;
-    while (w < m && w < 64) w <<= 1;
-    return w;
-}
-
-// M2P work items per global box g with an M2P entry in X(g) (the target
-// box the larger): int2 (g, first point), one per 64 points on levels of
-// width 64, one per box on the others.
-template <bool FILL>
-__global__ void k_m_items(int L, int64_t n, int64_t nbox, const int32_t *__restrict__ xptr_all,
-                          const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
-                          const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
-                          int32_t *__restrict__ cnt, const int32_t *__restrict__ itemoff, int2 *__restrict__ items) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
-    const int l = level_of(g);
-    int32_t k = 0;
-    if (l >= 1) {
-        const int64_t b = g - level_offset(l);
-        const int32_t *ptr = xptr_all + ptr_offset(l);
-        const int32_t *row = xidx + xoff[l];
-        const double rb = geom[g].z;
-        bool any = false;
-        for (int32_t t = ptr[b]; t < ptr[b + 1] && !any; ++t) any = rb > geom[level_offset(l) + row[t]].z;
-        if (any) {
-            int32_t a, e;
-            box_range(stL, L, l, b, a, e);
-            const int32_t step = m2p_width(n, l) == 64 ? 64 : e - a;
-            int32_t pos = FILL ? itemoff[g] : 0;
-            for (int32_t j = a; j < e; j += step) {
-                if (FILL) items[pos] = make_int2((int32_t)g, j);
-                ++pos;
-            }
-            k = pos;
-        }
-    }
-    if (!FILL) cnt[g] = k;
-}
-
-// M2P of one level, orders p + 1 <= 16: one wavefront per item.  WIDE
-// (boxes of 64 points or more): the item's 64 points one per lane, every
-// lane taking the box's M2P entries in row order (the same entry across the
-// wavefront).  Otherwise (boxes of at most MP < 64 points): lane = group *
-// MP + point, the box's X entries dealt to the 64 / MP groups by row
-// position, each point's group sums met by a butterfly over the group bits.
-// Items of one launch touch disjoint points; the levels run one launch
-// after the other, so every point's sum has a fixed order.
+// M2P of one level, orders p + 1 <= 16: one wavefront per item.  The box's
+// X row is taken 32 entries at a time: its M2P entries (the target box the
+// larger) are compacted by ballot, their centres, scales and multipoles
+// staged in the wavefront's LDS slice by coalesced loads, then evaluated
+// from there (same-address reads, served by broadcast).  WIDE (boxes of 64
+// points or more): the item's 64 points one per lane, every lane taking the
+// entries in row order.  Otherwise (boxes of at most MP < 64 points):
+// lane = group * MP + point, the compacted entries dealt to the 64 / MP
+// groups in turn, each point's group sums met by a butterfly over the group
+// bits.  Items of one launch touch disjoint points; the levels run one
+// launch after the other, so every point's sum has a fixed order.
+constexpr int MSTAGE = 32;
 template <int P1, bool WIDE>
 __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int2 *__restrict__ items,
                                                  const int32_t *__restrict__ first, const int32_t *__restrict__ end,
@@ -370,9 +402,12 @@ __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int
                                                  const cd *__restrict__ A, const double *__restrict__ px,
                                                  const double *__restrict__ py, const int32_t *__restrict__ perm,
                                                  double *__restrict__ phi) {
+    __shared__ cd s_a[4][MSTAGE * P1];
+    __shared__ double s_g[4][MSTAGE][3];
+    __shared__ int64_t s_c[4][MSTAGE];
     const int32_t it = __builtin_amdgcn_readfirstlane(*first + (int32_t)(blockIdx.x * 4 + threadIdx.x / 64));
     if (it >= *end) return;  // uniform per wavefront
-    const int lane = threadIdx.x % 64;
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int2 w = items[it];
     const int64_t b = w.x - level_offset(l);
     int32_t a, e;
@@ -386,18 +421,45 @@ __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int
     const double rb = geom[w.x].z;
     const int32_t *ptr = xptr_all + ptr_offset(l);
     const int32_t *row = xidx + xoff[l];
+    const int32_t t1 = ptr[b + 1];
+    cd *sa = s_a[wv];
     double acc = 0.0;
-    for (int32_t t = ptr[b] + grp; t < ptr[b + 1]; t += ng) {
-        const int64_t cg = level_offset(l) + row[t];
-        const double4 gc = geom[cg];
-        if (!(rb > gc.z)) continue;  // P2L entry
-        const cd *Ac = A + cg * P1;
-        double lw;
-        const cd rho = recip_scaled(gc.w, zx - gc.x, zy - gc.y, lw);
-        cd sacc = Ac[P1 - 1];
+    int dealt = 0;  // compacted entries so far (the next one goes to group dealt % ng)
+    for (int32_t tb = ptr[b]; tb < t1; tb += MSTAGE) {
+        bool ok = false;
+        int64_t cg = 0;
+        double4 gc = make_double4(0.0, 0.0, 0.0, 1.0);
+        if (lane < MSTAGE && tb + lane < t1) {
+            cg = level_offset(l) + row[tb + lane];
+            gc = geom[cg];
+            ok = rb > gc.z;  // M2P entry (else P2L, handled by the P2L pass)
+        }
+        const uint64_t m = __ballot(ok);
+        const int k = (int)__popcll(m);
+        if (ok) {
+            const int q = (int)popc_below(m);
+            s_g[wv][q][0] = gc.x;
+            s_g[wv][q][1] = gc.y;
+            s_g[wv][q][2] = gc.w;
+            s_c[wv][q] = cg;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int idx = lane; idx < k * P1; idx += 64) {
+            const int q = idx / P1;
+            sa[idx] = A[s_c[wv][q] * P1 + (idx - q * P1)];
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int q = WIDE ? 0 : ((grp - dealt) % ng + ng) % ng; q < k; q += ng) {
+            const cd *Ac = sa + q * P1;
+            double lw;
+            const cd rho = recip_scaled(s_g[wv][q][2], zx - s_g[wv][q][0], zy - s_g[wv][q][1], lw);
+            cd sacc = Ac[P1 - 1];
 #pragma unroll
-        for (int q = P1 - 2; q >= 1; --q) sacc = cfma(sacc, rho, Ac[q]);
-        acc += fma(sacc.re, rho.re, fma(-sacc.im, rho.im, Ac[0].re * lw));  // Re(sacc rho) + A_0 log|w|
+            for (int r = P1 - 2; r >= 1; --r) sacc = cfma(sacc, rho, Ac[r]);
+            acc += fma(sacc.re, rho.re, fma(-sacc.im, rho.im, Ac[0].re * lw));  // Re(sacc rho) + A_0 log|w|
+        }
+        dealt += k;
+        __builtin_amdgcn_wave_barrier();  // the slice is rewritten by the next stage
     }
     if (!WIDE)
         for (int off = mp; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -481,14 +543,6 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);  // X pool offset of each level
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     const double4 *geom = t.geom.as<double4>();
-    hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox,
-                       lane_level, xptr, xidx, xoff, geom, stL, c->scr.segcnt.as<int32_t>(), nullptr, nullptr);
-    FMM2D_TRY(hipGetLastError());
-    FMM2D_TRY(scan_exclusive(c, c->scr.segcnt.as<int32_t>(), nbox, t.x_itemoff.as<int32_t>()));
-    hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox,
-                       lane_level, xptr, xidx, xoff, geom, stL, nullptr, t.x_itemoff.as<int32_t>(),
-                       t.x_items.as<int4>());
-    FMM2D_TRY(hipGetLastError());
     t.x_bound_wave = bw;
     t.x_bound_lane = bl;
     t.x_lane_level = lane_level;
@@ -505,12 +559,16 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     FMM2D_TRY(c->scr.mcnt.ensure(sizeof(int32_t) * nbox));
     FMM2D_TRY(t.m_itemoff.ensure(sizeof(int32_t) * (nbox + 1)));
     FMM2D_TRY(t.m_items.ensure(sizeof(int2) * (mb > 0 ? mb : 1)));
-    hipLaunchKernelGGL(k_m_items<false>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
-                       xidx, xoff, geom, stL, c->scr.mcnt.as<int32_t>(), nullptr, nullptr);
+    int32_t *cnts[2] = {c->scr.segcnt.as<int32_t>(), c->scr.mcnt.as<int32_t>()};
+    int32_t *offs[2] = {t.x_itemoff.as<int32_t>(), t.m_itemoff.as<int32_t>()};
+    hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 4)), dim3(256), 0, c->stream, L, t.n, nbox,
+                       lane_level, xptr, xidx, xoff, geom, stL, cnts[0], cnts[1], nullptr, nullptr, nullptr, nullptr);
     FMM2D_TRY(hipGetLastError());
-    FMM2D_TRY(scan_exclusive(c, c->scr.mcnt.as<int32_t>(), nbox, t.m_itemoff.as<int32_t>()));
-    hipLaunchKernelGGL(k_m_items<true>, dim3(grid_for(nbox, 256)), dim3(256), 0, c->stream, L, t.n, nbox, xptr,
-                       xidx, xoff, geom, stL, nullptr, t.m_itemoff.as<int32_t>(), t.m_items.as<int2>());
+    const int32_t *cin[2] = {cnts[0], cnts[1]};
+    FMM2D_TRY(scan_exclusive_n(c, 2, cin, nbox, offs));
+    hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 4)), dim3(256), 0, c->stream, L, t.n, nbox,
+                       lane_level, xptr, xidx, xoff, geom, stL, nullptr, nullptr, offs[0], offs[1],
+                       t.x_items.as<int4>(), t.m_items.as<int2>());
     FMM2D_TRY(hipGetLastError());
     t.x_ready = true;
     return hipSuccess;
@@ -561,7 +619,7 @@ hipError_t p2l_all(fmm2d_ctx *c, int p) {
     }
     }
     FMM2D_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_x_reduce, dim3((unsigned)nbox), dim3(64), 0, c->stream, p, nbox, itemoff, e.xpart.as<cd>(),
+    hipLaunchKernelGGL(k_x_reduce, dim3(grid_for(nbox, 4)), dim3(256), 0, c->stream, p, nbox, itemoff, e.xpart.as<cd>(),
                        e.xsum.as<cd>());
     return hipGetLastError();
 }

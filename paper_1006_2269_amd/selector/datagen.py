@@ -2,8 +2,9 @@
 
 For each layout (``workloads.selector_layout``): its density features, the
 binary64 judge at 1000 sampled targets, and for every level count L in
-{L0 - 1, ..., L0 + 2} (L0 = round(log4(N / 16))) and theta in
-{0.35, ..., 0.75} the GPU times of build_tree and connectivity (warm: the
+{L0 - 3, ..., L0 + 1} (L0 = round(log4(N / 16)); with the structural list
+options the cheapest tree is coarser than one of about 16 points per leaf)
+and theta in {0.35, ..., 0.75} the GPU times of build_tree and connectivity (warm: the
 least of three calls after one that may allocate; the lists with the
 structural options of ``selector.LIST_OPTIONS``), then for p = 4, 5, ... the
 time of evaluate (mode fp32, the reduced form for tolerances >= 1e-7) and
@@ -12,7 +13,7 @@ FP32 near field sets a floor).  Evaluate times are the GPU phases of one call
 (HIP events), so growing buffers do not count.
 
     python -m paper_1006_2269_amd.selector.datagen --first 50000 --count 400 --out gpurun_out/runs.npz
-    python -m paper_1006_2269_amd.selector.datagen --first 60000 --count 40 --lo 6 --hi 7 --out gpurun_out/big.npz
+    python -m paper_1006_2269_amd.selector.datagen --first 60000 --count 40 --lo 6 --hi 7 --thetas 0.45 0.55 0.65 --out gpurun_out/big.npz
     python -m paper_1006_2269_amd.selector.datagen --retime runs.npz --out runs_retimed.npz
 """
 from __future__ import annotations
@@ -35,9 +36,12 @@ def L0_of(n: int) -> int:
     return int(math.floor(math.log(max(n / 16.0, 1.0)) / math.log(4.0) + 0.5))
 
 
+BELOW, ABOVE = 3, 1  # candidate level counts L0 - BELOW .. L0 + ABOVE
+
+
 def candidate_levels(n: int):
     L0 = L0_of(n)
-    return [L for L in range(L0 - 1, L0 + 3) if 1 <= L <= 13 and 4 ** L <= n]
+    return [L for L in range(L0 - BELOW, L0 + ABOVE + 1) if 1 <= L <= 13 and 4 ** L <= n]
 
 
 def phase_ms(f, names):
@@ -73,7 +77,7 @@ def time_lists(f, theta):
     return best
 
 
-def run_layout(f, ps, torch, samples=1000):
+def run_layout(f, ps, torch, samples=1000, thetas=THETAS):
     from paper_1006_2269_amd import workloads as W
     from paper_1006_2269_amd.fmm import FMM2DError
 
@@ -89,7 +93,7 @@ def run_layout(f, ps, torch, samples=1000):
     rows = []
     for L in candidate_levels(ps.n):
         t_tree = time_tree(f, x, y, L)
-        for th in THETAS:
+        for th in thetas:
             try:
                 t_lists = time_lists(f, th)
             except FMM2DError:
@@ -150,6 +154,7 @@ def main():
     ap.add_argument("--hi", type=float, default=6.0)
     ap.add_argument("--out", required=True)
     ap.add_argument("--save-every", type=int, default=5, help="write the table every this many layouts")
+    ap.add_argument("--thetas", type=float, nargs="+", default=list(THETAS))
     args = ap.parse_args()
     import torch
 
@@ -167,7 +172,7 @@ def main():
     for i in range(args.count):
         seed = args.first + i
         ps = W.selector_layout(seed, args.lo, args.hi)
-        feat, rows = run_layout(f, ps, torch)
+        feat, rows = run_layout(f, ps, torch, thetas=tuple(args.thetas))
         feats.append(feat)
         ns.append(ps.n)
         table.extend((i,) + r for r in rows)
@@ -177,6 +182,7 @@ def main():
             np.savez_compressed(args.out, feats=np.array(feats, dtype=np.float32), n=np.array(ns, dtype=np.int64),
                      seeds=np.arange(args.first, args.first + i + 1), runs=np.array(table, dtype=np.float64),
                      log10_range=np.array([args.lo, args.hi]), mode=np.array(MODE),
+                     levels_rel=np.array([-BELOW, ABOVE]), thetas=np.array(args.thetas),
                      list_options=np.array(sorted(LIST_OPTIONS.items()), dtype=object).astype(str),
                      columns=np.array(["layout", "L", "theta", "p", "t_tree_ms", "t_lists_ms", "t_eval_ms",
                                        "e_inf"]))

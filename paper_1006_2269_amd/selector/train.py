@@ -3,8 +3,10 @@ network's forward pass, gradient and Adam steps are the library's kernels).
 
 Samples.  For a layout of the run table and a tolerance TOL = 10^U[-7, -3]
 (several per layout, seeded), the label is the cheapest measured
-(L, theta, p) whose error meets TOL, the cost being the measured GPU time of
-build_tree + connectivity + evaluate.  The input is the layout's feature
+(L, theta, p) whose error meets TOL / M (the label margin M, default 2: a
+configuration at the reduced-precision error floor of its level, where a
+larger p gains nothing, is not taken for TOL itself), the cost being the
+measured GPU time of build_tree + connectivity + evaluate.  The input is the layout's feature
 vector with its second entry set to log10 TOL.  Pairs for which no measured
 configuration meets TOL (below the FP32 error floor) are left out.
 
@@ -86,7 +88,7 @@ def best_config(R, tol):
     return min(near, key=lambda c: (abs(c[2] - 0.55), c[1], c[0]))
 
 
-def make_samples(feats, ns, runs, layouts, per_layout, seed):
+def make_samples(feats, ns, runs, layouts, per_layout, seed, margin=2.0):
     """Inputs and targets (L - log4(N / 16), log10 C, theta), where log10 C puts the
     label's order in the middle of the error model's interval:
     log10 TOL = log10 C + (p + 1/2) log10 theta."""
@@ -97,7 +99,7 @@ def make_samples(feats, ns, runs, layouts, per_layout, seed):
         if R.shape[0] == 0:
             continue
         for lt in rng.uniform(TOL_LO, TOL_HI, per_layout):
-            b = best_config(R, 10.0 ** lt)
+            b = best_config(R, 10.0 ** lt / margin)
             if b is None:
                 continue
             x = feats[i].astype(np.float64).copy()
@@ -131,6 +133,7 @@ def main():
     ap.add_argument("--input-noise", type=float, default=0.5)
     ap.add_argument("--val-frac", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--label-margin", type=float, default=2.0)
     args = ap.parse_args()
     import torch
 
@@ -141,8 +144,8 @@ def main():
     order = np.random.default_rng(args.seed).permutation(nl)
     nval = max(1, int(round(args.val_frac * nl)))
     val_l, tr_l = order[:nval], order[nval:]
-    Xtr, Ytr = make_samples(feats, ns, runs, tr_l, args.per_layout, args.seed)
-    Xva, Yva = make_samples(feats, ns, runs, val_l, args.per_layout, args.seed + 1)
+    Xtr, Ytr = make_samples(feats, ns, runs, tr_l, args.per_layout, args.seed, args.label_margin)
+    Xva, Yva = make_samples(feats, ns, runs, val_l, args.per_layout, args.seed + 1, args.label_margin)
     print("[train] layouts %d (val %d), samples %d (val %d)" % (nl, nval, Xtr.shape[0], Xva.shape[0]), flush=True)
 
     xm = Xtr.mean(axis=0)
@@ -208,7 +211,7 @@ def main():
     blob.astype("<f4").tofile(args.out)
     meta = {"layouts": int(nl), "val_layouts": int(nval), "samples": int(Xtr.shape[0]),
             "val_samples": int(Xva.shape[0]), "steps": args.steps, "batch": args.batch, "lr": args.lr,
-            "weight_decay": args.weight_decay, "input_noise": args.input_noise,
+            "weight_decay": args.weight_decay, "input_noise": args.input_noise, "label_margin": args.label_margin,
             "val_levels_exact": float(dl_ok), "val_theta_exact": float(th_ok), "val_p_covers_label": float(p_ok),
             "best_step": int(best[1]), "best_val_loss": float(best[0]),
             "log10_n_range": [float(lnn.min()) - 0.1, float(lnn.max()) + 0.15], "log10_tol_range": [TOL_LO, TOL_HI]}
