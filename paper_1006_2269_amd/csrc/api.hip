@@ -180,7 +180,7 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->ev.xpart.release();
         c->ev.xsum.release();
         for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.work,
-                          &e.src})
+                          &e.src, &e.srclo})
             b->release();
         Scratch &s = c->scr;
         for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);

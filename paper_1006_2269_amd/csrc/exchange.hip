@@ -15,18 +15,16 @@
 // P2L work items, one per P2L entry on the deepest levels (from the first
 // level whose boxes hold at most LANE_PTS points, or at most LANE_PTS_MANY
 // when the level has LANE_ENTRIES P2L entries or more, onwards): one lane per
-// item walks the entry's source points (the next point's loads issued before
-// the current one is used) and writes the item's partial expansion.  On the
-// coarser levels an item is a chunk of one entry's points (at most 32 chunks
-// of balanced size, at least PCH points each), one wavefront per item, one
-// lane per point, the lanes' sums met in a transposing butterfly.  Items are
-// ordered by target box and summed per box in item order, and the L2L pass
-// adds that sum into B: results do not depend on scheduling.  M2P gathers per
-// leaf: one wavefront per leaf, one lane per M2P entry of the leaf's
-// ancestors (all levels flattened), the leaf's points taken 16 at a time,
-// each point's sum over the lanes formed by the butterfly; every point is
-// written once.  Orders above 15 (p + 1 > 16) use one lane per point
-// instead.
+// item walks the entry's source points and writes the item's partial
+// expansion.  On the coarser levels an item is a chunk of one entry's points
+// (at most 32 chunks of balanced size, at least PCH points each), one
+// wavefront per item, one lane per point, the lanes' sums met in a
+// transposing butterfly.  Items are ordered by target box and summed per box
+// in item order, and the L2L pass adds that sum into B: results do not
+// depend on scheduling.  M2P runs one launch per level: items of 64 points
+// of one box (or a whole box of fewer points, its entries dealt to lane
+// groups), the box's M2P entries staged in LDS.  Orders above 31
+// (p + 1 > 32) take generic kernels with one lane per point.
 #include "evaluate.h"
 #include "wavesum.h"
 
@@ -37,7 +35,8 @@ constexpr int LANE_PTS = 256;         // boxes of at most this many points: one 
 constexpr int LANE_PTS_MANY = 4096;   // ... or this many, on levels with LANE_ENTRIES entries or more
 constexpr int64_t LANE_ENTRIES = 32768;
 constexpr int PCH = 512;  // least points per chunk on the other levels
-constexpr int XT = 16;    // coefficients per pass (orders above 15)
+constexpr int XT = 16;    // coefficients per pass (orders above PMAX_FAST - 1)
+constexpr int PMAX_FAST = 32;  // orders p + 1 up to this many take the specialised kernels
 constexpr int MPC = 16;   // leaf points per M2P pass
 
 // Point range [a, e) of box b of level l (its leaves are b 4^(L-l) onwards).
@@ -196,7 +195,7 @@ __device__ inline void p2l_sums(double x, double y, double q, double4 gb, cd *s)
 // Coefficient k of a P2L partial: the sums times -1/k (k >= 1).
 __device__ inline double p2l_coef(double v, int k) { return k == 0 ? v : -v / (double)k; }
 
-// Wavefront-per-item P2L (chunks of one entry), orders p + 1 <= 16: items
+// Wavefront-per-item P2L (chunks of one entry), orders p + 1 <= 32: items
 // [0, *wave_end).
 template <int P1>
 __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__restrict__ items,
@@ -205,7 +204,7 @@ __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__res
                                              const int32_t *__restrict__ stL, const double *__restrict__ px,
                                              const double *__restrict__ py, const double *__restrict__ qs,
                                              double *__restrict__ xpart) {
-    static_assert(P1 >= 2 && P1 <= 16, "one pass of 2 P1 <= 32 values");
+    static_assert(P1 >= 2 && P1 <= PMAX_FAST, "two passes of at most 32 values");
     const int64_t it = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (it >= *wave_end) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
@@ -234,19 +233,23 @@ __global__ void __launch_bounds__(256) k_p2l(int L, int64_t n, const int4 *__res
         for (int u = 0; u < 4; ++u) p2l_sums<P1>(bx[u], by[u], bq[u], gb, s);
     }
     for (; j < j1; j += 64) p2l_sums<P1>(px[j], py[j], qs[j], gb, s);
-    double v[32];
+    // coefficients 16 at a time: lane i receives the total of value i / 2 of
+    // the pass, coefficient k0 + i / 4, part (i / 2) % 2
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        v[2 * k] = k < P1 ? s[k].re : 0.0;
-        v[2 * k + 1] = k < P1 ? s[k].im : 0.0;
+    for (int k0 = 0; k0 < P1; k0 += 16) {
+        double v[32];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v[2 * k] = k0 + k < P1 ? s[k0 + k].re : 0.0;
+            v[2 * k + 1] = k0 + k < P1 ? s[k0 + k].im : 0.0;
+        }
+        const double tot = wave_transpose_sum<32>(v, lane);
+        const int vi = lane / 2, k = k0 + vi / 2;
+        if ((lane & 1) == 0 && k < P1) xpart[it * 2 * P1 + 2 * k0 + vi] = p2l_coef(tot, k);
     }
-    // lane i receives the total of value i / 2: coefficient i / 4, part (i / 2) % 2
-    const double tot = wave_transpose_sum<32>(v, lane);
-    const int vi = lane / 2, k = vi / 2;
-    if ((lane & 1) == 0 && k < P1) xpart[it * 2 * P1 + vi] = p2l_coef(tot, k);
 }
 
-// Lane-per-item P2L (whole entries), orders p + 1 <= 16: items
+// Lane-per-item P2L (whole entries), orders p + 1 <= 32: items
 // [*wave_end, *nitem).  Each lane walks its entry's source points in bursts
 // of 8: the burst's loads are issued together (consecutive addresses of one
 // lane, so a cache line is fetched once per burst rather than once per
@@ -291,7 +294,7 @@ __global__ void __launch_bounds__(256) k_p2l_lane(int L, const int4 *__restrict_
     }
 }
 
-// The same for orders p + 1 > 16: XT coefficients per pass, one lane per
+// The same for orders p + 1 > 32: XT coefficients per pass, one lane per
 // point (entries of an item taken one after the other).
 __device__ inline void p2l_point(double px_, double py_, double q, double4 gb, int k0, int p, double *ar,
                                  double *ai) {
@@ -381,18 +384,20 @@ __global__ void __launch_bounds__(256) k_x_reduce(int p, int64_t nbox, const int
     xsum[g * (p + 1) + lane] = acc;
 }
 
-// M2P of one level, orders p + 1 <= 16: one wavefront per item.  The box's
+// M2P of one level, orders p + 1 <= 32: one wavefront per item.  The box's
 // X row is taken 32 entries at a time: its M2P entries (the target box the
 // larger) are compacted by ballot, their centres, scales and multipoles
 // staged in the wavefront's LDS slice by coalesced loads, then evaluated
-// from there (same-address reads, served by broadcast).  WIDE (boxes of 64
+// from there (same-address reads, served by broadcast; 16 entries at a time
+// above order 16).  WIDE (boxes of 64
 // points or more): the item's 64 points one per lane, every lane taking the
 // entries in row order.  Otherwise (boxes of at most MP < 64 points):
 // lane = group * MP + point, the compacted entries dealt to the 64 / MP
 // groups in turn, each point's group sums met by a butterfly over the group
 // bits.  Items of one launch touch disjoint points; the levels run one
 // launch after the other, so every point's sum has a fixed order.
-constexpr int MSTAGE = 32;
+template <int P1>
+constexpr int m_stage() { return P1 <= 16 ? 32 : 16; }  // entries staged at once (LDS of 32 KB per block)
 template <int P1, bool WIDE>
 __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int2 *__restrict__ items,
                                                  const int32_t *__restrict__ first, const int32_t *__restrict__ end,
@@ -402,6 +407,7 @@ __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int
                                                  const cd *__restrict__ A, const double *__restrict__ px,
                                                  const double *__restrict__ py, const int32_t *__restrict__ perm,
                                                  double *__restrict__ phi) {
+    constexpr int MSTAGE = m_stage<P1>();
     __shared__ cd s_a[4][MSTAGE * P1];
     __shared__ double s_g[4][MSTAGE][3];
     __shared__ int64_t s_c[4][MSTAGE];
@@ -466,7 +472,7 @@ __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int
     if (grp == 0 && act) phi[perm[i]] += acc;
 }
 
-// M2P for orders p + 1 > 16: one lane per point of the leaf.
+// M2P for orders p + 1 > 32: one lane per point of the leaf.
 __global__ void __launch_bounds__(256) k_m2p_gen(int p, int L, int64_t nleaf, const int32_t *__restrict__ stL,
                                                  const int32_t *__restrict__ xptr_all,
                                                  const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
@@ -612,6 +618,9 @@ hipError_t p2l_all(fmm2d_ctx *c, int p) {
         break;
         FMM2D_P2L(2) FMM2D_P2L(3) FMM2D_P2L(4) FMM2D_P2L(5) FMM2D_P2L(6) FMM2D_P2L(7) FMM2D_P2L(8) FMM2D_P2L(9)
         FMM2D_P2L(10) FMM2D_P2L(11) FMM2D_P2L(12) FMM2D_P2L(13) FMM2D_P2L(14) FMM2D_P2L(15) FMM2D_P2L(16)
+        FMM2D_P2L(17) FMM2D_P2L(18) FMM2D_P2L(19) FMM2D_P2L(20) FMM2D_P2L(21) FMM2D_P2L(22) FMM2D_P2L(23)
+        FMM2D_P2L(24) FMM2D_P2L(25) FMM2D_P2L(26) FMM2D_P2L(27) FMM2D_P2L(28) FMM2D_P2L(29) FMM2D_P2L(30)
+        FMM2D_P2L(31) FMM2D_P2L(32)
 #undef FMM2D_P2L
         default:
             hipLaunchKernelGGL(k_p2l_gen, dim3(grid_for(bound, 4)), block, 0, c->stream, p, t.L, t.n, items, nitem,
@@ -636,7 +645,7 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
     const cd *A = c->ev.A.as<cd>();
     const double *px = t.px.as<double>(), *py = t.py.as<double>();
     PhaseScope kernel_scope(c, PH_M2P_KERNEL);  // the M2P kernels alone
-    if (p + 1 > 16) {
+    if (p + 1 > PMAX_FAST) {
         const int64_t nleaf = int64_t(1) << (2 * L);
         hipLaunchKernelGGL(k_m2p_gen, dim3(grid_for(nleaf, 4)), block, 0, c->stream, p, L, nleaf, stL, xptr, xidx,
                            xoff, geom, A, px, py, perm, phi);
@@ -661,7 +670,9 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
         break;
             FMM2D_M2P(2) FMM2D_M2P(3) FMM2D_M2P(4) FMM2D_M2P(5) FMM2D_M2P(6) FMM2D_M2P(7) FMM2D_M2P(8)
             FMM2D_M2P(9) FMM2D_M2P(10) FMM2D_M2P(11) FMM2D_M2P(12) FMM2D_M2P(13) FMM2D_M2P(14) FMM2D_M2P(15)
-            FMM2D_M2P(16)
+            FMM2D_M2P(16) FMM2D_M2P(17) FMM2D_M2P(18) FMM2D_M2P(19) FMM2D_M2P(20) FMM2D_M2P(21) FMM2D_M2P(22)
+            FMM2D_M2P(23) FMM2D_M2P(24) FMM2D_M2P(25) FMM2D_M2P(26) FMM2D_M2P(27) FMM2D_M2P(28) FMM2D_M2P(29)
+            FMM2D_M2P(30) FMM2D_M2P(31) FMM2D_M2P(32)
 #undef FMM2D_M2P
             default:
                 return hipErrorInvalidValue;

@@ -81,7 +81,7 @@ struct TreeState {
     DevBuf trans;           // int32 per S_L record t = (b, c) with c > b: the position of b in S_L(c)
     DevBuf spart;           // float: source-side near-field partial sums per S_L record and source lane
     DevBuf pool_state;      // int64 [3 (L+2) + 1]: s, w, x offsets, overflow
-    DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range, FP32 centre offset, threshold
+    DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range; 2 float4 (FP32 centre offset, thresholds, low part)
     bool nrec_valid = false;
     Schedule m2l_all;               // weak lists of all levels (rows = global box ids)
     Schedule near_seg;              // finest-level strong lists (built on first use)
@@ -113,6 +113,7 @@ struct EvalState {
     DevBuf qs;              // double [n] charges in leaf order
     DevBuf work;            // mode-dependent scratch
     DevBuf src;             // float4 [n]: FP32 local offsets and charge
+    DevBuf srclo;           // float2 [n]: low parts of the offsets (FP32_ACC64's two-part differences)
     DevBuf part;            // partial sums of the M2L's list segments
     DevBuf npart;           // near-field partial sums (written on the second stream while the far field runs)
     DevBuf gpart;           // near-field gradient partial sums (fmm2d_evaluate_field)

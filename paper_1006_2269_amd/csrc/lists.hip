@@ -112,10 +112,11 @@ __device__ inline uint64_t full_groups(uint64_t m) {
 }
 __device__ inline uint64_t expand_groups(uint64_t g) { return g | (g << 1) | (g << 2) | (g << 3); }
 
-// The FP32 near-field record of target leaf b and source leaf c: the centre
-// offset c_b - c_c rounded to FP32 and the squared distance below which a
-// pair counts as coincident.  In b's own leaf both sides of a pair subtract
-// the same rounded offsets, so duplicates give exactly r^2 = 0 and only r^2
+// The FP32 near-field record of target leaf b and source leaf c, two float4
+// at 2t and 2t + 1 for strong entry t.  The first: the centre offset
+// c_b - c_c rounded to FP32 and the squared distance below which a pair
+// counts as coincident.  In b's own leaf both sides of a pair subtract the
+// same rounded offsets, so duplicates give exactly r^2 = 0 and only r^2
 // below the smallest normal float is masked (the logarithm's argument stays
 // normal).  Across leaves a coincident pair shows a rounding distance: with
 // u = 2^-24, the offsets x - c_b and x - c_c, the FP32 c_b - c_c, the source
@@ -128,13 +129,23 @@ __device__ inline uint64_t expand_groups(uint64_t g) { return g | (g << 1) | (g 
 // FP32 offsets are off by at most u (2 R_b + 4 R_c + 2 |dxc| + 2 |dyc|)
 // <= 4 u mag, so its FP32 r^2 exceeds (12 u mag)^2 > threshold and the near
 // kernels may skip the coincidence test for the record.
-__device__ inline float4 near_record(double4 gb, double4 gc, double4 rb, double4 rc, bool self) {
-    const float dxc = (float)(gb.x - gc.x), dyc = (float)(gb.y - gc.y);
+// The second, for the differences in two FP32 parts (mode FP32_ACC64): the
+// low part of the centre offset (c_b - c_c minus its FP32 rounding) and the
+// coincidence threshold of that form.  There the offsets carry about 48
+// bits, the source offset in b's frame is formed by an exact two-term
+// difference, and a pair's difference is off by at most about
+// u |dx| + 2^-45 mag; pairs closer than 2^-42 mag count as coincident.
+__device__ inline void near_record(float4 *__restrict__ recd, int64_t t, double4 gb, double4 gc, double4 rb,
+                                   double4 rc, bool self) {
+    const double ddx = gb.x - gc.x, ddy = gb.y - gc.y;
+    const float dxc = (float)ddx, dyc = (float)ddy;
     const float mag = fabsf(dxc) + fabsf(dyc) + (float)gb.z + (float)gc.z;
     const float thr = self ? 0x1p-126f : (mag * 0x1p-21f) * (mag * 0x1p-21f);
+    const float thr2 = self ? 0x1p-126f : fmaxf((mag * 0x1p-42f) * (mag * 0x1p-42f), 0x1p-126f);
     const double gap = fmax(fmax(rb.x - rc.y, rc.x - rb.y), fmax(rb.z - rc.w, rc.z - rb.w));
     const bool sep = !self && gap > 0x1p-20 * (double)mag;
-    return make_float4(dxc, dyc, thr, sep ? 1.f : 0.f);
+    recd[2 * t] = make_float4(dxc, dyc, thr, sep ? 1.f : 0.f);
+    recd[2 * t + 1] = make_float4((float)(ddx - (double)dxc), (float)(ddy - (double)dyc), thr2, 0.f);
 }
 
 // Level 0: S_0(root) = {root}, W_0(root) empty; for a one-level tree
@@ -157,7 +168,7 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *xptr0, int
         owner0[0] = 0;
         selfpos[0] = 0;
         recj[0] = make_int2(stL[0], stL[1]);
-        recd[0] = near_record(geom0[0], geom0[0], rect0[0], rect0[0], true);
+        near_record(recd, 0, geom0[0], geom0[0], rect0[0], rect0[0], true);
     }
 }
 
@@ -236,7 +247,7 @@ __device__ inline void box_lists(int l, int L, int opt, double theta, const doub
                 if (records) {
                     const int32_t t = tS + pos;
                     recj[t] = make_int2(stL[cbox], stL[cbox + 1]);
-                    recd[t] = near_record(gb, gc, rectL[b], rectL[cbox], cbox == b);
+                    near_record(recd, t, gb, gc, rectL[b], rectL[cbox], cbox == b);
                 }
             }
         }
@@ -656,7 +667,7 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
                     if (records && fc.cbox[u] == fc.b[u]) selfpos[fc.b[u]] = posS;
                     if (records) {
                         recj[posS] = rr[u];
-                        recd[posS] = near_record(gb[u], gc[u], rb[u], rc[u], fc.cbox[u] == fc.b[u]);
+                        near_record(recd, posS, gb[u], gc[u], rb[u], rc[u], fc.cbox[u] == fc.b[u]);
                     }
                 }
                 if (fc.first[u]) {
@@ -697,7 +708,7 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s
     }
     // near-field records of the finest level's strong entries (<= cap_s)
     FMM2D_TRY(t.nrec_j.ensure(sizeof(int2) * cap_s));
-    FMM2D_TRY(t.nrec_d.ensure(sizeof(float4) * cap_s));
+    FMM2D_TRY(t.nrec_d.ensure(sizeof(float4) * 2 * cap_s));
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     // owners (rows) of the S entries of a level, for the next level's
     // decoding and (finest level) the near field; two buffers by level

@@ -25,6 +25,22 @@ namespace {
 constexpr double HALF_LN2_D = 0.34657359027997264;  // ln(2)/2
 constexpr int NWB = 4;                                // wavefronts per block
 
+// FP32_ACC64 takes coordinate differences in two FP32 parts: every offset is
+// hi + lo (lo the FP32 rounding of what hi leaves of the binary64 offset),
+// and a source offset in the target leaf's frame, (sh + sl) - (dh + dl) with
+// d the centre offset c_b - c_c, is formed by an exact two-term difference of
+// the high parts (Knuth's TwoSum) with the low parts' difference added to
+// its error term.  A pair's difference (th - h) + (tl - l) then has the
+// relative accuracy of FP32 in the difference itself, not in the leaf size:
+// close pairs in large leaves keep their logarithm (FP32 alone loses about
+// 2^-24 R / r of it, R the leaf's radius, r the pair's distance).
+__device__ inline void dd_sub(float sh, float sl, float dh, float dl, float &h, float &l) {
+    h = sh - dh;
+    const float bb = h - sh;
+    const float err = (sh - (h - bb)) + (-dh - bb);
+    l = err + (sl - dl);
+}
+
 // FP32 near field.  The segment's records (at most NEAR_SEG = 64, one per
 // lane) are staged in the wavefront's LDS slice once; each step reads its
 // record from LDS and the source points of the next step are loaded while the
@@ -34,7 +50,8 @@ constexpr int NWB = 4;                                // wavefronts per block
 // Requires the largest leaf to fit in GL lanes.
 template <int TM, int GL, bool ACC64>
 __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks, const int32_t *__restrict__ stL,
-                                                     const float4 *__restrict__ src, const int32_t *__restrict__ sptr,
+                                                     const float4 *__restrict__ src, const float2 *__restrict__ srclo,
+                                                     const int32_t *__restrict__ sptr,
                                                      const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
                                                      const int2 *__restrict__ recj, const float4 *__restrict__ recd,
                                                      double *__restrict__ part) {
@@ -42,6 +59,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
     constexpr int LPI = 64 / GL;  // source leaves per step
     __shared__ int2 s_rj[NWB][64];
     __shared__ float4 s_rd[NWB][64];
+    __shared__ float4 s_rl[NWB][ACC64 ? 64 : 1];
     const int64_t item = (int64_t)blockIdx.x * NWB + threadIdx.x / 64;
     if (item >= nitems) return;  // uniform per wavefront
     const int wv = threadIdx.x / 64;
@@ -61,11 +79,13 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
         const bool ok = t0 + lane < t1;
         const int32_t tr = ok ? t0 + lane : t0;
         const int2 rj = recj[tr];
-        const float4 rd = recd[tr];
+        const float4 rd = recd[2 * tr];
         s_rj[wv][lane] = ok ? rj : make_int2(0, 0);
         s_rd[wv][lane] = rd;
+        if constexpr (ACC64) s_rl[wv][lane] = recd[2 * tr + 1];
     }
     float tx[TM], ty[TM], acc[TM];
+    float txl[ACC64 ? TM : 1], tyl[ACC64 ? TM : 1];
     double tot64 = 0.0;  // ACC64: binary64 total of target lane / (64 / TM), added at each flush
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
@@ -73,6 +93,11 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
         tx[k] = s.x;
         ty[k] = s.y;
         acc[k] = 0.f;
+        if constexpr (ACC64) {
+            const float2 sl = srclo[a + (k < nt ? k : 0)];
+            txl[k] = sl.x;
+            tyl[k] = sl.y;
+        }
     }
     __builtin_amdgcn_wave_barrier();
     const int grp = lane / GL, jj = lane % GL;
@@ -81,35 +106,65 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
     // of its source leaf loads a point of the array, moved far from every
     // target, and carries no charge, so the load needs no branch and its
     // pairs add exactly zero
+    struct Src {
+        float4 v;
+        float2 l;
+    };
     auto load_src = [&](int st) {
         const int2 rj = s_rj[wv][st * LPI + grp];
         const bool ok = jj < rj.y - rj.x;
-        float4 v = src[ok ? rj.x + jj : 0];
-        v.x = ok ? v.x : 0x1p60f;
-        v.z = ok ? v.z : 0.f;
-        return v;
+        const int32_t j = ok ? rj.x + jj : 0;
+        Src s;
+        s.v = src[j];
+        s.v.x = ok ? s.v.x : 0x1p60f;
+        s.v.z = ok ? s.v.z : 0.f;
+        s.l = ACC64 ? srclo[j] : make_float2(0.f, 0.f);
+        return s;
     };
-    auto eval = [&](float4 sv, int st) {
+    auto eval = [&](const Src &sv, int st) {
         const float4 rd = s_rd[wv][st * LPI + grp];
-        const float sx = sv.x - rd.x, sy = sv.y - rd.y, q = sv.z, thr = rd.z;
-        float lg[TM];
+        const float q = sv.v.z;
+        float sx, sy, sxl = 0.f, syl = 0.f, thr;
+        if constexpr (ACC64) {
+            const float4 rl = s_rl[wv][st * LPI + grp];
+            dd_sub(sv.v.x, sv.l.x, rd.x, rl.x, sx, sxl);
+            dd_sub(sv.v.y, sv.l.y, rd.y, rl.y, sy, syl);
+            thr = rl.z;
+        } else {
+            sx = sv.v.x - rd.x;
+            sy = sv.v.y - rd.y;
+            thr = rd.z;
+        }
+        float lg[TM], r2[ACC64 ? TM : 1];
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
-            const float dx = tx[k] - sx, dy = ty[k] - sy;
-            lg[k] = __log2f(dx * dx + dy * dy);
+            if constexpr (ACC64) {
+                const float dx = (tx[k] - sx) + (txl[k] - sxl), dy = (ty[k] - sy) + (tyl[k] - syl);
+                r2[k] = dx * dx + dy * dy;
+                lg[k] = __log2f(r2[k]);
+            } else {
+                const float dx = tx[k] - sx, dy = ty[k] - sy;
+                lg[k] = __log2f(dx * dx + dy * dy);
+            }
         }
         // every record of the step separated: the mask would change nothing
         if (!__all(rd.w != 0.f)) {
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
-                const float dx = tx[k] - sx, dy = ty[k] - sy;
-                lg[k] = (dx * dx + dy * dy > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
+                float rr;
+                if constexpr (ACC64) {
+                    rr = r2[k];
+                } else {
+                    const float dx = tx[k] - sx, dy = ty[k] - sy;
+                    rr = dx * dx + dy * dy;
+                }
+                lg[k] = (rr > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
             }
         }
 #pragma unroll
         for (int k = 0; k < TM; ++k) acc[k] = fmaf(q, lg[k], acc[k]);
     };
-    float4 svA = load_src(0), svB;
+    Src svA = load_src(0), svB;
     for (int st = 0; st < nsteps; st += 2) {
         const bool two = st + 1 < nsteps;
         if (two) svB = load_src(st + 1);
@@ -163,8 +218,9 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
 // loaded while the current step is evaluated (two steps per loop iteration,
 // so the pipeline registers alternate instead of being copied).
 template <int TM, int GL, int CH, bool ACC64>
-__global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(4))) k_near32s(int64_t nitems, const int32_t *__restrict__ stL,
-                                                      const float4 *__restrict__ src, const int32_t *__restrict__ sptr,
+__global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(ACC64 ? 3 : 4))) k_near32s(int64_t nitems, const int32_t *__restrict__ stL,
+                                                      const float4 *__restrict__ src, const float2 *__restrict__ srclo,
+                                                      const int32_t *__restrict__ sptr,
                                                       const int32_t *__restrict__ selfpos,
                                                       const int32_t *__restrict__ transU,
                                                       const int2 *__restrict__ segtab,
@@ -178,6 +234,7 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(4
     constexpr int RING = 8;       // steps of source sums per exchange
     __shared__ int2 s_rj[NWB][64];
     __shared__ float4 s_rd[NWB][64];
+    __shared__ float4 s_rl[NWB][ACC64 ? 64 : 1];
     __shared__ int32_t s_tu[NWB][64];
     __shared__ float s_ring[2][RING][NWB][64];
     const int wv = threadIdx.x / 64;
@@ -198,12 +255,14 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(4
         const bool ok = t0 + lane < t1;
         const int32_t tr = ok ? t0 + lane : t0;
         const int2 rj = recj[tr];
-        const float4 rd = recd[tr];
+        const float4 rd = recd[2 * tr];
         s_rj[wv][lane] = ok ? rj : make_int2(0, 0);
         s_rd[wv][lane] = rd;
+        if constexpr (ACC64) s_rl[wv][lane] = recd[2 * tr + 1];
         s_tu[wv][lane] = (ok && tr != tself) ? transU[tr] : 0;
     }
     float tx[TM], ty[TM], tq[TM], acc[TM];
+    float txl[ACC64 ? TM : 1], tyl[ACC64 ? TM : 1];
     double tot64 = 0.0;  // ACC64: binary64 total of target lane / (64 / TM), added at each flush
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
@@ -212,17 +271,29 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(4
         ty[k] = s.y;
         tq[k] = k < nt ? s.z : 0.f;  // absent targets send nothing to the sources
         acc[k] = 0.f;
+        if constexpr (ACC64) {
+            const float2 sl = srclo[k < nt ? a + k : lb];
+            txl[k] = sl.x;
+            tyl[k] = sl.y;
+        }
     }
     __builtin_amdgcn_wave_barrier();
     const int grp = lane / GL, jj = lane % GL;
     const int nsteps = (t1 - t0 + LPI - 1) / LPI;
+    struct Src {
+        float4 v;
+        float2 l;
+    };
     auto load_src = [&](int st) {  // as in k_near32 (its source sum is not written either)
         const int2 rj = s_rj[wv][st * LPI + grp];
         const bool ok = jj < rj.y - rj.x;
-        float4 v = src[ok ? rj.x + jj : 0];
-        v.x = ok ? v.x : 0x1p60f;  // far from every target: finite log on the unmasked path
-        v.z = ok ? v.z : 0.f;
-        return v;
+        const int32_t j = ok ? rj.x + jj : 0;
+        Src s;
+        s.v = src[j];
+        s.v.x = ok ? s.v.x : 0x1p60f;  // far from every target: finite log on the unmasked path
+        s.v.z = ok ? s.v.z : 0.f;
+        s.l = ACC64 ? srclo[j] : make_float2(0.f, 0.f);
+        return s;
     };
     // The source sums of RING steps collect in one half of s_ring; at the
     // last step of the group (or of the segment) the block meets once, and
@@ -251,23 +322,46 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(4
     };
     // one step: both sides of every pair of this lane's source and the
     // wavefront's targets
-    auto eval = [&](float4 sv, int st) {
+    auto eval = [&](const Src &sv, int st) {
         const int r = st * LPI + grp;
         const float4 rd = s_rd[wv][r];
-        const float sx = sv.x - rd.x, sy = sv.y - rd.y, q = sv.z, thr = rd.z;
-        float sacc = 0.f, lg[TM];
+        const float q = sv.v.z;
+        float sx, sy, sxl = 0.f, syl = 0.f, thr;
+        if constexpr (ACC64) {
+            const float4 rl = s_rl[wv][r];
+            dd_sub(sv.v.x, sv.l.x, rd.x, rl.x, sx, sxl);
+            dd_sub(sv.v.y, sv.l.y, rd.y, rl.y, sy, syl);
+            thr = rl.z;
+        } else {
+            sx = sv.v.x - rd.x;
+            sy = sv.v.y - rd.y;
+            thr = rd.z;
+        }
+        float sacc = 0.f, lg[TM], r2[ACC64 ? TM : 1];
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
-            const float dx = tx[k] - sx, dy = ty[k] - sy;
-            lg[k] = __log2f(dx * dx + dy * dy);
+            if constexpr (ACC64) {
+                const float dx = (tx[k] - sx) + (txl[k] - sxl), dy = (ty[k] - sy) + (tyl[k] - syl);
+                r2[k] = dx * dx + dy * dy;
+                lg[k] = __log2f(r2[k]);
+            } else {
+                const float dx = tx[k] - sx, dy = ty[k] - sy;
+                lg[k] = __log2f(dx * dx + dy * dy);
+            }
         }
         // separated leaves only (every r^2 exceeds its threshold): the
         // coincidence mask would change nothing and is skipped
         if (!__all(rd.w != 0.f)) {
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
-                const float dx = tx[k] - sx, dy = ty[k] - sy;
-                lg[k] = (dx * dx + dy * dy > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
+                float rr;
+                if constexpr (ACC64) {
+                    rr = r2[k];
+                } else {
+                    const float dx = tx[k] - sx, dy = ty[k] - sy;
+                    rr = dx * dx + dy * dy;
+                }
+                lg[k] = (rr > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
             }
         }
 #pragma unroll
@@ -278,7 +372,7 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(4
         s_ring[(st / RING) & 1][st & (RING - 1)][wv][lane] = sacc;
         if ((st & (RING - 1)) == RING - 1 || st == nsteps - 1) exchange(st);  // uniform per block
     };
-    float4 svA = load_src(0), svB;
+    Src svA = load_src(0), svB;
     for (int st = 0; st < nsteps; st += 2) {
         const bool two = st + 1 < nsteps;
         if (two) svB = load_src(st + 1);
@@ -319,6 +413,7 @@ template <int TM, bool ACC64>
 __global__ void __launch_bounds__(64 * NWB) k_near32_big(int64_t nitems, int chunks, int maxleaf,
                                                          const int32_t *__restrict__ stL,
                                                          const float4 *__restrict__ src,
+                                                         const float2 *__restrict__ srclo,
                                                          const int32_t *__restrict__ sptr,
                                                          const int2 *__restrict__ segtab,
                                                          const int32_t *__restrict__ nseg_ptr,
@@ -337,6 +432,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32_big(int64_t nitems, int chu
     if (a >= le) return;
     const int nt = (le - a) < TM ? (le - a) : TM;
     float tx[TM], ty[TM], acc[TM];
+    float txl[ACC64 ? TM : 1], tyl[ACC64 ? TM : 1];
     double acc64[TM];
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
@@ -345,26 +441,46 @@ __global__ void __launch_bounds__(64 * NWB) k_near32_big(int64_t nitems, int chu
         ty[k] = s.y;
         acc[k] = 0.f;
         acc64[k] = 0.0;
+        if constexpr (ACC64) {
+            const float2 sl = srclo[a + (k < nt ? k : 0)];
+            txl[k] = sl.x;
+            tyl[k] = sl.y;
+        }
     }
     const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
     for (int32_t t = t0; t < t1; ++t) {
         const int2 rj = recj[t];
-        const float4 rd = recd[t];
+        const float4 rd = recd[2 * t];
+        const float4 rl = ACC64 ? recd[2 * t + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float thr = ACC64 ? rl.z : rd.z;
         for (int jb = 0; jb < maxleaf; jb += 64) {
             const int32_t j = rj.x + jb + lane;
-            float sx = 1e18f, sy = 1e18f, q = 0.f;
+            float sx = 1e18f, sy = 1e18f, sxl = 0.f, syl = 0.f, q = 0.f;
             if (j < rj.y) {
                 const float4 s = src[j];
-                sx = s.x - rd.x;
-                sy = s.y - rd.y;
+                if constexpr (ACC64) {
+                    const float2 sl = srclo[j];
+                    dd_sub(s.x, sl.x, rd.x, rl.x, sx, sxl);
+                    dd_sub(s.y, sl.y, rd.y, rl.y, sy, syl);
+                } else {
+                    sx = s.x - rd.x;
+                    sy = s.y - rd.y;
+                }
                 q = s.z;
             }
 #pragma unroll
             for (int k = 0; k < TM; ++k) {
-                const float dx = tx[k] - sx, dy = ty[k] - sy;
+                float dx, dy;
+                if constexpr (ACC64) {
+                    dx = (tx[k] - sx) + (txl[k] - sxl);
+                    dy = (ty[k] - sy) + (tyl[k] - syl);
+                } else {
+                    dx = tx[k] - sx;
+                    dy = ty[k] - sy;
+                }
                 const float r2 = dx * dx + dy * dy;
                 const float lg = __log2f(r2);
-                acc[k] = fmaf(q, (r2 > rd.z) ? lg : 0.f, acc[k]);
+                acc[k] = fmaf(q, (r2 > thr) ? lg : 0.f, acc[k]);
             }
         }
         if (ACC64) {
@@ -455,12 +571,20 @@ __global__ void __launch_bounds__(64 * NWB) k_near64(int64_t nitems, int chunks,
     if (lane < TM) part[item * TM + lane] = mine;
 }
 
+// FP32 sources (offset from the leaf centre, charge); with `lo`, the low
+// parts of the offsets for the two-part differences of FP32_ACC64.
 __global__ void k_pack_sources(const float2 *__restrict__ loc, const double *__restrict__ qs, int64_t n,
-                               float4 *__restrict__ src) {
+                               float4 *__restrict__ src, const double *__restrict__ px, const double *__restrict__ py,
+                               const int32_t *__restrict__ leafid, const double4 *__restrict__ geomL,
+                               float2 *__restrict__ lo) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const float2 l = loc[i];
         src[i] = make_float4(l.x, l.y, (float)qs[i], 0.0f);
+        if (lo) {
+            const double4 g = geomL[leafid[i]];
+            lo[i] = make_float2((float)((px[i] - g.x) - (double)l.x), (float)((py[i] - g.y) - (double)l.y));
+        }
     }
 }
 
@@ -575,13 +699,13 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage, double *phi
         PhaseScope kernel_scope(c, PH_NEAR_KERNEL, c->side);  // the near-field kernel alone
         if (mode == FMM2D_MODE_FP32_ACC64)
             hipLaunchKernelGGL((k_near32s<TM, GL, CH, true>), grid, block, 0, c->side, nitems, stL,
-                               e.src.as<float4>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
+                               e.src.as<float4>(), e.srclo.as<float2>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
                                sc.table.as<int2>(),
                                sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
                                spart);
         else
             hipLaunchKernelGGL((k_near32s<TM, GL, CH, false>), grid, block, 0, c->side, nitems, stL,
-                               e.src.as<float4>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
+                               e.src.as<float4>(), nullptr, sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
                                sc.table.as<int2>(),
                                sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
                                spart);
@@ -636,16 +760,16 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage, do
             if (maxleaf > 64) {
                 if (mode == FMM2D_MODE_FP32_ACC64)
                     hipLaunchKernelGGL((k_near32_big<TM, true>), grid, block, 0, c->side, nitems, chunks, maxleaf, stL,
-                                       e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+                                       e.src.as<float4>(), e.srclo.as<float2>(), sp, tab, nsp, rj, rd, part);
                 else
                     hipLaunchKernelGGL((k_near32_big<TM, false>), grid, block, 0, c->side, nitems, chunks, maxleaf, stL,
-                                       e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+                                       e.src.as<float4>(), nullptr, sp, tab, nsp, rj, rd, part);
             } else if (mode == FMM2D_MODE_FP32_ACC64) {
                 hipLaunchKernelGGL((k_near32<TM, GL, true>), grid, block, 0, c->side, nitems, chunks, stL,
-                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+                                   e.src.as<float4>(), e.srclo.as<float2>(), sp, tab, nsp, rj, rd, part);
             } else {
                 hipLaunchKernelGGL((k_near32<TM, GL, false>), grid, block, 0, c->side, nitems, chunks, stL,
-                                   e.src.as<float4>(), sp, tab, nsp, rj, rd, part);
+                                   e.src.as<float4>(), nullptr, sp, tab, nsp, rj, rd, part);
             }
         }
     }
@@ -666,8 +790,14 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage, double *phi) {
     if (!t.nrec_valid) return hipErrorInvalidValue;  // records come with the lists
     if (stage == NEAR_PREP && mode != FMM2D_MODE_FP64) {
         FMM2D_TRY(e.src.ensure(sizeof(float4) * n));
+        float2 *lo = nullptr;
+        if (mode == FMM2D_MODE_FP32_ACC64) {
+            FMM2D_TRY(e.srclo.ensure(sizeof(float2) * n));
+            lo = e.srclo.as<float2>();
+        }
         hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.loc.as<float2>(),
-                           e.qs.as<double>(), n, e.src.as<float4>());
+                           e.qs.as<double>(), n, e.src.as<float4>(), t.px.as<double>(), t.py.as<double>(),
+                           t.leafid.as<int32_t>(), t.geom.as<double4>() + level_offset(L), lo);
     }
     // GL lanes per source leaf: the smallest power of two >= the largest leaf
     // (capped at 64; larger leaves take the non-pipelined kernel)

@@ -3,7 +3,7 @@ network's forward pass, gradient and Adam steps are the library's kernels).
 
 Samples.  For a layout of the run table and a tolerance TOL = 10^U[-7, -3]
 (several per layout, seeded), the label is the cheapest measured
-(L, theta, p) whose error meets TOL / M (the label margin M, default 2: a
+(L, theta, p) whose error meets TOL / M (the label margin M, default 8: a
 configuration at the reduced-precision error floor of its level, where a
 larger p gains nothing, is not taken for TOL itself), the cost being the
 measured GPU time of build_tree + connectivity + evaluate.  The input is the layout's feature
@@ -70,7 +70,7 @@ def best_config(R, tol):
     """Cheapest (cost_ms, L, theta, p) of one layout's runs meeting tol.
     Near-ties (within 10%: the cost is flat across theta for most layouts,
     and timing noise would flip the label) go to theta nearest 0.55, then
-    fewer levels."""
+    more levels (smaller leaves: a lower reduced-precision error floor)."""
     cands = []
     keys = np.unique(R[:, 1:3], axis=0)
     for L, th in keys:
@@ -85,10 +85,10 @@ def best_config(R, tol):
         return None
     cmin = min(c[0] for c in cands)
     near = [c for c in cands if c[0] <= TIE * cmin]
-    return min(near, key=lambda c: (abs(c[2] - 0.55), c[1], c[0]))
+    return min(near, key=lambda c: (abs(c[2] - 0.55), -c[1], c[0]))
 
 
-def make_samples(feats, ns, runs, layouts, per_layout, seed, margin=2.0):
+def make_samples(feats, ns, runs, layouts, per_layout, seed, margin=8.0):
     """Inputs and targets (L - log4(N / 16), log10 C, theta), where log10 C puts the
     label's order in the middle of the error model's interval:
     log10 TOL = log10 C + (p + 1/2) log10 theta."""
@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--input-noise", type=float, default=0.5)
     ap.add_argument("--val-frac", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=7)
-    ap.add_argument("--label-margin", type=float, default=2.0)
+    ap.add_argument("--label-margin", type=float, default=8.0)
     args = ap.parse_args()
     import torch
 

@@ -11,7 +11,13 @@
   precision envelope (BF16X3 1e-3, FP32_ACC64 1e-6, binary64 1e-9) at the
   rule's parameters, against the oracle's direct sum at sampled targets.
 * 10M clustered points at 9 levels (10 levels exceed the int32 list-entry
-  limit, tested elsewhere): FP32_ACC64 within 1e-6 at sampled targets.
+  limit of the plain lists, tested elsewhere): FP32_ACC64 within 1e-6 at
+  sampled targets.
+* The benchmark's path on the 10M clustered points and the 4M ring points:
+  select_build_tree with the shipped weights, the lists with both
+  structural options, the reduced mode for 1e-6, within 1e-6 of the
+  oracle's direct sum at sampled targets; on the ring, each mode's envelope
+  with the structural options at the rule's parameters (FP32 1e-5 too).
 """
 import sys
 
@@ -105,8 +111,8 @@ def test_mixed_1m_benchmark_path_meets_tolerance(fmm, orc, mixed):
     _announce("mixed_1m benchmark path", ps.n)
     x, y, q = _dev(ps.x), _dev(ps.y), _dev(ps.q)
     L, p, th, _ = fmm.select_build_tree(x, y, 1e-6, w)
-    fmm.connectivity(th)
-    phi = fmm.evaluate(q, p, "fp32_acc64").cpu().numpy()
+    fmm.connectivity(th, **selector.LIST_OPTIONS)
+    phi = fmm.evaluate(q, p, selector.reduced_mode(1e-6)).cpu().numpy()
     assert _sampled_err(phi, orc, ps, 400) <= 1e-6
 
 
@@ -134,3 +140,32 @@ def test_clustered_10m_at_9_levels(fmm, orc):
     fmm.connectivity(th)
     phi = fmm.evaluate(_dev(ps.q), p, "fp32_acc64").cpu().numpy()
     assert _sampled_err(phi, orc, ps, 64) <= 1e-6
+
+
+@pytest.mark.parametrize("workload", ["clustered_10m", "ring_4m"])
+def test_benchmark_path_full_size(fmm, orc, workload):
+    from paper_1006_2269_amd import selector
+
+    ps = W.WORKLOADS[workload]()
+    w = selector.weights_tensor(torch.device("cuda", 0))
+    x, y, q = _dev(ps.x), _dev(ps.y), _dev(ps.q)
+    L, p, th, net = fmm.select_build_tree(x, y, 1e-6, w)
+    _announce(workload, "benchmark path", ps.n, L, p, th, net)
+    assert net, "the network decides inside its trained range"
+    fmm.connectivity(th, **selector.LIST_OPTIONS)
+    phi = fmm.evaluate(q, p, selector.reduced_mode(1e-6)).cpu().numpy()
+    assert _sampled_err(phi, orc, ps, 64) <= 1e-6
+
+
+@pytest.mark.parametrize("mode,tol", [("bf16x3", 1e-3), ("fp32", 1e-5), ("fp32_acc64", 1e-6), ("fp64", 1e-9)])
+def test_ring_4m_precision_envelope_structural(fmm, orc, mode, tol):
+    from oracle import select as S
+    from paper_1006_2269_amd import selector
+
+    ps = W.ring_4m()
+    L, p, th = S.rule(ps.n, tol)
+    _announce("ring_4m structural", mode, tol, ps.n, L, p, th)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity(th, **selector.LIST_OPTIONS)
+    phi = fmm.evaluate(_dev(ps.q), p, mode).cpu().numpy()
+    assert _sampled_err(phi, orc, ps, 150) <= tol

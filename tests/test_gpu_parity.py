@@ -356,3 +356,61 @@ def test_reduced_modes_refuse_out_of_range(fmm, orc, mode):
     phi = fmm.evaluate(_dev(q), 12, "fp64").cpu().numpy()
     ref = orc.fmm(x, y, q, 3, 12, 0.5)
     assert np.abs(phi - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("per_leaf", [12, 24, 48, 100])
+@pytest.mark.parametrize("across", [False, True])
+def test_acc64_two_part_differences_resolve_close_pairs(fmm, orc, per_leaf, across):
+    # A pair 2^-30 R apart (R the leaf's half diagonal), in one leaf or in two
+    # leaves across the x-median split line: far below what FP32 offsets
+    # resolve (about 2^-24 R), so FP32_ACC64's differences in two FP32 parts
+    # must carry it.  Masking or mis-resolving the pair would cost about
+    # |log r| ~ 20 at both points; the two-part difference is accurate to
+    # about 2^-23 of itself, its log to about 1e-6 absolute.
+    L = 1
+    g = np.random.default_rng(777 + per_leaf + 1000 * across)
+    n = 4 * per_leaf
+    h = n // 2 - 1
+    x = np.concatenate([[0.5, 0.5], g.uniform(0.0, 0.49, h), g.uniform(0.51, 1.0, n - 2 - h)])
+    y = np.concatenate([[0.3, 0.3], g.random(n - 2)])
+    q = g.uniform(-1.0, 1.0, n)
+    q[0] = q[1] = 1.0
+    t = orc.tree(x, y, L)
+    R = float(np.asarray(t.geom)[orc.level_offset(L):, 2].max())
+    r_pair = 2.0 ** -30 * R
+    if across:
+        x[0], x[1] = 0.5 - r_pair / 2, 0.5 + r_pair / 2
+    else:
+        x[1], y[1] = x[0] + r_pair * math.cos(0.7), y[0] + r_pair * math.sin(0.7)
+        x[0] -= 0.25  # both in the low-x half, away from the split line
+        x[1] -= 0.25
+    t = orc.tree(x, y, L)
+    pos = np.empty(n, dtype=np.int64)
+    pos[np.asarray(t.perm)] = np.arange(n)
+    leaf = np.searchsorted(np.asarray(t.leaf_start), pos[:2], side="right") - 1
+    assert (leaf[0] != leaf[1]) == across
+    _announce("two-part differences", per_leaf, across)
+    fmm.build_tree(_dev(x), _dev(y), L)
+    fmm.connectivity(0.5)
+    phi = fmm.evaluate(_dev(q), 20, "fp32_acc64").cpu().numpy()
+    ex = orc.direct(x, y, q)
+    err = np.abs(phi - ex)
+    assert err[:2].max() <= 1e-4, err[:2]
+    assert err.max() <= 2e-5 * np.abs(ex).max()
+
+
+def test_acc64_below_the_fp32_offset_floor(fmm, orc):
+    # A held-out selector layout (26438 points) whose clustered leaves hold
+    # pairs far closer than their leaf size: at 5 levels the FP32 offsets
+    # alone leave about 8e-6 of max |phi| (the reduced mode FP32 measures
+    # that); the two-part differences of FP32_ACC64 meet 1e-6.
+    ps = W.selector_layout(90155, 4.0, 7.0)
+    assert ps.n == 26438
+    _announce("acc64 floor layout", ps.n)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), 5)
+    fmm.connectivity(0.5, parent=True, swap="all")
+    q = _dev(ps.q)
+    ex = orc.direct(ps.x, ps.y, ps.q)
+    e64, _ = orc.rel_errors(fmm.evaluate(q, 20, "fp32_acc64").cpu().numpy(), ex)
+    e32, _ = orc.rel_errors(fmm.evaluate(q, 20, "fp32").cpu().numpy(), ex)
+    assert e64 <= 1e-6 < e32, (e64, e32)
