@@ -229,7 +229,8 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
                                                       double *__restrict__ part, float *__restrict__ spart) {
     static_assert(NEAR_SEG <= 64, "one record per lane");
     static_assert(CH == NWB, "the chunks of one segment fill a block");
-    static_assert(TM == 8 || TM == 16, "targets per wavefront");
+    static_assert(TM == 8 || TM == 12 || TM == 16, "targets per wavefront");
+    constexpr int NV = TM <= 8 ? 8 : 16;  // butterfly width (TM padded with zeros)
     constexpr int LPI = 64 / GL;  // source leaves per step
     constexpr int RING = 8;       // steps of source sums per exchange
     __shared__ int2 s_rj[NWB][64];
@@ -382,29 +383,32 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
             eval(svB, st + 1);
         }
         if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps, summed over the lanes at once
-            double v[TM];
+            double v[NV];
 #pragma unroll
-            for (int k = 0; k < TM; ++k) {
-                v[k] = (double)acc[k];
-                acc[k] = 0.f;
+            for (int k = 0; k < NV; ++k) {
+                v[k] = k < TM ? (double)acc[k < TM ? k : 0] : 0.0;
+                if (k < TM) acc[k] = 0.f;
             }
-            tot64 += wave_transpose_sum<TM>(v, lane);
+            tot64 += wave_transpose_sum<NV>(v, lane);
         }
     }
     // the 64 lanes' partial sums of each target, by the transposing
     // butterfly (fixed order; binary64 with ACC64, else FP32): lane i
-    // receives target i / (64 / TM)
+    // receives target i / (64 / NV)
     double tot;
     if constexpr (ACC64) {
-        double v[TM];
+        double v[NV];
 #pragma unroll
-        for (int k = 0; k < TM; ++k) v[k] = (double)acc[k];
-        tot = tot64 + wave_transpose_sum<TM>(v, lane);
+        for (int k = 0; k < NV; ++k) v[k] = k < TM ? (double)acc[k < TM ? k : 0] : 0.0;
+        tot = tot64 + wave_transpose_sum<NV>(v, lane);
     } else {
-        tot = (double)wave_transpose_sum<TM>(acc, lane);
+        float v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = k < TM ? acc[k < TM ? k : 0] : 0.f;
+        tot = (double)wave_transpose_sum<NV>(v, lane);
     }
-    constexpr int G = 64 / TM;
-    if (lane % G == 0) part[item * TM + lane / G] = tot;
+    constexpr int G = 64 / NV;
+    if (lane % G == 0 && lane / G < TM) part[item * TM + lane / G] = tot;
 }
 
 // FP32 near field for leaves larger than 64 points: a lane walks its source
@@ -806,6 +810,7 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage, double *phi) {
         // each leaf pair once, the four chunks of targets of a leaf in the
         // four wavefronts of a block
         if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode, stage, phi);
+        if (ml <= 48) return launch_near_sym<12, 64, 4>(c, p, mode, stage, phi);  // 4 chunks of 12 targets
         return launch_near_sym<16, 64, 4>(c, p, mode, stage, phi);
     }
     if (stage == NEAR_PREP) FMM2D_TRY(ensure_near_full_schedule(c));  // on the context stream, before the second stream waits

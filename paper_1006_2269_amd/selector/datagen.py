@@ -7,9 +7,9 @@ options the cheapest tree is coarser than one of about 16 points per leaf)
 and theta in {0.35, ..., 0.75} the GPU times of build_tree and connectivity (warm: the
 least of three calls after one that may allocate; the lists with the
 structural options of ``selector.LIST_OPTIONS``), then for p = 4, 5, ... the
-time of evaluate (mode fp32, the reduced form for tolerances >= 1e-7) and
-the normwise error against the judge, until the error drops below 5e-8 or stops improving (the
-FP32 near field sets a floor).  Evaluate times are the GPU phases of one call
+time of evaluate (mode FP32_ACC64, the reduced form below TOL 1e-5) and
+the normwise error against the judge, until the error drops below 1e-8 or
+stops improving (three orders without a 10 % gain).  Evaluate times are the GPU phases of one call
 (HIP events), so growing buffers do not count.
 
     python -m paper_1006_2269_amd.selector.datagen --first 50000 --count 400 --out gpurun_out/runs.npz
@@ -27,9 +27,9 @@ import numpy as np
 
 THETAS = (0.35, 0.45, 0.55, 0.65, 0.75)
 P_MIN, P_MAX = 4, 30
-E_STOP = 5e-8      # below every tolerance the selector is trained for
+E_STOP = 1e-8      # below every tolerance the selector is trained for, with the label margin
 PLATEAU = 3        # stop after this many orders without a 10% gain
-MODE = "fp32"
+MODE = "fp32_acc64"
 
 
 def L0_of(n: int) -> int:

@@ -3,7 +3,7 @@ network's forward pass, gradient and Adam steps are the library's kernels).
 
 Samples.  For a layout of the run table and a tolerance TOL = 10^U[-7, -3]
 (several per layout, seeded), the label is the cheapest measured
-(L, theta, p) whose error meets TOL / M (the label margin M, default 8: a
+(L, theta, p) whose error meets TOL / M (the label margin M, default 4: a
 configuration at the reduced-precision error floor of its level, where a
 larger p gains nothing, is not taken for TOL itself), the cost being the
 measured GPU time of build_tree + connectivity + evaluate.  The input is the layout's feature
@@ -88,7 +88,7 @@ def best_config(R, tol):
     return min(near, key=lambda c: (abs(c[2] - 0.55), -c[1], c[0]))
 
 
-def make_samples(feats, ns, runs, layouts, per_layout, seed, margin=8.0):
+def make_samples(feats, ns, runs, layouts, per_layout, seed, margin=4.0):
     """Inputs and targets (L - log4(N / 16), log10 C, theta), where log10 C puts the
     label's order in the middle of the error model's interval:
     log10 TOL = log10 C + (p + 1/2) log10 theta."""
@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--input-noise", type=float, default=0.5)
     ap.add_argument("--val-frac", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=7)
-    ap.add_argument("--label-margin", type=float, default=8.0)
+    ap.add_argument("--label-margin", type=float, default=4.0)
     args = ap.parse_args()
     import torch
 
