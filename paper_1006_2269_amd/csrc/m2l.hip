@@ -339,7 +339,8 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
     }
 }
 
-// Orders with p + 1 <= 16: one lane per pair, 64 pairs per chunk.  Each lane
+// Orders with p + 1 <= 32 (16 with split-BF16 products): one lane per pair,
+// 64 pairs per chunk, one or two 16-wide output tiles.  Each lane
 // computes its pair's geometry, power table and pre-scaled row u' (stored in
 // LDS as two operand rows, real and imaginary part); the matrix instruction
 // multiplies the 128 rows by M^T block by block, each block's result
@@ -354,16 +355,18 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
                                                const int64_t *__restrict__ woff, const cd *__restrict__ A,
                                                const int2 *__restrict__ segtab, const int32_t *__restrict__ nseg_ptr,
                                                cd *__restrict__ part, const double *__restrict__ Mhat) {
-    static_assert(P1 >= 1 && P1 <= 16, "one 16-wide coefficient tile");
+    static_assert(P1 >= 1 && P1 <= 32, "at most two 16-wide coefficient tiles");
+    static_assert(!BF3 || P1 <= 16, "split-BF16 products: one tile");
     using MF = Mfma<G>;
     using V = typename MF::V;
     using PT = typename std::conditional<std::is_same<ACC, float>::value, float, double>::type;
-    constexpr int KP = 17;                                   // padded row length
+    constexpr int NTL = (P1 + 15) / 16;                      // output tiles of 16 coefficients
+    constexpr int KP = 16 * NTL + 1;                         // padded row length
     constexpr int KS = (P1 + 3) / 4;                         // K steps of the FP32/FP64 instruction
-    // the post-scaled values (Re, Im) are summed in at most two passes of
-    // NV values (l < 8, then l >= 8), which bounds the live registers
-    constexpr int NH = P1 <= 8 ? 1 : 2;                      // passes
+    // the post-scaled values (Re, Im) are summed in passes of NV values
+    // (NV / 2 coefficients each), which bounds the live registers
     constexpr int NV = P1 <= 4 ? 8 : 16;                     // values per pass, power of two
+    constexpr int NH = (2 * P1 + NV - 1) / NV;               // passes
     constexpr int SPREAD = 64 / NV;                          // lanes sharing one value after the halving stages
     __shared__ G U[64][2][KP];
     const int64_t seg = blockIdx.x;
@@ -380,7 +383,7 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
     const int32_t t1 = (t0 + M2L_SEG) < wptr[b + 1] ? (t0 + M2L_SEG) : wptr[b + 1];
     const int row = lane % 16, g = lane / 16;
     const double4 gb = geomL[b];
-    G mreg[KS];
+    G mreg[NTL][KS];
     v4s mbh, mbl;
     if constexpr (BF3) {
 #pragma unroll
@@ -394,9 +397,12 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
         }
     } else {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int k = 4 * ks + g;
-            mreg[ks] = (k < P1 && row < P1) ? (G)Mhat[row * 64 + k] : (G)0;
+        for (int tl = 0; tl < NTL; ++tl) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + g, l = 16 * tl + row;
+                mreg[tl][ks] = (k < P1 && l < P1) ? (G)Mhat[l * 64 + k] : (G)0;
+            }
         }
     }
     ACC tot[NH];  // running totals of value lane / SPREAD of each pass
@@ -444,6 +450,7 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
             const int pa = 8 * rb + MF::pair_of_row(row);
             const G *ur = U[pa][MF::part_of_row(row)];
             V d = {0, 0, 0, 0};
+            V d2 = {0, 0, 0, 0};  // second tile (coefficients 16..31)
             if constexpr (BF3) {
                 v4s ah, al;
 #pragma unroll
@@ -458,12 +465,20 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
                 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, mbh, d, 0, 0, 0);
             } else {
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) d = MF::run(ur[4 * ks + g], mreg[ks], d);
+                for (int ks = 0; ks < KS; ++ks) {
+                    const G a = ur[4 * ks + g];
+                    d = MF::run(a, mreg[0][ks], d);
+                    if constexpr (NTL > 1) d2 = MF::run(a, mreg[NTL - 1][ks], d2);
+                }
             }
             // element r of lane group g is pair 8 rb + 2 g + r / 2, part r % 2,
-            // coefficient l = row: those rows of U belong to this block only
+            // coefficient l = 16 tl + row: those rows of U belong to this block
+            // only (both tiles are formed before either is written)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) U[8 * rb + 2 * g + r / 2][r % 2][row] = (G)d[r];
+            for (int r = 0; r < 4; ++r) {
+                U[8 * rb + 2 * g + r / 2][r % 2][row] = (G)d[r];
+                if constexpr (NTL > 1) U[8 * rb + 2 * g + r / 2][r % 2][16 + row] = (G)d2[r];
+            }
         }
         __syncthreads();
         cx<PT> tp{(PT)1, (PT)0};  // (2 rho_t)^l
@@ -513,9 +528,11 @@ void launch_m2l_lp(fmm2d_ctx *c, int mode, dim3 grid, const double4 *geom, const
     else if (mode == FMM2D_MODE_FP32_ACC64)
         hipLaunchKernelGGL((k_m2l_lp<P1, float, double, false>), grid, block, 0, c->stream, geom, wp, wi, woff, A, tab,
                            nsp, part, Mh);
-    else if (mode == FMM2D_MODE_BF16X3)
-        hipLaunchKernelGGL((k_m2l_lp<P1, float, float, true>), grid, block, 0, c->stream, geom, wp, wi, woff, A, tab,
-                           nsp, part, Mh);
+    else if (mode == FMM2D_MODE_BF16X3) {
+        if constexpr (P1 <= 16)
+            hipLaunchKernelGGL((k_m2l_lp<P1, float, float, true>), grid, block, 0, c->stream, geom, wp, wi, woff, A,
+                               tab, nsp, part, Mh);
+    }
     else
         hipLaunchKernelGGL((k_m2l_lp<P1, float, float, false>), grid, block, 0, c->stream, geom, wp, wi, woff, A, tab,
                            nsp, part, Mh);
@@ -558,6 +575,14 @@ hipError_t launch_m2l_all(fmm2d_ctx *c, int p, int mode) {
             FMM2D_M2L_LP(2) FMM2D_M2L_LP(3) FMM2D_M2L_LP(4) FMM2D_M2L_LP(5) FMM2D_M2L_LP(6) FMM2D_M2L_LP(7)
             FMM2D_M2L_LP(8) FMM2D_M2L_LP(9) FMM2D_M2L_LP(10) FMM2D_M2L_LP(11) FMM2D_M2L_LP(12)
             FMM2D_M2L_LP(13) FMM2D_M2L_LP(14) FMM2D_M2L_LP(15) FMM2D_M2L_LP(16)
+            default: return hipErrorInvalidValue;
+        }
+    } else if (NT == 2 && mode != FMM2D_MODE_BF16X3) {
+        switch (p + 1) {
+            FMM2D_M2L_LP(17) FMM2D_M2L_LP(18) FMM2D_M2L_LP(19) FMM2D_M2L_LP(20) FMM2D_M2L_LP(21)
+            FMM2D_M2L_LP(22) FMM2D_M2L_LP(23) FMM2D_M2L_LP(24) FMM2D_M2L_LP(25) FMM2D_M2L_LP(26)
+            FMM2D_M2L_LP(27) FMM2D_M2L_LP(28) FMM2D_M2L_LP(29) FMM2D_M2L_LP(30) FMM2D_M2L_LP(31)
+            FMM2D_M2L_LP(32)
 #undef FMM2D_M2L_LP
             default: return hipErrorInvalidValue;
         }
