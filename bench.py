@@ -92,6 +92,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU baseline until this much time has passed")
     ap.add_argument("--fp64", type=int, default=1, help="also time the plain FP64 form")
+    ap.add_argument("--fp32-plain", type=int, default=1,
+                    help="also time plain FP32 (FP32 accumulation, single-part offsets) at the reduced form's "
+                         "levels and theta, the least p passing the judge")
     ap.add_argument("--fp64-plain", type=int, default=0,
                     help="also time FP64 on the lists without the structural options (slow on clustered sets)")
     ap.add_argument("--sweep", choices=["field", "robustness", "precision"],
@@ -551,6 +554,32 @@ def main():
 
     if args.fp64:
         results["fp64"] = fp64_form(L, opts, "same lists")
+    if args.fp32_plain and "reduced" in results and mode_red != "fp32":
+        # plain FP32 (single-part offsets, FP32 accumulation) at the reduced
+        # form's levels and theta, the least p passing the judge
+        rf = results["reduced"]
+        try:
+            f.build_tree(x, y, rf["levels"])
+            f.connectivity(rf["theta"], **opts)
+            found = search_p("fp32")
+            if found is not None:
+                p32 = found[0]
+
+                def step32():
+                    f.build_tree(x, y, rf["levels"])
+                    f.connectivity(rf["theta"], **opts)
+                    f.evaluate(q, p32, "fp32", out=out)
+
+                _, dt, med, tm = run_steps(step32, max(2, args.steps // 3))
+                e = rel_err(out)
+                show("plain fp32 L=%d p=%d theta=%.2f" % (rf["levels"], p32, rf["theta"]), dt, med, tm,
+                     max(2, args.steps // 3), e)
+                results["fp32_plain"] = {"levels": rf["levels"], "p": p32, "theta": rf["theta"],
+                                         "points_per_s": n / dt, "e_inf": e}
+            else:
+                results["fp32_plain"] = {"levels": rf["levels"], "theta": rf["theta"], "met": False}
+        except FMM2DError as err:
+            log("[bench] plain fp32: %s" % err)
     if args.fp64_plain:
         # the lists without the structural options, at the most levels (up to
         # the configuration's) they fit in
@@ -672,6 +701,7 @@ def main():
                    {k: learned[k] for k in ("levels", "p", "theta", "network", "e_inf")},
                    "e_inf": main_form["e_inf"], "judge_samples": args.samples,
                    "fp64_points_per_s": round(fp64["points_per_s"], 1) if fp64 else None,
+                   "fp32_plain": results.get("fp32_plain"),
                    "fp64": fp64 and {k: fp64[k] for k in ("levels", "p", "theta", "e_inf")},
                    "fp64_plain_lists": fp64p and {"points_per_s": round(fp64p["points_per_s"], 1),
                                                   **{k: fp64p[k] for k in ("levels", "p", "theta", "e_inf")}}},
