@@ -214,9 +214,11 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
 // instead of TM.
 //
 // The segment's records (at most NEAR_SEG = 64, one per lane) are staged in
-// the wavefront's LDS slice once; the source points of the next step are
-// loaded while the current step is evaluated (two steps per loop iteration,
-// so the pipeline registers alternate instead of being copied).
+// the wavefront's LDS slice once, and their source points taken as one
+// stream, 64 per step (a step may span two or three source leaves, so
+// leaves of 33 to 63 points fill the lanes); the source points of the next
+// step are loaded while the current step is evaluated (two steps per loop
+// iteration, so the pipeline registers alternate instead of being copied).
 template <int TM, int GL, int CH, bool ACC64>
 __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(ACC64 ? 3 : 4))) k_near32s(int64_t nitems, const int32_t *__restrict__ stL,
                                                       const float4 *__restrict__ src, const float2 *__restrict__ srclo,
@@ -231,9 +233,9 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
     static_assert(CH == NWB, "the chunks of one segment fill a block");
     static_assert(TM == 8 || TM == 12 || TM == 16, "targets per wavefront");
     constexpr int NV = TM <= 8 ? 8 : 16;  // butterfly width (TM padded with zeros)
-    constexpr int LPI = 64 / GL;  // source leaves per step
-    constexpr int RING = 8;       // steps of source sums per exchange
-    __shared__ int2 s_rj[NWB][64];
+    constexpr int RING = 8;  // steps of source sums per exchange
+    __shared__ int32_t s_base[NWB][64];  // source position of a record's flat index f: s_base + f
+    __shared__ int32_t s_pre[NWB][64];   // first flat source index of each record
     __shared__ float4 s_rd[NWB][64];
     __shared__ float4 s_rl[NWB][ACC64 ? 64 : 1];
     __shared__ int32_t s_tu[NWB][64];
@@ -252,15 +254,21 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
     const int nt = (le - a) < 0 ? 0 : ((le - a) < TM ? (le - a) : TM);  // a chunk may be empty
     const int32_t t0 = se.y, t1 = (se.y + NEAR_SEG) < sptr[b + 1] ? (se.y + NEAR_SEG) : sptr[b + 1];
     const int32_t tself = selfpos[b];
+    int32_t rend;  // lane r: one past the last flat index of record r (records past the segment: the total)
     {
         const bool ok = t0 + lane < t1;
         const int32_t tr = ok ? t0 + lane : t0;
         const int2 rj = recj[tr];
         const float4 rd = recd[2 * tr];
-        s_rj[wv][lane] = ok ? rj : make_int2(0, 0);
         s_rd[wv][lane] = rd;
         if constexpr (ACC64) s_rl[wv][lane] = recd[2 * tr + 1];
         s_tu[wv][lane] = (ok && tr != tself) ? transU[tr] : 0;
+        // the records' source points as one stream, 64 per step: record r
+        // holds flat indices s_pre[r] .. rend(r) - 1
+        const int32_t size = ok ? rj.y - rj.x : 0;
+        rend = wave_incl_scan(size);
+        s_pre[wv][lane] = rend - size;
+        s_base[wv][lane] = ok ? rj.x - (rend - size) : 0;
     }
     float tx[TM], ty[TM], tq[TM], acc[TM];
     float txl[ACC64 ? TM : 1], tyl[ACC64 ? TM : 1];
@@ -279,21 +287,37 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
         }
     }
     __builtin_amdgcn_wave_barrier();
-    const int grp = lane / GL, jj = lane % GL;
-    const int nsteps = (t1 - t0 + LPI - 1) / LPI;
+    const int32_t nflat = __builtin_amdgcn_readlane(rend, 63);
+    const int nsteps = (nflat + 63) / 64;
     struct Src {
         float4 v;
         float2 l;
+        int r;  // the lane's record in this step
     };
-    auto load_src = [&](int st) {  // as in k_near32 (its source sum is not written either)
-        const int2 rj = s_rj[wv][st * LPI + grp];
-        const bool ok = jj < rj.y - rj.x;
-        const int32_t j = ok ? rj.x + jj : 0;
+    // record of flat index f = 64 st + lane (below nflat): the number of
+    // records ending at or before f.  Those ending before the step are
+    // counted at once by a ballot; the few ending inside it (a step of 64
+    // spans at most 64 / (smallest leaf) + 1 records) one by one, uniformly.
+    auto record_of = [&](int st) {
+        const int32_t f = 64 * st + lane;
+        const int r_lo = __popcll(__ballot(rend <= 64 * st));
+        const int r_hi = __popcll(__ballot(rend <= 64 * st + 63));
+        int r = r_lo;
+        for (int i = r_lo; i < r_hi; ++i) r += (f >= __builtin_amdgcn_readlane(rend, i)) ? 1 : 0;
+        return r;
+    };
+    auto load_src = [&](int st) {  // a lane past the stream loads a point far away with no charge
+        const int32_t f = 64 * st + lane;
+        const bool ok = f < nflat;
+        int r = record_of(st);  // with every lane active: the ballots read all records
+        r = ok ? r : 0;
+        const int32_t j = ok ? s_base[wv][r] + f : 0;
         Src s;
         s.v = src[j];
         s.v.x = ok ? s.v.x : 0x1p60f;  // far from every target: finite log on the unmasked path
         s.v.z = ok ? s.v.z : 0.f;
         s.l = ACC64 ? srclo[j] : make_float2(0.f, 0.f);
+        s.r = r;
         return s;
     };
     // The source sums of RING steps collect in one half of s_ring; at the
@@ -310,21 +334,20 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
         for (int u = 0; u < RING / NWB; ++u) {
             const int st = base + wv * (RING / NWB) + u;
             if (st > st_last) break;  // uniform per wavefront
-            const int r = st * LPI + grp;
-            const int32_t t = t0 + r;
-            const int2 rj = s_rj[wv][r];
-            if (t < t1 && t != tself && jj < rj.y - rj.x) {
+            const int32_t f = 64 * st + lane;
+            const int r = record_of(st);
+            if (f < nflat && t0 + r != tself) {
                 float v = 0.f;
 #pragma unroll
                 for (int w = 0; w < NWB; ++w) v += s_ring[half][st & (RING - 1)][w][lane];
-                spart[(int64_t)s_tu[wv][r] * GL + jj] = v;  // leaf c's own entry for b
+                spart[(int64_t)s_tu[wv][r] * GL + (f - s_pre[wv][r])] = v;  // leaf c's own entry for b
             }
         }
     };
     // one step: both sides of every pair of this lane's source and the
     // wavefront's targets
     auto eval = [&](const Src &sv, int st) {
-        const int r = st * LPI + grp;
+        const int r = sv.r;
         const float4 rd = s_rd[wv][r];
         const float q = sv.v.z;
         float sx, sy, sxl = 0.f, syl = 0.f, thr;
