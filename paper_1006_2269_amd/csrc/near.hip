@@ -222,6 +222,7 @@ __global__ void __launch_bounds__(64 * NWB) k_near32(int64_t nitems, int chunks,
 template <int TM, int GL, int CH, bool ACC64>
 __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(ACC64 ? 3 : 4))) k_near32s(int64_t nitems, const int32_t *__restrict__ stL,
                                                       const float4 *__restrict__ src, const float2 *__restrict__ srclo,
+                                                      int32_t jfar,
                                                       const int32_t *__restrict__ sptr,
                                                       const int32_t *__restrict__ selfpos,
                                                       const int32_t *__restrict__ transU,
@@ -290,9 +291,11 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
     const int32_t nflat = __builtin_amdgcn_readlane(rend, 63);
     const int nsteps = (nflat + 63) / 64;
     struct Src {
-        float4 v;
+        float3 v;   // x, y, q (three words: no dead register left for the compiler to reuse while the load is in flight)
         float2 l;
-        int r;  // the lane's record in this step
+        int r;      // the lane's record in this step
+        float3 rd;  // its centre offset (x, y) and coincidence threshold (z; FP32)
+        float3 rl;  // with ACC64: the offset's low part (x, y) and the two-part threshold (z)
     };
     // record of flat index f = 64 st + lane (below nflat): the number of
     // records ending at or before f.  Those ending before the step are
@@ -306,18 +309,19 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
         for (int i = r_lo; i < r_hi; ++i) r += (f >= __builtin_amdgcn_readlane(rend, i)) ? 1 : 0;
         return r;
     };
-    auto load_src = [&](int st) {  // a lane past the stream loads a point far away with no charge
+    // loads of one step, used a step later (nothing here waits for them)
+    auto load_src = [&](int st) {  // a lane past the stream loads the far point, which has no charge
         const int32_t f = 64 * st + lane;
         const bool ok = f < nflat;
         int r = record_of(st);  // with every lane active: the ballots read all records
         r = ok ? r : 0;
-        const int32_t j = ok ? s_base[wv][r] + f : 0;
+        const int32_t j = ok ? s_base[wv][r] + f : jfar;
         Src s;
-        s.v = src[j];
-        s.v.x = ok ? s.v.x : 0x1p60f;  // far from every target: finite log on the unmasked path
-        s.v.z = ok ? s.v.z : 0.f;
+        s.v = *reinterpret_cast<const float3 *>(src + j);
         s.l = ACC64 ? srclo[j] : make_float2(0.f, 0.f);
         s.r = r;
+        s.rd = *reinterpret_cast<const float3 *>(&s_rd[wv][r]);
+        if constexpr (ACC64) s.rl = *reinterpret_cast<const float3 *>(&s_rl[wv][r]);
         return s;
     };
     // The source sums of RING steps collect in one half of s_ring; at the
@@ -347,12 +351,11 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
     // one step: both sides of every pair of this lane's source and the
     // wavefront's targets
     auto eval = [&](const Src &sv, int st) {
-        const int r = sv.r;
-        const float4 rd = s_rd[wv][r];
+        const float3 rd = sv.rd;
         const float q = sv.v.z;
         float sx, sy, sxl = 0.f, syl = 0.f, thr;
         if constexpr (ACC64) {
-            const float4 rl = s_rl[wv][r];
+            const float3 rl = sv.rl;
             dd_sub(sv.v.x, sv.l.x, rd.x, rl.x, sx, sxl);
             dd_sub(sv.v.y, sv.l.y, rd.y, rl.y, sy, syl);
             thr = rl.z;
@@ -361,32 +364,26 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
             sy = sv.v.y - rd.y;
             thr = rd.z;
         }
-        float sacc = 0.f, lg[TM], r2[ACC64 ? TM : 1];
+        float sacc = 0.f, lg[TM], r2[TM];
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
             if constexpr (ACC64) {
                 const float dx = (tx[k] - sx) + (txl[k] - sxl), dy = (ty[k] - sy) + (tyl[k] - syl);
                 r2[k] = dx * dx + dy * dy;
-                lg[k] = __log2f(r2[k]);
             } else {
                 const float dx = tx[k] - sx, dy = ty[k] - sy;
-                lg[k] = __log2f(dx * dx + dy * dy);
+                r2[k] = dx * dx + dy * dy;
             }
+            lg[k] = __log2f(r2[k]);
         }
-        // separated leaves only (every r^2 exceeds its threshold): the
-        // coincidence mask would change nothing and is skipped
-        if (!__all(rd.w != 0.f)) {
+        // the coincidence mask only where some pair of the step is within its
+        // threshold (a point with itself in the leaf's own record, duplicates)
+        float rmin = r2[0];
 #pragma unroll
-            for (int k = 0; k < TM; ++k) {
-                float rr;
-                if constexpr (ACC64) {
-                    rr = r2[k];
-                } else {
-                    const float dx = tx[k] - sx, dy = ty[k] - sy;
-                    rr = dx * dx + dy * dy;
-                }
-                lg[k] = (rr > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
-            }
+        for (int k = 1; k < TM; ++k) rmin = fminf(rmin, r2[k]);
+        if (!__all(rmin > thr)) {
+#pragma unroll
+            for (int k = 0; k < TM; ++k) lg[k] = (r2[k] > thr) ? lg[k] : 0.f;  // coincident: log is masked, never multiplied
         }
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
@@ -396,15 +393,15 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
         s_ring[(st / RING) & 1][st & (RING - 1)][wv][lane] = sacc;
         if ((st & (RING - 1)) == RING - 1 || st == nsteps - 1) exchange(st);  // uniform per block
     };
+    // the loads are not conditional (a step past the stream loads the far
+    // point): on every path the same loads are in flight, so the wait before
+    // an evaluation covers only the loads it uses
     Src svA = load_src(0), svB;
     for (int st = 0; st < nsteps; st += 2) {
-        const bool two = st + 1 < nsteps;
-        if (two) svB = load_src(st + 1);
+        svB = load_src(st + 1);
         eval(svA, st);
-        if (two) {
-            if (st + 2 < nsteps) svA = load_src(st + 2);
-            eval(svB, st + 1);
-        }
+        svA = load_src(st + 2);
+        if (st + 1 < nsteps) eval(svB, st + 1);
         if (ACC64 && (st & 15) == 14) {  // binary64 flush every 16 steps, summed over the lanes at once
             double v[NV];
 #pragma unroll
@@ -612,6 +609,11 @@ __global__ void k_pack_sources(const float2 *__restrict__ loc, const double *__r
             const double4 g = geomL[leafid[i]];
             lo[i] = make_float2((float)((px[i] - g.x) - (double)l.x), (float)((py[i] - g.y) - (double)l.y));
         }
+    } else if (i == n) {
+        // entry n: a chargeless point far from every leaf (finite logs), which
+        // idle lanes of the pair-once kernel load instead of masking
+        src[n] = make_float4(0x1p60f, 0.f, 0.f, 0.f);
+        if (lo) lo[n] = make_float2(0.f, 0.f);
     }
 }
 
@@ -726,13 +728,14 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage, double *phi
         PhaseScope kernel_scope(c, PH_NEAR_KERNEL, c->side);  // the near-field kernel alone
         if (mode == FMM2D_MODE_FP32_ACC64)
             hipLaunchKernelGGL((k_near32s<TM, GL, CH, true>), grid, block, 0, c->side, nitems, stL,
-                               e.src.as<float4>(), e.srclo.as<float2>(), sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
+                               e.src.as<float4>(), e.srclo.as<float2>(), (int32_t)t.n, sp, t.selfpos.as<int32_t>(),
+                               t.trans.as<int32_t>(),
                                sc.table.as<int2>(),
                                sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
                                spart);
         else
             hipLaunchKernelGGL((k_near32s<TM, GL, CH, false>), grid, block, 0, c->side, nitems, stL,
-                               e.src.as<float4>(), nullptr, sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
+                               e.src.as<float4>(), nullptr, (int32_t)t.n, sp, t.selfpos.as<int32_t>(), t.trans.as<int32_t>(),
                                sc.table.as<int2>(),
                                sc.segoff.as<int32_t>() + nleaf, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), part,
                                spart);
@@ -816,13 +819,13 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage, double *phi) {
     const int64_t maxleaf = (n + nleaf - 1) >> (2 * L);  // ceil(n / 4^L)
     if (!t.nrec_valid) return hipErrorInvalidValue;  // records come with the lists
     if (stage == NEAR_PREP && mode != FMM2D_MODE_FP64) {
-        FMM2D_TRY(e.src.ensure(sizeof(float4) * n));
+        FMM2D_TRY(e.src.ensure(sizeof(float4) * (n + 1)));  // and the far point
         float2 *lo = nullptr;
         if (mode == FMM2D_MODE_FP32_ACC64) {
-            FMM2D_TRY(e.srclo.ensure(sizeof(float2) * n));
+            FMM2D_TRY(e.srclo.ensure(sizeof(float2) * (n + 1)));
             lo = e.srclo.as<float2>();
         }
-        hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, t.loc.as<float2>(),
+        hipLaunchKernelGGL(k_pack_sources, dim3(grid_for(n + 1, 256)), dim3(256), 0, c->stream, t.loc.as<float2>(),
                            e.qs.as<double>(), n, e.src.as<float4>(), t.px.as<double>(), t.py.as<double>(),
                            t.leafid.as<int32_t>(), t.geom.as<double4>() + level_offset(L), lo);
     }
