@@ -179,6 +179,7 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         c->tree.m_itemoff.release();
         c->ev.xpart.release();
         c->ev.xsum.release();
+        c->ev.mpart.release();
         for (DevBuf *b : {&e.binom, &e.mhat, &e.part, &e.npart, &e.gpart, &e.A, &e.B, &e.qs, &e.work,
                           &e.src, &e.srclo})
             b->release();

@@ -37,6 +37,7 @@ constexpr int64_t LANE_ENTRIES = 32768;
 constexpr int PCH = 512;  // least points per chunk on the other levels
 constexpr int XT = 16;    // coefficients per pass (orders above PMAX_FAST - 1)
 constexpr int PMAX_FAST = 32;  // orders p + 1 up to this many take the specialised kernels
+constexpr int MSPAN = 64;      // X row positions per M2P item (at most; the spans of a row are balanced)
 constexpr int MPC = 16;   // leaf points per M2P pass
 
 // Point range [a, e) of box b of level l (its leaves are b 4^(L-l) onwards).
@@ -75,8 +76,11 @@ __host__ __device__ inline int m2p_width(int64_t n, int l) {
 // P2L (the entries of X(g) whose source box is the larger): int4 (target
 // box, row position, row position + 1, first point of the chunk or -1 for
 // the whole entry); levels from `lane_level` on take whole entries.  M2P
-// (when X(g) holds an entry whose source box is the smaller): int2 (g, first
-// point), one per 64 points on levels of width 64, one per box on the others.
+// (when X(g) holds an entry whose source box is the smaller): int4 (g, first
+// point, row span start, end): the points in passes of 64 on levels of width
+// 64, the whole box on the others, times the row in balanced spans of at
+// most MSPAN positions (point pass major), so that no item holds more than
+// MSPAN entries however long the row.
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox, int lane_level,
                                                  const int32_t *__restrict__ xptr_all,
@@ -85,7 +89,7 @@ __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox,
                                                  int32_t *__restrict__ cnt, int32_t *__restrict__ mcnt,
                                                  const int32_t *__restrict__ itemoff,
                                                  const int32_t *__restrict__ mitemoff, int4 *__restrict__ items,
-                                                 int2 *__restrict__ mitems) {
+                                                 int4 *__restrict__ mitems) {
     const int64_t g = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (g >= nbox) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
@@ -141,10 +145,15 @@ __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox,
         int32_t a, e;
         box_range(stL, L, l, b, a, e);
         const int32_t step = m2p_width(n, l) == 64 ? 64 : e - a;
-        km = (e - a + step - 1) / step;
+        const int32_t npc = step > 0 ? (e - a + step - 1) / step : 0;
+        const int32_t nsp = (t1 - t0 + MSPAN - 1) / MSPAN, span = (t1 - t0 + nsp - 1) / nsp;
+        km = npc * nsp;
         if (FILL) {
             const int32_t m0 = mitemoff[g];
-            for (int32_t q = lane; q < km; q += 64) mitems[m0 + q] = make_int2((int32_t)g, a + q * step);
+            for (int32_t q = lane; q < km; q += 64) {
+                const int32_t pc = q / nsp, s0 = t0 + (q - pc * nsp) * span;
+                mitems[m0 + q] = make_int4((int32_t)g, a + pc * step, s0, s0 + span < t1 ? s0 + span : t1);
+            }
         }
     }
     if (!FILL && lane == 0) {
@@ -384,29 +393,28 @@ __global__ void __launch_bounds__(256) k_x_reduce(int p, int64_t nbox, const int
     xsum[g * (p + 1) + lane] = acc;
 }
 
-// M2P of one level, orders p + 1 <= 32: one wavefront per item.  The box's
-// X row is taken 32 entries at a time: its M2P entries (the target box the
-// larger) are compacted by ballot, their centres, scales and multipoles
-// staged in the wavefront's LDS slice by coalesced loads, then evaluated
-// from there (same-address reads, served by broadcast; 16 entries at a time
-// above order 16).  WIDE (boxes of 64
-// points or more): the item's 64 points one per lane, every lane taking the
-// entries in row order.  Otherwise (boxes of at most MP < 64 points):
-// lane = group * MP + point, the compacted entries dealt to the 64 / MP
-// groups in turn, each point's group sums met by a butterfly over the group
-// bits.  Items of one launch touch disjoint points; the levels run one
-// launch after the other, so every point's sum has a fixed order.
+// M2P, orders p + 1 <= 32: one wavefront per item, the items of every level
+// in one launch (those of levels of width 64, or those of the narrower
+// levels).  The item's row span is taken 32 positions at a time: its M2P
+// entries (the target box the larger) are compacted by ballot, their
+// centres, scales and multipoles staged in the wavefront's LDS slice by
+// coalesced loads, then evaluated from there (same-address reads, served by
+// broadcast; 16 entries at a time above order 16).  WIDE (levels of width
+// 64): the item's 64 points one per lane, every lane taking the entries in
+// row order.  Otherwise (boxes of at most mp < 64 points): lane = group * mp
+// + point, the compacted entries dealt to the 64 / mp groups in turn, each
+// point's group sums met by a butterfly over the group bits.  Each item
+// writes its sums at its points to its own row of mpart (lane = point
+// offset); k_m2p_sum adds them to the potentials.
 template <int P1>
 constexpr int m_stage() { return P1 <= 16 ? 32 : 16; }  // entries staged at once (LDS of 32 KB per block)
 template <int P1, bool WIDE>
-__global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int2 *__restrict__ items,
-                                                 const int32_t *__restrict__ first, const int32_t *__restrict__ end,
-                                                 const int32_t *__restrict__ xptr_all,
-                                                 const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
-                                                 const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
-                                                 const cd *__restrict__ A, const double *__restrict__ px,
-                                                 const double *__restrict__ py, const int32_t *__restrict__ perm,
-                                                 double *__restrict__ phi) {
+__global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__restrict__ items,
+                                             const int32_t *__restrict__ first, const int32_t *__restrict__ end,
+                                             const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
+                                             const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
+                                             const cd *__restrict__ A, const double *__restrict__ px,
+                                             const double *__restrict__ py, double *__restrict__ mpart) {
     constexpr int MSTAGE = m_stage<P1>();
     __shared__ cd s_a[4][MSTAGE * P1];
     __shared__ double s_g[4][MSTAGE][3];
@@ -414,10 +422,12 @@ __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int
     const int32_t it = __builtin_amdgcn_readfirstlane(*first + (int32_t)(blockIdx.x * 4 + threadIdx.x / 64));
     if (it >= *end) return;  // uniform per wavefront
     const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int2 w = items[it];
+    const int4 w = items[it];
+    const int l = level_of(w.x);
     const int64_t b = w.x - level_offset(l);
     int32_t a, e;
     box_range(stL, L, l, b, a, e);
+    const int mp = WIDE ? 64 : m2p_width(n, l);
     const int grp = WIDE ? 0 : lane / mp;
     const int ng = WIDE ? 1 : 64 / mp;
     const int32_t i = w.y + (WIDE ? lane : lane % mp);
@@ -425,13 +435,12 @@ __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int
     const int32_t ii = act ? i : a;  // lanes past the box evaluate at its first point (finite, not written)
     const double zx = px[ii], zy = py[ii];
     const double rb = geom[w.x].z;
-    const int32_t *ptr = xptr_all + ptr_offset(l);
     const int32_t *row = xidx + xoff[l];
-    const int32_t t1 = ptr[b + 1];
+    const int32_t t1 = w.w;
     cd *sa = s_a[wv];
     double acc = 0.0;
     int dealt = 0;  // compacted entries so far (the next one goes to group dealt % ng)
-    for (int32_t tb = ptr[b]; tb < t1; tb += MSTAGE) {
+    for (int32_t tb = w.z; tb < t1; tb += MSTAGE) {
         bool ok = false;
         int64_t cg = 0;
         double4 gc = make_double4(0.0, 0.0, 0.0, 1.0);
@@ -469,7 +478,35 @@ __global__ void __launch_bounds__(256) k_m2p_lvl(int L, int l, int mp, const int
     }
     if (!WIDE)
         for (int off = mp; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
-    if (grp == 0 && act) phi[perm[i]] += acc;
+    if (grp == 0 && act) mpart[(int64_t)it * 64 + lane] = acc;
+}
+
+// Per point (leaf order): its M2P sums, level by level and within a level in
+// item order (the row spans of its point pass), added to its potential.
+__global__ void __launch_bounds__(256) k_m2p_sum(int L, int64_t n, const int32_t *__restrict__ leafid,
+                                                 const int32_t *__restrict__ stL,
+                                                 const int32_t *__restrict__ itemoff,
+                                                 const double *__restrict__ mpart, const int32_t *__restrict__ perm,
+                                                 double *__restrict__ phi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t leaf = leafid[i];
+    double acc = 0.0;
+    bool any = false;
+    for (int l = 1; l <= L; ++l) {
+        const int64_t b = leaf >> (2 * (L - l)), g = level_offset(l) + b;
+        const int32_t i0 = itemoff[g], i1 = itemoff[g + 1];
+        if (i0 == i1) continue;
+        int32_t a, e;
+        box_range(stL, L, l, b, a, e);
+        const int32_t step = m2p_width(n, l) == 64 ? 64 : e - a;
+        const int32_t npc = (e - a + step - 1) / step, nsp = (i1 - i0) / npc;
+        const int32_t pc = ((int32_t)i - a) / step, o = (int32_t)i - a - pc * step;
+        const double *row = mpart + (int64_t)(i0 + pc * nsp) * 64 + o;
+        for (int32_t s = 0; s < nsp; ++s) acc += row[(int64_t)s * 64];
+        any = true;
+    }
+    if (any) phi[perm[i]] += acc;
 }
 
 // M2P for orders p + 1 > 32: one lane per point of the leaf.
@@ -552,19 +589,27 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     t.x_bound_wave = bw;
     t.x_bound_lane = bl;
     t.x_lane_level = lane_level;
-    // M2P items: at most min(4^l, X entries) boxes of level l have one, each
-    // with ceil(points / 64) items on levels of width 64, one on the others
-    int64_t mb = 0;
-    for (int l = 0; l <= L; ++l) {
-        const int64_t nx = l >= 1 ? t.x_off[l + 1] - t.x_off[l] : 0, nb = int64_t(1) << (2 * l);
+    // M2P items: at most min(4^l, X entries) boxes of level l have some, each
+    // with its point passes (ceil(points / 64) on levels of width 64, one on
+    // the others) times ceil(row / MSPAN) spans; the spans of a level's rows
+    // number at most boxes + entries / MSPAN.  Levels of width 64 come first.
+    int wl = L + 1;
+    for (int l = 1; l <= L; ++l)
+        if (m2p_width(t.n, l) < 64) {
+            wl = l;
+            break;
+        }
+    int64_t mw = 0, mn = 0;
+    for (int l = 1; l <= L; ++l) {
+        const int64_t nx = t.x_off[l + 1] - t.x_off[l], nb = int64_t(1) << (2 * l);
         const int64_t boxes = nx < nb ? nx : nb;
-        t.m_bound[l] = boxes * (m2p_width(t.n, l) == 64 ? (level_box_max(t.n, l) + 63) / 64 : 1);
-        mb += t.m_bound[l];
+        const int64_t npc = m2p_width(t.n, l) == 64 ? (level_box_max(t.n, l) + 63) / 64 : 1;
+        (l < wl ? mw : mn) += npc * (boxes + nx / MSPAN);
     }
-    for (int l = L + 1; l <= FMM2D_MAX_LEVELS; ++l) t.m_bound[l] = 0;
+    if (mw + mn > INT32_MAX) return hipErrorInvalidValue;  // item indices are int32
+    t.m_wide_level = wl;
     FMM2D_TRY(c->scr.mcnt.ensure(sizeof(int32_t) * nbox));
     FMM2D_TRY(t.m_itemoff.ensure(sizeof(int32_t) * (nbox + 1)));
-    FMM2D_TRY(t.m_items.ensure(sizeof(int2) * (mb > 0 ? mb : 1)));
     int32_t *cnts[2] = {c->scr.segcnt.as<int32_t>(), c->scr.mcnt.as<int32_t>()};
     int32_t *offs[2] = {t.x_itemoff.as<int32_t>(), t.m_itemoff.as<int32_t>()};
     hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 4)), dim3(256), 0, c->stream, L, t.n, nbox,
@@ -572,9 +617,19 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     FMM2D_TRY(hipGetLastError());
     const int32_t *cin[2] = {cnts[0], cnts[1]};
     FMM2D_TRY(scan_exclusive_n(c, 2, cin, nbox, offs));
+    // the M2P item counts (before the narrower levels, and in all), read back
+    // so that the items and their partial sums (512 bytes each) are sized to
+    // the count rather than to the bound
+    int32_t hm[2] = {0, 0};
+    FMM2D_TRY(hipMemcpyAsync(&hm[0], offs[1] + level_offset(wl), sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    FMM2D_TRY(hipMemcpyAsync(&hm[1], offs[1] + nbox, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    FMM2D_TRY(hipStreamSynchronize(c->stream));
+    t.m_bound_wide = hm[0];
+    t.m_bound_narrow = hm[1] - hm[0];
+    FMM2D_TRY(t.m_items.ensure(sizeof(int4) * (hm[1] > 0 ? hm[1] : 1)));
     hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 4)), dim3(256), 0, c->stream, L, t.n, nbox,
                        lane_level, xptr, xidx, xoff, geom, stL, nullptr, nullptr, offs[0], offs[1],
-                       t.x_items.as<int4>(), t.m_items.as<int2>());
+                       t.x_items.as<int4>(), t.m_items.as<int4>());
     FMM2D_TRY(hipGetLastError());
     t.x_ready = true;
     return hipSuccess;
@@ -651,22 +706,28 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
                            xoff, geom, A, px, py, perm, phi);
         return hipGetLastError();
     }
-    const int2 *items = t.m_items.as<int2>();
-    for (int l = 1; l <= L; ++l) {
-        if (t.m_bound[l] == 0) continue;
-        const int mp = m2p_width(t.n, l);
-        // the level's items: [m_itemoff[first box of l], m_itemoff[first box of l + 1])
-        const int32_t *first = t.m_itemoff.as<int32_t>() + level_offset(l), *end = t.m_itemoff.as<int32_t>() + level_offset(l + 1);
-        const dim3 grid(grid_for(t.m_bound[l], 4));
-        switch ((p + 1) * 2 + (mp == 64)) {
+    const int4 *items = t.m_items.as<int4>();
+    const int64_t nbox = level_offset(L + 1), mb = t.m_bound_wide + t.m_bound_narrow;
+    FMM2D_TRY(c->ev.mpart.ensure(sizeof(double) * 64 * (mb > 0 ? mb : 1)));
+    double *mpart = c->ev.mpart.as<double>();
+    const int32_t *off = t.m_itemoff.as<int32_t>();
+    for (int pass = 0; pass < 2; ++pass) {
+        // the items of the levels of width 64, then those of the others
+        const bool wide = pass == 0;
+        const int64_t bound = wide ? t.m_bound_wide : t.m_bound_narrow;
+        if (bound == 0) continue;
+        const int32_t *first = off + (wide ? 0 : level_offset(t.m_wide_level));
+        const int32_t *end = off + (wide ? level_offset(t.m_wide_level) : nbox);
+        const dim3 grid(grid_for(bound, 4));
+        switch ((p + 1) * 2 + wide) {
 #define FMM2D_M2P(P1)                                                                                             \
     case 2 * P1:                                                                                                  \
-        hipLaunchKernelGGL((k_m2p_lvl<P1, false>), grid, block, 0, c->stream, L, l, mp, items, first, end, xptr,  \
-                           xidx, xoff, geom, stL, A, px, py, perm, phi);                                          \
+        hipLaunchKernelGGL((k_m2p<P1, false>), grid, block, 0, c->stream, L, t.n, items, first, end, xidx, xoff,  \
+                           geom, stL, A, px, py, mpart);                                                          \
         break;                                                                                                    \
     case 2 * P1 + 1:                                                                                              \
-        hipLaunchKernelGGL((k_m2p_lvl<P1, true>), grid, block, 0, c->stream, L, l, mp, items, first, end, xptr,   \
-                           xidx, xoff, geom, stL, A, px, py, perm, phi);                                          \
+        hipLaunchKernelGGL((k_m2p<P1, true>), grid, block, 0, c->stream, L, t.n, items, first, end, xidx, xoff,   \
+                           geom, stL, A, px, py, mpart);                                                          \
         break;
             FMM2D_M2P(2) FMM2D_M2P(3) FMM2D_M2P(4) FMM2D_M2P(5) FMM2D_M2P(6) FMM2D_M2P(7) FMM2D_M2P(8)
             FMM2D_M2P(9) FMM2D_M2P(10) FMM2D_M2P(11) FMM2D_M2P(12) FMM2D_M2P(13) FMM2D_M2P(14) FMM2D_M2P(15)
@@ -679,6 +740,8 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
         }
         FMM2D_TRY(hipGetLastError());
     }
+    hipLaunchKernelGGL(k_m2p_sum, dim3(grid_for(t.n, 256)), block, 0, c->stream, L, t.n, t.leafid.as<int32_t>(), stL,
+                       off, mpart, perm, phi);
     return hipSuccess;
 }
 

@@ -94,8 +94,12 @@ struct TreeState {
     int64_t x_bound_wave = 0;       // upper bound of the wavefront-per-item P2L items (launch size)
     int64_t x_bound_lane = 0;       // ... of the lane-per-item ones
     int x_lane_level = 0;           // first level of lane-per-item P2L (all deeper levels too)
-    DevBuf m_items, m_itemoff;      // M2P work items (target box, first point) per box, level by level
-    int64_t m_bound[FMM2D_MAX_LEVELS + 1] = {};  // upper bound of each level's M2P items (launch size)
+    // M2P work items int4 (target box, first point, row span start, end) per
+    // box, level by level; per global box its first item (+ count)
+    DevBuf m_items, m_itemoff;
+    int m_wide_level = 0;           // first level whose M2P pass is narrower than 64 points
+    int64_t m_bound_wide = 0;       // upper bound of the M2P items of the levels before it (launch size)
+    int64_t m_bound_narrow = 0;     // ... of the levels from it on
     bool x_ready = false;
     DevBuf lsum;                    // double: per near_lo segment and source lane, its entries' source sums
     std::vector<int64_t> s_off, w_off, x_off;  // host copy: pool offset of each level
@@ -119,6 +123,7 @@ struct EvalState {
     DevBuf gpart;           // near-field gradient partial sums (fmm2d_evaluate_field)
     DevBuf xpart;           // P2L partial expansions of the exchanged-roles items
     DevBuf xsum;            // their sum per target box (boxes with items)
+    DevBuf mpart;           // double [M2P items][64]: each item's sums at its points
 };
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream

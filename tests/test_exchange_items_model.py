@@ -24,6 +24,13 @@ def level_offset(l):
     return (4 ** l - 1) // 3
 
 
+def level_of(g):
+    l = 0
+    while level_offset(l + 1) <= g:
+        l += 1
+    return l
+
+
 def level_box_max(n, l):
     return -(-n // 4 ** l)
 
@@ -107,36 +114,82 @@ def m2p_width(n, l):
     return w
 
 
+MSPAN = 64
+
+
 @pytest.mark.parametrize("case", ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "ring_scaled_20k_L6",
                                   "duplicates_4k_L4", "uniform_2000_L2", "uniform_10k_L5"])
 def test_m2p_items_cover_and_bound(orc, case):
-    """M2P items per level: each box with an M2P entry covered exactly once
-    (64-point items on levels of width 64, the whole box within the pass
-    width on the others), item counts within the per-level launch bounds."""
+    """M2P items: per box with an M2P entry, its point passes (64 points on
+    levels of width 64, the whole box within the pass width on the others)
+    times balanced spans of its X row of at most MSPAN positions, point pass
+    major.  Checks: the item count within the schedule's bound, every
+    (point, row position) pair of such a box in exactly one item, and the
+    per-point sum's indexing (pass and span from the box's item range) naming
+    exactly the items that hold the point, at a lane below 64."""
     maker, L = TREE_CASES[case]
     ps = maker()
     t = orc.tree(ps.x, ps.y, L)
     ls = orc.lists_opt(t, 0.5, parent=True, swap_levels=range(1, L + 1))
     n, starts = ps.n, t.leaf_start
-    total = 0
+    wl = next((l for l in range(1, L + 1) if m2p_width(n, l) < 64), L + 1)
+    bound_w = bound_n = 0
+    items, itemoff = [], {}
     for l in range(1, L + 1):
         nx = int(ls.xptr[l][-1])
         mp = m2p_width(n, l)
-        bound = min(nx, 4 ** l) * (-(-level_box_max(n, l) // 64) if mp == 64 else 1)
+        npc_max = -(-level_box_max(n, l) // 64) if mp == 64 else 1
+        bnd = npc_max * (min(nx, 4 ** l) + nx // MSPAN)
+        if l < wl:
+            bound_w += bnd
+        else:
+            bound_n += bnd
         r = t.geom[level_offset(l):level_offset(l + 1), 2]
-        count = 0
         for b in range(4 ** l):
-            row = ls.xidx[l][ls.xptr[l][b]:ls.xptr[l][b + 1]]
-            if not any(r[b] > r[c] for c in row):
-                continue
-            a, e = starts[b << 2 * (L - l)], starts[(b + 1) << 2 * (L - l)]
-            if mp == 64:
-                firsts = list(range(a, e, 64))
-                assert firsts[-1] + 64 >= e
-            else:
-                firsts = [a]
-                assert e - a <= mp
-            count += len(firsts)
-        assert count <= bound
-        total += count
-    assert total >= 0
+            t0, t1 = int(ls.xptr[l][b]), int(ls.xptr[l][b + 1])
+            row = ls.xidx[l][t0:t1]
+            g = level_offset(l) + b
+            i0 = len(items)
+            if any(r[b] > r[c] for c in row):
+                a, e = int(starts[b << 2 * (L - l)]), int(starts[(b + 1) << 2 * (L - l)])
+                step = 64 if mp == 64 else e - a
+                assert e - a <= step or mp == 64
+                npc = -(-(e - a) // step)
+                nsp = -(-(t1 - t0) // MSPAN)
+                span = -(-(t1 - t0) // nsp)
+                for q in range(npc * nsp):
+                    pc, sp = divmod(q, nsp)
+                    s0 = t0 + sp * span
+                    items.append((g, a + pc * step, s0, min(t1, s0 + span)))
+            itemoff[g] = (i0, len(items))
+    nw = sum(1 for it in items if level_of(it[0]) < wl)
+    assert nw <= bound_w and len(items) - nw <= bound_n
+    # items of a box consecutive, boxes in order (wide levels first)
+    gs = [it[0] for it in items]
+    assert gs == sorted(gs)
+    for g, (i0, i1) in itemoff.items():
+        if i0 == i1:
+            continue
+        l = level_of(g)
+        b = g - level_offset(l)
+        a, e = int(starts[b << 2 * (L - l)]), int(starts[(b + 1) << 2 * (L - l)])
+        t0, t1 = int(ls.xptr[l][b]), int(ls.xptr[l][b + 1])
+        step = 64 if m2p_width(n, l) == 64 else e - a
+        npc = -(-(e - a) // step)
+        assert (i1 - i0) % npc == 0
+        nsp = (i1 - i0) // npc
+        cover = np.zeros((e - a, t1 - t0), dtype=np.int64)
+        for k in range(i0, i1):
+            _, f, s0, s1 = items[k]
+            assert s1 - s0 <= MSPAN and t0 <= s0 < s1 <= t1
+            pts = np.arange(f, min(f + step, e))
+            cover[np.ix_(pts - a, np.arange(s0, s1) - t0)] += 1
+        assert (cover == 1).all()
+        # the per-point sum: pass pc, items i0 + pc * nsp + [0, nsp), lane o
+        for i in range(a, e):
+            pc = (i - a) // step
+            o = i - a - pc * step
+            assert 0 <= o < 64 and o < step
+            for s in range(nsp):
+                _, f, s0, s1 = items[i0 + pc * nsp + s]
+                assert f <= i < f + step and i - f == o
