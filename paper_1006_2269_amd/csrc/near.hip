@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(64 * NWB) __attribute__((amdgpu_waves_per_eu(A
                                                       double *__restrict__ part, float *__restrict__ spart) {
     static_assert(NEAR_SEG <= 64, "one record per lane");
     static_assert(CH == NWB, "the chunks of one segment fill a block");
-    static_assert(TM == 8 || TM == 12 || TM == 16, "targets per wavefront");
+    static_assert(TM == 8 || TM == 10 || TM == 12 || TM == 16, "targets per wavefront");
     constexpr int NV = TM <= 8 ? 8 : 16;  // butterfly width (TM padded with zeros)
     constexpr int RING = 8;  // steps of source sums per exchange
     __shared__ int32_t s_base[NWB][64];  // source position of a record's flat index f: s_base + f
@@ -836,6 +836,7 @@ hipError_t leaf_pass(fmm2d_ctx *c, int p, int mode, int stage, double *phi) {
         // each leaf pair once, the four chunks of targets of a leaf in the
         // four wavefronts of a block
         if (ml <= 32) return launch_near_sym<8, 32, 4>(c, p, mode, stage, phi);
+        if (ml <= 40) return launch_near_sym<10, 64, 4>(c, p, mode, stage, phi);  // 4 chunks of 10 targets
         if (ml <= 48) return launch_near_sym<12, 64, 4>(c, p, mode, stage, phi);  // 4 chunks of 12 targets
         return launch_near_sym<16, 64, 4>(c, p, mode, stage, phi);
     }

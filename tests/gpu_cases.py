@@ -60,9 +60,11 @@ TREE_CASES = {
     # leaves of 50 and 63 points: the FP32 near field in four chunks of 16
     # targets per leaf (one block of four wavefronts per list segment)
     "uniform_3200_L3": (lambda: W.uniform(3200, 14), 3),
-    # leaves of 39 points: the pair-once near field with 4 chunks of 12
+    # leaves of 39 points: the pair-once near field with 4 chunks of 10
     # targets per leaf
     "uniform_2500_L3": (lambda: W.uniform(2500, 16), 3),
+    # leaves of 45 and 46 points: 4 chunks of 12 targets
+    "uniform_2900_L3": (lambda: W.uniform(2900, 17), 3),
     "duplicates_4k_L3": (lambda: _duplicates(4000, 8), 3),
     # leaves of 125 points: more than one point per lane in the
     # wavefront-per-leaf multipole kernel

@@ -123,7 +123,7 @@ def test_direct_judge_matches_oracle(fmm, orc, case):
 @pytest.mark.parametrize("mode,tol", [("fp32", 2e-5), ("fp32_acc64", 2e-5), ("bf16x3", 1e-3)])
 @pytest.mark.parametrize("case", ["uniform_10k_L5", "clustered_scaled_20k_L6", "ring_scaled_20k_L6",
                                   "duplicates_4k_L4", "mixed_scaled_20k_L6", "uniform_20k_L5", "uniform_3200_L3",
-                                  "uniform_2500_L3", "duplicates_4k_L3"])
+                                  "uniform_2500_L3", "uniform_2900_L3", "duplicates_4k_L3"])
 def test_reduced_modes_error(fmm, orc, case, mode, tol):
     _skip_faulted(case, 0.5)
     maker, L = TREE_CASES[case]
