@@ -163,10 +163,15 @@ __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox,
 }
 
 // The scaled division and hypot for |w|^2 <= 2^-960 (where |w|^2 could
-// underflow), kept out of line: no input of ordinary scale reaches it.
-__device__ __attribute__((noinline)) cd recip_tiny(double s, double dx, double dy, double &logw) {
-    logw = log(hypot(dx, dy));
-    return cdiv(cd{s, 0.0}, cd{dx, dy});
+// underflow), kept out of line: no input of ordinary scale reaches it.  Both
+// results come back by value (a reference argument of an out-of-line call
+// would keep log|w| in scratch memory on the common path too).
+struct RhoLog {
+    cd rho;
+    double logw;
+};
+__device__ __attribute__((noinline)) RhoLog recip_tiny(double s, double dx, double dy) {
+    return RhoLog{cdiv(cd{s, 0.0}, cd{dx, dy}), log(hypot(dx, dy))};
 }
 
 // rho = s / w for w = (dx, dy) != 0, and log|w|.
@@ -182,7 +187,9 @@ __device__ inline cd recip_scaled(double s, double dx, double dy, double &logw) 
         const double inv = s * r;
         return cd{dx * inv, -dy * inv};
     }
-    return recip_tiny(s, dx, dy, logw);
+    const RhoLog t = recip_tiny(s, dx, dy);
+    logw = t.logw;
+    return t.rho;
 }
 
 // P2L sums of one source point about the target (gb): s[0] += q log|w|,
