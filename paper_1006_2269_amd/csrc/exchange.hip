@@ -61,14 +61,33 @@ __host__ __device__ inline int64_t level_chunk(int64_t n, int l) {
     return (m + k - 1) / k;
 }
 
-// Points of an M2P pass over a box of level l: 64 when its boxes hold 64
-// points or more (one item per 64 points), else the power of two at or
-// above the largest box (one item per box, 64 / that many lane groups).
+// M2P passes over the boxes of level l.  Boxes of M2P_WIDE_PTS points or
+// more: passes of 64 points, one per lane (WIDE).  Smaller boxes: passes of
+// w points, lane = group * w + point, the entries dealt to m2p_groups(w)
+// groups; w = ceil(m / passes) for the number of passes (the least possible,
+// ceil(m / 64), up to three more: each pass stages the entries again) that
+// fills the most lanes per entry evaluated (m points x groups / passes, m the
+// level's largest box), the fewest passes on a tie.  At most 8 groups: the
+// groups read different entries' coefficients at once, and 8 entries 272
+// bytes apart fall in distinct LDS banks.
+constexpr int M2P_WIDE_PTS = 256;
+__host__ __device__ inline int m2p_groups(int w) { return 64 / w < 8 ? 64 / w : 8; }
+__host__ __device__ inline bool m2p_wide(int64_t n, int l) { return level_box_max(n, l) >= M2P_WIDE_PTS; }
 __host__ __device__ inline int m2p_width(int64_t n, int l) {
     const int64_t m = level_box_max(n, l);
-    int w = 1;
-    while (w < m && w < 64) w <<= 1;
-    return w;
+    if (m >= M2P_WIDE_PTS) return 64;
+    int best_w = 64, best_g = 0, best_np = 1;
+    const int np0 = (int)((m + 63) / 64);
+    for (int np = np0; np <= np0 + 3; ++np) {
+        const int w = (int)((m + np - 1) / np);
+        const int ng = m2p_groups(w);
+        if ((int64_t)ng * best_np > (int64_t)best_g * np) {  // more lanes per pass and entry
+            best_w = w;
+            best_g = ng;
+            best_np = np;
+        }
+    }
+    return best_w;
 }
 
 // Work items per global box g, one wavefront per box (lanes over the X row,
@@ -77,10 +96,10 @@ __host__ __device__ inline int m2p_width(int64_t n, int l) {
 // box, row position, row position + 1, first point of the chunk or -1 for
 // the whole entry); levels from `lane_level` on take whole entries.  M2P
 // (when X(g) holds an entry whose source box is the smaller): int4 (g, first
-// point, row span start, end): the points in passes of 64 on levels of width
-// 64, the whole box on the others, times the row in balanced spans of at
-// most MSPAN positions (point pass major), so that no item holds more than
-// MSPAN entries however long the row.
+// point, row span start, end): the points in passes of m2p_width(n, l),
+// times the row in balanced spans of at most MSPAN positions (point pass
+// major), so that no item holds more than MSPAN entries however long the
+// row.
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox, int lane_level,
                                                  const int32_t *__restrict__ xptr_all,
@@ -144,8 +163,8 @@ __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox,
     if (m2p) {
         int32_t a, e;
         box_range(stL, L, l, b, a, e);
-        const int32_t step = m2p_width(n, l) == 64 ? 64 : e - a;
-        const int32_t npc = step > 0 ? (e - a + step - 1) / step : 0;
+        const int32_t step = m2p_width(n, l);
+        const int32_t npc = (e - a + step - 1) / step;
         const int32_t nsp = (t1 - t0 + MSPAN - 1) / MSPAN, span = (t1 - t0 + nsp - 1) / nsp;
         km = npc * nsp;
         if (FILL) {
@@ -401,18 +420,17 @@ __global__ void __launch_bounds__(256) k_x_reduce(int p, int64_t nbox, const int
 }
 
 // M2P, orders p + 1 <= 32: one wavefront per item, the items of every level
-// in one launch (those of levels of width 64, or those of the narrower
-// levels).  The item's row span is taken 32 positions at a time: its M2P
-// entries (the target box the larger) are compacted by ballot, their
-// centres, scales and multipoles staged in the wavefront's LDS slice by
-// coalesced loads, then evaluated from there (same-address reads, served by
-// broadcast; 16 entries at a time above order 16).  WIDE (levels of width
-// 64): the item's 64 points one per lane, every lane taking the entries in
-// row order.  Otherwise (boxes of at most mp < 64 points): lane = group * mp
-// + point, the compacted entries dealt to the 64 / mp groups in turn, each
-// point's group sums met by a butterfly over the group bits.  Each item
-// writes its sums at its points to its own row of mpart (lane = point
-// offset); k_m2p_sum adds them to the potentials.
+// in one launch (those of the WIDE levels, or those of the others).  The
+// item's row span is taken 32 positions at a time: its M2P entries (the
+// target box the larger) are compacted by ballot, their centres, scales and
+// multipoles staged in the wavefront's LDS slice by coalesced loads, then
+// evaluated from there (same-address reads within a group, served by
+// broadcast; 16 entries at a time above order 16).  WIDE: the item's 64
+// points one per lane, every lane taking the entries in row order.
+// Otherwise (passes of mp points): lane = group * mp + point, the compacted
+// entries dealt to the groups in turn, group 0 adding the others' sums at its
+// point in group order.  Each item writes its sums at its points to its own
+// row of mpart (lane = point offset); k_m2p_sum adds them to the potentials.
 template <int P1>
 constexpr int m_stage() { return P1 <= 16 ? 32 : 16; }  // entries staged at once (LDS of 32 KB per block)
 template <int P1, bool WIDE>
@@ -435,10 +453,10 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
     int32_t a, e;
     box_range(stL, L, l, b, a, e);
     const int mp = WIDE ? 64 : m2p_width(n, l);
-    const int grp = WIDE ? 0 : lane / mp;
-    const int ng = WIDE ? 1 : 64 / mp;
+    const int ng = WIDE ? 1 : m2p_groups(mp);
+    const int grp = WIDE ? 0 : lane / mp;  // lanes of group ng and above idle
     const int32_t i = w.y + (WIDE ? lane : lane % mp);
-    const bool act = i < e;
+    const bool act = i < e && i < w.y + mp && grp < ng;
     const int32_t ii = act ? i : a;  // lanes past the box evaluate at its first point (finite, not written)
     const double zx = px[ii], zy = py[ii];
     const double rb = geom[w.x].z;
@@ -483,8 +501,12 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
         dealt += k;
         __builtin_amdgcn_wave_barrier();  // the slice is rewritten by the next stage
     }
-    if (!WIDE)
-        for (int off = mp; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if (!WIDE) {
+        // group 0's lanes add the other groups' sums at their point, in group order
+        double tot = acc;
+        for (int gq = 1; gq < ng; ++gq) tot += __shfl(acc, lane + gq * mp < 64 ? lane + gq * mp : lane, 64);
+        acc = tot;
+    }
     if (grp == 0 && act) mpart[(int64_t)it * 64 + lane] = acc;
 }
 
@@ -506,7 +528,7 @@ __global__ void __launch_bounds__(256) k_m2p_sum(int L, int64_t n, const int32_t
         if (i0 == i1) continue;
         int32_t a, e;
         box_range(stL, L, l, b, a, e);
-        const int32_t step = m2p_width(n, l) == 64 ? 64 : e - a;
+        const int32_t step = m2p_width(n, l);
         const int32_t npc = (e - a + step - 1) / step, nsp = (i1 - i0) / npc;
         const int32_t pc = ((int32_t)i - a) / step, o = (int32_t)i - a - pc * step;
         const double *row = mpart + (int64_t)(i0 + pc * nsp) * 64 + o;
@@ -602,7 +624,7 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     // number at most boxes + entries / MSPAN.  Levels of width 64 come first.
     int wl = L + 1;
     for (int l = 1; l <= L; ++l)
-        if (m2p_width(t.n, l) < 64) {
+        if (!m2p_wide(t.n, l)) {
             wl = l;
             break;
         }
@@ -610,7 +632,7 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     for (int l = 1; l <= L; ++l) {
         const int64_t nx = t.x_off[l + 1] - t.x_off[l], nb = int64_t(1) << (2 * l);
         const int64_t boxes = nx < nb ? nx : nb;
-        const int64_t npc = m2p_width(t.n, l) == 64 ? (level_box_max(t.n, l) + 63) / 64 : 1;
+        const int64_t w = m2p_width(t.n, l), npc = (level_box_max(t.n, l) + w - 1) / w;
         (l < wl ? mw : mn) += npc * (boxes + nx / MSPAN);
     }
     if (mw + mn > INT32_MAX) return hipErrorInvalidValue;  // item indices are int32

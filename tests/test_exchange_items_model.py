@@ -107,11 +107,42 @@ def test_p2l_items_cover_and_bound(orc, case, thresholds):
     assert gs == sorted(gs)
 
 
+M2P_WIDE_PTS = 256
+
+
+def m2p_groups(w):
+    return min(64 // w, 8)
+
+
 def m2p_width(n, l):
-    m, w = level_box_max(n, l), 1
-    while w < m and w < 64:
-        w *= 2
-    return w
+    """Pass width: 64 on levels of M2P_WIDE_PTS points or more, else the
+    width of the pass count (ceil(m / 64) up to three more) with the most
+    groups per pass."""
+    m = level_box_max(n, l)
+    if m >= M2P_WIDE_PTS:
+        return 64
+    best_w, best_g, best_np = 64, 0, 1
+    np0 = -(-m // 64)
+    for np_ in range(np0, np0 + 4):
+        w = -(-m // np_)
+        ng = m2p_groups(w)
+        if ng * best_np > best_g * np_:
+            best_w, best_g, best_np = w, ng, np_
+    return best_w
+
+
+def test_m2p_width_fills_lanes():
+    """Worked cases: 38-point boxes in two passes of 19 over three groups (57
+    of 64 lanes), 152-point boxes in five passes of 31 over two groups, ten
+    points in one pass over six groups, 64-point passes from 256 points."""
+    assert m2p_width(38 * 4 ** 9, 9) == 19 and m2p_groups(19) == 3
+    assert m2p_width(152 * 4 ** 8, 8) == 31 and m2p_groups(31) == 2
+    assert m2p_width(10 * 4 ** 5, 5) == 10 and m2p_groups(10) == 6
+    assert m2p_width(256 * 4 ** 3, 3) == 64
+    for m in range(1, 256):
+        w = m2p_width(m * 4, 1)
+        assert 1 <= w <= 64 and -(-m // w) <= -(-m // 64) + 3
+        assert m2p_groups(w) * w <= 64
 
 
 MSPAN = 64
@@ -120,9 +151,8 @@ MSPAN = 64
 @pytest.mark.parametrize("case", ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "ring_scaled_20k_L6",
                                   "duplicates_4k_L4", "uniform_2000_L2", "uniform_10k_L5"])
 def test_m2p_items_cover_and_bound(orc, case):
-    """M2P items: per box with an M2P entry, its point passes (64 points on
-    levels of width 64, the whole box within the pass width on the others)
-    times balanced spans of its X row of at most MSPAN positions, point pass
+    """M2P items: per box with an M2P entry, its point passes (of
+    m2p_width(n, l) points) times balanced spans of its X row of at most MSPAN positions, point pass
     major.  Checks: the item count within the schedule's bound, every
     (point, row position) pair of such a box in exactly one item, and the
     per-point sum's indexing (pass and span from the box's item range) naming
@@ -132,13 +162,13 @@ def test_m2p_items_cover_and_bound(orc, case):
     t = orc.tree(ps.x, ps.y, L)
     ls = orc.lists_opt(t, 0.5, parent=True, swap_levels=range(1, L + 1))
     n, starts = ps.n, t.leaf_start
-    wl = next((l for l in range(1, L + 1) if m2p_width(n, l) < 64), L + 1)
+    wl = next((l for l in range(1, L + 1) if level_box_max(n, l) < M2P_WIDE_PTS), L + 1)
     bound_w = bound_n = 0
     items, itemoff = [], {}
     for l in range(1, L + 1):
         nx = int(ls.xptr[l][-1])
         mp = m2p_width(n, l)
-        npc_max = -(-level_box_max(n, l) // 64) if mp == 64 else 1
+        npc_max = -(-level_box_max(n, l) // mp)
         bnd = npc_max * (min(nx, 4 ** l) + nx // MSPAN)
         if l < wl:
             bound_w += bnd
@@ -152,9 +182,9 @@ def test_m2p_items_cover_and_bound(orc, case):
             i0 = len(items)
             if any(r[b] > r[c] for c in row):
                 a, e = int(starts[b << 2 * (L - l)]), int(starts[(b + 1) << 2 * (L - l)])
-                step = 64 if mp == 64 else e - a
-                assert e - a <= step or mp == 64
+                step = mp
                 npc = -(-(e - a) // step)
+                assert npc <= npc_max
                 nsp = -(-(t1 - t0) // MSPAN)
                 span = -(-(t1 - t0) // nsp)
                 for q in range(npc * nsp):
@@ -174,7 +204,7 @@ def test_m2p_items_cover_and_bound(orc, case):
         b = g - level_offset(l)
         a, e = int(starts[b << 2 * (L - l)]), int(starts[(b + 1) << 2 * (L - l)])
         t0, t1 = int(ls.xptr[l][b]), int(ls.xptr[l][b + 1])
-        step = 64 if m2p_width(n, l) == 64 else e - a
+        step = m2p_width(n, l)
         npc = -(-(e - a) // step)
         assert (i1 - i0) % npc == 0
         nsp = (i1 - i0) // npc
