@@ -404,19 +404,37 @@ __global__ void __launch_bounds__(256) k_p2l_gen(int p, int L, int64_t n, const 
     }
 }
 
-// Per target box with items: the sum of its items' partial expansions in
-// item order, one wavefront per box, one lane per coefficient.
+// Per target box with items: the sum of its items' partial expansions, one
+// wavefront per box.  Lanes are G = 64 / (p + 1) groups of one lane per
+// coefficient (one group above order 32); group q takes the box's items q, q
+// + G, ... in order, four loads in flight, and group 0 adds the groups' sums
+// in group order.
 __global__ void __launch_bounds__(256) k_x_reduce(int p, int64_t nbox, const int32_t *__restrict__ itemoff,
                                                   const cd *__restrict__ xpart, cd *__restrict__ xsum) {
     const int64_t g = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (g >= nbox) return;
     const int32_t i0 = itemoff[g], i1 = itemoff[g + 1];
     if (i0 == i1) return;  // uniform: a box without P2L entries
-    const int lane = threadIdx.x % 64;
-    if (lane > p) return;
+    const int lane = threadIdx.x % 64, P1 = p + 1;
+    const int G = P1 <= 32 ? 64 / P1 : 1;
+    const int grp = lane / P1, k = lane - grp * P1;  // lanes of group G and above idle
     cd acc{0.0, 0.0};
-    for (int32_t it = i0; it < i1; ++it) acc = cadd(acc, xpart[(int64_t)it * (p + 1) + lane]);
-    xsum[g * (p + 1) + lane] = acc;
+    if (grp < G) {
+        int32_t it = i0 + grp;
+        for (; it + 3 * G < i1; it += 4 * G) {
+            const cd v0 = xpart[(int64_t)it * P1 + k], v1 = xpart[(int64_t)(it + G) * P1 + k];
+            const cd v2 = xpart[(int64_t)(it + 2 * G) * P1 + k], v3 = xpart[(int64_t)(it + 3 * G) * P1 + k];
+            acc = cadd(cadd(cadd(cadd(acc, v0), v1), v2), v3);
+        }
+        for (; it < i1; it += G) acc = cadd(acc, xpart[(int64_t)it * P1 + k]);
+    }
+    cd tot = acc;
+    for (int q = 1; q < G; ++q) {
+        const int src = lane + q * P1 < 64 ? lane + q * P1 : lane;
+        tot.re += __shfl(acc.re, src, 64);
+        tot.im += __shfl(acc.im, src, 64);
+    }
+    if (grp == 0) xsum[g * P1 + k] = tot;
 }
 
 // M2P, orders p + 1 <= 32: one wavefront per item, the items of every level
