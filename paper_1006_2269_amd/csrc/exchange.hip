@@ -90,6 +90,17 @@ __host__ __device__ inline int m2p_width(int64_t n, int l) {
     return best_w;
 }
 
+// The pass width of every level, for the kernels (a kernel argument: no
+// division in the kernels).
+struct M2PWidths {
+    int32_t w[FMM2D_MAX_LEVELS + 1];
+};
+M2PWidths m2p_widths(int64_t n, int L) {
+    M2PWidths mw{};
+    for (int l = 0; l <= L && l <= FMM2D_MAX_LEVELS; ++l) mw.w[l] = m2p_width(n, l);
+    return mw;
+}
+
 // Work items per global box g, one wavefront per box (lanes over the X row,
 // 64 entries at a time, item positions by a wave prefix sum in row order).
 // P2L (the entries of X(g) whose source box is the larger): int4 (target
@@ -108,7 +119,7 @@ __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox,
                                                  int32_t *__restrict__ cnt, int32_t *__restrict__ mcnt,
                                                  const int32_t *__restrict__ itemoff,
                                                  const int32_t *__restrict__ mitemoff, int4 *__restrict__ items,
-                                                 int4 *__restrict__ mitems) {
+                                                 int4 *__restrict__ mitems, M2PWidths mw) {
     const int64_t g = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (g >= nbox) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64;
@@ -163,7 +174,7 @@ __global__ void __launch_bounds__(256) k_x_items(int L, int64_t n, int64_t nbox,
     if (m2p) {
         int32_t a, e;
         box_range(stL, L, l, b, a, e);
-        const int32_t step = m2p_width(n, l);
+        const int32_t step = mw.w[l];
         const int32_t npc = (e - a + step - 1) / step;
         const int32_t nsp = (t1 - t0 + MSPAN - 1) / MSPAN, span = (t1 - t0 + nsp - 1) / nsp;
         km = npc * nsp;
@@ -457,7 +468,8 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
                                              const int32_t *__restrict__ xidx, const int64_t *__restrict__ xoff,
                                              const double4 *__restrict__ geom, const int32_t *__restrict__ stL,
                                              const cd *__restrict__ A, const double *__restrict__ px,
-                                             const double *__restrict__ py, double *__restrict__ mpart) {
+                                             const double *__restrict__ py, double *__restrict__ mpart,
+                                             M2PWidths mw) {
     constexpr int MSTAGE = m_stage<P1>();
     __shared__ cd s_a[4][MSTAGE * P1];
     __shared__ double s_g[4][MSTAGE][3];
@@ -470,7 +482,7 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
     const int64_t b = w.x - level_offset(l);
     int32_t a, e;
     box_range(stL, L, l, b, a, e);
-    const int mp = WIDE ? 64 : m2p_width(n, l);
+    const int mp = WIDE ? 64 : mw.w[l];
     const int ng = WIDE ? 1 : m2p_groups(mp);
     const int grp = WIDE ? 0 : lane / mp;  // lanes of group ng and above idle
     const int32_t i = w.y + (WIDE ? lane : lane % mp);
@@ -482,7 +494,7 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
     const int32_t t1 = w.w;
     cd *sa = s_a[wv];
     double acc = 0.0;
-    int dealt = 0;  // compacted entries so far (the next one goes to group dealt % ng)
+    int qs = WIDE ? 0 : grp;  // this group's first compacted entry of the stage
     for (int32_t tb = w.z; tb < t1; tb += MSTAGE) {
         bool ok = false;
         int64_t cg = 0;
@@ -507,7 +519,8 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
             sa[idx] = A[s_c[wv][q] * P1 + (idx - q * P1)];
         }
         __builtin_amdgcn_wave_barrier();
-        for (int q = WIDE ? 0 : ((grp - dealt) % ng + ng) % ng; q < k; q += ng) {
+        int q = qs;
+        for (; q < k; q += ng) {
             const cd *Ac = sa + q * P1;
             double lw;
             const cd rho = recip_scaled(s_g[wv][q][2], zx - s_g[wv][q][0], zy - s_g[wv][q][1], lw);
@@ -516,7 +529,7 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
             for (int r = P1 - 2; r >= 1; --r) sacc = cfma(sacc, rho, Ac[r]);
             acc += fma(sacc.re, rho.re, fma(-sacc.im, rho.im, Ac[0].re * lw));  // Re(sacc rho) + A_0 log|w|
         }
-        dealt += k;
+        qs = q - k;  // the entries continue in the next stage
         __builtin_amdgcn_wave_barrier();  // the slice is rewritten by the next stage
     }
     if (!WIDE) {
@@ -534,7 +547,7 @@ __global__ void __launch_bounds__(256) k_m2p_sum(int L, int64_t n, const int32_t
                                                  const int32_t *__restrict__ stL,
                                                  const int32_t *__restrict__ itemoff,
                                                  const double *__restrict__ mpart, const int32_t *__restrict__ perm,
-                                                 double *__restrict__ phi) {
+                                                 double *__restrict__ phi, M2PWidths mw) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t leaf = leafid[i];
@@ -546,7 +559,7 @@ __global__ void __launch_bounds__(256) k_m2p_sum(int L, int64_t n, const int32_t
         if (i0 == i1) continue;
         int32_t a, e;
         box_range(stL, L, l, b, a, e);
-        const int32_t step = m2p_width(n, l);
+        const int32_t step = mw.w[l];
         const int32_t npc = (e - a + step - 1) / step, nsp = (i1 - i0) / npc;
         const int32_t pc = ((int32_t)i - a) / step, o = (int32_t)i - a - pc * step;
         const double *row = mpart + (int64_t)(i0 + pc * nsp) * 64 + o;
@@ -659,8 +672,10 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     FMM2D_TRY(t.m_itemoff.ensure(sizeof(int32_t) * (nbox + 1)));
     int32_t *cnts[2] = {c->scr.segcnt.as<int32_t>(), c->scr.mcnt.as<int32_t>()};
     int32_t *offs[2] = {t.x_itemoff.as<int32_t>(), t.m_itemoff.as<int32_t>()};
+    const M2PWidths widths = m2p_widths(t.n, L);
     hipLaunchKernelGGL(k_x_items<false>, dim3(grid_for(nbox, 4)), dim3(256), 0, c->stream, L, t.n, nbox,
-                       lane_level, xptr, xidx, xoff, geom, stL, cnts[0], cnts[1], nullptr, nullptr, nullptr, nullptr);
+                       lane_level, xptr, xidx, xoff, geom, stL, cnts[0], cnts[1], nullptr, nullptr, nullptr, nullptr,
+                       widths);
     FMM2D_TRY(hipGetLastError());
     const int32_t *cin[2] = {cnts[0], cnts[1]};
     FMM2D_TRY(scan_exclusive_n(c, 2, cin, nbox, offs));
@@ -676,7 +691,7 @@ hipError_t exchange_schedule(fmm2d_ctx *c) {
     FMM2D_TRY(t.m_items.ensure(sizeof(int4) * (hm[1] > 0 ? hm[1] : 1)));
     hipLaunchKernelGGL(k_x_items<true>, dim3(grid_for(nbox, 4)), dim3(256), 0, c->stream, L, t.n, nbox,
                        lane_level, xptr, xidx, xoff, geom, stL, nullptr, nullptr, offs[0], offs[1],
-                       t.x_items.as<int4>(), t.m_items.as<int4>());
+                       t.x_items.as<int4>(), t.m_items.as<int4>(), widths);
     FMM2D_TRY(hipGetLastError());
     t.x_ready = true;
     return hipSuccess;
@@ -758,6 +773,7 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
     FMM2D_TRY(c->ev.mpart.ensure(sizeof(double) * 64 * (mb > 0 ? mb : 1)));
     double *mpart = c->ev.mpart.as<double>();
     const int32_t *off = t.m_itemoff.as<int32_t>();
+    const M2PWidths widths = m2p_widths(t.n, L);
     for (int pass = 0; pass < 2; ++pass) {
         // the items of the levels of width 64, then those of the others
         const bool wide = pass == 0;
@@ -770,11 +786,11 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
 #define FMM2D_M2P(P1)                                                                                             \
     case 2 * P1:                                                                                                  \
         hipLaunchKernelGGL((k_m2p<P1, false>), grid, block, 0, c->stream, L, t.n, items, first, end, xidx, xoff,  \
-                           geom, stL, A, px, py, mpart);                                                          \
+                           geom, stL, A, px, py, mpart, widths);                                                  \
         break;                                                                                                    \
     case 2 * P1 + 1:                                                                                              \
         hipLaunchKernelGGL((k_m2p<P1, true>), grid, block, 0, c->stream, L, t.n, items, first, end, xidx, xoff,   \
-                           geom, stL, A, px, py, mpart);                                                          \
+                           geom, stL, A, px, py, mpart, widths);                                                  \
         break;
             FMM2D_M2P(2) FMM2D_M2P(3) FMM2D_M2P(4) FMM2D_M2P(5) FMM2D_M2P(6) FMM2D_M2P(7) FMM2D_M2P(8)
             FMM2D_M2P(9) FMM2D_M2P(10) FMM2D_M2P(11) FMM2D_M2P(12) FMM2D_M2P(13) FMM2D_M2P(14) FMM2D_M2P(15)
@@ -788,7 +804,7 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
         FMM2D_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_m2p_sum, dim3(grid_for(t.n, 256)), block, 0, c->stream, L, t.n, t.leafid.as<int32_t>(), stL,
-                       off, mpart, perm, phi);
+                       off, mpart, perm, phi, widths);
     return hipSuccess;
 }
 
