@@ -542,7 +542,8 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
 }
 
 // Per point (leaf order): its M2P sums, level by level and within a level in
-// item order (the row spans of its point pass), added to its potential.
+// item order (the row spans of its point pass), added to its potential.  The
+// item ranges and box starts of all levels are loaded before any is used.
 __global__ void __launch_bounds__(256) k_m2p_sum(int L, int64_t n, const int32_t *__restrict__ leafid,
                                                  const int32_t *__restrict__ stL,
                                                  const int32_t *__restrict__ itemoff,
@@ -551,18 +552,28 @@ __global__ void __launch_bounds__(256) k_m2p_sum(int L, int64_t n, const int32_t
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t leaf = leafid[i];
+    int32_t r0[FMM2D_MAX_LEVELS + 1], r1[FMM2D_MAX_LEVELS + 1], a0[FMM2D_MAX_LEVELS + 1];
+#pragma unroll
+    for (int l = 1; l <= FMM2D_MAX_LEVELS; ++l) {
+        r0[l] = r1[l] = a0[l] = 0;
+        if (l <= L) {
+            const int64_t b = leaf >> (2 * (L - l)), g = level_offset(l) + b;
+            r0[l] = itemoff[g];
+            r1[l] = itemoff[g + 1];
+            a0[l] = stL[b << (2 * (L - l))];  // the box's first point
+        }
+    }
     double acc = 0.0;
     bool any = false;
-    for (int l = 1; l <= L; ++l) {
-        const int64_t b = leaf >> (2 * (L - l)), g = level_offset(l) + b;
-        const int32_t i0 = itemoff[g], i1 = itemoff[g + 1];
-        if (i0 == i1) continue;
-        int32_t a, e;
-        box_range(stL, L, l, b, a, e);
-        const int32_t step = mw.w[l];
-        const int32_t npc = (e - a + step - 1) / step, nsp = (i1 - i0) / npc;
+#pragma unroll
+    for (int l = 1; l <= FMM2D_MAX_LEVELS; ++l) {
+        if (l > L || r0[l] == r1[l]) continue;
+        const int64_t b = leaf >> (2 * (L - l));
+        const int32_t e = stL[(b + 1) << (2 * (L - l))];
+        const int32_t a = a0[l], step = mw.w[l];
+        const int32_t npc = (e - a + step - 1) / step, nsp = (r1[l] - r0[l]) / npc;
         const int32_t pc = ((int32_t)i - a) / step, o = (int32_t)i - a - pc * step;
-        const double *row = mpart + (int64_t)(i0 + pc * nsp) * 64 + o;
+        const double *row = mpart + (int64_t)(r0[l] + pc * nsp) * 64 + o;
         for (int32_t s = 0; s < nsp; ++s) acc += row[(int64_t)s * 64];
         any = true;
     }

@@ -24,6 +24,7 @@ namespace fmm2d {
 namespace {
 
 constexpr int BN = 128;  // binomial table is BN x BN
+constexpr int REG_P1 = 24;  // M2M and L2L with coefficients in registers up to this order p + 1
 
 // ---- P2M: one thread per leaf, coefficients in registers -------------------
 template <int PB>
@@ -60,7 +61,7 @@ __global__ void __launch_bounds__(256) k_p2m(int p, const double *__restrict__ p
         if (k <= p) out[k] = cd{-ar[k] / k, -ai[k] / k};
 }
 
-// ---- P2M for leaves of more than 16 points, orders p + 1 <= 16: one
+// ---- P2M for leaves of more than 16 points, orders p + 1 <= 32: one
 // wavefront per leaf, one lane per point (points lane, lane + 64, ... of a
 // larger leaf), and the lanes' 2 PB partial sums (real parts, then imaginary
 // parts) added by a transposing butterfly in a fixed order.  The thread per
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(256) k_p2m_wave(int p, const double *__restric
                                                   const double *__restrict__ py, const double *__restrict__ qs,
                                                   const int32_t *__restrict__ stL, const double4 *__restrict__ geomL,
                                                   int64_t nleaf, cd *__restrict__ AL) {
-    static_assert(PB == 8 || PB == 16, "2 PB values per lane");
+    static_assert(PB == 8 || PB == 16 || PB == 32, "2 PB values per lane");
     const int lane = (int)(threadIdx.x % 64);
     const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (b >= nleaf) return;  // uniform per wavefront
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(256) k_p2m_wave(int p, const double *__restric
         }
     }
     const double s = wave_transpose_sum<2 * PB>(v, lane);  // value lane / G, G lanes each
-    constexpr int G = 32 / PB;
+    constexpr int G = 32 / PB;  // lanes per value
     if (lane % G == 0) {
         const int vi = lane / G;
         const bool im = vi >= PB;
@@ -130,56 +131,82 @@ __device__ inline double wave_powers_real(double x) {
     return v;
 }
 
-// ---- M2M: one wavefront per parent box, lane l = output coefficient --------
-__global__ void __launch_bounds__(64) k_m2m(int l, int p, const double4 *__restrict__ geom, cd *__restrict__ A,
-                                            const double *__restrict__ binom) {
-    __shared__ cd Ac[64];
-    __shared__ cd dp[64];
-    __shared__ double sp[64];
-    const int64_t P = blockIdx.x;
+// Binomials C(i, j), i, j <= p, from the table into the block's LDS copy
+// (row i at s_bin + 64 i), every thread of the block taking part.
+__device__ inline void stage_binomials(int p, const double *__restrict__ binom, double *s_bin) {
+    for (int idx = threadIdx.x; idx < (p + 1) * 64; idx += blockDim.x) s_bin[idx] = binom[(idx >> 6) * BN + (idx & 63)];
+    __syncthreads();
+}
+
+// ---- M2M: one wavefront per parent box, lane l = output coefficient; four
+// parents per block sharing one LDS copy of the binomials.  The four
+// children's coefficients are loaded before the first is used.
+__global__ void __launch_bounds__(256) k_m2m(int l, int p, int64_t np, const double4 *__restrict__ geom,
+                                             cd *__restrict__ A, const double *__restrict__ binom) {
+    __shared__ double s_bin[64 * 64];
+    __shared__ cd Ac[4][64];
+    __shared__ cd dp[4][64];
+    __shared__ double sp[4][64];
+    stage_binomials(p, binom, s_bin);
+    const int wv = threadIdx.x / 64;
+    const int64_t P = (int64_t)blockIdx.x * 4 + wv;
+    if (P >= np) return;  // uniform per wavefront (no block barrier below)
     const int lane = (int)lane_id();
     const int64_t pbox = level_offset(l) + P;
     const double4 gp = geom[pbox];
-    cd acc{0.0, 0.0};
+    double4 gch[4];
+    cd ach[4];
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int64_t cbox = level_offset(l + 1) + 4 * P + c;
-        const double4 gc = geom[cbox];
+        gch[c] = geom[cbox];
+        ach[c] = lane <= p ? A[cbox * (p + 1) + lane] : cd{0.0, 0.0};
+    }
+    cd acc{0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double4 gc = gch[c];
         const cd delta{(gc.x - gp.x) / gp.w, (gc.y - gp.y) / gp.w};
         const double sigma = gc.w / gp.w;
         const cd dpow = wave_powers(delta);
         const double spow = wave_powers_real(sigma);
-        if (lane <= p) Ac[lane] = A[cbox * (p + 1) + lane];
-        dp[lane] = dpow;
-        sp[lane] = spow;
-        __syncthreads();
+        Ac[wv][lane] = ach[c];
+        dp[wv][lane] = dpow;
+        sp[wv][lane] = spow;
+        __builtin_amdgcn_wave_barrier();
         if (lane <= p) {
             if (lane == 0) {
-                acc = cadd(acc, Ac[0]);
+                acc = cadd(acc, Ac[wv][0]);
             } else {
-                cd t = cscale(cmul(Ac[0], dp[lane]), -1.0 / lane);
+                cd t = cscale(cmul(Ac[wv][0], dp[wv][lane]), -1.0 / lane);
                 for (int k = 1; k <= lane; ++k) {
-                    const double coef = sp[k] * binom[(lane - 1) * BN + (k - 1)];
-                    t = cadd(t, cscale(cmul(Ac[k], dp[lane - k]), coef));
+                    const double coef = sp[wv][k] * s_bin[(lane - 1) * 64 + (k - 1)];
+                    t = cadd(t, cscale(cmul(Ac[wv][k], dp[wv][lane - k]), coef));
                 }
                 acc = cadd(acc, t);
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();  // the slices are rewritten for the next child
     }
     if (lane <= p) A[pbox * (p + 1) + lane] = acc;
 }
 
-// ---- L2L: one wavefront per child box, lane l = coefficient ----------------
+// ---- L2L: one wavefront per child box, lane l = coefficient, four children
+// per block sharing one LDS copy of the binomials ----------------------------
 // B(child) = the parent's local expansion re-centred at the child, plus the
 // child's M2L segment sums (segments of global box g are
 // [segoff[g], segoff[g + 1]) in part), added in segment order.
-__global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restrict__ geom, cd *__restrict__ B,
-                                            const double *__restrict__ binom, const int32_t *__restrict__ segoff,
-                                            const cd *__restrict__ part, const int32_t *__restrict__ xoff,
-                                            const cd *__restrict__ xsum) {
-    __shared__ cd Bp[64];
-    __shared__ cd dp[64];
-    const int64_t cidx = blockIdx.x;  // child within level l+1
+__global__ void __launch_bounds__(256) k_l2l(int l, int p, int64_t nc, const double4 *__restrict__ geom,
+                                             cd *__restrict__ B, const double *__restrict__ binom,
+                                             const int32_t *__restrict__ segoff, const cd *__restrict__ part,
+                                             const int32_t *__restrict__ xoff, const cd *__restrict__ xsum) {
+    __shared__ double s_bin[64 * 64];
+    __shared__ cd Bp[4][64];
+    __shared__ cd dp[4][64];
+    stage_binomials(p, binom, s_bin);
+    const int wv = threadIdx.x / 64;
+    const int64_t cidx = (int64_t)blockIdx.x * 4 + wv;  // child within level l+1
+    if (cidx >= nc) return;  // uniform per wavefront (no block barrier below)
     const int lane = (int)lane_id();
     const int64_t cbox = level_offset(l + 1) + cidx;
     const int64_t pbox = level_offset(l) + (cidx >> 2);
@@ -188,12 +215,13 @@ __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restr
     const double tau = gc.w / gp.w;
     const cd dpow = wave_powers(delta);
     const double tpow = wave_powers_real(tau);
-    if (lane <= p) Bp[lane] = B[pbox * (p + 1) + lane];
-    dp[lane] = dpow;
-    __syncthreads();
+    if (lane <= p) Bp[wv][lane] = B[pbox * (p + 1) + lane];
+    dp[wv][lane] = dpow;
+    __builtin_amdgcn_wave_barrier();
     if (lane <= p) {
         cd t{0.0, 0.0};
-        for (int k = lane; k <= p; ++k) t = cadd(t, cscale(cmul(Bp[k], dp[k - lane]), binom[k * BN + lane]));
+        for (int k = lane; k <= p; ++k)
+            t = cadd(t, cscale(cmul(Bp[wv][k], dp[wv][k - lane]), s_bin[k * 64 + lane]));
         cd v = cscale(t, tpow);
         const int32_t s0 = segoff[cbox], s1 = segoff[cbox + 1];
         if (s1 > s0) {
@@ -207,7 +235,7 @@ __global__ void __launch_bounds__(64) k_l2l(int l, int p, const double4 *__restr
     }
 }
 
-// ---- M2M and L2L for p + 1 <= 16: one lane per box, coefficients in registers
+// ---- M2M and L2L for p + 1 <= REG_P1: one lane per box, coefficients in registers
 // With C(n, k) = n! / (k! (n - k)!) the binomial sums are convolutions:
 //   M2M (parent coefficient l >= 1, from one child):
 //     (l - 1)! sum_{k=0..l} a'_k e_{l-k},  a'_0 = -A_0, a'_k = A_k sigma^k / (k - 1)!,
@@ -398,10 +426,11 @@ template <int PB>
 hipError_t launch_p2m(fmm2d_ctx *c, int p, cd *A) {
     TreeState &t = c->tree;
     const int64_t nleaf = int64_t(1) << (2 * t.L);
-    if constexpr (PB <= 16) {
+    if constexpr (PB <= 32) {
         const int64_t maxleaf = (t.n + nleaf - 1) >> (2 * t.L);  // ceil(n / 4^L)
         if (maxleaf > 16) {
-            hipLaunchKernelGGL(k_p2m_wave<PB>, dim3(grid_for(nleaf, 4)), dim3(256), 0, c->stream, p,
+            constexpr int PW = PB <= 8 ? 8 : (PB <= 16 ? 16 : 32);  // 2 PW values: a power of two
+            hipLaunchKernelGGL(k_p2m_wave<PW>, dim3(grid_for(nleaf, 4)), dim3(256), 0, c->stream, p,
                                t.px.as<double>(), t.py.as<double>(), c->ev.qs.as<double>(),
                                t.starts.as<int32_t>() + depth_offset(2 * t.L), t.geom.as<double4>() + level_offset(t.L),
                                nleaf, A + level_offset(t.L) * (p + 1));
@@ -449,22 +478,23 @@ hipError_t upward_pass(fmm2d_ctx *c, int p) {
     FMM2D_TRY(r);
     const double4 *geom = t.geom.as<double4>();
     // levels of at most COARSE parents (l <= 4) in one launch, after the finer ones
-    const int lc = p + 1 <= 16 ? std::min(L - 1, 4) : -1;
+    const int lc = p + 1 <= REG_P1 ? std::min(L - 1, 4) : -1;
     for (int l = L - 1; l > lc; --l) {
         const int64_t np = int64_t(1) << (2 * l);
-        if (p + 1 <= 16) {
+        if (p + 1 <= REG_P1) {
             const dim3 grid(grid_for(np, 64)), block(64);
             switch (p + 1) {
 #define FMM2D_M2M(P1) \
     case P1: hipLaunchKernelGGL(k_m2m_box<P1>, grid, block, 0, c->stream, l, np, geom, A); break;
                 FMM2D_M2M(2) FMM2D_M2M(3) FMM2D_M2M(4) FMM2D_M2M(5) FMM2D_M2M(6) FMM2D_M2M(7) FMM2D_M2M(8)
                 FMM2D_M2M(9) FMM2D_M2M(10) FMM2D_M2M(11) FMM2D_M2M(12) FMM2D_M2M(13) FMM2D_M2M(14)
-                FMM2D_M2M(15) FMM2D_M2M(16)
+                FMM2D_M2M(15) FMM2D_M2M(16) FMM2D_M2M(17) FMM2D_M2M(18) FMM2D_M2M(19) FMM2D_M2M(20)
+                FMM2D_M2M(21) FMM2D_M2M(22) FMM2D_M2M(23) FMM2D_M2M(24)
 #undef FMM2D_M2M
                 default: return hipErrorInvalidValue;
             }
         } else {
-            hipLaunchKernelGGL(k_m2m, dim3((unsigned)np), dim3(64), 0, c->stream, l, p, geom, A, binom);
+            hipLaunchKernelGGL(k_m2m, dim3(grid_for(np, 4)), dim3(256), 0, c->stream, l, p, np, geom, A, binom);
         }
     }
     if (lc >= 0) {
@@ -472,7 +502,8 @@ hipError_t upward_pass(fmm2d_ctx *c, int p) {
 #define FMM2D_M2MC(P1)     case P1: hipLaunchKernelGGL(k_m2m_coarse<P1>, dim3(1), dim3(COARSE), 0, c->stream, lc, geom, A); break;
             FMM2D_M2MC(2) FMM2D_M2MC(3) FMM2D_M2MC(4) FMM2D_M2MC(5) FMM2D_M2MC(6) FMM2D_M2MC(7) FMM2D_M2MC(8)
             FMM2D_M2MC(9) FMM2D_M2MC(10) FMM2D_M2MC(11) FMM2D_M2MC(12) FMM2D_M2MC(13) FMM2D_M2MC(14)
-            FMM2D_M2MC(15) FMM2D_M2MC(16)
+            FMM2D_M2MC(15) FMM2D_M2MC(16) FMM2D_M2MC(17) FMM2D_M2MC(18) FMM2D_M2MC(19) FMM2D_M2MC(20)
+                FMM2D_M2MC(21) FMM2D_M2MC(22) FMM2D_M2MC(23) FMM2D_M2MC(24)
 #undef FMM2D_M2MC
             default: return hipErrorInvalidValue;
         }
@@ -488,7 +519,7 @@ hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
     const int32_t *segoff = t.m2l_all.segoff.as<int32_t>();
     const int32_t *xoff = exchange_item_offsets(c);
     const cd *xsum = xoff ? e.xsum.as<cd>() : nullptr;
-    if (p + 1 <= 16) {
+    if (p + 1 <= REG_P1) {
         const dim3 grid(grid_for(nc, 64)), block(64);
         switch (p + 1) {
 #define FMM2D_L2L(P1)                                                                                            \
@@ -498,12 +529,13 @@ hipError_t l2l_level(fmm2d_ctx *c, int l, int p) {
         break;
             FMM2D_L2L(2) FMM2D_L2L(3) FMM2D_L2L(4) FMM2D_L2L(5) FMM2D_L2L(6) FMM2D_L2L(7) FMM2D_L2L(8)
             FMM2D_L2L(9) FMM2D_L2L(10) FMM2D_L2L(11) FMM2D_L2L(12) FMM2D_L2L(13) FMM2D_L2L(14) FMM2D_L2L(15)
-            FMM2D_L2L(16)
+            FMM2D_L2L(16) FMM2D_L2L(17) FMM2D_L2L(18) FMM2D_L2L(19) FMM2D_L2L(20)
+                FMM2D_L2L(21) FMM2D_L2L(22) FMM2D_L2L(23) FMM2D_L2L(24)
 #undef FMM2D_L2L
             default: return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL(k_l2l, dim3((unsigned)nc), dim3(64), 0, c->stream, l, p, geom, e.B.as<cd>(),
+        hipLaunchKernelGGL(k_l2l, dim3(grid_for(nc, 4)), dim3(256), 0, c->stream, l, p, nc, geom, e.B.as<cd>(),
                            e.binom.as<double>(), segoff, e.part.as<cd>(), xoff, xsum);
     }
     return hipGetLastError();
@@ -516,7 +548,7 @@ hipError_t l2l_pass(fmm2d_ctx *c, int p) {
     EvalState &e = c->ev;
     const int L = t.L;
     int l0 = 0;
-    if (p + 1 <= 16 && L >= 1) {
+    if (p + 1 <= REG_P1 && L >= 1) {
         const int lc = std::min(L - 1, 3);
         const double4 *geom = t.geom.as<double4>();
         const int32_t *segoff = t.m2l_all.segoff.as<int32_t>();
@@ -526,7 +558,8 @@ hipError_t l2l_pass(fmm2d_ctx *c, int p) {
 #define FMM2D_L2LC(P1)                                                                                                  case P1:                                                                                                                hipLaunchKernelGGL(k_l2l_coarse<P1>, dim3(1), dim3(COARSE), 0, c->stream, lc, geom, e.B.as<cd>(), segoff,                            e.part.as<cd>(), xoff, xsum);                                                                                break;
             FMM2D_L2LC(2) FMM2D_L2LC(3) FMM2D_L2LC(4) FMM2D_L2LC(5) FMM2D_L2LC(6) FMM2D_L2LC(7) FMM2D_L2LC(8)
             FMM2D_L2LC(9) FMM2D_L2LC(10) FMM2D_L2LC(11) FMM2D_L2LC(12) FMM2D_L2LC(13) FMM2D_L2LC(14)
-            FMM2D_L2LC(15) FMM2D_L2LC(16)
+            FMM2D_L2LC(15) FMM2D_L2LC(16) FMM2D_L2LC(17) FMM2D_L2LC(18) FMM2D_L2LC(19) FMM2D_L2LC(20)
+                FMM2D_L2LC(21) FMM2D_L2LC(22) FMM2D_L2LC(23) FMM2D_L2LC(24)
 #undef FMM2D_L2LC
             default: return hipErrorInvalidValue;
         }

@@ -617,6 +617,22 @@ __global__ void k_pack_sources(const float2 *__restrict__ loc, const double *__r
     }
 }
 
+// L2P: the local expansion B[0..p] at z (scaled offset) by Horner, the
+// coefficients loaded four at a time ahead of their use.
+__device__ inline cd l2p_horner(const cd *__restrict__ Bb, int p, cd z) {
+    cd v = Bb[p];
+    int l = p - 1;
+    for (; l >= 3; l -= 4) {
+        const cd b0 = Bb[l], b1 = Bb[l - 1], b2 = Bb[l - 2], b3 = Bb[l - 3];
+        v = cadd(cmul(v, z), b0);
+        v = cadd(cmul(v, z), b1);
+        v = cadd(cmul(v, z), b2);
+        v = cadd(cmul(v, z), b3);
+    }
+    for (; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
+    return v;
+}
+
 // Per point: the partial sums of its leaf's segments in segment order, times
 // `scale`, plus L2P (binary64 Horner) of the leaf's local expansion.
 __global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale, const int32_t *__restrict__ leafid,
@@ -634,9 +650,7 @@ __global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale
     for (int32_t sg = segoff[b]; sg < segoff[b + 1]; ++sg) near += part[((int64_t)sg * chunks + ch) * tm + k];
     const double4 g = geomL[b];
     const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
-    const cd *Bb = BL + (int64_t)b * (p + 1);
-    cd v = Bb[p];
-    for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
+    const cd v = l2p_horner(BL + (int64_t)b * (p + 1), p, z);
     phi[perm[i]] = v.re + scale * near;  // input order
 }
 
@@ -656,7 +670,13 @@ __global__ void __launch_bounds__(256) k_near_lsum(const int2 *__restrict__ segt
     const int2 se = segtab[sg];
     const int32_t u1 = (se.y + NEAR_SEG) < selfpos[se.x] ? (se.y + NEAR_SEG) : selfpos[se.x];
     double v = 0.0;
-    for (int32_t u = se.y + grp; u < u1; u += LPI) v += (double)spart[(int64_t)u * GL + jj];
+    int32_t u = se.y + grp;
+    for (; u + 3 * LPI < u1; u += 4 * LPI) {  // four loads in flight, added in entry order
+        const float f0 = spart[(int64_t)u * GL + jj], f1 = spart[(int64_t)(u + LPI) * GL + jj];
+        const float f2 = spart[(int64_t)(u + 2 * LPI) * GL + jj], f3 = spart[(int64_t)(u + 3 * LPI) * GL + jj];
+        v = (((v + (double)f0) + (double)f1) + (double)f2) + (double)f3;
+    }
+    for (; u < u1; u += LPI) v += (double)spart[(int64_t)u * GL + jj];
 #pragma unroll
     for (int off = GL; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
     if (lane < GL) lsum[sg * GL + jj] = v;
@@ -682,9 +702,7 @@ __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, do
     for (int32_t sg = losegoff[b]; sg < losegoff[b + 1]; ++sg) near += lsum[(int64_t)sg * gl + off];
     const double4 g = geomL[b];
     const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
-    const cd *Bb = BL + (int64_t)b * (p + 1);
-    cd v = Bb[p];
-    for (int l = p - 1; l >= 0; --l) v = cadd(cmul(v, z), Bb[l]);
+    const cd v = l2p_horner(BL + (int64_t)b * (p + 1), p, z);
     phi[perm[i]] = v.re + scale * near;  // input order
 }
 

@@ -79,22 +79,23 @@ __device__ inline void butterfly_stage(T *v, int lane) {
     }
 }
 
-// Sum of the 64 lanes' NV values (NV a power of two, 8 <= NV <= 32); lane i
+// Sum of the 64 lanes' NV values (NV a power of two, 8 <= NV <= 64); lane i
 // receives the total of value i / (64 / NV).  The additions follow a fixed
 // tree, so the result does not depend on timing.
 template <int NV, typename T>
 __device__ inline T wave_transpose_sum(T *v, int lane) {
-    static_assert(NV == 8 || NV == 16 || NV == 32, "value count");
+    static_assert(NV == 8 || NV == 16 || NV == 32 || NV == 64, "value count");
     butterfly_stage<32, NV / 2>(v, lane);
     butterfly_stage<16, NV / 4>(v, lane);
     butterfly_stage<8, NV / 8>(v, lane);
     if constexpr (NV >= 16) butterfly_stage<4, NV / 16>(v, lane);
-    if constexpr (NV >= 32) butterfly_stage<2, 1>(v, lane);
+    if constexpr (NV >= 32) butterfly_stage<2, NV / 32>(v, lane);
+    if constexpr (NV >= 64) butterfly_stage<1, 1>(v, lane);
     // lanes that now hold the same value: groups of 64 / NV neighbours
     T t = v[0];
     if constexpr (NV <= 8) t += partner<4>(t);
     if constexpr (NV <= 16) t += partner<2>(t);
-    t += partner<1>(t);
+    if constexpr (NV <= 32) t += partner<1>(t);
     return t;
 }
 
