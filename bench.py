@@ -50,12 +50,13 @@ def log(*a):
 
 
 def measured_traffic(kernels, workload):
-    """HBM bytes per step of the kernels whose names start with one of
-    `kernels` (their launches in one step summed), from the committed
-    rocprofv3 counter summary of this workload (FETCH_SIZE and WRITE_SIZE,
-    each scaled by what the counter reads for a plain copy of known size), or
-    None when there is none or a kernel's source file has changed since the
-    counters were taken."""
+    """HBM bytes per step of the phase's kernels: `kernels` lists (name
+    prefix, name suffix) pairs, each kernel instance of the committed
+    rocprofv3 counter summary of this workload that matches one counted once
+    (each runs once per step), its bytes per launch (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a plain copy of
+    known size); None when there is none or a kernel's source file has
+    changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
@@ -65,12 +66,12 @@ def measured_traffic(kernels, workload):
         table = json.load(fh).get("kernels", {})
     total, found = 0, False
     for name, entry in table.items():
-        if not any(name.startswith(k) for k in kernels):
+        if not any(name.startswith(pre) and name.endswith(suf) for pre, suf in kernels):
             continue
         with open(os.path.join(ROOT, entry["source"]), "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != entry["source_sha256"]:
                 return None
-        total += entry["bytes_per_step"]
+        total += entry["bytes_per_launch"]
         found = True
     return total if found else None
 
@@ -601,26 +602,30 @@ def main():
         weak_all = float(sum(f.list_sizes(l)[1] for l in range(Lm + 1)))
         t_p2l, t_m2p, fl_p2l, fl_m2p = exchange_work(f, Lm, n, p)
         maxleaf = -(-n // 4 ** Lm)
+        acc = ", true>" if mode_red == "fp32_acc64" else ", false>"
         if 16 < maxleaf <= 64:
-            near_name, near_k = "k_near32s (pair-once near field, one launch)", ["k_near32s<"]
+            near_name, near_k = "k_near32s (pair-once near field, one launch)", [("k_near32s<", acc)]
             near_flops = (pairs - diag) / 2.0 * 10.0 + diag * 8.0
             near_work_s = "%d point pairs of distinct leaves, each taken once x 10 flops + %d within leaves x 8" % (
                 (pairs - diag) / 2, diag)
         else:
             kn = "k_near32_big" if maxleaf > 64 else "k_near32"
-            near_name, near_k = "%s (near field, one launch)" % kn, [kn + "<"]
+            near_name, near_k = "%s (near field, one launch)" % kn, [(kn + "<", acc)]
             near_flops = pairs * 8.0
             near_work_s = "%d point pairs x 8 flops" % pairs
         # (time per step, name, bound, algorithmic flops per step, peak, work, kernels of the phase)
         cands = [
             (per("near_kernel"), near_name, "alu", near_flops, MI355X["fp32_TFLOPs"], near_work_s, near_k),
             (per("m2l_kernel"), "k_m2l_lp (M2L, all levels, one launch)", "mfma", weak_all * 4.0 * (p + 1) ** 2,
-             MI355X["fp32_mfma_TFLOPs"], "%d weak pairs x 4(p+1)^2 flops" % weak_all, ["k_m2l_lp<"]),
+             MI355X["fp32_mfma_TFLOPs"], "%d weak pairs x 4(p+1)^2 flops" % weak_all,
+             [("k_m2l_lp<%d," % (p + 1), ">")]),
             (per("p2l_kernel"), "k_p2l + k_p2l_lane (exchanged roles, P2L: chunks and whole entries, two launches)",
              "alu", fl_p2l, MI355X["fp64_TFLOPs"],
-             "%d source-point terms x (10(p+1)-7) flops, binary64" % t_p2l, ["k_p2l<", "k_p2l_lane<"]),
-            (per("m2p_kernel"), "k_m2p_lvl (exchanged roles, M2P, one launch per level)", "alu", fl_m2p,
-             MI355X["fp64_TFLOPs"], "%d target-point terms x (8(p+1)-1) flops, binary64" % t_m2p, ["k_m2p_lvl<"]),
+             "%d source-point terms x (10(p+1)-7) flops, binary64" % t_p2l,
+             [("k_p2l<%d>" % (p + 1), ">"), ("k_p2l_lane<%d>" % (p + 1), ">")]),
+            (per("m2p_kernel"), "k_m2p + k_m2p_sum (exchanged roles, M2P: one launch per pass width, per-point sum)",
+             "alu", fl_m2p, MI355X["fp64_TFLOPs"], "%d target-point terms x (8(p+1)-1) flops, binary64" % t_m2p,
+             [("k_m2p<%d," % (p + 1), ">"), ("k_m2p_sum", "")]),
         ]
         for ms, name, bound, flops, peak, work, _ in cands:
             log("[bench] kernel %-45s %8.3f ms  %8.2f TFLOP/s  (%s)" % (name, ms, flops / max(ms, 1e-9) / 1e9, work))
@@ -628,7 +633,13 @@ def main():
         ach = flops / (ms * 1e-3) / 1e12
         roof = {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 5), "traffic": measured_traffic(kern, args.workload), "work": work,
-                "launch_ms": round(ms, 4)}
+                "launch_ms": round(ms, 4),
+                # every phase kernel of the step, the same way (times overlap: the near field runs on
+                # a second stream beside M2L and P2L)
+                "kernels": [{"kernel": c[1], "launch_ms": round(c[0], 4),
+                             "achieved": round(c[3] / (c[0] * 1e-3) / 1e12, 3), "peak": c[4],
+                             "frac": round(c[3] / (c[0] * 1e-3) / 1e12 / c[4], 5),
+                             "traffic": measured_traffic(c[6], args.workload)} for c in cands]}
 
     cpu = None
     if args.cpu_baseline and main_form:

@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(256) k_x_reduce(int p, int64_t nbox, const int
 // Otherwise (passes of mp points): lane = group * mp + point, the compacted
 // entries dealt to the groups in turn, group 0 adding the others' sums at its
 // point in group order.  Each item writes its sums at its points to its own
-// row of mpart (lane = point offset); k_m2p_sum adds them to the potentials.
+// row of mpart (lane = point offset); the leaf pass adds them per point.
 template <int P1>
 constexpr int m_stage() { return P1 <= 16 ? 32 : 16; }  // entries staged at once (LDS of 32 KB per block)
 template <int P1, bool WIDE>
@@ -539,45 +539,6 @@ __global__ void __launch_bounds__(256) k_m2p(int L, int64_t n, const int4 *__res
         acc = tot;
     }
     if (grp == 0 && act) mpart[(int64_t)it * 64 + lane] = acc;
-}
-
-// Per point (leaf order): its M2P sums, level by level and within a level in
-// item order (the row spans of its point pass), added to its potential.  The
-// item ranges and box starts of all levels are loaded before any is used.
-__global__ void __launch_bounds__(256) k_m2p_sum(int L, int64_t n, const int32_t *__restrict__ leafid,
-                                                 const int32_t *__restrict__ stL,
-                                                 const int32_t *__restrict__ itemoff,
-                                                 const double *__restrict__ mpart, const int32_t *__restrict__ perm,
-                                                 double *__restrict__ phi, M2PWidths mw) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t leaf = leafid[i];
-    int32_t r0[FMM2D_MAX_LEVELS + 1], r1[FMM2D_MAX_LEVELS + 1], a0[FMM2D_MAX_LEVELS + 1];
-#pragma unroll
-    for (int l = 1; l <= FMM2D_MAX_LEVELS; ++l) {
-        r0[l] = r1[l] = a0[l] = 0;
-        if (l <= L) {
-            const int64_t b = leaf >> (2 * (L - l)), g = level_offset(l) + b;
-            r0[l] = itemoff[g];
-            r1[l] = itemoff[g + 1];
-            a0[l] = stL[b << (2 * (L - l))];  // the box's first point
-        }
-    }
-    double acc = 0.0;
-    bool any = false;
-#pragma unroll
-    for (int l = 1; l <= FMM2D_MAX_LEVELS; ++l) {
-        if (l > L || r0[l] == r1[l]) continue;
-        const int64_t b = leaf >> (2 * (L - l));
-        const int32_t e = stL[(b + 1) << (2 * (L - l))];
-        const int32_t a = a0[l], step = mw.w[l];
-        const int32_t npc = (e - a + step - 1) / step, nsp = (r1[l] - r0[l]) / npc;
-        const int32_t pc = ((int32_t)i - a) / step, o = (int32_t)i - a - pc * step;
-        const double *row = mpart + (int64_t)(r0[l] + pc * nsp) * 64 + o;
-        for (int32_t s = 0; s < nsp; ++s) acc += row[(int64_t)s * 64];
-        any = true;
-    }
-    if (any) phi[perm[i]] += acc;
 }
 
 // M2P for orders p + 1 > 32: one lane per point of the leaf.
@@ -761,24 +722,19 @@ hipError_t p2l_all(fmm2d_ctx *c, int p) {
     return hipGetLastError();
 }
 
-hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
+hipError_t m2p_partials(fmm2d_ctx *c, int p) {
     TreeState &t = c->tree;
-    if (!t.x_ready) return hipSuccess;
+    c->ev.m2p = M2PSum{};
+    if (!t.x_ready || p + 1 > PMAX_FAST) return hipSuccess;
     const int L = t.L;
     const dim3 block(256);
     const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
     const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);
-    const int32_t *xptr = t.xptr.as<int32_t>(), *xidx = t.xidx.as<int32_t>(), *perm = t.perm.as<int32_t>();
+    const int32_t *xidx = t.xidx.as<int32_t>();
     const double4 *geom = t.geom.as<double4>();
     const cd *A = c->ev.A.as<cd>();
     const double *px = t.px.as<double>(), *py = t.py.as<double>();
     PhaseScope kernel_scope(c, PH_M2P_KERNEL);  // the M2P kernels alone
-    if (p + 1 > PMAX_FAST) {
-        const int64_t nleaf = int64_t(1) << (2 * L);
-        hipLaunchKernelGGL(k_m2p_gen, dim3(grid_for(nleaf, 4)), block, 0, c->stream, p, L, nleaf, stL, xptr, xidx,
-                           xoff, geom, A, px, py, perm, phi);
-        return hipGetLastError();
-    }
     const int4 *items = t.m_items.as<int4>();
     const int64_t nbox = level_offset(L + 1), mb = t.m_bound_wide + t.m_bound_narrow;
     FMM2D_TRY(c->ev.mpart.ensure(sizeof(double) * 64 * (mb > 0 ? mb : 1)));
@@ -814,9 +770,26 @@ hipError_t m2p_all(fmm2d_ctx *c, int p, double *phi) {
         }
         FMM2D_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_m2p_sum, dim3(grid_for(t.n, 256)), block, 0, c->stream, L, t.n, t.leafid.as<int32_t>(), stL,
-                       off, mpart, perm, phi, widths);
+    M2PSum ms;
+    ms.itemoff = off;
+    ms.mpart = mpart;
+    for (int l = 0; l <= FMM2D_MAX_LEVELS; ++l) ms.w[l] = widths.w[l];
+    c->ev.m2p = ms;
     return hipSuccess;
+}
+
+hipError_t m2p_direct(fmm2d_ctx *c, int p, double *phi) {
+    TreeState &t = c->tree;
+    if (!t.x_ready || p + 1 <= PMAX_FAST) return hipSuccess;
+    const int L = t.L;
+    const int32_t *stL = t.starts.as<int32_t>() + depth_offset(2 * L);
+    const int64_t *xoff = t.pool_state.as<int64_t>() + 2 * (L + 2);
+    const int32_t *xptr = t.xptr.as<int32_t>(), *xidx = t.xidx.as<int32_t>(), *perm = t.perm.as<int32_t>();
+    PhaseScope kernel_scope(c, PH_M2P_KERNEL);
+    const int64_t nleaf = int64_t(1) << (2 * L);
+    hipLaunchKernelGGL(k_m2p_gen, dim3(grid_for(nleaf, 4)), dim3(256), 0, c->stream, p, L, nleaf, stL, xptr, xidx,
+                       xoff, t.geom.as<double4>(), c->ev.A.as<cd>(), t.px.as<double>(), t.py.as<double>(), perm, phi);
+    return hipGetLastError();
 }
 
 }  // namespace fmm2d

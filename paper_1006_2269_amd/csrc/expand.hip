@@ -607,9 +607,11 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
     FMM2D_TRY(e.part.ensure(sizeof(cd)));  // a valid pointer also when there is no weak pair
     {
         // exchanged roles, target the smaller box: its P2L partials, which
-        // the L2L pass adds into B
+        // the L2L pass adds into B; target the larger box: the M2P sums at
+        // its points, which the leaf pass adds
         PhaseScope ps(c, PH_EXCHANGE);
         FMM2D_TRY(p2l_all(c, p));
+        FMM2D_TRY(m2p_partials(c, p));
     }
     {
         PhaseScope ps(c, PH_L2L);
@@ -620,9 +622,9 @@ hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, doubl
         FMM2D_TRY(leaf_pass(c, p, mode, NEAR_FINISH, phi));
     }
     {
-        // exchanged roles, target the larger box: M2P at its points
+        // exchanged roles above order 32: M2P added into phi at the end
         PhaseScope ps(c, PH_EXCHANGE);
-        FMM2D_TRY(m2p_all(c, p, phi));
+        FMM2D_TRY(m2p_direct(c, p, phi));
     }
     return hipGetLastError();
 }

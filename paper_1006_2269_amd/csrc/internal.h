@@ -108,6 +108,16 @@ struct TreeState {
     double root_r = 0.0;            // half diagonal of the root box (host copy, read with the lists)
 };
 
+// The M2P sums of the exchanged-roles items for the near-field reduction
+// (a kernel argument): per global box its first M2P item (+ count), each
+// item's sums at its points (64 doubles), and every level's pass width; no
+// M2P sums when itemoff is null.
+struct M2PSum {
+    const int32_t *itemoff = nullptr;
+    const double *mpart = nullptr;
+    int32_t w[FMM2D_MAX_LEVELS + 1] = {};
+};
+
 struct EvalState {
     DevBuf binom;           // double [128][128] binomial coefficients
     bool binom_ready = false;
@@ -124,6 +134,7 @@ struct EvalState {
     DevBuf xpart;           // P2L partial expansions of the exchanged-roles items
     DevBuf xsum;            // their sum per target box (boxes with items)
     DevBuf mpart;           // double [M2P items][64]: each item's sums at its points
+    M2PSum m2p;             // the M2P sums of this evaluation (set before the leaf pass finishes)
 };
 
 // Per-phase GPU time, measured with HIP events recorded on the context stream

@@ -634,13 +634,14 @@ __device__ inline cd l2p_horner(const cd *__restrict__ Bb, int p, cd z) {
 }
 
 // Per point: the partial sums of its leaf's segments in segment order, times
-// `scale`, plus L2P (binary64 Horner) of the leaf's local expansion.
+// `scale`, plus L2P (binary64 Horner) of the leaf's local expansion and the
+// exchanged-roles M2P sums.
 __global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale, const int32_t *__restrict__ leafid,
                               const int32_t *__restrict__ stL, const int32_t *__restrict__ segoff,
                               const double *__restrict__ part, const double4 *__restrict__ geomL,
                               const double *__restrict__ px, const double *__restrict__ py,
                               const cd *__restrict__ BL, const int32_t *__restrict__ perm,
-                              double *__restrict__ phi) {
+                              double *__restrict__ phi, int L, M2PSum ms) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t b = leafid[i];
@@ -651,7 +652,8 @@ __global__ void k_near_reduce(int p, int64_t n, int tm, int chunks, double scale
     const double4 g = geomL[b];
     const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
     const cd v = l2p_horner(BL + (int64_t)b * (p + 1), p, z);
-    phi[perm[i]] = v.re + scale * near;  // input order
+    const double xm = ms.itemoff ? m2p_point_sum(ms, L, i, b, stL) : 0.0;  // exchanged roles, M2P
+    phi[perm[i]] = (v.re + scale * near) + xm;  // input order
 }
 
 // Source-side sums of the entries of S_L(c) before c's own (written there by
@@ -684,14 +686,15 @@ __global__ void __launch_bounds__(256) k_near_lsum(const int2 *__restrict__ segt
 
 // Per point of the pair-once path: its leaf's target-side segment sums, then
 // the source-side sums of the leaves c < b (segment sums of the entries of
-// S_L(b) before b's own), times `scale`, plus L2P.
+// S_L(b) before b's own), times `scale`, plus L2P and the exchanged-roles M2P
+// sums.
 __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, double scale,
                                   const int32_t *__restrict__ leafid, const int32_t *__restrict__ stL,
                                   const int32_t *__restrict__ segoff, const double *__restrict__ part,
                                   const int32_t *__restrict__ losegoff, const double *__restrict__ lsum,
                                   const double4 *__restrict__ geomL, const double *__restrict__ px,
                                   const double *__restrict__ py, const cd *__restrict__ BL,
-                                  const int32_t *__restrict__ perm, double *__restrict__ phi) {
+                                  const int32_t *__restrict__ perm, double *__restrict__ phi, int L, M2PSum ms) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t b = leafid[i];
@@ -703,7 +706,8 @@ __global__ void k_near_reduce_sym(int p, int64_t n, int tm, int ch_n, int gl, do
     const double4 g = geomL[b];
     const cd z{(px[i] - g.x) / g.w, (py[i] - g.y) / g.w};
     const cd v = l2p_horner(BL + (int64_t)b * (p + 1), p, z);
-    phi[perm[i]] = v.re + scale * near;  // input order
+    const double xm = ms.itemoff ? m2p_point_sum(ms, L, i, b, stL) : 0.0;  // exchanged roles, M2P
+    phi[perm[i]] = (v.re + scale * near) + xm;  // input order
 }
 
 // FP32 paths with leaves of at most 64 points: each leaf pair once.  Stage
@@ -738,7 +742,7 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage, double *phi
         hipLaunchKernelGGL(k_near_reduce_sym, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, CH, GL,
                            HALF_LN2_D, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part,
                            lo.segoff.as<int32_t>(), t.lsum.as<double>(), gL, t.px.as<double>(), t.py.as<double>(),
-                           BL, t.perm.as<int32_t>(), phi);
+                           BL, t.perm.as<int32_t>(), phi, L, e.m2p);
         return hipGetLastError();
     }
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
@@ -795,7 +799,7 @@ hipError_t launch_near(fmm2d_ctx *c, int p, int mode, int maxleaf, int stage, do
         FMM2D_TRY(side_join(c));
         hipLaunchKernelGGL(k_near_reduce, dim3(grid_for(t.n, 256)), dim3(256), 0, c->stream, p, t.n, TM, chunks,
                            scale, t.leafid.as<int32_t>(), stL, sc.segoff.as<int32_t>(), part, gL, t.px.as<double>(),
-                           t.py.as<double>(), BL, t.perm.as<int32_t>(), phi);
+                           t.py.as<double>(), BL, t.perm.as<int32_t>(), phi, L, e.m2p);
         return hipGetLastError();
     }
     const dim3 grid(grid_for(nitems, NWB)), block(64 * NWB);
