@@ -618,14 +618,14 @@ def main():
             (per("near_kernel"), near_name, "alu", near_flops, MI355X["fp32_TFLOPs"], near_work_s, near_k),
             (per("m2l_kernel"), "k_m2l_lp (M2L, all levels, one launch)", "mfma", weak_all * 4.0 * (p + 1) ** 2,
              MI355X["fp32_mfma_TFLOPs"], "%d weak pairs x 4(p+1)^2 flops" % weak_all,
-             [("k_m2l_lp<%d," % (p + 1), ">")]),
+             [("k_m2l_lp<%d," % (p + 1), ", float, double, false>" if mode_red == "fp32_acc64" else ", float, float, false>")]),
             (per("p2l_kernel"), "k_p2l + k_p2l_lane (exchanged roles, P2L: chunks and whole entries, two launches)",
              "alu", fl_p2l, MI355X["fp64_TFLOPs"],
              "%d source-point terms x (10(p+1)-7) flops, binary64" % t_p2l,
              [("k_p2l<%d>" % (p + 1), ">"), ("k_p2l_lane<%d>" % (p + 1), ">")]),
-            (per("m2p_kernel"), "k_m2p + k_m2p_sum (exchanged roles, M2P: one launch per pass width, per-point sum)",
+            (per("m2p_kernel"), "k_m2p (exchanged roles, M2P: one launch per pass width)",
              "alu", fl_m2p, MI355X["fp64_TFLOPs"], "%d target-point terms x (8(p+1)-1) flops, binary64" % t_m2p,
-             [("k_m2p<%d," % (p + 1), ">"), ("k_m2p_sum", "")]),
+             [("k_m2p<%d," % (p + 1), ">")]),
         ]
         for ms, name, bound, flops, peak, work, _ in cands:
             log("[bench] kernel %-45s %8.3f ms  %8.2f TFLOP/s  (%s)" % (name, ms, flops / max(ms, 1e-9) / 1e9, work))
