@@ -664,13 +664,15 @@ template <int GL>
 __global__ void __launch_bounds__(256) k_near_lsum(const int2 *__restrict__ segtab,
                                                    const int32_t *__restrict__ nseg_ptr,
                                                    const int32_t *__restrict__ selfpos, const float *__restrict__ spart,
-                                                   double *__restrict__ lsum) {
+                                                   const int32_t *__restrict__ stL, double *__restrict__ lsum) {
     constexpr int LPI = 64 / GL;
     const int64_t sg = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     if (sg >= *nseg_ptr) return;  // uniform per wavefront
     const int lane = threadIdx.x % 64, grp = lane / GL, jj = lane % GL;
     const int2 se = segtab[sg];
-    const int32_t u1 = (se.y + NEAR_SEG) < selfpos[se.x] ? (se.y + NEAR_SEG) : selfpos[se.x];
+    // lanes past the leaf's points read nothing (their sums are never used)
+    const int32_t u1 = jj >= stL[se.x + 1] - stL[se.x] ? se.y
+                       : ((se.y + NEAR_SEG) < selfpos[se.x] ? (se.y + NEAR_SEG) : selfpos[se.x]);
     double v = 0.0;
     int32_t u = se.y + grp;
     for (; u + 3 * LPI < u1; u += 4 * LPI) {  // four loads in flight, added in entry order
@@ -764,7 +766,7 @@ hipError_t launch_near_sym(fmm2d_ctx *c, int p, int mode, int stage, double *phi
     }
     FMM2D_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_near_lsum<GL>, dim3(grid_for(lo.bound > 0 ? lo.bound : 1, 4)), dim3(256), 0, c->side,
-                       lo.table.as<int2>(), lo.segoff.as<int32_t>() + nleaf, t.selfpos.as<int32_t>(), spart,
+                       lo.table.as<int2>(), lo.segoff.as<int32_t>() + nleaf, t.selfpos.as<int32_t>(), spart, stL,
                        t.lsum.as<double>());
     FMM2D_TRY(hipGetLastError());
     return side_end(c);
