@@ -33,6 +33,12 @@
 namespace fmm2d {
 namespace {
 
+// log|z| for z with |z|^2 = d2 > 0: log_pos of d2, and for |z|^2 <= 2^-960
+// (where d2 could underflow) the library's hypot and log, kept out of line
+// (no input of ordinary scale reaches it) and returned by value.
+__device__ __attribute__((noinline)) double log_abs_tiny(double x, double y) { return log(hypot(x, y)); }
+__device__ inline double log_abs(cd z, double d2) { return d2 > 0x1p-960 ? 0.5 * log_pos(d2) : log_abs_tiny(z.re, z.im); }
+
 // Global box id of a weak-list entry of level lvl: a box of that level, or,
 // with FMM2D_VFLAG set, a box of the level above (interaction via the
 // parent box, Section 4's structural option).
@@ -257,7 +263,7 @@ __global__ void __launch_bounds__(64) k_m2l(int p, const double4 *__restrict__ g
                     sc2 *= (PT)2;
                 }
             }
-            if (slot == 0) ext0 += a_cur[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im)));
+            if (slot == 0) ext0 += a_cur[0].re * log_abs(z0, d2);
         } else {
 #pragma unroll
             for (int kk = 0; kk < KRMAX; ++kk) {
@@ -425,7 +431,7 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
             const double inv = gc.w / d2;
             const cd rs = d2 > 0x1p-960 ? cd{z0.re * inv, -z0.im * inv} : cdiv(cd{gc.w, 0.0}, z0);
             const cd rt = cscale(rs, gb.w / gc.w);
-            ext0 += (ACC)(a[0].re * (d2 > 0x1p-960 ? 0.5 * log(d2) : log(hypot(z0.re, z0.im))));
+            ext0 += (ACC)(a[0].re * log_abs(z0, d2));
             // 2 rho: the exact factors 2^k of the rescaled matrix ride on the powers
             const cx<PT> rsp{(PT)(2.0 * rs.re), (PT)(2.0 * rs.im)};
             rtp = cx<PT>{(PT)(2.0 * rt.re), (PT)(2.0 * rt.im)};
