@@ -371,8 +371,9 @@ int fmm2d_get_xlists(fmm2d_ctx *ctx, int level, int64_t *nx, int32_t *xptr, int3
 #define FMM2D_PHASE_NEAR_KERNEL  9  /* the near-field kernel (in LEAF)       */
 #define FMM2D_PHASE_M2L_KERNEL  10  /* the M2L kernel, all levels (in M2L)   */
 #define FMM2D_PHASE_EXCHANGE    11  /* P2L and M2P of exchanged-roles pairs  */
-#define FMM2D_PHASE_P2L_KERNEL  12  /* the P2L kernel (in EXCHANGE)          */
-#define FMM2D_PHASE_M2P_KERNEL  13  /* the M2P kernel (in EXCHANGE)          */
+#define FMM2D_PHASE_P2L_KERNEL  12  /* the P2L kernels (in EXCHANGE)         */
+#define FMM2D_PHASE_M2P_KERNEL  13  /* the M2P kernels (in EXCHANGE; their  */
+                                    /* sums are added per point in LEAF)    */
 #define FMM2D_NPHASE       14
 
 /* enable = 1 clears the accumulated timings and starts recording HIP events
