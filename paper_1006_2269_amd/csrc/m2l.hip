@@ -367,7 +367,11 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
     using V = typename MF::V;
     using PT = typename std::conditional<std::is_same<ACC, float>::value, float, double>::type;
     constexpr int NTL = (P1 + 15) / 16;                      // output tiles of 16 coefficients
-    constexpr int KP = 16 * NTL + 1;                         // padded row length
+    // row length: the products' K columns, and the outputs read back (the
+    // first tile's 16, of the second only those below P1), plus one column of
+    // padding against bank conflicts
+    constexpr int KW = (4 * ((P1 + 3) / 4) > (NTL > 1 ? P1 : 16)) ? 4 * ((P1 + 3) / 4) : (NTL > 1 ? P1 : 16);
+    constexpr int KP = KW + 1;
     constexpr int KS = (P1 + 3) / 4;                         // K steps of the FP32/FP64 instruction
     // the post-scaled values (Re, Im) are summed in passes of NV values
     // (NV / 2 coefficients each), which bounds the live registers
@@ -483,7 +487,8 @@ __global__ void __launch_bounds__(64) k_m2l_lp(const double4 *__restrict__ geom,
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 U[8 * rb + 2 * g + r / 2][r % 2][row] = (G)d[r];
-                if constexpr (NTL > 1) U[8 * rb + 2 * g + r / 2][r % 2][16 + row] = (G)d2[r];
+                if constexpr (NTL > 1)
+                    if (16 + row < P1) U[8 * rb + 2 * g + r / 2][r % 2][16 + row] = (G)d2[r];
             }
         }
         __syncthreads();
