@@ -22,6 +22,10 @@ multipole methods":
 * ``lists_opt``  -- the same with the structural optimisations of Section 4:
                     interaction via the parent box, and exchanged roles
                     (P2L / M2P) for boxes of very different radii.
+* ``lists_relaxed`` -- the plain rule with a locally relaxed theta (Section 4,
+                    last paragraph): pairs with their own theta_i above theta
+                    admitted as weak while the level's mean of theta_i^(p+1)
+                    stays at most theta^(p+1).
 * ``fmm``        -- upward pass, M2L along weak lists, downward pass, direct
                     sum along the finest strong lists (Section 4) in the
                     complex multipole representation (Section 5).
@@ -83,6 +87,8 @@ def _load():
     lib.orc_swap_test.restype = i32
     lib.orc_lists_level_opt.argtypes = [i32, d, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i64]
     lib.orc_lists_level_opt.restype = i32
+    lib.orc_lists_level_relaxed.argtypes = [i32, d, d, i32, i32, i32, P, P, P, P, P, P, P, i64, P, P]
+    lib.orc_lists_level_relaxed.restype = i32
     lib.orc_p2l.argtypes = [i64, P, P, P, d, d, d, i32, P]
     lib.orc_p2l.restype = None
     lib.orc_fmm_eval_opt.argtypes = [i64, P, P, P, i32, i32] + [P] * 17
@@ -327,6 +333,67 @@ def lists_opt(t: Tree, theta: float, parent: bool = True, swap_levels=None) -> L
         vptr.append(vp); vidx.append(vi[:vp[-1]].copy())
         xptr.append(xp); xidx.append(xi[:xp[-1]].copy())
     return ListsOpt(theta, sptr, sidx, wptr, widx, vptr, vidx, xptr, xidx, bool(parent), swap_levels)
+
+
+@dataclass
+class ListsRelaxed(Lists):
+    theta_max: float = 0.0
+    p: int = 0
+    k0: int = 0
+    k1: int = 0
+    count: list = None   # per level: int64 [k0 + k1], candidates of each threshold bin
+    kmax: list = None    # per level: last bin admitted as weak (k0 - 1 = the plain rule)
+
+
+def relax_thresholds(theta: float, theta_max: float, k0: int, k1: int) -> np.ndarray:
+    """The grid of thresholds on which the relaxed lists read theta_i:
+    k0 steps up to theta (the last one theta itself), then k1 steps to
+    theta_max, each a binary64 expression evaluated as written."""
+    t = [theta * float(k + 1) / float(k0) for k in range(k0)]
+    t += [theta + (theta_max - theta) * float(k + 1) / float(k1) for k in range(k1)]
+    return np.array(t, dtype=np.float64)
+
+
+def lists_relaxed(t: Tree, theta: float, theta_max: float, p: int, k0: int = 16,
+                  k1: int = 16) -> ListsRelaxed:
+    """Lists under a locally relaxed theta-criterion (Section 4, last
+    paragraph): on every level the candidates whose least grid threshold
+    passing Criterion 2.1 lies above theta are admitted as weak, lowest
+    thresholds first, while the mean of t^(p+1) over the level's weak pairs
+    stays at most theta^(p+1).  theta_max = theta gives the plain lists."""
+    if not (0.0 < theta <= theta_max < 1.0):
+        raise ValueError("need 0 < theta <= theta_max < 1")
+    if p < 0 or k0 < 1 or k1 < 1 or k0 + k1 > 256:
+        raise ValueError("need p >= 0, k0, k1 >= 1 and k0 + k1 <= 256")
+    lib = _load()
+    sptr = [np.array([0, 1], dtype=np.int64)]
+    sidx = [np.array([0], dtype=np.int64)]
+    wptr = [np.array([0, 0], dtype=np.int64)]
+    widx = [np.zeros(0, dtype=np.int64)]
+    count = [np.zeros(k0 + k1, dtype=np.int64)]
+    kmax = [k0 - 1]
+    for l in range(1, t.levels + 1):
+        nb = 4 ** l
+        cap = 16 * int(sidx[-1].shape[0])
+        sp = np.empty(nb + 1, dtype=np.int64)
+        wp = np.empty(nb + 1, dtype=np.int64)
+        si = np.empty(max(cap, 1), dtype=np.int64)
+        wi = np.empty(max(cap, 1), dtype=np.int64)
+        cnt = np.zeros(k0 + k1, dtype=np.int64)
+        km = ctypes.c_int(0)
+        g = np.ascontiguousarray(t.level_geom(l))
+        rc = lib.orc_lists_level_relaxed(l, theta, theta_max, p, k0, k1, _p(g), _p(sptr[-1]),
+                                         _p(sidx[-1]), _p(sp), _p(si), _p(wp), _p(wi), cap,
+                                         _p(cnt), ctypes.byref(km))
+        if rc != 0:
+            raise RuntimeError("orc_lists_level_relaxed failed: %d" % rc)
+        sptr.append(sp)
+        sidx.append(si[:sp[-1]].copy())
+        wptr.append(wp)
+        widx.append(wi[:wp[-1]].copy())
+        count.append(cnt)
+        kmax.append(int(km.value))
+    return ListsRelaxed(theta, sptr, sidx, wptr, widx, theta_max, p, k0, k1, count, kmax)
 
 
 # --------------------------------------------------------------------------

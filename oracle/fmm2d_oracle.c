@@ -330,6 +330,95 @@ int orc_lists_level_opt(int l, double theta, int parent, int swap, const double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Locally relaxed theta (Section 4, last paragraph): pairs may be admitted
+ * as weak with their own theta_i > theta as long as the mean of
+ * theta_i^(p+1) over the admitted pairs stays at most theta^(p+1).
+ *
+ * theta_i of a pair is read on a fixed grid of thresholds
+ *     t_k = theta (k + 1) / k0                        k = 0 .. k0 - 1
+ *     t_k = theta + (theta_max - theta)(k - k0 + 1) / k1   k = k0 .. k0 + k1 - 1
+ * (t_{k0-1} = theta exactly): the bin of a candidate is the least k whose
+ * threshold passes Criterion 2.1, and t_bin^(p+1) stands in for theta_i^(p+1)
+ * (an upper bound).  Per level: count the candidates of every bin, then take
+ * the largest K >= k0 - 1 such that for every k in k0 - 1 .. K
+ *     sum_{j <= k} count_j t_j^(p+1)  <=  theta^(p+1) sum_{j <= k} count_j
+ * (sums in j order, powers by p repeated products); candidates of bins up to
+ * K are weak, the rest strong.  With theta_max = theta this is the plain
+ * rule.  Returns 0, or -1 if a capacity is exceeded.                      */
+/* ------------------------------------------------------------------------ */
+static double relax_threshold(double theta, double theta_max, int k0, int k1, int k)
+{
+    if (k < k0) return theta * (double)(k + 1) / (double)k0;
+    return theta + (theta_max - theta) * (double)(k - k0 + 1) / (double)k1;
+}
+
+static double power_p1(double t, int p)
+{
+    double e = t;
+    for (int i = 0; i < p; ++i) e *= t;
+    return e;
+}
+
+/* Least k with the criterion true at t_k, or nbin when none is. */
+static int relax_bin(const double *tk, int nbin, const double *gb, const double *gc)
+{
+    for (int k = 0; k < nbin; ++k)
+        if (orc_theta_test(tk[k], gb, gc)) return k;
+    return nbin;
+}
+
+int orc_lists_level_relaxed(int l, double theta, double theta_max, int p, int k0, int k1,
+                            const double *geom_l, const int64_t *sptr_prev, const int64_t *sidx_prev,
+                            int64_t *sptr, int64_t *sidx, int64_t *wptr, int64_t *widx,
+                            int64_t cap, int64_t *count, int *kmax)
+{
+    if (k0 < 1 || k1 < 1 || k0 + k1 > 256) return -2;
+    int nbin = k0 + k1;
+    double tk[256];
+    for (int k = 0; k < nbin; ++k) tk[k] = relax_threshold(theta, theta_max, k0, k1, k);
+    int64_t nb = ((int64_t)1) << (2 * l);
+    for (int k = 0; k < nbin; ++k) count[k] = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t P = b / 4;
+        for (int64_t t = sptr_prev[P]; t < sptr_prev[P + 1]; ++t)
+            for (int64_t c = 4 * sidx_prev[t]; c < 4 * sidx_prev[t] + 4; ++c) {
+                int k = relax_bin(tk, nbin, geom_l + 3 * b, geom_l + 3 * c);
+                if (k < nbin) ++count[k];
+            }
+    }
+    double etheta = power_p1(theta, p);
+    double sum = 0.0;
+    int64_t n = 0;
+    int K = k0 - 1;
+    for (int k = 0; k < nbin; ++k) {
+        sum += (double)count[k] * power_p1(tk[k], p);
+        n += count[k];
+        if (k < k0 - 1) continue;
+        if (k > k0 - 1 && !(sum <= etheta * (double)n)) break;
+        K = k;
+    }
+    *kmax = K;
+    int64_t ns = 0, nw = 0;
+    sptr[0] = 0; wptr[0] = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t P = b / 4;
+        for (int64_t t = sptr_prev[P]; t < sptr_prev[P + 1]; ++t)
+            for (int64_t c = 4 * sidx_prev[t]; c < 4 * sidx_prev[t] + 4; ++c) {
+                if (relax_bin(tk, nbin, geom_l + 3 * b, geom_l + 3 * c) <= K) {
+                    if (nw >= cap) return -1;
+                    widx[nw++] = c;
+                } else {
+                    if (ns >= cap) return -1;
+                    sidx[ns++] = c;
+                }
+            }
+        sptr[b + 1] = ns;
+        wptr[b + 1] = nw;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* O4: the expansion operators in the classical complex representation
  * (Section 5), with every expansion normalised by its box scale s.
  *
