@@ -178,6 +178,33 @@ int fmm2d_connectivity(fmm2d_ctx *ctx, double theta);
  * FMM2D_EINVAL for unknown bits.  fmm2d_evaluate_field needs opt = 0. */
 int fmm2d_connectivity_opt(fmm2d_ctx *ctx, double theta, int opt);
 
+/* The plain lists under a locally relaxed theta-criterion (Section 4, last
+ * paragraph: differing theta_i are admissible while the mean of
+ * theta_i^(p+1) over the observed values stays at most theta^(p+1)).
+ * A pair's theta_i is read on a grid of k0 + k1 thresholds,
+ *     t_k = theta (k + 1) / k0                             k < k0
+ *     t_k = theta + (theta_max - theta) (k - k0 + 1) / k1   k >= k0
+ * (binary64, evaluated as written; t_{k0-1} = theta): a candidate's bin is
+ * the least k at which the criterion holds.  On every level the bins are
+ * counted, and bins 0..K are weak for the largest K >= k0 - 1 such that for
+ * each k from k0 - 1 to K
+ *     sum_{j<=k} count_j t_j^(p+1) <= theta^(p+1) sum_{j<=k} count_j
+ * (powers by p repeated products, sums in bin order, binary64); the other
+ * candidates are strong.  theta_max = theta gives fmm2d_connectivity's
+ * lists.  p is the expansion order the lists are meant for (later
+ * evaluations may use any order).  0 < theta <= theta_max < 1,
+ * 0 <= p <= 1024, k0, k1 >= 1, k0 + k1 <= 256; FMM2D_EINVAL otherwise,
+ * FMM2D_ESTATE without a tree, FMM2D_ECAPACITY as fmm2d_connectivity.
+ * Synchronises the stream as fmm2d_connectivity does. */
+int fmm2d_connectivity_relaxed(fmm2d_ctx *ctx, double theta, double theta_max, int p, int k0, int k1);
+
+/* The bin counts and admitted bins of the lists built by
+ * fmm2d_connectivity_relaxed.  count: host int64 [(L + 1) (k0 + k1)], level
+ * by level (level 0 all zero); kmax: host int32 [L + 1], the last weak bin
+ * of each level (k0 - 1 for level 0).  FMM2D_ESTATE unless the current
+ * lists came from fmm2d_connectivity_relaxed.  Synchronises the stream. */
+int fmm2d_get_relax_bins(fmm2d_ctx *ctx, int64_t *count, int32_t *kmax);
+
 /* Evaluates phi (eq. (1.1)) with expansion order p (degrees 0..p, so p + 1
  * coefficients per expansion), 1 <= p <= 63, in precision `mode`
  * (FMM2D_MODE_*).  q: device binary64 [n] charges in input order.  phi:

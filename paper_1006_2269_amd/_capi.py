@@ -39,6 +39,8 @@ SIGNATURES = [
     ("fmm2d_build_tree", I32, [P, P, P, I64, I32]),
     ("fmm2d_connectivity", I32, [P, D]),
     ("fmm2d_connectivity_opt", I32, [P, D, I32]),
+    ("fmm2d_connectivity_relaxed", I32, [P, D, D, I32, I32, I32]),
+    ("fmm2d_get_relax_bins", I32, [P, P, P]),
     ("fmm2d_evaluate", I32, [P, P, I32, I32, P]),
     ("fmm2d_evaluate_field", I32, [P, P, I32, I32, P, P, P]),
     ("fmm2d_direct", I32, [P, P, P, P, I64, P, I64, P]),

@@ -161,7 +161,8 @@ int fmm2d_destroy(fmm2d_ctx *c) {
         for (DevBuf *b : {&t.xsorted, &t.ysorted, &t.xorder, &t.XLx, &t.XLy, &t.YLx, &t.YLy, &t.T0, &t.T1,
                           &t.starts, &t.rects, &t.prect, &t.geom, &t.perm, &t.leafid, &t.px, &t.py, &t.loc, &t.sptr, &t.wptr,
                           &t.sidx, &t.widx, &t.xptr, &t.xidx, &t.cnt_x, &t.cnt_s, &t.cnt_w, &t.pool_state, &t.nrec_j, &t.nrec_d, &t.bits,
-                          &t.owner0, &t.owner1, &t.selfpos, &t.trans, &t.spart})
+                          &t.owner0, &t.owner1, &t.selfpos, &t.trans, &t.spart, &t.relax_tk, &t.relax_hist,
+                          &t.relax_lv, &t.relax_k})
             b->release();
         EvalState &e = c->ev;
         c->tree.m2l_all.segoff.release();
@@ -326,14 +327,10 @@ int fmm2d_select_build_tree(fmm2d_ctx *c, const double *x, const double *y, int6
     return FMM2D_OK;
 }
 
-int fmm2d_connectivity_opt(fmm2d_ctx *c, double theta, int opt) {
-    if (!c) return FMM2D_EINVAL;
-    c->err.clear();
-    if (!(theta > 0.0 && theta < 1.0)) return fail(c, FMM2D_EINVAL, "connectivity: theta must lie in (0, 1)");
-    if (opt & ~(FMM2D_OPT_PARENT | FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL))
-        return fail(c, FMM2D_EINVAL, "connectivity: unknown option bits 0x%x", opt);
+// The list build with its pool regrowth, shared by the connectivity calls
+// (arguments already checked).
+static int connectivity_impl(fmm2d_ctx *c, double theta, int opt, const RelaxRule *rx) {
     TreeState &t = c->tree;
-    if (t.L < 0) return fail(c, FMM2D_ESTATE, "connectivity: no tree (call fmm2d_build_tree first)");
     CtxScope g(c);
     const int64_t nbox = level_offset(t.L + 1);
     const bool swaps = (opt & (FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL)) != 0;
@@ -349,7 +346,7 @@ int fmm2d_connectivity_opt(fmm2d_ctx *c, double theta, int opt) {
         {
             PhaseScope ps(c, PH_LISTS);
             t.nrec_valid = false;
-            e = build_lists_device(c, theta, opt, cap_s, cap_w, cap_x, c->list_limit, &overflow);
+            e = build_lists_device(c, theta, opt, cap_s, cap_w, cap_x, c->list_limit, &overflow, rx);
         }
         if (e != hipSuccess) {
             t.has_lists = false;
@@ -400,7 +397,69 @@ int fmm2d_connectivity_opt(fmm2d_ctx *c, double theta, int opt) {
     return fail(c, FMM2D_ECAPACITY, "connectivity: interaction lists exceed 2^34 entries");
 }
 
+int fmm2d_connectivity_opt(fmm2d_ctx *c, double theta, int opt) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!(theta > 0.0 && theta < 1.0)) return fail(c, FMM2D_EINVAL, "connectivity: theta must lie in (0, 1)");
+    if (opt & ~(FMM2D_OPT_PARENT | FMM2D_OPT_SWAP_FINEST | FMM2D_OPT_SWAP_ALL))
+        return fail(c, FMM2D_EINVAL, "connectivity: unknown option bits 0x%x", opt);
+    if (c->tree.L < 0) return fail(c, FMM2D_ESTATE, "connectivity: no tree (call fmm2d_build_tree first)");
+    return connectivity_impl(c, theta, opt, nullptr);
+}
+
 int fmm2d_connectivity(fmm2d_ctx *c, double theta) { return fmm2d_connectivity_opt(c, theta, 0); }
+
+// t^(p+1) by p repeated products, each rounded (the sums of the admission
+// test use the same values on the device).
+static double power_p1(double t, int p) {
+    double e = t;
+    for (int i = 0; i < p; ++i) e *= t;
+    return e;
+}
+
+int fmm2d_connectivity_relaxed(fmm2d_ctx *c, double theta, double theta_max, int p, int k0, int k1) {
+#pragma clang fp contract(off)
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    if (!(theta > 0.0 && theta <= theta_max && theta_max < 1.0))
+        return fail(c, FMM2D_EINVAL, "connectivity_relaxed: need 0 < theta <= theta_max < 1");
+    if (p < 0 || p > 1024 || k0 < 1 || k1 < 1 || k0 + k1 > RELAX_MAX_BINS)
+        return fail(c, FMM2D_EINVAL, "connectivity_relaxed: need 0 <= p <= 1024, k0, k1 >= 1, k0 + k1 <= %d",
+                    RELAX_MAX_BINS);
+    TreeState &t = c->tree;
+    if (t.L < 0) return fail(c, FMM2D_ESTATE, "connectivity_relaxed: no tree (call fmm2d_build_tree first)");
+    const int nbin = k0 + k1;
+    t.relax_host.assign(2 * nbin, 0.0);
+    for (int k = 0; k < nbin; ++k) {
+        const double tk = k < k0 ? theta * (double)(k + 1) / (double)k0
+                                 : theta + (theta_max - theta) * (double)(k - k0 + 1) / (double)k1;
+        t.relax_host[k] = tk;
+        t.relax_host[nbin + k] = power_p1(tk, p);
+    }
+    RelaxRule rx{theta, theta_max, power_p1(theta, p), p, k0, k1};
+    return connectivity_impl(c, theta, 0, &rx);
+}
+
+int fmm2d_get_relax_bins(fmm2d_ctx *c, int64_t *count, int32_t *kmax) {
+    if (!c) return FMM2D_EINVAL;
+    c->err.clear();
+    TreeState &t = c->tree;
+    if (!t.has_lists || t.relax_nbin == 0)
+        return fail(c, FMM2D_ESTATE, "get_relax_bins: no lists from fmm2d_connectivity_relaxed");
+    if (!count || !kmax) return fail(c, FMM2D_EINVAL, "get_relax_bins: NULL output");
+    CtxScope g(c);
+    const int nbin = t.relax_nbin, L = t.L;
+    std::vector<uint32_t> h((size_t)(L + 1) * nbin);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(h.data(), t.relax_hist.ptr, sizeof(uint32_t) * h.size(), hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(kmax, t.relax_k.ptr, sizeof(int32_t) * (L + 1), hipMemcpyDeviceToHost, c->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return hip_fail(c, e, "get_relax_bins");
+    for (size_t i = 0; i < h.size(); ++i) count[i] = h[i];
+    return FMM2D_OK;
+}
 
 int fmm2d_evaluate(fmm2d_ctx *c, const double *q, int p, int mode, double *phi) {
     if (!c) return FMM2D_EINVAL;

@@ -82,6 +82,13 @@ struct TreeState {
     DevBuf spart;           // float: source-side near-field partial sums per S_L record and source lane
     DevBuf pool_state;      // int64 [3 (L+2) + 1]: s, w, x offsets, overflow
     DevBuf nrec_j, nrec_d;  // per finest-level strong entry: source range; 2 float4 (FP32 centre offset, thresholds, low part)
+    // relaxed criterion (fmm2d_connectivity_relaxed): thresholds t_k and
+    // t_k^(p+1) (double [nbin] each), candidates per bin and level (uint32
+    // [(L+1) nbin]), each level's admitted threshold (double [L+1]) and last
+    // admitted bin (int32 [L+1]); relax_nbin 0 when the lists are plain
+    DevBuf relax_tk, relax_hist, relax_lv, relax_k;
+    std::vector<double> relax_host;  // t_k then t_k^(p+1), the source of the copy to relax_tk
+    int relax_nbin = 0, relax_k0 = 0;
     bool nrec_valid = false;
     Schedule m2l_all;               // weak lists of all levels (rows = global box ids)
     Schedule near_seg;              // finest-level strong lists (built on first use)
@@ -251,8 +258,14 @@ hipError_t build_tree_device(fmm2d_ctx *c, const double *x, const double *y, boo
 // to grow before a retry;
 // opt: FMM2D_OPT_* (0: the plain lists)
 constexpr int LIST_GROW_S = 4, LIST_GROW_W = 8, LIST_GROW_X = 16, LIST_GROW_CAND = 32;
+// rx (plain lists with the relaxed criterion) or nullptr
+struct RelaxRule {
+    double theta, theta_max, etheta;  // etheta = theta^(p+1) by p repeated products
+    int p, k0, k1;
+};
+constexpr int RELAX_MAX_BINS = 256;
 hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s, int64_t cap_w, int64_t cap_x,
-                              int64_t limit, int *overflow);
+                              int64_t limit, int *overflow, const RelaxRule *rx = nullptr);
 // expand.hip
 hipError_t evaluate_device(fmm2d_ctx *c, const double *q, int p, int mode, double *phi);
 // judge.hip

@@ -164,8 +164,8 @@ __global__ void k_lists_init(int32_t *sptr0, int32_t *wptr0, int32_t *xptr0, int
     sidx_pool[0] = 0;
     for (int k = 0; k <= slot_flag(L); ++k) pool_state[k] = 0;
     pool_state[1] = 1;  // S offset of level 1
+    owner0[0] = 0;      // row of level 0's one strong entry (a flat level 1 decodes by it)
     if (L == 0) {
-        owner0[0] = 0;
         selfpos[0] = 0;
         recj[0] = make_int2(stL[0], stL[1]);
         near_record(recd, 0, geom0[0], geom0[0], rect0[0], rect0[0], true);
@@ -454,8 +454,11 @@ __device__ inline ListDecision flat_masks(bool OPT, int opt, int l, int L, doubl
     return decide(ok, weak, exch, vok);
 }
 
+// lvth: each level's threshold on the device (relaxed criterion), else
+// nullptr and theta for every level.
 template <bool OPT>
 __global__ void __launch_bounds__(256) k_flat_count(int l, int L, int opt, double theta,
+                                                    const double *__restrict__ lvth,
                                                     const double4 *__restrict__ geomL,
                                                     const double4 *__restrict__ geomP,
                                                     const int32_t *__restrict__ sptr_prev, int64_t nb_prev,
@@ -466,6 +469,7 @@ __global__ void __launch_bounds__(256) k_flat_count(int l, int L, int opt, doubl
                                                     int32_t *__restrict__ cnt_s, int32_t *__restrict__ cnt_w,
                                                     int32_t *__restrict__ cnt_x) {
     if (pool_state[slot_flag(L)]) return;  // uniform
+    const double th = lvth ? lvth[l] : theta;
     const int64_t NC = level_candidates(sptr_prev, nb_prev);
     const int64_t nwords = (NC + 63) >> 6;
     const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
@@ -483,7 +487,7 @@ __global__ void __launch_bounds__(256) k_flat_count(int l, int L, int opt, doubl
         }
 #pragma unroll
         for (int u = 0; u < FB; ++u) {
-            const ListDecision d = flat_masks(OPT, opt, l, L, theta, fc.ok[u], fc.ent[u], gb[u], gc[u], geomP);
+            const ListDecision d = flat_masks(OPT, opt, l, L, th, fc.ok[u], fc.ent[u], gb[u], gc[u], geomP);
             if (lane == (uint32_t)u && w0 + u < nwords) {
                 bits[w0 + u] = d.mwo;
                 cnt_s[w0 + u] = (int32_t)__popcll(d.ms);
@@ -494,6 +498,100 @@ __global__ void __launch_bounds__(256) k_flat_count(int l, int L, int opt, doubl
                     cnt_x[w0 + u] = (int32_t)__popcll(d.mx);
                 }
             }
+        }
+    }
+}
+
+// ---- relaxed criterion (Section 4, last paragraph) ----------------------
+// Every candidate of level l is binned by the least threshold t_k of the
+// grid (tk, nbin entries, ascending) at which the criterion holds, and the
+// bins are counted (hist, nbin counters of the level, zeroed beforehand).
+// The criterion is monotone in t on the grid (neighbouring thresholds lie
+// far more than rounding apart), so a bisection finds the least one.  Each
+// block counts in LDS and adds its counts once.
+__global__ void __launch_bounds__(256) k_relax_hist(int l, int L, int nbin, const double *__restrict__ tk,
+                                                    const double4 *__restrict__ geomL,
+                                                    const int32_t *__restrict__ sptr_prev, int64_t nb_prev,
+                                                    const int32_t *__restrict__ sidx_pool,
+                                                    const int32_t *__restrict__ owner_prev,
+                                                    const int64_t *__restrict__ pool_state,
+                                                    uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[RELAX_MAX_BINS];
+    __shared__ double t_s[RELAX_MAX_BINS];
+    for (int k = threadIdx.x; k < nbin; k += blockDim.x) {
+        h[k] = 0;
+        t_s[k] = tk[k];
+    }
+    __syncthreads();
+    if (!pool_state[slot_flag(L)]) {  // uniform: a flagged level is not examined
+        const int64_t NC = level_candidates(sptr_prev, nb_prev);
+        const int64_t nwords = (NC + 63) >> 6;
+        const int32_t *sidx_prev = sidx_pool + pool_state[l - 1];
+        const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+        for (int64_t w0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * FB; w0 < nwords;
+             w0 += nwaves * FB) {
+            FlatCand fc;
+            flat_decode(w0, NC, owner_prev, sptr_prev, sidx_prev, fc);
+            double4 gb[FB], gc[FB];
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                gb[u] = fc.ok[u] ? geomL[fc.b[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+                gc[u] = fc.ok[u] ? geomL[fc.cbox[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < FB; ++u) {
+                if (!fc.ok[u]) continue;
+                int lo = 0, hi = nbin;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const double t = t_s[mid];
+                    if (theta_separated(t, t * t, gb[u], gc[u])) hi = mid;
+                    else lo = mid + 1;
+                }
+                if (lo < nbin) atomicAdd(&h[lo], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nbin; k += blockDim.x)
+        if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+// The level's admitted bins: the largest K >= k0 - 1 such that for every k
+// from k0 - 1 to K the counts of bins 0..k satisfy
+//     sum_j count_j t_j^(p+1) <= theta^(p+1) sum_j count_j
+// (binary64, summed in bin order, products and sums rounded one by one);
+// writes K and t_K, the threshold the count and fill passes then apply.
+__global__ void k_relax_pick(int l, int L, int nbin, int k0, double etheta, const double *__restrict__ tk,
+                             const double *__restrict__ ek, const uint32_t *__restrict__ hist,
+                             double *__restrict__ lvth, int32_t *__restrict__ lvk,
+                             const int64_t *__restrict__ pool_state) {
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || pool_state[slot_flag(L)]) return;
+    double sum = 0.0;
+    int64_t n = 0;
+    int K = k0 - 1;
+    for (int k = 0; k < nbin; ++k) {
+        const double term = (double)hist[k] * ek[k];
+        sum = sum + term;
+        n += hist[k];
+        if (k < k0 - 1) continue;
+        if (k > k0 - 1 && !(sum <= etheta * (double)n)) break;
+        K = k;
+    }
+    lvk[l] = K;
+    lvth[l] = tk[K];
+}
+
+// Zeroes the bin counts of all levels; level 0 (the root alone) admits the
+// plain threshold.
+__global__ void k_relax_init(int L, int nbin, int k0, double theta, uint32_t *__restrict__ hist,
+                             double *__restrict__ lvth, int32_t *__restrict__ lvk) {
+    for (int64_t i = threadIdx.x; i < (int64_t)(L + 1) * nbin; i += blockDim.x) hist[i] = 0;
+    if (threadIdx.x == 0) {
+        for (int l = 0; l <= L; ++l) {
+            lvth[l] = theta;
+            lvk[l] = k0 - 1;
         }
     }
 }
@@ -683,7 +781,7 @@ __global__ void __launch_bounds__(256) k_flat_fill(int l, int L, const double4 *
 }  // namespace
 
 hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s, int64_t cap_w, int64_t cap_x,
-                              int64_t limit, int *overflow) {
+                              int64_t limit, int *overflow, const RelaxRule *rx) {
     TreeState &t = c->tree;
     const int L = t.L;
     const int64_t nptr = ptr_offset(L + 1);
@@ -723,9 +821,24 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s
     const double4 *rectL = (t.shrink ? t.prect : t.rects).as<double4>() + level_offset(L);
     hipLaunchKernelGGL(k_lists_init, dim3(1), dim3(1), 0, c->stream, sptr, wptr, xptr, t.sidx.as<int32_t>(), ps, L,
                        stL, geom, rectL, t.nrec_j.as<int2>(), t.nrec_d.as<float4>(), owner[0], selfpos);
+    // relaxed criterion: the grid and its powers, zeroed bin counts; every
+    // level then runs the flat passes (each needs its threshold first)
+    const int nbin = rx ? rx->k0 + rx->k1 : 0;
+    double *lvth = nullptr;
+    if (rx) {
+        FMM2D_TRY(t.relax_tk.ensure(sizeof(double) * 2 * nbin));
+        FMM2D_TRY(t.relax_hist.ensure(sizeof(uint32_t) * (size_t)(L + 1) * nbin));
+        FMM2D_TRY(t.relax_lv.ensure(sizeof(double) * (L + 1)));
+        FMM2D_TRY(t.relax_k.ensure(sizeof(int32_t) * (L + 1)));
+        FMM2D_TRY(hipMemcpyAsync(t.relax_tk.ptr, t.relax_host.data(), sizeof(double) * 2 * nbin,
+                                 hipMemcpyHostToDevice, c->stream));
+        lvth = t.relax_lv.as<double>();
+        hipLaunchKernelGGL(k_relax_init, dim3(1), dim3(256), 0, c->stream, L, nbin, rx->k0, rx->theta,
+                           t.relax_hist.as<uint32_t>(), lvth, t.relax_k.as<int32_t>());
+    }
     // levels of at most 64 boxes: one workgroup, one launch
     int K = 0;
-    while (K < L && (int64_t(1) << (2 * (K + 1))) <= SMALL_BOXES) ++K;
+    while (!rx && K < L && (int64_t(1) << (2 * (K + 1))) <= SMALL_BOXES) ++K;
     if (K >= 1)
         hipLaunchKernelGGL(k_lists_small, dim3(1), dim3(SMALL_THREADS), 0, c->stream, K, L, opt, theta, geom, sptr,
                            wptr, xptr, t.sidx.as<int32_t>(), t.widx.as<int32_t>(), t.xidx.as<int32_t>(), ps, cap_s,
@@ -756,15 +869,25 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s
             const int32_t *own_prev = owner[(l - 1) & 1];
             int32_t *own_cur = owner[l & 1];
             if (OPT) {
-                hipLaunchKernelGGL(k_flat_count<true>, dim3(fgrid), dim3(256), 0, c->stream, l, L, opt, theta, gL, gP,
-                                   sp_prev, nb_prev, t.sidx.as<int32_t>(), own_prev, ps, bits, words, cs, cw, cx);
+                hipLaunchKernelGGL(k_flat_count<true>, dim3(fgrid), dim3(256), 0, c->stream, l, L, opt, theta,
+                                   (const double *)nullptr, gL, gP, sp_prev, nb_prev, t.sidx.as<int32_t>(), own_prev,
+                                   ps, bits, words, cs, cw, cx);
                 hipLaunchKernelGGL(k_wscan_tiles<3>, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps,
                                    cs, cw, cx, tsum, ntile);
                 hipLaunchKernelGGL(k_wscan_apply<3>, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps,
                                    cs, cw, cx, tsum, ntile, sp_cur, wp_cur, xp_cur, nb);
             } else {
-                hipLaunchKernelGGL(k_flat_count<false>, dim3(fgrid), dim3(256), 0, c->stream, l, L, opt, theta, gL,
-                                   gP, sp_prev, nb_prev, t.sidx.as<int32_t>(), own_prev, ps, bits, words, cs, cw, cx);
+                if (rx) {
+                    uint32_t *hl = t.relax_hist.as<uint32_t>() + (size_t)l * nbin;
+                    const double *tk = t.relax_tk.as<double>();
+                    hipLaunchKernelGGL(k_relax_hist, dim3(fgrid), dim3(256), 0, c->stream, l, L, nbin, tk, gL,
+                                       sp_prev, nb_prev, t.sidx.as<int32_t>(), own_prev, ps, hl);
+                    hipLaunchKernelGGL(k_relax_pick, dim3(1), dim3(64), 0, c->stream, l, L, nbin, rx->k0,
+                                       rx->etheta, tk, tk + nbin, hl, lvth, t.relax_k.as<int32_t>(), ps);
+                }
+                hipLaunchKernelGGL(k_flat_count<false>, dim3(fgrid), dim3(256), 0, c->stream, l, L, opt, theta,
+                                   (const double *)lvth, gL, gP, sp_prev, nb_prev, t.sidx.as<int32_t>(), own_prev,
+                                   ps, bits, words, cs, cw, cx);
                 hipLaunchKernelGGL(k_wscan_tiles<2>, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps,
                                    cs, cw, cx, tsum, ntile);
                 hipLaunchKernelGGL(k_wscan_apply<2>, dim3(ntile), dim3(WS_T), 0, c->stream, L, sp_prev, nb_prev, ps,
@@ -797,6 +920,8 @@ hipError_t build_lists_device(fmm2d_ctx *c, double theta, int opt, int64_t cap_s
         for (int l = K + 1; l <= L; ++l) t.x_off[l + 1] = t.x_off[l];
     }
     t.opt = opt;
+    t.relax_nbin = nbin;
+    t.relax_k0 = rx ? rx->k0 : 0;
     return hipSuccess;
 }
 

@@ -140,6 +140,25 @@ class FMM2D:
                                                      "all": _capi.OPT_SWAP_ALL}[swap]
         self._check(self._lib.fmm2d_connectivity_opt(self._h, float(theta), opt))
 
+    def connectivity_relaxed(self, theta: float, theta_max: float, p: int, k0: int = 16, k1: int = 16):
+        """Plain lists under the locally relaxed theta-criterion (Section 4,
+        last paragraph): candidates up to theta_max admitted as weak, lowest
+        first, while each level's mean of theta_i^(p+1) stays within
+        theta^(p+1)."""
+        self._check(self._lib.fmm2d_connectivity_relaxed(self._h, float(theta), float(theta_max), int(p),
+                                                          int(k0), int(k1)))
+        self._relax_bins = int(k0) + int(k1)
+
+    def relax_bins(self):
+        """(count int64 [L + 1, k0 + k1], kmax int32 [L + 1]) of the relaxed lists."""
+        nbin = getattr(self, "_relax_bins", 0)
+        if not nbin or self.levels is None:
+            raise RuntimeError("no lists from connectivity_relaxed")
+        count = torch.zeros((self.levels + 1) * nbin, dtype=torch.int64)
+        kmax = torch.zeros(self.levels + 1, dtype=torch.int32)
+        self._check(self._lib.fmm2d_get_relax_bins(self._h, _ptr(count), _ptr(kmax)))
+        return count.reshape(self.levels + 1, nbin), kmax
+
     def evaluate(self, q: torch.Tensor, p: int, mode: str = "fp64", out: torch.Tensor | None = None):
         _require(q, torch.float64, self.device, "q")
         if self.n is not None and q.numel() != self.n:

@@ -1,0 +1,123 @@
+"""GPU parity of the locally relaxed theta-criterion (Section 4, last
+paragraph) against the CPU oracle.
+
+* Lists bit-exact against the oracle's relaxed lists, with the bin counts
+  and the admitted bin of every level, at (theta, theta_max, p) admitting
+  pairs above theta and at theta_max = theta (the plain lists).
+* Binary64 potentials on the relaxed lists within 1e-12 of the oracle FMM
+  on the same lists (both M2L kernels).
+* The reduced modes on relaxed lists within their tolerance of the
+  oracle's direct sum.
+* Argument and state errors.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_cases import TREE_CASES
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    ctx = FMM2D(0)
+    yield ctx
+    ctx.close()
+
+
+def _announce(*a):
+    print("[case]", *a, flush=True)
+
+
+CASES = ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "ring_scaled_20k_L6", "duplicates_4k_L4",
+         "uniform_1k_L3", "single_box_L0"]
+RULES = [(0.5, 0.9, 12), (0.35, 0.8, 6), (0.7, 0.7, 12)]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("theta,theta_max,p", RULES)
+def test_relaxed_lists_bit_exact(fmm, orc, case, theta, theta_max, p):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    _announce("relaxed lists", case, ps.n, L, theta, theta_max, p)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity_relaxed(theta, theta_max, p)
+    ls = orc.lists_relaxed(orc.tree(ps.x, ps.y, L), theta, theta_max, p)
+    torch.cuda.synchronize()
+    count, kmax = fmm.relax_bins()
+    for l in range(L + 1):
+        sp, si, wp, wi = (a.cpu().numpy().astype(np.int64) for a in fmm.lists(l))
+        assert np.array_equal(sp, ls.sptr[l]) and np.array_equal(si, ls.sidx[l])
+        assert np.array_equal(wp, ls.wptr[l]) and np.array_equal(wi, ls.widx[l])
+        assert np.array_equal(count[l].numpy(), ls.count[l])
+        assert int(kmax[l]) == ls.kmax[l]
+
+
+def test_relaxed_at_theta_is_plain(fmm, orc):
+    maker, L = TREE_CASES["clustered_scaled_20k_L6"]
+    ps = maker()
+    _announce("relaxed at theta", ps.n, L)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity(0.5)
+    plain = [[a.cpu().numpy() for a in fmm.lists(l)] for l in range(L + 1)]
+    fmm.connectivity_relaxed(0.5, 0.5, 10)
+    torch.cuda.synchronize()
+    for l in range(L + 1):
+        for a, b in zip(plain[l], fmm.lists(l)):
+            assert np.array_equal(a, b.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "ring_scaled_20k_L6"])
+@pytest.mark.parametrize("p", [6, 15, 20])
+def test_relaxed_fp64_matches_oracle_fmm(fmm, orc, case, p):
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    _announce("relaxed fp64", case, ps.n, L, p)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity_relaxed(0.5, 0.9, p)
+    phi = fmm.evaluate(_dev(ps.q), p, "fp64")
+    t = orc.tree(ps.x, ps.y, L)
+    ref = orc.fmm_eval(ps.x, ps.y, ps.q, t, orc.lists_relaxed(t, 0.5, 0.9, p), p)
+    torch.cuda.synchronize()
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mode,tol", [("fp32", 2e-5), ("fp32_acc64", 2e-5), ("bf16x3", 1e-3)])
+def test_relaxed_reduced_modes(fmm, orc, mode, tol):
+    maker, L = TREE_CASES["clustered_scaled_20k_L6"]
+    ps = maker()
+    _announce("relaxed reduced", ps.n, L, mode)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity_relaxed(0.5, 0.9, 16)
+    phi = fmm.evaluate(_dev(ps.q), 16, mode)
+    ex = orc.direct(ps.x, ps.y, ps.q)
+    torch.cuda.synchronize()
+    e, _ = orc.rel_errors(phi.cpu().numpy(), ex)
+    assert e <= tol
+
+
+def test_relaxed_argument_and_state_errors(fmm):
+    maker, L = TREE_CASES["uniform_1k_L3"]
+    ps = maker()
+    _announce("relaxed errors", ps.n, L)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    for bad in [(0.5, 0.4, 4, 16, 16), (0.5, 1.0, 4, 16, 16), (0.0, 0.5, 4, 16, 16), (0.5, 0.9, -1, 16, 16),
+                (0.5, 0.9, 4, 0, 16), (0.5, 0.9, 4, 200, 57)]:
+        with pytest.raises(RuntimeError):
+            fmm.connectivity_relaxed(*bad)
+    fmm.connectivity(0.5)
+    with pytest.raises(RuntimeError):
+        fmm.relax_bins()  # plain lists carry no bins
+    fmm.connectivity_relaxed(0.5, 0.9, 8)
+    count, kmax = fmm.relax_bins()
+    assert int(count[0].sum()) == 0 and int(kmax[0]) == 15

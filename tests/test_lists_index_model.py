@@ -54,10 +54,12 @@ VFLAG = 1 << 30
 GROW_S, GROW_W, GROW_X, GROW_CAND = 4, 8, 16, 32
 
 
-def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0):
+def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0, all_flat=False):
     """One build_lists_device call; returns (overflow flag, pool offsets,
     replayed S and W lists per level).  With optimised lists (``ls.vptr``
-    present) the W output holds V entries (flagged) and an X pool is used."""
+    present) the W output holds V entries (flagged) and an X pool is used.
+    ``all_flat``: every level in the flat passes (the relaxed criterion's
+    build, which needs each level's threshold before its count pass)."""
     opt = getattr(ls, "vptr", None) is not None
     nS = [int(ls.sptr[l][-1]) for l in range(L + 1)]
     nW = [int(ls.wptr[l][-1]) + (int(ls.vptr[l][-1]) if opt else 0) for l in range(L + 1)]
@@ -77,7 +79,7 @@ def _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x=0):
     words_cap = (cap_s + cap_w + 63) // 64 + 1
     ntile = (words_cap + WS_TILE - 1) // WS_TILE
     K = 0
-    while K < L and 4 ** (K + 1) <= SMALL_BOXES:
+    while not all_flat and K < L and 4 ** (K + 1) <= SMALL_BOXES:
         K += 1
 
     def advance(l):
@@ -198,7 +200,7 @@ def split_w(W):
     return W[~flagged], W[flagged] & (VFLAG - 1)
 
 
-def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX, swaps=False, hint_x=0):
+def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX, swaps=False, hint_x=0, all_flat=False):
     """fmm2d_connectivity's retry loop around the replayed build.  Returns
     (status, attempts, bounds, caps)."""
     nbox = level_offset(L + 1)
@@ -208,7 +210,7 @@ def replay_connectivity(ls, L, hint_s=0, hint_w=0, limit=INT32_MAX, swaps=False,
     bd = Bounds()
     opt = getattr(ls, "vptr", None) is not None
     for attempt in range(16):
-        flag, s_off, got_s, got_w, got_x, offs = _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x)
+        flag, s_off, got_s, got_w, got_x, offs = _attempt(ls, L, cap_s, cap_w, limit, bd, cap_x, all_flat)
         if flag == 0:
             for l in range(L + 1):
                 assert np.array_equal(got_s[l], ls.sidx[l]), "replayed S list of level %d differs" % l
@@ -279,4 +281,24 @@ def test_opt_list_indices_in_bounds(orc, case, parent, swap):
     for hint in (0, 1 << 22):
         status, attempts, bd, caps = replay_connectivity(ls, L, hint, 3 * hint, swaps=swap != "none",
                                                          hint_x=hint)
+        assert status == "ok"
+
+
+@pytest.mark.parametrize("case", ["clustered_scaled_20k_L6", "mixed_scaled_20k_L6", "ring_scaled_20k_L6",
+                                  "uniform_20k_L5", "duplicates_4k_L4", "scales_3k_L4", "single_box_L0",
+                                  "uniform_1k_L3"])
+@pytest.mark.parametrize("theta,theta_max,p", [(0.5, 0.9, 12), (0.35, 0.8, 6), (0.7, 0.7, 12)])
+def test_relaxed_list_indices_in_bounds(orc, case, theta, theta_max, p):
+    """The relaxed criterion's build: every level (the coarse ones too) in the
+    flat passes, with the lists the relaxed rule gives; the bin counters of
+    a level are (L + 1) (k0 + k1) words, indexed l (k0 + k1) + bin."""
+    maker, L = TREE_CASES[case]
+    ps = maker()
+    ls = orc.lists_relaxed(orc.tree(ps.x, ps.y, L), theta, theta_max, p)
+    nbin = ls.k0 + ls.k1
+    for l in range(L + 1):
+        assert len(ls.count[l]) == nbin and 0 <= ls.kmax[l] < nbin
+        assert l * nbin + nbin - 1 < (L + 1) * nbin
+    for hint in (0, 1 << 22):
+        status, attempts, bd, caps = replay_connectivity(ls, L, hint, 3 * hint, all_flat=True)
         assert status == "ok"
