@@ -98,7 +98,7 @@ def parse():
                          "levels and theta, the least p passing the judge")
     ap.add_argument("--fp64-plain", type=int, default=0,
                     help="also time FP64 on the lists without the structural options (slow on clustered sets)")
-    ap.add_argument("--sweep", choices=["field", "robustness", "precision"],
+    ap.add_argument("--sweep", choices=["field", "robustness", "precision", "relaxed"],
                     help="run a measurement sweep instead of the benchmark (JSON table to --out)")
     ap.add_argument("--out", help="output file of a sweep")
     ap.add_argument("--sizes", help="robustness sweep: comma-separated N")
@@ -232,6 +232,76 @@ def sweep_robustness(args):
     f.close()
     return 0
 
+
+
+def sweep_relaxed(args):
+    """The trade of the locally relaxed theta-criterion (Section 4, last
+    paragraph): near-field pairs moved into the far field at the same error
+    estimate.  On the 1M mixed, 4M ring and 10M clustered workloads, at
+    theta = 1/2 and p in {12, 16}: the plain lists against the relaxed ones
+    (theta_max 0.7 and 0.9), evaluated in FP32_ACC64.  Per form: finest
+    strong and all weak entries, time of connectivity + evaluate (median of 3
+    after a warm-up, HIP events on the library stream), e_inf against the
+    binary64 direct sum at 1000 sampled targets."""
+    import numpy as np
+    import torch
+
+    from paper_1006_2269_amd import workloads as W
+    from paper_1006_2269_amd.fmm import FMM2D
+
+    f = FMM2D(0)
+    dev = f.device
+    theta = 0.5
+    rows = []
+    for wl, L in (("mixed_1m", 8), ("ring_4m", 9), ("clustered_10m", 9)):
+        ps = W.WORKLOADS[wl]()
+        x, y, q = (torch.from_numpy(a).to(dev) for a in (ps.x, ps.y, ps.q))
+        tg = torch.from_numpy(W.sample_targets(ps.n, 1000, seed=4242)).to(dev)
+        exact = f.direct(x, y, q, tg)
+        scale = float(exact.abs().max())
+        out = torch.empty_like(q)
+        f.build_tree(x, y, L)
+        for p in (12, 16):
+            for tmax in (None, 0.7, 0.9):
+                def lists():
+                    if tmax is None:
+                        f.connectivity(theta)
+                    else:
+                        f.connectivity_relaxed(theta, tmax, p)
+
+                def step():
+                    lists()
+                    f.evaluate(q, p, "fp32_acc64", out=out)
+
+                step()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(3):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(f.stream)
+                    step()
+                    b.record(f.stream)
+                    b.synchronize()
+                    ts.append(a.elapsed_time(b))
+                e = float((out[tg] - exact).abs().max()) / scale
+                ns_L = f.list_sizes(L)[0]
+                nw = sum(f.list_sizes(l)[1] for l in range(L + 1))
+                rec = {"workload": wl, "n": ps.n, "levels": L, "theta": theta, "p": p,
+                       "theta_max": tmax, "strong_finest": ns_L, "weak_all": nw,
+                       "ms": float(np.median(ts)), "e_inf": e}
+                if tmax is not None:
+                    count, kmax = f.relax_bins()
+                    rec["kmax"] = [int(k) for k in kmax]
+                rows.append(rec)
+                print("[relaxed] %-13s L=%d p=%2d theta_max=%-4s S_L=%10d W=%10d %8.2f ms e=%.2e"
+                      % (wl, L, p, tmax, ns_L, nw, rec["ms"], e), flush=True)
+        del x, y, q, out
+        torch.cuda.empty_cache()
+    with open(args.out, "w") as fh:
+        json.dump({"theta": theta, "mode": "fp32_acc64", "rows": rows}, fh, indent=1)
+    f.close()
+    return 0
 
 
 def sweep_precision(args):
@@ -412,7 +482,7 @@ def main():
             print("--sweep needs --out", file=sys.stderr)
             sys.exit(2)
         sys.exit({"field": sweep_field, "robustness": sweep_robustness,
-                  "precision": sweep_precision}[args.sweep](args))
+                  "precision": sweep_precision, "relaxed": sweep_relaxed}[args.sweep](args))
     import numpy as np
     import torch
 
