@@ -8,6 +8,8 @@ paragraph) against the CPU oracle.
   on the same lists (both M2L kernels).
 * The reduced modes on relaxed lists within their tolerance of the
   oracle's direct sum.
+* Full size: the 1M-point mixed workload at 7 and 8 levels, lists bit-exact
+  and FP32_ACC64 within 1e-6 of the direct sum at sampled targets.
 * Argument and state errors.
 """
 import numpy as np
@@ -121,3 +123,30 @@ def test_relaxed_argument_and_state_errors(fmm):
     fmm.connectivity_relaxed(0.5, 0.9, 8)
     count, kmax = fmm.relax_bins()
     assert int(count[0].sum()) == 0 and int(kmax[0]) == 15
+
+
+@pytest.mark.parametrize("L,theta_max,p", [(7, 0.9, 12), (8, 0.7, 16)])
+def test_relaxed_full_size_mixed_1m(fmm, orc, L, theta_max, p):
+    """The 1M-point mixed workload: relaxed lists, bin counts and admitted
+    bins bit-exact at 7 and 8 levels, and the FP32_ACC64 evaluation on them
+    within 1e-6 of the oracle's direct sum at 1000 sampled targets."""
+    from paper_1006_2269_amd import workloads as W
+
+    ps = W.mixed_1m()
+    _announce("relaxed full size", ps.n, L, theta_max, p)
+    fmm.build_tree(_dev(ps.x), _dev(ps.y), L)
+    fmm.connectivity_relaxed(0.5, theta_max, p)
+    ls = orc.lists_relaxed(orc.tree(ps.x, ps.y, L), 0.5, theta_max, p)
+    torch.cuda.synchronize()
+    count, kmax = fmm.relax_bins()
+    assert [int(k) for k in kmax] == ls.kmax
+    for l in range(L + 1):
+        assert np.array_equal(count[l].numpy(), ls.count[l])
+        sp, si, wp, wi = (a.cpu().numpy().astype(np.int64) for a in fmm.lists(l))
+        assert np.array_equal(sp, ls.sptr[l]) and np.array_equal(si, ls.sidx[l])
+        assert np.array_equal(wp, ls.wptr[l]) and np.array_equal(wi, ls.widx[l])
+    if p == 16:
+        phi = fmm.evaluate(_dev(ps.q), p, "fp32_acc64").cpu().numpy()
+        tg = W.sample_targets(ps.n, 1000, seed=4242)
+        ex = orc.direct(ps.x, ps.y, ps.q, tg)
+        assert np.abs(phi[tg] - ex).max() <= 1e-6 * np.abs(ex).max()
