@@ -12,6 +12,9 @@ multipole methods":
 
 * ``direct``     -- the interaction sum (1.1) with charges and G = log|x - y|.
 * ``tree``       -- the balanced median-split pyramid (Section 4, Fig. 1.1).
+* ``tree_midpoint`` -- the uniform quadtree (midpoint splits, all leaves at
+                    one depth) that Section 5's second experiment compares
+                    the adaptive tree with.
 * ``shrink``     -- the same boxes with the balls of Criterion 2.1 drawn
                     around each box's points (their bounding box) instead of
                     the tiling rectangle.
@@ -77,6 +80,8 @@ def _load():
     lib.orc_direct.restype = None
     lib.orc_tree.argtypes = [i64, P, P, i32, P, P, P]
     lib.orc_tree.restype = i32
+    lib.orc_tree_midpoint.argtypes = [i64, P, P, i32, P, P, P]
+    lib.orc_tree_midpoint.restype = i32
     lib.orc_geometry.argtypes = [i64, P, P]
     lib.orc_geometry.restype = None
     lib.orc_theta_test.argtypes = [d, P, P]
@@ -199,6 +204,26 @@ def tree(x, y, levels: int) -> Tree:
         raise RuntimeError("orc_tree failed: %d" % rc)
     geom = geometry(rects)
     return Tree(n, levels, perm, start, rects, geom)
+
+
+def tree_midpoint(x, y, levels: int) -> Tree:
+    """The uniform quadtree of the comparison in Section 5's second
+    experiment: every box split at its rectangle's midpoint in both
+    coordinates, all leaves at depth ``levels`` (congruent boxes per level,
+    any number of points per box, empty boxes included)."""
+    lib = _load()
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    if levels < 0 or levels > 13 or n < 1:
+        raise ValueError("need 0 <= levels <= 13 and n >= 1")
+    nbox = level_offset(levels + 1)
+    perm = np.empty(n, dtype=np.int64)
+    start = np.empty(4 ** levels + 1, dtype=np.int64)
+    rects = np.empty((nbox, 4), dtype=np.float64)
+    rc = lib.orc_tree_midpoint(n, _p(x), _p(y), levels, _p(perm), _p(start), _p(rects))
+    if rc != 0:
+        raise RuntimeError("orc_tree_midpoint failed: %d" % rc)
+    return Tree(n, levels, perm, start, rects, geometry(rects))
 
 
 def point_rects(t: Tree, x, y) -> np.ndarray:

@@ -173,6 +173,70 @@ int orc_tree(int64_t n, const double *x_in, const double *y_in, int L,
     return 0;
 }
 
+/* The uniform quadtree that Section 5's second experiment compares against
+ * (the standard, non-adaptive subdivision): the same root box, every box
+ * split at the midpoint of its rectangle in both coordinates at once, all
+ * leaves at depth L, so boxes of one level are congruent and may hold any
+ * number of points, none included.  Child numbering as in orc_tree
+ * (4b + 2 [x high] + [y high]); a point on a split line goes to the high
+ * side.  Inside a leaf points are listed by (x, index).  Any n >= 1.
+ * Returns 0, -1 for bad arguments, -2 when out of memory.                  */
+int orc_tree_midpoint(int64_t n, const double *x_in, const double *y_in, int L,
+                      int64_t *perm, int64_t *leaf_start, double *rects)
+{
+    if (L < 0 || L > 13 || n < 1)
+        return -1;
+    int64_t nleaf = ((int64_t)1) << (2 * L);
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    int64_t *leaf = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *fill = (int64_t *)calloc((size_t)(nleaf + 1), sizeof(int64_t));
+    if (!x || !y || !leaf || !fill) { free(x); free(y); free(leaf); free(fill); return -2; }
+    for (int64_t i = 0; i < n; ++i) { x[i] = x_in[i] + 0.0; y[i] = y_in[i] + 0.0; }
+    double xmin = x[0], xmax = x[0], ymin = y[0], ymax = y[0];
+    for (int64_t i = 1; i < n; ++i) {
+        if (x[i] < xmin) xmin = x[i];
+        if (x[i] > xmax) xmax = x[i];
+        if (y[i] < ymin) ymin = y[i];
+        if (y[i] > ymax) ymax = y[i];
+    }
+    rects[0] = xmin; rects[1] = xmax; rects[2] = ymin; rects[3] = ymax;
+    /* rectangles, level by level: the four quarters of the parent's */
+    for (int l = 0; l < L; ++l) {
+        int64_t nb = ((int64_t)1) << (2 * l);
+        for (int64_t b = 0; b < nb; ++b) {
+            const double *R = rects + 4 * (level_offset(l) + b);
+            double mx = 0.5 * (R[0] + R[1]);
+            double my = 0.5 * (R[2] + R[3]);
+            for (int c = 0; c < 4; ++c) {
+                double *C = rects + 4 * (level_offset(l + 1) + 4 * b + c);
+                int hx = c >> 1, hy = c & 1;
+                C[0] = hx ? mx : R[0]; C[1] = hx ? R[1] : mx;
+                C[2] = hy ? my : R[2]; C[3] = hy ? R[3] : my;
+            }
+        }
+    }
+    /* each point's leaf: down the tree, comparing with the split lines */
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t b = 0;
+        for (int l = 0; l < L; ++l) {
+            const double *R = rects + 4 * (level_offset(l) + b);
+            double mx = 0.5 * (R[0] + R[1]);
+            double my = 0.5 * (R[2] + R[3]);
+            b = 4 * b + 2 * (x[i] >= mx) + (y[i] >= my);
+        }
+        leaf[i] = b;
+        ++fill[b + 1];
+    }
+    for (int64_t b = 0; b < nleaf; ++b) fill[b + 1] += fill[b];
+    memcpy(leaf_start, fill, sizeof(int64_t) * (size_t)(nleaf + 1));
+    for (int64_t i = 0; i < n; ++i) perm[fill[leaf[i]]++] = i;  /* index order inside each leaf */
+    for (int64_t b = 0; b < nleaf; ++b)
+        sort_by(perm + leaf_start[b], leaf_start[b + 1] - leaf_start[b], x);
+    free(x); free(y); free(leaf); free(fill);
+    return 0;
+}
+
 /* Box centre and radius of the enclosing ball (half diagonal), each line a
  * single rounded binary64 operation (Criterion 2.1 applied to the tiling
  * rectangle).                                                               */

@@ -4,10 +4,12 @@
  * AddressSanitizer and UndefinedBehaviorSanitizer (tests/test_oracle_sanitized.py).
  *
  * Inputs: a clustered set with exact duplicates and a point repeated many
- * times, and a uniform set of exactly 4^L points.  Each is taken through the
- * tree, the geometry, the plain, optimised and relaxed lists of every level,
- * the three FMM evaluations and both direct sums, and the FMM potentials are
- * compared with the direct sum (a loose check: the sanitizers are the point).
+ * times (with the median tree and with the uniform quadtree, whose leaves
+ * are empty or hold hundreds of points), and a uniform set of exactly 4^L
+ * points.  Each is taken through the tree, the geometry, the plain,
+ * optimised and relaxed lists of every level, the three FMM evaluations and
+ * both direct sums, and the FMM potentials are compared with the direct sum
+ * (a loose check: the sanitizers are the point).
  * Prints "ok" and returns 0 when everything ran and agreed.
  */
 #include <math.h>
@@ -21,6 +23,8 @@ void orc_direct(int64_t n, const double *x, const double *y, const double *q, in
 void orc_direct_field(int64_t n, const double *x, const double *y, const double *q, int64_t m,
                       const int64_t *targets, double *gx, double *gy);
 int orc_tree(int64_t n, const double *x, const double *y, int L, int64_t *perm, int64_t *leaf_start, double *rects);
+int orc_tree_midpoint(int64_t n, const double *x, const double *y, int L, int64_t *perm, int64_t *leaf_start,
+                      double *rects);
 void orc_geometry(int64_t nbox, const double *rects, double *geom);
 int orc_lists_level(int l, double theta, const double *geom_l, const int64_t *sptr_prev, const int64_t *sidx_prev,
                     int64_t *sptr, int64_t *sidx, int64_t *wptr, int64_t *widx, int64_t cap);
@@ -126,7 +130,8 @@ static double max_rel_diff(const double *a, const double *b, int64_t n) {
     return num / den;
 }
 
-static void run(const char *name, int64_t n, const double *x, const double *y, const double *q, int L) {
+static void run(const char *name, int64_t n, const double *x, const double *y, const double *q, int L,
+                int midpoint) {
     const int p = 10;
     const double theta = 0.5;
     const int64_t nbox = level_offset(L + 1), nleaf = (int64_t)1 << (2 * L);
@@ -134,7 +139,9 @@ static void run(const char *name, int64_t n, const double *x, const double *y, c
     int64_t *leaf_start = xmalloc(sizeof(int64_t) * (size_t)(nleaf + 1));
     double *rects = xmalloc(sizeof(double) * 4 * (size_t)nbox);
     double *geom = xmalloc(sizeof(double) * 3 * (size_t)nbox);
-    if (orc_tree(n, x, y, L, perm, leaf_start, rects) != 0) FAIL("%s: orc_tree", name);
+    if ((midpoint ? orc_tree_midpoint(n, x, y, L, perm, leaf_start, rects) : orc_tree(n, x, y, L, perm, leaf_start,
+                                                                                         rects)) != 0)
+        FAIL("%s: tree", name);
     orc_geometry(nbox, rects, geom);
 
     int64_t *tg = xmalloc(sizeof(int64_t) * (size_t)n);
@@ -255,7 +262,8 @@ int main(void) {
         x[i] = 0.5;
         y[i] = 0.5;
     }
-    run("clustered", n1, x, y, q, 4);
+    run("clustered", n1, x, y, q, 4, 0);
+    run("clustered, uniform quadtree", n1, x, y, q, 4, 1);
     free(x); free(y); free(q);
 
     /* uniform, exactly 4^L points (one leaf size) */
@@ -268,7 +276,7 @@ int main(void) {
         y[i] = urand();
         q[i] = 2.0 * urand() - 1.0;
     }
-    run("uniform", n2, x, y, q, 5);
+    run("uniform", n2, x, y, q, 5, 0);
     free(x); free(y); free(q);
     printf("ok\n");
     return 0;
