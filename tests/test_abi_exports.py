@@ -56,5 +56,7 @@ def test_version_and_argument_errors_without_gpu():
     assert lib.fmm2d_destroy(None) == _capi.EINVAL
     assert lib.fmm2d_build_tree(None, None, None, 10, 1) == _capi.EINVAL
     assert lib.fmm2d_connectivity(None, 0.5) == _capi.EINVAL
+    assert lib.fmm2d_connectivity_relaxed(None, 0.5, 0.9, 12, 16, 16) == _capi.EINVAL
+    assert lib.fmm2d_get_relax_bins(None, None, None) == _capi.EINVAL
     assert lib.fmm2d_evaluate(None, None, 10, 0, None) == _capi.EINVAL
     assert lib.fmm2d_last_error(None) == b"fmm2d: NULL context"
